@@ -1,0 +1,274 @@
+"""TEST INFRASTRUCTURE ONLY -- the FP64 CPU oracle of the implicit M1 multigrid.
+
+This package wraps ``m1_oracle.c`` (plain C, FP64, no fast-math) with ctypes and
+adds ``dense.py`` (an independent numpy form of the discrete operator with a
+dense Newton solver for tiny grids).  Only ``tests/``, ``__graft_entry__.smoke()``
+and the ``cpu_baseline`` leg of ``bench.py`` may import it.  The GPU product path
+never imports it and shares no code with it.
+
+State arrays are numpy float64 of shape (4, ny, nx) holding E, Fx, Fy, T;
+opacity arrays are (2, ny, nx) holding sigma_a, sigma_s.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "m1_oracle.c")
+_LIB = os.path.join(_HERE, "libm1oracle.so")
+
+BC = {"periodic": 0, "reflective": 1, "neumann": 2, "dirichlet": 3}
+DTAU_RULE = {"signed": 0, "literal": 1}
+
+
+class Grid(ctypes.Structure):
+    _fields_ = [
+        ("dim", ctypes.c_int32), ("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("pad_", ctypes.c_int32),
+        ("hx", ctypes.c_double), ("hy", ctypes.c_double), ("dt", ctypes.c_double), ("c", ctypes.c_double),
+        ("a_r", ctypes.c_double), ("c_v", ctypes.c_double),
+        ("bc_kind", ctypes.c_int32 * 4),
+        ("bc_E", ctypes.c_double * 4), ("bc_Fx", ctypes.c_double * 4), ("bc_Fy", ctypes.c_double * 4),
+    ]
+
+
+class Params(ctypes.Structure):
+    _fields_ = [
+        ("levels", ctypes.c_int32), ("nu0", ctypes.c_int32), ("nu_l", ctypes.c_int32),
+        ("pseudo_steps", ctypes.c_int32), ("sub_steps", ctypes.c_int32), ("max_cycles", ctypes.c_int32),
+        ("dtau_rule", ctypes.c_int32), ("pseudo_local", ctypes.c_int32),
+        ("dtau_im0", ctypes.c_double), ("eps_inc", ctypes.c_double), ("eps_dec", ctypes.c_double),
+        ("eta", ctypes.c_double), ("rtol", ctypes.c_double), ("dtau_min", ctypes.c_double),
+        ("dtau_max", ctypes.c_double), ("omega", ctypes.c_double),
+    ]
+
+
+class Info(ctypes.Structure):
+    _fields_ = [
+        ("cycles", ctypes.c_int32), ("status", ctypes.c_int32), ("levels", ctypes.c_int32), ("pad_", ctypes.c_int32),
+        ("r0", ctypes.c_double), ("rel_residual", ctypes.c_double), ("dtau", ctypes.c_double),
+    ]
+
+
+def build(force: bool = False) -> str:
+    """Compile the oracle with gcc (always when ``force``)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        cmd = ["gcc", "-O2", "-std=c99", "-fopenmp", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared",
+               "-Wall", "-o", _LIB + ".tmp", _SRC, "-lm"]
+        subprocess.run(cmd, check=True)
+        os.replace(_LIB + ".tmp", _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        build()
+        L = ctypes.CDLL(_LIB)
+        dp = ctypes.POINTER(ctypes.c_double)
+        gp, pp = ctypes.POINTER(Grid), ctypes.POINTER(Params)
+        L.or_chi.restype = ctypes.c_double
+        L.or_chi.argtypes = [ctypes.c_double]
+        L.or_closure.argtypes = [ctypes.c_double] * 4 + [dp]
+        L.or_local_solve.argtypes = [ctypes.c_double] * 7 + [dp, dp]
+        L.or_ray.restype = ctypes.c_double
+        L.or_ray.argtypes = [ctypes.c_double, dp, dp]
+        L.or_admissible.restype = ctypes.c_int
+        L.or_admissible.argtypes = [ctypes.c_double, dp]
+        L.or_apply_A.argtypes = [gp, dp, dp, dp]
+        L.or_residual.argtypes = [gp, dp, dp, dp, dp]
+        L.or_norm.restype = ctypes.c_double
+        L.or_norm.argtypes = [gp, dp]
+        L.or_jacobi.argtypes = [gp, dp, ctypes.c_double, ctypes.c_double, dp, dp, dp, dp]
+        L.or_sweep.argtypes = [gp, dp, ctypes.c_double, dp, dp, dp]
+        L.or_restrict.argtypes = [gp, dp, ctypes.c_int32, dp]
+        L.or_prolong.argtypes = [gp, dp, ctypes.c_int32, dp]
+        L.or_pseudo_step.argtypes = [gp, dp, pp, ctypes.c_double, dp, dp, dp]
+        L.or_project.argtypes = [gp, pp, dp, dp, dp]
+        L.or_coarse_grid.restype = Grid
+        L.or_coarse_grid.argtypes = [gp]
+        L.or_num_levels.restype = ctypes.c_int32
+        L.or_num_levels.argtypes = [gp, pp]
+        L.or_vcycle.argtypes = [gp, dp, pp, ctypes.c_double, dp, dp, dp]
+        L.or_step.restype = ctypes.c_int32
+        L.or_step.argtypes = [gp, dp, pp, dp, ctypes.c_int32, ctypes.POINTER(Info), dp, ctypes.c_int32]
+        L.or_threads.restype = ctypes.c_int32
+        _lib = L
+    return _lib
+
+
+def _p(a: np.ndarray):
+    assert a.dtype == np.float64 and a.flags.c_contiguous
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def make_grid(problem: dict) -> Grid:
+    """Oracle grid struct from a problem description dict (see paper_2208_14703_amd.inputs)."""
+    g = Grid()
+    g.dim, g.nx, g.ny = problem["dim"], problem["nx"], problem["ny"]
+    g.hx, g.hy, g.dt = problem["hx"], problem["hy"], problem["dt"]
+    g.c, g.a_r, g.c_v = problem["c"], problem["a_r"], problem["c_v"]
+    for s, bc in enumerate(problem["bc"]):
+        g.bc_kind[s] = BC[bc["kind"]]
+        g.bc_E[s], g.bc_Fx[s], g.bc_Fy[s] = bc.get("E", 0.0), bc.get("Fx", 0.0), bc.get("Fy", 0.0)
+    return g
+
+
+def make_params(**kw) -> Params:
+    """Oracle solver parameters.
+
+    Defaults: the paper's nu0=3, m=3, nu_l=1, dtau_im=1e-3 and undamped Jacobi
+    (omega=1), with the local pseudo-time step reading (pseudo_local=1).
+    """
+    d = dict(levels=0, nu0=3, nu_l=1, pseudo_steps=3, sub_steps=4, max_cycles=10000, dtau_rule="signed",
+             pseudo_local=1, dtau_im0=1e-3, eps_inc=0.05, eps_dec=0.0, eta=0.9, rtol=1e-10, dtau_min=1e-6,
+             dtau_max=1e6, omega=1.0)
+    d.update(kw)
+    p = Params()
+    for k, v in d.items():
+        setattr(p, k, DTAU_RULE[v] if k == "dtau_rule" else v)
+    return p
+
+
+class Oracle:
+    """Thin numpy-facing wrapper over the C oracle for one grid level."""
+
+    def __init__(self, problem: dict, sigma: np.ndarray | None = None):
+        self.problem = problem
+        self.g = make_grid(problem)
+        self.L = lib()
+        ny, nx = problem["ny"], problem["nx"]
+        self.sigma = np.ascontiguousarray(sigma if sigma is not None else np.zeros((2, ny, nx)), dtype=np.float64)
+
+    # -- helpers
+    def _new(self, nfield=4, g=None):
+        g = g or self.g
+        return np.zeros((nfield, g.ny, g.nx))
+
+    @staticmethod
+    def _c(a):
+        return np.ascontiguousarray(a, dtype=np.float64)
+
+    def rhs(self, v):
+        b = self._c(v).copy()
+        b[3] *= self.g.c_v
+        return b
+
+    def apply_A(self, v, sigma=None, g=None):
+        g = g or self.g
+        s = self.sigma if sigma is None else self._c(sigma)
+        out = self._new(g=g)
+        self.L.or_apply_A(ctypes.byref(g), _p(s), _p(self._c(v)), _p(out))
+        return out
+
+    def residual(self, b, v):
+        r = self._new()
+        self.L.or_residual(ctypes.byref(self.g), _p(self.sigma), _p(self._c(b)), _p(self._c(v)), _p(r))
+        return r
+
+    def norm(self, r, g=None):
+        g = g or self.g
+        return self.L.or_norm(ctypes.byref(g), _p(self._c(r)))
+
+    def jacobi(self, rhs, v, beta=0.0, gamma=1.0, sigma=None, g=None, gamma_cell=None):
+        g = g or self.g
+        s = self.sigma if sigma is None else self._c(sigma)
+        out = self._new(g=g)
+        gc = _p(self._c(gamma_cell)) if gamma_cell is not None else None
+        self.L.or_jacobi(ctypes.byref(g), _p(s), beta, gamma, gc, _p(self._c(rhs)), _p(self._c(v)), _p(out))
+        return out
+
+    def sweep(self, b, v, omega=1.0):
+        out = self._new()
+        self.L.or_sweep(ctypes.byref(self.g), _p(self.sigma), omega, _p(self._c(b)), _p(self._c(v)), _p(out))
+        return out
+
+    def coarse_grid(self, g=None):
+        return self.L.or_coarse_grid(ctypes.byref(g or self.g))
+
+    def restrict(self, x, g=None):
+        g = g or self.g
+        x = self._c(x)
+        cg = self.coarse_grid(g)
+        out = np.zeros((x.shape[0], cg.ny, cg.nx))
+        self.L.or_restrict(ctypes.byref(g), _p(x), x.shape[0], _p(out))
+        return out
+
+    def prolong(self, xc, g=None):
+        g = g or self.g
+        xc = self._c(xc)
+        out = np.zeros((xc.shape[0], g.ny, g.nx))
+        self.L.or_prolong(ctypes.byref(g), _p(xc), xc.shape[0], _p(out))
+        return out
+
+    def pseudo_step(self, f, u, dtau, params=None, sigma=None, g=None):
+        g = g or self.g
+        p = params or make_params()
+        s = self.sigma if sigma is None else self._c(sigma)
+        out = self._new(g=g)
+        self.L.or_pseudo_step(ctypes.byref(g), _p(s), ctypes.byref(p), dtau, _p(self._c(f)), _p(self._c(u)),
+                              _p(out))
+        return out
+
+    def project(self, u, w, params=None, g=None):
+        g = g or self.g
+        p = params or make_params()
+        out = self._new(g=g)
+        self.L.or_project(ctypes.byref(g), ctypes.byref(p), _p(self._c(u)), _p(self._c(w)), _p(out))
+        return out
+
+    def num_levels(self, params=None):
+        return self.L.or_num_levels(ctypes.byref(self.g), ctypes.byref(params or make_params()))
+
+    def vcycle(self, b, v, dtau, params=None):
+        p = params or make_params()
+        out = self._new()
+        self.L.or_vcycle(ctypes.byref(self.g), _p(self.sigma), ctypes.byref(p), dtau, _p(self._c(b)),
+                         _p(self._c(v)), _p(out))
+        return out
+
+    def step(self, v, nsteps=1, params=None, history_len=100000):
+        p = params or make_params()
+        v = self._c(v).copy()
+        info = Info()
+        hist = np.zeros(history_len)
+        st = self.L.or_step(ctypes.byref(self.g), _p(self.sigma), ctypes.byref(p), _p(v), nsteps,
+                            ctypes.byref(info), _p(hist), history_len)
+        n = min(info.cycles, history_len)
+        return v, {"status": st, "cycles": info.cycles, "levels": info.levels, "r0": info.r0,
+                   "rel_residual": info.rel_residual, "dtau": info.dtau, "history": hist[:n].copy()}
+
+
+def chi(f: float) -> float:
+    return lib().or_chi(f)
+
+
+def closure(E, Fx, Fy, c=1.0):
+    P = np.zeros(3)
+    lib().or_closure(E, Fx, Fy, c, _p(P))
+    return P
+
+
+def local_solve(beta, gamma, a, ka, ks, cv, ar, B):
+    B = np.ascontiguousarray(B, dtype=np.float64)
+    out = np.zeros(4)
+    lib().or_local_solve(beta, gamma, a, ka, ks, cv, ar, _p(B), _p(out))
+    return out
+
+
+def ray(c, w, s):
+    return lib().or_ray(c, _p(np.ascontiguousarray(w, dtype=np.float64)), _p(np.ascontiguousarray(s, dtype=np.float64)))
+
+
+def admissible(c, w):
+    return bool(lib().or_admissible(c, _p(np.ascontiguousarray(w, dtype=np.float64))))
+
+
+def threads() -> int:
+    return lib().or_threads()

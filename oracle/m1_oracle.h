@@ -1,0 +1,88 @@
+/*
+ * m1_oracle.h -- TEST INFRASTRUCTURE ONLY.
+ *
+ * Plain, slow, FP64 CPU oracle of the implicit M1 radiative-transfer
+ * multigrid method of Bloch, Tremblin, Gonzalez & Audit, "Towards a multigrid
+ * method for the M1 model for radiative transfer" (arXiv 2208.14703).
+ *
+ * Only the test suite, the smoke check and the CPU-baseline leg of the
+ * benchmark may load this library.  The GPU product path never includes this
+ * header, never links this code and shares no helper with it.
+ *
+ * Layout conventions (the oracle's own):
+ *   a state is one contiguous double array of 4*nx*ny values holding the
+ *   fields E, Fx, Fy, T one after the other, each row-major with x fastest;
+ *   an opacity array holds sigma_a then sigma_s (2*nx*ny values).
+ * In one dimension ny == 1 and the Fy field stays identically zero.
+ */
+#ifndef M1_ORACLE_H
+#define M1_ORACLE_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum { OR_BC_PERIODIC = 0, OR_BC_REFLECTIVE = 1, OR_BC_NEUMANN = 2, OR_BC_DIRICHLET = 3 };
+enum { OR_DTAU_SIGNED = 0, OR_DTAU_LITERAL = 1 };
+
+typedef struct {
+    int32_t dim, nx, ny, pad_;
+    double hx, hy, dt, c, a_r, c_v;
+    int32_t bc_kind[4];              /* sides x-, x+, y-, y+ */
+    double bc_E[4], bc_Fx[4], bc_Fy[4]; /* Dirichlet ghost state per side */
+} or_grid;
+
+typedef struct {
+    int32_t levels;        /* total number of levels incl. the finest; 0 = down to side 4 */
+    int32_t nu0;           /* Jacobi sweeps before and after the correction, finest level */
+    int32_t nu_l;          /* Jacobi sweeps per implicit pseudo-time step, coarse levels */
+    int32_t pseudo_steps;  /* pseudo-time steps per coarse smoothing */
+    int32_t sub_steps;     /* max explicit sub-steps per pseudo-time step */
+    int32_t max_cycles;
+    int32_t dtau_rule;     /* OR_DTAU_SIGNED or OR_DTAU_LITERAL */
+    int32_t pseudo_local;  /* 1: implicit pseudo-time step uses each cell's own tau_i; 0: dtau_im everywhere */
+    double dtau_im0, eps_inc, eps_dec, eta, rtol, dtau_min, dtau_max;
+    double omega;          /* relaxation weight of the finest-level Jacobi sweeps (1 = Algorithm 1) */
+} or_params;
+
+typedef struct {
+    int32_t cycles, status, levels, pad_;
+    double r0, rel_residual, dtau;
+} or_info;
+
+/* single-cell pieces */
+double or_chi(double f);
+void   or_closure(double E, double Fx, double Fy, double c, double P[3]);
+void   or_local_solve(double beta, double gamma, double a, double ka, double ks, double cv, double ar,
+                      const double B[4], double out[4]);
+double or_ray(double c, const double w[4], const double s[4]);
+int    or_admissible(double c, const double w[4]);
+
+/* grid operators (one level, spacing taken from g) */
+void   or_apply_A(const or_grid* g, const double* sigma, const double* v, double* out);
+void   or_residual(const or_grid* g, const double* sigma, const double* b, const double* v, double* r);
+double or_norm(const or_grid* g, const double* r);
+void   or_jacobi(const or_grid* g, const double* sigma, double beta, double gamma, const double* gamma_cell,
+                 const double* rhs, const double* v_in, double* v_out);
+void   or_sweep(const or_grid* g, const double* sigma, double omega, const double* b, const double* v_in,
+                double* v_out);
+void   or_restrict(const or_grid* fine, const double* x_fine, int32_t nfields, double* x_coarse);
+void   or_prolong(const or_grid* fine, const double* x_coarse, int32_t nfields, double* x_fine);
+void   or_pseudo_step(const or_grid* g, const double* sigma, const or_params* p, double dtau,
+                      const double* f, const double* u_in, double* u_out);
+void   or_project(const or_grid* g, const or_params* p, const double* u, const double* w, double* out);
+or_grid or_coarse_grid(const or_grid* g);
+
+/* whole method */
+int32_t or_num_levels(const or_grid* g, const or_params* p);
+void   or_vcycle(const or_grid* g, const double* sigma, const or_params* p, double dtau,
+                 const double* b, const double* v, double* out);
+int32_t or_step(const or_grid* g, const double* sigma, const or_params* p, double* v, int32_t nsteps,
+                or_info* info, double* history, int32_t history_len);
+int32_t or_threads(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif
