@@ -91,7 +91,7 @@ def test_free_streaming_2d_beam_along_x():
     # F = (cE, 0): x is pure upwind, y keeps the Rusanov diffusion (alpha_y / 2).
     nx, ny, cfl = 16, 8, 6.0
     prob = inputs.grid_problem(2, nx, ny, cfl, inputs.bc_all("periodic"), length=1.0)
-    prob["hy"] = 0.5 / ny  # anisotropic cells: alpha_y != alpha_x catches an x/y swap
+    prob["hy"] = prob["hx"] / 2  # anisotropic cells: alpha_y = 2 alpha_x catches an x/y swap
     ax, ay = prob["c"] * prob["dt"] / prob["hx"], prob["c"] * prob["dt"] / prob["hy"]
     rng = np.random.default_rng(5)
     En = rng.uniform(1, 3, (ny, nx))
