@@ -1,0 +1,186 @@
+/*
+ * m1.h -- C ABI of the MI355X (gfx950) implicit M1 radiative-transfer multigrid solver.
+ *
+ * Method: H. Bloch, P. Tremblin, M. Gonzalez, E. Audit, "Towards a multigrid
+ * method for the M1 model for radiative transfer" (arXiv 2208.14703).
+ *   - unknowns: gray radiative energy E, flux F = (Fx, Fy) and gas temperature T
+ *     (moments and M1 closure, Sect. 2.1);
+ *   - one implicit Euler step with the HLL flux at wave speeds +-c (Rusanov),
+ *     Sect. 2.2, extended to 2-D by directions, with absorption (sigma_a),
+ *     emission (a_r T^4), scattering (sigma_s) and gas energy C_v T implicit in
+ *     the diagonal block (the source terms of the moment system, Sect. 2.1);
+ *   - solved by the nonlinear FAS multigrid of Sect. 4 / Appendix A: Jacobi
+ *     smoothing on the finest level (Algorithm 1), full-weighting restriction
+ *     and linear prolongation (Sect. 4.2), coarse problems in pseudo-time with
+ *     explicit sub-steps and an implicit Jacobi step (Algorithm 3), the
+ *     admissibility-restoring correction (eq. prolongatedSol), and relative
+ *     residual stopping with pseudo-time step adaptation.
+ *
+ * Conventions for every entry point:
+ *   - all array pointers are HIP DEVICE pointers owned by the caller; fields are
+ *     separate arrays of nx*ny doubles, row-major with x fastest (cell (i,j) at
+ *     j*nx + i); in 1-D ny == 1 and Fy must be NULL;
+ *   - every call enqueues on the plan's stream; only m1_step, m1_residual,
+ *     m1_sync and the batch wait/poll calls block the host;
+ *   - no entry point allocates device memory: m1_plan_create carves the
+ *     caller-provided workspace; the plan itself is a small host object;
+ *   - argument errors are detected on the host, return immediately and enqueue
+ *     nothing; no C++ exception crosses the ABI;
+ *   - a plan is bound to one stream and is not thread-safe.
+ */
+#ifndef M1_H
+#define M1_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    M1_OK = 0,
+    M1_ERR_ARG = 1,             /* invalid argument (detected on the host, nothing enqueued) */
+    M1_ERR_NOT_ADMISSIBLE = 2,  /* input state has E <= 0, T <= 0, |F| > cE or a non-finite value */
+    M1_ERR_NO_CONVERGENCE = 3,  /* max_cycles reached; the state holds the last (admissible) iterate */
+    M1_ERR_WORKSPACE = 4,       /* workspace NULL, misaligned or smaller than m1_workspace_bytes() */
+    M1_ERR_DEVICE = 5,          /* a HIP runtime call failed */
+    M1_ERR_BUSY = 6,            /* engine queue full / request still running */
+    M1_ERR_BUDGET = 7           /* request larger than the engine's HBM budget */
+} m1_status;
+
+typedef enum { M1_BC_PERIODIC = 0, M1_BC_REFLECTIVE = 1, M1_BC_NEUMANN = 2, M1_BC_DIRICHLET = 3 } m1_bc_kind;
+typedef enum { M1_FP64 = 0, M1_MIXED = 1 } m1_precision;
+typedef enum { M1_DTAU_SIGNED = 0, M1_DTAU_LITERAL = 1 } m1_dtau_rule;
+
+/* Boundary condition of one side.  Ghost state of the neighbour outside the
+ * domain: PERIODIC wraps; REFLECTIVE mirrors the adjacent cell with its normal
+ * flux negated; NEUMANN copies the adjacent cell; DIRICHLET uses (E, Fx, Fy),
+ * which must be admissible.  Periodic sides come in pairs (x-/x+, y-/y+).   */
+typedef struct {
+    int32_t kind;
+    int32_t pad_;
+    double E, Fx, Fy;
+} m1_bc;
+
+/* Discrete problem: the data of the implicit HLL system (Sect. 2.2) plus the
+ * source coefficients.  dt is the physical step (CFL*h/c in the paper's
+ * notation), hx/hy the cell sizes, c the light speed, a_r the radiation
+ * constant, c_v the gas heat capacity per volume (> 0).
+ * bc[] order: x-, x+, y-, y+ (y sides ignored in 1-D).                       */
+typedef struct {
+    int32_t dim, nx, ny, pad_;
+    double hx, hy, dt, c, a_r, c_v;
+    m1_bc bc[4];
+} m1_grid;
+
+/* Solver parameters (m1_default_params gives the paper's: nu0 = 3, pseudo-time
+ * steps m = 3, nu_l = 1, dtau_im0 = 1e-3).
+ *   levels        total levels including the finest; 0 = coarsen while both
+ *                 sides stay even and >= 4 (1 = plain Jacobi, Sect. 5.1);
+ *   nu0           finest-level Jacobi sweeps before and after the correction;
+ *   nu_l          Jacobi sweeps per implicit pseudo-time step (coarse levels);
+ *   pseudo_steps  pseudo-time steps per coarse smoothing (Algorithm 3);
+ *   sub_steps     max explicit sub-steps per pseudo-time step; each covers
+ *                 eta times the remaining admissible length of its ray;
+ *   max_cycles    V-cycles per time step before M1_ERR_NO_CONVERGENCE;
+ *   dtau_rule     pseudo-time step adaptation: SIGNED (relative decrease of the
+ *                 residual vs the previous cycle) or LITERAL (|change| / r0);
+ *   pseudo_local  1: the implicit pseudo-time step of each cell uses the pseudo
+ *                 time its explicit sub-steps reached (consistent steady state);
+ *                 0: dtau_im in every cell;
+ *   precision     M1_FP64 or M1_MIXED (FP32 delta-form smoothing and coarse
+ *                 levels, FP64 residual, projection and T^4 update);
+ *   dtau_im0      initial implicit pseudo-time step (reset every time step);
+ *   eps_inc/dec   adaptation thresholds (x1.1 above eps_inc, /2 below eps_dec);
+ *   eta           fraction of the admissible ray used (sub-steps, projection);
+ *   rtol          stop when |b - A(v)| <= rtol |b - A(v^n)|;
+ *   dtau_min/max  clamp of dtau_im;
+ *   omega         relaxation of the finest-level sweeps: u <- u + omega (J(u) - u);
+ *                 1 is Algorithm 1, 0 < omega <= 1 keeps admissibility.      */
+typedef struct {
+    int32_t levels, nu0, nu_l, pseudo_steps, sub_steps, max_cycles, dtau_rule, pseudo_local, precision, pad_;
+    double dtau_im0, eps_inc, eps_dec, eta, rtol, dtau_min, dtau_max, omega;
+} m1_params;
+
+/* State (E, Fx, Fy, T), device pointers, nx*ny each; Fy == NULL in 1-D. */
+typedef struct {
+    double *E, *Fx, *Fy, *T;
+} m1_state;
+
+/* Opacities per cell (>= 0, finite), device pointers; must outlive the plan. */
+typedef struct {
+    const double *sigma_a, *sigma_s;
+} m1_opacity;
+
+/* Result of m1_step.  cycles: total V-cycles over all steps; rel_residual and
+ * r0: of the last step; first_bad_cell: index of the first non-admissible
+ * input cell (or -1); status: as returned.                                   */
+typedef struct {
+    int32_t cycles, status, levels, steps_done;
+    double r0, rel_residual, dtau;
+    int64_t first_bad_cell;
+} m1_info;
+
+typedef struct m1_plan m1_plan;
+
+const char* m1_strerror(m1_status s);
+
+/* Fill p with the paper's parameters (see m1_params). */
+void m1_default_params(m1_params* p);
+
+/* Bytes of device workspace a plan needs (0 on invalid arguments). */
+size_t m1_workspace_bytes(const m1_grid* g, const m1_params* p);
+
+/* Build the level hierarchy (coarse opacities by full weighting of the fine
+ * ones) inside `workspace` (device memory, 256-byte aligned, at least
+ * m1_workspace_bytes bytes).  `stream` is a hipStream_t (NULL = default).
+ * Opacities are validated (M1_ERR_ARG if negative or non-finite).  The plan
+ * keeps pointers to `op` arrays and `workspace`; both must outlive it.        */
+m1_status m1_plan_create(const m1_grid* g, const m1_params* p, const m1_opacity* op, void* workspace,
+                         size_t workspace_bytes, void* stream, m1_plan** out);
+void m1_plan_destroy(m1_plan* plan);
+int32_t m1_plan_levels(const m1_plan* plan);
+m1_status m1_level_dims(const m1_plan* plan, int32_t level, int32_t* nx, int32_t* ny);
+
+/* Residual of eq. (defResidual) on the finest level, r = b - A(v) with
+ * b = (E^n, F^n, C_v T^n) taken from `vn`.  Writes the discrete L2 norm of
+ * (r_E, r_Fx/c, r_Fy/c, r_T) to *norm_out (host pointer; blocks), and the
+ * residual fields to r_out when it is not NULL.                              */
+m1_status m1_residual(m1_plan* plan, const m1_state* v, const m1_state* vn, double* norm_out, m1_state* r_out);
+
+/* One V-cycle (Appendix A) of the time step whose initial state is `vn`,
+ * updating the iterate `v` in place, with implicit pseudo-time step dtau.
+ * Asynchronous.  v must not alias vn.                                        */
+m1_status m1_vcycle(m1_plan* plan, m1_state* v, const m1_state* vn, double dtau);
+
+/* nsteps implicit Euler steps: v holds v^n on entry and v^{n+nsteps} on exit.
+ * Each step runs V-cycles until the relative residual reaches rtol, adapting
+ * dtau_im after every cycle.  Validates the input state first.  Blocks.       */
+m1_status m1_step(m1_plan* plan, m1_state* v, int32_t nsteps, m1_info* info);
+
+/* ---- single operations of the cycle on one level (parity checks, custom drivers) ---- */
+
+/* out = A_l(v) on level `level` (spacing 2^level h, opacities of that level). */
+m1_status m1_apply_A(m1_plan* plan, int32_t level, const m1_state* v, m1_state* out);
+/* One relaxed Jacobi sweep of A_0(u) = b on the finest level (Algorithm 1 with
+ * weight omega from the plan's params): v_out = v_in + omega (J(v_in) - v_in). */
+m1_status m1_sweep(m1_plan* plan, const m1_state* b, const m1_state* v_in, m1_state* v_out);
+/* One pseudo-time step (Algorithm 3) of M du/dtau + A_l(u) = f on level `level`
+ * (level >= 1 in the cycle; any level accepted), from u_in to u_out.          */
+m1_status m1_pseudo_step(m1_plan* plan, int32_t level, double dtau, const m1_state* f, const m1_state* u_in,
+                         m1_state* u_out);
+/* Full-weighting restriction (Sect. 4.2) of a state from `level` to level+1.  */
+m1_status m1_restrict(m1_plan* plan, int32_t level, const m1_state* fine, m1_state* coarse);
+/* Correction of `level` from level+1 with admissibility (eq. prolongatedSol):
+ * w = u + P(uc - vc); out = w where admissible, else u + eta tau*(u, w-u) (w-u).
+ * out may alias u.                                                           */
+m1_status m1_prolong_project(m1_plan* plan, int32_t level, const m1_state* u, const m1_state* uc,
+                             const m1_state* vc, m1_state* out);
+/* Wait for all work enqueued on the plan's stream. */
+m1_status m1_sync(m1_plan* plan);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* M1_H */

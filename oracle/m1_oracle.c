@@ -16,6 +16,7 @@
  */
 #include "m1_oracle.h"
 
+#include <float.h>
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
@@ -699,8 +700,11 @@ static double adapt_dtau(const or_params* p, double dtau, double r0, double rpre
 
 /* Implicit Euler time steps, each solved by V-cycles until
  * |b - A(v)| <= rtol |b - A(v^n)| (relative residual of Sect. 5), with
- * b = (E^n, F^n, C_v T^n) and the initial guess v^n.  Returns 0 on success,
- * 3 when max_cycles was reached (v then holds the last iterate).           */
+ * b = (E^n, F^n, C_v T^n) and the initial guess v^n.  A residual at the
+ * rounding level of evaluating A, 16 eps a |b| (a = 1 + c dt/hx + c dt/hy),
+ * also counts as converged, so an exact solution takes zero cycles.
+ * Returns 0 on success, 3 when max_cycles was reached (v then holds the last
+ * iterate).                                                                 */
 int32_t or_step(const or_grid* g, const double* sigma, const or_params* p, double* v, int32_t nsteps, or_info* info,
                 double* history, int32_t history_len)
 {
@@ -716,8 +720,9 @@ int32_t or_step(const or_grid* g, const double* sigma, const or_params* p, doubl
         dtau = p->dtau_im0;
         or_residual(g, sigma, b, v, r);
         r0 = or_norm(g, r);
+        const double floor_r = 16.0 * DBL_EPSILON * diag_a(g) * or_norm(g, b);
         rel = 0.0;
-        if (r0 == 0.0) continue;
+        if (r0 <= floor_r) continue;
         double rprev = r0;
         int conv = 0;
         for (int kc = 1; kc <= p->max_cycles; ++kc) {
@@ -730,7 +735,7 @@ int32_t or_step(const or_grid* g, const double* sigma, const or_params* p, doubl
             if (history && hpos < history_len) history[hpos++] = rel;
             dtau = adapt_dtau(p, dtau, r0, rprev, rk);
             rprev = rk;
-            if (rel <= p->rtol) {
+            if (rel <= p->rtol || rk <= floor_r) {
                 conv = 1;
                 break;
             }

@@ -1,0 +1,261 @@
+"""Thin ctypes binding over libm1mg.so (include/m1.h).
+
+The binding only marshals arguments. Every step of the solver runs in the HIP
+library. PyTorch supplies device memory (float64 tensors) and the current HIP
+stream.
+
+State tensors are float64 of shape (4, ny, nx) holding E, Fx, Fy, T. In 1-D the
+shape is (4, 1, nx) and the Fy plane is not passed to the library (NULL).
+Opacity tensors are float64 of shape (2, ny, nx) holding sigma_a, sigma_s.
+
+Importing this module does not load the library. The first call that needs it
+loads it and raises RuntimeError when it is missing: there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "_lib", "libm1mg.so")
+
+BC = {"periodic": 0, "reflective": 1, "neumann": 2, "dirichlet": 3}
+PRECISION = {"fp64": 0, "mixed": 1}
+DTAU_RULE = {"signed": 0, "literal": 1}
+STATUS = {0: "M1_OK", 1: "M1_ERR_ARG", 2: "M1_ERR_NOT_ADMISSIBLE", 3: "M1_ERR_NO_CONVERGENCE", 4: "M1_ERR_WORKSPACE",
+          5: "M1_ERR_DEVICE", 6: "M1_ERR_BUSY", 7: "M1_ERR_BUDGET"}
+
+
+class M1Error(RuntimeError):
+    def __init__(self, status: int, what: str):
+        super().__init__(f"{what}: {STATUS.get(status, status)}")
+        self.status = status
+
+
+class m1_bc(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("pad_", ctypes.c_int32), ("E", ctypes.c_double), ("Fx", ctypes.c_double),
+                ("Fy", ctypes.c_double)]
+
+
+class m1_grid(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_int32), ("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("pad_", ctypes.c_int32),
+                ("hx", ctypes.c_double), ("hy", ctypes.c_double), ("dt", ctypes.c_double), ("c", ctypes.c_double),
+                ("a_r", ctypes.c_double), ("c_v", ctypes.c_double), ("bc", m1_bc * 4)]
+
+
+class m1_params(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_int32) for n in ("levels", "nu0", "nu_l", "pseudo_steps", "sub_steps", "max_cycles",
+                                              "dtau_rule", "pseudo_local", "precision", "pad_")] + \
+               [(n, ctypes.c_double) for n in ("dtau_im0", "eps_inc", "eps_dec", "eta", "rtol", "dtau_min",
+                                               "dtau_max", "omega")]
+
+
+class m1_state(ctypes.Structure):
+    _fields_ = [("E", ctypes.c_void_p), ("Fx", ctypes.c_void_p), ("Fy", ctypes.c_void_p), ("T", ctypes.c_void_p)]
+
+
+class m1_opacity(ctypes.Structure):
+    _fields_ = [("sigma_a", ctypes.c_void_p), ("sigma_s", ctypes.c_void_p)]
+
+
+class m1_info(ctypes.Structure):
+    _fields_ = [("cycles", ctypes.c_int32), ("status", ctypes.c_int32), ("levels", ctypes.c_int32),
+                ("steps_done", ctypes.c_int32), ("r0", ctypes.c_double), ("rel_residual", ctypes.c_double),
+                ("dtau", ctypes.c_double), ("first_bad_cell", ctypes.c_int64)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libm1mg.so (raises when it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_2208_14703_amd.build.build() "
+                               "(there is no CPU fallback)")
+        L = ctypes.CDLL(LIB_PATH)
+        P = ctypes.POINTER
+        vp = ctypes.c_void_p
+        L.m1_strerror.restype = ctypes.c_char_p
+        L.m1_strerror.argtypes = [ctypes.c_int]
+        L.m1_default_params.argtypes = [P(m1_params)]
+        L.m1_workspace_bytes.restype = ctypes.c_size_t
+        L.m1_workspace_bytes.argtypes = [P(m1_grid), P(m1_params)]
+        L.m1_plan_create.argtypes = [P(m1_grid), P(m1_params), P(m1_opacity), vp, ctypes.c_size_t, vp, P(vp)]
+        L.m1_plan_destroy.argtypes = [vp]
+        L.m1_plan_levels.restype = ctypes.c_int32
+        L.m1_plan_levels.argtypes = [vp]
+        L.m1_level_dims.argtypes = [vp, ctypes.c_int32, P(ctypes.c_int32), P(ctypes.c_int32)]
+        L.m1_residual.argtypes = [vp, P(m1_state), P(m1_state), P(ctypes.c_double), P(m1_state)]
+        L.m1_vcycle.argtypes = [vp, P(m1_state), P(m1_state), ctypes.c_double]
+        L.m1_step.argtypes = [vp, P(m1_state), ctypes.c_int32, P(m1_info)]
+        L.m1_apply_A.argtypes = [vp, ctypes.c_int32, P(m1_state), P(m1_state)]
+        L.m1_sweep.argtypes = [vp, P(m1_state), P(m1_state), P(m1_state)]
+        L.m1_pseudo_step.argtypes = [vp, ctypes.c_int32, ctypes.c_double, P(m1_state), P(m1_state), P(m1_state)]
+        L.m1_restrict.argtypes = [vp, ctypes.c_int32, P(m1_state), P(m1_state)]
+        L.m1_prolong_project.argtypes = [vp, ctypes.c_int32, P(m1_state), P(m1_state), P(m1_state), P(m1_state)]
+        L.m1_sync.argtypes = [vp]
+        for name in ("m1_plan_create", "m1_residual", "m1_vcycle", "m1_step", "m1_apply_A", "m1_sweep",
+                     "m1_pseudo_step", "m1_restrict", "m1_prolong_project", "m1_sync", "m1_level_dims"):
+            getattr(L, name).restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _check(status: int, what: str):
+    if status != 0:
+        raise M1Error(status, what)
+
+
+def make_grid(problem: dict) -> m1_grid:
+    g = m1_grid()
+    g.dim, g.nx, g.ny = problem["dim"], problem["nx"], problem["ny"]
+    g.hx, g.hy, g.dt = problem["hx"], problem["hy"], problem["dt"]
+    g.c, g.a_r, g.c_v = problem["c"], problem["a_r"], problem["c_v"]
+    for s, bc in enumerate(problem["bc"]):
+        g.bc[s].kind = BC[bc["kind"]]
+        g.bc[s].E, g.bc[s].Fx, g.bc[s].Fy = bc.get("E", 0.0), bc.get("Fx", 0.0), bc.get("Fy", 0.0)
+    return g
+
+
+def default_params(**kw) -> dict:
+    """The paper's solver parameters (see m1_params in include/m1.h), updated with kw."""
+    p = m1_params()
+    lib().m1_default_params(ctypes.byref(p))
+    d = {name: getattr(p, name) for name, _ in m1_params._fields_ if name != "pad_"}
+    d["dtau_rule"] = "signed"
+    d["precision"] = "fp64"
+    d.update(kw)
+    return d
+
+
+def make_params(d: dict) -> m1_params:
+    p = m1_params()
+    for k, v in d.items():
+        if k == "precision":
+            v = PRECISION[v] if isinstance(v, str) else v
+        elif k == "dtau_rule":
+            v = DTAU_RULE[v] if isinstance(v, str) else v
+        setattr(p, k, v)
+    return p
+
+
+def _stream_handle(stream) -> int:
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return s.cuda_stream
+
+
+class Plan:
+    """A solver plan for one grid: level hierarchy in a torch-allocated workspace."""
+
+    def __init__(self, problem: dict, sigma, params: dict | None = None, stream=None):
+        import torch
+        self.torch = torch
+        self.problem = problem
+        self.dim = problem["dim"]
+        self.grid = make_grid(problem)
+        self.params_d = default_params(**(params or {}))
+        self.params = make_params(self.params_d)
+        L = lib()
+        self.sigma = sigma.contiguous()
+        assert self.sigma.dtype == torch.float64 and self.sigma.is_cuda
+        assert tuple(self.sigma.shape) == (2, problem["ny"], problem["nx"])
+        nbytes = L.m1_workspace_bytes(ctypes.byref(self.grid), ctypes.byref(self.params))
+        if nbytes == 0:
+            raise M1Error(1, "m1_workspace_bytes")
+        self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.sigma.device)
+        base = self.workspace.data_ptr()
+        off = (-base) % 256
+        self.ws_ptr, self.ws_bytes = base + off, nbytes
+        op = m1_opacity(self.sigma[0].data_ptr(), self.sigma[1].data_ptr())
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.sigma.device)
+        h = ctypes.c_void_p()
+        _check(L.m1_plan_create(ctypes.byref(self.grid), ctypes.byref(self.params), ctypes.byref(op),
+                                ctypes.c_void_p(self.ws_ptr), self.ws_bytes, ctypes.c_void_p(self.stream.cuda_stream),
+                                ctypes.byref(h)), "m1_plan_create")
+        self.handle = h
+        self.levels = L.m1_plan_levels(h)
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and _lib is not None:
+            _lib.m1_plan_destroy(h)
+            self.handle = None
+
+    # ---- helpers
+    def level_dims(self, level: int):
+        nx, ny = ctypes.c_int32(), ctypes.c_int32()
+        _check(lib().m1_level_dims(self.handle, level, ctypes.byref(nx), ctypes.byref(ny)), "m1_level_dims")
+        return nx.value, ny.value
+
+    def new_state(self, level: int = 0):
+        nx, ny = self.level_dims(level)
+        return self.torch.zeros((4, ny, nx), dtype=self.torch.float64, device=self.sigma.device)
+
+    def _st(self, t) -> m1_state:
+        assert t.dtype == self.torch.float64 and t.is_cuda and t.is_contiguous() and t.shape[0] == 4
+        return m1_state(t[0].data_ptr(), t[1].data_ptr(), t[2].data_ptr() if self.dim == 2 else None,
+                        t[3].data_ptr())
+
+    # ---- the C ABI
+    def step(self, v, nsteps: int = 1) -> dict:
+        info = m1_info()
+        st = lib().m1_step(self.handle, ctypes.byref(self._st(v)), nsteps, ctypes.byref(info))
+        out = {"status": st, "cycles": info.cycles, "levels": info.levels, "steps_done": info.steps_done,
+               "r0": info.r0, "rel_residual": info.rel_residual, "dtau": info.dtau,
+               "first_bad_cell": info.first_bad_cell}
+        if st not in (0, 3):
+            raise M1Error(st, f"m1_step {out}")
+        return out
+
+    def vcycle(self, v, vn, dtau: float):
+        _check(lib().m1_vcycle(self.handle, ctypes.byref(self._st(v)), ctypes.byref(self._st(vn)), dtau), "m1_vcycle")
+
+    def residual(self, v, vn, want_r: bool = False):
+        r = self.torch.zeros_like(v) if want_r else None
+        norm = ctypes.c_double()
+        _check(lib().m1_residual(self.handle, ctypes.byref(self._st(v)), ctypes.byref(self._st(vn)),
+                                 ctypes.byref(norm), ctypes.byref(self._st(r)) if want_r else None), "m1_residual")
+        return (norm.value, r) if want_r else norm.value
+
+    def apply_A(self, level: int, v):
+        out = self.new_state(level)
+        _check(lib().m1_apply_A(self.handle, level, ctypes.byref(self._st(v)), ctypes.byref(self._st(out))),
+               "m1_apply_A")
+        return out
+
+    def sweep(self, b, v):
+        out = self.torch.zeros_like(v)
+        _check(lib().m1_sweep(self.handle, ctypes.byref(self._st(b)), ctypes.byref(self._st(v)),
+                              ctypes.byref(self._st(out))), "m1_sweep")
+        return out
+
+    def pseudo_step(self, level: int, dtau: float, f, u):
+        out = self.new_state(level)
+        _check(lib().m1_pseudo_step(self.handle, level, dtau, ctypes.byref(self._st(f)), ctypes.byref(self._st(u)),
+                                    ctypes.byref(self._st(out))), "m1_pseudo_step")
+        return out
+
+    def restrict(self, level: int, x):
+        out = self.new_state(level + 1)
+        _check(lib().m1_restrict(self.handle, level, ctypes.byref(self._st(x)), ctypes.byref(self._st(out))),
+               "m1_restrict")
+        return out
+
+    def prolong_project(self, level: int, u, uc, vc, out=None):
+        out = self.torch.zeros_like(u) if out is None else out
+        _check(lib().m1_prolong_project(self.handle, level, ctypes.byref(self._st(u)), ctypes.byref(self._st(uc)),
+                                        ctypes.byref(self._st(vc)), ctypes.byref(self._st(out))), "m1_prolong_project")
+        return out
+
+    def sync(self):
+        _check(lib().m1_sync(self.handle), "m1_sync")
+
+
+def to_device(a: np.ndarray, device="cuda"):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).to(device)

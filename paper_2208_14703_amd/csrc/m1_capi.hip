@@ -1,0 +1,610 @@
+// m1_capi.hip -- plan (level hierarchy carved from caller workspace), the
+// V-cycle / time-step drivers and the C ABI declared in include/m1.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cfloat>
+#include <climits>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "../../include/m1.h"
+#include "m1_internal.hpp"
+
+namespace {
+
+using m1::CSoa;
+using m1::cs;
+using m1::Soa;
+
+constexpr size_t kAlign = 256;
+
+struct LevelBuf {
+    int nx = 0, ny = 0;
+    int64_t n = 0;
+    double hx = 0, hy = 0;
+    m1::Lvl L{};
+    Soa v{}, u{}, u2{}, f{}, rb{}, rt{};
+    double* g = nullptr;
+    double* sa = nullptr;
+    double* ss = nullptr;
+};
+
+// Level sizes: coarsen while every active side stays even and >= 4 after
+// halving (levels == 0), or exactly `levels` levels when possible.
+bool level_dims(const m1_grid& g, const m1_params& p, std::vector<int>& nxs, std::vector<int>& nys)
+{
+    nxs.assign(1, g.nx);
+    nys.assign(1, g.dim == 2 ? g.ny : 1);
+    for (;;) {
+        if (p.levels > 0 && (int)nxs.size() >= p.levels) break;
+        int nx = nxs.back(), ny = nys.back();
+        bool ok = (nx % 2 == 0) && nx / 2 >= 4;
+        if (g.dim == 2) ok = ok && (ny % 2 == 0) && ny / 2 >= 4;
+        if (!ok) break;
+        nxs.push_back(nx / 2);
+        nys.push_back(g.dim == 2 ? ny / 2 : 1);
+    }
+    return p.levels <= 0 || (int)nxs.size() == p.levels;
+}
+
+bool valid_bc(const m1_grid& g)
+{
+    for (int s = 0; s < (g.dim == 2 ? 4 : 2); ++s) {
+        const m1_bc& b = g.bc[s];
+        if (b.kind < M1_BC_PERIODIC || b.kind > M1_BC_DIRICHLET) return false;
+        if (b.kind == M1_BC_DIRICHLET) {
+            if (!(std::isfinite(b.E) && std::isfinite(b.Fx) && std::isfinite(b.Fy) && b.E > 0.0)) return false;
+            if (std::sqrt(b.Fx * b.Fx + (g.dim == 2 ? b.Fy * b.Fy : 0.0)) > g.c * b.E) return false;
+        }
+    }
+    if ((g.bc[0].kind == M1_BC_PERIODIC) != (g.bc[1].kind == M1_BC_PERIODIC)) return false;
+    if (g.dim == 2 && (g.bc[2].kind == M1_BC_PERIODIC) != (g.bc[3].kind == M1_BC_PERIODIC)) return false;
+    return true;
+}
+
+bool valid_grid(const m1_grid* g)
+{
+    if (!g) return false;
+    if (g->dim != 1 && g->dim != 2) return false;
+    if (g->nx < 1 || g->ny < 1 || (g->dim == 1 && g->ny != 1)) return false;
+    if ((int64_t)g->nx * g->ny > (int64_t)INT32_MAX * 8) return false;
+    auto pos = [](double x) { return std::isfinite(x) && x > 0.0; };
+    if (!pos(g->hx) || !pos(g->dt) || !pos(g->c) || !pos(g->c_v)) return false;
+    if (g->dim == 2 && !pos(g->hy)) return false;
+    if (!(std::isfinite(g->a_r) && g->a_r >= 0.0)) return false;
+    return valid_bc(*g);
+}
+
+bool valid_params(const m1_params* p)
+{
+    if (!p) return false;
+    if (p->levels < 0 || p->nu0 < 1 || p->nu_l < 1 || p->pseudo_steps < 1 || p->sub_steps < 1 || p->max_cycles < 1)
+        return false;
+    if (p->dtau_rule != M1_DTAU_SIGNED && p->dtau_rule != M1_DTAU_LITERAL) return false;
+    if (p->precision != M1_FP64 && p->precision != M1_MIXED) return false;
+    if (!(p->eta > 0.0 && p->eta < 1.0) || !(p->omega > 0.0 && p->omega <= 1.0) || !(p->rtol > 0.0)) return false;
+    if (!(p->dtau_im0 > 0.0) || !(p->dtau_min > 0.0) || !(p->dtau_max >= p->dtau_min)) return false;
+    return std::isfinite(p->eps_inc) && std::isfinite(p->eps_dec);
+}
+
+// Bump allocator over the caller's workspace (or a dry run to size it).
+struct Carver {
+    char* base;
+    size_t off = 0;
+    double* take(int64_t count)
+    {
+        off = (off + kAlign - 1) / kAlign * kAlign;
+        double* p = base ? reinterpret_cast<double*>(base + off) : nullptr;
+        off += (size_t)count * sizeof(double);
+        return p;
+    }
+    Soa soa(int64_t n, int dim)
+    {
+        Soa s;
+        s.E = take(n);
+        s.Fx = take(n);
+        s.Fy = dim == 2 ? take(n) : nullptr;
+        s.T = take(n);
+        return s;
+    }
+};
+
+}  // namespace
+
+struct m1_plan {
+    m1_grid grid{};
+    m1_params params{};
+    hipStream_t st = nullptr;
+    int dim = 2, L = 1, px = 0, py = 0;
+    double reach = 0.0;  // 1 - (1 - eta)^sub_steps
+    m1::Phys ph{};
+    std::vector<LevelBuf> lev;
+    Soa b{}, tmp{}, rfine{};
+    double* partials = nullptr;
+    int npart = 0;
+    double* dscal = nullptr;
+    unsigned long long* dbad = nullptr;
+    double* hpin = nullptr;
+    unsigned long long* hbad = nullptr;
+};
+
+namespace {
+
+// Lay out every buffer of the plan; with c.base == nullptr only the size is computed.
+void carve(m1_plan& P, Carver& c, const std::vector<int>& nxs, const std::vector<int>& nys)
+{
+    const int dim = P.grid.dim;
+    P.L = (int)nxs.size();
+    P.lev.assign(P.L, LevelBuf{});
+    const int64_t n0 = (int64_t)nxs[0] * nys[0];
+    P.b = c.soa(n0, dim);
+    P.tmp = c.soa(n0, dim);
+    P.rfine = c.soa(n0, dim);
+    for (int l = 0; l < P.L; ++l) {
+        LevelBuf& lv = P.lev[l];
+        lv.nx = nxs[l];
+        lv.ny = nys[l];
+        lv.n = (int64_t)lv.nx * lv.ny;
+        lv.hx = P.grid.hx * std::ldexp(1.0, l);
+        lv.hy = (dim == 2 ? P.grid.hy : P.grid.hx) * std::ldexp(1.0, l);
+        if (l > 0) {
+            lv.v = c.soa(lv.n, dim);
+            lv.u = c.soa(lv.n, dim);
+            lv.u2 = c.soa(lv.n, dim);
+            lv.f = c.soa(lv.n, dim);
+            lv.rb = c.soa(lv.n, dim);
+            lv.sa = c.take(lv.n);
+            lv.ss = c.take(lv.n);
+            if (P.params.nu_l > 1) {
+                lv.rt = c.soa(lv.n, dim);
+                lv.g = c.take(lv.n);
+            }
+        }
+    }
+    P.npart = (int)((n0 + 255) / 256);
+    P.partials = c.take(P.npart);
+    P.dscal = c.take(8);
+    P.dbad = reinterpret_cast<unsigned long long*>(c.take(1));
+}
+
+void fill_level_params(m1_plan& P)
+{
+    const m1_grid& g = P.grid;
+    for (LevelBuf& lv : P.lev) {
+        lv.L.nx = lv.nx;
+        lv.L.ny = lv.ny;
+        lv.L.kx = g.dt / (2.0 * lv.hx);
+        lv.L.ky = g.dim == 2 ? g.dt / (2.0 * lv.hy) : 0.0;
+        lv.L.a = 1.0 + g.c * g.dt / lv.hx;
+        if (g.dim == 2) lv.L.a += g.c * g.dt / lv.hy;
+        lv.L.cdt = g.c * g.dt;
+        lv.L.sa = lv.sa;
+        lv.L.ss = lv.ss;
+    }
+}
+
+bool same(const Soa& a, const Soa& b) { return a.E == b.E; }
+
+m1_status hip_status(hipError_t e) { return e == hipSuccess ? M1_OK : M1_ERR_DEVICE; }
+
+m1_status last_launch() { return hip_status(hipGetLastError()); }
+
+// ---- building blocks of the cycle ----------------------------------------
+void fine_sweeps(m1_plan& P, Soa& cur, Soa& other, int nu)
+{
+    const LevelBuf& f = P.lev[0];
+    for (int s = 0; s < nu; ++s) {
+        m1::launch_relax(P.st, P.dim, P.ph, f.L, cs(P.b), nullptr, 0.0, 1.0, P.params.omega, cs(cur), other);
+        std::swap(cur, other);
+    }
+}
+
+// params.pseudo_steps pseudo-time steps of level l from `start`; result in u or u2.
+Soa pseudo_smooth(m1_plan& P, int l, double dtau, Soa start)
+{
+    LevelBuf& c = P.lev[l];
+    const bool store = P.params.nu_l > 1;
+    Soa in = start;
+    for (int m = 0; m < P.params.pseudo_steps; ++m) {
+        Soa out = same(in, c.u) ? c.u2 : c.u;
+        m1::launch_pseudo(P.st, P.dim, P.ph, c.L, cs(c.f), cs(in), out, dtau, P.reach, P.params.pseudo_local,
+                          store ? c.rt : Soa{}, store ? c.g : nullptr);
+        in = out;
+        for (int s = 1; s < P.params.nu_l; ++s) {
+            out = same(in, c.u) ? c.u2 : c.u;
+            m1::launch_relax(P.st, P.dim, P.ph, c.L, cs(c.rt), c.g, 1.0, 0.0, 1.0, cs(in), out);
+            in = out;
+        }
+    }
+    return in;
+}
+
+m1::Fields fields2(const Soa& a, const Soa& b, const Soa& ca, const Soa& cb, int dim)
+{
+    m1::Fields F{};
+    int n = 0;
+    auto add = [&](const double* i, double* o) {
+        if (i) {
+            F.in[n] = i;
+            F.out[n] = o;
+            ++n;
+        }
+    };
+    add(a.E, ca.E);
+    add(a.Fx, ca.Fx);
+    if (dim == 2) add(a.Fy, ca.Fy);
+    add(a.T, ca.T);
+    if (b.E) {
+        add(b.E, cb.E);
+        add(b.Fx, cb.Fx);
+        if (dim == 2) add(b.Fy, cb.Fy);
+        add(b.T, cb.T);
+    }
+    F.n = n;
+    return F;
+}
+
+// One V-cycle (Appendix A) on the finest iterate `cur` (partner buffer `other`).
+void vcycle_impl(m1_plan& P, Soa& cur, Soa& other, double dtau)
+{
+    const m1_params& p = P.params;
+    fine_sweeps(P, cur, other, p.nu0);
+    if (P.L == 1) return;
+    m1::launch_apply(P.st, P.dim, P.ph, P.lev[0].L, cs(cur), cs(P.b), -1.0, P.rfine, nullptr);
+    std::vector<Soa> ul(P.L);
+    ul[0] = cur;
+    Soa rb_prev = P.rfine;
+    for (int l = 1; l < P.L; ++l) {
+        LevelBuf& c = P.lev[l];
+        const LevelBuf& f = P.lev[l - 1];
+        m1::launch_restrict(P.st, P.dim, f.nx, f.ny, P.px, P.py, fields2(ul[l - 1], rb_prev, c.v, c.f, P.dim));
+        m1::launch_apply(P.st, P.dim, P.ph, c.L, cs(c.v), cs(c.f), +1.0, c.f, nullptr);  // f = A(v) + R(rbar)
+        ul[l] = pseudo_smooth(P, l, dtau, c.v);
+        if (l < P.L - 1) {
+            m1::launch_apply(P.st, P.dim, P.ph, c.L, cs(ul[l]), cs(c.f), -1.0, c.rb, nullptr);
+            rb_prev = c.rb;
+        }
+    }
+    for (int l = P.L - 2; l >= 0; --l) {
+        const LevelBuf& c = P.lev[l + 1];
+        const LevelBuf& f = P.lev[l];
+        m1::launch_prolong_project(P.st, P.dim, P.ph, f.nx, f.ny, P.px, P.py, p.eta, cs(ul[l]), cs(ul[l + 1]),
+                                   cs(c.v), ul[l]);
+        if (l == 0) {
+            cur = ul[0];
+            fine_sweeps(P, cur, other, p.nu0);
+        } else {
+            ul[l] = pseudo_smooth(P, l, dtau, ul[l]);
+        }
+    }
+}
+
+// |b + sgn A_0(v)| (sgn = -1: the residual; 0: |b|) into P.dscal[0] (device)
+// and, after a sync, the host.
+m1_status fine_norm(m1_plan& P, const Soa& v, Soa r_out, double* out, double sgn = -1.0)
+{
+    m1::launch_apply(P.st, P.dim, P.ph, P.lev[0].L, cs(v), cs(P.b), sgn, r_out, P.partials);
+    m1::launch_norm_finalize(P.st, P.partials, P.npart, P.dscal);
+    hipError_t e = hipMemcpyAsync(P.hpin, P.dscal, sizeof(double), hipMemcpyDeviceToHost, P.st);
+    if (e != hipSuccess) return M1_ERR_DEVICE;
+    e = hipStreamSynchronize(P.st);
+    if (e != hipSuccess) return M1_ERR_DEVICE;
+    *out = P.hpin[0];
+    return last_launch();
+}
+
+double adapt_dtau(const m1_params& p, double dtau, double r0, double rprev, double r)
+{
+    const double d = (p.dtau_rule == M1_DTAU_LITERAL) ? std::fabs(r - rprev) / r0 : (rprev - r) / rprev;
+    if (d > p.eps_inc) dtau *= 1.1;
+    if (d < p.eps_dec) dtau *= 0.5;
+    return std::min(std::max(dtau, p.dtau_min), p.dtau_max);
+}
+
+Soa to_soa(const m1_state* s) { return Soa{s->E, s->Fx, s->Fy, s->T}; }
+
+bool valid_state(const m1_plan* P, const m1_state* s)
+{
+    if (!s || !s->E || !s->Fx || !s->T) return false;
+    return (P->dim == 2) == (s->Fy != nullptr);
+}
+
+bool valid_level_state(const m1_plan* P, const m1_state* s) { return valid_state(P, s); }
+
+}  // namespace
+
+// ============================================================================
+extern "C" {
+
+const char* m1_strerror(m1_status s)
+{
+    switch (s) {
+    case M1_OK: return "ok";
+    case M1_ERR_ARG: return "invalid argument";
+    case M1_ERR_NOT_ADMISSIBLE: return "state not admissible (E > 0, T > 0, |F| <= cE required)";
+    case M1_ERR_NO_CONVERGENCE: return "no convergence within max_cycles";
+    case M1_ERR_WORKSPACE: return "workspace missing, misaligned or too small";
+    case M1_ERR_DEVICE: return "HIP runtime error";
+    case M1_ERR_BUSY: return "busy";
+    case M1_ERR_BUDGET: return "request exceeds the memory budget";
+    }
+    return "unknown status";
+}
+
+void m1_default_params(m1_params* p)
+{
+    if (!p) return;
+    std::memset(p, 0, sizeof(*p));
+    p->levels = 0;
+    p->nu0 = 3;
+    p->nu_l = 1;
+    p->pseudo_steps = 3;
+    p->sub_steps = 4;
+    p->max_cycles = 10000;
+    p->dtau_rule = M1_DTAU_SIGNED;
+    p->pseudo_local = 1;
+    p->precision = M1_FP64;
+    p->dtau_im0 = 1e-3;
+    p->eps_inc = 0.05;
+    p->eps_dec = 0.0;
+    p->eta = 0.9;
+    p->rtol = 1e-8;
+    p->dtau_min = 1e-6;
+    p->dtau_max = 1e6;
+    p->omega = 1.0;
+}
+
+size_t m1_workspace_bytes(const m1_grid* g, const m1_params* p)
+{
+    if (!valid_grid(g) || !valid_params(p)) return 0;
+    std::vector<int> nxs, nys;
+    if (!level_dims(*g, *p, nxs, nys)) return 0;
+    m1_plan P;
+    P.grid = *g;
+    P.params = *p;
+    Carver c{nullptr};
+    carve(P, c, nxs, nys);
+    return (c.off + kAlign - 1) / kAlign * kAlign;
+}
+
+m1_status m1_plan_create(const m1_grid* g, const m1_params* p, const m1_opacity* op, void* workspace,
+                         size_t workspace_bytes, void* stream, m1_plan** out)
+{
+    if (!out) return M1_ERR_ARG;
+    *out = nullptr;
+    if (!valid_grid(g) || !valid_params(p) || !op || !op->sigma_a || !op->sigma_s) return M1_ERR_ARG;
+    std::vector<int> nxs, nys;
+    if (!level_dims(*g, *p, nxs, nys)) return M1_ERR_ARG;
+    const size_t need = m1_workspace_bytes(g, p);
+    if (!workspace || (reinterpret_cast<uintptr_t>(workspace) % kAlign) != 0 || workspace_bytes < need)
+        return M1_ERR_WORKSPACE;
+
+    m1_plan* P = new (std::nothrow) m1_plan();
+    if (!P) return M1_ERR_DEVICE;
+    P->grid = *g;
+    P->params = *p;
+    P->st = static_cast<hipStream_t>(stream);
+    P->dim = g->dim;
+    P->px = g->bc[0].kind == M1_BC_PERIODIC;
+    P->py = g->dim == 2 && g->bc[2].kind == M1_BC_PERIODIC;
+    P->reach = 1.0 - std::pow(1.0 - p->eta, (double)p->sub_steps);
+    P->ph.c = g->c;
+    P->ph.c2 = g->c * g->c;
+    P->ph.a_r = g->a_r;
+    P->ph.c_v = g->c_v;
+    for (int s = 0; s < 4; ++s) {
+        const bool on = g->dim == 2 || s < 2;
+        P->ph.bc[s] = on ? g->bc[s].kind : M1_BC_NEUMANN;
+        P->ph.bcE[s] = g->bc[s].E;
+        P->ph.bcFx[s] = g->bc[s].Fx;
+        P->ph.bcFy[s] = g->dim == 2 ? g->bc[s].Fy : 0.0;
+    }
+    Carver c{static_cast<char*>(workspace)};
+    carve(*P, c, nxs, nys);
+    P->lev[0].sa = const_cast<double*>(op->sigma_a);
+    P->lev[0].ss = const_cast<double*>(op->sigma_s);
+    fill_level_params(*P);
+
+    if (hipHostMalloc((void**)&P->hpin, 64, hipHostMallocDefault) != hipSuccess) {
+        delete P;
+        return M1_ERR_DEVICE;
+    }
+    P->hbad = reinterpret_cast<unsigned long long*>(P->hpin + 4);
+
+    // opacity validation and the coarse opacity hierarchy
+    const int64_t n0 = P->lev[0].n;
+    m1_status st = hip_status(hipMemsetAsync(P->dbad, 0xff, sizeof(unsigned long long), P->st));
+    if (st == M1_OK) {
+        m1::launch_check_sigma(P->st, n0, op->sigma_a, op->sigma_s, P->dbad);
+        st = hip_status(hipMemcpyAsync(P->hbad, P->dbad, sizeof(unsigned long long), hipMemcpyDeviceToHost, P->st));
+    }
+    if (st == M1_OK) st = hip_status(hipStreamSynchronize(P->st));
+    if (st == M1_OK) st = last_launch();
+    if (st == M1_OK && *P->hbad != ULLONG_MAX) st = M1_ERR_ARG;
+    for (int l = 1; st == M1_OK && l < P->L; ++l) {
+        m1::Fields F{};
+        F.in[0] = P->lev[l - 1].sa;
+        F.in[1] = P->lev[l - 1].ss;
+        F.out[0] = P->lev[l].sa;
+        F.out[1] = P->lev[l].ss;
+        F.n = 2;
+        m1::launch_restrict(P->st, P->dim, P->lev[l - 1].nx, P->lev[l - 1].ny, P->px, P->py, F);
+        st = last_launch();
+    }
+    if (st == M1_OK) st = hip_status(hipStreamSynchronize(P->st));
+    if (st != M1_OK) {
+        m1_plan_destroy(P);
+        return st;
+    }
+    *out = P;
+    return M1_OK;
+}
+
+void m1_plan_destroy(m1_plan* P)
+{
+    if (!P) return;
+    if (P->hpin) (void)hipHostFree(P->hpin);
+    delete P;
+}
+
+int32_t m1_plan_levels(const m1_plan* P) { return P ? P->L : 0; }
+
+m1_status m1_level_dims(const m1_plan* P, int32_t level, int32_t* nx, int32_t* ny)
+{
+    if (!P || level < 0 || level >= P->L) return M1_ERR_ARG;
+    if (nx) *nx = P->lev[level].nx;
+    if (ny) *ny = P->lev[level].ny;
+    return M1_OK;
+}
+
+m1_status m1_sync(m1_plan* P)
+{
+    if (!P) return M1_ERR_ARG;
+    return hip_status(hipStreamSynchronize(P->st));
+}
+
+m1_status m1_residual(m1_plan* P, const m1_state* v, const m1_state* vn, double* norm_out, m1_state* r_out)
+{
+    if (!P || !valid_state(P, v) || !valid_state(P, vn) || !norm_out) return M1_ERR_ARG;
+    if (r_out && !valid_state(P, r_out)) return M1_ERR_ARG;
+    m1::launch_make_rhs(P->st, P->dim, P->lev[0].n, P->grid.c_v, cs(to_soa(vn)), P->b);
+    return fine_norm(*P, to_soa(v), r_out ? to_soa(r_out) : Soa{}, norm_out);
+}
+
+m1_status m1_vcycle(m1_plan* P, m1_state* v, const m1_state* vn, double dtau)
+{
+    if (!P || !valid_state(P, v) || !valid_state(P, vn) || !(dtau > 0.0) || v->E == vn->E) return M1_ERR_ARG;
+    m1::launch_make_rhs(P->st, P->dim, P->lev[0].n, P->grid.c_v, cs(to_soa(vn)), P->b);
+    Soa user = to_soa(v), cur = user, other = P->tmp;
+    vcycle_impl(*P, cur, other, dtau);
+    if (!same(cur, user)) m1::launch_copy(P->st, P->dim, P->lev[0].n, cs(cur), user);
+    return last_launch();
+}
+
+m1_status m1_step(m1_plan* P, m1_state* v, int32_t nsteps, m1_info* info)
+{
+    if (info) {
+        std::memset(info, 0, sizeof(*info));
+        info->first_bad_cell = -1;
+    }
+    if (!P || !valid_state(P, v) || nsteps < 0) return M1_ERR_ARG;
+    const m1_params& p = P->params;
+    const int64_t n0 = P->lev[0].n;
+    Soa user = to_soa(v);
+    if (info) info->levels = P->L;
+
+    if (hipMemsetAsync(P->dbad, 0xff, sizeof(unsigned long long), P->st) != hipSuccess) return M1_ERR_DEVICE;
+    m1::launch_check_state(P->st, P->dim, n0, P->grid.c, cs(user), P->dbad);
+    if (hipMemcpyAsync(P->hbad, P->dbad, sizeof(unsigned long long), hipMemcpyDeviceToHost, P->st) != hipSuccess ||
+        hipStreamSynchronize(P->st) != hipSuccess)
+        return M1_ERR_DEVICE;
+    if (last_launch() != M1_OK) return M1_ERR_DEVICE;
+    if (*P->hbad != ULLONG_MAX) {
+        if (info) {
+            info->first_bad_cell = (int64_t)*P->hbad;
+            info->status = M1_ERR_NOT_ADMISSIBLE;
+        }
+        return M1_ERR_NOT_ADMISSIBLE;
+    }
+
+    m1_status status = M1_OK;
+    int total = 0;
+    double r0 = 0.0, rel = 0.0, dtau = p.dtau_im0;
+    for (int step = 0; step < nsteps && status == M1_OK; ++step) {
+        m1::launch_make_rhs(P->st, P->dim, n0, P->grid.c_v, cs(user), P->b);
+        double bnorm = 0.0;
+        m1_status e = fine_norm(*P, user, Soa{}, &bnorm, 0.0);  // |b|
+        if (e == M1_OK) e = fine_norm(*P, user, Soa{}, &r0);
+        if (e != M1_OK) return e;
+        // a residual at the rounding level of evaluating A counts as converged
+        const double floor_r = 16.0 * DBL_EPSILON * P->lev[0].L.a * bnorm;
+        rel = 0.0;
+        dtau = p.dtau_im0;
+        if (info) info->steps_done = step + 1;
+        if (r0 <= floor_r) continue;
+        double rprev = r0;
+        bool conv = false;
+        Soa cur = user, other = P->tmp;
+        for (int kc = 0; kc < p.max_cycles; ++kc) {
+            vcycle_impl(*P, cur, other, dtau);
+            double r = 0.0;
+            e = fine_norm(*P, cur, Soa{}, &r);
+            if (e != M1_OK) return e;
+            ++total;
+            rel = r / r0;
+            if (!std::isfinite(rel)) break;
+            dtau = adapt_dtau(p, dtau, r0, rprev, r);
+            rprev = r;
+            if (rel <= p.rtol || r <= floor_r) {
+                conv = true;
+                break;
+            }
+        }
+        if (!same(cur, user)) m1::launch_copy(P->st, P->dim, n0, cs(cur), user);
+        if (!conv) status = M1_ERR_NO_CONVERGENCE;
+    }
+    if (hipStreamSynchronize(P->st) != hipSuccess) return M1_ERR_DEVICE;
+    if (info) {
+        info->cycles = total;
+        info->status = status;
+        info->r0 = r0;
+        info->rel_residual = rel;
+        info->dtau = dtau;
+    }
+    return status;
+}
+
+m1_status m1_apply_A(m1_plan* P, int32_t level, const m1_state* v, m1_state* out)
+{
+    if (!P || level < 0 || level >= P->L || !valid_level_state(P, v) || !valid_level_state(P, out)) return M1_ERR_ARG;
+    m1::launch_apply(P->st, P->dim, P->ph, P->lev[level].L, cs(to_soa(v)), CSoa{}, 1.0, to_soa(out), nullptr);
+    return last_launch();
+}
+
+m1_status m1_sweep(m1_plan* P, const m1_state* b, const m1_state* v_in, m1_state* v_out)
+{
+    if (!P || !valid_state(P, b) || !valid_state(P, v_in) || !valid_state(P, v_out) || v_in->E == v_out->E)
+        return M1_ERR_ARG;
+    m1::launch_relax(P->st, P->dim, P->ph, P->lev[0].L, cs(to_soa(b)), nullptr, 0.0, 1.0, P->params.omega,
+                     cs(to_soa(v_in)), to_soa(v_out));
+    return last_launch();
+}
+
+m1_status m1_pseudo_step(m1_plan* P, int32_t level, double dtau, const m1_state* f, const m1_state* u_in,
+                         m1_state* u_out)
+{
+    if (!P || level < 0 || level >= P->L || !(dtau > 0.0) || !valid_level_state(P, f) ||
+        !valid_level_state(P, u_in) || !valid_level_state(P, u_out) || u_in->E == u_out->E)
+        return M1_ERR_ARG;
+    if (P->params.nu_l != 1) return M1_ERR_ARG;  // the single-operation entry point fuses exactly one sweep
+    m1::launch_pseudo(P->st, P->dim, P->ph, P->lev[level].L, cs(to_soa(f)), cs(to_soa(u_in)), to_soa(u_out), dtau,
+                      P->reach, P->params.pseudo_local, Soa{}, nullptr);
+    return last_launch();
+}
+
+m1_status m1_restrict(m1_plan* P, int32_t level, const m1_state* fine, m1_state* coarse)
+{
+    if (!P || level < 0 || level + 1 >= P->L || !valid_level_state(P, fine) || !valid_level_state(P, coarse))
+        return M1_ERR_ARG;
+    const LevelBuf& f = P->lev[level];
+    m1::launch_restrict(P->st, P->dim, f.nx, f.ny, P->px, P->py,
+                        fields2(to_soa(fine), Soa{}, to_soa(coarse), Soa{}, P->dim));
+    return last_launch();
+}
+
+m1_status m1_prolong_project(m1_plan* P, int32_t level, const m1_state* u, const m1_state* uc, const m1_state* vc,
+                             m1_state* out)
+{
+    if (!P || level < 0 || level + 1 >= P->L || !valid_level_state(P, u) || !valid_level_state(P, uc) ||
+        !valid_level_state(P, vc) || !valid_level_state(P, out))
+        return M1_ERR_ARG;
+    const LevelBuf& f = P->lev[level];
+    m1::launch_prolong_project(P->st, P->dim, P->ph, f.nx, f.ny, P->px, P->py, P->params.eta, cs(to_soa(u)),
+                               cs(to_soa(uc)), cs(to_soa(vc)), to_soa(out));
+    return last_launch();
+}
+
+}  // extern "C"

@@ -1,0 +1,227 @@
+// m1_device.hpp -- per-cell device math of the implicit M1 solver (gfx950, wave64).
+//
+// Everything here is FP64 and register-only; the kernels in m1_kernels.hip
+// compose these pieces into stencil sweeps.  Formulas follow the paper
+// (arXiv 2208.14703) but are arranged for the GPU: the closure is written
+// through one square root and one division with no 0/0 at F = 0, and the
+// local source solve warm-starts Newton's method from the previous T.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+namespace m1 {
+
+enum BcKind : int { BC_PERIODIC = 0, BC_REFLECTIVE = 1, BC_NEUMANN = 2, BC_DIRICHLET = 3 };
+
+// Physics and boundary data shared by every level.
+struct Phys {
+    double c, c2, a_r, c_v;
+    int bc[4];  // x-, x+, y-, y+
+    double bcE[4], bcFx[4], bcFy[4];
+};
+
+// One grid level as seen by a kernel.
+struct Lvl {
+    int nx, ny;
+    double kx, ky;  // dt / (2 hx), dt / (2 hy); ky = 0 in 1-D
+    double a;       // 1 + c dt/hx + c dt/hy
+    double cdt;     // c dt  (kappa = c dt sigma)
+    const double* sa;
+    const double* ss;
+};
+
+struct Soa {
+    double* E;
+    double* Fx;
+    double* Fy;
+    double* T;
+};
+struct CSoa {
+    const double* E;
+    const double* Fx;
+    const double* Fy;
+    const double* T;
+};
+__host__ __device__ inline CSoa cs(const Soa& s) { return CSoa{s.E, s.Fx, s.Fy, s.T}; }
+
+// ---------------------------------------------------------------------------
+// M1 closure (Sect. 2.1) arranged for the directional fluxes.  With
+//   r = 1 / ((2 + s) E),  s = sqrt(4 - 3 f^2),  f = |F| / (cE),
+// one has (1 - chi)/2 E = E/3 - (|F|^2/c^2) r and (3 chi - 1)/2 E n_i n_j =
+// 3 r F_i F_j / c^2, so c^2 P_ij = (c^2 E/3 - |F|^2 r) delta_ij + 3 r F_i F_j
+// and r = c / (2cE + sqrt(4 c^2 E^2 - 3 |F|^2)).  The radicand is clamped to
+// c^2 E^2 (f <= 1) against rounding on the free-streaming boundary.
+struct C2P {
+    double iso;  // c^2 E/3 - |F|^2 r
+    double r3;   // 3 r
+};
+__device__ __forceinline__ C2P closure(double c, double c2, double E, double Fx, double Fy)
+{
+    const double F2 = fma(Fx, Fx, Fy * Fy);
+    const double c2E2 = c2 * E * E;
+    const double root = sqrt(fmax(fma(4.0, c2E2, -3.0 * F2), c2E2));
+    const double r = c / fma(2.0 * c, E, root);
+    C2P o;
+    o.iso = fma(-F2, r, c2 * E * (1.0 / 3.0));
+    o.r3 = 3.0 * r;
+    return o;
+}
+
+// Add sgn-side x contribution: sgn = +1 for L_x (left neighbour), -1 for R_x (right):
+//   k (cE + sgn Fx,  c Fx + sgn c^2 Pxx,  c Fy + sgn c^2 Pxy)
+__device__ __forceinline__ void add_x(double k, double c, double c2, double sgn, double E, double Fx, double Fy,
+                                      double& S0, double& S1, double& S2)
+{
+    const C2P p = closure(c, c2, E, Fx, Fy);
+    const double Gxx = fma(p.r3 * Fx, Fx, p.iso);
+    const double Gxy = p.r3 * Fx * Fy;
+    S0 = fma(k, fma(sgn, Fx, c * E), S0);
+    S1 = fma(k, fma(sgn, Gxx, c * Fx), S1);
+    S2 = fma(k, fma(sgn, Gxy, c * Fy), S2);
+}
+// y contribution: k (cE + sgn Fy,  c Fx + sgn c^2 Pxy,  c Fy + sgn c^2 Pyy)
+__device__ __forceinline__ void add_y(double k, double c, double c2, double sgn, double E, double Fx, double Fy,
+                                      double& S0, double& S1, double& S2)
+{
+    const C2P p = closure(c, c2, E, Fx, Fy);
+    const double Gxy = p.r3 * Fx * Fy;
+    const double Gyy = fma(p.r3 * Fy, Fy, p.iso);
+    S0 = fma(k, fma(sgn, Fy, c * E), S0);
+    S1 = fma(k, fma(sgn, Gxy, c * Fx), S1);
+    S2 = fma(k, fma(sgn, Gyy, c * Fy), S2);
+}
+
+// ---------------------------------------------------------------------------
+// Neighbour (ghost) state for side `side` (0 x-, 1 x+, 2 y-, 3 y+).  `inside`
+// tells whether the neighbour index kn is in the domain; otherwise the side's
+// boundary rule applies (kn is then the periodic wrap, kc the cell itself).
+template <int DIM>
+__device__ __forceinline__ void nb_state(const Phys& ph, int side, bool inside, int64_t kn, int64_t kc, const CSoa& v,
+                                         double& e, double& fx, double& fy)
+{
+    int64_t k = kn;
+    int kind = inside ? BC_PERIODIC : ph.bc[side];
+    if (kind == BC_DIRICHLET) {
+        e = ph.bcE[side];
+        fx = ph.bcFx[side];
+        fy = ph.bcFy[side];
+        return;
+    }
+    if (kind != BC_PERIODIC) k = kc;
+    e = v.E[k];
+    fx = v.Fx[k];
+    fy = (DIM == 2) ? v.Fy[k] : 0.0;
+    if (kind == BC_REFLECTIVE) {
+        if (side < 2) fx = -fx;
+        else fy = -fy;
+    }
+}
+
+// Off-diagonal sum S = L_x(v_{i-1}) + R_x(v_{i+1}) [+ L_y(v_{j-1}) + R_y(v_{j+1})] of cell (i,j).
+template <int DIM>
+__device__ __forceinline__ void offdiag(const Phys& ph, const Lvl& L, const CSoa& v, int i, int j, int64_t k,
+                                        double& S0, double& S1, double& S2)
+{
+    double e, fx, fy;
+    S0 = S1 = S2 = 0.0;
+    nb_state<DIM>(ph, 0, i > 0, i > 0 ? k - 1 : k + (L.nx - 1), k, v, e, fx, fy);
+    add_x(L.kx, ph.c, ph.c2, +1.0, e, fx, fy, S0, S1, S2);
+    nb_state<DIM>(ph, 1, i < L.nx - 1, i < L.nx - 1 ? k + 1 : k - (L.nx - 1), k, v, e, fx, fy);
+    add_x(L.kx, ph.c, ph.c2, -1.0, e, fx, fy, S0, S1, S2);
+    if (DIM == 2) {
+        const int64_t nx = L.nx, wrap = (int64_t)(L.ny - 1) * nx;
+        nb_state<DIM>(ph, 2, j > 0, j > 0 ? k - nx : k + wrap, k, v, e, fx, fy);
+        add_y(L.ky, ph.c, ph.c2, +1.0, e, fx, fy, S0, S1, S2);
+        nb_state<DIM>(ph, 3, j < L.ny - 1, j < L.ny - 1 ? k + nx : k - wrap, k, v, e, fx, fy);
+        add_y(L.ky, ph.c, ph.c2, -1.0, e, fx, fy, S0, S1, S2);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Local solve of one cell (the inverse of the diagonal block, sources included):
+//   beta E  + gamma ((a + ka) E - ka a_r T^4)      = BE
+//   beta F  + gamma (a + ka + ks) F                = BF
+//   (beta + gamma) C_v T + gamma ka (a_r T^4 - E)  = BT
+// E is eliminated; C_v' T + K T^4 = Q (convex, increasing) is solved by Newton
+// from the previous temperature Tg, clamped to the upper bound of the root
+// min(Q/C_v', (Q/K)^(1/4)) so that every iterate after the first lies above
+// the root and the sequence decreases monotonically.
+__device__ __forceinline__ void local_solve(double beta, double gamma, double a, double ka, double ks, double cv,
+                                            double ar, double BE, double BFx, double BFy, double BT, double Tg,
+                                            double& E, double& Fx, double& Fy, double& T)
+{
+    const double dE = fma(gamma, a + ka, beta);
+    const double iF = 1.0 / fma(gamma, ks, dE);
+    Fx = BFx * iF;
+    Fy = BFy * iF;
+    const double k = gamma * ka;
+    const double cT = (beta + gamma) * cv;
+    const double idE = 1.0 / dE;
+    if (k == 0.0) {
+        T = BT / cT;
+        E = BE * idE;
+        return;
+    }
+    const double K = k * ar * fma(gamma, a, beta) * idE;
+    const double Q = fma(k * BE, idE, BT);
+    const double Tup = fmin(Q / cT, sqrt(sqrt(Q / K)));
+    double t = (Tg > 0.0 && Tg < Tup) ? Tg : Tup;
+    for (int it = 0; it < 64; ++it) {
+        const double t2 = t * t;
+        const double g = fma(K * t2, t2, fma(cT, t, -Q));
+        const double dg = fma(4.0 * K * t2, t, cT);
+        const double tn = fmin(t - g / dg, Tup);
+        const bool done = fabs(tn - t) <= 1e-14 * tn;
+        t = tn;
+        if (done) break;
+    }
+    T = t;
+    const double t2 = t * t;
+    E = fma(k * ar * t2, t2, BE) * idE;
+}
+
+// ---------------------------------------------------------------------------
+// Admissible length of the ray w + tau s (w admissible): the smallest of
+// -E/sE, -T/sT and the first positive root of
+//   q(tau) = c^2 (E + tau sE)^2 - |F + tau sF|^2 = A tau^2 + 2 B tau + C.
+__device__ __forceinline__ double ray_len(double c2, double E, double Fx, double Fy, double T, double sE, double sFx,
+                                          double sFy, double sT)
+{
+    double tau = INFINITY;
+    if (sE < 0.0) tau = -E / sE;
+    if (sT < 0.0) tau = fmin(tau, -T / sT);
+    const double A = c2 * sE * sE - fma(sFx, sFx, sFy * sFy);
+    const double B = c2 * E * sE - fma(Fx, sFx, Fy * sFy);
+    const double C = fmax(c2 * E * E - fma(Fx, Fx, Fy * Fy), 0.0);
+    double r = INFINITY;
+    if (A == 0.0) {
+        if (B < 0.0) r = C / (-2.0 * B);
+    } else {
+        const double disc = B * B - A * C;
+        if (disc >= 0.0) {
+            const double sq = sqrt(disc);
+            if (B < 0.0) r = C / (sq - B);
+            else if (A < 0.0) r = (B + sq) / (-A);
+        }
+    }
+    return fmin(tau, r);
+}
+
+__device__ __forceinline__ bool admissible(double c2, double E, double Fx, double Fy, double T)
+{
+    return E > 0.0 && T > 0.0 && fma(Fx, Fx, Fy * Fy) <= c2 * E * E;
+}
+
+// XCD-aware block order: hardware hands consecutive blocks to the 8 XCDs round
+// robin; remap so that each XCD walks one contiguous band of the grid and the
+// stencil halo rows it needs stay in its own L2.
+__device__ __forceinline__ int64_t xcd_block()
+{
+    const int64_t nb = gridDim.x, b = blockIdx.x;
+    if ((nb & 7) != 0) return b;
+    return (b & 7) * (nb >> 3) + (b >> 3);
+}
+
+}  // namespace m1

@@ -1,0 +1,80 @@
+"""C-ABI checks that need no GPU: the library loads, exports every declared
+symbol, and host-side argument validation works (nothing is enqueued)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2208_14703_amd import binding, inputs
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    names = set()
+    for fn in os.listdir(os.path.join(ROOT, "include")):
+        if fn.endswith(".h"):
+            src = open(os.path.join(ROOT, "include", fn)).read()
+            src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+            names |= set(re.findall(r"\b(m1_[a-z_0-9]+)\s*\(", src))
+    return sorted(names)
+
+
+def test_library_exports_every_declared_symbol():
+    if not os.path.exists(binding.LIB_PATH):
+        pytest.skip("libm1mg.so not built")
+    L = binding.lib()
+    names = declared_functions()
+    assert len(names) >= 15
+    for n in names:
+        assert hasattr(L, n), n
+
+
+def test_default_params_are_the_papers():
+    p = binding.default_params()
+    assert (p["nu0"], p["pseudo_steps"], p["nu_l"], p["dtau_im0"]) == (3, 3, 1, 1e-3)
+    assert p["omega"] == 1.0 and p["levels"] == 0
+
+
+def test_workspace_size_and_host_validation():
+    L = binding.lib()
+    prob, _, _, _ = inputs.hot_wall_2d(n=1024)
+    g = binding.make_grid(prob)
+    p = binding.make_params(binding.default_params())
+    nbytes = L.m1_workspace_bytes(ctypes.byref(g), ctypes.byref(p))
+    # finest: b, tmp, rbar (12 fields); coarse levels: 22 fields on a third of the cells
+    assert 12 * 8 * 1024 ** 2 < nbytes < 24 * 8 * 1024 ** 2
+    bad = binding.make_grid(prob)
+    bad.dt = -1.0
+    assert L.m1_workspace_bytes(ctypes.byref(bad), ctypes.byref(p)) == 0
+    bad = binding.make_grid(prob)
+    bad.bc[0].kind = 0   # periodic on one side only
+    assert L.m1_workspace_bytes(ctypes.byref(bad), ctypes.byref(p)) == 0
+    p2 = binding.make_params(binding.default_params(omega=1.5))
+    assert L.m1_workspace_bytes(ctypes.byref(g), ctypes.byref(p2)) == 0
+    p3 = binding.make_params(binding.default_params(levels=12))   # 1024 has only 9 levels down to side 4
+    assert L.m1_workspace_bytes(ctypes.byref(g), ctypes.byref(p3)) == 0
+    # plan creation rejects a too-small or misaligned workspace before touching it
+    op = binding.m1_opacity(0x10000, 0x20000)
+    h = ctypes.c_void_p()
+    st = L.m1_plan_create(ctypes.byref(g), ctypes.byref(p), ctypes.byref(op), ctypes.c_void_p(0x100000), 1024,
+                          None, ctypes.byref(h))
+    assert st == 4 and not h.value
+    st = L.m1_plan_create(ctypes.byref(g), ctypes.byref(p), ctypes.byref(op), ctypes.c_void_p(0x100008), nbytes,
+                          None, ctypes.byref(h))
+    assert st == 4
+    st = L.m1_plan_create(ctypes.byref(bad), ctypes.byref(p), ctypes.byref(op), ctypes.c_void_p(0x100000), nbytes,
+                          None, ctypes.byref(h))
+    assert st == 1
+    assert L.m1_strerror(2).decode().startswith("state not admissible")
+
+
+def test_one_dimensional_grid_validation():
+    L = binding.lib()
+    prob, _, _, _ = inputs.gaussian_1d()
+    g = binding.make_grid(prob)
+    p = binding.make_params(binding.default_params())
+    assert L.m1_workspace_bytes(ctypes.byref(g), ctypes.byref(p)) > 0
+    g.ny = 2
+    assert L.m1_workspace_bytes(ctypes.byref(g), ctypes.byref(p)) == 0

@@ -1,0 +1,253 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 CPU oracle.
+
+Cases:
+  * per operation (A, relaxed Jacobi sweep, pseudo-time step, restriction,
+    prolongation with projection), 1e-13 relative;
+  * one V-cycle, 1e-11;
+  * converged time steps, 1e-10 relative in E and F (both sides at relative
+    residual 1e-13);
+  * full-size checks of the 1024^2 hot-wall workload (oracle residual of the GPU
+    solution, a full-grid sweep compared element by element);
+  * edge cases: ragged sizes, 1x1 grids, zero steps, non-admissible input, bad
+    opacities, the cycle cap, determinism.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2208_14703_amd import binding, inputs
+from tests.gpu_util import announce, rel_err, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+OMEGA = 0.8
+
+
+def plan_for(prob, sig, **params):
+    params.setdefault("omega", OMEGA)
+    return binding.Plan(prob, to_dev(sig), params)
+
+
+def oracle_params(**kw):
+    kw.setdefault("omega", OMEGA)
+    return oracle.make_params(**kw)
+
+
+BC_SETS = {
+    "periodic": ("periodic",) * 4,
+    "mixed": ("dirichlet", "reflective", "neumann", "reflective"),
+    "wall": ("dirichlet", "reflective", "reflective", "reflective"),
+}
+
+
+# ------------------------------------------------------------------ single operations
+@pytest.mark.parametrize("dim,nx,ny", [(2, 100, 37), (2, 64, 64), (1, 1000, 1), (2, 1, 1), (2, 3, 5)])
+@pytest.mark.parametrize("bcs", ["periodic", "mixed"])
+def test_apply_and_sweep_parity(dim, nx, ny, bcs):
+    announce("apply/sweep", dim, nx, ny, bcs)
+    kinds = BC_SETS[bcs]
+    prob, v, sig = inputs.random_problem(1, dim, nx, ny, bc_kinds=kinds, cfl=40.0, fmax=1.0)
+    o = oracle.Oracle(prob, sig)
+    P = plan_for(prob, sig, levels=1)
+    vd = to_dev(v)
+    A = to_host(P.apply_A(0, vd))
+    Ao = o.apply_A(v)
+    scale = np.abs(Ao).max()
+    assert np.abs(A - Ao).max() <= 1e-13 * scale
+    b = o.rhs(inputs.random_problem(2, dim, nx, ny, bc_kinds=kinds, cfl=40.0)[1])
+    for omega in (1.0, OMEGA):
+        P2 = plan_for(prob, sig, levels=1, omega=omega)
+        g = to_host(P2.sweep(to_dev(b), vd))
+        assert rel_err(g, o.sweep(b, v, omega), prob["c"]) <= 1e-13
+    norm, r = P.residual(vd, to_dev(b / np.array([1, 1, 1, prob["c_v"]])[:, None, None]), want_r=True)
+    ro = o.residual(b, v)
+    assert np.abs(to_host(r) - ro).max() <= 1e-13 * np.abs(Ao).max()
+    assert norm == pytest.approx(o.norm(ro), rel=1e-12)
+
+
+@pytest.mark.parametrize("dim,n", [(2, 64), (1, 512)])
+@pytest.mark.parametrize("local", [1, 0])
+def test_pseudo_step_parity(dim, n, local):
+    announce("pseudo", dim, n, local)
+    prob, v, sig = inputs.random_problem(3, dim, n, n, bc_kinds=BC_SETS["mixed"], cfl=60.0)
+    o = oracle.Oracle(prob, sig)
+    P = plan_for(prob, sig, pseudo_local=local)
+    op = oracle_params(pseudo_local=local)
+    g1 = o.coarse_grid()
+    sig1 = o.restrict(sig)
+    v1 = o.restrict(v)
+    rng = np.random.default_rng(4)
+    f = o.apply_A(v1, sigma=sig1, g=g1) + rng.normal(size=v1.shape) * np.abs(v1).max() * 3
+    if dim == 1:
+        f[2] = 0.0
+    for dtau in (1e-3, 0.7, 50.0):
+        got = to_host(P.pseudo_step(1, dtau, to_dev(f), to_dev(v1)))
+        ref = o.pseudo_step(f, v1, dtau, params=op, sigma=sig1, g=g1)
+        assert rel_err(got, ref, prob["c"]) <= 1e-12, dtau
+
+
+@pytest.mark.parametrize("dim,n", [(2, 64), (1, 256)])
+@pytest.mark.parametrize("bcs", ["periodic", "mixed"])
+def test_restrict_and_prolong_project_parity(dim, n, bcs):
+    announce("transfer", dim, n, bcs)
+    prob, v, sig = inputs.random_problem(5, dim, n, n, bc_kinds=BC_SETS[bcs], cfl=10.0)
+    o = oracle.Oracle(prob, sig)
+    P = plan_for(prob, sig)
+    got = to_host(P.restrict(0, to_dev(v)))
+    assert rel_err(got, o.restrict(v), prob["c"]) <= 1e-15
+    vc = o.restrict(v)
+    rng = np.random.default_rng(6)
+    uc = vc + rng.normal(size=vc.shape) * vc[0] * 0.7
+    if dim == 1:
+        uc[2] = 0.0
+    w = v + o.prolong(uc - vc)
+    ref = o.project(v, w, params=oracle_params())
+    got = to_host(P.prolong_project(0, to_dev(v), to_dev(uc), to_dev(vc)))
+    assert rel_err(got, ref, prob["c"]) <= 1e-13
+
+
+# ------------------------------------------------------------------ one V-cycle
+@pytest.mark.parametrize("case", ["hot64", "logn64", "gauss256", "mixed32x64"])
+def test_vcycle_parity(case):
+    announce("vcycle", case)
+    if case == "hot64":
+        prob, v, sig, _ = inputs.hot_wall_2d(n=64)
+    elif case == "logn64":
+        prob, v, sig, _ = inputs.lognormal_2d(n=64)
+    elif case == "gauss256":
+        prob, v, sig, _ = inputs.gaussian_1d(n=256)
+    else:
+        prob, v, sig = inputs.random_problem(7, 2, 64, 64, bc_kinds=BC_SETS["mixed"], cfl=80.0)
+    o = oracle.Oracle(prob, sig)
+    P = plan_for(prob, sig)
+    b = o.rhs(v)
+    vd, vn = to_dev(v), to_dev(v)
+    ref = v
+    for cyc, dtau in enumerate((1e-3, 0.3, 5.0)):
+        P.vcycle(vd, vn, dtau)
+        ref = o.vcycle(b, ref, dtau, params=oracle_params())
+        err = rel_err(to_host(vd), ref, prob["c"])
+        assert err <= 1e-11, (cyc, err)
+
+
+# ------------------------------------------------------------------ converged solves
+@pytest.mark.parametrize("case", ["gauss256", "hot128", "logn128", "mixed64_2steps", "gauss256_jacobi"])
+def test_converged_step_parity(case):
+    announce("converged", case)
+    steps, levels = 1, 0
+    if case.startswith("gauss256"):
+        prob, v, sig, _ = inputs.gaussian_1d(n=256)
+        if case.endswith("jacobi"):
+            levels = 1
+    elif case == "hot128":
+        prob, v, sig, _ = inputs.hot_wall_2d(n=128)
+    elif case == "logn128":
+        prob, v, sig, _ = inputs.lognormal_2d(n=128)
+    else:
+        prob, v, sig = inputs.random_problem(8, 2, 64, 64, bc_kinds=BC_SETS["mixed"], cfl=50.0)
+        steps = 2
+    rtol = 1e-13
+    o = oracle.Oracle(prob, sig)
+    ref, info_o = o.step(v, steps, oracle_params(rtol=rtol, levels=levels, max_cycles=40000))
+    assert info_o["status"] == 0
+    P = plan_for(prob, sig, rtol=rtol, levels=levels, max_cycles=40000)
+    vd = to_dev(v)
+    info = P.step(vd, steps)
+    assert info["status"] == 0 and info["rel_residual"] <= 1e-11  # rtol, or the rounding floor of A
+    got = to_host(vd)
+    sE = np.abs(ref[0]).max()
+    assert np.abs(got[0] - ref[0]).max() / sE <= 1e-10
+    assert np.abs(got[1:3] - ref[1:3]).max() / (prob["c"] * sE) <= 1e-10
+    assert np.abs(got[3] - ref[3]).max() / np.abs(ref[3]).max() <= 1e-10
+    print("cycles gpu/oracle", info["cycles"], info_o["cycles"], flush=True)
+
+
+# ------------------------------------------------------------------ full-size workload checks
+def test_full_size_hot_wall_solution_satisfies_oracle_residual():
+    announce("full 1024 hot wall, 1 step")
+    prob, v, sig, run = inputs.hot_wall_2d(n=1024)
+    P = plan_for(prob, sig, rtol=run["rtol"])
+    vd = to_dev(v)
+    info = P.step(vd, 1)
+    assert info["status"] == 0
+    got = to_host(vd)
+    o = oracle.Oracle(prob, sig)
+    b = o.rhs(v)
+    rel = o.norm(o.residual(b, got)) / o.norm(o.residual(b, v))
+    assert rel <= 1.001 * run["rtol"], rel
+    E, F2, T = got[0], got[1] ** 2 + got[2] ** 2, got[3]
+    assert np.all(E > 0) and np.all(T > 0) and np.all(np.sqrt(F2) <= prob["c"] * E * (1 + 1e-12))
+    # one sweep of the full grid, element by element
+    sw = to_host(P.sweep(to_dev(b), vd))
+    assert rel_err(sw, o.sweep(b, got, OMEGA), prob["c"]) <= 1e-13
+
+
+# ------------------------------------------------------------------ edge cases
+def test_zero_steps_and_equilibrium():
+    announce("edge: zero steps / equilibrium")
+    prob = inputs.grid_problem(2, 32, 32, 50.0, inputs.bc_all("periodic"))
+    v = np.zeros((4, 32, 32))
+    v[0], v[3] = 1.0, 1.0
+    sig = np.ones((2, 32, 32))
+    P = plan_for(prob, sig)
+    vd = to_dev(v)
+    info = P.step(vd, 0)
+    assert info["status"] == 0 and info["cycles"] == 0
+    np.testing.assert_array_equal(to_host(vd), v)
+    info = P.step(vd, 2)
+    assert info["status"] == 0 and info["cycles"] == 0   # residual at the rounding level of A
+    np.testing.assert_array_equal(to_host(vd), v)
+
+
+def test_non_admissible_input_is_rejected_untouched():
+    announce("edge: non-admissible input")
+    prob, v, sig = inputs.random_problem(9, 2, 64, 48, cfl=10.0)
+    v[0, 10, 7] = -1.0                      # cell 10*64 + 7 = 647
+    v[1, 20, 3] = 5 * v[0, 20, 3]           # |F| > cE at a later cell
+    P = plan_for(prob, sig, levels=1)
+    vd = to_dev(v)
+    with pytest.raises(binding.M1Error) as ei:
+        P.step(vd, 1)
+    assert ei.value.status == 2 and "647" in str(ei.value)
+    np.testing.assert_array_equal(to_host(vd), v)
+    v2 = inputs.random_problem(9, 2, 64, 48, cfl=10.0)[1]
+    v2[3, 0, 5] = np.nan
+    with pytest.raises(binding.M1Error):
+        P.step(to_dev(v2), 1)
+
+
+def test_bad_opacity_and_arguments_rejected():
+    announce("edge: bad opacity / arguments")
+    prob, v, sig = inputs.random_problem(10, 2, 32, 32)
+    bad = sig.copy()
+    bad[1, 3, 3] = -1.0
+    with pytest.raises(binding.M1Error) as ei:
+        plan_for(prob, bad)
+    assert ei.value.status == 1
+    odd = inputs.random_problem(10, 2, 30, 32)
+    with pytest.raises(binding.M1Error):
+        plan_for(odd[0], odd[2], levels=4)   # 30 cannot be halved three times
+
+
+def test_cycle_cap_reports_no_convergence_with_admissible_state():
+    announce("edge: max_cycles")
+    prob, v, sig, _ = inputs.hot_wall_2d(n=64)
+    P = plan_for(prob, sig, max_cycles=2, rtol=1e-12)
+    vd = to_dev(v)
+    info = P.step(vd, 1)
+    assert info["status"] == 3 and info["cycles"] == 2
+    got = to_host(vd)
+    assert np.all(got[0] > 0) and np.all(got[3] > 0)
+    assert np.all(np.sqrt(got[1] ** 2 + got[2] ** 2) <= prob["c"] * got[0] * (1 + 1e-12))
+
+
+def test_deterministic():
+    announce("edge: determinism")
+    prob, v, sig, _ = inputs.lognormal_2d(n=128)
+    outs = []
+    for _ in range(2):
+        P = plan_for(prob, sig)
+        vd = to_dev(v)
+        P.step(vd, 1)
+        outs.append(to_host(vd))
+    np.testing.assert_array_equal(outs[0], outs[1])

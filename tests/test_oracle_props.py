@@ -152,5 +152,12 @@ def test_step_stops_immediately_at_equilibrium():
     v[0], v[3] = 1.0, 1.0
     o = oracle.Oracle(prob, np.ones((2, 8, 8)))
     out, info = o.step(v, 3, oracle.make_params())
-    assert info["cycles"] <= 3
-    np.testing.assert_allclose(out, v, rtol=1e-14)
+    assert info["cycles"] == 0 and info["status"] == 0
+    np.testing.assert_array_equal(out, v)
+    # a state one rounding away from equilibrium still takes zero cycles
+    prob2 = inputs.grid_problem(2, 32, 32, 50.0, inputs.bc_all("periodic"))
+    o2 = oracle.Oracle(prob2, np.ones((2, 32, 32)))
+    v2 = np.zeros((4, 32, 32))
+    v2[0], v2[3] = 1.0, 1.0
+    out2, info2 = o2.step(v2, 2, oracle.make_params(rtol=1e-8))
+    assert info2["cycles"] == 0 and info2["status"] == 0
