@@ -6,6 +6,7 @@
 #include <cfloat>
 #include <climits>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <vector>
@@ -129,6 +130,10 @@ struct m1_plan {
     unsigned long long* dbad = nullptr;
     double* hpin = nullptr;
     unsigned long long* hbad = nullptr;
+    m1::Ctrl* dctrl = nullptr;     // device cycle control (workspace)
+    m1::Ctrl* hctrl = nullptr;     // pinned host copy
+    m1::TailArgs* dtail = nullptr; // device copy of the tail description (workspace)
+    int lt = 0;                    // first level run by the single-workgroup tail (L: none)
 };
 
 namespace {
@@ -168,6 +173,15 @@ void carve(m1_plan& P, Carver& c, const std::vector<int>& nxs, const std::vector
     P.partials = c.take(P.npart);
     P.dscal = c.take(8);
     P.dbad = reinterpret_cast<unsigned long long*>(c.take(1));
+    P.dctrl = reinterpret_cast<m1::Ctrl*>(c.take((sizeof(m1::Ctrl) + 7) / 8));
+    P.dtail = reinterpret_cast<m1::TailArgs*>(c.take((sizeof(m1::TailArgs) + 7) / 8));
+}
+
+// Levels with at most this many cells run inside the single-workgroup tail kernel.
+int64_t tail_cells()
+{
+    const char* e = std::getenv("M1_TAIL_CELLS");
+    return e ? std::atoll(e) : 256;
 }
 
 void fill_level_params(m1_plan& P)
@@ -193,29 +207,45 @@ m1_status hip_status(hipError_t e) { return e == hipSuccess ? M1_OK : M1_ERR_DEV
 m1_status last_launch() { return hip_status(hipGetLastError()); }
 
 // ---- building blocks of the cycle ----------------------------------------
-void fine_sweeps(m1_plan& P, Soa& cur, Soa& other, int nu)
+// Per-cycle gating: the pseudo-time step and the `active` flag either come from
+// the device cycle control (whole cycles enqueued ahead) or are plain values.
+struct Gate {
+    double dtau;
+    const double* dtau_dev;
+    const int* active;
+};
+
+// nu finest-level sweeps.  With `control` the first sweep also reduces the
+// residual norm of its input (the previous cycle's result) and the cycle
+// control then updates dtau / the stop flag before the rest of the cycle runs.
+void fine_sweeps(m1_plan& P, Soa& cur, Soa& other, int nu, const Gate& G, bool control = false)
 {
     const LevelBuf& f = P.lev[0];
     for (int s = 0; s < nu; ++s) {
-        m1::launch_relax(P.st, P.dim, P.ph, f.L, cs(P.b), nullptr, 0.0, 1.0, P.params.omega, cs(cur), other);
+        const bool norm = control && s == 0;
+        m1::launch_relax(P.st, P.dim, P.ph, f.L, cs(P.b), nullptr, 0.0, 1.0, P.params.omega, cs(cur), other,
+                         norm ? P.partials : nullptr, G.active);
+        if (norm) m1::launch_norm_control(P.st, P.partials, P.npart, P.dctrl);
         std::swap(cur, other);
     }
 }
 
 // params.pseudo_steps pseudo-time steps of level l from `start`; result in u or u2.
-Soa pseudo_smooth(m1_plan& P, int l, double dtau, Soa start)
+// `first`: the smoothing starts from v_l and its first step forms f = A(v_l) + R(rbar).
+Soa pseudo_smooth(m1_plan& P, int l, const Gate& G, Soa start, bool first)
 {
     LevelBuf& c = P.lev[l];
     const bool store = P.params.nu_l > 1;
     Soa in = start;
     for (int m = 0; m < P.params.pseudo_steps; ++m) {
         Soa out = same(in, c.u) ? c.u2 : c.u;
-        m1::launch_pseudo(P.st, P.dim, P.ph, c.L, cs(c.f), cs(in), out, dtau, P.reach, P.params.pseudo_local,
-                          store ? c.rt : Soa{}, store ? c.g : nullptr);
+        m1::launch_pseudo(P.st, P.dim, P.ph, c.L, c.f, cs(in), out, G.dtau, G.dtau_dev, P.reach,
+                          P.params.pseudo_local, first && m == 0, store ? c.rt : Soa{}, store ? c.g : nullptr,
+                          G.active);
         in = out;
         for (int s = 1; s < P.params.nu_l; ++s) {
             out = same(in, c.u) ? c.u2 : c.u;
-            m1::launch_relax(P.st, P.dim, P.ph, c.L, cs(c.rt), c.g, 1.0, 0.0, 1.0, cs(in), out);
+            m1::launch_relax(P.st, P.dim, P.ph, c.L, cs(c.rt), c.g, 1.0, 0.0, 1.0, cs(in), out, nullptr, G.active);
             in = out;
         }
     }
@@ -248,36 +278,44 @@ m1::Fields fields2(const Soa& a, const Soa& b, const Soa& ca, const Soa& cb, int
 }
 
 // One V-cycle (Appendix A) on the finest iterate `cur` (partner buffer `other`).
-void vcycle_impl(m1_plan& P, Soa& cur, Soa& other, double dtau)
+// Levels below P.lt run as grid kernels; levels P.lt..L-1 run inside the
+// single-workgroup tail kernel (which leaves its result in lev[lt].u).
+void vcycle_impl(m1_plan& P, Soa& cur, Soa& other, const Gate& G, bool control = false)
 {
     const m1_params& p = P.params;
-    fine_sweeps(P, cur, other, p.nu0);
+    fine_sweeps(P, cur, other, p.nu0, G, control);
     if (P.L == 1) return;
-    m1::launch_apply(P.st, P.dim, P.ph, P.lev[0].L, cs(cur), cs(P.b), -1.0, P.rfine, nullptr);
+    m1::launch_apply(P.st, P.dim, P.ph, P.lev[0].L, cs(cur), cs(P.b), -1.0, P.rfine, nullptr, G.active);
     std::vector<Soa> ul(P.L);
     ul[0] = cur;
     Soa rb_prev = P.rfine;
     for (int l = 1; l < P.L; ++l) {
         LevelBuf& c = P.lev[l];
         const LevelBuf& f = P.lev[l - 1];
-        m1::launch_restrict(P.st, P.dim, f.nx, f.ny, P.px, P.py, fields2(ul[l - 1], rb_prev, c.v, c.f, P.dim));
-        m1::launch_apply(P.st, P.dim, P.ph, c.L, cs(c.v), cs(c.f), +1.0, c.f, nullptr);  // f = A(v) + R(rbar)
-        ul[l] = pseudo_smooth(P, l, dtau, c.v);
+        m1::launch_restrict(P.st, P.dim, f.nx, f.ny, P.px, P.py, fields2(ul[l - 1], rb_prev, c.v, c.f, P.dim),
+                            G.active);
+        if (l == P.lt) {  // the rest of the cycle below (and including) level lt
+            m1::launch_tail(P.st, P.dim, P.dtail, G.dtau, G.dtau_dev, G.active);
+            ul[l] = c.u;
+            break;
+        }
+        ul[l] = pseudo_smooth(P, l, G, c.v, true);  // also forms f = A(v) + R(rbar)
         if (l < P.L - 1) {
-            m1::launch_apply(P.st, P.dim, P.ph, c.L, cs(ul[l]), cs(c.f), -1.0, c.rb, nullptr);
+            m1::launch_apply(P.st, P.dim, P.ph, c.L, cs(ul[l]), cs(c.f), -1.0, c.rb, nullptr, G.active);
             rb_prev = c.rb;
         }
     }
-    for (int l = P.L - 2; l >= 0; --l) {
+    const int top = std::min(P.lt, P.L - 1);
+    for (int l = top - 1; l >= 0; --l) {
         const LevelBuf& c = P.lev[l + 1];
         const LevelBuf& f = P.lev[l];
         m1::launch_prolong_project(P.st, P.dim, P.ph, f.nx, f.ny, P.px, P.py, p.eta, cs(ul[l]), cs(ul[l + 1]),
-                                   cs(c.v), ul[l]);
+                                   cs(c.v), ul[l], G.active);
         if (l == 0) {
             cur = ul[0];
-            fine_sweeps(P, cur, other, p.nu0);
+            fine_sweeps(P, cur, other, p.nu0, G);
         } else {
-            ul[l] = pseudo_smooth(P, l, dtau, ul[l]);
+            ul[l] = pseudo_smooth(P, l, G, ul[l], false);
         }
     }
 }
@@ -286,7 +324,7 @@ void vcycle_impl(m1_plan& P, Soa& cur, Soa& other, double dtau)
 // and, after a sync, the host.
 m1_status fine_norm(m1_plan& P, const Soa& v, Soa r_out, double* out, double sgn = -1.0)
 {
-    m1::launch_apply(P.st, P.dim, P.ph, P.lev[0].L, cs(v), cs(P.b), sgn, r_out, P.partials);
+    m1::launch_apply(P.st, P.dim, P.ph, P.lev[0].L, cs(v), cs(P.b), sgn, r_out, P.partials, nullptr);
     m1::launch_norm_finalize(P.st, P.partials, P.npart, P.dscal);
     hipError_t e = hipMemcpyAsync(P.hpin, P.dscal, sizeof(double), hipMemcpyDeviceToHost, P.st);
     if (e != hipSuccess) return M1_ERR_DEVICE;
@@ -408,11 +446,36 @@ m1_status m1_plan_create(const m1_grid* g, const m1_params* p, const m1_opacity*
     P->lev[0].ss = const_cast<double*>(op->sigma_s);
     fill_level_params(*P);
 
-    if (hipHostMalloc((void**)&P->hpin, 64, hipHostMallocDefault) != hipSuccess) {
+    if (hipHostMalloc((void**)&P->hpin, 64 + sizeof(m1::Ctrl), hipHostMallocDefault) != hipSuccess) {
         delete P;
         return M1_ERR_DEVICE;
     }
     P->hbad = reinterpret_cast<unsigned long long*>(P->hpin + 4);
+    P->hctrl = reinterpret_cast<m1::Ctrl*>(P->hpin + 8);
+
+    // levels small enough for one workgroup form the tail of the cycle
+    P->lt = P->L;
+    for (int l = 1; l < P->L; ++l)
+        if (P->lev[l].n <= tail_cells()) {
+            P->lt = l;
+            break;
+        }
+    m1::TailArgs ta{};
+    ta.ph = P->ph;
+    ta.lt = P->lt;
+    ta.L = P->L;
+    ta.px = P->px;
+    ta.py = P->py;
+    ta.pseudo_steps = p->pseudo_steps;
+    ta.local = p->pseudo_local;
+    ta.reach = P->reach;
+    ta.eta = p->eta;
+    const bool tail_ok = P->L <= m1::kMaxLevels && p->nu_l == 1;
+    if (!tail_ok) P->lt = P->L;  // the tail fuses exactly one Jacobi sweep per pseudo-time step
+    for (int l = 0; l < P->L && l < m1::kMaxLevels; ++l) {
+        const LevelBuf& lv = P->lev[l];
+        ta.lev[l] = m1::TailLevel{lv.L, lv.v, lv.u, lv.u2, lv.f, lv.rb};
+    }
 
     // opacity validation and the coarse opacity hierarchy
     const int64_t n0 = P->lev[0].n;
@@ -431,9 +494,10 @@ m1_status m1_plan_create(const m1_grid* g, const m1_params* p, const m1_opacity*
         F.out[0] = P->lev[l].sa;
         F.out[1] = P->lev[l].ss;
         F.n = 2;
-        m1::launch_restrict(P->st, P->dim, P->lev[l - 1].nx, P->lev[l - 1].ny, P->px, P->py, F);
+        m1::launch_restrict(P->st, P->dim, P->lev[l - 1].nx, P->lev[l - 1].ny, P->px, P->py, F, nullptr);
         st = last_launch();
     }
+    if (st == M1_OK) st = hip_status(hipMemcpyAsync(P->dtail, &ta, sizeof(ta), hipMemcpyHostToDevice, P->st));
     if (st == M1_OK) st = hip_status(hipStreamSynchronize(P->st));
     if (st != M1_OK) {
         m1_plan_destroy(P);
@@ -479,7 +543,7 @@ m1_status m1_vcycle(m1_plan* P, m1_state* v, const m1_state* vn, double dtau)
     if (!P || !valid_state(P, v) || !valid_state(P, vn) || !(dtau > 0.0) || v->E == vn->E) return M1_ERR_ARG;
     m1::launch_make_rhs(P->st, P->dim, P->lev[0].n, P->grid.c_v, cs(to_soa(vn)), P->b);
     Soa user = to_soa(v), cur = user, other = P->tmp;
-    vcycle_impl(*P, cur, other, dtau);
+    vcycle_impl(*P, cur, other, Gate{dtau, nullptr, nullptr});
     if (!same(cur, user)) m1::launch_copy(P->st, P->dim, P->lev[0].n, cs(cur), user);
     return last_launch();
 }
@@ -513,6 +577,8 @@ m1_status m1_step(m1_plan* P, m1_state* v, int32_t nsteps, m1_info* info)
     m1_status status = M1_OK;
     int total = 0;
     double r0 = 0.0, rel = 0.0, dtau = p.dtau_im0;
+    // the iterate returns to the same buffer after a cycle unless it has an odd number of sweeps
+    const bool flips = (P->L == 1) && (p.nu0 % 2 == 1);
     for (int step = 0; step < nsteps && status == M1_OK; ++step) {
         m1::launch_make_rhs(P->st, P->dim, n0, P->grid.c_v, cs(user), P->b);
         double bnorm = 0.0;
@@ -525,26 +591,63 @@ m1_status m1_step(m1_plan* P, m1_state* v, int32_t nsteps, m1_info* info)
         dtau = p.dtau_im0;
         if (info) info->steps_done = step + 1;
         if (r0 <= floor_r) continue;
-        double rprev = r0;
-        bool conv = false;
+
+        m1::Ctrl init{};
+        init.r0 = r0;
+        init.rprev = r0;
+        init.dtau = p.dtau_im0;
+        init.rel = 1.0;
+        init.floor_r = floor_r;
+        init.rtol = p.rtol;
+        init.eps_inc = p.eps_inc;
+        init.eps_dec = p.eps_dec;
+        init.dtau_min = p.dtau_min;
+        init.dtau_max = p.dtau_max;
+        init.active = 1;
+        init.cycles = -1;  // the first control call measures r0 (no cycle done yet)
+        init.max_cycles = p.max_cycles;
+        init.literal = p.dtau_rule == M1_DTAU_LITERAL;
+        m1::launch_ctrl_init(P->st, P->dctrl, init);
+        const Gate G{p.dtau_im0, &P->dctrl->dtau, &P->dctrl->active};
+
+        // Enqueue whole cycles ahead of the host's check; kernels of cycles
+        // after convergence exit at once.  Each cycle's first sweep measures the
+        // residual of the previous result, so one more (partial) cycle than
+        // needed is enqueued.  The chunk follows the observed rate.
         Soa cur = user, other = P->tmp;
-        for (int kc = 0; kc < p.max_cycles; ++kc) {
-            vcycle_impl(*P, cur, other, dtau);
-            double r = 0.0;
-            e = fine_norm(*P, cur, Soa{}, &r);
-            if (e != M1_OK) return e;
-            ++total;
-            rel = r / r0;
-            if (!std::isfinite(rel)) break;
-            dtau = adapt_dtau(p, dtau, r0, rprev, r);
-            rprev = r;
-            if (rel <= p.rtol || r <= floor_r) {
-                conv = true;
-                break;
+        int enqueued = 0, chunk = 2;
+        double prev_rel = 1.0;
+        int prev_cycles = 0;
+        for (;;) {
+            const int todo = std::min(chunk, p.max_cycles + 1 - enqueued);
+            for (int c = 0; c < todo; ++c) vcycle_impl(*P, cur, other, G, true);
+            enqueued += todo;
+            if (hipMemcpyAsync(P->hctrl, P->dctrl, sizeof(m1::Ctrl), hipMemcpyDeviceToHost, P->st) != hipSuccess ||
+                hipStreamSynchronize(P->st) != hipSuccess)
+                return M1_ERR_DEVICE;
+            if (last_launch() != M1_OK) return M1_ERR_DEVICE;
+            const m1::Ctrl h = *P->hctrl;
+            if (!h.active || enqueued >= p.max_cycles + 1) break;
+            // cycles still needed at the recent convergence rate (at least 1, at most 16 per chunk)
+            const int dc = h.cycles - prev_cycles;
+            double need = 4.0;
+            if (dc > 0 && h.rel > 0.0 && h.rel < prev_rel) {
+                const double rate = std::pow(h.rel / prev_rel, 1.0 / dc);
+                need = std::log(p.rtol / h.rel) / std::log(rate);
             }
+            chunk = (int)std::min(16.0, std::max(1.0, std::ceil(need)));
+            prev_rel = h.rel;
+            prev_cycles = h.cycles;
         }
-        if (!same(cur, user)) m1::launch_copy(P->st, P->dim, n0, cs(cur), user);
-        if (!conv) status = M1_ERR_NO_CONVERGENCE;
+        const m1::Ctrl h = *P->hctrl;
+        total += h.cycles;
+        rel = h.rel;
+        dtau = h.dtau;
+        // with an odd number of sweeps per cycle the result sits in `user` after an even cycle count
+        Soa res = user;
+        if (flips && (h.cycles % 2 == 1)) res = P->tmp;
+        if (!same(res, user)) m1::launch_copy(P->st, P->dim, n0, cs(res), user);
+        if (!h.conv) status = M1_ERR_NO_CONVERGENCE;
     }
     if (hipStreamSynchronize(P->st) != hipSuccess) return M1_ERR_DEVICE;
     if (info) {
@@ -560,7 +663,8 @@ m1_status m1_step(m1_plan* P, m1_state* v, int32_t nsteps, m1_info* info)
 m1_status m1_apply_A(m1_plan* P, int32_t level, const m1_state* v, m1_state* out)
 {
     if (!P || level < 0 || level >= P->L || !valid_level_state(P, v) || !valid_level_state(P, out)) return M1_ERR_ARG;
-    m1::launch_apply(P->st, P->dim, P->ph, P->lev[level].L, cs(to_soa(v)), CSoa{}, 1.0, to_soa(out), nullptr);
+    m1::launch_apply(P->st, P->dim, P->ph, P->lev[level].L, cs(to_soa(v)), CSoa{}, 1.0, to_soa(out), nullptr,
+                     nullptr);
     return last_launch();
 }
 
@@ -569,7 +673,7 @@ m1_status m1_sweep(m1_plan* P, const m1_state* b, const m1_state* v_in, m1_state
     if (!P || !valid_state(P, b) || !valid_state(P, v_in) || !valid_state(P, v_out) || v_in->E == v_out->E)
         return M1_ERR_ARG;
     m1::launch_relax(P->st, P->dim, P->ph, P->lev[0].L, cs(to_soa(b)), nullptr, 0.0, 1.0, P->params.omega,
-                     cs(to_soa(v_in)), to_soa(v_out));
+                     cs(to_soa(v_in)), to_soa(v_out), nullptr, nullptr);
     return last_launch();
 }
 
@@ -580,8 +684,8 @@ m1_status m1_pseudo_step(m1_plan* P, int32_t level, double dtau, const m1_state*
         !valid_level_state(P, u_in) || !valid_level_state(P, u_out) || u_in->E == u_out->E)
         return M1_ERR_ARG;
     if (P->params.nu_l != 1) return M1_ERR_ARG;  // the single-operation entry point fuses exactly one sweep
-    m1::launch_pseudo(P->st, P->dim, P->ph, P->lev[level].L, cs(to_soa(f)), cs(to_soa(u_in)), to_soa(u_out), dtau,
-                      P->reach, P->params.pseudo_local, Soa{}, nullptr);
+    m1::launch_pseudo(P->st, P->dim, P->ph, P->lev[level].L, to_soa(const_cast<m1_state*>(f)), cs(to_soa(u_in)),
+                      to_soa(u_out), dtau, nullptr, P->reach, P->params.pseudo_local, 0, Soa{}, nullptr, nullptr);
     return last_launch();
 }
 
@@ -591,7 +695,7 @@ m1_status m1_restrict(m1_plan* P, int32_t level, const m1_state* fine, m1_state*
         return M1_ERR_ARG;
     const LevelBuf& f = P->lev[level];
     m1::launch_restrict(P->st, P->dim, f.nx, f.ny, P->px, P->py,
-                        fields2(to_soa(fine), Soa{}, to_soa(coarse), Soa{}, P->dim));
+                        fields2(to_soa(fine), Soa{}, to_soa(coarse), Soa{}, P->dim), nullptr);
     return last_launch();
 }
 
@@ -603,7 +707,7 @@ m1_status m1_prolong_project(m1_plan* P, int32_t level, const m1_state* u, const
         return M1_ERR_ARG;
     const LevelBuf& f = P->lev[level];
     m1::launch_prolong_project(P->st, P->dim, P->ph, f.nx, f.ny, P->px, P->py, P->params.eta, cs(to_soa(u)),
-                               cs(to_soa(uc)), cs(to_soa(vc)), to_soa(out));
+                               cs(to_soa(uc)), cs(to_soa(vc)), to_soa(out), nullptr);
     return last_launch();
 }
 

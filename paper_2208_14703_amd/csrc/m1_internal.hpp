@@ -1,32 +1,58 @@
-// m1_internal.hpp -- kernel launchers shared by the plan/driver code.
+// m1_internal.hpp -- kernel launchers and device-side control structures
+// shared by the plan/driver code and the kernels.
 #pragma once
 
 #include "m1_device.hpp"
 
 namespace m1 {
 
-struct Fields;
+constexpr int kMaxLevels = 24;
 
-void launch_relax(hipStream_t st, int dim, const Phys& ph, const Lvl& L, CSoa rhs, const double* gamma_cell,
-                  double beta, double gamma, double omega, CSoa u, Soa out);
-void launch_pseudo(hipStream_t st, int dim, const Phys& ph, const Lvl& L, CSoa f, CSoa u, Soa out, double dtau,
-                   double reach, int local, Soa rhs_store, double* g_store);
-unsigned apply_blocks(const Lvl& L);
-void launch_apply(hipStream_t st, int dim, const Phys& ph, const Lvl& L, CSoa v, CSoa X, double sgn, Soa out,
-                  double* partials);
-void launch_norm_finalize(hipStream_t st, const double* partials, int n, double* out);
-void launch_restrict(hipStream_t st, int dim, int nxf, int nyf, int px, int py, const Fields& F);
-void launch_prolong_project(hipStream_t st, int dim, const Phys& ph, int nx, int ny, int px, int py, double eta,
-                            CSoa u, CSoa uc, CSoa vc, Soa out);
-void launch_make_rhs(hipStream_t st, int dim, int64_t n, double cv, CSoa v, Soa b);
-void launch_copy(hipStream_t st, int dim, int64_t n, CSoa a, Soa b);
-void launch_check_state(hipStream_t st, int dim, int64_t n, double c, CSoa v, unsigned long long* bad);
-void launch_check_sigma(hipStream_t st, int64_t n, const double* sa, const double* ss, unsigned long long* bad);
-
+// Up to 10 fields restricted by one launch (in[q] -> out[q]).
 struct Fields {
     const double* in[10];
     double* out[10];
     int n;
 };
+
+// Device-side cycle control of one time step (pseudo-time step adaptation and
+// the stopping test of the relative residual), updated after every V-cycle.
+struct Ctrl {
+    double r0, rprev, dtau, rel, floor_r, rtol, eps_inc, eps_dec, dtau_min, dtau_max;
+    int active, cycles, conv, max_cycles, literal, pad_;
+};
+
+// One level of the single-workgroup bottom of the V-cycle.
+struct TailLevel {
+    Lvl L;
+    Soa v, u, u2, f, rb;
+};
+
+struct TailArgs {
+    Phys ph;
+    int lt, L, px, py, pseudo_steps, local;
+    double reach, eta;
+    TailLevel lev[kMaxLevels];
+};
+
+void launch_relax(hipStream_t st, int dim, const Phys& ph, const Lvl& L, CSoa rhs, const double* gcell, double beta,
+                  double gamma, double omega, CSoa u, Soa out, double* partials, const int* active);
+void launch_pseudo(hipStream_t st, int dim, const Phys& ph, const Lvl& L, Soa f, CSoa u, Soa out, double dtau,
+                   const double* dtau_dev, double reach, int local, int first, Soa rs, double* gs, const int* active);
+unsigned apply_blocks(const Lvl& L);
+void launch_apply(hipStream_t st, int dim, const Phys& ph, const Lvl& L, CSoa v, CSoa X, double sgn, Soa out,
+                  double* partials, const int* active);
+void launch_norm_finalize(hipStream_t st, const double* partials, int n, double* out);
+void launch_norm_control(hipStream_t st, const double* partials, int n, Ctrl* ctrl);
+void launch_ctrl_init(hipStream_t st, Ctrl* ctrl, const Ctrl& init);
+void launch_restrict(hipStream_t st, int dim, int nxf, int nyf, int px, int py, const Fields& F, const int* active);
+void launch_prolong_project(hipStream_t st, int dim, const Phys& ph, int nx, int ny, int px, int py, double eta,
+                            CSoa u, CSoa uc, CSoa vc, Soa out, const int* active);
+void launch_tail(hipStream_t st, int dim, const TailArgs* args_dev, double dtau, const double* dtau_dev,
+                 const int* active);
+void launch_make_rhs(hipStream_t st, int dim, int64_t n, double cv, CSoa v, Soa b);
+void launch_copy(hipStream_t st, int dim, int64_t n, CSoa a, Soa b);
+void launch_check_state(hipStream_t st, int dim, int64_t n, double c, CSoa v, unsigned long long* bad);
+void launch_check_sigma(hipStream_t st, int64_t n, const double* sa, const double* ss, unsigned long long* bad);
 
 }  // namespace m1

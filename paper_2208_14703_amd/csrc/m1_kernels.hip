@@ -1,50 +1,70 @@
 // m1_kernels.hip -- stencil kernels of the implicit M1 multigrid (gfx950).
 //
-// All kernels run one thread per cell (256-thread blocks = 4 wave64s) over a
+// Grid kernels run one thread per cell (256-thread blocks = 4 wave64s) over a
 // 1-D launch in the XCD-aware block order of m1::xcd_block(); cell (i,j) =
 // (t % nx, t / nx).  Fields are SoA FP64 arrays.  The work is a memory-bound
-// 5-point nonlinear stencil: no MFMA, no LDS staging in this version; the
-// neighbour loads of a cell are served by L1/L2 (each cell value is fetched
-// from HBM once per sweep and re-read from cache by its four neighbours).
+// nonlinear 5-point stencil: no MFMA.  The per-cell bodies are __device__
+// functions shared by the grid kernels and by k_tail, which runs the whole
+// bottom of the V-cycle (every level small enough for one workgroup) in a
+// single launch with block barriers between the phases.
+//
+// Cycle kernels take an optional device flag `active` (skip all work when it
+// is 0) and an optional device pseudo-time step `dtau_dev`, so that whole
+// V-cycles can be enqueued ahead of the host's convergence check.
 #include "m1_internal.hpp"
 
 namespace m1 {
 
 constexpr int kBlock = 256;
+constexpr int kTailThreads = 1024;
 
 static inline unsigned nblocks(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
 
-__device__ __forceinline__ bool cell_of(const Lvl& L, int64_t& k, int& i, int& j)
+__device__ __forceinline__ bool inactive(const int* active) { return active && *active == 0; }
+
+__device__ __forceinline__ void ij_of(int nx, int64_t k, int& i, int& j)
 {
-    k = xcd_block() * kBlock + threadIdx.x;
-    const int64_t n = (int64_t)L.nx * L.ny;
-    if (k >= n) return false;
-    j = (int)(k / L.nx);
-    i = (int)(k - (int64_t)j * L.nx);
-    return true;
+    j = (int)(k / nx);
+    i = (int)(k - (int64_t)j * nx);
 }
 
-// ---------------------------------------------------------------------------
+// ===========================================================================
+// Per-cell bodies
+// ===========================================================================
+
 // Jacobi sweep of (beta M + gamma A)(u) = rhs, M = diag(1,1,1,C_v):
-//   u_out = u_in + omega (local_solve(rhs + gamma S(u_in)) - u_in).
-// gamma_cell (nullable) gives a per-cell gamma.
-template <int DIM>
-__global__ __launch_bounds__(kBlock) void k_relax(Phys ph, Lvl L, CSoa rhs, const double* __restrict__ gamma_cell,
-                                                  double beta, double gamma, double omega, CSoa u, Soa out)
+//   out = u + omega (local_solve(rhs + gamma S(u)) - u);  gcell: per-cell gamma.
+// With NORM (only for the finest-level sweep, beta = 0, gamma = 1) the cell's
+// share of |b - A(u)|^2 of the INPUT u is returned: b - A(u) = B - D(u), where
+// B = b + S(u) is formed for the update anyway.
+template <int DIM, bool NORM = false>
+__device__ __forceinline__ double relax_cell(const Phys& ph, const Lvl& L, const CSoa& rhs, const double* gcell,
+                                             double beta, double gamma, double omega, const CSoa& u, const Soa& out,
+                                             int64_t k, int i, int j)
 {
-    int64_t k;
-    int i, j;
-    if (!cell_of(L, k, i, j)) return;
     double S0, S1, S2;
     offdiag<DIM>(ph, L, u, i, j, k, S0, S1, S2);
-    const double g = gamma_cell ? gamma_cell[k] : gamma;
+    const double g = gcell ? gcell[k] : gamma;
     const double BE = fma(g, S0, rhs.E[k]);
     const double BFx = fma(g, S1, rhs.Fx[k]);
     const double BFy = (DIM == 2) ? fma(g, S2, rhs.Fy[k]) : 0.0;
+    const double BT = rhs.T[k];
     const double ka = L.cdt * L.sa[k], ks = L.cdt * L.ss[k];
     const double Tin = u.T[k];
+    double q = 0.0;
+    if (NORM) {
+        const double Ein = u.E[k], Fxin = u.Fx[k], Fyin = (DIM == 2) ? u.Fy[k] : 0.0;
+        const double T2 = Tin * Tin;
+        const double ex = ka * fma(-ph.a_r * T2, T2, Ein);  // ka (E - a_r T^4)
+        const double dF = L.a + ka + ks;
+        const double rE = BE - fma(L.a, Ein, ex);
+        const double ic = 1.0 / ph.c;
+        const double rFx = (BFx - dF * Fxin) * ic, rFy = (BFy - dF * Fyin) * ic;
+        const double rT = BT - fma(ph.c_v, Tin, -ex);
+        q = fma(rE, rE, fma(rFx, rFx, fma(rFy, rFy, rT * rT)));
+    }
     double E, Fx, Fy, T;
-    local_solve(beta, g, L.a, ka, ks, ph.c_v, ph.a_r, BE, BFx, BFy, rhs.T[k], Tin, E, Fx, Fy, T);
+    local_solve(beta, g, L.a, ka, ks, ph.c_v, ph.a_r, BE, BFx, BFy, BT, Tin, E, Fx, Fy, T);
     if (omega != 1.0) {
         const double Ein = u.E[k], Fxin = u.Fx[k];
         E = fma(omega, E - Ein, Ein);
@@ -59,32 +79,47 @@ __global__ __launch_bounds__(kBlock) void k_relax(Phys ph, Lvl L, CSoa rhs, cons
     out.Fx[k] = Fx;
     if (DIM == 2) out.Fy[k] = Fy;
     out.T[k] = T;
+    return q;
 }
 
-// ---------------------------------------------------------------------------
 // One pseudo-time step (Algorithm 3) of M du/dtau + A(u) = f, fused:
-//   s = M^{-1} f;  tau_i = min(dtau, tau*(u, s) (1 - (1-eta)^K))  (the pseudo
+//   s = M^{-1} f;  tau_i = min(dtau, tau*(u, s) (1 - (1-eta)^K)) -- the pseudo
 //   time reached by K explicit sub-steps, each eta of the remaining admissible
-//   ray); u~ = u + tau_i s;  one Jacobi sweep of (M + g A)(u) = M u~ from u,
-//   g = tau_i (local) or dtau.  With nu_l > 1 the rhs M u~ and g are stored for
-//   the further sweeps (k_relax with gamma_cell).
-template <int DIM>
-__global__ __launch_bounds__(kBlock) void k_pseudo(Phys ph, Lvl L, CSoa f, CSoa u, Soa out, double dtau, double reach,
-                                                   int local, Soa rhs_store, double* __restrict__ g_store)
+//   ray;  u~ = u + tau_i s;  one Jacobi sweep of (M + g A)(u) = M u~ from u,
+//   with g = tau_i (local) or dtau.  rs/gs (nullable) keep M u~ and g for
+//   further sweeps.  With FIRST (the first step of the pre-smoothing, u = v_l)
+//   f holds the restricted residual on entry and the FAS right-hand side
+//   f = A(v_l) + R(rbar) is formed here and written back (A(v) = D(v) - S(v),
+//   S(v) being needed for the sweep anyway).
+template <int DIM, bool FIRST = false>
+__device__ __forceinline__ void pseudo_cell(const Phys& ph, const Lvl& L, const CSoa& fin, const Soa& fout,
+                                            const CSoa& u, const Soa& out, double dtau, double reach, int local,
+                                            const Soa& rs, double* gs, int64_t k, int i, int j)
 {
-    int64_t k;
-    int i, j;
-    if (!cell_of(L, k, i, j)) return;
     const double uE = u.E[k], uFx = u.Fx[k], uFy = (DIM == 2) ? u.Fy[k] : 0.0, uT = u.T[k];
-    const double sE = f.E[k], sFx = f.Fx[k], sFy = (DIM == 2) ? f.Fy[k] : 0.0, sT = f.T[k] / ph.c_v;
+    double S0, S1, S2;
+    offdiag<DIM>(ph, L, u, i, j, k, S0, S1, S2);
+    const double ka = L.cdt * L.sa[k], ks = L.cdt * L.ss[k];
+    double fE = fin.E[k], fFx = fin.Fx[k], fFy = (DIM == 2) ? fin.Fy[k] : 0.0, fT = fin.T[k];
+    if (FIRST) {
+        const double T2 = uT * uT;
+        const double ex = ka * fma(-ph.a_r * T2, T2, uE);
+        const double dF = L.a + ka + ks;
+        fE += fma(L.a, uE, ex) - S0;
+        fFx += fma(dF, uFx, -S1);
+        fFy += fma(dF, uFy, -S2);
+        fT += fma(ph.c_v, uT, -ex);
+        fout.E[k] = fE;
+        fout.Fx[k] = fFx;
+        if (DIM == 2) fout.Fy[k] = fFy;
+        fout.T[k] = fT;
+    }
+    const double sE = fE, sFx = fFx, sFy = fFy, sT = fT / ph.c_v;
     const double ts = ray_len(ph.c2, uE, uFx, uFy, uT, sE, sFx, sFy, sT);
     const double tau = fmin(dtau, ts * reach);
     const double tE = fma(tau, sE, uE), tFx = fma(tau, sFx, uFx), tFy = fma(tau, sFy, uFy);
     const double tT = ph.c_v * fma(tau, sT, uT);
     const double g = local ? tau : dtau;
-    double S0, S1, S2;
-    offdiag<DIM>(ph, L, u, i, j, k, S0, S1, S2);
-    const double ka = L.cdt * L.sa[k], ks = L.cdt * L.ss[k];
     double E, Fx, Fy, T;
     local_solve(1.0, g, L.a, ka, ks, ph.c_v, ph.a_r, fma(g, S0, tE), fma(g, S1, tFx), fma(g, S2, tFy), tT, uT, E, Fx,
                 Fy, T);
@@ -92,194 +127,176 @@ __global__ __launch_bounds__(kBlock) void k_pseudo(Phys ph, Lvl L, CSoa f, CSoa 
     out.Fx[k] = Fx;
     if (DIM == 2) out.Fy[k] = Fy;
     out.T[k] = T;
-    if (g_store) {
-        rhs_store.E[k] = tE;
-        rhs_store.Fx[k] = tFx;
-        if (DIM == 2) rhs_store.Fy[k] = tFy;
-        rhs_store.T[k] = tT;
-        g_store[k] = g;
+    if (gs) {
+        rs.E[k] = tE;
+        rs.Fx[k] = tFx;
+        if (DIM == 2) rs.Fy[k] = tFy;
+        rs.T[k] = tT;
+        gs[k] = g;
     }
 }
 
-// ---------------------------------------------------------------------------
-// out = X + sgn A(v) (X nullable -> out = sgn A(v)); optionally stores out and
-// writes per-block partial sums of r_E^2 + (r_F/c)^2 + r_T^2 for the norm.
+// out = X + sgn A(v) (X.E == nullptr: out = sgn A(v)); out stored when out.E
+// is set.  Returns r_E^2 + (r_F/c)^2 + r_T^2 of the result (norm contribution).
 template <int DIM>
-__global__ __launch_bounds__(kBlock) void k_apply(Phys ph, Lvl L, CSoa v, CSoa X, double sgn, Soa out,
-                                                  double* __restrict__ partials)
+__device__ __forceinline__ double apply_cell(const Phys& ph, const Lvl& L, const CSoa& v, const CSoa& X, double sgn,
+                                             const Soa& out, int64_t k, int i, int j)
 {
-    __shared__ double red[kBlock / 64];
-    int64_t k;
-    int i, j;
-    double q = 0.0;
-    if (cell_of(L, k, i, j)) {
-        double S0, S1, S2;
-        offdiag<DIM>(ph, L, v, i, j, k, S0, S1, S2);
-        const double E = v.E[k], Fx = v.Fx[k], Fy = (DIM == 2) ? v.Fy[k] : 0.0, T = v.T[k];
-        const double ka = L.cdt * L.sa[k], ks = L.cdt * L.ss[k];
-        const double T2 = T * T;
-        const double ex = ka * fma(-ph.a_r * T2, T2, E);  // ka (E - a_r T^4)
-        double aE = fma(L.a, E, ex) - S0;
-        double aFx = fma(L.a + ka + ks, Fx, -S1);
-        double aFy = fma(L.a + ka + ks, Fy, -S2);
-        double aT = fma(ph.c_v, T, -ex);
-        double rE = sgn * aE, rFx = sgn * aFx, rFy = sgn * aFy, rT = sgn * aT;
-        if (X.E) {
-            rE += X.E[k];
-            rFx += X.Fx[k];
-            if (DIM == 2) rFy += X.Fy[k];
-            rT += X.T[k];
-        }
-        if (out.E) {
-            out.E[k] = rE;
-            out.Fx[k] = rFx;
-            if (DIM == 2) out.Fy[k] = rFy;
-            out.T[k] = rT;
-        }
-        const double ic = 1.0 / ph.c;
-        const double fx = rFx * ic, fy = (DIM == 2) ? rFy * ic : 0.0;
-        q = fma(rE, rE, fma(fx, fx, fma(fy, fy, rT * rT)));
+    double S0, S1, S2;
+    offdiag<DIM>(ph, L, v, i, j, k, S0, S1, S2);
+    const double E = v.E[k], Fx = v.Fx[k], Fy = (DIM == 2) ? v.Fy[k] : 0.0, T = v.T[k];
+    const double ka = L.cdt * L.sa[k], ks = L.cdt * L.ss[k];
+    const double T2 = T * T;
+    const double ex = ka * fma(-ph.a_r * T2, T2, E);  // ka (E - a_r T^4)
+    const double dF = L.a + ka + ks;
+    double rE = sgn * (fma(L.a, E, ex) - S0);
+    double rFx = sgn * fma(dF, Fx, -S1);
+    double rFy = sgn * fma(dF, Fy, -S2);
+    double rT = sgn * fma(ph.c_v, T, -ex);
+    if (X.E) {
+        rE += X.E[k];
+        rFx += X.Fx[k];
+        if (DIM == 2) rFy += X.Fy[k];
+        rT += X.T[k];
     }
-    if (partials) {
-        // fixed-order block reduction: wave64 butterfly, then the 4 waves in order
-        for (int off = 32; off > 0; off >>= 1) q += __shfl_xor(q, off, 64);
-        if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = q;
-        __syncthreads();
-        if (threadIdx.x == 0) partials[xcd_block()] = (red[0] + red[1]) + (red[2] + red[3]);
+    if (out.E) {
+        out.E[k] = rE;
+        out.Fx[k] = rFx;
+        if (DIM == 2) out.Fy[k] = rFy;
+        out.T[k] = rT;
     }
+    const double ic = 1.0 / ph.c;
+    const double fx = rFx * ic, fy = (DIM == 2) ? rFy * ic : 0.0;
+    return fma(rE, rE, fma(fx, fx, fma(fy, fy, rT * rT)));
 }
 
-// Sum of the partials in a fixed order by one block; writes sqrt to out[0].
-__global__ __launch_bounds__(1024) void k_norm_finalize(const double* __restrict__ partials, int n,
-                                                        double* __restrict__ out)
+// Full-weighting weights along one axis (1/4, 1/2, 1/4 on fine 2I-1, 2I, 2I+1):
+// periodic axes wrap, otherwise outside points get weight 0 (index clamped to a
+// valid cell) and the others are renormalised to sum 1.  Always 3 entries so
+// that every load is issued unconditionally.
+__device__ __forceinline__ void rweights(int I, int nf, bool periodic, int idx[3], double w[3])
 {
-    __shared__ double red[16];
-    double s = 0.0;
-    for (int m = threadIdx.x; m < n; m += blockDim.x) s += partials[m];
-    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        double t = 0.0;
-        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t += red[w];
-        out[0] = sqrt(t);
-    }
-}
-
-// ---------------------------------------------------------------------------
-// Full-weighting restriction (weights 1/4, 1/2, 1/4 per axis) of up to 10
-// fields from a fine level (nxf x nyf) to the coarse one.  Periodic axes wrap;
-// otherwise points outside the domain are dropped and the weights renormalised.
-__device__ __forceinline__ int rweights(int I, int nf, bool periodic, int idx[3], double w[3])
-{
-    int cnt = 0;
     double sum = 0.0;
-    const double base[3] = {0.25, 0.5, 0.25};
+#pragma unroll
     for (int m = 0; m < 3; ++m) {
+        const double base = (m == 1) ? 0.5 : 0.25;
         int f = 2 * I - 1 + m;
+        double wm = base;
         if (f < 0 || f >= nf) {
-            if (!periodic) continue;
-            f = f < 0 ? f + nf : f - nf;
+            if (periodic) {
+                f = f < 0 ? f + nf : f - nf;
+            } else {
+                f = f < 0 ? 0 : nf - 1;
+                wm = 0.0;
+            }
         }
-        idx[cnt] = f;
-        w[cnt] = base[m];
-        sum += base[m];
-        ++cnt;
+        idx[m] = f;
+        w[m] = wm;
+        sum += wm;
     }
-    if (sum != 1.0)
-        for (int m = 0; m < cnt; ++m) w[m] /= sum;
-    return cnt;
-}
-
-template <int DIM>
-__global__ __launch_bounds__(kBlock) void k_restrict(int nxf, int nyf, int px, int py, Fields F)
-{
-    const int nxc = nxf / 2, nyc = (DIM == 2) ? nyf / 2 : 1;
-    const int64_t k = xcd_block() * kBlock + threadIdx.x;
-    if (k >= (int64_t)nxc * nyc) return;
-    const int J = (int)(k / nxc), I = (int)(k - (int64_t)J * nxc);
-    int ix[3], iy[3];
-    double wx[3], wy[3];
-    const int cx = rweights(I, nxf, px != 0, ix, wx);
-    int cy = 1;
-    iy[0] = 0;
-    wy[0] = 1.0;
-    if (DIM == 2) cy = rweights(J, nyf, py != 0, iy, wy);
-    for (int q = 0; q < F.n; ++q) {
-        const double* __restrict__ src = F.in[q];
-        double s = 0.0;
-        for (int b = 0; b < cy; ++b) {
-            double t = 0.0;
-            const int64_t row = (int64_t)iy[b] * nxf;
-            for (int a = 0; a < cx; ++a) t = fma(wx[a], src[row + ix[a]], t);
-            s = fma(wy[b], t, s);
-        }
-        F.out[q][k] = s;
+    if (sum != 1.0) {
+#pragma unroll
+        for (int m = 0; m < 3; ++m) w[m] /= sum;
     }
 }
 
-// ---------------------------------------------------------------------------
-// Correction from the coarse level with admissibility (eq. prolongatedSol):
-//   e = P(uc - vc) (fine 2I <- coarse I, odd fine cells average two coarse
-//   neighbours; periodic wrap, else the missing neighbour is dropped);
-//   w = u + e; out = w if admissible, else u + eta min(tau*(u, w - u), 1) (w - u).
-__device__ __forceinline__ int pweights(int i, int nc, bool periodic, int idx[2], double w[2])
+// Restriction of NF fields for coarse cell k; all 9 x NF loads are independent.
+template <int DIM, int NF>
+__device__ __forceinline__ void restrict_cell(int nxf, int nyf, int px, int py, const double* const* in,
+                                              double* const* out, int64_t k)
 {
+    const int nxc = nxf / 2;
+    int I, J;
+    ij_of(nxc, k, I, J);
+    int ix[3], iy[3] = {0, 0, 0};
+    double wx[3], wy[3] = {1.0, 0.0, 0.0};
+    rweights(I, nxf, px != 0, ix, wx);
+    if (DIM == 2) rweights(J, nyf, py != 0, iy, wy);
+    constexpr int NB = (DIM == 2) ? 3 : 1;
+    double s[NF];
+#pragma unroll
+    for (int q = 0; q < NF; ++q) s[q] = 0.0;
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+        const int64_t row = (int64_t)iy[b] * nxf;
+        double t[NF];
+#pragma unroll
+        for (int q = 0; q < NF; ++q) t[q] = 0.0;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+#pragma unroll
+            for (int q = 0; q < NF; ++q) t[q] = fma(wx[a], in[q][row + ix[a]], t[q]);
+        }
+#pragma unroll
+        for (int q = 0; q < NF; ++q) s[q] = fma(wy[b], t[q], s[q]);
+    }
+#pragma unroll
+    for (int q = 0; q < NF; ++q) out[q][k] = s[q];
+}
+
+// Linear prolongation weights along one axis: fine 2I <- coarse I; odd fine
+// cells average coarse I and I+1 (periodic wrap, else the missing one gets
+// weight 0 and the other 1).  Always 2 entries.
+__device__ __forceinline__ void pweights(int i, int nc, bool periodic, int idx[2], double w[2])
+{
+    const int I0 = i >> 1;
+    idx[0] = I0;
     if ((i & 1) == 0) {
-        idx[0] = i >> 1;
+        idx[1] = I0;
         w[0] = 1.0;
-        return 1;
+        w[1] = 0.0;
+        return;
     }
-    int I0 = (i - 1) >> 1, I1 = I0 + 1;
+    int I1 = I0 + 1;
     if (I1 >= nc) {
         if (!periodic) {
-            idx[0] = I0;
+            idx[1] = I0;
             w[0] = 1.0;
-            return 1;
+            w[1] = 0.0;
+            return;
         }
         I1 -= nc;
     }
-    idx[0] = I0;
     idx[1] = I1;
     w[0] = 0.5;
     w[1] = 0.5;
-    return 2;
 }
 
+// Correction with admissibility (eq. prolongatedSol):
+//   w = u + P(uc - vc); out = w if admissible, else u + eta min(tau*(u, w - u), 1) (w - u).
 template <int DIM>
-__global__ __launch_bounds__(kBlock) void k_prolong_project(Phys ph, int nx, int ny, int px, int py, double eta, CSoa u,
-                                                            CSoa uc, CSoa vc, Soa out)
+__device__ __forceinline__ void prolong_cell(const Phys& ph, int nx, int ny, int px, int py, double eta, const CSoa& u,
+                                             const CSoa& uc, const CSoa& vc, const Soa& out, int64_t k)
 {
-    const int64_t k = xcd_block() * kBlock + threadIdx.x;
-    if (k >= (int64_t)nx * ny) return;
-    const int j = (int)(k / nx), i = (int)(k - (int64_t)j * nx);
+    int i, j;
+    ij_of(nx, k, i, j);
     const int nxc = nx / 2, nyc = (DIM == 2) ? ny / 2 : 1;
-    int ix[2], iy[2];
-    double wx[2], wy[2];
-    const int cx = pweights(i, nxc, px != 0, ix, wx);
-    int cy = 1;
-    iy[0] = 0;
-    wy[0] = 1.0;
-    if (DIM == 2) cy = pweights(j, nyc, py != 0, iy, wy);
-    double e[4] = {0.0, 0.0, 0.0, 0.0};
-    for (int b = 0; b < cy; ++b)
-        for (int a = 0; a < cx; ++a) {
+    int ix[2], iy[2] = {0, 0};
+    double wx[2], wy[2] = {1.0, 0.0};
+    pweights(i, nxc, px != 0, ix, wx);
+    if (DIM == 2) pweights(j, nyc, py != 0, iy, wy);
+    constexpr int NB = (DIM == 2) ? 2 : 1;
+    double e0 = 0.0, e1 = 0.0, e2 = 0.0, e3 = 0.0;
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+#pragma unroll
+        for (int a = 0; a < 2; ++a) {
             const int64_t kc = (int64_t)iy[b] * nxc + ix[a];
             const double w = wx[a] * wy[b];
-            e[0] = fma(w, uc.E[kc] - vc.E[kc], e[0]);
-            e[1] = fma(w, uc.Fx[kc] - vc.Fx[kc], e[1]);
-            if (DIM == 2) e[2] = fma(w, uc.Fy[kc] - vc.Fy[kc], e[2]);
-            e[3] = fma(w, uc.T[kc] - vc.T[kc], e[3]);
+            e0 = fma(w, uc.E[kc] - vc.E[kc], e0);
+            e1 = fma(w, uc.Fx[kc] - vc.Fx[kc], e1);
+            if (DIM == 2) e2 = fma(w, uc.Fy[kc] - vc.Fy[kc], e2);
+            e3 = fma(w, uc.T[kc] - vc.T[kc], e3);
         }
+    }
     const double uE = u.E[k], uFx = u.Fx[k], uFy = (DIM == 2) ? u.Fy[k] : 0.0, uT = u.T[k];
-    double wE = uE + e[0], wFx = uFx + e[1], wFy = uFy + e[2], wT = uT + e[3];
+    double wE = uE + e0, wFx = uFx + e1, wFy = uFy + e2, wT = uT + e3;
     if (!admissible(ph.c2, wE, wFx, wFy, wT)) {
-        const double ts = fmin(ray_len(ph.c2, uE, uFx, uFy, uT, e[0], e[1], e[2], e[3]), 1.0);
-        const double th = eta * ts;
-        wE = fma(th, e[0], uE);
-        wFx = fma(th, e[1], uFx);
-        wFy = fma(th, e[2], uFy);
-        wT = fma(th, e[3], uT);
+        const double th = eta * fmin(ray_len(ph.c2, uE, uFx, uFy, uT, e0, e1, e2, e3), 1.0);
+        wE = fma(th, e0, uE);
+        wFx = fma(th, e1, uFx);
+        wFy = fma(th, e2, uFy);
+        wT = fma(th, e3, uT);
     }
     out.E[k] = wE;
     out.Fx[k] = wFx;
@@ -287,8 +304,241 @@ __global__ __launch_bounds__(kBlock) void k_prolong_project(Phys ph, int nx, int
     out.T[k] = wT;
 }
 
+// ===========================================================================
+// Grid kernels
+// ===========================================================================
+__device__ __forceinline__ bool cell_of(const Lvl& L, int64_t& k, int& i, int& j)
+{
+    k = xcd_block() * kBlock + threadIdx.x;
+    if (k >= (int64_t)L.nx * L.ny) return false;
+    ij_of(L.nx, k, i, j);
+    return true;
+}
+
+// Fixed-order block reduction (wave64 butterfly, then the waves in order) of q
+// into partials[block].
+__device__ __forceinline__ void block_partial(double q, double* partials, int64_t block)
+{
+    __shared__ double red[kBlock / 64];
+    for (int off = 32; off > 0; off >>= 1) q += __shfl_xor(q, off, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = q;
+    __syncthreads();
+    if (threadIdx.x == 0) partials[block] = (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+// Jacobi sweep; with partials != nullptr it also writes the block partials of
+// |b - A(u)|^2 of its input (finest level, beta = 0, gamma = 1 only).
+template <int DIM>
+__global__ __launch_bounds__(kBlock) void k_relax(Phys ph, Lvl L, CSoa rhs, const double* __restrict__ gcell,
+                                                  double beta, double gamma, double omega, CSoa u, Soa out,
+                                                  double* __restrict__ partials, const int* __restrict__ active)
+{
+    if (inactive(active)) return;
+    int64_t k;
+    int i, j;
+    const bool in = cell_of(L, k, i, j);
+    if (!partials) {
+        if (in) relax_cell<DIM>(ph, L, rhs, gcell, beta, gamma, omega, u, out, k, i, j);
+        return;
+    }
+    double q = 0.0;
+    if (in) q = relax_cell<DIM, true>(ph, L, rhs, gcell, beta, gamma, omega, u, out, k, i, j);
+    block_partial(q, partials, xcd_block());
+}
+
+// One pseudo-time step; `first`: also form the FAS right-hand side in f (u = v_l).
+template <int DIM>
+__global__ __launch_bounds__(kBlock) void k_pseudo(Phys ph, Lvl L, Soa f, CSoa u, Soa out, double dtau,
+                                                   const double* __restrict__ dtau_dev, double reach, int local,
+                                                   int first, Soa rs, double* __restrict__ gs,
+                                                   const int* __restrict__ active)
+{
+    if (inactive(active)) return;
+    int64_t k;
+    int i, j;
+    if (!cell_of(L, k, i, j)) return;
+    const double dt = dtau_dev ? *dtau_dev : dtau;
+    if (first) pseudo_cell<DIM, true>(ph, L, cs(f), f, u, out, dt, reach, local, rs, gs, k, i, j);
+    else pseudo_cell<DIM, false>(ph, L, cs(f), f, u, out, dt, reach, local, rs, gs, k, i, j);
+}
+
+template <int DIM>
+__global__ __launch_bounds__(kBlock) void k_apply(Phys ph, Lvl L, CSoa v, CSoa X, double sgn, Soa out,
+                                                  double* __restrict__ partials, const int* __restrict__ active)
+{
+    if (inactive(active)) return;
+    int64_t k;
+    int i, j;
+    double q = 0.0;
+    if (cell_of(L, k, i, j)) q = apply_cell<DIM>(ph, L, v, X, sgn, out, k, i, j);
+    if (partials) block_partial(q, partials, xcd_block());
+}
+
+// Sum of the partials in a fixed order by one block.
+__device__ __forceinline__ double block_sum(const double* __restrict__ partials, int n)
+{
+    __shared__ double red[16];
+    double s = 0.0;
+    for (int m = threadIdx.x; m < n; m += blockDim.x) s += partials[m];
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+    __syncthreads();
+    double t = 0.0;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t += red[w];
+    return t;
+}
+
+__global__ __launch_bounds__(1024) void k_norm_finalize(const double* __restrict__ partials, int n,
+                                                        double* __restrict__ out)
+{
+    const double t = block_sum(partials, n);
+    if (threadIdx.x == 0) out[0] = sqrt(t);
+}
+
+// End of a V-cycle: finish the residual norm and update the cycle control
+// (pseudo-time step adaptation, stopping test, cycle count).
+__global__ __launch_bounds__(1024) void k_norm_control(const double* __restrict__ partials, int n, Ctrl* ctrl)
+{
+    if (ctrl->active == 0) return;
+    const double r = sqrt(block_sum(partials, n));
+    if (threadIdx.x != 0) return;
+    ctrl->cycles += 1;
+    const double rel = r / ctrl->r0;
+    ctrl->rel = rel;
+    const double d = ctrl->literal ? fabs(r - ctrl->rprev) / ctrl->r0 : (ctrl->rprev - r) / ctrl->rprev;
+    double dt = ctrl->dtau;
+    if (d > ctrl->eps_inc) dt *= 1.1;
+    if (d < ctrl->eps_dec) dt *= 0.5;
+    ctrl->dtau = fmin(fmax(dt, ctrl->dtau_min), ctrl->dtau_max);
+    ctrl->rprev = r;
+    if (rel <= ctrl->rtol || r <= ctrl->floor_r) {
+        ctrl->conv = 1;
+        ctrl->active = 0;
+    } else if (!isfinite(rel) || ctrl->cycles >= ctrl->max_cycles) {
+        ctrl->active = 0;
+    }
+}
+
+template <int DIM, int NF>
+__global__ __launch_bounds__(kBlock) void k_restrict(int nxf, int nyf, int px, int py, Fields F,
+                                                     const int* __restrict__ active)
+{
+    if (inactive(active)) return;
+    const int64_t nc = (int64_t)(nxf / 2) * ((DIM == 2) ? nyf / 2 : 1);
+    const int64_t k = xcd_block() * kBlock + threadIdx.x;
+    if (k >= nc) return;
+    restrict_cell<DIM, NF>(nxf, nyf, px, py, F.in, F.out, k);
+}
+
+template <int DIM>
+__global__ __launch_bounds__(kBlock) void k_prolong_project(Phys ph, int nx, int ny, int px, int py, double eta,
+                                                            CSoa u, CSoa uc, CSoa vc, Soa out,
+                                                            const int* __restrict__ active)
+{
+    if (inactive(active)) return;
+    const int64_t k = xcd_block() * kBlock + threadIdx.x;
+    if (k >= (int64_t)nx * ny) return;
+    prolong_cell<DIM>(ph, nx, ny, px, py, eta, u, uc, vc, out, k);
+}
+
 // ---------------------------------------------------------------------------
-// b = (E, Fx, Fy, C_v T) of the time step's initial state.
+// Bottom of the V-cycle in one workgroup: levels lt..L-1 (all small), entered
+// with v_lt = R(u_{lt-1}) and f_lt = R(rbar_{lt-1}) already in place; leaves
+// the smoothed, corrected u_lt in lev[lt].u.  Same per-cell bodies and the same
+// order of operations as the grid path, with __syncthreads between phases.
+template <int DIM>
+__device__ __forceinline__ Soa tail_pseudo(const TailArgs& A, const TailLevel& T, double dtau, Soa in, bool first)
+{
+    const int64_t n = (int64_t)T.L.nx * T.L.ny;
+    for (int m = 0; m < A.pseudo_steps; ++m) {
+        const Soa out = (in.E == T.u.E) ? T.u2 : T.u;
+        for (int64_t k = threadIdx.x; k < n; k += blockDim.x) {
+            int i, j;
+            ij_of(T.L.nx, k, i, j);
+            if (first && m == 0)
+                pseudo_cell<DIM, true>(A.ph, T.L, cs(T.f), T.f, cs(in), out, dtau, A.reach, A.local, Soa{}, nullptr,
+                                       k, i, j);
+            else
+                pseudo_cell<DIM, false>(A.ph, T.L, cs(T.f), T.f, cs(in), out, dtau, A.reach, A.local, Soa{},
+                                        nullptr, k, i, j);
+        }
+        __syncthreads();
+        in = out;
+    }
+    return in;
+}
+
+template <int DIM>
+__global__ __launch_bounds__(kTailThreads) void k_tail(const TailArgs* __restrict__ Ap, double dtau,
+                                                       const double* __restrict__ dtau_dev,
+                                                       const int* __restrict__ active)
+{
+    if (inactive(active)) return;
+    const TailArgs& A = *Ap;
+    const double dt = dtau_dev ? *dtau_dev : dtau;
+    unsigned in_u2 = 0;  // bit l set: the current iterate of level l is in u2 (else u)
+    auto cur = [&](int l) { return ((in_u2 >> l) & 1u) ? A.lev[l].u2 : A.lev[l].u; };
+    auto set = [&](int l, const Soa& s) {
+        if (s.E == A.lev[l].u2.E) in_u2 |= 1u << l;
+        else in_u2 &= ~(1u << l);
+    };
+    for (int l = A.lt; l < A.L; ++l) {
+        const TailLevel& T = A.lev[l];
+        const int64_t n = (int64_t)T.L.nx * T.L.ny;
+        if (l > A.lt) {
+            const TailLevel& F = A.lev[l - 1];
+            const Soa uf = cur(l - 1);
+            const double* in[8] = {uf.E, uf.Fx, uf.Fy, uf.T, F.rb.E, F.rb.Fx, F.rb.Fy, F.rb.T};
+            double* out[8] = {T.v.E, T.v.Fx, T.v.Fy, T.v.T, T.f.E, T.f.Fx, T.f.Fy, T.f.T};
+            if (DIM == 1) {  // no Fy planes: (E, Fx, T) of u then of rbar
+                in[2] = in[3];
+                in[3] = in[4];
+                in[4] = in[5];
+                in[5] = in[7];
+                out[2] = out[3];
+                out[3] = out[4];
+                out[4] = out[5];
+                out[5] = out[7];
+            }
+            for (int64_t k = threadIdx.x; k < n; k += blockDim.x)
+                restrict_cell<DIM, DIM == 2 ? 8 : 6>(F.L.nx, F.L.ny, A.px, A.py, in, out, k);
+            __syncthreads();
+        }
+        set(l, tail_pseudo<DIM>(A, T, dt, T.v, true));  // forms f = A(v) + R(rbar) on the way
+        if (l < A.L - 1) {
+            const Soa u = cur(l);
+            for (int64_t k = threadIdx.x; k < n; k += blockDim.x) {  // rbar = f - A(u)
+                int i, j;
+                ij_of(T.L.nx, k, i, j);
+                apply_cell<DIM>(A.ph, T.L, cs(u), cs(T.f), -1.0, T.rb, k, i, j);
+            }
+            __syncthreads();
+        }
+    }
+    for (int l = A.L - 2; l >= A.lt; --l) {
+        const TailLevel& T = A.lev[l];
+        const TailLevel& C = A.lev[l + 1];
+        const int64_t n = (int64_t)T.L.nx * T.L.ny;
+        const Soa u = cur(l), uc = cur(l + 1);
+        for (int64_t k = threadIdx.x; k < n; k += blockDim.x)
+            prolong_cell<DIM>(A.ph, T.L.nx, T.L.ny, A.px, A.py, A.eta, cs(u), cs(uc), cs(C.v), u, k);
+        __syncthreads();
+        set(l, tail_pseudo<DIM>(A, T, dt, u, false));
+    }
+    const TailLevel& T = A.lev[A.lt];
+    const Soa res = cur(A.lt);
+    if (res.E != T.u.E) {
+        const int64_t n = (int64_t)T.L.nx * T.L.ny;
+        for (int64_t k = threadIdx.x; k < n; k += blockDim.x) {
+            T.u.E[k] = res.E[k];
+            T.u.Fx[k] = res.Fx[k];
+            if (DIM == 2) T.u.Fy[k] = res.Fy[k];
+            T.u.T[k] = res.T[k];
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
 template <int DIM>
 __global__ __launch_bounds__(kBlock) void k_make_rhs(int64_t n, double cv, CSoa v, Soa b)
 {
@@ -312,7 +562,7 @@ __global__ __launch_bounds__(kBlock) void k_copy(int64_t n, CSoa a, Soa b)
 }
 
 // Index of the first cell that is not admissible (E > 0, T > 0, |F| <= cE (1 + 1e-12),
-// all finite); *bad must hold INT64_MAX on entry.
+// all finite); *bad must hold UINT64_MAX on entry.
 template <int DIM>
 __global__ __launch_bounds__(kBlock) void k_check_state(int64_t n, double c, CSoa v, unsigned long long* bad)
 {
@@ -334,34 +584,37 @@ __global__ __launch_bounds__(kBlock) void k_check_sigma(int64_t n, const double*
     if (!(isfinite(a) && isfinite(s) && a >= 0.0 && s >= 0.0)) atomicMin(bad, (unsigned long long)k);
 }
 
+__global__ void k_ctrl_init(Ctrl* ctrl, Ctrl init) { *ctrl = init; }
+
 // ===========================================================================
 // Launchers
 // ===========================================================================
-#define M1_DISPATCH(DIM_, KERNEL, GRID, ...)                                                       \
-    do {                                                                                           \
+#define M1_DISPATCH(DIM_, KERNEL, GRID, ...)                                                          \
+    do {                                                                                              \
         if ((DIM_) == 2) hipLaunchKernelGGL(KERNEL<2>, dim3(GRID), dim3(kBlock), 0, st, __VA_ARGS__); \
-        else hipLaunchKernelGGL(KERNEL<1>, dim3(GRID), dim3(kBlock), 0, st, __VA_ARGS__);         \
+        else hipLaunchKernelGGL(KERNEL<1>, dim3(GRID), dim3(kBlock), 0, st, __VA_ARGS__);            \
     } while (0)
 
-void launch_relax(hipStream_t st, int dim, const Phys& ph, const Lvl& L, CSoa rhs, const double* gamma_cell,
-                  double beta, double gamma, double omega, CSoa u, Soa out)
+void launch_relax(hipStream_t st, int dim, const Phys& ph, const Lvl& L, CSoa rhs, const double* gcell, double beta,
+                  double gamma, double omega, CSoa u, Soa out, double* partials, const int* active)
 {
-    M1_DISPATCH(dim, k_relax, nblocks((int64_t)L.nx * L.ny), ph, L, rhs, gamma_cell, beta, gamma, omega, u, out);
+    M1_DISPATCH(dim, k_relax, nblocks((int64_t)L.nx * L.ny), ph, L, rhs, gcell, beta, gamma, omega, u, out, partials,
+                active);
 }
 
-void launch_pseudo(hipStream_t st, int dim, const Phys& ph, const Lvl& L, CSoa f, CSoa u, Soa out, double dtau,
-                   double reach, int local, Soa rhs_store, double* g_store)
+void launch_pseudo(hipStream_t st, int dim, const Phys& ph, const Lvl& L, Soa f, CSoa u, Soa out, double dtau,
+                   const double* dtau_dev, double reach, int local, int first, Soa rs, double* gs, const int* active)
 {
-    M1_DISPATCH(dim, k_pseudo, nblocks((int64_t)L.nx * L.ny), ph, L, f, u, out, dtau, reach, local, rhs_store,
-                g_store);
+    M1_DISPATCH(dim, k_pseudo, nblocks((int64_t)L.nx * L.ny), ph, L, f, u, out, dtau, dtau_dev, reach, local, first,
+                rs, gs, active);
 }
 
 unsigned apply_blocks(const Lvl& L) { return nblocks((int64_t)L.nx * L.ny); }
 
 void launch_apply(hipStream_t st, int dim, const Phys& ph, const Lvl& L, CSoa v, CSoa X, double sgn, Soa out,
-                  double* partials)
+                  double* partials, const int* active)
 {
-    M1_DISPATCH(dim, k_apply, apply_blocks(L), ph, L, v, X, sgn, out, partials);
+    M1_DISPATCH(dim, k_apply, apply_blocks(L), ph, L, v, X, sgn, out, partials, active);
 }
 
 void launch_norm_finalize(hipStream_t st, const double* partials, int n, double* out)
@@ -369,16 +622,47 @@ void launch_norm_finalize(hipStream_t st, const double* partials, int n, double*
     hipLaunchKernelGGL(k_norm_finalize, dim3(1), dim3(1024), 0, st, partials, n, out);
 }
 
-void launch_restrict(hipStream_t st, int dim, int nxf, int nyf, int px, int py, const Fields& F)
+void launch_norm_control(hipStream_t st, const double* partials, int n, Ctrl* ctrl)
+{
+    hipLaunchKernelGGL(k_norm_control, dim3(1), dim3(1024), 0, st, partials, n, ctrl);
+}
+
+void launch_ctrl_init(hipStream_t st, Ctrl* ctrl, const Ctrl& init)
+{
+    hipLaunchKernelGGL(k_ctrl_init, dim3(1), dim3(1), 0, st, ctrl, init);
+}
+
+void launch_restrict(hipStream_t st, int dim, int nxf, int nyf, int px, int py, const Fields& F, const int* active)
 {
     const int64_t nc = (int64_t)(nxf / 2) * (dim == 2 ? nyf / 2 : 1);
-    M1_DISPATCH(dim, k_restrict, nblocks(nc), nxf, nyf, px, py, F);
+    const unsigned g = nblocks(nc);
+    const dim3 b(kBlock);
+    if (dim == 2) {
+        switch (F.n) {
+        case 2: hipLaunchKernelGGL((k_restrict<2, 2>), dim3(g), b, 0, st, nxf, nyf, px, py, F, active); break;
+        case 4: hipLaunchKernelGGL((k_restrict<2, 4>), dim3(g), b, 0, st, nxf, nyf, px, py, F, active); break;
+        default: hipLaunchKernelGGL((k_restrict<2, 8>), dim3(g), b, 0, st, nxf, nyf, px, py, F, active); break;
+        }
+    } else {
+        switch (F.n) {
+        case 2: hipLaunchKernelGGL((k_restrict<1, 2>), dim3(g), b, 0, st, nxf, nyf, px, py, F, active); break;
+        case 3: hipLaunchKernelGGL((k_restrict<1, 3>), dim3(g), b, 0, st, nxf, nyf, px, py, F, active); break;
+        default: hipLaunchKernelGGL((k_restrict<1, 6>), dim3(g), b, 0, st, nxf, nyf, px, py, F, active); break;
+        }
+    }
 }
 
 void launch_prolong_project(hipStream_t st, int dim, const Phys& ph, int nx, int ny, int px, int py, double eta,
-                            CSoa u, CSoa uc, CSoa vc, Soa out)
+                            CSoa u, CSoa uc, CSoa vc, Soa out, const int* active)
 {
-    M1_DISPATCH(dim, k_prolong_project, nblocks((int64_t)nx * ny), ph, nx, ny, px, py, eta, u, uc, vc, out);
+    M1_DISPATCH(dim, k_prolong_project, nblocks((int64_t)nx * ny), ph, nx, ny, px, py, eta, u, uc, vc, out, active);
+}
+
+void launch_tail(hipStream_t st, int dim, const TailArgs* args_dev, double dtau, const double* dtau_dev,
+                 const int* active)
+{
+    if (dim == 2) hipLaunchKernelGGL(k_tail<2>, dim3(1), dim3(kTailThreads), 0, st, args_dev, dtau, dtau_dev, active);
+    else hipLaunchKernelGGL(k_tail<1>, dim3(1), dim3(kTailThreads), 0, st, args_dev, dtau, dtau_dev, active);
 }
 
 void launch_make_rhs(hipStream_t st, int dim, int64_t n, double cv, CSoa v, Soa b)

@@ -162,6 +162,32 @@ def test_converged_step_parity(case):
     print("cycles gpu/oracle", info["cycles"], info_o["cycles"], flush=True)
 
 
+@pytest.mark.parametrize("case", ["gauss256", "hot128", "logn128", "hot128_literal", "hot128_paper"])
+def test_cycle_counts_match_oracle(case):
+    # same algorithm and readings on both sides: the cycle count to the workload's
+    # tolerance agrees up to a rounding flip of the last stopping test
+    announce("cycle counts", case)
+    extra = {}
+    if case == "gauss256":
+        prob, v, sig, run = inputs.gaussian_1d(n=256)
+    elif case.startswith("hot128"):
+        prob, v, sig, run = inputs.hot_wall_2d(n=128)
+        if case.endswith("literal"):
+            extra = dict(dtau_rule="literal", eps_inc=1e-3, eps_dec=1e-5)
+        if case.endswith("paper"):
+            extra = dict(omega=1.0, max_cycles=3000)
+    else:
+        prob, v, sig, run = inputs.lognormal_2d(n=128)
+    o = oracle.Oracle(prob, sig)
+    ref, info_o = o.step(v, 1, oracle_params(rtol=run["rtol"], **extra))
+    P = plan_for(prob, sig, rtol=run["rtol"], **extra)
+    vd = to_dev(v)
+    info = P.step(vd, 1)
+    assert info["status"] == info_o["status"] == 0
+    assert abs(info["cycles"] - info_o["cycles"]) <= 1, (info["cycles"], info_o["cycles"])
+    assert info["dtau"] == pytest.approx(info_o["dtau"], rel=0.25)
+
+
 # ------------------------------------------------------------------ full-size workload checks
 def test_full_size_hot_wall_solution_satisfies_oracle_residual():
     announce("full 1024 hot wall, 1 step")
