@@ -47,6 +47,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-cycles", type=int, default=8, help="oracle V-cycles in the CPU-baseline sample")
     ap.add_argument("--profile-only", action="store_true", help="short run for profilers: no roofline/cpu legs")
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"],
+                    help="fp64 (the workload's definition) or mixed (FP32 delta-form smoothing)")
     return ap.parse_args()
 
 
@@ -96,7 +98,7 @@ def main():
     cells = prob["nx"] * prob["ny"]
     dev_sig = binding.to_device(sig)
     v_init = binding.to_device(v0)
-    plan = binding.Plan(prob, dev_sig, dict(rtol=run["rtol"], max_cycles=20000, **SOLVER))
+    plan = binding.Plan(prob, dev_sig, dict(rtol=run["rtol"], max_cycles=20000, precision=args.precision, **SOLVER))
     v = torch.empty_like(v_init)
 
     def one_solve():
@@ -119,11 +121,11 @@ def main():
     out = {
         "metric": METRIC, "value": round(value, 3), "unit": "Mcell-updates/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(ms_per_step, 3), "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "vs_baseline": None, "dtype": "f64" if args.precision == "fp64" else "f64+f32", "data": "synthetic",
         "config": {"workload": f"hot-wall 2-D {prob['nx']}x{prob['ny']}, {run['steps']} implicit steps, "
-                               f"dt=100h/c, block opacity, FP64, rtol {run['rtol']:g}",
+                               f"dt=100h/c, block opacity, {args.precision.upper()}, rtol {run['rtol']:g}",
                    "nx": prob["nx"], "ny": prob["ny"], "time_steps": run["steps"], "rtol": run["rtol"],
-                   "precision": "fp64", "levels": infos[-1]["levels"], "omega": SOLVER["omega"]},
+                   "precision": args.precision, "levels": infos[-1]["levels"], "omega": SOLVER["omega"]},
         "time_to_rtol_ms_per_time_step": round(ms_per_step / run["steps"], 3),
         "cycles_per_time_step": cycles / run["steps"], "solver_status": status,
         "final_rel_residual": infos[-1]["rel_residual"],

@@ -3,6 +3,8 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <initializer_list>
+#include <utility>
 #include <cfloat>
 #include <climits>
 #include <cmath>
@@ -17,8 +19,10 @@
 namespace {
 
 using m1::CSoa;
+using m1::CSoa32;
 using m1::cs;
 using m1::Soa;
+using m1::Soa32;
 
 constexpr size_t kAlign = 256;
 
@@ -31,6 +35,12 @@ struct LevelBuf {
     double* g = nullptr;
     double* sa = nullptr;
     double* ss = nullptr;
+    // mixed precision (FP32): base w, restricted correction d, iterates e/e2,
+    // right-hand side g, residual rho, opacities
+    m1::Lvl32 L32{};
+    Soa32 w{}, d{}, e{}, e2{}, gg{}, rho{};
+    float* sa32 = nullptr;
+    float* ss32 = nullptr;
 };
 
 // Level sizes: coarsen while every active side stays even and >= 4 after
@@ -111,6 +121,16 @@ struct Carver {
         s.T = take(n);
         return s;
     }
+    float* take32(int64_t count) { return reinterpret_cast<float*>(take((count + 1) / 2)); }
+    Soa32 soa32(int64_t n, int dim)
+    {
+        Soa32 s;
+        s.E = take32(n);
+        s.Fx = take32(n);
+        s.Fy = dim == 2 ? take32(n) : nullptr;
+        s.T = take32(n);
+        return s;
+    }
 };
 
 }  // namespace
@@ -134,6 +154,8 @@ struct m1_plan {
     m1::Ctrl* hctrl = nullptr;     // pinned host copy
     m1::TailArgs* dtail = nullptr; // device copy of the tail description (workspace)
     int lt = 0;                    // first level run by the single-workgroup tail (L: none)
+    bool mixed = false;
+    Soa32 base32{}, r32{}, dA{}, dB{}, rho0{};  // mixed: finest-level FP32 buffers
 };
 
 namespace {
@@ -169,6 +191,26 @@ void carve(m1_plan& P, Carver& c, const std::vector<int>& nxs, const std::vector
             }
         }
     }
+    if (P.params.precision == M1_MIXED) {
+        P.base32 = c.soa32(n0, dim);
+        P.r32 = c.soa32(n0, dim);
+        P.dA = c.soa32(n0, dim);
+        P.dB = c.soa32(n0, dim);
+        P.rho0 = c.soa32(n0, dim);
+        for (int l = 0; l < P.L; ++l) {
+            LevelBuf& lv = P.lev[l];
+            lv.sa32 = c.take32(lv.n);
+            lv.ss32 = c.take32(lv.n);
+            if (l > 0) {
+                lv.w = c.soa32(lv.n, dim);
+                lv.d = c.soa32(lv.n, dim);
+                lv.e = c.soa32(lv.n, dim);
+                lv.e2 = c.soa32(lv.n, dim);
+                lv.gg = c.soa32(lv.n, dim);
+                lv.rho = c.soa32(lv.n, dim);
+            }
+        }
+    }
     P.npart = (int)((n0 + 255) / 256);
     P.partials = c.take(P.npart);
     P.dscal = c.take(8);
@@ -197,6 +239,8 @@ void fill_level_params(m1_plan& P)
         lv.L.cdt = g.c * g.dt;
         lv.L.sa = lv.sa;
         lv.L.ss = lv.ss;
+        lv.L32 = m1::Lvl32{lv.nx, lv.ny, (float)lv.L.kx, (float)lv.L.ky, (float)lv.L.a, (float)lv.L.cdt, lv.sa32,
+                           lv.ss32};
     }
 }
 
@@ -318,6 +362,100 @@ void vcycle_impl(m1_plan& P, Soa& cur, Soa& other, const Gate& G, bool control =
             ul[l] = pseudo_smooth(P, l, G, ul[l], false);
         }
     }
+}
+
+// ---- mixed precision -------------------------------------------------------
+m1::Fields32 fields32(std::initializer_list<std::pair<const Soa32*, const Soa32*>> pairs, int dim)
+{
+    m1::Fields32 F{};
+    int n = 0;
+    for (auto& pr : pairs) {
+        const Soa32& a = *pr.first;
+        const Soa32& b = *pr.second;
+        F.in[n] = a.E;
+        F.out[n++] = b.E;
+        F.in[n] = a.Fx;
+        F.out[n++] = b.Fx;
+        if (dim == 2) {
+            F.in[n] = a.Fy;
+            F.out[n++] = b.Fy;
+        }
+        F.in[n] = a.T;
+        F.out[n++] = b.T;
+    }
+    F.n = n;
+    return F;
+}
+
+bool same32(const Soa32& a, const Soa32& b) { return a.E == b.E; }
+
+Soa32 mx_pseudo_smooth(m1_plan& P, int l, const Gate& G, Soa32 start, bool first)
+{
+    LevelBuf& c = P.lev[l];
+    Soa32 in = start;
+    for (int m = 0; m < P.params.pseudo_steps; ++m) {
+        const Soa32 out = same32(in, c.e) ? c.e2 : c.e;
+        m1::launch_mx_pseudo(P.st, P.dim, P.ph, c.L32, cs(c.w), c.gg, cs(in), out, G.dtau, G.dtau_dev,
+                             (float)P.reach, P.params.pseudo_local, first && m == 0, G.active);
+        in = out;
+    }
+    return in;
+}
+
+// One mixed-precision V-cycle.  cur64 holds the FP64 state; the pending FP32
+// correction of the previous cycle (`first`: none) is applied by the FP64
+// residual kernel, which writes the updated state into the partner buffer.
+// On return `pend` is this cycle's correction (applied by the next cycle or
+// by the caller).  With `control` the FP64 residual norm feeds the cycle control.
+void mx_vcycle(m1_plan& P, Soa& cur64, Soa& other64, const Gate& G, bool control, bool first, Soa32& pend)
+{
+    const m1_params& p = P.params;
+    const LevelBuf& f0 = P.lev[0];
+    m1::launch_mx_resid(P.st, P.dim, P.ph, f0.L, p.eta, cs(cur64), first ? CSoa32{} : cs(pend), cs(P.b), other64,
+                        P.base32, P.r32, control ? P.partials : nullptr, G.active);
+    std::swap(cur64, other64);
+    if (control) m1::launch_norm_control(P.st, P.partials, P.npart, P.dctrl);
+    const float om = (float)p.omega;
+    auto sweeps = [&](Soa32 d, int count, bool from_zero) {
+        for (int s = 0; s < count; ++s) {
+            const Soa32 out = same32(d, P.dA) ? P.dB : P.dA;
+            m1::launch_mx_sweep(P.st, P.dim, P.ph, f0.L32, cs(P.base32), (from_zero && s == 0) ? CSoa32{} : cs(d),
+                                cs(P.r32), 0.0f, 1.0f, om, out, G.active);
+            d = out;
+        }
+        return d;
+    };
+    Soa32 d = sweeps(P.dB, p.nu0, true);
+    if (P.L == 1) {
+        pend = d;
+        return;
+    }
+    m1::launch_mx_apply(P.st, P.dim, P.ph, f0.L32, cs(P.base32), cs(d), cs(P.r32), -1.0f, P.rho0, G.active);
+    std::vector<Soa32> el(P.L);
+    el[0] = d;
+    const Soa32* wprev = &P.base32;
+    const Soa32* rprev = &P.rho0;
+    for (int l = 1; l < P.L; ++l) {
+        LevelBuf& c = P.lev[l];
+        const LevelBuf& fl = P.lev[l - 1];
+        m1::launch_mx_restrict(P.st, P.dim, fl.nx, fl.ny, P.px, P.py,
+                               fields32({{wprev, &c.w}, {&el[l - 1], &c.d}, {rprev, &c.gg}}, P.dim), G.active);
+        el[l] = mx_pseudo_smooth(P, l, G, c.d, true);  // forms g = N_w(d) + R(rho)
+        if (l < P.L - 1)
+            m1::launch_mx_apply(P.st, P.dim, P.ph, c.L32, cs(c.w), cs(el[l]), cs(c.gg), -1.0f, c.rho, G.active);
+        wprev = &c.w;
+        rprev = &c.rho;
+    }
+    for (int l = P.L - 2; l >= 1; --l) {
+        const LevelBuf& c = P.lev[l + 1];
+        const LevelBuf& fl = P.lev[l];
+        m1::launch_mx_prolong(P.st, P.dim, P.ph, fl.nx, fl.ny, P.px, P.py, (float)p.eta, cs(fl.w), cs(el[l]),
+                              cs(el[l + 1]), cs(c.d), el[l], G.active);
+        el[l] = mx_pseudo_smooth(P, l, G, el[l], false);
+    }
+    m1::launch_mx_prolong_fine(P.st, P.dim, P.ph, f0.nx, f0.ny, P.px, P.py, p.eta, cs(cur64), cs(el[0]), cs(el[1]),
+                               cs(P.lev[1].d), el[0], G.active);
+    pend = sweeps(el[0], p.nu0, false);
 }
 
 // |b + sgn A_0(v)| (sgn = -1: the residual; 0: |b|) into P.dscal[0] (device)
@@ -470,7 +608,8 @@ m1_status m1_plan_create(const m1_grid* g, const m1_params* p, const m1_opacity*
     ta.local = p->pseudo_local;
     ta.reach = P->reach;
     ta.eta = p->eta;
-    const bool tail_ok = P->L <= m1::kMaxLevels && p->nu_l == 1;
+    P->mixed = p->precision == M1_MIXED;
+    const bool tail_ok = P->L <= m1::kMaxLevels && p->nu_l == 1 && !P->mixed;
     if (!tail_ok) P->lt = P->L;  // the tail fuses exactly one Jacobi sweep per pseudo-time step
     for (int l = 0; l < P->L && l < m1::kMaxLevels; ++l) {
         const LevelBuf& lv = P->lev[l];
@@ -495,6 +634,11 @@ m1_status m1_plan_create(const m1_grid* g, const m1_params* p, const m1_opacity*
         F.out[1] = P->lev[l].ss;
         F.n = 2;
         m1::launch_restrict(P->st, P->dim, P->lev[l - 1].nx, P->lev[l - 1].ny, P->px, P->py, F, nullptr);
+        st = last_launch();
+    }
+    for (int l = 0; st == M1_OK && P->mixed && l < P->L; ++l) {
+        m1::launch_to_f32(P->st, P->lev[l].n, P->lev[l].sa, P->lev[l].sa32);
+        m1::launch_to_f32(P->st, P->lev[l].n, P->lev[l].ss, P->lev[l].ss32);
         st = last_launch();
     }
     if (st == M1_OK) st = hip_status(hipMemcpyAsync(P->dtail, &ta, sizeof(ta), hipMemcpyHostToDevice, P->st));
@@ -543,6 +687,14 @@ m1_status m1_vcycle(m1_plan* P, m1_state* v, const m1_state* vn, double dtau)
     if (!P || !valid_state(P, v) || !valid_state(P, vn) || !(dtau > 0.0) || v->E == vn->E) return M1_ERR_ARG;
     m1::launch_make_rhs(P->st, P->dim, P->lev[0].n, P->grid.c_v, cs(to_soa(vn)), P->b);
     Soa user = to_soa(v), cur = user, other = P->tmp;
+    if (P->mixed) {
+        Soa32 pend{};
+        mx_vcycle(*P, cur, other, Gate{dtau, nullptr, nullptr}, false, true, pend);
+        // apply the correction: the state is now in tmp; write the update back to v
+        m1::launch_mx_resid(P->st, P->dim, P->ph, P->lev[0].L, P->params.eta, cs(cur), cs(pend), cs(P->b), user,
+                            P->base32, P->r32, nullptr, nullptr);
+        return last_launch();
+    }
     vcycle_impl(*P, cur, other, Gate{dtau, nullptr, nullptr});
     if (!same(cur, user)) m1::launch_copy(P->st, P->dim, P->lev[0].n, cs(cur), user);
     return last_launch();
@@ -615,12 +767,16 @@ m1_status m1_step(m1_plan* P, m1_state* v, int32_t nsteps, m1_info* info)
         // residual of the previous result, so one more (partial) cycle than
         // needed is enqueued.  The chunk follows the observed rate.
         Soa cur = user, other = P->tmp;
+        Soa32 pend{};
         int enqueued = 0, chunk = 2;
         double prev_rel = 1.0;
         int prev_cycles = 0;
         for (;;) {
             const int todo = std::min(chunk, p.max_cycles + 1 - enqueued);
-            for (int c = 0; c < todo; ++c) vcycle_impl(*P, cur, other, G, true);
+            for (int c = 0; c < todo; ++c) {
+                if (P->mixed) mx_vcycle(*P, cur, other, G, true, enqueued + c == 0, pend);
+                else vcycle_impl(*P, cur, other, G, true);
+            }
             enqueued += todo;
             if (hipMemcpyAsync(P->hctrl, P->dctrl, sizeof(m1::Ctrl), hipMemcpyDeviceToHost, P->st) != hipSuccess ||
                 hipStreamSynchronize(P->st) != hipSuccess)
@@ -643,9 +799,15 @@ m1_status m1_step(m1_plan* P, m1_state* v, int32_t nsteps, m1_info* info)
         total += h.cycles;
         rel = h.rel;
         dtau = h.dtau;
-        // with an odd number of sweeps per cycle the result sits in `user` after an even cycle count
+        // with an odd number of sweeps per cycle the result sits in `user` after an even cycle count;
+        // in mixed precision every executed cycle (h.cycles + 1 of them, the last one only
+        // measuring) writes the FP64 state into the other buffer
         Soa res = user;
-        if (flips && (h.cycles % 2 == 1)) res = P->tmp;
+        if (P->mixed) {
+            if ((h.cycles + 1) % 2 == 1) res = P->tmp;
+        } else if (flips && (h.cycles % 2 == 1)) {
+            res = P->tmp;
+        }
         if (!same(res, user)) m1::launch_copy(P->st, P->dim, n0, cs(res), user);
         if (!h.conv) status = M1_ERR_NO_CONVERGENCE;
     }

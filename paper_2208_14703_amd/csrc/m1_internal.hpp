@@ -3,6 +3,7 @@
 #pragma once
 
 #include "m1_device.hpp"
+#include "m1_mixed.hpp"
 
 namespace m1 {
 
@@ -12,6 +13,13 @@ constexpr int kMaxLevels = 24;
 struct Fields {
     const double* in[10];
     double* out[10];
+    int n;
+};
+
+// Up to 12 FP32 fields restricted by one launch.
+struct Fields32 {
+    const float* in[12];
+    float* out[12];
     int n;
 };
 
@@ -54,5 +62,23 @@ void launch_make_rhs(hipStream_t st, int dim, int64_t n, double cv, CSoa v, Soa 
 void launch_copy(hipStream_t st, int dim, int64_t n, CSoa a, Soa b);
 void launch_check_state(hipStream_t st, int dim, int64_t n, double c, CSoa v, unsigned long long* bad);
 void launch_check_sigma(hipStream_t st, int64_t n, const double* sa, const double* ss, unsigned long long* bad);
+
+// mixed precision (m1_mixed.hip)
+void launch_mx_resid(hipStream_t st, int dim, const Phys& ph, const Lvl& L, double eta, CSoa v, CSoa32 d, CSoa b,
+                     Soa vnew, Soa32 base, Soa32 r32, double* partials, const int* active);
+void launch_mx_sweep(hipStream_t st, int dim, const Phys& ph, const Lvl32& L, CSoa32 w, CSoa32 d, CSoa32 rhs,
+                     float beta, float gamma, float omega, Soa32 out, const int* active);
+void launch_mx_apply(hipStream_t st, int dim, const Phys& ph, const Lvl32& L, CSoa32 w, CSoa32 d, CSoa32 X, float sgn,
+                     Soa32 out, const int* active);
+void launch_mx_pseudo(hipStream_t st, int dim, const Phys& ph, const Lvl32& L, CSoa32 w, Soa32 g, CSoa32 e,
+                      Soa32 out, double dtau, const double* dtau_dev, float reach, int local, int first,
+                      const int* active);
+void launch_mx_prolong(hipStream_t st, int dim, const Phys& ph, int nx, int ny, int px, int py, float eta, CSoa32 w,
+                       CSoa32 e, CSoa32 ec, CSoa32 dc, Soa32 out, const int* active);
+void launch_mx_prolong_fine(hipStream_t st, int dim, const Phys& ph, int nx, int ny, int px, int py, double eta,
+                            CSoa v, CSoa32 e, CSoa32 ec, CSoa32 dc, Soa32 out, const int* active);
+void launch_mx_restrict(hipStream_t st, int dim, int nxf, int nyf, int px, int py, const Fields32& F,
+                        const int* active);
+void launch_to_f32(hipStream_t st, int64_t n, const double* a, float* b);
 
 }  // namespace m1

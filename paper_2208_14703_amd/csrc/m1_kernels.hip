@@ -402,6 +402,17 @@ __global__ __launch_bounds__(1024) void k_norm_control(const double* __restrict_
     if (ctrl->active == 0) return;
     const double r = sqrt(block_sum(partials, n));
     if (threadIdx.x != 0) return;
+    if (ctrl->cycles < 0) {  // first call of a time step: the residual of v^n itself, no adaptation
+        ctrl->cycles = 0;
+        ctrl->r0 = r;
+        ctrl->rprev = r;
+        ctrl->rel = 1.0;
+        if (r <= ctrl->floor_r) {
+            ctrl->conv = 1;
+            ctrl->active = 0;
+        }
+        return;
+    }
     ctrl->cycles += 1;
     const double rel = r / ctrl->r0;
     ctrl->rel = rel;
