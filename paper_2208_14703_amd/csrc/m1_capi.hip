@@ -156,6 +156,7 @@ struct m1_plan {
     int lt = 0;                    // first level run by the single-workgroup tail (L: none)
     bool mixed = false;
     Soa32 base32{}, r32{}, dA{}, dB{}, rho0{};  // mixed: finest-level FP32 buffers
+    m1::TailArgs32* dtail32 = nullptr;           // mixed: device copy of the tail description
 };
 
 namespace {
@@ -217,6 +218,8 @@ void carve(m1_plan& P, Carver& c, const std::vector<int>& nxs, const std::vector
     P.dbad = reinterpret_cast<unsigned long long*>(c.take(1));
     P.dctrl = reinterpret_cast<m1::Ctrl*>(c.take((sizeof(m1::Ctrl) + 7) / 8));
     P.dtail = reinterpret_cast<m1::TailArgs*>(c.take((sizeof(m1::TailArgs) + 7) / 8));
+    if (P.params.precision == M1_MIXED)
+        P.dtail32 = reinterpret_cast<m1::TailArgs32*>(c.take((sizeof(m1::TailArgs32) + 7) / 8));
 }
 
 // Levels with at most this many cells run inside the single-workgroup tail kernel.
@@ -440,13 +443,18 @@ void mx_vcycle(m1_plan& P, Soa& cur64, Soa& other64, const Gate& G, bool control
         const LevelBuf& fl = P.lev[l - 1];
         m1::launch_mx_restrict(P.st, P.dim, fl.nx, fl.ny, P.px, P.py,
                                fields32({{wprev, &c.w}, {&el[l - 1], &c.d}, {rprev, &c.gg}}, P.dim), G.active);
+        if (l == P.lt) {  // the rest of the cycle below (and including) level lt in one workgroup
+            m1::launch_mx_tail(P.st, P.dim, P.dtail32, G.dtau, G.dtau_dev, G.active);
+            el[l] = c.e;
+            break;
+        }
         el[l] = mx_pseudo_smooth(P, l, G, c.d, true);  // forms g = N_w(d) + R(rho)
         if (l < P.L - 1)
             m1::launch_mx_apply(P.st, P.dim, P.ph, c.L32, cs(c.w), cs(el[l]), cs(c.gg), -1.0f, c.rho, G.active);
         wprev = &c.w;
         rprev = &c.rho;
     }
-    for (int l = P.L - 2; l >= 1; --l) {
+    for (int l = std::min(P.lt, P.L - 1) - 1; l >= 1; --l) {
         const LevelBuf& c = P.lev[l + 1];
         const LevelBuf& fl = P.lev[l];
         m1::launch_mx_prolong(P.st, P.dim, P.ph, fl.nx, fl.ny, P.px, P.py, (float)p.eta, cs(fl.w), cs(el[l]),
@@ -609,11 +617,25 @@ m1_status m1_plan_create(const m1_grid* g, const m1_params* p, const m1_opacity*
     ta.reach = P->reach;
     ta.eta = p->eta;
     P->mixed = p->precision == M1_MIXED;
-    const bool tail_ok = P->L <= m1::kMaxLevels && p->nu_l == 1 && !P->mixed;
+    const bool tail_ok = P->L <= m1::kMaxLevels && p->nu_l == 1;
     if (!tail_ok) P->lt = P->L;  // the tail fuses exactly one Jacobi sweep per pseudo-time step
     for (int l = 0; l < P->L && l < m1::kMaxLevels; ++l) {
         const LevelBuf& lv = P->lev[l];
         ta.lev[l] = m1::TailLevel{lv.L, lv.v, lv.u, lv.u2, lv.f, lv.rb};
+    }
+    m1::TailArgs32 ta32{};
+    ta32.ph = P->ph;
+    ta32.lt = P->lt;
+    ta32.L = P->L;
+    ta32.px = P->px;
+    ta32.py = P->py;
+    ta32.pseudo_steps = p->pseudo_steps;
+    ta32.local = p->pseudo_local;
+    ta32.reach = (float)P->reach;
+    ta32.eta = p->eta;
+    for (int l = 0; l < P->L && l < m1::kMaxLevels; ++l) {
+        const LevelBuf& lv = P->lev[l];
+        ta32.lev[l] = m1::TailLevel32{lv.L32, lv.w, lv.d, lv.e, lv.e2, lv.gg, lv.rho};
     }
 
     // opacity validation and the coarse opacity hierarchy
@@ -642,6 +664,8 @@ m1_status m1_plan_create(const m1_grid* g, const m1_params* p, const m1_opacity*
         st = last_launch();
     }
     if (st == M1_OK) st = hip_status(hipMemcpyAsync(P->dtail, &ta, sizeof(ta), hipMemcpyHostToDevice, P->st));
+    if (st == M1_OK && P->mixed)
+        st = hip_status(hipMemcpyAsync(P->dtail32, &ta32, sizeof(ta32), hipMemcpyHostToDevice, P->st));
     if (st == M1_OK) st = hip_status(hipStreamSynchronize(P->st));
     if (st != M1_OK) {
         m1_plan_destroy(P);

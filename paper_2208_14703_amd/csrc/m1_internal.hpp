@@ -63,6 +63,20 @@ void launch_copy(hipStream_t st, int dim, int64_t n, CSoa a, Soa b);
 void launch_check_state(hipStream_t st, int dim, int64_t n, double c, CSoa v, unsigned long long* bad);
 void launch_check_sigma(hipStream_t st, int64_t n, const double* sa, const double* ss, unsigned long long* bad);
 
+// One level of the mixed-precision single-workgroup tail.
+struct TailLevel32 {
+    Lvl32 L;
+    Soa32 w, d, e, e2, g, rho;
+};
+
+struct TailArgs32 {
+    Phys ph;
+    int lt, L, px, py, pseudo_steps, local;
+    float reach;
+    double eta;
+    TailLevel32 lev[kMaxLevels];
+};
+
 // mixed precision (m1_mixed.hip)
 void launch_mx_resid(hipStream_t st, int dim, const Phys& ph, const Lvl& L, double eta, CSoa v, CSoa32 d, CSoa b,
                      Soa vnew, Soa32 base, Soa32 r32, double* partials, const int* active);
@@ -79,6 +93,8 @@ void launch_mx_prolong_fine(hipStream_t st, int dim, const Phys& ph, int nx, int
                             CSoa v, CSoa32 e, CSoa32 ec, CSoa32 dc, Soa32 out, const int* active);
 void launch_mx_restrict(hipStream_t st, int dim, int nxf, int nyf, int px, int py, const Fields32& F,
                         const int* active);
+void launch_mx_tail(hipStream_t st, int dim, const TailArgs32* args_dev, double dtau, const double* dtau_dev,
+                    const int* active);
 void launch_to_f32(hipStream_t st, int64_t n, const double* a, float* b);
 
 }  // namespace m1

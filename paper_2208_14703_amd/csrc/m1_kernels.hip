@@ -200,7 +200,9 @@ __device__ __forceinline__ void rweights(int I, int nf, bool periodic, int idx[3
     }
 }
 
-// Restriction of NF fields for coarse cell k; all 9 x NF loads are independent.
+// Restriction of NF fields for coarse cell k.  All 3x3 x NF values are
+// gathered first (32-bit offsets from the per-field bases) so that every load
+// is in flight before the first use, then summed.
 template <int DIM, int NF>
 __device__ __forceinline__ void restrict_cell(int nxf, int nyf, int px, int py, const double* const* in,
                                               double* const* out, int64_t k)
@@ -213,25 +215,26 @@ __device__ __forceinline__ void restrict_cell(int nxf, int nyf, int px, int py, 
     rweights(I, nxf, px != 0, ix, wx);
     if (DIM == 2) rweights(J, nyf, py != 0, iy, wy);
     constexpr int NB = (DIM == 2) ? 3 : 1;
-    double s[NF];
+    uint32_t off[NB * 3];
 #pragma unroll
-    for (int q = 0; q < NF; ++q) s[q] = 0.0;
+    for (int b = 0; b < NB; ++b)
 #pragma unroll
-    for (int b = 0; b < NB; ++b) {
-        const int64_t row = (int64_t)iy[b] * nxf;
-        double t[NF];
+        for (int a = 0; a < 3; ++a) off[b * 3 + a] = (uint32_t)iy[b] * (uint32_t)nxf + (uint32_t)ix[a];
+    double val[NF][NB * 3];
 #pragma unroll
-        for (int q = 0; q < NF; ++q) t[q] = 0.0;
+    for (int q = 0; q < NF; ++q)
 #pragma unroll
-        for (int a = 0; a < 3; ++a) {
+        for (int m = 0; m < NB * 3; ++m) val[q][m] = in[q][off[m]];
 #pragma unroll
-            for (int q = 0; q < NF; ++q) t[q] = fma(wx[a], in[q][row + ix[a]], t[q]);
+    for (int q = 0; q < NF; ++q) {
+        double s = 0.0;
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+            const double t = fma(wx[2], val[q][b * 3 + 2], fma(wx[1], val[q][b * 3 + 1], wx[0] * val[q][b * 3]));
+            s = fma(wy[b], t, s);
         }
-#pragma unroll
-        for (int q = 0; q < NF; ++q) s[q] = fma(wy[b], t[q], s[q]);
+        out[q][k] = s;
     }
-#pragma unroll
-    for (int q = 0; q < NF; ++q) out[q][k] = s[q];
 }
 
 // Linear prolongation weights along one axis: fine 2I <- coarse I; odd fine

@@ -185,13 +185,9 @@ __device__ __forceinline__ void n_inc(const Phys& ph, const Lvl32& L, const CSoa
 
 // out = X + sgn N(d).
 template <int DIM>
-__global__ __launch_bounds__(kBlock32) void k_mx_apply(Phys ph, Lvl32 L, CSoa32 w, CSoa32 d, CSoa32 X, float sgn,
-                                                       Soa32 out, const int* __restrict__ active)
+__device__ __forceinline__ void mx_apply_cell(const Phys& ph, const Lvl32& L, const CSoa32& w, const CSoa32& d,
+                                              const CSoa32& X, float sgn, const Soa32& out, int64_t k, int i, int j)
 {
-    if (mx_inactive(active)) return;
-    int64_t k;
-    int i, j;
-    if (!mx_cell(L.nx, L.ny, k, i, j)) return;
     float NE, NFx, NFy, NT;
     n_inc<DIM>(ph, L, w, d, k, i, j, NE, NFx, NFy, NT);
     out.E[k] = fmaf(sgn, NE, X.E[k]);
@@ -200,19 +196,25 @@ __global__ __launch_bounds__(kBlock32) void k_mx_apply(Phys ph, Lvl32 L, CSoa32 
     out.T[k] = fmaf(sgn, NT, X.T[k]);
 }
 
-// One pseudo-time step of M de/dtau + N_w(e) = g (Algorithm 3 in increment
-// form).  `first`: e_in = d_l = R(correction above) and g holds R(rho) on entry;
-// g = N_w(d_l) + R(rho) is formed and stored.
 template <int DIM>
-__global__ __launch_bounds__(kBlock32) void k_mx_pseudo(Phys ph, Lvl32 L, CSoa32 w, Soa32 g, CSoa32 e, Soa32 out,
-                                                        double dtau, const double* __restrict__ dtau_dev,
-                                                        float reach, int local, int first,
-                                                        const int* __restrict__ active)
+__global__ __launch_bounds__(kBlock32) void k_mx_apply(Phys ph, Lvl32 L, CSoa32 w, CSoa32 d, CSoa32 X, float sgn,
+                                                       Soa32 out, const int* __restrict__ active)
 {
     if (mx_inactive(active)) return;
     int64_t k;
     int i, j;
     if (!mx_cell(L.nx, L.ny, k, i, j)) return;
+    mx_apply_cell<DIM>(ph, L, w, d, X, sgn, out, k, i, j);
+}
+
+// One pseudo-time step of M de/dtau + N_w(e) = g (Algorithm 3 in increment
+// form).  FIRST: e_in = d_l = R(correction above) and g holds R(rho) on entry;
+// g = N_w(d_l) + R(rho) is formed and stored.
+template <int DIM, bool FIRST>
+__device__ __forceinline__ void mx_pseudo_cell(const Phys& ph, const Lvl32& L, const CSoa32& w, const Soa32& g,
+                                               const CSoa32& e, const Soa32& out, float dt, float reach, int local,
+                                               int64_t k, int i, int j)
+{
     const float c2 = (float)ph.c2, cv = (float)ph.c_v;
     float S0, S1, S2;
     offdiag_inc<DIM>(ph, L, w, e, i, j, k, S0, S1, S2);
@@ -220,7 +222,7 @@ __global__ __launch_bounds__(kBlock32) void k_mx_pseudo(Phys ph, Lvl32 L, CSoa32
     const float wE = w.E[k], wFx = w.Fx[k], wFy = (DIM == 2) ? w.Fy[k] : 0.0f, wT = w.T[k];
     const double ka = (double)L.cdt * L.sa[k], ks = (double)L.cdt * L.ss[k];
     float gE = g.E[k], gFx = g.Fx[k], gFy = (DIM == 2) ? g.Fy[k] : 0.0f, gT = g.T[k];
-    if (first) {
+    if (FIRST) {
         float DE, DFx, DFy, DT;
         diag_inc(L.a, ka, ks, ph.c_v, ph.a_r, wT, eE, eFx, eFy, eT, DE, DFx, DFy, DT);
         gE += DE - S0;
@@ -232,8 +234,7 @@ __global__ __launch_bounds__(kBlock32) void k_mx_pseudo(Phys ph, Lvl32 L, CSoa32
         if (DIM == 2) g.Fy[k] = gFy;
         g.T[k] = gT;
     }
-    const float dt = (float)(dtau_dev ? *dtau_dev : dtau);
-    const float sT = gT / cv;
+    const float sT = gT * rcp32(cv);
     const float ts = ray_len32(c2, wE + eE, wFx + eFx, wFy + eFy, wT + eT, gE, gFx, gFy, sT);
     const float tau = fminf(dt, ts * reach);
     const float tE = fmaf(tau, gE, eE), tFx = fmaf(tau, gFx, eFx), tFy = fmaf(tau, gFy, eFy);
@@ -246,6 +247,21 @@ __global__ __launch_bounds__(kBlock32) void k_mx_pseudo(Phys ph, Lvl32 L, CSoa32
     out.Fx[k] = xFx;
     if (DIM == 2) out.Fy[k] = xFy;
     out.T[k] = xT;
+}
+
+template <int DIM>
+__global__ __launch_bounds__(kBlock32) void k_mx_pseudo(Phys ph, Lvl32 L, CSoa32 w, Soa32 g, CSoa32 e, Soa32 out,
+                                                        double dtau, const double* __restrict__ dtau_dev,
+                                                        float reach, int local, int first,
+                                                        const int* __restrict__ active)
+{
+    if (mx_inactive(active)) return;
+    int64_t k;
+    int i, j;
+    if (!mx_cell(L.nx, L.ny, k, i, j)) return;
+    const float dt = (float)(dtau_dev ? *dtau_dev : dtau);
+    if (first) mx_pseudo_cell<DIM, true>(ph, L, w, g, e, out, dt, reach, local, k, i, j);
+    else mx_pseudo_cell<DIM, false>(ph, L, w, g, e, out, dt, reach, local, k, i, j);
 }
 
 // ---------------------------------------------------------------------------
@@ -294,13 +310,10 @@ __device__ __forceinline__ void coarse_corr(int nx, int ny, int px, int py, cons
 }
 
 template <int DIM>
-__global__ __launch_bounds__(kBlock32) void k_mx_prolong(Phys ph, int nx, int ny, int px, int py, float eta, CSoa32 w,
-                                                         CSoa32 e, CSoa32 ec, CSoa32 dc, Soa32 out,
-                                                         const int* __restrict__ active)
+__device__ __forceinline__ void mx_prolong_cell(const Phys& ph, int nx, int ny, int px, int py, float eta,
+                                                const CSoa32& w, const CSoa32& e, const CSoa32& ec, const CSoa32& dc,
+                                                const Soa32& out, int64_t k)
 {
-    if (mx_inactive(active)) return;
-    const int64_t k = xcd_block() * kBlock32 + threadIdx.x;
-    if (k >= (int64_t)nx * ny) return;
     float c0, c1, c2, c3;
     coarse_corr<DIM>(nx, ny, px, py, ec, dc, k, c0, c1, c2, c3);
     const float eE = e.E[k], eFx = e.Fx[k], eFy = (DIM == 2) ? e.Fy[k] : 0.0f, eT = e.T[k];
@@ -313,6 +326,17 @@ __global__ __launch_bounds__(kBlock32) void k_mx_prolong(Phys ph, int nx, int ny
     out.Fx[k] = fmaf(th, c1, eFx);
     if (DIM == 2) out.Fy[k] = fmaf(th, c2, eFy);
     out.T[k] = fmaf(th, c3, eT);
+}
+
+template <int DIM>
+__global__ __launch_bounds__(kBlock32) void k_mx_prolong(Phys ph, int nx, int ny, int px, int py, float eta, CSoa32 w,
+                                                         CSoa32 e, CSoa32 ec, CSoa32 dc, Soa32 out,
+                                                         const int* __restrict__ active)
+{
+    if (mx_inactive(active)) return;
+    const int64_t k = xcd_block() * kBlock32 + threadIdx.x;
+    if (k >= (int64_t)nx * ny) return;
+    mx_prolong_cell<DIM>(ph, nx, ny, px, py, eta, w, e, ec, dc, out, k);
 }
 
 template <int DIM>
@@ -337,16 +361,13 @@ __global__ __launch_bounds__(kBlock32) void k_mx_prolong_fine(Phys ph, int nx, i
     out.T[k] = (float)fma(th, (double)c3, (double)eT);
 }
 
-// FP32 restriction of up to 12 fields (base, correction, residual of a level).
+// FP32 restriction of NF fields (base, correction, residual of a level) for
+// coarse cell k: full weighting, all values gathered before the sums.
 template <int DIM, int NF>
-__global__ __launch_bounds__(kBlock32) void k_mx_restrict(int nxf, int nyf, int px, int py, Fields32 F,
-                                                          const int* __restrict__ active)
+__device__ __forceinline__ void mx_restrict_cell(int nxf, int nyf, int px, int py, const float* const* in,
+                                                 float* const* out, int64_t k)
 {
-    if (mx_inactive(active)) return;
     const int nxc = nxf / 2;
-    const int64_t nc = (int64_t)nxc * ((DIM == 2) ? nyf / 2 : 1);
-    const int64_t k = xcd_block() * kBlock32 + threadIdx.x;
-    if (k >= nc) return;
     const int J = (int)(k / nxc), I = (int)(k - (int64_t)J * nxc);
     int ix[3], iy[3] = {0, 0, 0};
     float wx[3], wy[3] = {1.0f, 0.0f, 0.0f};
@@ -374,24 +395,124 @@ __global__ __launch_bounds__(kBlock32) void k_mx_restrict(int nxf, int nyf, int 
     weights(I, nxf, px != 0, ix, wx);
     if (DIM == 2) weights(J, nyf, py != 0, iy, wy);
     constexpr int NB = (DIM == 2) ? 3 : 1;
-    float s[NF];
+    uint32_t off[NB * 3];
 #pragma unroll
-    for (int q = 0; q < NF; ++q) s[q] = 0.0f;
+    for (int b = 0; b < NB; ++b)
 #pragma unroll
-    for (int b = 0; b < NB; ++b) {
-        const int64_t row = (int64_t)iy[b] * nxf;
-        float t[NF];
+        for (int a = 0; a < 3; ++a) off[b * 3 + a] = (uint32_t)iy[b] * (uint32_t)nxf + (uint32_t)ix[a];
+    float val[NF][NB * 3];
 #pragma unroll
-        for (int q = 0; q < NF; ++q) t[q] = 0.0f;
+    for (int q = 0; q < NF; ++q)
 #pragma unroll
-        for (int a = 0; a < 3; ++a)
+        for (int m = 0; m < NB * 3; ++m) val[q][m] = in[q][off[m]];
 #pragma unroll
-            for (int q = 0; q < NF; ++q) t[q] = fmaf(wx[a], F.in[q][row + ix[a]], t[q]);
+    for (int q = 0; q < NF; ++q) {
+        float s = 0.0f;
 #pragma unroll
-        for (int q = 0; q < NF; ++q) s[q] = fmaf(wy[b], t[q], s[q]);
+        for (int b = 0; b < NB; ++b) {
+            const float t = fmaf(wx[2], val[q][b * 3 + 2], fmaf(wx[1], val[q][b * 3 + 1], wx[0] * val[q][b * 3]));
+            s = fmaf(wy[b], t, s);
+        }
+        out[q][k] = s;
     }
-#pragma unroll
-    for (int q = 0; q < NF; ++q) F.out[q][k] = s[q];
+}
+
+template <int DIM, int NF>
+__global__ __launch_bounds__(kBlock32) void k_mx_restrict(int nxf, int nyf, int px, int py, Fields32 F,
+                                                          const int* __restrict__ active)
+{
+    if (mx_inactive(active)) return;
+    const int64_t nc = (int64_t)(nxf / 2) * ((DIM == 2) ? nyf / 2 : 1);
+    const int64_t k = xcd_block() * kBlock32 + threadIdx.x;
+    if (k >= nc) return;
+    mx_restrict_cell<DIM, NF>(nxf, nyf, px, py, F.in, F.out, k);
+}
+
+// ---------------------------------------------------------------------------
+// Bottom of the mixed cycle in one workgroup: levels lt..L-1, entered with
+// w_lt, d_lt and g_lt (= R(rho)) restricted; leaves e_lt (corrected, smoothed)
+// in lev[lt].e.  Same per-cell bodies and order as the grid path.
+template <int DIM>
+__device__ __forceinline__ Soa32 mx_tail_pseudo(const TailArgs32& A, const TailLevel32& T, float dt, Soa32 in,
+                                                bool first)
+{
+    const int64_t n = (int64_t)T.L.nx * T.L.ny;
+    for (int m = 0; m < A.pseudo_steps; ++m) {
+        const Soa32 out = (in.E == T.e.E) ? T.e2 : T.e;
+        for (int64_t k = threadIdx.x; k < n; k += blockDim.x) {
+            const int j = (int)(k / T.L.nx), i = (int)(k - (int64_t)j * T.L.nx);
+            if (first && m == 0) mx_pseudo_cell<DIM, true>(A.ph, T.L, cs(T.w), T.g, cs(in), out, dt, A.reach, A.local, k, i, j);
+            else mx_pseudo_cell<DIM, false>(A.ph, T.L, cs(T.w), T.g, cs(in), out, dt, A.reach, A.local, k, i, j);
+        }
+        __syncthreads();
+        in = out;
+    }
+    return in;
+}
+
+template <int DIM>
+__global__ __launch_bounds__(1024) void k_mx_tail(const TailArgs32* __restrict__ Ap, double dtau,
+                                                  const double* __restrict__ dtau_dev, const int* __restrict__ active)
+{
+    if (mx_inactive(active)) return;
+    const TailArgs32& A = *Ap;
+    const float dt = (float)(dtau_dev ? *dtau_dev : dtau);
+    unsigned in_e2 = 0;
+    auto cur = [&](int l) { return ((in_e2 >> l) & 1u) ? A.lev[l].e2 : A.lev[l].e; };
+    auto set = [&](int l, const Soa32& s) {
+        if (s.E == A.lev[l].e2.E) in_e2 |= 1u << l;
+        else in_e2 &= ~(1u << l);
+    };
+    for (int l = A.lt; l < A.L; ++l) {
+        const TailLevel32& T = A.lev[l];
+        const int64_t n = (int64_t)T.L.nx * T.L.ny;
+        if (l > A.lt) {
+            const TailLevel32& F = A.lev[l - 1];
+            const Soa32 ef = cur(l - 1);
+            const float* in[12] = {F.w.E, F.w.Fx, F.w.Fy, F.w.T, ef.E, ef.Fx, ef.Fy, ef.T, F.rho.E, F.rho.Fx, F.rho.Fy, F.rho.T};
+            float* out[12] = {T.w.E, T.w.Fx, T.w.Fy, T.w.T, T.d.E, T.d.Fx, T.d.Fy, T.d.T, T.g.E, T.g.Fx, T.g.Fy, T.g.T};
+            if (DIM == 1) {  // no Fy planes
+                const int keep[9] = {0, 1, 3, 4, 5, 7, 8, 9, 11};
+                for (int m = 0; m < 9; ++m) {
+                    in[m] = in[keep[m]];
+                    out[m] = out[keep[m]];
+                }
+            }
+            for (int64_t k = threadIdx.x; k < n; k += blockDim.x)
+                mx_restrict_cell<DIM, DIM == 2 ? 12 : 9>(F.L.nx, F.L.ny, A.px, A.py, in, out, k);
+            __syncthreads();
+        }
+        set(l, mx_tail_pseudo<DIM>(A, T, dt, T.d, true));
+        if (l < A.L - 1) {
+            const Soa32 e = cur(l);
+            for (int64_t k = threadIdx.x; k < n; k += blockDim.x) {
+                const int j = (int)(k / T.L.nx), i = (int)(k - (int64_t)j * T.L.nx);
+                mx_apply_cell<DIM>(A.ph, T.L, cs(T.w), cs(e), cs(T.g), -1.0f, T.rho, k, i, j);
+            }
+            __syncthreads();
+        }
+    }
+    for (int l = A.L - 2; l >= A.lt; --l) {
+        const TailLevel32& T = A.lev[l];
+        const TailLevel32& C = A.lev[l + 1];
+        const int64_t n = (int64_t)T.L.nx * T.L.ny;
+        const Soa32 e = cur(l), ec = cur(l + 1);
+        for (int64_t k = threadIdx.x; k < n; k += blockDim.x)
+            mx_prolong_cell<DIM>(A.ph, T.L.nx, T.L.ny, A.px, A.py, (float)A.eta, cs(T.w), cs(e), cs(ec), cs(C.d), e, k);
+        __syncthreads();
+        set(l, mx_tail_pseudo<DIM>(A, T, dt, e, false));
+    }
+    const TailLevel32& T = A.lev[A.lt];
+    const Soa32 res = cur(A.lt);
+    if (res.E != T.e.E) {
+        const int64_t n = (int64_t)T.L.nx * T.L.ny;
+        for (int64_t k = threadIdx.x; k < n; k += blockDim.x) {
+            T.e.E[k] = res.E[k];
+            T.e.Fx[k] = res.Fx[k];
+            if (DIM == 2) T.e.Fy[k] = res.Fy[k];
+            T.e.T[k] = res.T[k];
+        }
+    }
 }
 
 __global__ __launch_bounds__(kBlock32) void k_to_f32(int64_t n, const double* __restrict__ a, float* __restrict__ b)
@@ -457,6 +578,13 @@ void launch_mx_restrict(hipStream_t st, int dim, int nxf, int nyf, int px, int p
         if (F.n == 9) hipLaunchKernelGGL((k_mx_restrict<1, 9>), g, b, 0, st, nxf, nyf, px, py, F, active);
         else hipLaunchKernelGGL((k_mx_restrict<1, 2>), g, b, 0, st, nxf, nyf, px, py, F, active);
     }
+}
+
+void launch_mx_tail(hipStream_t st, int dim, const TailArgs32* args_dev, double dtau, const double* dtau_dev,
+                    const int* active)
+{
+    if (dim == 2) hipLaunchKernelGGL(k_mx_tail<2>, dim3(1), dim3(1024), 0, st, args_dev, dtau, dtau_dev, active);
+    else hipLaunchKernelGGL(k_mx_tail<1>, dim3(1), dim3(1024), 0, st, args_dev, dtau, dtau_dev, active);
 }
 
 void launch_to_f32(hipStream_t st, int64_t n, const double* a, float* b)

@@ -48,6 +48,11 @@ struct Lvl32 {
 struct DP {
     float xx, xy, yy;
 };
+// FP32 reciprocal and square root from the hardware instructions (about 1 ulp):
+// FP32 is only used for corrections, whose relative accuracy this does not
+// limit, and the correctly rounded sequences cost several times more.
+__device__ __forceinline__ float rcp32(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ float sqrt32(float x) { return __builtin_amdgcn_sqrtf(x); }
 __device__ __forceinline__ DP closure_inc(float c, float c2, float E, float Fx, float Fy, float e, float gx, float gy)
 {
     const float q = fmaf(Fx, Fx, Fy * Fy);
@@ -58,15 +63,16 @@ __device__ __forceinline__ DP closure_inc(float c, float c2, float E, float Fx, 
     const float ee = e * (2.0f * E + e);
     float dX = fmaf(4.0f * c2, ee, -3.0f * dq);
     dX = fmaxf(dX, fmaf(c2, ee, -3.0f * m));
-    const float sX = sqrtf(X);
-    const float sXn = sqrtf(fmaxf(X + dX, 0.0f));
-    const float dsq = (sXn + sX) > 0.0f ? dX / (sXn + sX) : 0.0f;
+    const float sX = sqrt32(X);
+    const float sXn = sqrt32(fmaxf(X + dX, 0.0f));
+    const float dsq = (sXn + sX) > 0.0f ? dX * rcp32(sXn + sX) : 0.0f;
     const float den = fmaf(2.0f * c, E, sX);
     const float dden = fmaf(2.0f * c, e, dsq);
     const float denn = den + dden;
-    const float r = c / den;
-    const float rn = c / denn;
-    const float dr = -r * dden / denn;
+    const float iden = rcp32(den), idenn = rcp32(denn);
+    const float r = c * iden;
+    const float rn = c * idenn;
+    const float dr = -r * dden * idenn;
     const float diso = fmaf(c2 * (1.0f / 3.0f), e, -fmaf(dq, rn, q * dr));
     const float Fxn = Fx + gx, Fyn = Fy + gy;
     DP o;
