@@ -180,6 +180,59 @@ m1_status m1_prolong_project(m1_plan* plan, int32_t level, const m1_state* u, co
 /* Wait for all work enqueued on the plan's stream. */
 m1_status m1_sync(m1_plan* plan);
 
+/* ---- batched and served solves ------------------------------------------------
+ * An engine advances many independent problems (requests) together.  Each
+ * request is one 2-D problem (grid, opacity, state, number of implicit steps);
+ * when admitted -- first come, first served, as soon as its workspace fits in
+ * the engine's arena -- it gets its own plan carved from the arena.  All
+ * admitted requests then run the same V-cycle: every level operation is ONE
+ * launch over all of them (a work list of (request, 256-cell tile) entries),
+ * the levels of at most 256 cells run as one workgroup per request, and every
+ * request keeps its own pseudo-time step, residual norm and stopping test, so
+ * its result equals the result of solving it alone.  A request's state stays
+ * in its own device arrays, updated in place, across its steps; requests that
+ * finish a step start the next one, finished requests free their workspace
+ * and waiting ones are admitted between rounds (continuous batching).
+ * Engine calls are serialised internally: submit/poll/cancel may be called from
+ * other threads while one thread runs rounds. */
+typedef struct m1_engine m1_engine;
+
+/* Workspace one request of this grid takes from the engine arena. */
+size_t m1_engine_request_bytes(const m1_grid* g, const m1_params* p);
+
+/* Engine over `arena` (device memory, 256-byte aligned, `arena_bytes` long;
+ * owned by the caller, must outlive the engine).  `p` fixes the smoothing
+ * structure every request must share (nu0, pseudo_steps (odd), sub_steps,
+ * pseudo_local, omega, eta, nu_l = 1, precision M1_FP64); per-request
+ * tolerances (rtol, max_cycles, dtau settings) may differ.  At most
+ * `max_requests` requests are resident at once.  stream: hipStream_t.        */
+m1_status m1_engine_create(const m1_params* p, void* arena, size_t arena_bytes, int32_t max_requests, void* stream,
+                           m1_engine** out);
+void m1_engine_destroy(m1_engine* e);
+
+/* Queue a request of `nsteps` implicit steps on state `v` (device arrays,
+ * caller-owned, updated in place; v and the opacity must outlive the request).
+ * p == NULL uses the engine's parameters.  M1_ERR_BUDGET if the request can
+ * never fit in the arena, M1_ERR_ARG if it is not 2-D or not compatible.     */
+m1_status m1_batch_submit(m1_engine* e, const m1_grid* g, const m1_params* p, const m1_opacity* op, m1_state* v,
+                          int32_t nsteps, uint64_t* ticket);
+/* One round: admit waiting requests that fit, start pending time steps, run
+ * `cycles` V-cycles of every resident request, retire finished steps and
+ * requests.  Blocks until the round's work is done.                          */
+m1_status m1_batch_run(m1_engine* e, int32_t cycles, int32_t* n_running, int32_t* n_pending);
+/* M1_OK and the request's result in *info once it is done, M1_ERR_BUSY while
+ * it is queued or running.                                                   */
+m1_status m1_batch_poll(m1_engine* e, uint64_t ticket, m1_info* info);
+/* Run rounds until the request is done; returns its final status.            */
+m1_status m1_batch_wait(m1_engine* e, uint64_t ticket, m1_info* info);
+/* Drop a queued or running request at the next round boundary (its state is
+ * left at its last admissible iterate).                                      */
+m1_status m1_batch_cancel(m1_engine* e, uint64_t ticket);
+/* Host steady-clock times (s) of submission, admission and completion.       */
+m1_status m1_batch_times(m1_engine* e, uint64_t ticket, double* t_submit, double* t_admit, double* t_done);
+/* Forget a finished request (frees its host record).                         */
+m1_status m1_batch_release(m1_engine* e, uint64_t ticket);
+
 #ifdef __cplusplus
 }
 #endif

@@ -98,8 +98,23 @@ def lib():
         L.m1_restrict.argtypes = [vp, ctypes.c_int32, P(m1_state), P(m1_state)]
         L.m1_prolong_project.argtypes = [vp, ctypes.c_int32, P(m1_state), P(m1_state), P(m1_state), P(m1_state)]
         L.m1_sync.argtypes = [vp]
+        L.m1_engine_request_bytes.restype = ctypes.c_size_t
+        L.m1_engine_request_bytes.argtypes = [P(m1_grid), P(m1_params)]
+        L.m1_engine_create.argtypes = [P(m1_params), vp, ctypes.c_size_t, ctypes.c_int32, vp, P(vp)]
+        L.m1_engine_destroy.argtypes = [vp]
+        L.m1_batch_submit.argtypes = [vp, P(m1_grid), P(m1_params), P(m1_opacity), P(m1_state), ctypes.c_int32,
+                                      P(ctypes.c_uint64)]
+        L.m1_batch_run.argtypes = [vp, ctypes.c_int32, P(ctypes.c_int32), P(ctypes.c_int32)]
+        L.m1_batch_poll.argtypes = [vp, ctypes.c_uint64, P(m1_info)]
+        L.m1_batch_wait.argtypes = [vp, ctypes.c_uint64, P(m1_info)]
+        L.m1_batch_cancel.argtypes = [vp, ctypes.c_uint64]
+        L.m1_batch_times.argtypes = [vp, ctypes.c_uint64, P(ctypes.c_double), P(ctypes.c_double),
+                                     P(ctypes.c_double)]
+        L.m1_batch_release.argtypes = [vp, ctypes.c_uint64]
         for name in ("m1_plan_create", "m1_residual", "m1_vcycle", "m1_step", "m1_apply_A", "m1_sweep",
-                     "m1_pseudo_step", "m1_restrict", "m1_prolong_project", "m1_sync", "m1_level_dims"):
+                     "m1_pseudo_step", "m1_restrict", "m1_prolong_project", "m1_sync", "m1_level_dims",
+                     "m1_engine_create", "m1_batch_submit", "m1_batch_run", "m1_batch_poll", "m1_batch_wait",
+                     "m1_batch_cancel", "m1_batch_times", "m1_batch_release"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -254,6 +269,92 @@ class Plan:
 
     def sync(self):
         _check(lib().m1_sync(self.handle), "m1_sync")
+
+
+def _info_dict(info: m1_info) -> dict:
+    return {"status": info.status, "cycles": info.cycles, "levels": info.levels, "steps_done": info.steps_done,
+            "r0": info.r0, "rel_residual": info.rel_residual, "dtau": info.dtau}
+
+
+class Engine:
+    """Batched / continuously batched solves of many 2-D problems (m1_engine).
+
+    The arena (a torch uint8 tensor) is allocated once; each request's plan is
+    carved from it when the request is admitted.  Requests keep references to
+    their state and opacity tensors until they are released.
+    """
+
+    def __init__(self, arena_bytes: int, params: dict | None = None, max_requests: int = 1024, device="cuda",
+                 stream=None):
+        import torch
+        self.torch = torch
+        self.params_d = default_params(**(params or {}))
+        self.params = make_params(self.params_d)
+        self.arena = torch.empty(int(arena_bytes) + 256, dtype=torch.uint8, device=device)
+        base = self.arena.data_ptr()
+        off = (-base) % 256
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.arena.device)
+        h = ctypes.c_void_p()
+        _check(lib().m1_engine_create(ctypes.byref(self.params), ctypes.c_void_p(base + off), int(arena_bytes),
+                                      max_requests, ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h)),
+               "m1_engine_create")
+        self.handle = h
+        self.keep = {}
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and _lib is not None:
+            _lib.m1_engine_destroy(h)
+            self.handle = None
+
+    @staticmethod
+    def request_bytes(problem: dict, params: dict | None = None) -> int:
+        return lib().m1_engine_request_bytes(ctypes.byref(make_grid(problem)),
+                                             ctypes.byref(make_params(default_params(**(params or {})))))
+
+    def submit(self, problem: dict, sigma, v, nsteps: int, params: dict | None = None) -> int:
+        assert v.dtype == self.torch.float64 and v.is_cuda and v.is_contiguous() and tuple(v.shape)[0] == 4
+        sigma = sigma.contiguous()
+        g = make_grid(problem)
+        p = make_params(default_params(**{**self.params_d, **(params or {})})) if params else None
+        op = m1_opacity(sigma[0].data_ptr(), sigma[1].data_ptr())
+        st = m1_state(v[0].data_ptr(), v[1].data_ptr(), v[2].data_ptr(), v[3].data_ptr())
+        t = ctypes.c_uint64()
+        _check(lib().m1_batch_submit(self.handle, ctypes.byref(g), ctypes.byref(p) if p else None, ctypes.byref(op),
+                                     ctypes.byref(st), nsteps, ctypes.byref(t)), "m1_batch_submit")
+        self.keep[t.value] = (sigma, v)
+        return t.value
+
+    def run(self, cycles: int = 4):
+        nr, npd = ctypes.c_int32(), ctypes.c_int32()
+        _check(lib().m1_batch_run(self.handle, cycles, ctypes.byref(nr), ctypes.byref(npd)), "m1_batch_run")
+        return nr.value, npd.value
+
+    def poll(self, ticket: int):
+        info = m1_info()
+        st = lib().m1_batch_poll(self.handle, ticket, ctypes.byref(info))
+        if st == 6:
+            return None
+        _check(st, "m1_batch_poll")
+        return _info_dict(info)
+
+    def wait(self, ticket: int) -> dict:
+        info = m1_info()
+        lib().m1_batch_wait(self.handle, ticket, ctypes.byref(info))
+        return _info_dict(info)
+
+    def cancel(self, ticket: int):
+        _check(lib().m1_batch_cancel(self.handle, ticket), "m1_batch_cancel")
+
+    def times(self, ticket: int):
+        a, b, c = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+        _check(lib().m1_batch_times(self.handle, ticket, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)),
+               "m1_batch_times")
+        return a.value, b.value, c.value
+
+    def release(self, ticket: int):
+        _check(lib().m1_batch_release(self.handle, ticket), "m1_batch_release")
+        self.keep.pop(ticket, None)
 
 
 def to_device(a: np.ndarray, device="cuda"):

@@ -898,3 +898,548 @@ m1_status m1_prolong_project(m1_plan* P, int32_t level, const m1_state* u, const
 }
 
 }  // extern "C"
+
+// ============================================================================
+// Batched / served solves: an engine over a caller-provided device arena.
+// ============================================================================
+#include <chrono>
+#include <deque>
+#include <map>
+#include <mutex>
+#include <unordered_map>
+
+namespace {
+
+double now_s()
+{
+    return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+enum ReqState { REQ_PENDING = 0, REQ_RUNNING = 1, REQ_DONE = 2 };
+
+}  // namespace
+
+struct m1_req {
+    uint64_t ticket = 0;
+    m1_grid grid{};
+    m1_params params{};
+    m1_opacity op{};
+    m1_state v{};
+    int nsteps = 0, steps_done = 0, cycles = 0, state = REQ_PENDING;
+    m1_status status = M1_OK;
+    double rel = 0.0, r0 = 0.0, dtau = 0.0;
+    size_t ws_off = 0, ws_bytes = 0;
+    m1_plan* plan = nullptr;
+    bool need_init = true, cancel = false;
+    double t_submit = 0.0, t_admit = 0.0, t_done = 0.0;
+};
+
+struct m1_engine {
+    m1_params params{};
+    hipStream_t st = nullptr;
+    char* arena = nullptr;
+    size_t arena_bytes = 0, pool_off = 0, pool_bytes = 0;
+    int maxp = 0;
+    m1::BProb* dP = nullptr;
+    m1::BSlot* dS = nullptr;
+    uint32_t* dWL = nullptr;
+    size_t wl_cap = 0;
+    int* dPL = nullptr;
+    m1::Ctrl* dCtrl = nullptr;
+    m1::Ctrl* hCtrl = nullptr;
+    std::map<size_t, size_t> free_;  // pool offset -> size
+    std::mutex qmu;                   // pending queue and ticket table
+    std::mutex rmu;                   // one round at a time
+    std::deque<m1_req*> pending;
+    std::vector<m1_req*> running;
+    std::unordered_map<uint64_t, m1_req*> reqs;
+    uint64_t next = 1;
+    bool dirty = true;
+    struct List {
+        int off = 0, n = 0;
+    };
+    List fine;
+    std::vector<List> restr, pdown, up;
+    int n_all = 0, n_tail = 0;
+    int Lmax = 1;
+    std::vector<uint32_t> hwl;
+    std::vector<int> hpl;
+};
+
+namespace {
+
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+bool pool_alloc(m1_engine& E, size_t bytes, size_t& off)
+{
+    bytes = align_up(bytes);
+    for (auto it = E.free_.begin(); it != E.free_.end(); ++it) {
+        if (it->second >= bytes) {
+            off = it->first;
+            const size_t rest = it->second - bytes;
+            E.free_.erase(it);
+            if (rest) E.free_[off + bytes] = rest;
+            return true;
+        }
+    }
+    return false;
+}
+
+void pool_free(m1_engine& E, size_t off, size_t bytes)
+{
+    bytes = align_up(bytes);
+    auto it = E.free_.emplace(off, bytes).first;
+    auto nx = std::next(it);
+    if (nx != E.free_.end() && it->first + it->second == nx->first) {
+        it->second += nx->second;
+        E.free_.erase(nx);
+    }
+    if (it != E.free_.begin()) {
+        auto pv = std::prev(it);
+        if (pv->first + pv->second == it->first) {
+            pv->second += it->second;
+            E.free_.erase(it);
+        }
+    }
+}
+
+// Requests in a batch: 2-D, at least two levels, an odd number of pseudo-time
+// steps, the engine's smoothing structure; tolerances may differ per request.
+bool batch_compatible(const m1_engine& E, const m1_grid* g, const m1_params* p)
+{
+    if (!valid_grid(g) || !valid_params(p) || g->dim != 2) return false;
+    const m1_params& e = E.params;
+    if (p->nu0 != e.nu0 || p->nu_l != 1 || p->pseudo_steps != e.pseudo_steps || p->sub_steps != e.sub_steps ||
+        p->pseudo_local != e.pseudo_local || p->precision != e.precision || p->omega != e.omega || p->eta != e.eta)
+        return false;
+    std::vector<int> nxs, nys;
+    if (!level_dims(*g, *p, nxs, nys) || nxs.size() < 2 || (int)nxs.size() > m1::kMaxLevels) return false;
+    return true;
+}
+
+void finish(m1_engine& E, m1_req* R, m1_status st)
+{
+    R->status = st;
+    R->t_done = now_s();
+    if (R->plan) {
+        m1_plan_destroy(R->plan);
+        R->plan = nullptr;
+    }
+    pool_free(E, R->ws_off, R->ws_bytes);
+    std::lock_guard<std::mutex> g(E.qmu);
+    R->state = REQ_DONE;
+}
+
+// FIFO admission: take pending requests while their workspace fits.
+void admit(m1_engine& E)
+{
+    for (;;) {
+        m1_req* R = nullptr;
+        {
+            std::lock_guard<std::mutex> g(E.qmu);
+            if (E.pending.empty() || (int)E.running.size() >= E.maxp) return;
+            R = E.pending.front();
+            if (R->cancel) {
+                E.pending.pop_front();
+                R->state = REQ_DONE;
+                R->status = M1_ERR_BUSY;
+                R->t_done = now_s();
+                continue;
+            }
+            size_t off;
+            if (!pool_alloc(E, R->ws_bytes, off)) return;
+            R->ws_off = off;
+            E.pending.pop_front();
+        }
+        m1_status st = m1_plan_create(&R->grid, &R->params, &R->op, E.arena + E.pool_off + R->ws_off, R->ws_bytes,
+                                      E.st, &R->plan);
+        if (st != M1_OK) {
+            finish(E, R, st);
+            continue;
+        }
+        R->t_admit = now_s();
+        R->need_init = true;
+        {
+            std::lock_guard<std::mutex> g(E.qmu);
+            R->state = REQ_RUNNING;
+        }
+        E.running.push_back(R);
+        E.dirty = true;
+    }
+}
+
+// Device tables of the running set: per-problem data, (problem, level) slots,
+// and the work lists of every level operation.
+m1_status rebuild(m1_engine& E)
+{
+    const int np = (int)E.running.size();
+    std::vector<m1::BProb> hp(np);
+    std::vector<m1::BSlot> hs((size_t)np * m1::kMaxLevels);
+    E.Lmax = 1;
+    for (int i = 0; i < np; ++i) {
+        const m1_plan& P = *E.running[i]->plan;
+        const m1_params& rp = E.running[i]->params;
+        m1::BProb& b = hp[i];
+        b.ph = P.ph;
+        b.px = P.px;
+        b.py = P.py;
+        b.L = P.L;
+        b.lt = P.lt;
+        b.local = rp.pseudo_local;
+        b.pseudo_steps = rp.pseudo_steps;
+        b.npart = P.npart;
+        b.eta = rp.eta;
+        b.reach = P.reach;
+        b.omega = rp.omega;
+        b.ctrl = P.dctrl;
+        b.partials = P.partials;
+        b.tail = P.dtail;
+        m1::Ctrl c{};
+        c.dtau = rp.dtau_im0;
+        c.rtol = rp.rtol;
+        c.eps_inc = rp.eps_inc;
+        c.eps_dec = rp.eps_dec;
+        c.dtau_min = rp.dtau_min;
+        c.dtau_max = rp.dtau_max;
+        c.max_cycles = rp.max_cycles;
+        c.literal = rp.dtau_rule == M1_DTAU_LITERAL;
+        b.proto = c;
+        for (int l = 0; l < P.L; ++l) {
+            m1::BSlot& s = hs[(size_t)i * m1::kMaxLevels + l];
+            const LevelBuf& lv = P.lev[l];
+            s.L = lv.L;
+            s.v = lv.v;
+            s.u = lv.u;
+            s.u2 = lv.u2;
+            s.f = lv.f;
+            s.rb = lv.rb;
+            if (l == 0) {
+                s.b = P.b;
+                s.x0 = to_soa(&E.running[i]->v);
+                s.x1 = P.tmp;
+                s.rf = P.rfine;
+            }
+        }
+        E.Lmax = std::max(E.Lmax, P.L);
+    }
+    // work lists
+    E.hwl.clear();
+    auto tiles = [](int64_t n) { return (uint32_t)((n + 255) / 256); };
+    auto make = [&](auto pred, int level) {
+        m1_engine::List L;
+        L.off = (int)E.hwl.size();
+        for (int i = 0; i < np; ++i) {
+            const m1_plan& P = *E.running[i]->plan;
+            if (level >= P.L || !pred(P)) continue;
+            const uint32_t nt = tiles(P.lev[level].n);
+            for (uint32_t t = 0; t < nt; ++t) E.hwl.push_back(((uint32_t)i << m1::kTileBits) | t);
+        }
+        L.n = (int)E.hwl.size() - L.off;
+        return L;
+    };
+    E.fine = make([](const m1_plan&) { return true; }, 0);
+    E.restr.assign(E.Lmax, {});
+    E.pdown.assign(E.Lmax, {});
+    E.up.assign(E.Lmax, {});
+    for (int l = 0; l < E.Lmax; ++l) {
+        auto top = [](const m1_plan& P) { return std::min(P.lt, P.L - 1); };
+        if (l >= 1) {
+            E.restr[l] = make([&](const m1_plan& P) { return l <= top(P); }, l);
+            E.pdown[l] = make([&](const m1_plan& P) { return l < P.lt; }, l);
+        }
+        E.up[l] = make([&](const m1_plan& P) { return l < top(P); }, l);
+    }
+    if (E.hwl.size() > E.wl_cap) return M1_ERR_BUDGET;
+    // problem lists: all, then those with a tail
+    E.hpl.clear();
+    for (int i = 0; i < np; ++i) E.hpl.push_back(i);
+    E.n_all = np;
+    for (int i = 0; i < np; ++i)
+        if (E.running[i]->plan->lt < E.running[i]->plan->L) E.hpl.push_back(i);
+    E.n_tail = (int)E.hpl.size() - np;
+    if (np > 0) {
+        if (hipMemcpyAsync(E.dP, hp.data(), sizeof(m1::BProb) * np, hipMemcpyHostToDevice, E.st) != hipSuccess ||
+            hipMemcpyAsync(E.dS, hs.data(), sizeof(m1::BSlot) * hs.size(), hipMemcpyHostToDevice, E.st) !=
+                hipSuccess ||
+            hipMemcpyAsync(E.dWL, E.hwl.data(), sizeof(uint32_t) * E.hwl.size(), hipMemcpyHostToDevice, E.st) !=
+                hipSuccess ||
+            hipMemcpyAsync(E.dPL, E.hpl.data(), sizeof(int) * E.hpl.size(), hipMemcpyHostToDevice, E.st) != hipSuccess)
+            return M1_ERR_DEVICE;
+        if (hipStreamSynchronize(E.st) != hipSuccess) return M1_ERR_DEVICE;
+    }
+    E.dirty = false;
+    return M1_OK;
+}
+
+// One V-cycle of every running problem: each level operation is one launch.
+// Selectors: with an odd number of pseudo-time steps every level's down-leg,
+// up-leg and tail results end in u; the up leg starts from u2.
+void b_vcycle(m1_engine& E)
+{
+    const int nu0 = E.params.nu0, m = E.params.pseudo_steps;
+    const uint32_t* wl = E.dWL;
+    int in_x1 = 0;
+    for (int s = 0; s < nu0; ++s) {
+        m1::launch_b_relax(E.st, E.dP, E.dS, wl + E.fine.off, E.fine.n, in_x1, s == 0);
+        if (s == 0) m1::launch_b_norm_control(E.st, E.dP, E.dPL, E.n_all);
+        in_x1 ^= 1;
+    }
+    m1::launch_b_apply(E.st, E.dP, E.dS, wl + E.up[0].off, E.up[0].n, 0, in_x1);
+    for (int l = 1; l < E.Lmax; ++l) {
+        m1::launch_b_restrict(E.st, E.dP, E.dS, wl + E.restr[l].off, E.restr[l].n, l, l == 1 ? in_x1 : 1);
+        int in = 0;
+        for (int k = 0; k < m; ++k) {
+            const int out = (in == 1) ? 2 : 1;
+            m1::launch_b_pseudo(E.st, E.dP, E.dS, wl + E.pdown[l].off, E.pdown[l].n, l, in, out, k == 0);
+            in = out;
+        }
+        m1::launch_b_apply(E.st, E.dP, E.dS, wl + E.up[l].off, E.up[l].n, l, 1);
+    }
+    m1::launch_b_tail(E.st, E.dP, E.dPL + E.n_all, E.n_tail);
+    for (int l = E.Lmax - 2; l >= 0; --l) {
+        if (l == 0) {
+            m1::launch_b_prolong(E.st, E.dP, E.dS, wl + E.up[0].off, E.up[0].n, 0, in_x1, 0);
+        } else {
+            m1::launch_b_prolong(E.st, E.dP, E.dS, wl + E.up[l].off, E.up[l].n, l, 1, 2);
+            int in = 2;
+            for (int k = 0; k < m; ++k) {
+                const int out = (in == 1) ? 2 : 1;
+                m1::launch_b_pseudo(E.st, E.dP, E.dS, wl + E.up[l].off, E.up[l].n, l, in, out, 0);
+                in = out;
+            }
+        }
+    }
+    for (int s = 0; s < nu0; ++s) {
+        m1::launch_b_relax(E.st, E.dP, E.dS, wl + E.fine.off, E.fine.n, in_x1, 0);
+        in_x1 ^= 1;
+    }
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t m1_engine_request_bytes(const m1_grid* g, const m1_params* p) { return align_up(m1_workspace_bytes(g, p)); }
+
+m1_status m1_engine_create(const m1_params* p, void* arena, size_t arena_bytes, int32_t max_requests, void* stream,
+                           m1_engine** out)
+{
+    if (!out) return M1_ERR_ARG;
+    *out = nullptr;
+    if (!valid_params(p) || max_requests < 1 || max_requests > (1 << (32 - m1::kTileBits)) ||
+        p->pseudo_steps % 2 == 0 || p->nu_l != 1 || p->precision != M1_FP64)
+        return M1_ERR_ARG;
+    if (!arena || (reinterpret_cast<uintptr_t>(arena) % kAlign) != 0) return M1_ERR_WORKSPACE;
+    m1_engine* E = new (std::nothrow) m1_engine();
+    if (!E) return M1_ERR_DEVICE;
+    E->params = *p;
+    E->st = static_cast<hipStream_t>(stream);
+    E->arena = static_cast<char*>(arena);
+    E->arena_bytes = arena_bytes;
+    E->maxp = max_requests;
+    // tables at the start of the arena; work lists sized for the whole pool
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t o = off;
+        off = align_up(off + bytes);
+        return E->arena + o;
+    };
+    E->dP = reinterpret_cast<m1::BProb*>(take(sizeof(m1::BProb) * max_requests));
+    E->dS = reinterpret_cast<m1::BSlot*>(take(sizeof(m1::BSlot) * (size_t)max_requests * m1::kMaxLevels));
+    E->dPL = reinterpret_cast<int*>(take(sizeof(int) * 3 * (size_t)max_requests));
+    E->dCtrl = reinterpret_cast<m1::Ctrl*>(take(sizeof(m1::Ctrl) * max_requests));
+    E->wl_cap = std::max<size_t>(arena_bytes / 512, 1 << 16);
+    E->dWL = reinterpret_cast<uint32_t*>(take(sizeof(uint32_t) * E->wl_cap));
+    if (off >= arena_bytes) {
+        delete E;
+        return M1_ERR_WORKSPACE;
+    }
+    E->pool_off = off;
+    E->pool_bytes = arena_bytes - off;
+    E->free_[0] = E->pool_bytes / kAlign * kAlign;
+    if (hipHostMalloc((void**)&E->hCtrl, sizeof(m1::Ctrl) * max_requests, hipHostMallocDefault) != hipSuccess) {
+        delete E;
+        return M1_ERR_DEVICE;
+    }
+    *out = E;
+    return M1_OK;
+}
+
+void m1_engine_destroy(m1_engine* E)
+{
+    if (!E) return;
+    (void)hipStreamSynchronize(E->st);
+    for (auto& kv : E->reqs) {
+        if (kv.second->plan) m1_plan_destroy(kv.second->plan);
+        delete kv.second;
+    }
+    if (E->hCtrl) (void)hipHostFree(E->hCtrl);
+    delete E;
+}
+
+m1_status m1_batch_submit(m1_engine* E, const m1_grid* g, const m1_params* p, const m1_opacity* op, m1_state* v,
+                          int32_t nsteps, uint64_t* ticket)
+{
+    if (!E || !ticket || !op || !op->sigma_a || !op->sigma_s || !v || !v->E || !v->Fx || !v->Fy || !v->T ||
+        nsteps < 1)
+        return M1_ERR_ARG;
+    const m1_params& pp = p ? *p : E->params;
+    if (!batch_compatible(*E, g, &pp)) return M1_ERR_ARG;
+    const size_t need = m1_engine_request_bytes(g, &pp);
+    if (need == 0) return M1_ERR_ARG;
+    if (need > E->pool_bytes) return M1_ERR_BUDGET;
+    m1_req* R = new (std::nothrow) m1_req();
+    if (!R) return M1_ERR_DEVICE;
+    R->grid = *g;
+    R->params = pp;
+    R->op = *op;
+    R->v = *v;
+    R->nsteps = nsteps;
+    R->ws_bytes = need;
+    R->t_submit = now_s();
+    std::lock_guard<std::mutex> lk(E->qmu);
+    R->ticket = E->next++;
+    E->reqs[R->ticket] = R;
+    E->pending.push_back(R);
+    *ticket = R->ticket;
+    return M1_OK;
+}
+
+m1_status m1_batch_run(m1_engine* E, int32_t cycles, int32_t* n_running, int32_t* n_pending)
+{
+    if (!E || cycles < 1) return M1_ERR_ARG;
+    std::lock_guard<std::mutex> lk(E->rmu);
+    // drop cancelled running requests
+    for (size_t i = 0; i < E->running.size();) {
+        m1_req* R = E->running[i];
+        if (R->cancel) {
+            finish(*E, R, M1_ERR_BUSY);
+            E->running.erase(E->running.begin() + i);
+            E->dirty = true;
+        } else {
+            ++i;
+        }
+    }
+    admit(*E);
+    m1_status st = M1_OK;
+    if (!E->running.empty()) {
+        if (E->dirty) st = rebuild(*E);
+        if (st != M1_OK) return st;
+        std::vector<int> init;
+        for (int i = 0; i < (int)E->running.size(); ++i)
+            if (E->running[i]->need_init) {
+                init.push_back(i);
+                E->running[i]->need_init = false;
+            }
+        if (!init.empty()) {
+            int* dinit = E->dPL + 2 * E->maxp;
+            if (hipMemcpyAsync(dinit, init.data(), sizeof(int) * init.size(), hipMemcpyHostToDevice, E->st) !=
+                hipSuccess)
+                return M1_ERR_DEVICE;
+            m1::launch_b_step_init(E->st, E->dP, E->dS, dinit, (int)init.size());
+        }
+        for (int c = 0; c < cycles; ++c) b_vcycle(*E);
+        const int np = (int)E->running.size();
+        m1::launch_b_gather_ctrl(E->st, E->dP, np, E->dCtrl);
+        if (hipMemcpyAsync(E->hCtrl, E->dCtrl, sizeof(m1::Ctrl) * np, hipMemcpyDeviceToHost, E->st) != hipSuccess ||
+            hipStreamSynchronize(E->st) != hipSuccess || hipGetLastError() != hipSuccess)
+            return M1_ERR_DEVICE;
+        std::vector<m1_req*> keep;
+        for (int i = 0; i < np; ++i) {
+            m1_req* R = E->running[i];
+            const m1::Ctrl& h = E->hCtrl[i];
+            if (h.active) {
+                keep.push_back(R);
+                continue;
+            }
+            R->cycles += std::max(h.cycles, 0);
+            R->rel = h.rel;
+            R->r0 = h.r0;
+            R->dtau = h.dtau;
+            if (!h.conv) {
+                finish(*E, R, M1_ERR_NO_CONVERGENCE);
+                continue;
+            }
+            R->steps_done += 1;
+            if (R->steps_done >= R->nsteps) {
+                finish(*E, R, M1_OK);
+            } else {
+                R->need_init = true;
+                keep.push_back(R);
+            }
+        }
+        if (keep.size() != E->running.size()) E->dirty = true;
+        E->running.swap(keep);
+    }
+    std::lock_guard<std::mutex> g(E->qmu);
+    if (n_running) *n_running = (int32_t)E->running.size();
+    if (n_pending) *n_pending = (int32_t)E->pending.size();
+    return M1_OK;
+}
+
+m1_status m1_batch_poll(m1_engine* E, uint64_t ticket, m1_info* info)
+{
+    if (!E) return M1_ERR_ARG;
+    std::lock_guard<std::mutex> lk(E->qmu);
+    auto it = E->reqs.find(ticket);
+    if (it == E->reqs.end()) return M1_ERR_ARG;
+    const m1_req* R = it->second;
+    if (info) {
+        std::memset(info, 0, sizeof(*info));
+        info->cycles = R->cycles;
+        info->status = R->status;
+        info->levels = R->plan ? R->plan->L : 0;
+        info->steps_done = R->steps_done;
+        info->r0 = R->r0;
+        info->rel_residual = R->rel;
+        info->dtau = R->dtau;
+        info->first_bad_cell = -1;
+    }
+    return R->state == REQ_DONE ? M1_OK : M1_ERR_BUSY;
+}
+
+m1_status m1_batch_wait(m1_engine* E, uint64_t ticket, m1_info* info)
+{
+    if (!E) return M1_ERR_ARG;
+    for (;;) {
+        m1_status s = m1_batch_poll(E, ticket, info);
+        if (s != M1_ERR_BUSY) return s == M1_OK ? (m1_status)info->status : s;
+        s = m1_batch_run(E, 4, nullptr, nullptr);
+        if (s != M1_OK) return s;
+    }
+}
+
+m1_status m1_batch_cancel(m1_engine* E, uint64_t ticket)
+{
+    if (!E) return M1_ERR_ARG;
+    std::lock_guard<std::mutex> lk(E->qmu);
+    auto it = E->reqs.find(ticket);
+    if (it == E->reqs.end()) return M1_ERR_ARG;
+    it->second->cancel = true;
+    return M1_OK;
+}
+
+m1_status m1_batch_times(m1_engine* E, uint64_t ticket, double* t_submit, double* t_admit, double* t_done)
+{
+    if (!E) return M1_ERR_ARG;
+    std::lock_guard<std::mutex> lk(E->qmu);
+    auto it = E->reqs.find(ticket);
+    if (it == E->reqs.end()) return M1_ERR_ARG;
+    if (t_submit) *t_submit = it->second->t_submit;
+    if (t_admit) *t_admit = it->second->t_admit;
+    if (t_done) *t_done = it->second->t_done;
+    return M1_OK;
+}
+
+m1_status m1_batch_release(m1_engine* E, uint64_t ticket)
+{
+    if (!E) return M1_ERR_ARG;
+    std::lock_guard<std::mutex> lk(E->qmu);
+    auto it = E->reqs.find(ticket);
+    if (it == E->reqs.end() || it->second->state != REQ_DONE) return M1_ERR_ARG;
+    delete it->second;
+    E->reqs.erase(it);
+    return M1_OK;
+}
+
+}  // extern "C"

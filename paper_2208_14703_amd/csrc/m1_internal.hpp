@@ -77,7 +77,45 @@ struct TailArgs32 {
     TailLevel32 lev[kMaxLevels];
 };
 
+// ---- batched execution (many independent problems, one launch per level op) ----
+// Work-list entries pack (problem << kTileBits) | tile; a tile is 256 cells of
+// one level of one problem.
+constexpr int kTileBits = 20;
+
+// One (problem, level) of a batch: device pointers of that level's buffers.
+struct BSlot {
+    Lvl L;
+    Soa v, u, u2, f, rb;  // level >= 1
+    Soa b, x0, x1, rf;    // level 0: rhs, the two iterate buffers (x0 = the request's state), residual
+};
+
+// Per-problem data of a batch.
+struct BProb {
+    Phys ph;
+    int px, py, L, lt, local, pseudo_steps, npart, pad_;
+    double eta, reach, omega;
+    Ctrl* ctrl;
+    double* partials;
+    const TailArgs* tail;
+    Ctrl proto;  // solver tolerances of this problem, copied into ctrl at every step start
+};
+
 // mixed precision (m1_mixed.hip)
+// batched FP64 kernels (m1_kernels.hip); `wl` is a work list of nwl entries,
+// `plist` a list of problem indices
+void launch_b_relax(hipStream_t st, const BProb* P, const BSlot* S, const uint32_t* wl, int nwl, int in_x1, int norm);
+void launch_b_norm_control(hipStream_t st, const BProb* P, const int* plist, int np);
+void launch_b_apply(hipStream_t st, const BProb* P, const BSlot* S, const uint32_t* wl, int nwl, int level, int in_sel);
+void launch_b_restrict(hipStream_t st, const BProb* P, const BSlot* S, const uint32_t* wl, int nwl, int level,
+                       int in_sel);
+void launch_b_pseudo(hipStream_t st, const BProb* P, const BSlot* S, const uint32_t* wl, int nwl, int level,
+                     int in_sel, int out_sel, int first);
+void launch_b_prolong(hipStream_t st, const BProb* P, const BSlot* S, const uint32_t* wl, int nwl, int level,
+                      int in_sel, int out_sel);
+void launch_b_tail(hipStream_t st, const BProb* P, const int* plist, int np);
+void launch_b_step_init(hipStream_t st, const BProb* P, const BSlot* S, const int* plist, int np);
+void launch_b_gather_ctrl(hipStream_t st, const BProb* P, int np, Ctrl* out);
+
 void launch_mx_resid(hipStream_t st, int dim, const Phys& ph, const Lvl& L, double eta, CSoa v, CSoa32 d, CSoa b,
                      Soa vnew, Soa32 base, Soa32 r32, double* partials, const int* active);
 void launch_mx_sweep(hipStream_t st, int dim, const Phys& ph, const Lvl32& L, CSoa32 w, CSoa32 d, CSoa32 rhs,

@@ -11,7 +11,10 @@
 // Cycle kernels take an optional device flag `active` (skip all work when it
 // is 0) and an optional device pseudo-time step `dtau_dev`, so that whole
 // V-cycles can be enqueued ahead of the host's convergence check.
-#include "m1_internal.hpp"
+#include <algorithm>
+#include <cfloat>
+
+#include "m1_cells.hpp"
 
 namespace m1 {
 
@@ -22,290 +25,6 @@ static inline unsigned nblocks(int64_t n) { return (unsigned)((n + kBlock - 1) /
 
 __device__ __forceinline__ bool inactive(const int* active) { return active && *active == 0; }
 
-__device__ __forceinline__ void ij_of(int nx, int64_t k, int& i, int& j)
-{
-    j = (int)(k / nx);
-    i = (int)(k - (int64_t)j * nx);
-}
-
-// ===========================================================================
-// Per-cell bodies
-// ===========================================================================
-
-// Jacobi sweep of (beta M + gamma A)(u) = rhs, M = diag(1,1,1,C_v):
-//   out = u + omega (local_solve(rhs + gamma S(u)) - u);  gcell: per-cell gamma.
-// With NORM (only for the finest-level sweep, beta = 0, gamma = 1) the cell's
-// share of |b - A(u)|^2 of the INPUT u is returned: b - A(u) = B - D(u), where
-// B = b + S(u) is formed for the update anyway.
-template <int DIM, bool NORM = false>
-__device__ __forceinline__ double relax_cell(const Phys& ph, const Lvl& L, const CSoa& rhs, const double* gcell,
-                                             double beta, double gamma, double omega, const CSoa& u, const Soa& out,
-                                             int64_t k, int i, int j)
-{
-    double S0, S1, S2;
-    offdiag<DIM>(ph, L, u, i, j, k, S0, S1, S2);
-    const double g = gcell ? gcell[k] : gamma;
-    const double BE = fma(g, S0, rhs.E[k]);
-    const double BFx = fma(g, S1, rhs.Fx[k]);
-    const double BFy = (DIM == 2) ? fma(g, S2, rhs.Fy[k]) : 0.0;
-    const double BT = rhs.T[k];
-    const double ka = L.cdt * L.sa[k], ks = L.cdt * L.ss[k];
-    const double Tin = u.T[k];
-    double q = 0.0;
-    if (NORM) {
-        const double Ein = u.E[k], Fxin = u.Fx[k], Fyin = (DIM == 2) ? u.Fy[k] : 0.0;
-        const double T2 = Tin * Tin;
-        const double ex = ka * fma(-ph.a_r * T2, T2, Ein);  // ka (E - a_r T^4)
-        const double dF = L.a + ka + ks;
-        const double rE = BE - fma(L.a, Ein, ex);
-        const double ic = 1.0 / ph.c;
-        const double rFx = (BFx - dF * Fxin) * ic, rFy = (BFy - dF * Fyin) * ic;
-        const double rT = BT - fma(ph.c_v, Tin, -ex);
-        q = fma(rE, rE, fma(rFx, rFx, fma(rFy, rFy, rT * rT)));
-    }
-    double E, Fx, Fy, T;
-    local_solve(beta, g, L.a, ka, ks, ph.c_v, ph.a_r, BE, BFx, BFy, BT, Tin, E, Fx, Fy, T);
-    if (omega != 1.0) {
-        const double Ein = u.E[k], Fxin = u.Fx[k];
-        E = fma(omega, E - Ein, Ein);
-        Fx = fma(omega, Fx - Fxin, Fxin);
-        if (DIM == 2) {
-            const double Fyin = u.Fy[k];
-            Fy = fma(omega, Fy - Fyin, Fyin);
-        }
-        T = fma(omega, T - Tin, Tin);
-    }
-    out.E[k] = E;
-    out.Fx[k] = Fx;
-    if (DIM == 2) out.Fy[k] = Fy;
-    out.T[k] = T;
-    return q;
-}
-
-// One pseudo-time step (Algorithm 3) of M du/dtau + A(u) = f, fused:
-//   s = M^{-1} f;  tau_i = min(dtau, tau*(u, s) (1 - (1-eta)^K)) -- the pseudo
-//   time reached by K explicit sub-steps, each eta of the remaining admissible
-//   ray;  u~ = u + tau_i s;  one Jacobi sweep of (M + g A)(u) = M u~ from u,
-//   with g = tau_i (local) or dtau.  rs/gs (nullable) keep M u~ and g for
-//   further sweeps.  With FIRST (the first step of the pre-smoothing, u = v_l)
-//   f holds the restricted residual on entry and the FAS right-hand side
-//   f = A(v_l) + R(rbar) is formed here and written back (A(v) = D(v) - S(v),
-//   S(v) being needed for the sweep anyway).
-template <int DIM, bool FIRST = false>
-__device__ __forceinline__ void pseudo_cell(const Phys& ph, const Lvl& L, const CSoa& fin, const Soa& fout,
-                                            const CSoa& u, const Soa& out, double dtau, double reach, int local,
-                                            const Soa& rs, double* gs, int64_t k, int i, int j)
-{
-    const double uE = u.E[k], uFx = u.Fx[k], uFy = (DIM == 2) ? u.Fy[k] : 0.0, uT = u.T[k];
-    double S0, S1, S2;
-    offdiag<DIM>(ph, L, u, i, j, k, S0, S1, S2);
-    const double ka = L.cdt * L.sa[k], ks = L.cdt * L.ss[k];
-    double fE = fin.E[k], fFx = fin.Fx[k], fFy = (DIM == 2) ? fin.Fy[k] : 0.0, fT = fin.T[k];
-    if (FIRST) {
-        const double T2 = uT * uT;
-        const double ex = ka * fma(-ph.a_r * T2, T2, uE);
-        const double dF = L.a + ka + ks;
-        fE += fma(L.a, uE, ex) - S0;
-        fFx += fma(dF, uFx, -S1);
-        fFy += fma(dF, uFy, -S2);
-        fT += fma(ph.c_v, uT, -ex);
-        fout.E[k] = fE;
-        fout.Fx[k] = fFx;
-        if (DIM == 2) fout.Fy[k] = fFy;
-        fout.T[k] = fT;
-    }
-    const double sE = fE, sFx = fFx, sFy = fFy, sT = fT / ph.c_v;
-    const double ts = ray_len(ph.c2, uE, uFx, uFy, uT, sE, sFx, sFy, sT);
-    const double tau = fmin(dtau, ts * reach);
-    const double tE = fma(tau, sE, uE), tFx = fma(tau, sFx, uFx), tFy = fma(tau, sFy, uFy);
-    const double tT = ph.c_v * fma(tau, sT, uT);
-    const double g = local ? tau : dtau;
-    double E, Fx, Fy, T;
-    local_solve(1.0, g, L.a, ka, ks, ph.c_v, ph.a_r, fma(g, S0, tE), fma(g, S1, tFx), fma(g, S2, tFy), tT, uT, E, Fx,
-                Fy, T);
-    out.E[k] = E;
-    out.Fx[k] = Fx;
-    if (DIM == 2) out.Fy[k] = Fy;
-    out.T[k] = T;
-    if (gs) {
-        rs.E[k] = tE;
-        rs.Fx[k] = tFx;
-        if (DIM == 2) rs.Fy[k] = tFy;
-        rs.T[k] = tT;
-        gs[k] = g;
-    }
-}
-
-// out = X + sgn A(v) (X.E == nullptr: out = sgn A(v)); out stored when out.E
-// is set.  Returns r_E^2 + (r_F/c)^2 + r_T^2 of the result (norm contribution).
-template <int DIM>
-__device__ __forceinline__ double apply_cell(const Phys& ph, const Lvl& L, const CSoa& v, const CSoa& X, double sgn,
-                                             const Soa& out, int64_t k, int i, int j)
-{
-    double S0, S1, S2;
-    offdiag<DIM>(ph, L, v, i, j, k, S0, S1, S2);
-    const double E = v.E[k], Fx = v.Fx[k], Fy = (DIM == 2) ? v.Fy[k] : 0.0, T = v.T[k];
-    const double ka = L.cdt * L.sa[k], ks = L.cdt * L.ss[k];
-    const double T2 = T * T;
-    const double ex = ka * fma(-ph.a_r * T2, T2, E);  // ka (E - a_r T^4)
-    const double dF = L.a + ka + ks;
-    double rE = sgn * (fma(L.a, E, ex) - S0);
-    double rFx = sgn * fma(dF, Fx, -S1);
-    double rFy = sgn * fma(dF, Fy, -S2);
-    double rT = sgn * fma(ph.c_v, T, -ex);
-    if (X.E) {
-        rE += X.E[k];
-        rFx += X.Fx[k];
-        if (DIM == 2) rFy += X.Fy[k];
-        rT += X.T[k];
-    }
-    if (out.E) {
-        out.E[k] = rE;
-        out.Fx[k] = rFx;
-        if (DIM == 2) out.Fy[k] = rFy;
-        out.T[k] = rT;
-    }
-    const double ic = 1.0 / ph.c;
-    const double fx = rFx * ic, fy = (DIM == 2) ? rFy * ic : 0.0;
-    return fma(rE, rE, fma(fx, fx, fma(fy, fy, rT * rT)));
-}
-
-// Full-weighting weights along one axis (1/4, 1/2, 1/4 on fine 2I-1, 2I, 2I+1):
-// periodic axes wrap, otherwise outside points get weight 0 (index clamped to a
-// valid cell) and the others are renormalised to sum 1.  Always 3 entries so
-// that every load is issued unconditionally.
-__device__ __forceinline__ void rweights(int I, int nf, bool periodic, int idx[3], double w[3])
-{
-    double sum = 0.0;
-#pragma unroll
-    for (int m = 0; m < 3; ++m) {
-        const double base = (m == 1) ? 0.5 : 0.25;
-        int f = 2 * I - 1 + m;
-        double wm = base;
-        if (f < 0 || f >= nf) {
-            if (periodic) {
-                f = f < 0 ? f + nf : f - nf;
-            } else {
-                f = f < 0 ? 0 : nf - 1;
-                wm = 0.0;
-            }
-        }
-        idx[m] = f;
-        w[m] = wm;
-        sum += wm;
-    }
-    if (sum != 1.0) {
-#pragma unroll
-        for (int m = 0; m < 3; ++m) w[m] /= sum;
-    }
-}
-
-// Restriction of NF fields for coarse cell k.  All 3x3 x NF values are
-// gathered first (32-bit offsets from the per-field bases) so that every load
-// is in flight before the first use, then summed.
-template <int DIM, int NF>
-__device__ __forceinline__ void restrict_cell(int nxf, int nyf, int px, int py, const double* const* in,
-                                              double* const* out, int64_t k)
-{
-    const int nxc = nxf / 2;
-    int I, J;
-    ij_of(nxc, k, I, J);
-    int ix[3], iy[3] = {0, 0, 0};
-    double wx[3], wy[3] = {1.0, 0.0, 0.0};
-    rweights(I, nxf, px != 0, ix, wx);
-    if (DIM == 2) rweights(J, nyf, py != 0, iy, wy);
-    constexpr int NB = (DIM == 2) ? 3 : 1;
-    uint32_t off[NB * 3];
-#pragma unroll
-    for (int b = 0; b < NB; ++b)
-#pragma unroll
-        for (int a = 0; a < 3; ++a) off[b * 3 + a] = (uint32_t)iy[b] * (uint32_t)nxf + (uint32_t)ix[a];
-    double val[NF][NB * 3];
-#pragma unroll
-    for (int q = 0; q < NF; ++q)
-#pragma unroll
-        for (int m = 0; m < NB * 3; ++m) val[q][m] = in[q][off[m]];
-#pragma unroll
-    for (int q = 0; q < NF; ++q) {
-        double s = 0.0;
-#pragma unroll
-        for (int b = 0; b < NB; ++b) {
-            const double t = fma(wx[2], val[q][b * 3 + 2], fma(wx[1], val[q][b * 3 + 1], wx[0] * val[q][b * 3]));
-            s = fma(wy[b], t, s);
-        }
-        out[q][k] = s;
-    }
-}
-
-// Linear prolongation weights along one axis: fine 2I <- coarse I; odd fine
-// cells average coarse I and I+1 (periodic wrap, else the missing one gets
-// weight 0 and the other 1).  Always 2 entries.
-__device__ __forceinline__ void pweights(int i, int nc, bool periodic, int idx[2], double w[2])
-{
-    const int I0 = i >> 1;
-    idx[0] = I0;
-    if ((i & 1) == 0) {
-        idx[1] = I0;
-        w[0] = 1.0;
-        w[1] = 0.0;
-        return;
-    }
-    int I1 = I0 + 1;
-    if (I1 >= nc) {
-        if (!periodic) {
-            idx[1] = I0;
-            w[0] = 1.0;
-            w[1] = 0.0;
-            return;
-        }
-        I1 -= nc;
-    }
-    idx[1] = I1;
-    w[0] = 0.5;
-    w[1] = 0.5;
-}
-
-// Correction with admissibility (eq. prolongatedSol):
-//   w = u + P(uc - vc); out = w if admissible, else u + eta min(tau*(u, w - u), 1) (w - u).
-template <int DIM>
-__device__ __forceinline__ void prolong_cell(const Phys& ph, int nx, int ny, int px, int py, double eta, const CSoa& u,
-                                             const CSoa& uc, const CSoa& vc, const Soa& out, int64_t k)
-{
-    int i, j;
-    ij_of(nx, k, i, j);
-    const int nxc = nx / 2, nyc = (DIM == 2) ? ny / 2 : 1;
-    int ix[2], iy[2] = {0, 0};
-    double wx[2], wy[2] = {1.0, 0.0};
-    pweights(i, nxc, px != 0, ix, wx);
-    if (DIM == 2) pweights(j, nyc, py != 0, iy, wy);
-    constexpr int NB = (DIM == 2) ? 2 : 1;
-    double e0 = 0.0, e1 = 0.0, e2 = 0.0, e3 = 0.0;
-#pragma unroll
-    for (int b = 0; b < NB; ++b) {
-#pragma unroll
-        for (int a = 0; a < 2; ++a) {
-            const int64_t kc = (int64_t)iy[b] * nxc + ix[a];
-            const double w = wx[a] * wy[b];
-            e0 = fma(w, uc.E[kc] - vc.E[kc], e0);
-            e1 = fma(w, uc.Fx[kc] - vc.Fx[kc], e1);
-            if (DIM == 2) e2 = fma(w, uc.Fy[kc] - vc.Fy[kc], e2);
-            e3 = fma(w, uc.T[kc] - vc.T[kc], e3);
-        }
-    }
-    const double uE = u.E[k], uFx = u.Fx[k], uFy = (DIM == 2) ? u.Fy[k] : 0.0, uT = u.T[k];
-    double wE = uE + e0, wFx = uFx + e1, wFy = uFy + e2, wT = uT + e3;
-    if (!admissible(ph.c2, wE, wFx, wFy, wT)) {
-        const double th = eta * fmin(ray_len(ph.c2, uE, uFx, uFy, uT, e0, e1, e2, e3), 1.0);
-        wE = fma(th, e0, uE);
-        wFx = fma(th, e1, uFx);
-        wFy = fma(th, e2, uFy);
-        wT = fma(th, e3, uT);
-    }
-    out.E[k] = wE;
-    out.Fx[k] = wFx;
-    if (DIM == 2) out.Fy[k] = wFy;
-    out.T[k] = wT;
-}
 
 // ===========================================================================
 // Grid kernels
@@ -316,17 +35,6 @@ __device__ __forceinline__ bool cell_of(const Lvl& L, int64_t& k, int& i, int& j
     if (k >= (int64_t)L.nx * L.ny) return false;
     ij_of(L.nx, k, i, j);
     return true;
-}
-
-// Fixed-order block reduction (wave64 butterfly, then the waves in order) of q
-// into partials[block].
-__device__ __forceinline__ void block_partial(double q, double* partials, int64_t block)
-{
-    __shared__ double red[kBlock / 64];
-    for (int off = 32; off > 0; off >>= 1) q += __shfl_xor(q, off, 64);
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = q;
-    __syncthreads();
-    if (threadIdx.x == 0) partials[block] = (red[0] + red[1]) + (red[2] + red[3]);
 }
 
 // Jacobi sweep; with partials != nullptr it also writes the block partials of
@@ -346,7 +54,7 @@ __global__ __launch_bounds__(kBlock) void k_relax(Phys ph, Lvl L, CSoa rhs, cons
     }
     double q = 0.0;
     if (in) q = relax_cell<DIM, true>(ph, L, rhs, gcell, beta, gamma, omega, u, out, k, i, j);
-    block_partial(q, partials, xcd_block());
+    block_partial(q, partials + xcd_block());
 }
 
 // One pseudo-time step; `first`: also form the FAS right-hand side in f (u = v_l).
@@ -374,21 +82,7 @@ __global__ __launch_bounds__(kBlock) void k_apply(Phys ph, Lvl L, CSoa v, CSoa X
     int i, j;
     double q = 0.0;
     if (cell_of(L, k, i, j)) q = apply_cell<DIM>(ph, L, v, X, sgn, out, k, i, j);
-    if (partials) block_partial(q, partials, xcd_block());
-}
-
-// Sum of the partials in a fixed order by one block.
-__device__ __forceinline__ double block_sum(const double* __restrict__ partials, int n)
-{
-    __shared__ double red[16];
-    double s = 0.0;
-    for (int m = threadIdx.x; m < n; m += blockDim.x) s += partials[m];
-    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
-    __syncthreads();
-    double t = 0.0;
-    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t += red[w];
-    return t;
+    if (partials) block_partial(q, partials + xcd_block());
 }
 
 __global__ __launch_bounds__(1024) void k_norm_finalize(const double* __restrict__ partials, int n,
@@ -404,33 +98,7 @@ __global__ __launch_bounds__(1024) void k_norm_control(const double* __restrict_
 {
     if (ctrl->active == 0) return;
     const double r = sqrt(block_sum(partials, n));
-    if (threadIdx.x != 0) return;
-    if (ctrl->cycles < 0) {  // first call of a time step: the residual of v^n itself, no adaptation
-        ctrl->cycles = 0;
-        ctrl->r0 = r;
-        ctrl->rprev = r;
-        ctrl->rel = 1.0;
-        if (r <= ctrl->floor_r) {
-            ctrl->conv = 1;
-            ctrl->active = 0;
-        }
-        return;
-    }
-    ctrl->cycles += 1;
-    const double rel = r / ctrl->r0;
-    ctrl->rel = rel;
-    const double d = ctrl->literal ? fabs(r - ctrl->rprev) / ctrl->r0 : (ctrl->rprev - r) / ctrl->rprev;
-    double dt = ctrl->dtau;
-    if (d > ctrl->eps_inc) dt *= 1.1;
-    if (d < ctrl->eps_dec) dt *= 0.5;
-    ctrl->dtau = fmin(fmax(dt, ctrl->dtau_min), ctrl->dtau_max);
-    ctrl->rprev = r;
-    if (rel <= ctrl->rtol || r <= ctrl->floor_r) {
-        ctrl->conv = 1;
-        ctrl->active = 0;
-    } else if (!isfinite(rel) || ctrl->cycles >= ctrl->max_cycles) {
-        ctrl->active = 0;
-    }
+    if (threadIdx.x == 0) ctrl_update(ctrl, r);
 }
 
 template <int DIM, int NF>
@@ -455,101 +123,13 @@ __global__ __launch_bounds__(kBlock) void k_prolong_project(Phys ph, int nx, int
     prolong_cell<DIM>(ph, nx, ny, px, py, eta, u, uc, vc, out, k);
 }
 
-// ---------------------------------------------------------------------------
-// Bottom of the V-cycle in one workgroup: levels lt..L-1 (all small), entered
-// with v_lt = R(u_{lt-1}) and f_lt = R(rbar_{lt-1}) already in place; leaves
-// the smoothed, corrected u_lt in lev[lt].u.  Same per-cell bodies and the same
-// order of operations as the grid path, with __syncthreads between phases.
-template <int DIM>
-__device__ __forceinline__ Soa tail_pseudo(const TailArgs& A, const TailLevel& T, double dtau, Soa in, bool first)
-{
-    const int64_t n = (int64_t)T.L.nx * T.L.ny;
-    for (int m = 0; m < A.pseudo_steps; ++m) {
-        const Soa out = (in.E == T.u.E) ? T.u2 : T.u;
-        for (int64_t k = threadIdx.x; k < n; k += blockDim.x) {
-            int i, j;
-            ij_of(T.L.nx, k, i, j);
-            if (first && m == 0)
-                pseudo_cell<DIM, true>(A.ph, T.L, cs(T.f), T.f, cs(in), out, dtau, A.reach, A.local, Soa{}, nullptr,
-                                       k, i, j);
-            else
-                pseudo_cell<DIM, false>(A.ph, T.L, cs(T.f), T.f, cs(in), out, dtau, A.reach, A.local, Soa{},
-                                        nullptr, k, i, j);
-        }
-        __syncthreads();
-        in = out;
-    }
-    return in;
-}
-
 template <int DIM>
 __global__ __launch_bounds__(kTailThreads) void k_tail(const TailArgs* __restrict__ Ap, double dtau,
                                                        const double* __restrict__ dtau_dev,
                                                        const int* __restrict__ active)
 {
     if (inactive(active)) return;
-    const TailArgs& A = *Ap;
-    const double dt = dtau_dev ? *dtau_dev : dtau;
-    unsigned in_u2 = 0;  // bit l set: the current iterate of level l is in u2 (else u)
-    auto cur = [&](int l) { return ((in_u2 >> l) & 1u) ? A.lev[l].u2 : A.lev[l].u; };
-    auto set = [&](int l, const Soa& s) {
-        if (s.E == A.lev[l].u2.E) in_u2 |= 1u << l;
-        else in_u2 &= ~(1u << l);
-    };
-    for (int l = A.lt; l < A.L; ++l) {
-        const TailLevel& T = A.lev[l];
-        const int64_t n = (int64_t)T.L.nx * T.L.ny;
-        if (l > A.lt) {
-            const TailLevel& F = A.lev[l - 1];
-            const Soa uf = cur(l - 1);
-            const double* in[8] = {uf.E, uf.Fx, uf.Fy, uf.T, F.rb.E, F.rb.Fx, F.rb.Fy, F.rb.T};
-            double* out[8] = {T.v.E, T.v.Fx, T.v.Fy, T.v.T, T.f.E, T.f.Fx, T.f.Fy, T.f.T};
-            if (DIM == 1) {  // no Fy planes: (E, Fx, T) of u then of rbar
-                in[2] = in[3];
-                in[3] = in[4];
-                in[4] = in[5];
-                in[5] = in[7];
-                out[2] = out[3];
-                out[3] = out[4];
-                out[4] = out[5];
-                out[5] = out[7];
-            }
-            for (int64_t k = threadIdx.x; k < n; k += blockDim.x)
-                restrict_cell<DIM, DIM == 2 ? 8 : 6>(F.L.nx, F.L.ny, A.px, A.py, in, out, k);
-            __syncthreads();
-        }
-        set(l, tail_pseudo<DIM>(A, T, dt, T.v, true));  // forms f = A(v) + R(rbar) on the way
-        if (l < A.L - 1) {
-            const Soa u = cur(l);
-            for (int64_t k = threadIdx.x; k < n; k += blockDim.x) {  // rbar = f - A(u)
-                int i, j;
-                ij_of(T.L.nx, k, i, j);
-                apply_cell<DIM>(A.ph, T.L, cs(u), cs(T.f), -1.0, T.rb, k, i, j);
-            }
-            __syncthreads();
-        }
-    }
-    for (int l = A.L - 2; l >= A.lt; --l) {
-        const TailLevel& T = A.lev[l];
-        const TailLevel& C = A.lev[l + 1];
-        const int64_t n = (int64_t)T.L.nx * T.L.ny;
-        const Soa u = cur(l), uc = cur(l + 1);
-        for (int64_t k = threadIdx.x; k < n; k += blockDim.x)
-            prolong_cell<DIM>(A.ph, T.L.nx, T.L.ny, A.px, A.py, A.eta, cs(u), cs(uc), cs(C.v), u, k);
-        __syncthreads();
-        set(l, tail_pseudo<DIM>(A, T, dt, u, false));
-    }
-    const TailLevel& T = A.lev[A.lt];
-    const Soa res = cur(A.lt);
-    if (res.E != T.u.E) {
-        const int64_t n = (int64_t)T.L.nx * T.L.ny;
-        for (int64_t k = threadIdx.x; k < n; k += blockDim.x) {
-            T.u.E[k] = res.E[k];
-            T.u.Fx[k] = res.Fx[k];
-            if (DIM == 2) T.u.Fy[k] = res.Fy[k];
-            T.u.T[k] = res.T[k];
-        }
-    }
+    tail_body<DIM>(*Ap, dtau_dev ? *dtau_dev : dtau);
 }
 
 // ---------------------------------------------------------------------------
@@ -601,6 +181,170 @@ __global__ __launch_bounds__(kBlock) void k_check_sigma(int64_t n, const double*
 __global__ void k_ctrl_init(Ctrl* ctrl, Ctrl init) { *ctrl = init; }
 
 // ===========================================================================
+// Batched kernels: persistent grid-stride loops over a work list of
+// (problem, tile) entries; every problem carries its own level data, cycle
+// control (dtau, stop flag) and norm partials.  Buffer selectors are the same
+// for all problems (all run the same sequence of operations):
+//   level 0: in_x1 picks x1 (else x0) as the current iterate;
+//   level >= 1: sel 0 = v, 1 = u, 2 = u2.
+__device__ __forceinline__ const Soa& pick(const BSlot& s, int sel) { return sel == 0 ? s.v : (sel == 1 ? s.u : s.u2); }
+
+#define B_LOOP(wl, nwl)                                                     \
+    for (int w = blockIdx.x; w < (nwl); w += gridDim.x) {                   \
+        const uint32_t item = (wl)[w];                                      \
+        const int p = (int)(item >> kTileBits);                             \
+        const int64_t tile = (int64_t)(item & ((1u << kTileBits) - 1u));    \
+        const BProb& pb = P[p];                                             \
+        if (pb.ctrl->active == 0) continue;                                 \
+        const int64_t k = tile * kBlock + threadIdx.x;
+
+__global__ __launch_bounds__(kBlock) void kb_relax(const BProb* __restrict__ P, const BSlot* __restrict__ S,
+                                                   const uint32_t* __restrict__ wl, int nwl, int in_x1, int norm)
+{
+    B_LOOP(wl, nwl)
+    const BSlot& s = S[p * kMaxLevels];
+    const Soa& in = in_x1 ? s.x1 : s.x0;
+    const Soa& out = in_x1 ? s.x0 : s.x1;
+    const bool inside = k < (int64_t)s.L.nx * s.L.ny;
+    int i = 0, j = 0;
+    if (inside) ij_of(s.L.nx, k, i, j);
+    if (!norm) {
+        if (inside) relax_cell<2>(pb.ph, s.L, cs(s.b), nullptr, 0.0, 1.0, pb.omega, cs(in), out, k, i, j);
+        continue;
+    }
+    double q = 0.0;
+    if (inside) q = relax_cell<2, true>(pb.ph, s.L, cs(s.b), nullptr, 0.0, 1.0, pb.omega, cs(in), out, k, i, j);
+    block_partial(q, pb.partials + tile);
+    }
+}
+
+// One block per problem: finish its residual norm and update its cycle control.
+__global__ __launch_bounds__(1024) void kb_norm_control(const BProb* __restrict__ P, const int* __restrict__ plist)
+{
+    const BProb& pb = P[plist[blockIdx.x]];
+    if (pb.ctrl->active == 0) return;
+    const double r = sqrt(block_sum(pb.partials, pb.npart));
+    if (threadIdx.x == 0) ctrl_update(pb.ctrl, r);
+}
+
+// level 0: rf = b - A(x_cur);  level >= 1: rb = f - A(pick(in_sel)).
+__global__ __launch_bounds__(kBlock) void kb_apply(const BProb* __restrict__ P, const BSlot* __restrict__ S,
+                                                   const uint32_t* __restrict__ wl, int nwl, int level, int in_sel)
+{
+    B_LOOP(wl, nwl)
+    const BSlot& s = S[p * kMaxLevels + level];
+    if (k >= (int64_t)s.L.nx * s.L.ny) continue;
+    int i, j;
+    ij_of(s.L.nx, k, i, j);
+    if (level == 0) apply_cell<2>(pb.ph, s.L, cs(in_sel ? s.x1 : s.x0), cs(s.b), -1.0, s.rf, k, i, j);
+    else apply_cell<2>(pb.ph, s.L, cs(pick(s, in_sel)), cs(s.f), -1.0, s.rb, k, i, j);
+    }
+}
+
+// Restriction into `level` of the current iterate and residual of level-1.
+__global__ __launch_bounds__(kBlock) void kb_restrict(const BProb* __restrict__ P, const BSlot* __restrict__ S,
+                                                      const uint32_t* __restrict__ wl, int nwl, int level, int in_sel)
+{
+    B_LOOP(wl, nwl)
+    const BSlot& c = S[p * kMaxLevels + level];
+    const BSlot& f = S[p * kMaxLevels + level - 1];
+    if (k >= (int64_t)c.L.nx * c.L.ny) continue;
+    const Soa& u = (level == 1) ? (in_sel ? f.x1 : f.x0) : pick(f, in_sel);
+    const Soa& r = (level == 1) ? f.rf : f.rb;
+    const double* in[8] = {u.E, u.Fx, u.Fy, u.T, r.E, r.Fx, r.Fy, r.T};
+    double* out[8] = {c.v.E, c.v.Fx, c.v.Fy, c.v.T, c.f.E, c.f.Fx, c.f.Fy, c.f.T};
+    restrict_cell<2, 8>(f.L.nx, f.L.ny, pb.px, pb.py, in, out, k);
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void kb_pseudo(const BProb* __restrict__ P, const BSlot* __restrict__ S,
+                                                    const uint32_t* __restrict__ wl, int nwl, int level, int in_sel,
+                                                    int out_sel, int first)
+{
+    B_LOOP(wl, nwl)
+    const BSlot& s = S[p * kMaxLevels + level];
+    if (k >= (int64_t)s.L.nx * s.L.ny) continue;
+    int i, j;
+    ij_of(s.L.nx, k, i, j);
+    const double dt = pb.ctrl->dtau;
+    if (first)
+        pseudo_cell<2, true>(pb.ph, s.L, cs(s.f), s.f, cs(pick(s, in_sel)), pick(s, out_sel), dt, pb.reach, pb.local,
+                             Soa{}, nullptr, k, i, j);
+    else
+        pseudo_cell<2, false>(pb.ph, s.L, cs(s.f), s.f, cs(pick(s, in_sel)), pick(s, out_sel), dt, pb.reach,
+                              pb.local, Soa{}, nullptr, k, i, j);
+    }
+}
+
+// Correction of `level` from level+1.  Fine side: level 0 in place on x_cur
+// (in_sel = in_x1), else pick(in_sel) -> pick(out_sel).  Coarse side: the final
+// iterate of level+1, always in u (with an odd number of pseudo-time steps the
+// down leg, the up leg and the tail all end there).
+__global__ __launch_bounds__(kBlock) void kb_prolong(const BProb* __restrict__ P, const BSlot* __restrict__ S,
+                                                     const uint32_t* __restrict__ wl, int nwl, int level, int in_sel,
+                                                     int out_sel)
+{
+    B_LOOP(wl, nwl)
+    const BSlot& f = S[p * kMaxLevels + level];
+    const BSlot& c = S[p * kMaxLevels + level + 1];
+    if (k >= (int64_t)f.L.nx * f.L.ny) continue;
+    const Soa& u = (level == 0) ? (in_sel ? f.x1 : f.x0) : pick(f, in_sel);
+    const Soa& o = (level == 0) ? u : pick(f, out_sel);
+    prolong_cell<2>(pb.ph, f.L.nx, f.L.ny, pb.px, pb.py, pb.eta, cs(u), cs(c.u), cs(c.v), o, k);
+    }
+}
+
+// One workgroup per problem: the bottom of its cycle.
+__global__ __launch_bounds__(kTailThreads) void kb_tail(const BProb* __restrict__ P, const int* __restrict__ plist)
+{
+    const BProb& pb = P[plist[blockIdx.x]];
+    if (pb.ctrl->active == 0) return;
+    tail_body<2>(*pb.tail, pb.ctrl->dtau);
+}
+
+// One block per problem: start a time step from the state in x0 -- b = (E, F,
+// C_v T), |b| for the rounding floor, and a fresh cycle control.
+__global__ __launch_bounds__(1024) void kb_step_init(const BProb* __restrict__ P, const BSlot* __restrict__ S,
+                                                     const int* __restrict__ plist)
+{
+    const int p = plist[blockIdx.x];
+    const BProb& pb = P[p];
+    const BSlot& s = S[p * kMaxLevels];
+    const int64_t n = (int64_t)s.L.nx * s.L.ny;
+    const double ic = 1.0 / pb.ph.c;
+    double q = 0.0;
+    for (int64_t k = threadIdx.x; k < n; k += blockDim.x) {
+        const double E = s.x0.E[k], Fx = s.x0.Fx[k], Fy = s.x0.Fy[k], T = pb.ph.c_v * s.x0.T[k];
+        s.b.E[k] = E;
+        s.b.Fx[k] = Fx;
+        s.b.Fy[k] = Fy;
+        s.b.T[k] = T;
+        q = fma(E, E, fma(Fx * ic, Fx * ic, fma(Fy * ic, Fy * ic, fma(T, T, q))));
+    }
+    // fixed-order block reduction of q (wave butterfly, then the 16 waves in order)
+    __shared__ double red[kTailThreads / 64];
+    for (int off = 32; off > 0; off >>= 1) q += __shfl_xor(q, off, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = q;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t += red[w];
+        Ctrl c = pb.proto;
+        c.floor_r = 16.0 * DBL_EPSILON * s.L.a * sqrt(t);
+        c.active = 1;
+        c.cycles = -1;
+        c.conv = 0;
+        *pb.ctrl = c;
+    }
+}
+
+__global__ void kb_gather_ctrl(const BProb* __restrict__ P, int np, Ctrl* __restrict__ out)
+{
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p < np) out[p] = *P[p].ctrl;
+}
+
+// ===========================================================================
 // Launchers
 // ===========================================================================
 #define M1_DISPATCH(DIM_, KERNEL, GRID, ...)                                                          \
@@ -629,6 +373,51 @@ void launch_apply(hipStream_t st, int dim, const Phys& ph, const Lvl& L, CSoa v,
                   double* partials, const int* active)
 {
     M1_DISPATCH(dim, k_apply, apply_blocks(L), ph, L, v, X, sgn, out, partials, active);
+}
+
+static unsigned bgrid(int nwl) { return (unsigned)std::max(1, std::min(nwl, 16384)); }
+
+void launch_b_relax(hipStream_t st, const BProb* P, const BSlot* S, const uint32_t* wl, int nwl, int in_x1, int norm)
+{
+    if (nwl > 0) hipLaunchKernelGGL(kb_relax, dim3(bgrid(nwl)), dim3(kBlock), 0, st, P, S, wl, nwl, in_x1, norm);
+}
+void launch_b_norm_control(hipStream_t st, const BProb* P, const int* plist, int np)
+{
+    if (np > 0) hipLaunchKernelGGL(kb_norm_control, dim3(np), dim3(1024), 0, st, P, plist);
+}
+void launch_b_apply(hipStream_t st, const BProb* P, const BSlot* S, const uint32_t* wl, int nwl, int level, int in_sel)
+{
+    if (nwl > 0) hipLaunchKernelGGL(kb_apply, dim3(bgrid(nwl)), dim3(kBlock), 0, st, P, S, wl, nwl, level, in_sel);
+}
+void launch_b_restrict(hipStream_t st, const BProb* P, const BSlot* S, const uint32_t* wl, int nwl, int level,
+                       int in_sel)
+{
+    if (nwl > 0) hipLaunchKernelGGL(kb_restrict, dim3(bgrid(nwl)), dim3(kBlock), 0, st, P, S, wl, nwl, level, in_sel);
+}
+void launch_b_pseudo(hipStream_t st, const BProb* P, const BSlot* S, const uint32_t* wl, int nwl, int level,
+                     int in_sel, int out_sel, int first)
+{
+    if (nwl > 0)
+        hipLaunchKernelGGL(kb_pseudo, dim3(bgrid(nwl)), dim3(kBlock), 0, st, P, S, wl, nwl, level, in_sel, out_sel,
+                           first);
+}
+void launch_b_prolong(hipStream_t st, const BProb* P, const BSlot* S, const uint32_t* wl, int nwl, int level,
+                      int in_sel, int out_sel)
+{
+    if (nwl > 0)
+        hipLaunchKernelGGL(kb_prolong, dim3(bgrid(nwl)), dim3(kBlock), 0, st, P, S, wl, nwl, level, in_sel, out_sel);
+}
+void launch_b_tail(hipStream_t st, const BProb* P, const int* plist, int np)
+{
+    if (np > 0) hipLaunchKernelGGL(kb_tail, dim3(np), dim3(kTailThreads), 0, st, P, plist);
+}
+void launch_b_step_init(hipStream_t st, const BProb* P, const BSlot* S, const int* plist, int np)
+{
+    if (np > 0) hipLaunchKernelGGL(kb_step_init, dim3(np), dim3(kTailThreads), 0, st, P, S, plist);
+}
+void launch_b_gather_ctrl(hipStream_t st, const BProb* P, int np, Ctrl* out)
+{
+    if (np > 0) hipLaunchKernelGGL(kb_gather_ctrl, dim3((np + 255) / 256), dim3(256), 0, st, P, np, out);
 }
 
 void launch_norm_finalize(hipStream_t st, const double* partials, int n, double* out)

@@ -1,0 +1,89 @@
+"""Batched solves (m1_engine): many problems of uneven sizes advance together,
+one launch per level operation.  Each request must give exactly the result of
+solving it alone (same kernels, same per-request norms and controls), also
+when the arena is so small that requests queue and are admitted as others
+finish (continuous batching).  The alone-results are themselves checked
+against the oracle by the parity tests.
+"""
+import numpy as np
+import pytest
+
+from paper_2208_14703_amd import binding, inputs
+from tests.gpu_util import announce, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+PARAMS = dict(omega=0.8, rtol=1e-8)
+
+
+def problems(n, sides=(64, 128, 256)):
+    out = []
+    rng = np.random.default_rng(5)
+    for k in range(n):
+        side = int(sides[k % len(sides)])
+        prob, v, sig = inputs.random_problem(300 + k, 2, side, side, cfl=100.0, log10_sa=(-3, 3), fmax=0.95,
+                                             block=32 if side >= 64 else 8)
+        if k % 3 == 2:   # a hot wall on some of them
+            prob["bc"] = [dict(kind="dirichlet", E=30.0, Fx=0.0, Fy=0.0)] + [dict(kind="reflective")] * 3
+        out.append((prob, v, sig, 1 + int(rng.integers(0, 3))))
+    return out
+
+
+def alone(prob, v, sig, nsteps):
+    P = binding.Plan(prob, to_dev(sig), PARAMS)
+    vd = to_dev(v)
+    info = P.step(vd, nsteps)
+    return to_host(vd), info
+
+
+@pytest.mark.parametrize("arena_mb", [4096, 24])
+def test_batch_matches_alone(arena_mb):
+    announce("batch vs alone, arena MB", arena_mb)
+    cases = problems(9)
+    E = binding.Engine(arena_mb << 20, PARAMS, max_requests=64)
+    need = max(binding.Engine.request_bytes(p, PARAMS) for p, _, _, _ in cases)
+    if arena_mb == 24:
+        assert 2 * need < (arena_mb << 20) < 3 * need, "arena meant to hold only two large requests at once"
+    states, tickets = [], []
+    for prob, v, sig, ns in cases:
+        vd = to_dev(v)
+        states.append(vd)
+        tickets.append(E.submit(prob, to_dev(sig), vd, ns))
+    done = set()
+    rounds = 0
+    while len(done) < len(tickets):
+        E.run(3)
+        rounds += 1
+        for t in tickets:
+            if t not in done and E.poll(t) is not None:
+                done.add(t)
+        assert rounds < 5000
+    for (prob, v, sig, ns), vd, t in zip(cases, states, tickets):
+        info = E.poll(t)
+        ref, info_a = alone(prob, v, sig, ns)
+        assert info["status"] == 0 and info["steps_done"] == ns
+        assert info["cycles"] == info_a["cycles"], (info["cycles"], info_a["cycles"])
+        np.testing.assert_array_equal(to_host(vd), ref)
+
+
+def test_batch_budget_cancel_and_arguments():
+    announce("batch: budget / cancel / args")
+    E = binding.Engine(32 << 20, PARAMS, max_requests=8)
+    prob, v, sig = inputs.random_problem(1, 2, 512, 512, cfl=100.0)
+    with pytest.raises(binding.M1Error) as ei:
+        E.submit(prob, to_dev(sig), to_dev(v), 1)
+    assert ei.value.status == 7   # can never fit
+    p1 = inputs.gaussian_1d(n=64)
+    with pytest.raises(binding.M1Error) as ei:
+        E.submit(p1[0], to_dev(p1[2]), to_dev(p1[1]), 1)
+    assert ei.value.status == 1   # batches are 2-D
+    prob, v, sig = inputs.random_problem(2, 2, 64, 64, cfl=100.0)
+    vd = to_dev(v)
+    t = E.submit(prob, to_dev(sig), vd, 20)
+    E.run(1)
+    E.cancel(t)
+    E.run(1)
+    info = E.poll(t)
+    assert info is not None and info["status"] == 6
+    got = to_host(vd)
+    assert np.all(got[0] > 0) and np.all(got[3] > 0)
