@@ -1,21 +1,37 @@
 """Benchmark of the MI355X implicit M1 multigrid solver.
 
-Workload: the 2-D hot-wall problem, 1024 x 1024 cells on [0,1]^2, dt = 100 h/c.
-Opacity is piecewise constant on 32x32 blocks with log10 sigma_a ~ U[-2,2] and
-sigma_s ~ U[0,1]. The x = 0 side is a hot Dirichlet wall; the other sides are
-reflective. The solver is plain FP64 and takes 10 implicit Euler steps, each
-run to relative residual 1e-8.
+Default line (the headline workload): the 2-D hot-wall problem.
+- Grid: 1024 x 1024 cells on [0,1]^2, dt = 100 h/c.
+- Opacity: piecewise constant on 32x32 blocks, log10 sigma_a ~ U[-2,2], sigma_s ~ U[0,1].
+- Boundaries: a hot Dirichlet wall at x = 0, reflective elsewhere.
+- Solver: plain FP64, 10 implicit Euler steps, each run to relative residual 1e-8.
 
-One benchmark "step" solves the whole workload (all 10 implicit steps) from the
-same initial state, already resident in HBM. The timed region covers
-exactly --steps such solves, bracketed by device synchronisation. The reported
-value is cell-updates/s = cells * implicit steps / wall time, in millions.
+One benchmark "step" solves the whole workload (all 10 implicit steps) from the same
+initial state, already resident in HBM. The timed region covers exactly --steps such
+solves, bracketed by device synchronisation. value = cells * implicit steps / wall
+time, in millions (Mcell-updates/s).
 
 The same JSON line also carries:
-  * roofline: the finest-level Jacobi sweep kernel, timed with HIP events on
-    the solver's stream; 112 algorithmic bytes per cell;
-  * cpu_baseline: the FP64 CPU oracle timed on the host cores over a bounded
-    sample of V-cycles of the same workload.
+- roofline: the finest-level Jacobi sweep kernel k_relax<2>, timed with HIP events on the
+  solver's stream, at 112 algorithmic bytes per cell.
+- traffic: the kernel's FETCH_SIZE + WRITE_SIZE counter bytes per launch, scaled by the same
+  counters on a plain copy of known size. They are read from the counter summary under
+  profiles/, and are null when the kernel sources have changed since it was taken.
+- cpu_baseline: the FP64 CPU oracle on the host cores, over a bounded sample of V-cycles
+  of the same workload.
+- batched: 256 independent problems of uneven size, seeded 1000+k, side log-uniform in
+  {64..512}, one implicit step each to 1e-8. They are solved by the batching engine (one
+  launch per level operation) and, for comparison, one by one with the plain FP64 path.
+  It reports solves/s and per-problem latency p50/p99.
+- serving: a short Poisson request stream through the engine's serving loop (sides 64..2048,
+  1..20 steps per request, contrast 10^0..10^6). It reports solves/s and request latency
+  p50/p99.
+
+Other modes:
+- --workload lognormal: the 4096^2 single solve (mixed or fp64).
+- --workload serve: the serving sweep over arrival rates.
+- --profile sweeps: only the sweep kernel and a copy kernel of known size, for PMC counter
+  runs.
 """
 from __future__ import annotations
 
@@ -31,11 +47,14 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 from paper_2208_14703_amd import binding, inputs  # noqa: E402
+from paper_2208_14703_amd.profsum import sources_hash  # noqa: E402
 
 METRIC = "Mcell-updates/s + time to 1e-8 residual; batched solves/s with p50/p99 latency"
 HBM_PEAK_GBS = 8000.0
 SWEEP_BYTES_PER_CELL = 112  # v (E,Fx,Fy,T) 32 + b 32 + sigma 16 read, v' 32 written
 SOLVER = dict(omega=0.8, levels=0)
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_relax_hotwall1024_traffic.txt")
+COPY_ELEMS = 1 << 27  # 1 GiB of float64 per copy launch
 
 
 def parse():
@@ -43,17 +62,37 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--n", type=int, default=1024, help="grid side (the workload is 1024)")
+    ap.add_argument("--workload", default="hotwall", choices=["hotwall", "lognormal", "serve"])
+    ap.add_argument("--n", type=int, default=0, help="grid side (default: the workload's own)")
+    ap.add_argument("--precision", default=None, choices=["fp64", "mixed"],
+                    help="default: fp64 for hotwall, mixed for lognormal")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-cycles", type=int, default=8, help="oracle V-cycles in the CPU-baseline sample")
-    ap.add_argument("--profile-only", action="store_true", help="short run for profilers: no roofline/cpu legs")
-    ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"],
-                    help="fp64 (the workload's definition) or mixed (FP32 delta-form smoothing)")
+    ap.add_argument("--cpu-cycles", type=int, default=60, help="oracle V-cycles in the CPU-baseline sample")
+    ap.add_argument("--no-extras", action="store_true", help="skip the batched and serving legs")
+    ap.add_argument("--batch", type=int, default=256, help="problems in the batched leg")
+    ap.add_argument("--requests", type=int, default=48, help="requests per rate in the serving leg")
+    ap.add_argument("--rates", default="50", help="comma-separated arrival rates (1/s) for serving")
+    ap.add_argument("--arena-gb", type=float, default=64.0, help="engine HBM budget for serving")
+    ap.add_argument("--profile", default="none", choices=["none", "sweeps"],
+                    help="sweeps: only sweep launches and a copy of known size (for counter runs)")
+    ap.add_argument("--reps", type=int, default=40, help="sweep launches timed for the roofline")
     return ap.parse_args()
 
 
-def sweep_timing(torch, plan, b, v, reps=40):
-    """Average duration of the finest-level sweep kernel (HIP events on the plan's stream)."""
+def read_traffic(cells: int):
+    """Counter bytes per k_relax launch from the committed summary, if the kernel is unchanged."""
+    try:
+        kv = dict(line.split(":", 1) for line in open(TRAFFIC_FILE) if ":" in line and not line.startswith(" "))
+    except OSError:
+        return None
+    kv = {k.strip(): v.strip() for k, v in kv.items()}
+    if kv.get("sources_sha256") != sources_hash() or int(kv.get("cells", -1)) != cells:
+        return None
+    return float(kv["traffic_bytes_per_launch"])
+
+
+def sweep_timing(torch, plan, b, v, reps):
+    """Average duration of the finest-level sweep kernel: HIP events on the plan's stream."""
     out = torch.empty_like(v)
     for _ in range(3):
         plan.sweep(b, v)
@@ -61,13 +100,30 @@ def sweep_timing(torch, plan, b, v, reps=40):
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record(st)
     src, dst = v.clone(), out
+    L = binding.lib()
     for _ in range(reps):
-        binding.lib().m1_sweep(plan.handle, binding.ctypes.byref(plan._st(b)), binding.ctypes.byref(plan._st(src)),
-                               binding.ctypes.byref(plan._st(dst)))
+        binding._check(L.m1_sweep(plan.handle, binding.ctypes.byref(plan._st(b)), binding.ctypes.byref(plan._st(src)),
+                                  binding.ctypes.byref(plan._st(dst))), "m1_sweep")
         src, dst = dst, src
     e1.record(st)
     e1.synchronize()
     return e0.elapsed_time(e1) / reps * 1e-3
+
+
+def copy_timing(torch, reps=10):
+    """A plain copy of known size (torch.neg: 8 B read + 8 B written per element)."""
+    x = torch.ones(COPY_ELEMS, dtype=torch.float64, device="cuda")
+    y = torch.empty_like(x)
+    torch.neg(x, out=y)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        torch.neg(x, out=y)
+    e1.record()
+    e1.synchronize()
+    t = e0.elapsed_time(e1) / reps * 1e-3
+    return {"bytes": 16 * COPY_ELEMS, "avg_launch_us": round(t * 1e6, 2), "GB_per_s": round(16 * COPY_ELEMS / t / 1e9, 1)}
 
 
 def cpu_baseline(prob, v, sig, run, gpu_cycles_per_step, ncycles):
@@ -80,13 +136,121 @@ def cpu_baseline(prob, v, sig, run, gpu_cycles_per_step, ncycles):
     per_cycle = dt / max(info["cycles"], 1)
     projected = per_cycle * gpu_cycles_per_step * run["steps"]
     cells = prob["nx"] * prob["ny"]
-    return {"value": cells * run["steps"] / projected / 1e6, "unit": "Mcell-updates/s", "cores": oracle.threads(),
-            "kind": "oracle",
+    return {"value": round(cells * run["steps"] / projected / 1e6, 4), "unit": "Mcell-updates/s",
+            "cores": oracle.threads(), "kind": "oracle",
             "sample": f"{info['cycles']} V-cycles of time step 1 of the same workload in {dt:.1f} s "
-                      f"({per_cycle:.2f} s/cycle), projected to the GPU's {gpu_cycles_per_step:.1f} cycles/step "
-                      f"x {run['steps']} steps"}
+                      f"({per_cycle:.3f} s/cycle), projected to the GPU's {gpu_cycles_per_step:.1f} cycles/step "
+                      f"x {run['steps']} steps (same algorithm, same cycle count)"}
 
 
+def pct(x, q):
+    return float(np.percentile(np.asarray(x), q)) if len(x) else None
+
+
+# ---------------------------------------------------------------------------
+# batched leg: many problems of uneven size
+# ---------------------------------------------------------------------------
+def batch_leg(torch, nprob: int):
+    params = dict(rtol=1e-8, max_cycles=20000, **SOLVER)
+    cases = [inputs.batch_problem(k) for k in range(nprob)]
+    sig_d = [binding.to_device(c[2]) for c in cases]
+    v0_d = [binding.to_device(c[1]) for c in cases]
+    cells = sum(c[0]["nx"] * c[0]["ny"] for c in cases)
+    need = sum(binding.Engine.request_bytes(c[0], params) for c in cases)
+    E = binding.Engine(need + (256 << 20), params, max_requests=nprob)
+
+    def engine_run(idx):
+        vs = [v0_d[i].clone() for i in idx]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        tk = [E.submit(cases[i][0], sig_d[i], v, 1) for i, v in zip(idx, vs)]
+        pending = set(tk)
+        while pending:
+            E.run(4)
+            pending = {t for t in pending if E.poll(t) is None}
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        infos = [E.poll(t) for t in tk]
+        lat = [E.times(t)[2] - E.times(t)[0] for t in tk]
+        for t in tk:
+            E.release(t)
+        return vs, infos, lat, wall
+
+    engine_run(list(range(min(8, nprob))))  # warm-up (module load, first launches)
+    vs, infos, lat, wall = engine_run(list(range(nprob)))
+    # the plain FP64 path, one problem after another (plans made before the clock starts)
+    plans = [binding.Plan(c[0], s, params) for c, s in zip(cases, sig_d)]
+    ws = [v.clone() for v in v0_d]
+    plans[0].step(v0_d[0].clone(), 1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    seq_info = [p.step(w, 1) for p, w in zip(plans, ws)]
+    torch.cuda.synchronize()
+    seq_wall = time.perf_counter() - t0
+    same = all(torch.equal(a, b) for a, b in zip(vs, ws))
+    ndiff = sum(not torch.equal(a, b) for a, b in zip(vs, ws))
+    maxrel = max(float(((a - b).abs().amax(dim=(1, 2)) / b.abs().amax(dim=(1, 2))).max()) for a, b in zip(vs, ws))
+    cyc_diff = sum(i["cycles"] != j["cycles"] for i, j in zip(infos, seq_info))
+    ok = all(i["status"] == 0 for i in infos) and all(i["status"] == 0 for i in seq_info)
+    del plans, E
+    return {"workload": f"{nprob} problems seeded 1000+k, side log-uniform in 64..512 "
+                        f"({cells / 1e6:.1f} M cells), 1 implicit step each to 1e-8, FP64",
+            "solves_per_s": round(nprob / wall, 2), "wall_s": round(wall, 4),
+            "latency_p50_ms": round(pct(lat, 50) * 1e3, 2), "latency_p99_ms": round(pct(lat, 99) * 1e3, 2),
+            "Mcell_updates_per_s": round(cells / wall / 1e6, 2),
+            "plain_fp64_one_by_one_solves_per_s": round(nprob / seq_wall, 2),
+            "speedup_vs_plain": round(seq_wall / wall, 3),
+            "bitwise_equal_to_plain": bool(same), "problems_differing": ndiff, "max_rel_diff": maxrel,
+            "cycle_count_mismatches": cyc_diff, "all_converged": bool(ok),
+            "cycles_mean": round(float(np.mean([i["cycles"] for i in infos])), 2)}
+
+
+# ---------------------------------------------------------------------------
+# serving leg: a Poisson request stream through the serving loop
+# ---------------------------------------------------------------------------
+def serve_leg(torch, nreq: int, rate: float, arena_bytes: int, seed: int = 7):
+    params = dict(rtol=1e-8, max_cycles=20000, **SOLVER)
+    rng = np.random.Generator(np.random.PCG64(seed))
+    reqs = [inputs.serve_request(rng) for _ in range(nreq)]
+    arr = np.cumsum(np.random.Generator(np.random.PCG64(seed + 1)).exponential(1.0 / rate, nreq))
+    sig_d = [binding.to_device(r[2]) for r in reqs]
+    v_d = [binding.to_device(r[1]) for r in reqs]
+    E = binding.Engine(arena_bytes, params, max_requests=1024)
+    # warm-up request (not counted)
+    w = inputs.batch_problem(0)
+    E.wait(E.submit(w[0], binding.to_device(w[2]), binding.to_device(w[1]), 1))
+    torch.cuda.synchronize()
+    E.serve_start(4)
+    t0 = time.perf_counter()
+    tickets = []
+    for i, r in enumerate(reqs):
+        d = t0 + arr[i] - time.perf_counter()
+        if d > 0:
+            time.sleep(d)
+        tickets.append(E.submit(r[0], sig_d[i], v_d[i], r[3]["steps"]))
+    infos = [E.wait(t) for t in tickets]
+    E.serve_stop()
+    tm = [E.times(t) for t in tickets]
+    lat = [d - s for s, _, d in tm]
+    span = max(d for _, _, d in tm) - min(s for s, _, _ in tm)
+    solves = sum(r[3]["steps"] for r in reqs)
+    cell_steps = sum(r[0]["nx"] * r[0]["ny"] * r[3]["steps"] for r in reqs)
+    # overlap: requests admitted while another request was still running
+    adm = sorted((a, d) for _, a, d in tm)
+    overlapped = sum(1 for k in range(1, len(adm)) if adm[k][0] < max(d for _, d in adm[:k]))
+    ok = all(i["status"] == 0 for i in infos)
+    del E
+    return {"rate_per_s": rate, "requests": nreq, "solves": solves, "solves_per_s": round(solves / span, 2),
+            "requests_per_s": round(nreq / span, 3), "Mcell_updates_per_s": round(cell_steps / span / 1e6, 2),
+            "latency_p50_ms": round(pct(lat, 50) * 1e3, 1), "latency_p99_ms": round(pct(lat, 99) * 1e3, 1),
+            "admitted_while_others_ran": overlapped, "all_converged": bool(ok), "wall_s": round(span, 2)}
+
+
+SERVE_DESC = ("Poisson stream, side log-uniform in 64..2048, contrast 10^U[0,6], 1..20 steps per request to 1e-8, "
+              "FP64, state resident in HBM across steps, continuous batching under an HBM budget")
+
+
+# ---------------------------------------------------------------------------
 def main():
     args = parse()
     if args.gpus != 1:
@@ -94,19 +258,50 @@ def main():
         sys.exit(2)
     import torch
     torch.cuda.init()
-    prob, v0, sig, run = inputs.hot_wall_2d(n=args.n)
+
+    if args.workload == "serve":
+        legs = [serve_leg(torch, args.requests, float(r), int(args.arena_gb * (1 << 30)))
+                for r in args.rates.split(",")]
+        best = max(legs, key=lambda x: x["solves_per_s"])
+        print(json.dumps({"metric": METRIC, "value": best["solves_per_s"], "unit": "solves/s", "n_gpus": 1,
+                          "steps": 1, "warmup": 1, "ms_per_step": round(best["wall_s"] * 1e3, 1),
+                          "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+                          "data": "synthetic", "config": {"workload": SERVE_DESC, "arena_gb": args.arena_gb},
+                          "rates": legs}), flush=True)
+        return
+
+    if args.workload == "lognormal":
+        prob, v0, sig, run = inputs.lognormal_2d(n=args.n or 4096)
+        precision = args.precision or "mixed"
+        desc = (f"lognormal 2-D {prob['nx']}x{prob['ny']}, periodic, |F|=0.9cE, block opacity seed 2, "
+                f"1 implicit step, dt=100h/c, {precision}, rtol 1e-8")
+    else:
+        prob, v0, sig, run = inputs.hot_wall_2d(n=args.n or 1024)
+        precision = args.precision or "fp64"
+        desc = (f"hot-wall 2-D {prob['nx']}x{prob['ny']}, {run['steps']} implicit steps, dt=100h/c, "
+                f"block opacity, {precision.upper()}, rtol {run['rtol']:g}")
     cells = prob["nx"] * prob["ny"]
     dev_sig = binding.to_device(sig)
     v_init = binding.to_device(v0)
-    plan = binding.Plan(prob, dev_sig, dict(rtol=run["rtol"], max_cycles=20000, precision=args.precision, **SOLVER))
+    plan = binding.Plan(prob, dev_sig, dict(rtol=run["rtol"], max_cycles=20000, precision=precision, **SOLVER))
     v = torch.empty_like(v_init)
+    b = v_init.clone()
+    b[3] *= prob["c_v"]
+
+    if args.profile == "sweeps":
+        t_sweep = sweep_timing(torch, plan, b, v_init.clone(), args.reps)
+        cp = copy_timing(torch)
+        print(json.dumps({"profile": "sweeps", "cells": cells, "sweep_avg_launch_us": round(t_sweep * 1e6, 2),
+                          "sweep_GB_per_s": round(SWEEP_BYTES_PER_CELL * cells / t_sweep / 1e9, 1), "copy": cp}),
+              flush=True)
+        return
 
     def one_solve():
         v.copy_(v_init)
         return plan.step(v, run["steps"])
 
     for _ in range(args.warmup):
-        info = one_solve()
+        one_solve()
     torch.cuda.synchronize()
     infos = []
     t0 = time.perf_counter()
@@ -117,30 +312,34 @@ def main():
     ms_per_step = elapsed / args.steps * 1e3
     value = cells * run["steps"] * args.steps / elapsed / 1e6
     cycles = infos[-1]["cycles"]
-    status = infos[-1]["status"]
     out = {
         "metric": METRIC, "value": round(value, 3), "unit": "Mcell-updates/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(ms_per_step, 3), "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "f64" if args.precision == "fp64" else "f64+f32", "data": "synthetic",
-        "config": {"workload": f"hot-wall 2-D {prob['nx']}x{prob['ny']}, {run['steps']} implicit steps, "
-                               f"dt=100h/c, block opacity, {args.precision.upper()}, rtol {run['rtol']:g}",
-                   "nx": prob["nx"], "ny": prob["ny"], "time_steps": run["steps"], "rtol": run["rtol"],
-                   "precision": args.precision, "levels": infos[-1]["levels"], "omega": SOLVER["omega"]},
+        "vs_baseline": None, "dtype": "f64" if precision == "fp64" else "f64+f32", "data": "synthetic",
+        "config": {"workload": desc, "nx": prob["nx"], "ny": prob["ny"], "time_steps": run["steps"],
+                   "rtol": run["rtol"], "precision": precision, "levels": infos[-1]["levels"],
+                   "omega": SOLVER["omega"]},
         "time_to_rtol_ms_per_time_step": round(ms_per_step / run["steps"], 3),
-        "cycles_per_time_step": cycles / run["steps"], "solver_status": status,
+        "cycles_per_time_step": cycles / run["steps"], "solver_status": infos[-1]["status"],
         "final_rel_residual": infos[-1]["rel_residual"],
     }
-    if not args.profile_only:
-        b = v_init.clone()
-        b[3] *= prob["c_v"]
-        t_sweep = sweep_timing(torch, plan, b, v)
-        achieved = SWEEP_BYTES_PER_CELL * cells / t_sweep / 1e9
-        out["roofline"] = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                           "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                           "kernel": "k_relax<2> (finest-level Jacobi sweep)",
-                           "avg_launch_us": round(t_sweep * 1e6, 2)}
-        if not args.no_cpu_baseline:
-            out["cpu_baseline"] = cpu_baseline(prob, v0, sig, run, cycles / run["steps"], args.cpu_cycles)
+    t_sweep = sweep_timing(torch, plan, b, v_init.clone(), args.reps)
+    achieved = SWEEP_BYTES_PER_CELL * cells / t_sweep / 1e9
+    traffic = read_traffic(cells) if args.workload == "hotwall" and precision == "fp64" else None
+    out["roofline"] = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                       "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                       "kernel": "k_relax<2> (finest-level FP64 Jacobi sweep)",
+                       "algorithmic_bytes_per_launch": SWEEP_BYTES_PER_CELL * cells,
+                       "avg_launch_us": round(t_sweep * 1e6, 2)}
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(prob, v0, sig, run, cycles / run["steps"], args.cpu_cycles)
+    if args.workload == "hotwall" and not args.no_extras:
+        del plan
+        torch.cuda.empty_cache()
+        out["batched"] = batch_leg(torch, args.batch)
+        torch.cuda.empty_cache()
+        out["serving"] = {"workload": SERVE_DESC, **serve_leg(torch, args.requests, float(args.rates.split(",")[0]),
+                                                              int(args.arena_gb * (1 << 30)))}
     print(json.dumps(out), flush=True)
 
 

@@ -223,7 +223,9 @@ m1_status m1_batch_run(m1_engine* e, int32_t cycles, int32_t* n_running, int32_t
 /* M1_OK and the request's result in *info once it is done, M1_ERR_BUSY while
  * it is queued or running.                                                   */
 m1_status m1_batch_poll(m1_engine* e, uint64_t ticket, m1_info* info);
-/* Run rounds until the request is done; returns its final status.            */
+/* Wait until the request is done and return its final status: while the
+ * serving loop runs, sleep until it finishes the request; otherwise run
+ * rounds (4 V-cycles each) on the calling thread.  info may be NULL.         */
 m1_status m1_batch_wait(m1_engine* e, uint64_t ticket, m1_info* info);
 /* Drop a queued or running request at the next round boundary (its state is
  * left at its last admissible iterate).                                      */
@@ -232,6 +234,21 @@ m1_status m1_batch_cancel(m1_engine* e, uint64_t ticket);
 m1_status m1_batch_times(m1_engine* e, uint64_t ticket, double* t_submit, double* t_admit, double* t_done);
 /* Forget a finished request (frees its host record).                         */
 m1_status m1_batch_release(m1_engine* e, uint64_t ticket);
+
+/* Serving loop (continuous batching without a driving caller).  Starts one
+ * host thread of the library that runs rounds of `cycles` V-cycles as long as
+ * requests are resident or waiting and sleeps while the engine is empty, so
+ * requests submitted from any thread while others are on the GPU are admitted
+ * as memory and slots free up.  Clients only submit, then poll or wait.
+ * M1_ERR_BUSY if a loop is already started (or ended on an error and has not
+ * been stopped); M1_ERR_ARG for cycles < 1.                                  */
+m1_status m1_serve_start(m1_engine* e, int32_t cycles);
+/* Stop the serving loop after its current round and join its thread (no-op
+ * if none).  Requests not yet done stay in the engine; a later
+ * m1_serve_start or m1_batch_run continues them.  Returns the first error the
+ * loop met (its rounds stop at the first error), else M1_OK.  Also called by
+ * m1_engine_destroy.                                                         */
+m1_status m1_serve_stop(m1_engine* e);
 
 #ifdef __cplusplus
 }

@@ -111,10 +111,12 @@ def lib():
         L.m1_batch_times.argtypes = [vp, ctypes.c_uint64, P(ctypes.c_double), P(ctypes.c_double),
                                      P(ctypes.c_double)]
         L.m1_batch_release.argtypes = [vp, ctypes.c_uint64]
+        L.m1_serve_start.argtypes = [vp, ctypes.c_int32]
+        L.m1_serve_stop.argtypes = [vp]
         for name in ("m1_plan_create", "m1_residual", "m1_vcycle", "m1_step", "m1_apply_A", "m1_sweep",
                      "m1_pseudo_step", "m1_restrict", "m1_prolong_project", "m1_sync", "m1_level_dims",
                      "m1_engine_create", "m1_batch_submit", "m1_batch_run", "m1_batch_poll", "m1_batch_wait",
-                     "m1_batch_cancel", "m1_batch_times", "m1_batch_release"):
+                     "m1_batch_cancel", "m1_batch_times", "m1_batch_release", "m1_serve_start", "m1_serve_stop"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -339,9 +341,20 @@ class Engine:
         return _info_dict(info)
 
     def wait(self, ticket: int) -> dict:
+        """Block until the request is done (the request's own status is in the result)."""
         info = m1_info()
-        lib().m1_batch_wait(self.handle, ticket, ctypes.byref(info))
+        st = lib().m1_batch_wait(self.handle, ticket, ctypes.byref(info))
+        if self.poll(ticket) is None:  # not done: the engine or the serving loop failed
+            raise M1Error(st, "m1_batch_wait")
         return _info_dict(info)
+
+    def serve_start(self, cycles: int = 4):
+        """Start the library's serving thread (rounds of `cycles` V-cycles)."""
+        _check(lib().m1_serve_start(self.handle, cycles), "m1_serve_start")
+
+    def serve_stop(self):
+        """Stop and join the serving thread; raises the first error it met."""
+        _check(lib().m1_serve_stop(self.handle), "m1_serve_stop")
 
     def cancel(self, ticket: int):
         _check(lib().m1_batch_cancel(self.handle, ticket), "m1_batch_cancel")

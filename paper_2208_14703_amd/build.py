@@ -13,9 +13,12 @@ SOURCES = ["m1_kernels.hip", "m1_mixed.hip", "m1_capi.hip"]
 ARCH = os.environ.get("M1_OFFLOAD_ARCH", "gfx950")
 
 FLAGS = [
-    "-O3", "-std=c++17", "-fPIC", "-shared", f"--offload-arch={ARCH}",
+    "-O3", "-std=c++17", "-fPIC", "-shared", "-pthread", f"--offload-arch={ARCH}",
     # no packed FP32 instructions are generated (hardware-correctness policy of this project)
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # multiply-add fusion decided per source expression, not by the backend's context: every kernel
+    # that shares a per-cell function rounds identically (batched results equal solo results bitwise)
+    "-ffp-contract=on",
     "-Wall", "-Wno-unused-function", "-Wno-unused-command-line-argument",
 ]
 

@@ -902,10 +902,13 @@ m1_status m1_prolong_project(m1_plan* P, int32_t level, const m1_state* u, const
 // ============================================================================
 // Batched / served solves: an engine over a caller-provided device arena.
 // ============================================================================
+#include <atomic>
 #include <chrono>
+#include <condition_variable>
 #include <deque>
 #include <map>
 #include <mutex>
+#include <thread>
 #include <unordered_map>
 
 namespace {
@@ -964,6 +967,15 @@ struct m1_engine {
     int Lmax = 1;
     std::vector<uint32_t> hwl;
     std::vector<int> hpl;
+    // serving loop
+    int device = 0;
+    std::thread server;
+    std::atomic<bool> serving{false}, stop{false};
+    std::atomic<int> n_run{0};
+    int serve_cycles = 4;
+    m1_status serve_status = M1_OK;   // first error of the serving loop (under qmu)
+    std::condition_variable work_cv;  // submit / stop -> serving loop (with qmu)
+    std::condition_variable done_cv;  // request finished / loop ended -> waiters (with qmu)
 };
 
 namespace {
@@ -1026,8 +1038,11 @@ void finish(m1_engine& E, m1_req* R, m1_status st)
         R->plan = nullptr;
     }
     pool_free(E, R->ws_off, R->ws_bytes);
-    std::lock_guard<std::mutex> g(E.qmu);
-    R->state = REQ_DONE;
+    {
+        std::lock_guard<std::mutex> g(E.qmu);
+        R->state = REQ_DONE;
+    }
+    E.done_cv.notify_all();
 }
 
 // FIFO admission: take pending requests while their workspace fits.
@@ -1044,6 +1059,7 @@ void admit(m1_engine& E)
                 R->state = REQ_DONE;
                 R->status = M1_ERR_BUSY;
                 R->t_done = now_s();
+                E.done_cv.notify_all();
                 continue;
             }
             size_t off;
@@ -1237,6 +1253,10 @@ m1_status m1_engine_create(const m1_params* p, void* arena, size_t arena_bytes, 
     E->arena = static_cast<char*>(arena);
     E->arena_bytes = arena_bytes;
     E->maxp = max_requests;
+    if (hipGetDevice(&E->device) != hipSuccess) {
+        delete E;
+        return M1_ERR_DEVICE;
+    }
     // tables at the start of the arena; work lists sized for the whole pool
     size_t off = 0;
     auto take = [&](size_t bytes) {
@@ -1268,6 +1288,7 @@ m1_status m1_engine_create(const m1_params* p, void* arena, size_t arena_bytes, 
 void m1_engine_destroy(m1_engine* E)
 {
     if (!E) return;
+    (void)m1_serve_stop(E);
     (void)hipStreamSynchronize(E->st);
     for (auto& kv : E->reqs) {
         if (kv.second->plan) m1_plan_destroy(kv.second->plan);
@@ -1297,11 +1318,14 @@ m1_status m1_batch_submit(m1_engine* E, const m1_grid* g, const m1_params* p, co
     R->nsteps = nsteps;
     R->ws_bytes = need;
     R->t_submit = now_s();
-    std::lock_guard<std::mutex> lk(E->qmu);
-    R->ticket = E->next++;
-    E->reqs[R->ticket] = R;
-    E->pending.push_back(R);
-    *ticket = R->ticket;
+    {
+        std::lock_guard<std::mutex> lk(E->qmu);
+        R->ticket = E->next++;
+        E->reqs[R->ticket] = R;
+        E->pending.push_back(R);
+        *ticket = R->ticket;
+    }
+    E->work_cv.notify_one();
     return M1_OK;
 }
 
@@ -1371,6 +1395,7 @@ m1_status m1_batch_run(m1_engine* E, int32_t cycles, int32_t* n_running, int32_t
         if (keep.size() != E->running.size()) E->dirty = true;
         E->running.swap(keep);
     }
+    E->n_run.store((int)E->running.size());
     std::lock_guard<std::mutex> g(E->qmu);
     if (n_running) *n_running = (int32_t)E->running.size();
     if (n_pending) *n_pending = (int32_t)E->pending.size();
@@ -1401,9 +1426,21 @@ m1_status m1_batch_poll(m1_engine* E, uint64_t ticket, m1_info* info)
 m1_status m1_batch_wait(m1_engine* E, uint64_t ticket, m1_info* info)
 {
     if (!E) return M1_ERR_ARG;
+    m1_info tmp;
+    if (!info) info = &tmp;
     for (;;) {
         m1_status s = m1_batch_poll(E, ticket, info);
         if (s != M1_ERR_BUSY) return s == M1_OK ? (m1_status)info->status : s;
+        if (E->serving.load()) {
+            // the serving loop drives the rounds: sleep until a request finishes
+            std::unique_lock<std::mutex> lk(E->qmu);
+            auto it = E->reqs.find(ticket);
+            if (it == E->reqs.end()) return M1_ERR_ARG;
+            const m1_req* R = it->second;
+            E->done_cv.wait(lk, [&] { return R->state == REQ_DONE || !E->serving.load(); });
+            if (R->state != REQ_DONE && E->serve_status != M1_OK) return E->serve_status;
+            continue;
+        }
         s = m1_batch_run(E, 4, nullptr, nullptr);
         if (s != M1_OK) return s;
     }
@@ -1440,6 +1477,67 @@ m1_status m1_batch_release(m1_engine* E, uint64_t ticket)
     delete it->second;
     E->reqs.erase(it);
     return M1_OK;
+}
+
+static void serve_loop(m1_engine* E)
+{
+    if (hipSetDevice(E->device) != hipSuccess) {
+        std::lock_guard<std::mutex> lk(E->qmu);
+        E->serve_status = M1_ERR_DEVICE;
+    } else {
+        for (;;) {
+            {
+                std::unique_lock<std::mutex> lk(E->qmu);
+                E->work_cv.wait(lk, [&] { return E->stop.load() || !E->pending.empty() || E->n_run.load() > 0; });
+                if (E->stop.load()) break;
+            }
+            const m1_status s = m1_batch_run(E, E->serve_cycles, nullptr, nullptr);
+            if (s != M1_OK) {
+                std::lock_guard<std::mutex> lk(E->qmu);
+                E->serve_status = s;
+                break;
+            }
+        }
+    }
+    {
+        std::lock_guard<std::mutex> lk(E->qmu);
+        E->serving.store(false);
+    }
+    E->done_cv.notify_all();
+}
+
+m1_status m1_serve_start(m1_engine* E, int32_t cycles)
+{
+    if (!E || cycles < 1) return M1_ERR_ARG;
+    if (E->serving.load() || E->server.joinable()) return M1_ERR_BUSY;
+    {
+        std::lock_guard<std::mutex> lk(E->qmu);
+        E->serve_status = M1_OK;
+    }
+    E->serve_cycles = cycles;
+    E->stop.store(false);
+    E->serving.store(true);
+    try {
+        E->server = std::thread(serve_loop, E);
+    } catch (...) {
+        E->serving.store(false);
+        return M1_ERR_DEVICE;
+    }
+    return M1_OK;
+}
+
+m1_status m1_serve_stop(m1_engine* E)
+{
+    if (!E) return M1_ERR_ARG;
+    if (!E->server.joinable()) return M1_OK;
+    {
+        std::lock_guard<std::mutex> lk(E->qmu);
+        E->stop.store(true);
+    }
+    E->work_cv.notify_all();
+    E->server.join();
+    std::lock_guard<std::mutex> lk(E->qmu);
+    return E->serve_status;
 }
 
 }  // extern "C"

@@ -378,7 +378,7 @@ __device__ __forceinline__ Soa tail_pseudo(const TailArgs& A, const TailLevel& T
 }
 
 template <int DIM>
-__device__ void tail_body(const TailArgs& A, double dt)
+__device__ __forceinline__ void tail_body(const TailArgs& A, double dt)
 {
     unsigned in_u2 = 0;  // bit l set: the current iterate of level l is in u2 (else u)
     auto cur = [&](int l) { return ((in_u2 >> l) & 1u) ? A.lev[l].u2 : A.lev[l].u; };

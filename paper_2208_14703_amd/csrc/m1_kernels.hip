@@ -19,7 +19,11 @@
 namespace m1 {
 
 constexpr int kBlock = 256;
-constexpr int kTailThreads = 1024;
+// The bottom of the cycle holds at most a few hundred cells per level: one
+// thread per cell, and 256 threads leave the per-cell body its full register
+// file (a 1024-thread bound caps it at 128 VGPRs and it spills).
+constexpr int kTailThreads = 256;
+constexpr int kStepThreads = 1024;
 
 static inline unsigned nblocks(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
 
@@ -64,11 +68,11 @@ __global__ __launch_bounds__(kBlock) void k_pseudo(Phys ph, Lvl L, Soa f, CSoa u
                                                    int first, Soa rs, double* __restrict__ gs,
                                                    const int* __restrict__ active)
 {
+    const double dt = dtau_dev ? *dtau_dev : dtau;  // both control loads in flight together
     if (inactive(active)) return;
     int64_t k;
     int i, j;
     if (!cell_of(L, k, i, j)) return;
-    const double dt = dtau_dev ? *dtau_dev : dtau;
     if (first) pseudo_cell<DIM, true>(ph, L, cs(f), f, u, out, dt, reach, local, rs, gs, k, i, j);
     else pseudo_cell<DIM, false>(ph, L, cs(f), f, u, out, dt, reach, local, rs, gs, k, i, j);
 }
@@ -128,8 +132,9 @@ __global__ __launch_bounds__(kTailThreads) void k_tail(const TailArgs* __restric
                                                        const double* __restrict__ dtau_dev,
                                                        const int* __restrict__ active)
 {
+    const double dt = dtau_dev ? *dtau_dev : dtau;
     if (inactive(active)) return;
-    tail_body<DIM>(*Ap, dtau_dev ? *dtau_dev : dtau);
+    tail_body<DIM>(*Ap, dt);
 }
 
 // ---------------------------------------------------------------------------
@@ -304,7 +309,7 @@ __global__ __launch_bounds__(kTailThreads) void kb_tail(const BProb* __restrict_
 
 // One block per problem: start a time step from the state in x0 -- b = (E, F,
 // C_v T), |b| for the rounding floor, and a fresh cycle control.
-__global__ __launch_bounds__(1024) void kb_step_init(const BProb* __restrict__ P, const BSlot* __restrict__ S,
+__global__ __launch_bounds__(kStepThreads) void kb_step_init(const BProb* __restrict__ P, const BSlot* __restrict__ S,
                                                      const int* __restrict__ plist)
 {
     const int p = plist[blockIdx.x];
@@ -322,7 +327,7 @@ __global__ __launch_bounds__(1024) void kb_step_init(const BProb* __restrict__ P
         q = fma(E, E, fma(Fx * ic, Fx * ic, fma(Fy * ic, Fy * ic, fma(T, T, q))));
     }
     // fixed-order block reduction of q (wave butterfly, then the 16 waves in order)
-    __shared__ double red[kTailThreads / 64];
+    __shared__ double red[kStepThreads / 64];
     for (int off = 32; off > 0; off >>= 1) q += __shfl_xor(q, off, 64);
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = q;
     __syncthreads();
@@ -413,7 +418,7 @@ void launch_b_tail(hipStream_t st, const BProb* P, const int* plist, int np)
 }
 void launch_b_step_init(hipStream_t st, const BProb* P, const BSlot* S, const int* plist, int np)
 {
-    if (np > 0) hipLaunchKernelGGL(kb_step_init, dim3(np), dim3(kTailThreads), 0, st, P, S, plist);
+    if (np > 0) hipLaunchKernelGGL(kb_step_init, dim3(np), dim3(kStepThreads), 0, st, P, S, plist);
 }
 void launch_b_gather_ctrl(hipStream_t st, const BProb* P, int np, Ctrl* out)
 {

@@ -451,7 +451,7 @@ __device__ __forceinline__ Soa32 mx_tail_pseudo(const TailArgs32& A, const TailL
 }
 
 template <int DIM>
-__global__ __launch_bounds__(1024) void k_mx_tail(const TailArgs32* __restrict__ Ap, double dtau,
+__global__ __launch_bounds__(256) void k_mx_tail(const TailArgs32* __restrict__ Ap, double dtau,
                                                   const double* __restrict__ dtau_dev, const int* __restrict__ active)
 {
     if (mx_inactive(active)) return;
@@ -583,8 +583,8 @@ void launch_mx_restrict(hipStream_t st, int dim, int nxf, int nyf, int px, int p
 void launch_mx_tail(hipStream_t st, int dim, const TailArgs32* args_dev, double dtau, const double* dtau_dev,
                     const int* active)
 {
-    if (dim == 2) hipLaunchKernelGGL(k_mx_tail<2>, dim3(1), dim3(1024), 0, st, args_dev, dtau, dtau_dev, active);
-    else hipLaunchKernelGGL(k_mx_tail<1>, dim3(1), dim3(1024), 0, st, args_dev, dtau, dtau_dev, active);
+    if (dim == 2) hipLaunchKernelGGL(k_mx_tail<2>, dim3(1), dim3(256), 0, st, args_dev, dtau, dtau_dev, active);
+    else hipLaunchKernelGGL(k_mx_tail<1>, dim3(1), dim3(256), 0, st, args_dev, dtau, dtau_dev, active);
 }
 
 void launch_to_f32(hipStream_t st, int64_t n, const double* a, float* b)

@@ -5,6 +5,8 @@ when the arena is so small that requests queue and are admitted as others
 finish (continuous batching).  The alone-results are themselves checked
 against the oracle by the parity tests.
 """
+import time
+
 import numpy as np
 import pytest
 
@@ -87,3 +89,38 @@ def test_batch_budget_cancel_and_arguments():
     assert info is not None and info["status"] == 6
     got = to_host(vd)
     assert np.all(got[0] > 0) and np.all(got[3] > 0)
+
+
+def test_serving_loop_matches_alone():
+    """Requests submitted while others are on the GPU (the library's serving
+    thread drives the rounds) are admitted as memory frees up, overlap on the
+    device, and each result equals solving it alone, bitwise."""
+    announce("serving loop vs alone")
+    cases = problems(7)
+    E = binding.Engine(24 << 20, PARAMS, max_requests=64)
+    E.serve_start(2)
+    states, tickets = [], []
+    for k, (prob, v, sig, ns) in enumerate(cases):
+        vd = to_dev(v)
+        sd = to_dev(sig)
+        states.append(vd)
+        tickets.append(E.submit(prob, sd, vd, ns))
+        time.sleep(0.01)
+    infos = [E.wait(t) for t in tickets]
+    E.serve_stop()
+    tm = [E.times(t) for t in tickets]
+    # some request was admitted while an earlier one was still running
+    assert any(tm[k][1] < max(tm[j][2] for j in range(k)) for k in range(1, len(tm)))
+    for (prob, v, sig, ns), vd, info in zip(cases, states, infos):
+        ref, info_a = alone(prob, v, sig, ns)
+        assert info["status"] == 0 and info["steps_done"] == ns
+        assert info["cycles"] == info_a["cycles"]
+        np.testing.assert_array_equal(to_host(vd), ref)
+    # the loop sleeps when empty and serves again after a restart
+    E.serve_start(3)
+    prob, v, sig, ns = cases[0]
+    vd = to_dev(v)
+    t = E.submit(prob, to_dev(sig), vd, ns)
+    assert E.wait(t)["status"] == 0
+    E.serve_stop()
+    np.testing.assert_array_equal(to_host(vd), alone(prob, v, sig, ns)[0])
