@@ -76,6 +76,8 @@ def parse():
     ap.add_argument("--profile", default="none", choices=["none", "sweeps"],
                     help="sweeps: only sweep launches and a copy of known size (for counter runs)")
     ap.add_argument("--reps", type=int, default=40, help="sweep launches timed for the roofline")
+    ap.add_argument("--stream", default="own", choices=["own", "default"],
+                    help="own: run on a created stream (default priority); default: the null stream")
     return ap.parse_args()
 
 
@@ -258,6 +260,9 @@ def main():
         sys.exit(2)
     import torch
     torch.cuda.init()
+    if args.stream == "own":
+        # a created stream: launches on the legacy null stream carry extra per-launch overhead
+        torch.cuda.set_stream(torch.cuda.Stream())
 
     if args.workload == "serve":
         legs = [serve_leg(torch, args.requests, float(r), int(args.arena_gb * (1 << 30)))

@@ -67,7 +67,9 @@ typedef struct {
  * source coefficients.  dt is the physical step (CFL*h/c in the paper's
  * notation), hx/hy the cell sizes, c the light speed, a_r the radiation
  * constant, c_v the gas heat capacity per volume (> 0).
- * bc[] order: x-, x+, y-, y+ (y sides ignored in 1-D).                       */
+ * bc[] order: x-, x+, y-, y+ (y sides ignored in 1-D).  At most 2^29 cells
+ * (nx*ny; e.g. 16384 x 16384 or 23170^2), so that every cell's byte offset in
+ * an FP64 field fits 32 bits; larger grids are rejected with M1_ERR_ARG.    */
 typedef struct {
     int32_t dim, nx, ny, pad_;
     double hx, hy, dt, c, a_r, c_v;

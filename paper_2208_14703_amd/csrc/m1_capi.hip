@@ -25,6 +25,7 @@ using m1::Soa;
 using m1::Soa32;
 
 constexpr size_t kAlign = 256;
+constexpr int64_t kMaxCells = int64_t(1) << 29;  // cells of a grid: byte offsets of FP64 fields fit 32 bits
 
 struct LevelBuf {
     int nx = 0, ny = 0;
@@ -81,7 +82,7 @@ bool valid_grid(const m1_grid* g)
     if (!g) return false;
     if (g->dim != 1 && g->dim != 2) return false;
     if (g->nx < 1 || g->ny < 1 || (g->dim == 1 && g->ny != 1)) return false;
-    if ((int64_t)g->nx * g->ny > (int64_t)INT32_MAX * 8) return false;
+    if ((int64_t)g->nx * g->ny > kMaxCells) return false;  // 32-bit cell byte offsets
     auto pos = [](double x) { return std::isfinite(x) && x > 0.0; };
     if (!pos(g->hx) || !pos(g->dt) || !pos(g->c) || !pos(g->c_v)) return false;
     if (g->dim == 2 && !pos(g->hy)) return false;
@@ -151,6 +152,7 @@ struct m1_plan {
     double* hpin = nullptr;
     unsigned long long* hbad = nullptr;
     m1::Ctrl* dctrl = nullptr;     // device cycle control (workspace)
+    m1::Ctrl* dfix = nullptr;      // always-live control for single operations (active = 1, settable dtau)
     m1::Ctrl* hctrl = nullptr;     // pinned host copy
     m1::TailArgs* dtail = nullptr; // device copy of the tail description (workspace)
     int lt = 0;                    // first level run by the single-workgroup tail (L: none)
@@ -217,6 +219,7 @@ void carve(m1_plan& P, Carver& c, const std::vector<int>& nxs, const std::vector
     P.dscal = c.take(8);
     P.dbad = reinterpret_cast<unsigned long long*>(c.take(1));
     P.dctrl = reinterpret_cast<m1::Ctrl*>(c.take((sizeof(m1::Ctrl) + 7) / 8));
+    P.dfix = reinterpret_cast<m1::Ctrl*>(c.take((sizeof(m1::Ctrl) + 7) / 8));
     P.dtail = reinterpret_cast<m1::TailArgs*>(c.take((sizeof(m1::TailArgs) + 7) / 8));
     if (P.params.precision == M1_MIXED)
         P.dtail32 = reinterpret_cast<m1::TailArgs32*>(c.take((sizeof(m1::TailArgs32) + 7) / 8));
@@ -235,6 +238,7 @@ void fill_level_params(m1_plan& P)
     for (LevelBuf& lv : P.lev) {
         lv.L.nx = lv.nx;
         lv.L.ny = lv.ny;
+        lv.L.sh = m1::row_shift(lv.nx);
         lv.L.kx = g.dt / (2.0 * lv.hx);
         lv.L.ky = g.dim == 2 ? g.dt / (2.0 * lv.hy) : 0.0;
         lv.L.a = 1.0 + g.c * g.dt / lv.hx;
@@ -261,6 +265,17 @@ struct Gate {
     const double* dtau_dev;
     const int* active;
 };
+
+// Gate of a single operation outside a time step: the plan's always-live
+// control, with its pseudo-time step set to `dtau` (stream-ordered).
+Gate fixed_gate(m1_plan& P, double dtau)
+{
+    m1::Ctrl fix{};
+    fix.active = 1;
+    fix.dtau = dtau;
+    m1::launch_ctrl_init(P.st, P.dfix, fix);
+    return Gate{dtau, &P.dfix->dtau, &P.dfix->active};
+}
 
 // nu finest-level sweeps.  With `control` the first sweep also reduces the
 // residual norm of its input (the previous cycle's result) and the cycle
@@ -470,7 +485,7 @@ void mx_vcycle(m1_plan& P, Soa& cur64, Soa& other64, const Gate& G, bool control
 // and, after a sync, the host.
 m1_status fine_norm(m1_plan& P, const Soa& v, Soa r_out, double* out, double sgn = -1.0)
 {
-    m1::launch_apply(P.st, P.dim, P.ph, P.lev[0].L, cs(v), cs(P.b), sgn, r_out, P.partials, nullptr);
+    m1::launch_apply(P.st, P.dim, P.ph, P.lev[0].L, cs(v), cs(P.b), sgn, r_out, P.partials, &P.dfix->active);
     m1::launch_norm_finalize(P.st, P.partials, P.npart, P.dscal);
     hipError_t e = hipMemcpyAsync(P.hpin, P.dscal, sizeof(double), hipMemcpyDeviceToHost, P.st);
     if (e != hipSuccess) return M1_ERR_DEVICE;
@@ -640,6 +655,12 @@ m1_status m1_plan_create(const m1_grid* g, const m1_params* p, const m1_opacity*
 
     // opacity validation and the coarse opacity hierarchy
     const int64_t n0 = P->lev[0].n;
+    {
+        m1::Ctrl fix{};
+        fix.active = 1;
+        fix.dtau = P->params.dtau_im0;
+        m1::launch_ctrl_init(P->st, P->dfix, fix);
+    }
     m1_status st = hip_status(hipMemsetAsync(P->dbad, 0xff, sizeof(unsigned long long), P->st));
     if (st == M1_OK) {
         m1::launch_check_sigma(P->st, n0, op->sigma_a, op->sigma_s, P->dbad);
@@ -655,7 +676,7 @@ m1_status m1_plan_create(const m1_grid* g, const m1_params* p, const m1_opacity*
         F.out[0] = P->lev[l].sa;
         F.out[1] = P->lev[l].ss;
         F.n = 2;
-        m1::launch_restrict(P->st, P->dim, P->lev[l - 1].nx, P->lev[l - 1].ny, P->px, P->py, F, nullptr);
+        m1::launch_restrict(P->st, P->dim, P->lev[l - 1].nx, P->lev[l - 1].ny, P->px, P->py, F, &P->dfix->active);
         st = last_launch();
     }
     for (int l = 0; st == M1_OK && P->mixed && l < P->L; ++l) {
@@ -713,13 +734,13 @@ m1_status m1_vcycle(m1_plan* P, m1_state* v, const m1_state* vn, double dtau)
     Soa user = to_soa(v), cur = user, other = P->tmp;
     if (P->mixed) {
         Soa32 pend{};
-        mx_vcycle(*P, cur, other, Gate{dtau, nullptr, nullptr}, false, true, pend);
+        mx_vcycle(*P, cur, other, fixed_gate(*P, dtau), false, true, pend);
         // apply the correction: the state is now in tmp; write the update back to v
         m1::launch_mx_resid(P->st, P->dim, P->ph, P->lev[0].L, P->params.eta, cs(cur), cs(pend), cs(P->b), user,
                             P->base32, P->r32, nullptr, nullptr);
         return last_launch();
     }
-    vcycle_impl(*P, cur, other, Gate{dtau, nullptr, nullptr});
+    vcycle_impl(*P, cur, other, fixed_gate(*P, dtau));
     if (!same(cur, user)) m1::launch_copy(P->st, P->dim, P->lev[0].n, cs(cur), user);
     return last_launch();
 }
@@ -850,7 +871,7 @@ m1_status m1_apply_A(m1_plan* P, int32_t level, const m1_state* v, m1_state* out
 {
     if (!P || level < 0 || level >= P->L || !valid_level_state(P, v) || !valid_level_state(P, out)) return M1_ERR_ARG;
     m1::launch_apply(P->st, P->dim, P->ph, P->lev[level].L, cs(to_soa(v)), CSoa{}, 1.0, to_soa(out), nullptr,
-                     nullptr);
+                     &P->dfix->active);
     return last_launch();
 }
 
@@ -859,7 +880,7 @@ m1_status m1_sweep(m1_plan* P, const m1_state* b, const m1_state* v_in, m1_state
     if (!P || !valid_state(P, b) || !valid_state(P, v_in) || !valid_state(P, v_out) || v_in->E == v_out->E)
         return M1_ERR_ARG;
     m1::launch_relax(P->st, P->dim, P->ph, P->lev[0].L, cs(to_soa(b)), nullptr, 0.0, 1.0, P->params.omega,
-                     cs(to_soa(v_in)), to_soa(v_out), nullptr, nullptr);
+                     cs(to_soa(v_in)), to_soa(v_out), nullptr, &P->dfix->active);
     return last_launch();
 }
 
@@ -870,8 +891,9 @@ m1_status m1_pseudo_step(m1_plan* P, int32_t level, double dtau, const m1_state*
         !valid_level_state(P, u_in) || !valid_level_state(P, u_out) || u_in->E == u_out->E)
         return M1_ERR_ARG;
     if (P->params.nu_l != 1) return M1_ERR_ARG;  // the single-operation entry point fuses exactly one sweep
+    const Gate G = fixed_gate(*P, dtau);
     m1::launch_pseudo(P->st, P->dim, P->ph, P->lev[level].L, to_soa(const_cast<m1_state*>(f)), cs(to_soa(u_in)),
-                      to_soa(u_out), dtau, nullptr, P->reach, P->params.pseudo_local, 0, Soa{}, nullptr, nullptr);
+                      to_soa(u_out), dtau, G.dtau_dev, P->reach, P->params.pseudo_local, 0, Soa{}, nullptr, G.active);
     return last_launch();
 }
 
@@ -881,7 +903,7 @@ m1_status m1_restrict(m1_plan* P, int32_t level, const m1_state* fine, m1_state*
         return M1_ERR_ARG;
     const LevelBuf& f = P->lev[level];
     m1::launch_restrict(P->st, P->dim, f.nx, f.ny, P->px, P->py,
-                        fields2(to_soa(fine), Soa{}, to_soa(coarse), Soa{}, P->dim), nullptr);
+                        fields2(to_soa(fine), Soa{}, to_soa(coarse), Soa{}, P->dim), &P->dfix->active);
     return last_launch();
 }
 
@@ -893,7 +915,7 @@ m1_status m1_prolong_project(m1_plan* P, int32_t level, const m1_state* u, const
         return M1_ERR_ARG;
     const LevelBuf& f = P->lev[level];
     m1::launch_prolong_project(P->st, P->dim, P->ph, f.nx, f.ny, P->px, P->py, P->params.eta, cs(to_soa(u)),
-                               cs(to_soa(uc)), cs(to_soa(vc)), to_soa(out), nullptr);
+                               cs(to_soa(uc)), cs(to_soa(vc)), to_soa(out), &P->dfix->active);
     return last_launch();
 }
 

@@ -1,17 +1,11 @@
 // m1_cells.hpp -- per-cell bodies of the FP64 cycle operations, shared by the
 // single-problem grid kernels (m1_kernels.hip) and the batched kernels
-// (m1_batch.hip), plus the body of the single-workgroup tail.
+// (same file), plus the body of the single-workgroup tail.
 #pragma once
 
 #include "m1_internal.hpp"
 
 namespace m1 {
-
-__device__ __forceinline__ void ij_of(int nx, int64_t k, int& i, int& j)
-{
-    j = (int)(k / nx);
-    i = (int)(k - (int64_t)j * nx);
-}
 
 // ===========================================================================
 // Per-cell bodies
@@ -25,20 +19,20 @@ __device__ __forceinline__ void ij_of(int nx, int64_t k, int& i, int& j)
 template <int DIM, bool NORM = false>
 __device__ __forceinline__ double relax_cell(const Phys& ph, const Lvl& L, const CSoa& rhs, const double* gcell,
                                              double beta, double gamma, double omega, const CSoa& u, const Soa& out,
-                                             int64_t k, int i, int j)
+                                             uint32_t k, int i, int j)
 {
     double S0, S1, S2;
     offdiag<DIM>(ph, L, u, i, j, k, S0, S1, S2);
-    const double g = gcell ? gcell[k] : gamma;
-    const double BE = fma(g, S0, rhs.E[k]);
-    const double BFx = fma(g, S1, rhs.Fx[k]);
-    const double BFy = (DIM == 2) ? fma(g, S2, rhs.Fy[k]) : 0.0;
-    const double BT = rhs.T[k];
-    const double ka = L.cdt * L.sa[k], ks = L.cdt * L.ss[k];
-    const double Tin = u.T[k];
+    const double g = gcell ? ld(gcell, k) : gamma;
+    const double BE = fma(g, S0, ld(rhs.E, k));
+    const double BFx = fma(g, S1, ld(rhs.Fx, k));
+    const double BFy = (DIM == 2) ? fma(g, S2, ld(rhs.Fy, k)) : 0.0;
+    const double BT = ld(rhs.T, k);
+    const double ka = L.cdt * ld(L.sa, k), ks = L.cdt * ld(L.ss, k);
+    const double Tin = ld(u.T, k);
     double q = 0.0;
     if (NORM) {
-        const double Ein = u.E[k], Fxin = u.Fx[k], Fyin = (DIM == 2) ? u.Fy[k] : 0.0;
+        const double Ein = ld(u.E, k), Fxin = ld(u.Fx, k), Fyin = (DIM == 2) ? ld(u.Fy, k) : 0.0;
         const double T2 = Tin * Tin;
         const double ex = ka * fma(-ph.a_r * T2, T2, Ein);  // ka (E - a_r T^4)
         const double dF = L.a + ka + ks;
@@ -51,19 +45,19 @@ __device__ __forceinline__ double relax_cell(const Phys& ph, const Lvl& L, const
     double E, Fx, Fy, T;
     local_solve(beta, g, L.a, ka, ks, ph.c_v, ph.a_r, BE, BFx, BFy, BT, Tin, E, Fx, Fy, T);
     if (omega != 1.0) {
-        const double Ein = u.E[k], Fxin = u.Fx[k];
+        const double Ein = ld(u.E, k), Fxin = ld(u.Fx, k);
         E = fma(omega, E - Ein, Ein);
         Fx = fma(omega, Fx - Fxin, Fxin);
         if (DIM == 2) {
-            const double Fyin = u.Fy[k];
+            const double Fyin = ld(u.Fy, k);
             Fy = fma(omega, Fy - Fyin, Fyin);
         }
         T = fma(omega, T - Tin, Tin);
     }
-    out.E[k] = E;
-    out.Fx[k] = Fx;
-    if (DIM == 2) out.Fy[k] = Fy;
-    out.T[k] = T;
+    st(out.E, k, E);
+    st(out.Fx, k, Fx);
+    if (DIM == 2) st(out.Fy, k, Fy);
+    st(out.T, k, T);
     return q;
 }
 
@@ -79,13 +73,13 @@ __device__ __forceinline__ double relax_cell(const Phys& ph, const Lvl& L, const
 template <int DIM, bool FIRST = false>
 __device__ __forceinline__ void pseudo_cell(const Phys& ph, const Lvl& L, const CSoa& fin, const Soa& fout,
                                             const CSoa& u, const Soa& out, double dtau, double reach, int local,
-                                            const Soa& rs, double* gs, int64_t k, int i, int j)
+                                            const Soa& rs, double* gs, uint32_t k, int i, int j, bool live = true)
 {
-    const double uE = u.E[k], uFx = u.Fx[k], uFy = (DIM == 2) ? u.Fy[k] : 0.0, uT = u.T[k];
+    const double uE = ld(u.E, k), uFx = ld(u.Fx, k), uFy = (DIM == 2) ? ld(u.Fy, k) : 0.0, uT = ld(u.T, k);
     double S0, S1, S2;
     offdiag<DIM>(ph, L, u, i, j, k, S0, S1, S2);
-    const double ka = L.cdt * L.sa[k], ks = L.cdt * L.ss[k];
-    double fE = fin.E[k], fFx = fin.Fx[k], fFy = (DIM == 2) ? fin.Fy[k] : 0.0, fT = fin.T[k];
+    const double ka = L.cdt * ld(L.sa, k), ks = L.cdt * ld(L.ss, k);
+    double fE = ld(fin.E, k), fFx = ld(fin.Fx, k), fFy = (DIM == 2) ? ld(fin.Fy, k) : 0.0, fT = ld(fin.T, k);
     if (FIRST) {
         const double T2 = uT * uT;
         const double ex = ka * fma(-ph.a_r * T2, T2, uE);
@@ -94,10 +88,12 @@ __device__ __forceinline__ void pseudo_cell(const Phys& ph, const Lvl& L, const 
         fFx += fma(dF, uFx, -S1);
         fFy += fma(dF, uFy, -S2);
         fT += fma(ph.c_v, uT, -ex);
-        fout.E[k] = fE;
-        fout.Fx[k] = fFx;
-        if (DIM == 2) fout.Fy[k] = fFy;
-        fout.T[k] = fT;
+        if (live) {
+            st(fout.E, k, fE);
+            st(fout.Fx, k, fFx);
+            if (DIM == 2) st(fout.Fy, k, fFy);
+            st(fout.T, k, fT);
+        }
     }
     const double sE = fE, sFx = fFx, sFy = fFy, sT = fT / ph.c_v;
     const double ts = ray_len(ph.c2, uE, uFx, uFy, uT, sE, sFx, sFy, sT);
@@ -108,16 +104,17 @@ __device__ __forceinline__ void pseudo_cell(const Phys& ph, const Lvl& L, const 
     double E, Fx, Fy, T;
     local_solve(1.0, g, L.a, ka, ks, ph.c_v, ph.a_r, fma(g, S0, tE), fma(g, S1, tFx), fma(g, S2, tFy), tT, uT, E, Fx,
                 Fy, T);
-    out.E[k] = E;
-    out.Fx[k] = Fx;
-    if (DIM == 2) out.Fy[k] = Fy;
-    out.T[k] = T;
+    if (!live) return;
+    st(out.E, k, E);
+    st(out.Fx, k, Fx);
+    if (DIM == 2) st(out.Fy, k, Fy);
+    st(out.T, k, T);
     if (gs) {
-        rs.E[k] = tE;
-        rs.Fx[k] = tFx;
-        if (DIM == 2) rs.Fy[k] = tFy;
-        rs.T[k] = tT;
-        gs[k] = g;
+        st(rs.E, k, tE);
+        st(rs.Fx, k, tFx);
+        if (DIM == 2) st(rs.Fy, k, tFy);
+        st(rs.T, k, tT);
+        st(gs, k, g);
     }
 }
 
@@ -125,12 +122,12 @@ __device__ __forceinline__ void pseudo_cell(const Phys& ph, const Lvl& L, const 
 // is set.  Returns r_E^2 + (r_F/c)^2 + r_T^2 of the result (norm contribution).
 template <int DIM>
 __device__ __forceinline__ double apply_cell(const Phys& ph, const Lvl& L, const CSoa& v, const CSoa& X, double sgn,
-                                             const Soa& out, int64_t k, int i, int j)
+                                             const Soa& out, uint32_t k, int i, int j, bool live = true)
 {
     double S0, S1, S2;
     offdiag<DIM>(ph, L, v, i, j, k, S0, S1, S2);
-    const double E = v.E[k], Fx = v.Fx[k], Fy = (DIM == 2) ? v.Fy[k] : 0.0, T = v.T[k];
-    const double ka = L.cdt * L.sa[k], ks = L.cdt * L.ss[k];
+    const double E = ld(v.E, k), Fx = ld(v.Fx, k), Fy = (DIM == 2) ? ld(v.Fy, k) : 0.0, T = ld(v.T, k);
+    const double ka = L.cdt * ld(L.sa, k), ks = L.cdt * ld(L.ss, k);
     const double T2 = T * T;
     const double ex = ka * fma(-ph.a_r * T2, T2, E);  // ka (E - a_r T^4)
     const double dF = L.a + ka + ks;
@@ -139,16 +136,16 @@ __device__ __forceinline__ double apply_cell(const Phys& ph, const Lvl& L, const
     double rFy = sgn * fma(dF, Fy, -S2);
     double rT = sgn * fma(ph.c_v, T, -ex);
     if (X.E) {
-        rE += X.E[k];
-        rFx += X.Fx[k];
-        if (DIM == 2) rFy += X.Fy[k];
-        rT += X.T[k];
+        rE += ld(X.E, k);
+        rFx += ld(X.Fx, k);
+        if (DIM == 2) rFy += ld(X.Fy, k);
+        rT += ld(X.T, k);
     }
-    if (out.E) {
-        out.E[k] = rE;
-        out.Fx[k] = rFx;
-        if (DIM == 2) out.Fy[k] = rFy;
-        out.T[k] = rT;
+    if (out.E && live) {
+        st(out.E, k, rE);
+        st(out.Fx, k, rFx);
+        if (DIM == 2) st(out.Fy, k, rFy);
+        st(out.T, k, rT);
     }
     const double ic = 1.0 / ph.c;
     const double fx = rFx * ic, fy = (DIM == 2) ? rFy * ic : 0.0;
@@ -189,12 +186,12 @@ __device__ __forceinline__ void rweights(int I, int nf, bool periodic, int idx[3
 // gathered first (32-bit offsets from the per-field bases) so that every load
 // is in flight before the first use, then summed.
 template <int DIM, int NF>
-__device__ __forceinline__ void restrict_cell(int nxf, int nyf, int px, int py, const double* const* in,
-                                              double* const* out, int64_t k)
+__device__ __forceinline__ void restrict_cell(int nxf, int nyf, int shf, int px, int py, const double* const* in,
+                                              double* const* out, uint32_t k, bool live = true)
 {
     const int nxc = nxf / 2;
     int I, J;
-    ij_of(nxc, k, I, J);
+    ij_of(nxc, shf > 0 ? shf - 1 : -1, k, I, J);
     int ix[3], iy[3] = {0, 0, 0};
     double wx[3], wy[3] = {1.0, 0.0, 0.0};
     rweights(I, nxf, px != 0, ix, wx);
@@ -209,7 +206,7 @@ __device__ __forceinline__ void restrict_cell(int nxf, int nyf, int px, int py, 
 #pragma unroll
     for (int q = 0; q < NF; ++q)
 #pragma unroll
-        for (int m = 0; m < NB * 3; ++m) val[q][m] = in[q][off[m]];
+        for (int m = 0; m < NB * 3; ++m) val[q][m] = ld(in[q], off[m]);
 #pragma unroll
     for (int q = 0; q < NF; ++q) {
         double s = 0.0;
@@ -218,7 +215,7 @@ __device__ __forceinline__ void restrict_cell(int nxf, int nyf, int px, int py, 
             const double t = fma(wx[2], val[q][b * 3 + 2], fma(wx[1], val[q][b * 3 + 1], wx[0] * val[q][b * 3]));
             s = fma(wy[b], t, s);
         }
-        out[q][k] = s;
+        if (live) st(out[q], k, s);
     }
 }
 
@@ -253,11 +250,12 @@ __device__ __forceinline__ void pweights(int i, int nc, bool periodic, int idx[2
 // Correction with admissibility (eq. prolongatedSol):
 //   w = u + P(uc - vc); out = w if admissible, else u + eta min(tau*(u, w - u), 1) (w - u).
 template <int DIM>
-__device__ __forceinline__ void prolong_cell(const Phys& ph, int nx, int ny, int px, int py, double eta, const CSoa& u,
-                                             const CSoa& uc, const CSoa& vc, const Soa& out, int64_t k)
+__device__ __forceinline__ void prolong_cell(const Phys& ph, int nx, int ny, int sh, int px, int py, double eta,
+                                             const CSoa& u, const CSoa& uc, const CSoa& vc, const Soa& out, uint32_t k,
+                                             bool live = true)
 {
     int i, j;
-    ij_of(nx, k, i, j);
+    ij_of(nx, sh, k, i, j);
     const int nxc = nx / 2, nyc = (DIM == 2) ? ny / 2 : 1;
     int ix[2], iy[2] = {0, 0};
     double wx[2], wy[2] = {1.0, 0.0};
@@ -269,15 +267,15 @@ __device__ __forceinline__ void prolong_cell(const Phys& ph, int nx, int ny, int
     for (int b = 0; b < NB; ++b) {
 #pragma unroll
         for (int a = 0; a < 2; ++a) {
-            const int64_t kc = (int64_t)iy[b] * nxc + ix[a];
+            const uint32_t kc = (uint32_t)iy[b] * (uint32_t)nxc + (uint32_t)ix[a];
             const double w = wx[a] * wy[b];
-            e0 = fma(w, uc.E[kc] - vc.E[kc], e0);
-            e1 = fma(w, uc.Fx[kc] - vc.Fx[kc], e1);
-            if (DIM == 2) e2 = fma(w, uc.Fy[kc] - vc.Fy[kc], e2);
-            e3 = fma(w, uc.T[kc] - vc.T[kc], e3);
+            e0 = fma(w, ld(uc.E, kc) - ld(vc.E, kc), e0);
+            e1 = fma(w, ld(uc.Fx, kc) - ld(vc.Fx, kc), e1);
+            if (DIM == 2) e2 = fma(w, ld(uc.Fy, kc) - ld(vc.Fy, kc), e2);
+            e3 = fma(w, ld(uc.T, kc) - ld(vc.T, kc), e3);
         }
     }
-    const double uE = u.E[k], uFx = u.Fx[k], uFy = (DIM == 2) ? u.Fy[k] : 0.0, uT = u.T[k];
+    const double uE = ld(u.E, k), uFx = ld(u.Fx, k), uFy = (DIM == 2) ? ld(u.Fy, k) : 0.0, uT = ld(u.T, k);
     double wE = uE + e0, wFx = uFx + e1, wFy = uFy + e2, wT = uT + e3;
     if (!admissible(ph.c2, wE, wFx, wFy, wT)) {
         const double th = eta * fmin(ray_len(ph.c2, uE, uFx, uFy, uT, e0, e1, e2, e3), 1.0);
@@ -286,10 +284,11 @@ __device__ __forceinline__ void prolong_cell(const Phys& ph, int nx, int ny, int
         wFy = fma(th, e2, uFy);
         wT = fma(th, e3, uT);
     }
-    out.E[k] = wE;
-    out.Fx[k] = wFx;
-    if (DIM == 2) out.Fy[k] = wFy;
-    out.T[k] = wT;
+    if (!live) return;
+    st(out.E, k, wE);
+    st(out.Fx, k, wFx);
+    if (DIM == 2) st(out.Fy, k, wFy);
+    st(out.T, k, wT);
 }
 
 
@@ -358,12 +357,12 @@ __device__ __forceinline__ void block_partial(double q, double* dst)
 template <int DIM>
 __device__ __forceinline__ Soa tail_pseudo(const TailArgs& A, const TailLevel& T, double dtau, Soa in, bool first)
 {
-    const int64_t n = (int64_t)T.L.nx * T.L.ny;
+    const uint32_t n = (uint32_t)T.L.nx * (uint32_t)T.L.ny;
     for (int m = 0; m < A.pseudo_steps; ++m) {
         const Soa out = (in.E == T.u.E) ? T.u2 : T.u;
-        for (int64_t k = threadIdx.x; k < n; k += blockDim.x) {
+        for (uint32_t k = threadIdx.x; k < n; k += blockDim.x) {
             int i, j;
-            ij_of(T.L.nx, k, i, j);
+            ij_of(T.L.nx, T.L.sh, k, i, j);
             if (first && m == 0)
                 pseudo_cell<DIM, true>(A.ph, T.L, cs(T.f), T.f, cs(in), out, dtau, A.reach, A.local, Soa{}, nullptr,
                                        k, i, j);
@@ -388,7 +387,7 @@ __device__ __forceinline__ void tail_body(const TailArgs& A, double dt)
     };
     for (int l = A.lt; l < A.L; ++l) {
         const TailLevel& T = A.lev[l];
-        const int64_t n = (int64_t)T.L.nx * T.L.ny;
+        const uint32_t n = (uint32_t)T.L.nx * (uint32_t)T.L.ny;
         if (l > A.lt) {
             const TailLevel& F = A.lev[l - 1];
             const Soa uf = cur(l - 1);
@@ -404,16 +403,16 @@ __device__ __forceinline__ void tail_body(const TailArgs& A, double dt)
                 out[4] = out[5];
                 out[5] = out[7];
             }
-            for (int64_t k = threadIdx.x; k < n; k += blockDim.x)
-                restrict_cell<DIM, DIM == 2 ? 8 : 6>(F.L.nx, F.L.ny, A.px, A.py, in, out, k);
+            for (uint32_t k = threadIdx.x; k < n; k += blockDim.x)
+                restrict_cell<DIM, DIM == 2 ? 8 : 6>(F.L.nx, F.L.ny, F.L.sh, A.px, A.py, in, out, k);
             __syncthreads();
         }
         set(l, tail_pseudo<DIM>(A, T, dt, T.v, true));  // forms f = A(v) + R(rbar) on the way
         if (l < A.L - 1) {
             const Soa u = cur(l);
-            for (int64_t k = threadIdx.x; k < n; k += blockDim.x) {  // rbar = f - A(u)
+            for (uint32_t k = threadIdx.x; k < n; k += blockDim.x) {  // rbar = f - A(u)
                 int i, j;
-                ij_of(T.L.nx, k, i, j);
+                ij_of(T.L.nx, T.L.sh, k, i, j);
                 apply_cell<DIM>(A.ph, T.L, cs(u), cs(T.f), -1.0, T.rb, k, i, j);
             }
             __syncthreads();
@@ -422,22 +421,22 @@ __device__ __forceinline__ void tail_body(const TailArgs& A, double dt)
     for (int l = A.L - 2; l >= A.lt; --l) {
         const TailLevel& T = A.lev[l];
         const TailLevel& C = A.lev[l + 1];
-        const int64_t n = (int64_t)T.L.nx * T.L.ny;
+        const uint32_t n = (uint32_t)T.L.nx * (uint32_t)T.L.ny;
         const Soa u = cur(l), uc = cur(l + 1);
-        for (int64_t k = threadIdx.x; k < n; k += blockDim.x)
-            prolong_cell<DIM>(A.ph, T.L.nx, T.L.ny, A.px, A.py, A.eta, cs(u), cs(uc), cs(C.v), u, k);
+        for (uint32_t k = threadIdx.x; k < n; k += blockDim.x)
+            prolong_cell<DIM>(A.ph, T.L.nx, T.L.ny, T.L.sh, A.px, A.py, A.eta, cs(u), cs(uc), cs(C.v), u, k);
         __syncthreads();
         set(l, tail_pseudo<DIM>(A, T, dt, u, false));
     }
     const TailLevel& T = A.lev[A.lt];
     const Soa res = cur(A.lt);
     if (res.E != T.u.E) {
-        const int64_t n = (int64_t)T.L.nx * T.L.ny;
-        for (int64_t k = threadIdx.x; k < n; k += blockDim.x) {
-            T.u.E[k] = res.E[k];
-            T.u.Fx[k] = res.Fx[k];
-            if (DIM == 2) T.u.Fy[k] = res.Fy[k];
-            T.u.T[k] = res.T[k];
+        const uint32_t n = (uint32_t)T.L.nx * (uint32_t)T.L.ny;
+        for (uint32_t k = threadIdx.x; k < n; k += blockDim.x) {
+            st(T.u.E, k, ld(res.E, k));
+            st(T.u.Fx, k, ld(res.Fx, k));
+            if (DIM == 2) st(T.u.Fy, k, ld(res.Fy, k));
+            st(T.u.T, k, ld(res.T, k));
         }
     }
 }

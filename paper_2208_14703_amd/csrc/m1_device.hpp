@@ -22,9 +22,11 @@ struct Phys {
     double bcE[4], bcFx[4], bcFy[4];
 };
 
-// One grid level as seen by a kernel.
+// One grid level as seen by a kernel.  Cells are numbered k = j nx + i in
+// 32 bits (a level holds at most 2^29 cells, so byte offsets fit too).
 struct Lvl {
     int nx, ny;
+    int sh;         // log2(nx) when nx is a power of two, else -1
     double kx, ky;  // dt / (2 hx), dt / (2 hy); ky = 0 in 1-D
     double a;       // 1 + c dt/hx + c dt/hy
     double cdt;     // c dt  (kappa = c dt sigma)
@@ -46,6 +48,43 @@ struct CSoa {
 };
 __host__ __device__ inline CSoa cs(const Soa& s) { return CSoa{s.E, s.Fx, s.Fy, s.T}; }
 
+// Field element k as the field's (wave-uniform) base plus a 32-bit byte
+// offset: the scalar-base addressing form of the global loads and stores, one
+// offset register shared by every field at the same cell.
+__device__ __forceinline__ double ld(const double* p, uint32_t k)
+{
+    return *reinterpret_cast<const double*>(reinterpret_cast<const char*>(p) + (k << 3));
+}
+__device__ __forceinline__ void st(double* p, uint32_t k, double x)
+{
+    *reinterpret_cast<double*>(reinterpret_cast<char*>(p) + (k << 3)) = x;
+}
+
+// (i, j) of cell k: shift and mask for power-of-two rows, else a 32-bit divide.
+__device__ __forceinline__ void ij_of(int nx, int sh, uint32_t k, int& i, int& j)
+{
+    if (sh >= 0) {
+        j = (int)(k >> sh);
+        i = (int)(k & (uint32_t)(nx - 1));
+    } else {
+        const uint32_t q = k / (uint32_t)nx;
+        j = (int)q;
+        i = (int)(k - q * (uint32_t)nx);
+    }
+}
+
+// 1/x for positive finite x: the hardware estimate refined by two
+// Newton-Raphson steps y <- y + y (1 - x y), each squaring the relative error
+// (about 1 ulp at the end; not the correctly rounded quotient).
+__device__ __forceinline__ double rcp64(double x)
+{
+    double y = __builtin_amdgcn_rcp(x);
+    double e = fma(-x, y, 1.0);
+    y = fma(y, e, y);
+    e = fma(-x, y, 1.0);
+    return fma(y, e, y);
+}
+
 // ---------------------------------------------------------------------------
 // M1 closure (Sect. 2.1) arranged for the directional fluxes.  With
 //   r = 1 / ((2 + s) E),  s = sqrt(4 - 3 f^2),  f = |F| / (cE),
@@ -62,7 +101,7 @@ __device__ __forceinline__ C2P closure(double c, double c2, double E, double Fx,
     const double F2 = fma(Fx, Fx, Fy * Fy);
     const double c2E2 = c2 * E * E;
     const double root = sqrt(fmax(fma(4.0, c2E2, -3.0 * F2), c2E2));
-    const double r = c / fma(2.0 * c, E, root);
+    const double r = c * rcp64(fma(2.0 * c, E, root));
     C2P o;
     o.iso = fma(-F2, r, c2 * E * (1.0 / 3.0));
     o.r3 = 3.0 * r;
@@ -97,41 +136,43 @@ __device__ __forceinline__ void add_y(double k, double c, double c2, double sgn,
 // Neighbour (ghost) state for side `side` (0 x-, 1 x+, 2 y-, 3 y+).  `inside`
 // tells whether the neighbour index kn is in the domain; otherwise the side's
 // boundary rule applies (kn is then the periodic wrap, kc the cell itself).
+// Branch-free: the load always happens (from kn or kc) and the boundary rule
+// is applied by selects, so the four neighbours' loads are all in flight at once.
 template <int DIM>
-__device__ __forceinline__ void nb_state(const Phys& ph, int side, bool inside, int64_t kn, int64_t kc, const CSoa& v,
-                                         double& e, double& fx, double& fy)
+__device__ __forceinline__ void nb_state(const Phys& ph, int side, bool inside, uint32_t kn, uint32_t kc,
+                                         const CSoa& v, double& e, double& fx, double& fy)
 {
-    int64_t k = kn;
-    int kind = inside ? BC_PERIODIC : ph.bc[side];
-    if (kind == BC_DIRICHLET) {
-        e = ph.bcE[side];
-        fx = ph.bcFx[side];
-        fy = ph.bcFy[side];
-        return;
-    }
-    if (kind != BC_PERIODIC) k = kc;
-    e = v.E[k];
-    fx = v.Fx[k];
-    fy = (DIM == 2) ? v.Fy[k] : 0.0;
-    if (kind == BC_REFLECTIVE) {
-        if (side < 2) fx = -fx;
-        else fy = -fy;
-    }
+    const int kind = ph.bc[side];
+    const bool ghost = !inside && kind != BC_PERIODIC;
+    const uint32_t k = ghost ? kc : kn;
+    const double le = ld(v.E, k), lfx = ld(v.Fx, k), lfy = (DIM == 2) ? ld(v.Fy, k) : 0.0;
+    // keep = 1 (own or wrapped value) or 0 (Dirichlet wall value); sx, sy = -1
+    // flip the normal flux at a reflective wall.  The loaded values are always
+    // used, so the compiler cannot sink the loads into per-lane branches; every
+    // product is exact (x 1, x 0 of a finite value, x -1).
+    const bool dir = ghost && kind == BC_DIRICHLET;
+    const bool flip = ghost && kind == BC_REFLECTIVE;
+    const double keep = dir ? 0.0 : 1.0;
+    const double sx = (flip && side < 2) ? -keep : keep, sy = (flip && side >= 2) ? -keep : keep;
+    e = fma(keep, le, dir ? ph.bcE[side] : 0.0);
+    fx = fma(sx, lfx, dir ? ph.bcFx[side] : 0.0);
+    fy = fma(sy, lfy, dir ? ph.bcFy[side] : 0.0);
 }
 
 // Off-diagonal sum S = L_x(v_{i-1}) + R_x(v_{i+1}) [+ L_y(v_{j-1}) + R_y(v_{j+1})] of cell (i,j).
 template <int DIM>
-__device__ __forceinline__ void offdiag(const Phys& ph, const Lvl& L, const CSoa& v, int i, int j, int64_t k,
+__device__ __forceinline__ void offdiag(const Phys& ph, const Lvl& L, const CSoa& v, int i, int j, uint32_t k,
                                         double& S0, double& S1, double& S2)
 {
     double e, fx, fy;
     S0 = S1 = S2 = 0.0;
-    nb_state<DIM>(ph, 0, i > 0, i > 0 ? k - 1 : k + (L.nx - 1), k, v, e, fx, fy);
+    const uint32_t wx = (uint32_t)(L.nx - 1);
+    nb_state<DIM>(ph, 0, i > 0, i > 0 ? k - 1 : k + wx, k, v, e, fx, fy);
     add_x(L.kx, ph.c, ph.c2, +1.0, e, fx, fy, S0, S1, S2);
-    nb_state<DIM>(ph, 1, i < L.nx - 1, i < L.nx - 1 ? k + 1 : k - (L.nx - 1), k, v, e, fx, fy);
+    nb_state<DIM>(ph, 1, i < L.nx - 1, i < L.nx - 1 ? k + 1 : k - wx, k, v, e, fx, fy);
     add_x(L.kx, ph.c, ph.c2, -1.0, e, fx, fy, S0, S1, S2);
     if (DIM == 2) {
-        const int64_t nx = L.nx, wrap = (int64_t)(L.ny - 1) * nx;
+        const uint32_t nx = (uint32_t)L.nx, wrap = (uint32_t)(L.ny - 1) * nx;
         nb_state<DIM>(ph, 2, j > 0, j > 0 ? k - nx : k + wrap, k, v, e, fx, fy);
         add_y(L.ky, ph.c, ph.c2, +1.0, e, fx, fy, S0, S1, S2);
         nb_state<DIM>(ph, 3, j < L.ny - 1, j < L.ny - 1 ? k + nx : k - wrap, k, v, e, fx, fy);
@@ -153,12 +194,12 @@ __device__ __forceinline__ void local_solve(double beta, double gamma, double a,
                                             double& E, double& Fx, double& Fy, double& T)
 {
     const double dE = fma(gamma, a + ka, beta);
-    const double iF = 1.0 / fma(gamma, ks, dE);
+    const double iF = rcp64(fma(gamma, ks, dE));
     Fx = BFx * iF;
     Fy = BFy * iF;
     const double k = gamma * ka;
     const double cT = (beta + gamma) * cv;
-    const double idE = 1.0 / dE;
+    const double idE = rcp64(dE);
     if (k == 0.0) {
         T = BT / cT;
         E = BE * idE;
@@ -172,7 +213,7 @@ __device__ __forceinline__ void local_solve(double beta, double gamma, double a,
         const double t2 = t * t;
         const double g = fma(K * t2, t2, fma(cT, t, -Q));
         const double dg = fma(4.0 * K * t2, t, cT);
-        const double tn = fmin(t - g / dg, Tup);
+        const double tn = fmin(fma(-g, rcp64(dg), t), Tup);
         const bool done = fabs(tn - t) <= 1e-14 * tn;
         t = tn;
         if (done) break;

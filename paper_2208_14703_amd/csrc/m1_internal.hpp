@@ -7,6 +7,16 @@
 
 namespace m1 {
 
+// log2(nx) when nx is a power of two, else -1 (the row shift of Lvl::sh).
+inline int row_shift(int nx)
+{
+    if (nx < 1 || (nx & (nx - 1)) != 0) return -1;
+    int sh = 0;
+    while ((1 << sh) < nx) ++sh;
+    return sh;
+}
+
+
 constexpr int kMaxLevels = 24;
 
 // Up to 10 fields restricted by one launch (in[q] -> out[q]).

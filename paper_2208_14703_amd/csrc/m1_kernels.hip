@@ -8,9 +8,9 @@
 // bottom of the V-cycle (every level small enough for one workgroup) in a
 // single launch with block barriers between the phases.
 //
-// Cycle kernels take an optional device flag `active` (skip all work when it
-// is 0) and an optional device pseudo-time step `dtau_dev`, so that whole
-// V-cycles can be enqueued ahead of the host's convergence check.
+// Cycle kernels take a device flag `active` (no effect when it is 0) and a
+// device pseudo-time step `dtau_dev` (both always valid pointers), so that
+// whole V-cycles can be enqueued ahead of the host's convergence check.
 #include <algorithm>
 #include <cfloat>
 
@@ -27,17 +27,31 @@ constexpr int kStepThreads = 1024;
 
 static inline unsigned nblocks(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
 
-__device__ __forceinline__ bool inactive(const int* active) { return active && *active == 0; }
 
+// Level kernels other than the finest sweep read the stop flag (and the
+// pseudo-time step) together with their data and gate only their stores on
+// it: on the small coarse levels a flag test ahead of the loads would add a
+// memory round trip to every launch.  (Kernels of cycles enqueued past
+// convergence then compute but write nothing.)  `active` and `dtau_dev` are
+// always valid device pointers here.  They are read through a per-lane offset
+// of 0 that the compiler cannot see as uniform, which keeps them ordinary
+// vector loads: these complete in order with the data loads, so their waits
+// land at the first use and not ahead of the data loads.
+__device__ __forceinline__ uint32_t lane_zero()
+{
+    uint32_t z = 0;
+    asm("" : "+v"(z));
+    return z;
+}
 
 // ===========================================================================
 // Grid kernels
 // ===========================================================================
-__device__ __forceinline__ bool cell_of(const Lvl& L, int64_t& k, int& i, int& j)
+__device__ __forceinline__ bool cell_of(const Lvl& L, uint32_t& k, int& i, int& j)
 {
-    k = xcd_block() * kBlock + threadIdx.x;
-    if (k >= (int64_t)L.nx * L.ny) return false;
-    ij_of(L.nx, k, i, j);
+    k = (uint32_t)xcd_block() * kBlock + threadIdx.x;
+    if (k >= (uint32_t)L.nx * (uint32_t)L.ny) return false;
+    ij_of(L.nx, L.sh, k, i, j);
     return true;
 }
 
@@ -48,8 +62,8 @@ __global__ __launch_bounds__(kBlock) void k_relax(Phys ph, Lvl L, CSoa rhs, cons
                                                   double beta, double gamma, double omega, CSoa u, Soa out,
                                                   double* __restrict__ partials, const int* __restrict__ active)
 {
-    if (inactive(active)) return;
-    int64_t k;
+    if (*active == 0) return;
+    uint32_t k;
     int i, j;
     const bool in = cell_of(L, k, i, j);
     if (!partials) {
@@ -68,25 +82,26 @@ __global__ __launch_bounds__(kBlock) void k_pseudo(Phys ph, Lvl L, Soa f, CSoa u
                                                    int first, Soa rs, double* __restrict__ gs,
                                                    const int* __restrict__ active)
 {
-    const double dt = dtau_dev ? *dtau_dev : dtau;  // both control loads in flight together
-    if (inactive(active)) return;
-    int64_t k;
+    const uint32_t z = lane_zero();
+    const double dt = dtau_dev[z];
+    const bool live = active[z] != 0;
+    uint32_t k;
     int i, j;
     if (!cell_of(L, k, i, j)) return;
-    if (first) pseudo_cell<DIM, true>(ph, L, cs(f), f, u, out, dt, reach, local, rs, gs, k, i, j);
-    else pseudo_cell<DIM, false>(ph, L, cs(f), f, u, out, dt, reach, local, rs, gs, k, i, j);
+    if (first) pseudo_cell<DIM, true>(ph, L, cs(f), f, u, out, dt, reach, local, rs, gs, k, i, j, live);
+    else pseudo_cell<DIM, false>(ph, L, cs(f), f, u, out, dt, reach, local, rs, gs, k, i, j, live);
 }
 
 template <int DIM>
 __global__ __launch_bounds__(kBlock) void k_apply(Phys ph, Lvl L, CSoa v, CSoa X, double sgn, Soa out,
                                                   double* __restrict__ partials, const int* __restrict__ active)
 {
-    if (inactive(active)) return;
-    int64_t k;
+    const bool live = active[lane_zero()] != 0;
+    uint32_t k;
     int i, j;
     double q = 0.0;
-    if (cell_of(L, k, i, j)) q = apply_cell<DIM>(ph, L, v, X, sgn, out, k, i, j);
-    if (partials) block_partial(q, partials + xcd_block());
+    if (cell_of(L, k, i, j)) q = apply_cell<DIM>(ph, L, v, X, sgn, out, k, i, j, live);
+    if (partials && live) block_partial(q, partials + xcd_block());
 }
 
 __global__ __launch_bounds__(1024) void k_norm_finalize(const double* __restrict__ partials, int n,
@@ -106,25 +121,25 @@ __global__ __launch_bounds__(1024) void k_norm_control(const double* __restrict_
 }
 
 template <int DIM, int NF>
-__global__ __launch_bounds__(kBlock) void k_restrict(int nxf, int nyf, int px, int py, Fields F,
+__global__ __launch_bounds__(kBlock) void k_restrict(int nxf, int nyf, int shf, int px, int py, Fields F,
                                                      const int* __restrict__ active)
 {
-    if (inactive(active)) return;
-    const int64_t nc = (int64_t)(nxf / 2) * ((DIM == 2) ? nyf / 2 : 1);
-    const int64_t k = xcd_block() * kBlock + threadIdx.x;
+    const bool live = active[lane_zero()] != 0;
+    const uint32_t nc = (uint32_t)(nxf / 2) * (uint32_t)((DIM == 2) ? nyf / 2 : 1);
+    const uint32_t k = (uint32_t)xcd_block() * kBlock + threadIdx.x;
     if (k >= nc) return;
-    restrict_cell<DIM, NF>(nxf, nyf, px, py, F.in, F.out, k);
+    restrict_cell<DIM, NF>(nxf, nyf, shf, px, py, F.in, F.out, k, live);
 }
 
 template <int DIM>
-__global__ __launch_bounds__(kBlock) void k_prolong_project(Phys ph, int nx, int ny, int px, int py, double eta,
-                                                            CSoa u, CSoa uc, CSoa vc, Soa out,
+__global__ __launch_bounds__(kBlock) void k_prolong_project(Phys ph, int nx, int ny, int sh, int px, int py,
+                                                            double eta, CSoa u, CSoa uc, CSoa vc, Soa out,
                                                             const int* __restrict__ active)
 {
-    if (inactive(active)) return;
-    const int64_t k = xcd_block() * kBlock + threadIdx.x;
-    if (k >= (int64_t)nx * ny) return;
-    prolong_cell<DIM>(ph, nx, ny, px, py, eta, u, uc, vc, out, k);
+    const bool live = active[lane_zero()] != 0;
+    const uint32_t k = (uint32_t)xcd_block() * kBlock + threadIdx.x;
+    if (k >= (uint32_t)nx * (uint32_t)ny) return;
+    prolong_cell<DIM>(ph, nx, ny, sh, px, py, eta, u, uc, vc, out, k, live);
 }
 
 template <int DIM>
@@ -132,8 +147,8 @@ __global__ __launch_bounds__(kTailThreads) void k_tail(const TailArgs* __restric
                                                        const double* __restrict__ dtau_dev,
                                                        const int* __restrict__ active)
 {
-    const double dt = dtau_dev ? *dtau_dev : dtau;
-    if (inactive(active)) return;
+    const double dt = *dtau_dev;
+    if (*active == 0) return;
     tail_body<DIM>(*Ap, dt);
 }
 
@@ -198,10 +213,10 @@ __device__ __forceinline__ const Soa& pick(const BSlot& s, int sel) { return sel
     for (int w = blockIdx.x; w < (nwl); w += gridDim.x) {                   \
         const uint32_t item = (wl)[w];                                      \
         const int p = (int)(item >> kTileBits);                             \
-        const int64_t tile = (int64_t)(item & ((1u << kTileBits) - 1u));    \
+        const uint32_t tile = item & ((1u << kTileBits) - 1u);              \
         const BProb& pb = P[p];                                             \
         if (pb.ctrl->active == 0) continue;                                 \
-        const int64_t k = tile * kBlock + threadIdx.x;
+        const uint32_t k = tile * kBlock + threadIdx.x;
 
 __global__ __launch_bounds__(kBlock) void kb_relax(const BProb* __restrict__ P, const BSlot* __restrict__ S,
                                                    const uint32_t* __restrict__ wl, int nwl, int in_x1, int norm)
@@ -210,9 +225,9 @@ __global__ __launch_bounds__(kBlock) void kb_relax(const BProb* __restrict__ P, 
     const BSlot& s = S[p * kMaxLevels];
     const Soa& in = in_x1 ? s.x1 : s.x0;
     const Soa& out = in_x1 ? s.x0 : s.x1;
-    const bool inside = k < (int64_t)s.L.nx * s.L.ny;
+    const bool inside = k < (uint32_t)s.L.nx * (uint32_t)s.L.ny;
     int i = 0, j = 0;
-    if (inside) ij_of(s.L.nx, k, i, j);
+    if (inside) ij_of(s.L.nx, s.L.sh, k, i, j);
     if (!norm) {
         if (inside) relax_cell<2>(pb.ph, s.L, cs(s.b), nullptr, 0.0, 1.0, pb.omega, cs(in), out, k, i, j);
         continue;
@@ -238,9 +253,9 @@ __global__ __launch_bounds__(kBlock) void kb_apply(const BProb* __restrict__ P, 
 {
     B_LOOP(wl, nwl)
     const BSlot& s = S[p * kMaxLevels + level];
-    if (k >= (int64_t)s.L.nx * s.L.ny) continue;
+    if (k >= (uint32_t)s.L.nx * (uint32_t)s.L.ny) continue;
     int i, j;
-    ij_of(s.L.nx, k, i, j);
+    ij_of(s.L.nx, s.L.sh, k, i, j);
     if (level == 0) apply_cell<2>(pb.ph, s.L, cs(in_sel ? s.x1 : s.x0), cs(s.b), -1.0, s.rf, k, i, j);
     else apply_cell<2>(pb.ph, s.L, cs(pick(s, in_sel)), cs(s.f), -1.0, s.rb, k, i, j);
     }
@@ -253,12 +268,12 @@ __global__ __launch_bounds__(kBlock) void kb_restrict(const BProb* __restrict__ 
     B_LOOP(wl, nwl)
     const BSlot& c = S[p * kMaxLevels + level];
     const BSlot& f = S[p * kMaxLevels + level - 1];
-    if (k >= (int64_t)c.L.nx * c.L.ny) continue;
+    if (k >= (uint32_t)c.L.nx * (uint32_t)c.L.ny) continue;
     const Soa& u = (level == 1) ? (in_sel ? f.x1 : f.x0) : pick(f, in_sel);
     const Soa& r = (level == 1) ? f.rf : f.rb;
     const double* in[8] = {u.E, u.Fx, u.Fy, u.T, r.E, r.Fx, r.Fy, r.T};
     double* out[8] = {c.v.E, c.v.Fx, c.v.Fy, c.v.T, c.f.E, c.f.Fx, c.f.Fy, c.f.T};
-    restrict_cell<2, 8>(f.L.nx, f.L.ny, pb.px, pb.py, in, out, k);
+    restrict_cell<2, 8>(f.L.nx, f.L.ny, f.L.sh, pb.px, pb.py, in, out, k);
     }
 }
 
@@ -268,9 +283,9 @@ __global__ __launch_bounds__(kBlock) void kb_pseudo(const BProb* __restrict__ P,
 {
     B_LOOP(wl, nwl)
     const BSlot& s = S[p * kMaxLevels + level];
-    if (k >= (int64_t)s.L.nx * s.L.ny) continue;
+    if (k >= (uint32_t)s.L.nx * (uint32_t)s.L.ny) continue;
     int i, j;
-    ij_of(s.L.nx, k, i, j);
+    ij_of(s.L.nx, s.L.sh, k, i, j);
     const double dt = pb.ctrl->dtau;
     if (first)
         pseudo_cell<2, true>(pb.ph, s.L, cs(s.f), s.f, cs(pick(s, in_sel)), pick(s, out_sel), dt, pb.reach, pb.local,
@@ -292,10 +307,10 @@ __global__ __launch_bounds__(kBlock) void kb_prolong(const BProb* __restrict__ P
     B_LOOP(wl, nwl)
     const BSlot& f = S[p * kMaxLevels + level];
     const BSlot& c = S[p * kMaxLevels + level + 1];
-    if (k >= (int64_t)f.L.nx * f.L.ny) continue;
+    if (k >= (uint32_t)f.L.nx * (uint32_t)f.L.ny) continue;
     const Soa& u = (level == 0) ? (in_sel ? f.x1 : f.x0) : pick(f, in_sel);
     const Soa& o = (level == 0) ? u : pick(f, out_sel);
-    prolong_cell<2>(pb.ph, f.L.nx, f.L.ny, pb.px, pb.py, pb.eta, cs(u), cs(c.u), cs(c.v), o, k);
+    prolong_cell<2>(pb.ph, f.L.nx, f.L.ny, f.L.sh, pb.px, pb.py, pb.eta, cs(u), cs(c.u), cs(c.v), o, k);
     }
 }
 
@@ -443,19 +458,20 @@ void launch_ctrl_init(hipStream_t st, Ctrl* ctrl, const Ctrl& init)
 void launch_restrict(hipStream_t st, int dim, int nxf, int nyf, int px, int py, const Fields& F, const int* active)
 {
     const int64_t nc = (int64_t)(nxf / 2) * (dim == 2 ? nyf / 2 : 1);
+    const int shf = row_shift(nxf);
     const unsigned g = nblocks(nc);
     const dim3 b(kBlock);
     if (dim == 2) {
         switch (F.n) {
-        case 2: hipLaunchKernelGGL((k_restrict<2, 2>), dim3(g), b, 0, st, nxf, nyf, px, py, F, active); break;
-        case 4: hipLaunchKernelGGL((k_restrict<2, 4>), dim3(g), b, 0, st, nxf, nyf, px, py, F, active); break;
-        default: hipLaunchKernelGGL((k_restrict<2, 8>), dim3(g), b, 0, st, nxf, nyf, px, py, F, active); break;
+        case 2: hipLaunchKernelGGL((k_restrict<2, 2>), dim3(g), b, 0, st, nxf, nyf, shf, px, py, F, active); break;
+        case 4: hipLaunchKernelGGL((k_restrict<2, 4>), dim3(g), b, 0, st, nxf, nyf, shf, px, py, F, active); break;
+        default: hipLaunchKernelGGL((k_restrict<2, 8>), dim3(g), b, 0, st, nxf, nyf, shf, px, py, F, active); break;
         }
     } else {
         switch (F.n) {
-        case 2: hipLaunchKernelGGL((k_restrict<1, 2>), dim3(g), b, 0, st, nxf, nyf, px, py, F, active); break;
-        case 3: hipLaunchKernelGGL((k_restrict<1, 3>), dim3(g), b, 0, st, nxf, nyf, px, py, F, active); break;
-        default: hipLaunchKernelGGL((k_restrict<1, 6>), dim3(g), b, 0, st, nxf, nyf, px, py, F, active); break;
+        case 2: hipLaunchKernelGGL((k_restrict<1, 2>), dim3(g), b, 0, st, nxf, nyf, shf, px, py, F, active); break;
+        case 3: hipLaunchKernelGGL((k_restrict<1, 3>), dim3(g), b, 0, st, nxf, nyf, shf, px, py, F, active); break;
+        default: hipLaunchKernelGGL((k_restrict<1, 6>), dim3(g), b, 0, st, nxf, nyf, shf, px, py, F, active); break;
         }
     }
 }
@@ -463,7 +479,8 @@ void launch_restrict(hipStream_t st, int dim, int nxf, int nyf, int px, int py, 
 void launch_prolong_project(hipStream_t st, int dim, const Phys& ph, int nx, int ny, int px, int py, double eta,
                             CSoa u, CSoa uc, CSoa vc, Soa out, const int* active)
 {
-    M1_DISPATCH(dim, k_prolong_project, nblocks((int64_t)nx * ny), ph, nx, ny, px, py, eta, u, uc, vc, out, active);
+    M1_DISPATCH(dim, k_prolong_project, nblocks((int64_t)nx * ny), ph, nx, ny, row_shift(nx), px, py, eta, u, uc, vc,
+                out, active);
 }
 
 void launch_tail(hipStream_t st, int dim, const TailArgs* args_dev, double dtau, const double* dtau_dev,
