@@ -246,7 +246,7 @@ void fill_level_params(m1_plan& P)
         lv.L.cdt = g.c * g.dt;
         lv.L.sa = lv.sa;
         lv.L.ss = lv.ss;
-        lv.L32 = m1::Lvl32{lv.nx, lv.ny, (float)lv.L.kx, (float)lv.L.ky, (float)lv.L.a, (float)lv.L.cdt, lv.sa32,
+        lv.L32 = m1::Lvl32{lv.nx, lv.ny, lv.L.sh, (float)lv.L.kx, (float)lv.L.ky, (float)lv.L.a, (float)lv.L.cdt, lv.sa32,
                            lv.ss32};
     }
 }
@@ -737,7 +737,7 @@ m1_status m1_vcycle(m1_plan* P, m1_state* v, const m1_state* vn, double dtau)
         mx_vcycle(*P, cur, other, fixed_gate(*P, dtau), false, true, pend);
         // apply the correction: the state is now in tmp; write the update back to v
         m1::launch_mx_resid(P->st, P->dim, P->ph, P->lev[0].L, P->params.eta, cs(cur), cs(pend), cs(P->b), user,
-                            P->base32, P->r32, nullptr, nullptr);
+                            P->base32, P->r32, nullptr, &P->dfix->active);
         return last_launch();
     }
     vcycle_impl(*P, cur, other, fixed_gate(*P, dtau));

@@ -20,14 +20,21 @@ constexpr int kBlock32 = 256;
 
 static inline unsigned nblk(int64_t n) { return (unsigned)((n + kBlock32 - 1) / kBlock32); }
 
-__device__ __forceinline__ bool mx_inactive(const int* active) { return active && *active == 0; }
-
-__device__ __forceinline__ bool mx_cell(int nx, int ny, int64_t& k, int& i, int& j)
+// Finest-level kernels (resid, sweep) exit at once when the stop flag is 0;
+// coarse-level kernels read it with their data and gate only their stores
+// (see the FP64 kernels).  `active` and `dtau_dev` are valid device pointers.
+__device__ __forceinline__ uint32_t mx_lane_zero()
 {
-    k = xcd_block() * kBlock32 + threadIdx.x;
-    if (k >= (int64_t)nx * ny) return false;
-    j = (int)(k / nx);
-    i = (int)(k - (int64_t)j * nx);
+    uint32_t z = 0;
+    asm("" : "+v"(z));
+    return z;
+}
+
+__device__ __forceinline__ bool mx_cell(int nx, int ny, int sh, uint32_t& k, int& i, int& j)
+{
+    k = (uint32_t)xcd_block() * kBlock32 + threadIdx.x;
+    if (k >= (uint32_t)nx * (uint32_t)ny) return false;
+    ij_of(nx, sh, k, i, j);
     return true;
 }
 
@@ -35,15 +42,15 @@ __device__ __forceinline__ bool mx_cell(int nx, int ny, int64_t& k, int& i, int&
 // FP64 state update with admissibility projection: w = v + d where admissible,
 // else v + eta min(tau*(v, d), 1) d.
 template <int DIM>
-__device__ __forceinline__ void upd64(const Phys& ph, double eta, const CSoa& v, const CSoa32& d, int64_t k,
+__device__ __forceinline__ void upd64(const Phys& ph, double eta, const CSoa& v, const CSoa32& d, uint32_t k,
                                       double& E, double& Fx, double& Fy, double& T)
 {
-    E = v.E[k];
-    Fx = v.Fx[k];
-    Fy = (DIM == 2) ? v.Fy[k] : 0.0;
-    T = v.T[k];
+    E = ld(v.E, k);
+    Fx = ld(v.Fx, k);
+    Fy = (DIM == 2) ? ld(v.Fy, k) : 0.0;
+    T = ld(v.T, k);
     if (!d.E) return;
-    const double e = d.E[k], gx = d.Fx[k], gy = (DIM == 2) ? (double)d.Fy[k] : 0.0, t = d.T[k];
+    const double e = ldf(d.E, k), gx = ldf(d.Fx, k), gy = (DIM == 2) ? (double)ldf(d.Fy, k) : 0.0, t = ldf(d.T, k);
     const double wE = E + e, wFx = Fx + gx, wFy = Fy + gy, wT = T + t;
     if (admissible(ph.c2, wE, wFx, wFy, wT)) {
         E = wE;
@@ -60,22 +67,20 @@ __device__ __forceinline__ void upd64(const Phys& ph, double eta, const CSoa& v,
 }
 
 template <int DIM>
-__device__ __forceinline__ void nb_upd64(const Phys& ph, double eta, int side, bool inside, int64_t kn, int64_t kc,
+__device__ __forceinline__ void nb_upd64(const Phys& ph, double eta, int side, bool inside, uint32_t kn, uint32_t kc,
                                          const CSoa& v, const CSoa32& d, double& E, double& Fx, double& Fy)
 {
-    const int kind = inside ? BC_PERIODIC : ph.bc[side];
-    if (kind == BC_DIRICHLET) {
-        E = ph.bcE[side];
-        Fx = ph.bcFx[side];
-        Fy = ph.bcFy[side];
-        return;
-    }
-    double T;
-    upd64<DIM>(ph, eta, v, d, kind == BC_PERIODIC ? kn : kc, E, Fx, Fy, T);
-    if (kind == BC_REFLECTIVE) {
-        if (side < 2) Fx = -Fx;
-        else Fy = -Fy;
-    }
+    const int kind = ph.bc[side];
+    const bool ghost = !inside && kind != BC_PERIODIC;
+    double lE, lFx, lFy, T;
+    upd64<DIM>(ph, eta, v, d, ghost ? kc : kn, lE, lFx, lFy, T);
+    const bool dir = ghost && kind == BC_DIRICHLET;
+    const bool flip = ghost && kind == BC_REFLECTIVE;
+    const double keep = dir ? 0.0 : 1.0;
+    const double sx = (flip && side < 2) ? -keep : keep, sy = (flip && side >= 2) ? -keep : keep;
+    E = fma(keep, lE, dir ? ph.bcE[side] : 0.0);
+    Fx = fma(sx, lFx, dir ? ph.bcFx[side] : 0.0);
+    Fy = fma(sy, lFy, dir ? ph.bcFy[side] : 0.0);
 }
 
 // v_new = proj(v + d); r = b - A(v_new) (FP64); base32 = (float) v_new; r32 = (float) r;
@@ -85,19 +90,20 @@ __global__ __launch_bounds__(kBlock32) void k_mx_resid(Phys ph, Lvl L, double et
                                                        Soa vnew, Soa32 base, Soa32 r32, double* __restrict__ partials,
                                                        const int* __restrict__ active)
 {
-    if (mx_inactive(active)) return;
+    if (*active == 0) return;
     __shared__ double red[kBlock32 / 64];
-    int64_t k;
+    uint32_t k;
     int i, j;
     double q = 0.0;
-    if (mx_cell(L.nx, L.ny, k, i, j)) {
+    if (mx_cell(L.nx, L.ny, L.sh, k, i, j)) {
         double S0 = 0.0, S1 = 0.0, S2 = 0.0, e, fx, fy;
-        nb_upd64<DIM>(ph, eta, 0, i > 0, i > 0 ? k - 1 : k + (L.nx - 1), k, v, d, e, fx, fy);
+        const uint32_t wx = (uint32_t)(L.nx - 1);
+        nb_upd64<DIM>(ph, eta, 0, i > 0, i > 0 ? k - 1 : k + wx, k, v, d, e, fx, fy);
         add_x(L.kx, ph.c, ph.c2, +1.0, e, fx, fy, S0, S1, S2);
-        nb_upd64<DIM>(ph, eta, 1, i < L.nx - 1, i < L.nx - 1 ? k + 1 : k - (L.nx - 1), k, v, d, e, fx, fy);
+        nb_upd64<DIM>(ph, eta, 1, i < L.nx - 1, i < L.nx - 1 ? k + 1 : k - wx, k, v, d, e, fx, fy);
         add_x(L.kx, ph.c, ph.c2, -1.0, e, fx, fy, S0, S1, S2);
         if (DIM == 2) {
-            const int64_t nx = L.nx, wrap = (int64_t)(L.ny - 1) * nx;
+            const uint32_t nx = (uint32_t)L.nx, wrap = (uint32_t)(L.ny - 1) * nx;
             nb_upd64<DIM>(ph, eta, 2, j > 0, j > 0 ? k - nx : k + wrap, k, v, d, e, fx, fy);
             add_y(L.ky, ph.c, ph.c2, +1.0, e, fx, fy, S0, S1, S2);
             nb_upd64<DIM>(ph, eta, 3, j < L.ny - 1, j < L.ny - 1 ? k + nx : k - wrap, k, v, d, e, fx, fy);
@@ -105,26 +111,26 @@ __global__ __launch_bounds__(kBlock32) void k_mx_resid(Phys ph, Lvl L, double et
         }
         double E, Fx, Fy, T;
         upd64<DIM>(ph, eta, v, d, k, E, Fx, Fy, T);
-        const double ka = L.cdt * L.sa[k], ks = L.cdt * L.ss[k];
+        const double ka = L.cdt * ld(L.sa, k), ks = L.cdt * ld(L.ss, k);
         const double T2 = T * T;
         const double ex = ka * fma(-ph.a_r * T2, T2, E);
         const double dF = L.a + ka + ks;
-        const double rE = b.E[k] - (fma(L.a, E, ex) - S0);
-        const double rFx = b.Fx[k] - fma(dF, Fx, -S1);
-        const double rFy = (DIM == 2) ? b.Fy[k] - fma(dF, Fy, -S2) : 0.0;
-        const double rT = b.T[k] - fma(ph.c_v, T, -ex);
-        vnew.E[k] = E;
-        vnew.Fx[k] = Fx;
-        if (DIM == 2) vnew.Fy[k] = Fy;
-        vnew.T[k] = T;
-        base.E[k] = (float)E;
-        base.Fx[k] = (float)Fx;
-        if (DIM == 2) base.Fy[k] = (float)Fy;
-        base.T[k] = (float)T;
-        r32.E[k] = (float)rE;
-        r32.Fx[k] = (float)rFx;
-        if (DIM == 2) r32.Fy[k] = (float)rFy;
-        r32.T[k] = (float)rT;
+        const double rE = ld(b.E, k) - (fma(L.a, E, ex) - S0);
+        const double rFx = ld(b.Fx, k) - fma(dF, Fx, -S1);
+        const double rFy = (DIM == 2) ? ld(b.Fy, k) - fma(dF, Fy, -S2) : 0.0;
+        const double rT = ld(b.T, k) - fma(ph.c_v, T, -ex);
+        st(vnew.E, k, E);
+        st(vnew.Fx, k, Fx);
+        if (DIM == 2) st(vnew.Fy, k, Fy);
+        st(vnew.T, k, T);
+        stf(base.E, k, (float)E);
+        stf(base.Fx, k, (float)Fx);
+        if (DIM == 2) stf(base.Fy, k, (float)Fy);
+        stf(base.T, k, (float)T);
+        stf(r32.E, k, (float)rE);
+        stf(r32.Fx, k, (float)rFx);
+        if (DIM == 2) stf(r32.Fy, k, (float)rFy);
+        stf(r32.T, k, (float)rT);
         const double ic = 1.0 / ph.c;
         q = fma(rE, rE, fma(rFx * ic, rFx * ic, fma(rFy * ic, rFy * ic, rT * rT)));
     }
@@ -145,38 +151,38 @@ __global__ __launch_bounds__(kBlock32) void k_mx_sweep(Phys ph, Lvl32 L, CSoa32 
                                                        float gamma, float omega, Soa32 out,
                                                        const int* __restrict__ active)
 {
-    if (mx_inactive(active)) return;
-    int64_t k;
+    if (*active == 0) return;
+    uint32_t k;
     int i, j;
-    if (!mx_cell(L.nx, L.ny, k, i, j)) return;
+    if (!mx_cell(L.nx, L.ny, L.sh, k, i, j)) return;
     float S0 = 0.0f, S1 = 0.0f, S2 = 0.0f;
     if (d.E) offdiag_inc<DIM>(ph, L, w, d, i, j, k, S0, S1, S2);
-    const double QE = fmaf(gamma, S0, rhs.E[k]);
-    const double QFx = fmaf(gamma, S1, rhs.Fx[k]);
-    const double QFy = (DIM == 2) ? fmaf(gamma, S2, rhs.Fy[k]) : 0.0;
-    const double QT = rhs.T[k];
-    const float dE = d.E ? d.E[k] : 0.0f, dFx = d.E ? d.Fx[k] : 0.0f;
-    const float dFy = (DIM == 2 && d.E) ? d.Fy[k] : 0.0f, dT = d.E ? d.T[k] : 0.0f;
-    const double ka = (double)L.cdt * L.sa[k], ks = (double)L.cdt * L.ss[k];
+    const double QE = fmaf(gamma, S0, ldf(rhs.E, k));
+    const double QFx = fmaf(gamma, S1, ldf(rhs.Fx, k));
+    const double QFy = (DIM == 2) ? fmaf(gamma, S2, ldf(rhs.Fy, k)) : 0.0;
+    const double QT = ldf(rhs.T, k);
+    const float dE = d.E ? ldf(d.E, k) : 0.0f, dFx = d.E ? ldf(d.Fx, k) : 0.0f;
+    const float dFy = (DIM == 2 && d.E) ? ldf(d.Fy, k) : 0.0f, dT = d.E ? ldf(d.T, k) : 0.0f;
+    const double ka = (double)L.cdt * ldf(L.sa, k), ks = (double)L.cdt * ldf(L.ss, k);
     float xE, xFx, xFy, xT;
-    local_solve_inc(beta, gamma, L.a, ka, ks, ph.c_v, ph.a_r, QE, QFx, QFy, QT, w.T[k], dT, xE, xFx, xFy, xT);
-    out.E[k] = fmaf(omega, xE - dE, dE);
-    out.Fx[k] = fmaf(omega, xFx - dFx, dFx);
-    if (DIM == 2) out.Fy[k] = fmaf(omega, xFy - dFy, dFy);
-    out.T[k] = fmaf(omega, xT - dT, dT);
+    local_solve_inc(beta, gamma, L.a, ka, ks, ph.c_v, ph.a_r, QE, QFx, QFy, QT, ldf(w.T, k), dT, xE, xFx, xFy, xT);
+    stf(out.E, k, fmaf(omega, xE - dE, dE));
+    stf(out.Fx, k, fmaf(omega, xFx - dFx, dFx));
+    if (DIM == 2) stf(out.Fy, k, fmaf(omega, xFy - dFy, dFy));
+    stf(out.T, k, fmaf(omega, xT - dT, dT));
 }
 
 // Increment of A for one cell: N(d) = (D(w + d) - D(w)) - dS(d).
 template <int DIM>
-__device__ __forceinline__ void n_inc(const Phys& ph, const Lvl32& L, const CSoa32& w, const CSoa32& d, int64_t k,
+__device__ __forceinline__ void n_inc(const Phys& ph, const Lvl32& L, const CSoa32& w, const CSoa32& d, uint32_t k,
                                       int i, int j, float& NE, float& NFx, float& NFy, float& NT)
 {
     float S0, S1, S2;
     offdiag_inc<DIM>(ph, L, w, d, i, j, k, S0, S1, S2);
-    const double ka = (double)L.cdt * L.sa[k], ks = (double)L.cdt * L.ss[k];
+    const double ka = (double)L.cdt * ldf(L.sa, k), ks = (double)L.cdt * ldf(L.ss, k);
     float DE, DFx, DFy, DT;
-    diag_inc(L.a, ka, ks, ph.c_v, ph.a_r, w.T[k], d.E[k], d.Fx[k], (DIM == 2) ? d.Fy[k] : 0.0f, d.T[k], DE, DFx,
-             DFy, DT);
+    diag_inc(L.a, ka, ks, ph.c_v, ph.a_r, ldf(w.T, k), ldf(d.E, k), ldf(d.Fx, k), (DIM == 2) ? ldf(d.Fy, k) : 0.0f,
+             ldf(d.T, k), DE, DFx, DFy, DT);
     NE = DE - S0;
     NFx = DFx - S1;
     NFy = DFy - S2;
@@ -186,25 +192,29 @@ __device__ __forceinline__ void n_inc(const Phys& ph, const Lvl32& L, const CSoa
 // out = X + sgn N(d).
 template <int DIM>
 __device__ __forceinline__ void mx_apply_cell(const Phys& ph, const Lvl32& L, const CSoa32& w, const CSoa32& d,
-                                              const CSoa32& X, float sgn, const Soa32& out, int64_t k, int i, int j)
+                                              const CSoa32& X, float sgn, const Soa32& out, uint32_t k, int i, int j,
+                                              bool live = true)
 {
     float NE, NFx, NFy, NT;
     n_inc<DIM>(ph, L, w, d, k, i, j, NE, NFx, NFy, NT);
-    out.E[k] = fmaf(sgn, NE, X.E[k]);
-    out.Fx[k] = fmaf(sgn, NFx, X.Fx[k]);
-    if (DIM == 2) out.Fy[k] = fmaf(sgn, NFy, X.Fy[k]);
-    out.T[k] = fmaf(sgn, NT, X.T[k]);
+    const float oE = fmaf(sgn, NE, ldf(X.E, k)), oFx = fmaf(sgn, NFx, ldf(X.Fx, k));
+    const float oFy = (DIM == 2) ? fmaf(sgn, NFy, ldf(X.Fy, k)) : 0.0f, oT = fmaf(sgn, NT, ldf(X.T, k));
+    if (!live) return;
+    stf(out.E, k, oE);
+    stf(out.Fx, k, oFx);
+    if (DIM == 2) stf(out.Fy, k, oFy);
+    stf(out.T, k, oT);
 }
 
 template <int DIM>
 __global__ __launch_bounds__(kBlock32) void k_mx_apply(Phys ph, Lvl32 L, CSoa32 w, CSoa32 d, CSoa32 X, float sgn,
                                                        Soa32 out, const int* __restrict__ active)
 {
-    if (mx_inactive(active)) return;
-    int64_t k;
+    const bool live = active[mx_lane_zero()] != 0;
+    uint32_t k;
     int i, j;
-    if (!mx_cell(L.nx, L.ny, k, i, j)) return;
-    mx_apply_cell<DIM>(ph, L, w, d, X, sgn, out, k, i, j);
+    if (!mx_cell(L.nx, L.ny, L.sh, k, i, j)) return;
+    mx_apply_cell<DIM>(ph, L, w, d, X, sgn, out, k, i, j, live);
 }
 
 // One pseudo-time step of M de/dtau + N_w(e) = g (Algorithm 3 in increment
@@ -213,15 +223,15 @@ __global__ __launch_bounds__(kBlock32) void k_mx_apply(Phys ph, Lvl32 L, CSoa32 
 template <int DIM, bool FIRST>
 __device__ __forceinline__ void mx_pseudo_cell(const Phys& ph, const Lvl32& L, const CSoa32& w, const Soa32& g,
                                                const CSoa32& e, const Soa32& out, float dt, float reach, int local,
-                                               int64_t k, int i, int j)
+                                               uint32_t k, int i, int j, bool live = true)
 {
     const float c2 = (float)ph.c2, cv = (float)ph.c_v;
     float S0, S1, S2;
     offdiag_inc<DIM>(ph, L, w, e, i, j, k, S0, S1, S2);
-    const float eE = e.E[k], eFx = e.Fx[k], eFy = (DIM == 2) ? e.Fy[k] : 0.0f, eT = e.T[k];
-    const float wE = w.E[k], wFx = w.Fx[k], wFy = (DIM == 2) ? w.Fy[k] : 0.0f, wT = w.T[k];
-    const double ka = (double)L.cdt * L.sa[k], ks = (double)L.cdt * L.ss[k];
-    float gE = g.E[k], gFx = g.Fx[k], gFy = (DIM == 2) ? g.Fy[k] : 0.0f, gT = g.T[k];
+    const float eE = ldf(e.E, k), eFx = ldf(e.Fx, k), eFy = (DIM == 2) ? ldf(e.Fy, k) : 0.0f, eT = ldf(e.T, k);
+    const float wE = ldf(w.E, k), wFx = ldf(w.Fx, k), wFy = (DIM == 2) ? ldf(w.Fy, k) : 0.0f, wT = ldf(w.T, k);
+    const double ka = (double)L.cdt * ldf(L.sa, k), ks = (double)L.cdt * ldf(L.ss, k);
+    float gE = ldf(g.E, k), gFx = ldf(g.Fx, k), gFy = (DIM == 2) ? ldf(g.Fy, k) : 0.0f, gT = ldf(g.T, k);
     if (FIRST) {
         float DE, DFx, DFy, DT;
         diag_inc(L.a, ka, ks, ph.c_v, ph.a_r, wT, eE, eFx, eFy, eT, DE, DFx, DFy, DT);
@@ -229,10 +239,12 @@ __device__ __forceinline__ void mx_pseudo_cell(const Phys& ph, const Lvl32& L, c
         gFx += DFx - S1;
         gFy += DFy - S2;
         gT += DT;
-        g.E[k] = gE;
-        g.Fx[k] = gFx;
-        if (DIM == 2) g.Fy[k] = gFy;
-        g.T[k] = gT;
+        if (live) {
+            stf(g.E, k, gE);
+            stf(g.Fx, k, gFx);
+            if (DIM == 2) stf(g.Fy, k, gFy);
+            stf(g.T, k, gT);
+        }
     }
     const float sT = gT * rcp32(cv);
     const float ts = ray_len32(c2, wE + eE, wFx + eFx, wFy + eFy, wT + eT, gE, gFx, gFy, sT);
@@ -243,10 +255,11 @@ __device__ __forceinline__ void mx_pseudo_cell(const Phys& ph, const Lvl32& L, c
     float xE, xFx, xFy, xT;
     local_solve_inc(1.0, gm, L.a, ka, ks, ph.c_v, ph.a_r, fmaf(gm, S0, tE), fmaf(gm, S1, tFx), fmaf(gm, S2, tFy), tT,
                     wT, eT, xE, xFx, xFy, xT);
-    out.E[k] = xE;
-    out.Fx[k] = xFx;
-    if (DIM == 2) out.Fy[k] = xFy;
-    out.T[k] = xT;
+    if (!live) return;
+    stf(out.E, k, xE);
+    stf(out.Fx, k, xFx);
+    if (DIM == 2) stf(out.Fy, k, xFy);
+    stf(out.T, k, xT);
 }
 
 template <int DIM>
@@ -255,13 +268,14 @@ __global__ __launch_bounds__(kBlock32) void k_mx_pseudo(Phys ph, Lvl32 L, CSoa32
                                                         float reach, int local, int first,
                                                         const int* __restrict__ active)
 {
-    if (mx_inactive(active)) return;
-    int64_t k;
+    const uint32_t z = mx_lane_zero();
+    const float dt = (float)dtau_dev[z];
+    const bool live = active[z] != 0;
+    uint32_t k;
     int i, j;
-    if (!mx_cell(L.nx, L.ny, k, i, j)) return;
-    const float dt = (float)(dtau_dev ? *dtau_dev : dtau);
-    if (first) mx_pseudo_cell<DIM, true>(ph, L, w, g, e, out, dt, reach, local, k, i, j);
-    else mx_pseudo_cell<DIM, false>(ph, L, w, g, e, out, dt, reach, local, k, i, j);
+    if (!mx_cell(L.nx, L.ny, L.sh, k, i, j)) return;
+    if (first) mx_pseudo_cell<DIM, true>(ph, L, w, g, e, out, dt, reach, local, k, i, j, live);
+    else mx_pseudo_cell<DIM, false>(ph, L, w, g, e, out, dt, reach, local, k, i, j, live);
 }
 
 // ---------------------------------------------------------------------------
@@ -285,10 +299,11 @@ __device__ __forceinline__ void pw32(int i, int nc, bool periodic, int idx[2], f
 }
 
 template <int DIM>
-__device__ __forceinline__ void coarse_corr(int nx, int ny, int px, int py, const CSoa32& ec, const CSoa32& dc,
-                                            int64_t k, float& c0, float& c1, float& c2, float& c3)
+__device__ __forceinline__ void coarse_corr(int nx, int ny, int sh, int px, int py, const CSoa32& ec, const CSoa32& dc,
+                                            uint32_t k, float& c0, float& c1, float& c2, float& c3)
 {
-    const int j = (int)(k / nx), i = (int)(k - (int64_t)j * nx);
+    int i, j;
+    ij_of(nx, sh, k, i, j);
     const int nxc = nx / 2, nyc = (DIM == 2) ? ny / 2 : 1;
     int ix[2], iy[2] = {0, 0};
     float wx[2], wy[2] = {1.0f, 0.0f};
@@ -300,75 +315,79 @@ __device__ __forceinline__ void coarse_corr(int nx, int ny, int px, int py, cons
     for (int b = 0; b < NB; ++b)
 #pragma unroll
         for (int a = 0; a < 2; ++a) {
-            const int64_t kc = (int64_t)iy[b] * nxc + ix[a];
+            const uint32_t kc = (uint32_t)iy[b] * (uint32_t)nxc + (uint32_t)ix[a];
             const float wgt = wx[a] * wy[b];
-            c0 = fmaf(wgt, ec.E[kc] - dc.E[kc], c0);
-            c1 = fmaf(wgt, ec.Fx[kc] - dc.Fx[kc], c1);
-            if (DIM == 2) c2 = fmaf(wgt, ec.Fy[kc] - dc.Fy[kc], c2);
-            c3 = fmaf(wgt, ec.T[kc] - dc.T[kc], c3);
+            c0 = fmaf(wgt, ldf(ec.E, kc) - ldf(dc.E, kc), c0);
+            c1 = fmaf(wgt, ldf(ec.Fx, kc) - ldf(dc.Fx, kc), c1);
+            if (DIM == 2) c2 = fmaf(wgt, ldf(ec.Fy, kc) - ldf(dc.Fy, kc), c2);
+            c3 = fmaf(wgt, ldf(ec.T, kc) - ldf(dc.T, kc), c3);
         }
 }
 
 template <int DIM>
-__device__ __forceinline__ void mx_prolong_cell(const Phys& ph, int nx, int ny, int px, int py, float eta,
+__device__ __forceinline__ void mx_prolong_cell(const Phys& ph, int nx, int ny, int sh, int px, int py, float eta,
                                                 const CSoa32& w, const CSoa32& e, const CSoa32& ec, const CSoa32& dc,
-                                                const Soa32& out, int64_t k)
+                                                const Soa32& out, uint32_t k, bool live = true)
 {
     float c0, c1, c2, c3;
-    coarse_corr<DIM>(nx, ny, px, py, ec, dc, k, c0, c1, c2, c3);
-    const float eE = e.E[k], eFx = e.Fx[k], eFy = (DIM == 2) ? e.Fy[k] : 0.0f, eT = e.T[k];
-    const float sE = w.E[k] + eE, sFx = w.Fx[k] + eFx, sFy = ((DIM == 2) ? w.Fy[k] : 0.0f) + eFy, sT = w.T[k] + eT;
+    coarse_corr<DIM>(nx, ny, sh, px, py, ec, dc, k, c0, c1, c2, c3);
+    const float eE = ldf(e.E, k), eFx = ldf(e.Fx, k), eFy = (DIM == 2) ? ldf(e.Fy, k) : 0.0f, eT = ldf(e.T, k);
+    const float sE = ldf(w.E, k) + eE, sFx = ldf(w.Fx, k) + eFx;
+    const float sFy = ((DIM == 2) ? ldf(w.Fy, k) : 0.0f) + eFy, sT = ldf(w.T, k) + eT;
     float th = 1.0f;
     const float cc2 = (float)ph.c2;
     if (!admissible32(cc2, sE + c0, sFx + c1, sFy + c2, sT + c3))
         th = eta * fminf(ray_len32(cc2, sE, sFx, sFy, sT, c0, c1, c2, c3), 1.0f);
-    out.E[k] = fmaf(th, c0, eE);
-    out.Fx[k] = fmaf(th, c1, eFx);
-    if (DIM == 2) out.Fy[k] = fmaf(th, c2, eFy);
-    out.T[k] = fmaf(th, c3, eT);
+    if (!live) return;
+    stf(out.E, k, fmaf(th, c0, eE));
+    stf(out.Fx, k, fmaf(th, c1, eFx));
+    if (DIM == 2) stf(out.Fy, k, fmaf(th, c2, eFy));
+    stf(out.T, k, fmaf(th, c3, eT));
 }
 
 template <int DIM>
-__global__ __launch_bounds__(kBlock32) void k_mx_prolong(Phys ph, int nx, int ny, int px, int py, float eta, CSoa32 w,
-                                                         CSoa32 e, CSoa32 ec, CSoa32 dc, Soa32 out,
+__global__ __launch_bounds__(kBlock32) void k_mx_prolong(Phys ph, int nx, int ny, int sh, int px, int py, float eta,
+                                                         CSoa32 w, CSoa32 e, CSoa32 ec, CSoa32 dc, Soa32 out,
                                                          const int* __restrict__ active)
 {
-    if (mx_inactive(active)) return;
-    const int64_t k = xcd_block() * kBlock32 + threadIdx.x;
-    if (k >= (int64_t)nx * ny) return;
-    mx_prolong_cell<DIM>(ph, nx, ny, px, py, eta, w, e, ec, dc, out, k);
+    const bool live = active[mx_lane_zero()] != 0;
+    const uint32_t k = (uint32_t)xcd_block() * kBlock32 + threadIdx.x;
+    if (k >= (uint32_t)nx * (uint32_t)ny) return;
+    mx_prolong_cell<DIM>(ph, nx, ny, sh, px, py, eta, w, e, ec, dc, out, k, live);
 }
 
 template <int DIM>
-__global__ __launch_bounds__(kBlock32) void k_mx_prolong_fine(Phys ph, int nx, int ny, int px, int py, double eta,
-                                                              CSoa v, CSoa32 e, CSoa32 ec, CSoa32 dc, Soa32 out,
-                                                              const int* __restrict__ active)
+__global__ __launch_bounds__(kBlock32) void k_mx_prolong_fine(Phys ph, int nx, int ny, int sh, int px, int py,
+                                                              double eta, CSoa v, CSoa32 e, CSoa32 ec, CSoa32 dc,
+                                                              Soa32 out, const int* __restrict__ active)
 {
-    if (mx_inactive(active)) return;
-    const int64_t k = xcd_block() * kBlock32 + threadIdx.x;
-    if (k >= (int64_t)nx * ny) return;
+    const bool live = active[mx_lane_zero()] != 0;
+    const uint32_t k = (uint32_t)xcd_block() * kBlock32 + threadIdx.x;
+    if (k >= (uint32_t)nx * (uint32_t)ny) return;
     float c0, c1, c2, c3;
-    coarse_corr<DIM>(nx, ny, px, py, ec, dc, k, c0, c1, c2, c3);
-    const float eE = e.E[k], eFx = e.Fx[k], eFy = (DIM == 2) ? e.Fy[k] : 0.0f, eT = e.T[k];
-    const double sE = v.E[k] + (double)eE, sFx = v.Fx[k] + (double)eFx;
-    const double sFy = ((DIM == 2) ? v.Fy[k] : 0.0) + (double)eFy, sT = v.T[k] + (double)eT;
+    coarse_corr<DIM>(nx, ny, sh, px, py, ec, dc, k, c0, c1, c2, c3);
+    const float eE = ldf(e.E, k), eFx = ldf(e.Fx, k), eFy = (DIM == 2) ? ldf(e.Fy, k) : 0.0f, eT = ldf(e.T, k);
+    const double sE = ld(v.E, k) + (double)eE, sFx = ld(v.Fx, k) + (double)eFx;
+    const double sFy = ((DIM == 2) ? ld(v.Fy, k) : 0.0) + (double)eFy, sT = ld(v.T, k) + (double)eT;
     double th = 1.0;
     if (!admissible(ph.c2, sE + c0, sFx + c1, sFy + c2, sT + c3))
         th = eta * fmin(ray_len(ph.c2, sE, sFx, sFy, sT, c0, c1, c2, c3), 1.0);
-    out.E[k] = (float)fma(th, (double)c0, (double)eE);
-    out.Fx[k] = (float)fma(th, (double)c1, (double)eFx);
-    if (DIM == 2) out.Fy[k] = (float)fma(th, (double)c2, (double)eFy);
-    out.T[k] = (float)fma(th, (double)c3, (double)eT);
+    if (!live) return;
+    stf(out.E, k, (float)fma(th, (double)c0, (double)eE));
+    stf(out.Fx, k, (float)fma(th, (double)c1, (double)eFx));
+    if (DIM == 2) stf(out.Fy, k, (float)fma(th, (double)c2, (double)eFy));
+    stf(out.T, k, (float)fma(th, (double)c3, (double)eT));
 }
 
 // FP32 restriction of NF fields (base, correction, residual of a level) for
 // coarse cell k: full weighting, all values gathered before the sums.
 template <int DIM, int NF>
-__device__ __forceinline__ void mx_restrict_cell(int nxf, int nyf, int px, int py, const float* const* in,
-                                                 float* const* out, int64_t k)
+__device__ __forceinline__ void mx_restrict_cell(int nxf, int nyf, int shf, int px, int py, const float* const* in,
+                                                 float* const* out, uint32_t k, bool live = true)
 {
     const int nxc = nxf / 2;
-    const int J = (int)(k / nxc), I = (int)(k - (int64_t)J * nxc);
+    int I, J;
+    ij_of(nxc, shf > 0 ? shf - 1 : -1, k, I, J);
     int ix[3], iy[3] = {0, 0, 0};
     float wx[3], wy[3] = {1.0f, 0.0f, 0.0f};
     auto weights = [](int c, int nf, bool per, int* idx, float* w) {
@@ -404,7 +423,7 @@ __device__ __forceinline__ void mx_restrict_cell(int nxf, int nyf, int px, int p
 #pragma unroll
     for (int q = 0; q < NF; ++q)
 #pragma unroll
-        for (int m = 0; m < NB * 3; ++m) val[q][m] = in[q][off[m]];
+        for (int m = 0; m < NB * 3; ++m) val[q][m] = ldf(in[q], off[m]);
 #pragma unroll
     for (int q = 0; q < NF; ++q) {
         float s = 0.0f;
@@ -413,19 +432,19 @@ __device__ __forceinline__ void mx_restrict_cell(int nxf, int nyf, int px, int p
             const float t = fmaf(wx[2], val[q][b * 3 + 2], fmaf(wx[1], val[q][b * 3 + 1], wx[0] * val[q][b * 3]));
             s = fmaf(wy[b], t, s);
         }
-        out[q][k] = s;
+        if (live) stf(out[q], k, s);
     }
 }
 
 template <int DIM, int NF>
-__global__ __launch_bounds__(kBlock32) void k_mx_restrict(int nxf, int nyf, int px, int py, Fields32 F,
+__global__ __launch_bounds__(kBlock32) void k_mx_restrict(int nxf, int nyf, int shf, int px, int py, Fields32 F,
                                                           const int* __restrict__ active)
 {
-    if (mx_inactive(active)) return;
-    const int64_t nc = (int64_t)(nxf / 2) * ((DIM == 2) ? nyf / 2 : 1);
-    const int64_t k = xcd_block() * kBlock32 + threadIdx.x;
+    const bool live = active[mx_lane_zero()] != 0;
+    const uint32_t nc = (uint32_t)(nxf / 2) * (uint32_t)((DIM == 2) ? nyf / 2 : 1);
+    const uint32_t k = (uint32_t)xcd_block() * kBlock32 + threadIdx.x;
     if (k >= nc) return;
-    mx_restrict_cell<DIM, NF>(nxf, nyf, px, py, F.in, F.out, k);
+    mx_restrict_cell<DIM, NF>(nxf, nyf, shf, px, py, F.in, F.out, k, live);
 }
 
 // ---------------------------------------------------------------------------
@@ -436,11 +455,12 @@ template <int DIM>
 __device__ __forceinline__ Soa32 mx_tail_pseudo(const TailArgs32& A, const TailLevel32& T, float dt, Soa32 in,
                                                 bool first)
 {
-    const int64_t n = (int64_t)T.L.nx * T.L.ny;
+    const uint32_t n = (uint32_t)T.L.nx * (uint32_t)T.L.ny;
     for (int m = 0; m < A.pseudo_steps; ++m) {
         const Soa32 out = (in.E == T.e.E) ? T.e2 : T.e;
-        for (int64_t k = threadIdx.x; k < n; k += blockDim.x) {
-            const int j = (int)(k / T.L.nx), i = (int)(k - (int64_t)j * T.L.nx);
+        for (uint32_t k = threadIdx.x; k < n; k += blockDim.x) {
+            int i, j;
+            ij_of(T.L.nx, T.L.sh, k, i, j);
             if (first && m == 0) mx_pseudo_cell<DIM, true>(A.ph, T.L, cs(T.w), T.g, cs(in), out, dt, A.reach, A.local, k, i, j);
             else mx_pseudo_cell<DIM, false>(A.ph, T.L, cs(T.w), T.g, cs(in), out, dt, A.reach, A.local, k, i, j);
         }
@@ -454,9 +474,9 @@ template <int DIM>
 __global__ __launch_bounds__(256) void k_mx_tail(const TailArgs32* __restrict__ Ap, double dtau,
                                                   const double* __restrict__ dtau_dev, const int* __restrict__ active)
 {
-    if (mx_inactive(active)) return;
+    const float dt = (float)*dtau_dev;
+    if (*active == 0) return;
     const TailArgs32& A = *Ap;
-    const float dt = (float)(dtau_dev ? *dtau_dev : dtau);
     unsigned in_e2 = 0;
     auto cur = [&](int l) { return ((in_e2 >> l) & 1u) ? A.lev[l].e2 : A.lev[l].e; };
     auto set = [&](int l, const Soa32& s) {
@@ -465,7 +485,7 @@ __global__ __launch_bounds__(256) void k_mx_tail(const TailArgs32* __restrict__ 
     };
     for (int l = A.lt; l < A.L; ++l) {
         const TailLevel32& T = A.lev[l];
-        const int64_t n = (int64_t)T.L.nx * T.L.ny;
+        const uint32_t n = (uint32_t)T.L.nx * (uint32_t)T.L.ny;
         if (l > A.lt) {
             const TailLevel32& F = A.lev[l - 1];
             const Soa32 ef = cur(l - 1);
@@ -478,15 +498,16 @@ __global__ __launch_bounds__(256) void k_mx_tail(const TailArgs32* __restrict__ 
                     out[m] = out[keep[m]];
                 }
             }
-            for (int64_t k = threadIdx.x; k < n; k += blockDim.x)
-                mx_restrict_cell<DIM, DIM == 2 ? 12 : 9>(F.L.nx, F.L.ny, A.px, A.py, in, out, k);
+            for (uint32_t k = threadIdx.x; k < n; k += blockDim.x)
+                mx_restrict_cell<DIM, DIM == 2 ? 12 : 9>(F.L.nx, F.L.ny, F.L.sh, A.px, A.py, in, out, k);
             __syncthreads();
         }
         set(l, mx_tail_pseudo<DIM>(A, T, dt, T.d, true));
         if (l < A.L - 1) {
             const Soa32 e = cur(l);
-            for (int64_t k = threadIdx.x; k < n; k += blockDim.x) {
-                const int j = (int)(k / T.L.nx), i = (int)(k - (int64_t)j * T.L.nx);
+            for (uint32_t k = threadIdx.x; k < n; k += blockDim.x) {
+                int i, j;
+                ij_of(T.L.nx, T.L.sh, k, i, j);
                 mx_apply_cell<DIM>(A.ph, T.L, cs(T.w), cs(e), cs(T.g), -1.0f, T.rho, k, i, j);
             }
             __syncthreads();
@@ -495,22 +516,23 @@ __global__ __launch_bounds__(256) void k_mx_tail(const TailArgs32* __restrict__ 
     for (int l = A.L - 2; l >= A.lt; --l) {
         const TailLevel32& T = A.lev[l];
         const TailLevel32& C = A.lev[l + 1];
-        const int64_t n = (int64_t)T.L.nx * T.L.ny;
+        const uint32_t n = (uint32_t)T.L.nx * (uint32_t)T.L.ny;
         const Soa32 e = cur(l), ec = cur(l + 1);
-        for (int64_t k = threadIdx.x; k < n; k += blockDim.x)
-            mx_prolong_cell<DIM>(A.ph, T.L.nx, T.L.ny, A.px, A.py, (float)A.eta, cs(T.w), cs(e), cs(ec), cs(C.d), e, k);
+        for (uint32_t k = threadIdx.x; k < n; k += blockDim.x)
+            mx_prolong_cell<DIM>(A.ph, T.L.nx, T.L.ny, T.L.sh, A.px, A.py, (float)A.eta, cs(T.w), cs(e), cs(ec),
+                                 cs(C.d), e, k);
         __syncthreads();
         set(l, mx_tail_pseudo<DIM>(A, T, dt, e, false));
     }
     const TailLevel32& T = A.lev[A.lt];
     const Soa32 res = cur(A.lt);
     if (res.E != T.e.E) {
-        const int64_t n = (int64_t)T.L.nx * T.L.ny;
-        for (int64_t k = threadIdx.x; k < n; k += blockDim.x) {
-            T.e.E[k] = res.E[k];
-            T.e.Fx[k] = res.Fx[k];
-            if (DIM == 2) T.e.Fy[k] = res.Fy[k];
-            T.e.T[k] = res.T[k];
+        const uint32_t n = (uint32_t)T.L.nx * (uint32_t)T.L.ny;
+        for (uint32_t k = threadIdx.x; k < n; k += blockDim.x) {
+            stf(T.e.E, k, ldf(res.E, k));
+            stf(T.e.Fx, k, ldf(res.Fx, k));
+            if (DIM == 2) stf(T.e.Fy, k, ldf(res.Fy, k));
+            stf(T.e.T, k, ldf(res.T, k));
         }
     }
 }
@@ -557,13 +579,15 @@ void launch_mx_pseudo(hipStream_t st, int dim, const Phys& ph, const Lvl32& L, C
 void launch_mx_prolong(hipStream_t st, int dim, const Phys& ph, int nx, int ny, int px, int py, float eta, CSoa32 w,
                        CSoa32 e, CSoa32 ec, CSoa32 dc, Soa32 out, const int* active)
 {
-    MX_DISPATCH(dim, k_mx_prolong, nblk((int64_t)nx * ny), ph, nx, ny, px, py, eta, w, e, ec, dc, out, active);
+    MX_DISPATCH(dim, k_mx_prolong, nblk((int64_t)nx * ny), ph, nx, ny, row_shift(nx), px, py, eta, w, e, ec, dc, out,
+                active);
 }
 
 void launch_mx_prolong_fine(hipStream_t st, int dim, const Phys& ph, int nx, int ny, int px, int py, double eta,
                             CSoa v, CSoa32 e, CSoa32 ec, CSoa32 dc, Soa32 out, const int* active)
 {
-    MX_DISPATCH(dim, k_mx_prolong_fine, nblk((int64_t)nx * ny), ph, nx, ny, px, py, eta, v, e, ec, dc, out, active);
+    MX_DISPATCH(dim, k_mx_prolong_fine, nblk((int64_t)nx * ny), ph, nx, ny, row_shift(nx), px, py, eta, v, e, ec, dc,
+                out, active);
 }
 
 void launch_mx_restrict(hipStream_t st, int dim, int nxf, int nyf, int px, int py, const Fields32& F,
@@ -571,12 +595,13 @@ void launch_mx_restrict(hipStream_t st, int dim, int nxf, int nyf, int px, int p
 {
     const int64_t nc = (int64_t)(nxf / 2) * (dim == 2 ? nyf / 2 : 1);
     const dim3 g(nblk(nc)), b(kBlock32);
+    const int shf = row_shift(nxf);
     if (dim == 2) {
-        if (F.n == 12) hipLaunchKernelGGL((k_mx_restrict<2, 12>), g, b, 0, st, nxf, nyf, px, py, F, active);
-        else hipLaunchKernelGGL((k_mx_restrict<2, 2>), g, b, 0, st, nxf, nyf, px, py, F, active);
+        if (F.n == 12) hipLaunchKernelGGL((k_mx_restrict<2, 12>), g, b, 0, st, nxf, nyf, shf, px, py, F, active);
+        else hipLaunchKernelGGL((k_mx_restrict<2, 2>), g, b, 0, st, nxf, nyf, shf, px, py, F, active);
     } else {
-        if (F.n == 9) hipLaunchKernelGGL((k_mx_restrict<1, 9>), g, b, 0, st, nxf, nyf, px, py, F, active);
-        else hipLaunchKernelGGL((k_mx_restrict<1, 2>), g, b, 0, st, nxf, nyf, px, py, F, active);
+        if (F.n == 9) hipLaunchKernelGGL((k_mx_restrict<1, 9>), g, b, 0, st, nxf, nyf, shf, px, py, F, active);
+        else hipLaunchKernelGGL((k_mx_restrict<1, 2>), g, b, 0, st, nxf, nyf, shf, px, py, F, active);
     }
 }
 

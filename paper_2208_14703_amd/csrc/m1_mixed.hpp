@@ -29,9 +29,20 @@ struct CSoa32 {
 };
 __host__ __device__ inline CSoa32 cs(const Soa32& s) { return CSoa32{s.E, s.Fx, s.Fy, s.T}; }
 
+// FP32 field element k: base plus 32-bit byte offset (as ld/st for FP64).
+__device__ __forceinline__ float ldf(const float* p, uint32_t k)
+{
+    return *reinterpret_cast<const float*>(reinterpret_cast<const char*>(p) + (k << 2));
+}
+__device__ __forceinline__ void stf(float* p, uint32_t k, float x)
+{
+    *reinterpret_cast<float*>(reinterpret_cast<char*>(p) + (k << 2)) = x;
+}
+
 // One level in the FP32 path: spacing data as for FP64, opacities in FP32.
 struct Lvl32 {
     int nx, ny;
+    int sh;  // log2(nx) when nx is a power of two, else -1
     float kx, ky, a, cdt;
     const float* sa;
     const float* ss;
@@ -84,42 +95,33 @@ __device__ __forceinline__ DP closure_inc(float c, float c2, float E, float Fx, 
 
 // Ghost of a neighbour in increment form: the base ghost follows the boundary
 // rule of the side; the correction ghost is its linear part (0 for Dirichlet).
+// Branch-free like nb_state: unconditional loads, exact arithmetic selects.
 template <int DIM>
-__device__ __forceinline__ void nb_inc(const Phys& ph, int side, bool inside, int64_t kn, int64_t kc,
+__device__ __forceinline__ void nb_inc(const Phys& ph, int side, bool inside, uint32_t kn, uint32_t kc,
                                        const CSoa32& w, const CSoa32& d, float& E, float& Fx, float& Fy, float& e,
                                        float& gx, float& gy)
 {
-    int64_t k = kn;
-    const int kind = inside ? BC_PERIODIC : ph.bc[side];
-    if (kind == BC_DIRICHLET) {
-        E = (float)ph.bcE[side];
-        Fx = (float)ph.bcFx[side];
-        Fy = (float)ph.bcFy[side];
-        e = gx = gy = 0.0f;
-        return;
-    }
-    if (kind != BC_PERIODIC) k = kc;
-    E = w.E[k];
-    Fx = w.Fx[k];
-    Fy = (DIM == 2) ? w.Fy[k] : 0.0f;
-    e = d.E[k];
-    gx = d.Fx[k];
-    gy = (DIM == 2) ? d.Fy[k] : 0.0f;
-    if (kind == BC_REFLECTIVE) {
-        if (side < 2) {
-            Fx = -Fx;
-            gx = -gx;
-        } else {
-            Fy = -Fy;
-            gy = -gy;
-        }
-    }
+    const int kind = ph.bc[side];
+    const bool ghost = !inside && kind != BC_PERIODIC;
+    const uint32_t k = ghost ? kc : kn;
+    const float lE = ldf(w.E, k), lFx = ldf(w.Fx, k), lFy = (DIM == 2) ? ldf(w.Fy, k) : 0.0f;
+    const float le = ldf(d.E, k), lgx = ldf(d.Fx, k), lgy = (DIM == 2) ? ldf(d.Fy, k) : 0.0f;
+    const bool dir = ghost && kind == BC_DIRICHLET;
+    const bool flip = ghost && kind == BC_REFLECTIVE;
+    const float keep = dir ? 0.0f : 1.0f;
+    const float sx = (flip && side < 2) ? -keep : keep, sy = (flip && side >= 2) ? -keep : keep;
+    E = fmaf(keep, lE, dir ? (float)ph.bcE[side] : 0.0f);
+    Fx = fmaf(sx, lFx, dir ? (float)ph.bcFx[side] : 0.0f);
+    Fy = fmaf(sy, lFy, dir ? (float)ph.bcFy[side] : 0.0f);
+    e = keep * le;
+    gx = sx * lgx;
+    gy = sy * lgy;
 }
 
 // Increment of the off-diagonal sum, dS = S(w + d) - S(w).
 template <int DIM>
 __device__ __forceinline__ void offdiag_inc(const Phys& ph, const Lvl32& L, const CSoa32& w, const CSoa32& d, int i,
-                                            int j, int64_t k, float& S0, float& S1, float& S2)
+                                            int j, uint32_t k, float& S0, float& S1, float& S2)
 {
     const float c = (float)ph.c, c2 = (float)ph.c2;
     float E, Fx, Fy, e, gx, gy;
@@ -133,12 +135,13 @@ __device__ __forceinline__ void offdiag_inc(const Phys& ph, const Lvl32& L, cons
         S1 = fmaf(kk, fmaf(sgn, G1, c * gx), S1);
         S2 = fmaf(kk, fmaf(sgn, G2, c * gy), S2);
     };
-    nb_inc<DIM>(ph, 0, i > 0, i > 0 ? k - 1 : k + (L.nx - 1), k, w, d, E, Fx, Fy, e, gx, gy);
+    const uint32_t wx = (uint32_t)(L.nx - 1);
+    nb_inc<DIM>(ph, 0, i > 0, i > 0 ? k - 1 : k + wx, k, w, d, E, Fx, Fy, e, gx, gy);
     add(L.kx, +1.0f, true);
-    nb_inc<DIM>(ph, 1, i < L.nx - 1, i < L.nx - 1 ? k + 1 : k - (L.nx - 1), k, w, d, E, Fx, Fy, e, gx, gy);
+    nb_inc<DIM>(ph, 1, i < L.nx - 1, i < L.nx - 1 ? k + 1 : k - wx, k, w, d, E, Fx, Fy, e, gx, gy);
     add(L.kx, -1.0f, true);
     if (DIM == 2) {
-        const int64_t nx = L.nx, wrap = (int64_t)(L.ny - 1) * nx;
+        const uint32_t nx = (uint32_t)L.nx, wrap = (uint32_t)(L.ny - 1) * nx;
         nb_inc<DIM>(ph, 2, j > 0, j > 0 ? k - nx : k + wrap, k, w, d, E, Fx, Fy, e, gx, gy);
         add(L.ky, +1.0f, false);
         nb_inc<DIM>(ph, 3, j < L.ny - 1, j < L.ny - 1 ? k + nx : k - wrap, k, w, d, E, Fx, Fy, e, gx, gy);
@@ -176,12 +179,12 @@ __device__ __forceinline__ void local_solve_inc(double beta, double gamma, doubl
                                                 double tg, float& xE, float& xFx, float& xFy, float& xT)
 {
     const double dE = fma(gamma, a + ka, beta);
-    const double iF = 1.0 / fma(gamma, ks, dE);
+    const double iF = rcp64(fma(gamma, ks, dE));
     xFx = (float)(QFx * iF);
     xFy = (float)(QFy * iF);
     const double k = gamma * ka;
     const double cT = (beta + gamma) * cv;
-    const double idE = 1.0 / dE;
+    const double idE = rcp64(dE);
     if (k == 0.0) {
         xT = (float)(QT / cT);
         xE = (float)(QE * idE);
@@ -199,7 +202,7 @@ __device__ __forceinline__ void local_solve_inc(double beta, double gamma, doubl
         const double Tx = T + x;
         const double g = fma(K, quartic_inc(T, x), fma(cT, x, -Q));
         const double dg = fma(4.0 * K * Tx * Tx, Tx, cT);
-        const double xn = fmin(x - g / dg, up);
+        const double xn = fmin(fma(-g, rcp64(dg), x), up);
         const bool done = fabs(xn - x) <= 1e-13 * fmax(fabs(xn), 1e-30 * T) || fabs(xn - x) <= 1e-15 * T;
         x = xn;
         if (done) break;
