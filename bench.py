@@ -21,8 +21,8 @@ The same JSON line also carries:
   of the same workload.
 - batched: 256 independent problems of uneven size, seeded 1000+k, side log-uniform in
   {64..512}, one implicit step each to 1e-8. They are solved by the batching engine (one
-  launch per level operation) and, for comparison, one by one with the plain FP64 path.
-  It reports solves/s and per-problem latency p50/p99.
+  launch per level operation) in FP64 and in mixed precision and, for comparison, one by
+  one with the plain FP64 path. It reports solves/s and per-problem latency p50/p99.
 - serving: a short Poisson request stream through the engine's serving loop (sides 64..2048,
   1..20 steps per request, contrast 10^0..10^6). It reports solves/s and request latency
   p50/p99.
@@ -73,6 +73,7 @@ def parse():
     ap.add_argument("--requests", type=int, default=48, help="requests per rate in the serving leg")
     ap.add_argument("--rates", default="50", help="comma-separated arrival rates (1/s) for serving")
     ap.add_argument("--arena-gb", type=float, default=64.0, help="engine HBM budget for serving")
+    ap.add_argument("--serve-precision", default="mixed", choices=["fp64", "mixed"])
     ap.add_argument("--profile", default="none", choices=["none", "sweeps"],
                     help="sweeps: only sweep launches and a copy of known size (for counter runs)")
     ap.add_argument("--reps", type=int, default=40, help="sweep launches timed for the roofline")
@@ -153,35 +154,14 @@ def pct(x, q):
 # batched leg: many problems of uneven size
 # ---------------------------------------------------------------------------
 def batch_leg(torch, nprob: int):
-    params = dict(rtol=1e-8, max_cycles=20000, **SOLVER)
+    base = dict(rtol=1e-8, max_cycles=20000, **SOLVER)
     cases = [inputs.batch_problem(k) for k in range(nprob)]
     sig_d = [binding.to_device(c[2]) for c in cases]
     v0_d = [binding.to_device(c[1]) for c in cases]
     cells = sum(c[0]["nx"] * c[0]["ny"] for c in cases)
-    need = sum(binding.Engine.request_bytes(c[0], params) for c in cases)
-    E = binding.Engine(need + (256 << 20), params, max_requests=nprob)
 
-    def engine_run(idx):
-        vs = [v0_d[i].clone() for i in idx]
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        tk = [E.submit(cases[i][0], sig_d[i], v, 1) for i, v in zip(idx, vs)]
-        pending = set(tk)
-        while pending:
-            E.run(4)
-            pending = {t for t in pending if E.poll(t) is None}
-        torch.cuda.synchronize()
-        wall = time.perf_counter() - t0
-        infos = [E.poll(t) for t in tk]
-        lat = [E.times(t)[2] - E.times(t)[0] for t in tk]
-        for t in tk:
-            E.release(t)
-        return vs, infos, lat, wall
-
-    engine_run(list(range(min(8, nprob))))  # warm-up (module load, first launches)
-    vs, infos, lat, wall = engine_run(list(range(nprob)))
     # the plain FP64 path, one problem after another (plans made before the clock starts)
-    plans = [binding.Plan(c[0], s, params) for c, s in zip(cases, sig_d)]
+    plans = [binding.Plan(c[0], s, base) for c, s in zip(cases, sig_d)]
     ws = [v.clone() for v in v0_d]
     plans[0].step(v0_d[0].clone(), 1)
     torch.cuda.synchronize()
@@ -189,29 +169,60 @@ def batch_leg(torch, nprob: int):
     seq_info = [p.step(w, 1) for p, w in zip(plans, ws)]
     torch.cuda.synchronize()
     seq_wall = time.perf_counter() - t0
-    same = all(torch.equal(a, b) for a, b in zip(vs, ws))
-    ndiff = sum(not torch.equal(a, b) for a, b in zip(vs, ws))
-    maxrel = max(float(((a - b).abs().amax(dim=(1, 2)) / b.abs().amax(dim=(1, 2))).max()) for a, b in zip(vs, ws))
-    cyc_diff = sum(i["cycles"] != j["cycles"] for i, j in zip(infos, seq_info))
-    ok = all(i["status"] == 0 for i in infos) and all(i["status"] == 0 for i in seq_info)
-    del plans, E
-    return {"workload": f"{nprob} problems seeded 1000+k, side log-uniform in 64..512 "
-                        f"({cells / 1e6:.1f} M cells), 1 implicit step each to 1e-8, FP64",
-            "solves_per_s": round(nprob / wall, 2), "wall_s": round(wall, 4),
-            "latency_p50_ms": round(pct(lat, 50) * 1e3, 2), "latency_p99_ms": round(pct(lat, 99) * 1e3, 2),
-            "Mcell_updates_per_s": round(cells / wall / 1e6, 2),
-            "plain_fp64_one_by_one_solves_per_s": round(nprob / seq_wall, 2),
-            "speedup_vs_plain": round(seq_wall / wall, 3),
-            "bitwise_equal_to_plain": bool(same), "problems_differing": ndiff, "max_rel_diff": maxrel,
-            "cycle_count_mismatches": cyc_diff, "all_converged": bool(ok),
-            "cycles_mean": round(float(np.mean([i["cycles"] for i in infos])), 2)}
+    del plans
+    torch.cuda.empty_cache()
+    out = {"workload": f"{nprob} problems seeded 1000+k, side log-uniform in 64..512 ({cells / 1e6:.1f} M cells), "
+                       f"1 implicit step each to 1e-8",
+           "plain_fp64_one_by_one": {"solves_per_s": round(nprob / seq_wall, 2), "wall_s": round(seq_wall, 4),
+                                     "all_converged": all(i["status"] == 0 for i in seq_info)}}
+
+    for prec in ("fp64", "mixed"):
+        params = dict(base, precision=prec)
+        need = sum(binding.Engine.request_bytes(c[0], params) for c in cases)
+        E = binding.Engine(need + (256 << 20), params, max_requests=nprob)
+
+        def engine_run(idx):
+            vs = [v0_d[i].clone() for i in idx]
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            tk = [E.submit(cases[i][0], sig_d[i], v, 1) for i, v in zip(idx, vs)]
+            pending = set(tk)
+            while pending:
+                E.run(4)
+                pending = {t for t in pending if E.poll(t) is None}
+            torch.cuda.synchronize()
+            wall = time.perf_counter() - t0
+            infos = [E.poll(t) for t in tk]
+            lat = [E.times(t)[2] - E.times(t)[0] for t in tk]
+            for t in tk:
+                E.release(t)
+            return vs, infos, lat, wall
+
+        engine_run(list(range(min(8, nprob))))  # warm-up (module load, first launches)
+        vs, infos, lat, wall = engine_run(list(range(nprob)))
+        rel = max(float(((a - b).abs().amax(dim=(1, 2)) / b.abs().amax(dim=(1, 2))).max()) for a, b in zip(vs, ws))
+        res = {"solves_per_s": round(nprob / wall, 2), "wall_s": round(wall, 4),
+               "latency_p50_ms": round(pct(lat, 50) * 1e3, 2), "latency_p99_ms": round(pct(lat, 99) * 1e3, 2),
+               "Mcell_updates_per_s": round(cells / wall / 1e6, 2),
+               "speedup_vs_plain_fp64": round(seq_wall / wall, 3),
+               "max_rel_diff_vs_plain_fp64": rel,
+               "all_converged": all(i["status"] == 0 for i in infos),
+               "cycles_mean": round(float(np.mean([i["cycles"] for i in infos])), 2)}
+        if prec == "fp64":
+            res["bitwise_equal_to_plain"] = all(torch.equal(a, b) for a, b in zip(vs, ws))
+            res["cycle_count_mismatches"] = sum(i["cycles"] != j["cycles"] for i, j in zip(infos, seq_info))
+        out[prec] = res
+        del E, vs
+        torch.cuda.empty_cache()
+    return out
 
 
 # ---------------------------------------------------------------------------
 # serving leg: a Poisson request stream through the serving loop
 # ---------------------------------------------------------------------------
-def serve_leg(torch, nreq: int, rate: float, arena_bytes: int, seed: int = 7):
-    params = dict(rtol=1e-8, max_cycles=20000, **SOLVER)
+def serve_leg(torch, nreq: int, rate: float, arena_bytes: int, precision: str = "mixed", compare_plain: bool = True,
+              seed: int = 7):
+    params = dict(rtol=1e-8, max_cycles=20000, precision=precision, **SOLVER)
     rng = np.random.Generator(np.random.PCG64(seed))
     reqs = [inputs.serve_request(rng) for _ in range(nreq)]
     arr = np.cumsum(np.random.Generator(np.random.PCG64(seed + 1)).exponential(1.0 / rate, nreq))
@@ -242,14 +253,31 @@ def serve_leg(torch, nreq: int, rate: float, arena_bytes: int, seed: int = 7):
     overlapped = sum(1 for k in range(1, len(adm)) if adm[k][0] < max(d for _, d in adm[:k]))
     ok = all(i["status"] == 0 for i in infos)
     del E
-    return {"rate_per_s": rate, "requests": nreq, "solves": solves, "solves_per_s": round(solves / span, 2),
+    plain = None
+    if compare_plain:
+        # the same requests, one after another, each on a plain FP64 plan (plans made in the timed region,
+        # as a server without the engine would have to)
+        base = dict(rtol=1e-8, max_cycles=20000, **SOLVER)
+        vs = [binding.to_device(r[1]) for r in reqs]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for r, sd, vd in zip(reqs, sig_d, vs):
+            binding.Plan(r[0], sd, base).step(vd, r[3]["steps"])
+        torch.cuda.synchronize()
+        pw = time.perf_counter() - t0
+        rel = max(float(((a - b).abs().amax(dim=(1, 2)) / b.abs().amax(dim=(1, 2))).max()) for a, b in zip(v_d, vs))
+        plain = {"solves_per_s": round(solves / pw, 2), "wall_s": round(pw, 2), "max_rel_diff_served_vs_plain": rel}
+        del vs
+    return {"precision": precision, "rate_per_s": rate, "requests": nreq, "solves": solves,
+            "solves_per_s": round(solves / span, 2),
             "requests_per_s": round(nreq / span, 3), "Mcell_updates_per_s": round(cell_steps / span / 1e6, 2),
             "latency_p50_ms": round(pct(lat, 50) * 1e3, 1), "latency_p99_ms": round(pct(lat, 99) * 1e3, 1),
-            "admitted_while_others_ran": overlapped, "all_converged": bool(ok), "wall_s": round(span, 2)}
+            "admitted_while_others_ran": overlapped, "all_converged": bool(ok), "wall_s": round(span, 2),
+            "plain_fp64_one_request_at_a_time": plain}
 
 
 SERVE_DESC = ("Poisson stream, side log-uniform in 64..2048, contrast 10^U[0,6], 1..20 steps per request to 1e-8, "
-              "FP64, state resident in HBM across steps, continuous batching under an HBM budget")
+              "state resident in HBM across steps, continuous batching under an HBM budget")
 
 
 # ---------------------------------------------------------------------------
@@ -265,12 +293,14 @@ def main():
         torch.cuda.set_stream(torch.cuda.Stream())
 
     if args.workload == "serve":
-        legs = [serve_leg(torch, args.requests, float(r), int(args.arena_gb * (1 << 30)))
-                for r in args.rates.split(",")]
+        legs = [serve_leg(torch, args.requests, float(r), int(args.arena_gb * (1 << 30)), args.serve_precision,
+                          compare_plain=(k == 0))
+                for k, r in enumerate(args.rates.split(","))]
         best = max(legs, key=lambda x: x["solves_per_s"])
         print(json.dumps({"metric": METRIC, "value": best["solves_per_s"], "unit": "solves/s", "n_gpus": 1,
                           "steps": 1, "warmup": 1, "ms_per_step": round(best["wall_s"] * 1e3, 1),
-                          "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+                          "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+                          "dtype": "f64" if args.serve_precision == "fp64" else "f64+f32",
                           "data": "synthetic", "config": {"workload": SERVE_DESC, "arena_gb": args.arena_gb},
                           "rates": legs}), flush=True)
         return
@@ -344,7 +374,7 @@ def main():
         out["batched"] = batch_leg(torch, args.batch)
         torch.cuda.empty_cache()
         out["serving"] = {"workload": SERVE_DESC, **serve_leg(torch, args.requests, float(args.rates.split(",")[0]),
-                                                              int(args.arena_gb * (1 << 30)))}
+                                                              int(args.arena_gb * (1 << 30)), args.serve_precision)}
     print(json.dumps(out), flush=True)
 
 

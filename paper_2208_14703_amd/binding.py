@@ -73,6 +73,10 @@ def lib():
     """Load libm1mg.so (raises when it has not been built)."""
     global _lib
     if _lib is None:
+        # The library must bind to the HIP runtime that torch uses (torch ships its own
+        # copy): load torch's first, or the process ends up with two runtimes and the
+        # library sees no device.
+        import torch  # noqa: F401
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_2208_14703_amd.build.build() "
                                "(there is no CPU fallback)")

@@ -660,6 +660,7 @@ m1_status m1_plan_create(const m1_grid* g, const m1_params* p, const m1_opacity*
         fix.active = 1;
         fix.dtau = P->params.dtau_im0;
         m1::launch_ctrl_init(P->st, P->dfix, fix);
+        m1::launch_ctrl_init(P->st, P->dctrl, m1::Ctrl{});  // stopped, state in x0
     }
     m1_status st = hip_status(hipMemsetAsync(P->dbad, 0xff, sizeof(unsigned long long), P->st));
     if (st == M1_OK) {
@@ -967,8 +968,11 @@ struct m1_engine {
     int maxp = 0;
     m1::BProb* dP = nullptr;
     m1::BSlot* dS = nullptr;
+    m1::BSlot32* dS32 = nullptr;  // mixed precision: FP32 buffers per (problem, level)
     uint32_t* dWL = nullptr;
     size_t wl_cap = 0;
+    uint32_t* dWL2 = nullptr;     // fine tiles of step starts and of result copies
+    bool mixed = false;
     int* dPL = nullptr;
     m1::Ctrl* dCtrl = nullptr;
     m1::Ctrl* hCtrl = nullptr;
@@ -987,7 +991,7 @@ struct m1_engine {
     std::vector<List> restr, pdown, up;
     int n_all = 0, n_tail = 0;
     int Lmax = 1;
-    std::vector<uint32_t> hwl;
+    std::vector<uint32_t> hwl, hwl2;
     std::vector<int> hpl;
     // serving loop
     int device = 0;
@@ -1113,6 +1117,7 @@ m1_status rebuild(m1_engine& E)
     const int np = (int)E.running.size();
     std::vector<m1::BProb> hp(np);
     std::vector<m1::BSlot> hs((size_t)np * m1::kMaxLevels);
+    std::vector<m1::BSlot32> hs32(E.mixed ? (size_t)np * m1::kMaxLevels : 0);
     E.Lmax = 1;
     for (int i = 0; i < np; ++i) {
         const m1_plan& P = *E.running[i]->plan;
@@ -1132,6 +1137,7 @@ m1_status rebuild(m1_engine& E)
         b.ctrl = P.dctrl;
         b.partials = P.partials;
         b.tail = P.dtail;
+        b.tail32 = P.dtail32;
         m1::Ctrl c{};
         c.dtau = rp.dtau_im0;
         c.rtol = rp.rtol;
@@ -1156,6 +1162,23 @@ m1_status rebuild(m1_engine& E)
                 s.x0 = to_soa(&E.running[i]->v);
                 s.x1 = P.tmp;
                 s.rf = P.rfine;
+            }
+            if (E.mixed) {
+                m1::BSlot32& t = hs32[(size_t)i * m1::kMaxLevels + l];
+                t.L = lv.L32;
+                t.w = lv.w;
+                t.d = lv.d;
+                t.e = lv.e;
+                t.e2 = lv.e2;
+                t.g = lv.gg;
+                t.rho = lv.rho;
+                if (l == 0) {
+                    t.base = P.base32;
+                    t.r32 = P.r32;
+                    t.dA = P.dA;
+                    t.dB = P.dB;
+                    t.rho0 = P.rho0;
+                }
             }
         }
         E.Lmax = std::max(E.Lmax, P.L);
@@ -1199,6 +1222,8 @@ m1_status rebuild(m1_engine& E)
         if (hipMemcpyAsync(E.dP, hp.data(), sizeof(m1::BProb) * np, hipMemcpyHostToDevice, E.st) != hipSuccess ||
             hipMemcpyAsync(E.dS, hs.data(), sizeof(m1::BSlot) * hs.size(), hipMemcpyHostToDevice, E.st) !=
                 hipSuccess ||
+            (E.mixed && hipMemcpyAsync(E.dS32, hs32.data(), sizeof(m1::BSlot32) * hs32.size(),
+                                       hipMemcpyHostToDevice, E.st) != hipSuccess) ||
             hipMemcpyAsync(E.dWL, E.hwl.data(), sizeof(uint32_t) * E.hwl.size(), hipMemcpyHostToDevice, E.st) !=
                 hipSuccess ||
             hipMemcpyAsync(E.dPL, E.hpl.data(), sizeof(int) * E.hpl.size(), hipMemcpyHostToDevice, E.st) != hipSuccess)
@@ -1206,6 +1231,21 @@ m1_status rebuild(m1_engine& E)
         if (hipStreamSynchronize(E.st) != hipSuccess) return M1_ERR_DEVICE;
     }
     E.dirty = false;
+    return M1_OK;
+}
+
+// Work list (uploaded to dWL2) of the finest-level tiles of the given running problems.
+m1_status fine_tiles(m1_engine& E, const std::vector<int>& idx)
+{
+    E.hwl2.clear();
+    for (int i : idx) {
+        const uint32_t nt = (uint32_t)((E.running[i]->plan->lev[0].n + 255) / 256);
+        for (uint32_t t = 0; t < nt; ++t) E.hwl2.push_back(((uint32_t)i << m1::kTileBits) | t);
+    }
+    if (E.hwl2.size() > E.wl_cap) return M1_ERR_BUDGET;
+    if (!E.hwl2.empty() && hipMemcpyAsync(E.dWL2, E.hwl2.data(), sizeof(uint32_t) * E.hwl2.size(),
+                                          hipMemcpyHostToDevice, E.st) != hipSuccess)
+        return M1_ERR_DEVICE;
     return M1_OK;
 }
 
@@ -1219,7 +1259,7 @@ void b_vcycle(m1_engine& E)
     int in_x1 = 0;
     for (int s = 0; s < nu0; ++s) {
         m1::launch_b_relax(E.st, E.dP, E.dS, wl + E.fine.off, E.fine.n, in_x1, s == 0);
-        if (s == 0) m1::launch_b_norm_control(E.st, E.dP, E.dPL, E.n_all);
+        if (s == 0) m1::launch_b_norm_control(E.st, E.dP, E.dPL, E.n_all, 0);
         in_x1 ^= 1;
     }
     m1::launch_b_apply(E.st, E.dP, E.dS, wl + E.up[0].off, E.up[0].n, 0, in_x1);
@@ -1253,6 +1293,54 @@ void b_vcycle(m1_engine& E)
     }
 }
 
+// One mixed-precision V-cycle of every running problem (the same sequence as
+// the single-problem mixed cycle).  Fine corrections alternate dA (0) / dB (1):
+// the pre-sweeps start from zero writing dA; coarse levels go d -> e / e2 with
+// the down leg ending in e and the up leg in e2 (odd pseudo_steps).
+void bm_vcycle(m1_engine& E)
+{
+    const int nu0 = E.params.nu0, m = E.params.pseudo_steps;
+    const uint32_t* wl = E.dWL;
+    const int pend = (nu0 % 2 == 1) ? 1 : 0;  // where the post-sweeps leave the correction
+    m1::launch_bm_resid(E.st, E.dP, E.dS, E.dS32, wl + E.fine.off, E.fine.n, pend);
+    m1::launch_b_norm_control(E.st, E.dP, E.dPL, E.n_all, 1);
+    int d = 1;
+    for (int s = 0; s < nu0; ++s) {
+        const int out = d ^ 1;
+        m1::launch_bm_sweep(E.st, E.dP, E.dS32, wl + E.fine.off, E.fine.n, d, out, s == 0);
+        d = out;
+    }
+    const int d0 = d;
+    m1::launch_bm_apply(E.st, E.dP, E.dS32, wl + E.up[0].off, E.up[0].n, 0, d0);
+    for (int l = 1; l < E.Lmax; ++l) {
+        m1::launch_bm_restrict(E.st, E.dP, E.dS32, wl + E.restr[l].off, E.restr[l].n, l, d0);
+        int in = 0;
+        for (int k = 0; k < m; ++k) {
+            const int out = (in == 1) ? 2 : 1;
+            m1::launch_bm_pseudo(E.st, E.dP, E.dS32, wl + E.pdown[l].off, E.pdown[l].n, l, in, out, k == 0);
+            in = out;
+        }
+        m1::launch_bm_apply(E.st, E.dP, E.dS32, wl + E.up[l].off, E.up[l].n, l, 1);
+    }
+    m1::launch_bm_tail(E.st, E.dP, E.dPL + E.n_all, E.n_tail);
+    for (int l = E.Lmax - 2; l >= 1; --l) {
+        m1::launch_bm_prolong(E.st, E.dP, E.dS32, wl + E.up[l].off, E.up[l].n, l);
+        int in = 1;
+        for (int k = 0; k < m; ++k) {
+            const int out = (in == 1) ? 2 : 1;
+            m1::launch_bm_pseudo(E.st, E.dP, E.dS32, wl + E.up[l].off, E.up[l].n, l, in, out, 0);
+            in = out;
+        }
+    }
+    m1::launch_bm_prolong_fine(E.st, E.dP, E.dS, E.dS32, wl + E.up[0].off, E.up[0].n, d0);
+    d = d0;
+    for (int s = 0; s < nu0; ++s) {
+        const int out = d ^ 1;
+        m1::launch_bm_sweep(E.st, E.dP, E.dS32, wl + E.fine.off, E.fine.n, d, out, 0);
+        d = out;
+    }
+}
+
 }  // namespace
 
 extern "C" {
@@ -1265,12 +1353,13 @@ m1_status m1_engine_create(const m1_params* p, void* arena, size_t arena_bytes, 
     if (!out) return M1_ERR_ARG;
     *out = nullptr;
     if (!valid_params(p) || max_requests < 1 || max_requests > (1 << (32 - m1::kTileBits)) ||
-        p->pseudo_steps % 2 == 0 || p->nu_l != 1 || p->precision != M1_FP64)
+        p->pseudo_steps % 2 == 0 || p->nu_l != 1)
         return M1_ERR_ARG;
     if (!arena || (reinterpret_cast<uintptr_t>(arena) % kAlign) != 0) return M1_ERR_WORKSPACE;
     m1_engine* E = new (std::nothrow) m1_engine();
     if (!E) return M1_ERR_DEVICE;
     E->params = *p;
+    E->mixed = p->precision == M1_MIXED;
     E->st = static_cast<hipStream_t>(stream);
     E->arena = static_cast<char*>(arena);
     E->arena_bytes = arena_bytes;
@@ -1290,8 +1379,13 @@ m1_status m1_engine_create(const m1_params* p, void* arena, size_t arena_bytes, 
     E->dS = reinterpret_cast<m1::BSlot*>(take(sizeof(m1::BSlot) * (size_t)max_requests * m1::kMaxLevels));
     E->dPL = reinterpret_cast<int*>(take(sizeof(int) * 3 * (size_t)max_requests));
     E->dCtrl = reinterpret_cast<m1::Ctrl*>(take(sizeof(m1::Ctrl) * max_requests));
-    E->wl_cap = std::max<size_t>(arena_bytes / 512, 1 << 16);
+    if (E->mixed)
+        E->dS32 = reinterpret_cast<m1::BSlot32*>(take(sizeof(m1::BSlot32) * (size_t)max_requests * m1::kMaxLevels));
+    // a 256-cell tile of a request's finest level needs more than 30 KB of its workspace and
+    // appears in at most a few work-list entries: one entry per 2 KB of arena is ample
+    E->wl_cap = std::max<size_t>(arena_bytes / 2048, 1 << 16);
     E->dWL = reinterpret_cast<uint32_t*>(take(sizeof(uint32_t) * E->wl_cap));
+    E->dWL2 = reinterpret_cast<uint32_t*>(take(sizeof(uint32_t) * E->wl_cap));
     if (off >= arena_bytes) {
         delete E;
         return M1_ERR_WORKSPACE;
@@ -1355,22 +1449,12 @@ m1_status m1_batch_run(m1_engine* E, int32_t cycles, int32_t* n_running, int32_t
 {
     if (!E || cycles < 1) return M1_ERR_ARG;
     std::lock_guard<std::mutex> lk(E->rmu);
-    // drop cancelled running requests
-    for (size_t i = 0; i < E->running.size();) {
-        m1_req* R = E->running[i];
-        if (R->cancel) {
-            finish(*E, R, M1_ERR_BUSY);
-            E->running.erase(E->running.begin() + i);
-            E->dirty = true;
-        } else {
-            ++i;
-        }
-    }
     admit(*E);
     m1_status st = M1_OK;
     if (!E->running.empty()) {
         if (E->dirty) st = rebuild(*E);
         if (st != M1_OK) return st;
+        // step starts: b, |b| and a fresh control per starting problem (state back in x0 first)
         std::vector<int> init;
         for (int i = 0; i < (int)E->running.size(); ++i)
             if (E->running[i]->need_init) {
@@ -1378,42 +1462,69 @@ m1_status m1_batch_run(m1_engine* E, int32_t cycles, int32_t* n_running, int32_t
                 E->running[i]->need_init = false;
             }
         if (!init.empty()) {
+            st = fine_tiles(*E, init);
+            if (st != M1_OK) return st;
             int* dinit = E->dPL + 2 * E->maxp;
             if (hipMemcpyAsync(dinit, init.data(), sizeof(int) * init.size(), hipMemcpyHostToDevice, E->st) !=
                 hipSuccess)
                 return M1_ERR_DEVICE;
-            m1::launch_b_step_init(E->st, E->dP, E->dS, dinit, (int)init.size());
+            m1::launch_b_init_tiles(E->st, E->dP, E->dS, E->dWL2, (int)E->hwl2.size());
+            m1::launch_b_init_ctrl(E->st, E->dP, E->dS, dinit, (int)init.size());
         }
-        for (int c = 0; c < cycles; ++c) b_vcycle(*E);
+        for (int c = 0; c < cycles; ++c) {
+            if (E->mixed) bm_vcycle(*E);
+            else b_vcycle(*E);
+        }
         const int np = (int)E->running.size();
         m1::launch_b_gather_ctrl(E->st, E->dP, np, E->dCtrl);
         if (hipMemcpyAsync(E->hCtrl, E->dCtrl, sizeof(m1::Ctrl) * np, hipMemcpyDeviceToHost, E->st) != hipSuccess ||
             hipStreamSynchronize(E->st) != hipSuccess || hipGetLastError() != hipSuccess)
             return M1_ERR_DEVICE;
+        // retire: cancelled, failed and completed requests leave with their state in x0
         std::vector<m1_req*> keep;
+        std::vector<std::pair<m1_req*, m1_status>> done;
+        std::vector<int> back;  // running indices whose state must be copied back from x1
         for (int i = 0; i < np; ++i) {
             m1_req* R = E->running[i];
             const m1::Ctrl& h = E->hCtrl[i];
-            if (h.active) {
-                keep.push_back(R);
-                continue;
+            bool cancel;
+            {
+                std::lock_guard<std::mutex> g(E->qmu);
+                cancel = R->cancel;
             }
-            R->cycles += std::max(h.cycles, 0);
-            R->rel = h.rel;
-            R->r0 = h.r0;
-            R->dtau = h.dtau;
-            if (!h.conv) {
-                finish(*E, R, M1_ERR_NO_CONVERGENCE);
-                continue;
+            if (!h.active || cancel) {
+                R->cycles += std::max(h.cycles, 0);
+                R->rel = h.rel;
+                R->r0 = h.r0;
+                R->dtau = h.dtau;
             }
-            R->steps_done += 1;
-            if (R->steps_done >= R->nsteps) {
-                finish(*E, R, M1_OK);
+            m1_status out = M1_OK;
+            bool leaves = false;
+            if (cancel) {
+                out = M1_ERR_BUSY;
+                leaves = true;
+            } else if (!h.active && !h.conv) {
+                out = M1_ERR_NO_CONVERGENCE;
+                leaves = true;
+            } else if (!h.active) {
+                R->steps_done += 1;
+                leaves = R->steps_done >= R->nsteps;
+                if (!leaves) R->need_init = true;
+            }
+            if (leaves) {
+                done.push_back({R, out});
+                if (h.flip) back.push_back(i);
             } else {
-                R->need_init = true;
                 keep.push_back(R);
             }
         }
+        if (!back.empty()) {
+            st = fine_tiles(*E, back);
+            if (st != M1_OK) return st;
+            m1::launch_b_flip_copy(E->st, E->dP, E->dS, E->dWL2, (int)E->hwl2.size());
+            if (hipStreamSynchronize(E->st) != hipSuccess || hipGetLastError() != hipSuccess) return M1_ERR_DEVICE;
+        }
+        for (auto& d : done) finish(*E, d.first, d.second);
         if (keep.size() != E->running.size()) E->dirty = true;
         E->running.swap(keep);
     }

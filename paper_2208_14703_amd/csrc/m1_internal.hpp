@@ -37,7 +37,8 @@ struct Fields32 {
 // the stopping test of the relative residual), updated after every V-cycle.
 struct Ctrl {
     double r0, rprev, dtau, rel, floor_r, rtol, eps_inc, eps_dec, dtau_min, dtau_max;
-    int active, cycles, conv, max_cycles, literal, pad_;
+    int active, cycles, conv, max_cycles, literal;
+    int flip;  // batched mixed precision: the FP64 state of the step is in x1 (toggled by every executed cycle)
 };
 
 // One level of the single-workgroup bottom of the V-cycle.
@@ -99,6 +100,13 @@ struct BSlot {
     Soa b, x0, x1, rf;    // level 0: rhs, the two iterate buffers (x0 = the request's state), residual
 };
 
+// One (problem, level) of a mixed-precision batch: the FP32 buffers of that level.
+struct BSlot32 {
+    Lvl32 L;
+    Soa32 w, d, e, e2, g, rho;      // level >= 1
+    Soa32 base, r32, dA, dB, rho0;  // level 0
+};
+
 // Per-problem data of a batch.
 struct BProb {
     Phys ph;
@@ -107,14 +115,26 @@ struct BProb {
     Ctrl* ctrl;
     double* partials;
     const TailArgs* tail;
+    const TailArgs32* tail32;  // mixed precision
     Ctrl proto;  // solver tolerances of this problem, copied into ctrl at every step start
 };
+
+// Batched kernels loop over a work list: block-stride over entries, skipping
+// problems whose step has stopped; k is the cell of the entry's 256-cell tile.
+#define M1_BATCH_LOOP(wl, nwl)                                          \
+    for (int w_ = blockIdx.x; w_ < (nwl); w_ += gridDim.x) {            \
+        const uint32_t item = (wl)[w_];                                 \
+        const int p = (int)(item >> kTileBits);                         \
+        const uint32_t tile = item & ((1u << kTileBits) - 1u);          \
+        const BProb& pb = P[p];                                         \
+        if (pb.ctrl->active == 0) continue;                             \
+        const uint32_t k = tile * 256u + threadIdx.x;
 
 // mixed precision (m1_mixed.hip)
 // batched FP64 kernels (m1_kernels.hip); `wl` is a work list of nwl entries,
 // `plist` a list of problem indices
 void launch_b_relax(hipStream_t st, const BProb* P, const BSlot* S, const uint32_t* wl, int nwl, int in_x1, int norm);
-void launch_b_norm_control(hipStream_t st, const BProb* P, const int* plist, int np);
+void launch_b_norm_control(hipStream_t st, const BProb* P, const int* plist, int np, int mixed);
 void launch_b_apply(hipStream_t st, const BProb* P, const BSlot* S, const uint32_t* wl, int nwl, int level, int in_sel);
 void launch_b_restrict(hipStream_t st, const BProb* P, const BSlot* S, const uint32_t* wl, int nwl, int level,
                        int in_sel);
@@ -123,7 +143,9 @@ void launch_b_pseudo(hipStream_t st, const BProb* P, const BSlot* S, const uint3
 void launch_b_prolong(hipStream_t st, const BProb* P, const BSlot* S, const uint32_t* wl, int nwl, int level,
                       int in_sel, int out_sel);
 void launch_b_tail(hipStream_t st, const BProb* P, const int* plist, int np);
-void launch_b_step_init(hipStream_t st, const BProb* P, const BSlot* S, const int* plist, int np);
+void launch_b_init_tiles(hipStream_t st, const BProb* P, const BSlot* S, const uint32_t* wl, int nwl);
+void launch_b_init_ctrl(hipStream_t st, const BProb* P, const BSlot* S, const int* plist, int np);
+void launch_b_flip_copy(hipStream_t st, const BProb* P, const BSlot* S, const uint32_t* wl, int nwl);
 void launch_b_gather_ctrl(hipStream_t st, const BProb* P, int np, Ctrl* out);
 
 void launch_mx_resid(hipStream_t st, int dim, const Phys& ph, const Lvl& L, double eta, CSoa v, CSoa32 d, CSoa b,
@@ -144,5 +166,23 @@ void launch_mx_restrict(hipStream_t st, int dim, int nxf, int nyf, int px, int p
 void launch_mx_tail(hipStream_t st, int dim, const TailArgs32* args_dev, double dtau, const double* dtau_dev,
                     const int* active);
 void launch_to_f32(hipStream_t st, int64_t n, const double* a, float* b);
+
+// batched mixed-precision kernels (m1_mixed.hip).  Fine-level selectors: the
+// FP64 state is x0 or x1 by ctrl->flip; sel 0/1 picks dA/dB.  Coarse levels:
+// sel 0 = d, 1 = e, 2 = e2.
+void launch_bm_resid(hipStream_t st, const BProb* P, const BSlot* S, const BSlot32* S32, const uint32_t* wl, int nwl,
+                     int pend_sel);
+void launch_bm_sweep(hipStream_t st, const BProb* P, const BSlot32* S32, const uint32_t* wl, int nwl, int in_sel,
+                     int out_sel, int from_zero);
+void launch_bm_apply(hipStream_t st, const BProb* P, const BSlot32* S32, const uint32_t* wl, int nwl, int level,
+                     int in_sel);
+void launch_bm_restrict(hipStream_t st, const BProb* P, const BSlot32* S32, const uint32_t* wl, int nwl, int level,
+                        int d0_sel);
+void launch_bm_pseudo(hipStream_t st, const BProb* P, const BSlot32* S32, const uint32_t* wl, int nwl, int level,
+                      int in_sel, int out_sel, int first);
+void launch_bm_prolong(hipStream_t st, const BProb* P, const BSlot32* S32, const uint32_t* wl, int nwl, int level);
+void launch_bm_prolong_fine(hipStream_t st, const BProb* P, const BSlot* S, const BSlot32* S32, const uint32_t* wl,
+                            int nwl, int e_sel);
+void launch_bm_tail(hipStream_t st, const BProb* P, const int* plist, int np);
 
 }  // namespace m1

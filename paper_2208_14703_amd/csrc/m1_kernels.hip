@@ -23,7 +23,6 @@ constexpr int kBlock = 256;
 // thread per cell, and 256 threads leave the per-cell body its full register
 // file (a 1024-thread bound caps it at 128 VGPRs and it spills).
 constexpr int kTailThreads = 256;
-constexpr int kStepThreads = 1024;
 
 static inline unsigned nblocks(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
 
@@ -209,19 +208,11 @@ __global__ void k_ctrl_init(Ctrl* ctrl, Ctrl init) { *ctrl = init; }
 //   level >= 1: sel 0 = v, 1 = u, 2 = u2.
 __device__ __forceinline__ const Soa& pick(const BSlot& s, int sel) { return sel == 0 ? s.v : (sel == 1 ? s.u : s.u2); }
 
-#define B_LOOP(wl, nwl)                                                     \
-    for (int w = blockIdx.x; w < (nwl); w += gridDim.x) {                   \
-        const uint32_t item = (wl)[w];                                      \
-        const int p = (int)(item >> kTileBits);                             \
-        const uint32_t tile = item & ((1u << kTileBits) - 1u);              \
-        const BProb& pb = P[p];                                             \
-        if (pb.ctrl->active == 0) continue;                                 \
-        const uint32_t k = tile * kBlock + threadIdx.x;
 
 __global__ __launch_bounds__(kBlock) void kb_relax(const BProb* __restrict__ P, const BSlot* __restrict__ S,
                                                    const uint32_t* __restrict__ wl, int nwl, int in_x1, int norm)
 {
-    B_LOOP(wl, nwl)
+    M1_BATCH_LOOP(wl, nwl)
     const BSlot& s = S[p * kMaxLevels];
     const Soa& in = in_x1 ? s.x1 : s.x0;
     const Soa& out = in_x1 ? s.x0 : s.x1;
@@ -239,19 +230,24 @@ __global__ __launch_bounds__(kBlock) void kb_relax(const BProb* __restrict__ P, 
 }
 
 // One block per problem: finish its residual norm and update its cycle control.
-__global__ __launch_bounds__(1024) void kb_norm_control(const BProb* __restrict__ P, const int* __restrict__ plist)
+// mixed: the cycle's residual kernel moved the FP64 state to the partner buffer.
+__global__ __launch_bounds__(1024) void kb_norm_control(const BProb* __restrict__ P, const int* __restrict__ plist,
+                                                        int mixed)
 {
     const BProb& pb = P[plist[blockIdx.x]];
     if (pb.ctrl->active == 0) return;
     const double r = sqrt(block_sum(pb.partials, pb.npart));
-    if (threadIdx.x == 0) ctrl_update(pb.ctrl, r);
+    if (threadIdx.x == 0) {
+        if (mixed) pb.ctrl->flip ^= 1;
+        ctrl_update(pb.ctrl, r);
+    }
 }
 
 // level 0: rf = b - A(x_cur);  level >= 1: rb = f - A(pick(in_sel)).
 __global__ __launch_bounds__(kBlock) void kb_apply(const BProb* __restrict__ P, const BSlot* __restrict__ S,
                                                    const uint32_t* __restrict__ wl, int nwl, int level, int in_sel)
 {
-    B_LOOP(wl, nwl)
+    M1_BATCH_LOOP(wl, nwl)
     const BSlot& s = S[p * kMaxLevels + level];
     if (k >= (uint32_t)s.L.nx * (uint32_t)s.L.ny) continue;
     int i, j;
@@ -265,7 +261,7 @@ __global__ __launch_bounds__(kBlock) void kb_apply(const BProb* __restrict__ P, 
 __global__ __launch_bounds__(kBlock) void kb_restrict(const BProb* __restrict__ P, const BSlot* __restrict__ S,
                                                       const uint32_t* __restrict__ wl, int nwl, int level, int in_sel)
 {
-    B_LOOP(wl, nwl)
+    M1_BATCH_LOOP(wl, nwl)
     const BSlot& c = S[p * kMaxLevels + level];
     const BSlot& f = S[p * kMaxLevels + level - 1];
     if (k >= (uint32_t)c.L.nx * (uint32_t)c.L.ny) continue;
@@ -281,7 +277,7 @@ __global__ __launch_bounds__(kBlock) void kb_pseudo(const BProb* __restrict__ P,
                                                     const uint32_t* __restrict__ wl, int nwl, int level, int in_sel,
                                                     int out_sel, int first)
 {
-    B_LOOP(wl, nwl)
+    M1_BATCH_LOOP(wl, nwl)
     const BSlot& s = S[p * kMaxLevels + level];
     if (k >= (uint32_t)s.L.nx * (uint32_t)s.L.ny) continue;
     int i, j;
@@ -304,7 +300,7 @@ __global__ __launch_bounds__(kBlock) void kb_prolong(const BProb* __restrict__ P
                                                      const uint32_t* __restrict__ wl, int nwl, int level, int in_sel,
                                                      int out_sel)
 {
-    B_LOOP(wl, nwl)
+    M1_BATCH_LOOP(wl, nwl)
     const BSlot& f = S[p * kMaxLevels + level];
     const BSlot& c = S[p * kMaxLevels + level + 1];
     if (k >= (uint32_t)f.L.nx * (uint32_t)f.L.ny) continue;
@@ -322,39 +318,80 @@ __global__ __launch_bounds__(kTailThreads) void kb_tail(const BProb* __restrict_
     tail_body<2>(*pb.tail, pb.ctrl->dtau);
 }
 
-// One block per problem: start a time step from the state in x0 -- b = (E, F,
-// C_v T), |b| for the rounding floor, and a fresh cycle control.
-__global__ __launch_bounds__(kStepThreads) void kb_step_init(const BProb* __restrict__ P, const BSlot* __restrict__ S,
+// Step start, per fine tile of the starting problems (their control is not
+// live): bring the state back to x0 when the previous step left it in x1
+// (mixed precision), form b = (E, F, C_v T) and the tile's partial of |b|^2,
+// with the same expression and reduction order as the single-problem path.
+__global__ __launch_bounds__(kBlock) void kb_init_tiles(const BProb* __restrict__ P, const BSlot* __restrict__ S,
+                                                        const uint32_t* __restrict__ wl, int nwl)
+{
+    for (int w_ = blockIdx.x; w_ < nwl; w_ += gridDim.x) {
+        const uint32_t item = wl[w_];
+        const int p = (int)(item >> kTileBits);
+        const uint32_t tile = item & ((1u << kTileBits) - 1u);
+        const BProb& pb = P[p];
+        const BSlot& s = S[p * kMaxLevels];
+        const uint32_t k = tile * kBlock + threadIdx.x;
+        double q = 0.0;
+        if (k < (uint32_t)s.L.nx * (uint32_t)s.L.ny) {
+            const bool fl = pb.ctrl->flip != 0;
+            const Soa& src = fl ? s.x1 : s.x0;
+            const double E = ld(src.E, k), Fx = ld(src.Fx, k), Fy = ld(src.Fy, k), T = ld(src.T, k);
+            if (fl) {
+                st(s.x0.E, k, E);
+                st(s.x0.Fx, k, Fx);
+                st(s.x0.Fy, k, Fy);
+                st(s.x0.T, k, T);
+            }
+            const double bT = pb.ph.c_v * T;
+            st(s.b.E, k, E);
+            st(s.b.Fx, k, Fx);
+            st(s.b.Fy, k, Fy);
+            st(s.b.T, k, bT);
+            const double ic = 1.0 / pb.ph.c;
+            const double fx = Fx * ic, fy = Fy * ic;
+            q = fma(E, E, fma(fx, fx, fma(fy, fy, bT * bT)));
+        }
+        block_partial(q, pb.partials + tile);
+    }
+}
+
+// One block per starting problem: |b| for the rounding floor and a fresh
+// cycle control (state in x0).
+__global__ __launch_bounds__(1024) void kb_init_ctrl(const BProb* __restrict__ P, const BSlot* __restrict__ S,
                                                      const int* __restrict__ plist)
 {
     const int p = plist[blockIdx.x];
     const BProb& pb = P[p];
-    const BSlot& s = S[p * kMaxLevels];
-    const int64_t n = (int64_t)s.L.nx * s.L.ny;
-    const double ic = 1.0 / pb.ph.c;
-    double q = 0.0;
-    for (int64_t k = threadIdx.x; k < n; k += blockDim.x) {
-        const double E = s.x0.E[k], Fx = s.x0.Fx[k], Fy = s.x0.Fy[k], T = pb.ph.c_v * s.x0.T[k];
-        s.b.E[k] = E;
-        s.b.Fx[k] = Fx;
-        s.b.Fy[k] = Fy;
-        s.b.T[k] = T;
-        q = fma(E, E, fma(Fx * ic, Fx * ic, fma(Fy * ic, Fy * ic, fma(T, T, q))));
-    }
-    // fixed-order block reduction of q (wave butterfly, then the 16 waves in order)
-    __shared__ double red[kStepThreads / 64];
-    for (int off = 32; off > 0; off >>= 1) q += __shfl_xor(q, off, 64);
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = q;
-    __syncthreads();
+    const double t = block_sum(pb.partials, pb.npart);
     if (threadIdx.x == 0) {
-        double t = 0.0;
-        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t += red[w];
         Ctrl c = pb.proto;
-        c.floor_r = 16.0 * DBL_EPSILON * s.L.a * sqrt(t);
+        c.floor_r = 16.0 * DBL_EPSILON * S[p * kMaxLevels].L.a * sqrt(t);
         c.active = 1;
         c.cycles = -1;
         c.conv = 0;
+        c.flip = 0;
         *pb.ctrl = c;
+    }
+}
+
+// x0 = x1 over the fine tiles of finished mixed-precision requests whose
+// result is in x1 (their control is not live).
+__global__ __launch_bounds__(kBlock) void kb_flip_copy(const BProb* __restrict__ P, const BSlot* __restrict__ S,
+                                                       const uint32_t* __restrict__ wl, int nwl)
+{
+    (void)P;
+    for (int w_ = blockIdx.x; w_ < nwl; w_ += gridDim.x) {
+        const uint32_t item = wl[w_];
+        const int p = (int)(item >> kTileBits);
+        const uint32_t tile = item & ((1u << kTileBits) - 1u);
+        const BSlot& s = S[p * kMaxLevels];
+        const uint32_t k = tile * kBlock + threadIdx.x;
+        if (k >= (uint32_t)s.L.nx * (uint32_t)s.L.ny) continue;
+        st(s.x0.E, k, ld(s.x1.E, k));
+        st(s.x0.Fx, k, ld(s.x1.Fx, k));
+        st(s.x0.Fy, k, ld(s.x1.Fy, k));
+        st(s.x0.T, k, ld(s.x1.T, k));
     }
 }
 
@@ -401,9 +438,9 @@ void launch_b_relax(hipStream_t st, const BProb* P, const BSlot* S, const uint32
 {
     if (nwl > 0) hipLaunchKernelGGL(kb_relax, dim3(bgrid(nwl)), dim3(kBlock), 0, st, P, S, wl, nwl, in_x1, norm);
 }
-void launch_b_norm_control(hipStream_t st, const BProb* P, const int* plist, int np)
+void launch_b_norm_control(hipStream_t st, const BProb* P, const int* plist, int np, int mixed)
 {
-    if (np > 0) hipLaunchKernelGGL(kb_norm_control, dim3(np), dim3(1024), 0, st, P, plist);
+    if (np > 0) hipLaunchKernelGGL(kb_norm_control, dim3(np), dim3(1024), 0, st, P, plist, mixed);
 }
 void launch_b_apply(hipStream_t st, const BProb* P, const BSlot* S, const uint32_t* wl, int nwl, int level, int in_sel)
 {
@@ -431,9 +468,17 @@ void launch_b_tail(hipStream_t st, const BProb* P, const int* plist, int np)
 {
     if (np > 0) hipLaunchKernelGGL(kb_tail, dim3(np), dim3(kTailThreads), 0, st, P, plist);
 }
-void launch_b_step_init(hipStream_t st, const BProb* P, const BSlot* S, const int* plist, int np)
+void launch_b_init_tiles(hipStream_t st, const BProb* P, const BSlot* S, const uint32_t* wl, int nwl)
 {
-    if (np > 0) hipLaunchKernelGGL(kb_step_init, dim3(np), dim3(kStepThreads), 0, st, P, S, plist);
+    if (nwl > 0) hipLaunchKernelGGL(kb_init_tiles, dim3(bgrid(nwl)), dim3(kBlock), 0, st, P, S, wl, nwl);
+}
+void launch_b_init_ctrl(hipStream_t st, const BProb* P, const BSlot* S, const int* plist, int np)
+{
+    if (np > 0) hipLaunchKernelGGL(kb_init_ctrl, dim3(np), dim3(1024), 0, st, P, S, plist);
+}
+void launch_b_flip_copy(hipStream_t st, const BProb* P, const BSlot* S, const uint32_t* wl, int nwl)
+{
+    if (nwl > 0) hipLaunchKernelGGL(kb_flip_copy, dim3(bgrid(nwl)), dim3(kBlock), 0, st, P, S, wl, nwl);
 }
 void launch_b_gather_ctrl(hipStream_t st, const BProb* P, int np, Ctrl* out)
 {

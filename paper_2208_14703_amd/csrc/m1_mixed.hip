@@ -83,63 +83,73 @@ __device__ __forceinline__ void nb_upd64(const Phys& ph, double eta, int side, b
     Fy = fma(sy, lFy, dir ? ph.bcFy[side] : 0.0);
 }
 
-// v_new = proj(v + d); r = b - A(v_new) (FP64); base32 = (float) v_new; r32 = (float) r;
-// optional block partials of |r|^2.  v and v_new must not alias (neighbours read v).
+// v_new = proj(v + d); r = b - A(v_new) (FP64); base32 = (float) v_new; r32 = (float) r.
+// Returns the cell's share of |r|^2.  v and v_new must not alias (neighbours read v).
+template <int DIM>
+__device__ __forceinline__ double mx_resid_cell(const Phys& ph, const Lvl& L, double eta, const CSoa& v,
+                                                const CSoa32& d, const CSoa& b, const Soa& vnew, const Soa32& base,
+                                                const Soa32& r32, uint32_t k, int i, int j)
+{
+    double S0 = 0.0, S1 = 0.0, S2 = 0.0, e, fx, fy;
+    const uint32_t wx = (uint32_t)(L.nx - 1);
+    nb_upd64<DIM>(ph, eta, 0, i > 0, i > 0 ? k - 1 : k + wx, k, v, d, e, fx, fy);
+    add_x(L.kx, ph.c, ph.c2, +1.0, e, fx, fy, S0, S1, S2);
+    nb_upd64<DIM>(ph, eta, 1, i < L.nx - 1, i < L.nx - 1 ? k + 1 : k - wx, k, v, d, e, fx, fy);
+    add_x(L.kx, ph.c, ph.c2, -1.0, e, fx, fy, S0, S1, S2);
+    if (DIM == 2) {
+        const uint32_t nx = (uint32_t)L.nx, wrap = (uint32_t)(L.ny - 1) * nx;
+        nb_upd64<DIM>(ph, eta, 2, j > 0, j > 0 ? k - nx : k + wrap, k, v, d, e, fx, fy);
+        add_y(L.ky, ph.c, ph.c2, +1.0, e, fx, fy, S0, S1, S2);
+        nb_upd64<DIM>(ph, eta, 3, j < L.ny - 1, j < L.ny - 1 ? k + nx : k - wrap, k, v, d, e, fx, fy);
+        add_y(L.ky, ph.c, ph.c2, -1.0, e, fx, fy, S0, S1, S2);
+    }
+    double E, Fx, Fy, T;
+    upd64<DIM>(ph, eta, v, d, k, E, Fx, Fy, T);
+    const double ka = L.cdt * ld(L.sa, k), ks = L.cdt * ld(L.ss, k);
+    const double T2 = T * T;
+    const double ex = ka * fma(-ph.a_r * T2, T2, E);
+    const double dF = L.a + ka + ks;
+    const double rE = ld(b.E, k) - (fma(L.a, E, ex) - S0);
+    const double rFx = ld(b.Fx, k) - fma(dF, Fx, -S1);
+    const double rFy = (DIM == 2) ? ld(b.Fy, k) - fma(dF, Fy, -S2) : 0.0;
+    const double rT = ld(b.T, k) - fma(ph.c_v, T, -ex);
+    st(vnew.E, k, E);
+    st(vnew.Fx, k, Fx);
+    if (DIM == 2) st(vnew.Fy, k, Fy);
+    st(vnew.T, k, T);
+    stf(base.E, k, (float)E);
+    stf(base.Fx, k, (float)Fx);
+    if (DIM == 2) stf(base.Fy, k, (float)Fy);
+    stf(base.T, k, (float)T);
+    stf(r32.E, k, (float)rE);
+    stf(r32.Fx, k, (float)rFx);
+    if (DIM == 2) stf(r32.Fy, k, (float)rFy);
+    stf(r32.T, k, (float)rT);
+    const double ic = 1.0 / ph.c;
+    return fma(rE, rE, fma(rFx * ic, rFx * ic, fma(rFy * ic, rFy * ic, rT * rT)));
+}
+
+// Fixed-order reduction of q over a 256-thread block into *dst (thread 0).
+__device__ __forceinline__ void mx_block_partial(double q, double* dst)
+{
+    __shared__ double red[kBlock32 / 64];
+    for (int off = 32; off > 0; off >>= 1) q += __shfl_xor(q, off, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = q;
+    __syncthreads();
+    if (threadIdx.x == 0) *dst = (red[0] + red[1]) + (red[2] + red[3]);
+}
+
 template <int DIM>
 __global__ __launch_bounds__(kBlock32) void k_mx_resid(Phys ph, Lvl L, double eta, CSoa v, CSoa32 d, CSoa b,
                                                        Soa vnew, Soa32 base, Soa32 r32, double* __restrict__ partials,
                                                        const int* __restrict__ active)
 {
     if (*active == 0) return;
-    __shared__ double red[kBlock32 / 64];
     uint32_t k;
     int i, j;
     double q = 0.0;
-    if (mx_cell(L.nx, L.ny, L.sh, k, i, j)) {
-        double S0 = 0.0, S1 = 0.0, S2 = 0.0, e, fx, fy;
-        const uint32_t wx = (uint32_t)(L.nx - 1);
-        nb_upd64<DIM>(ph, eta, 0, i > 0, i > 0 ? k - 1 : k + wx, k, v, d, e, fx, fy);
-        add_x(L.kx, ph.c, ph.c2, +1.0, e, fx, fy, S0, S1, S2);
-        nb_upd64<DIM>(ph, eta, 1, i < L.nx - 1, i < L.nx - 1 ? k + 1 : k - wx, k, v, d, e, fx, fy);
-        add_x(L.kx, ph.c, ph.c2, -1.0, e, fx, fy, S0, S1, S2);
-        if (DIM == 2) {
-            const uint32_t nx = (uint32_t)L.nx, wrap = (uint32_t)(L.ny - 1) * nx;
-            nb_upd64<DIM>(ph, eta, 2, j > 0, j > 0 ? k - nx : k + wrap, k, v, d, e, fx, fy);
-            add_y(L.ky, ph.c, ph.c2, +1.0, e, fx, fy, S0, S1, S2);
-            nb_upd64<DIM>(ph, eta, 3, j < L.ny - 1, j < L.ny - 1 ? k + nx : k - wrap, k, v, d, e, fx, fy);
-            add_y(L.ky, ph.c, ph.c2, -1.0, e, fx, fy, S0, S1, S2);
-        }
-        double E, Fx, Fy, T;
-        upd64<DIM>(ph, eta, v, d, k, E, Fx, Fy, T);
-        const double ka = L.cdt * ld(L.sa, k), ks = L.cdt * ld(L.ss, k);
-        const double T2 = T * T;
-        const double ex = ka * fma(-ph.a_r * T2, T2, E);
-        const double dF = L.a + ka + ks;
-        const double rE = ld(b.E, k) - (fma(L.a, E, ex) - S0);
-        const double rFx = ld(b.Fx, k) - fma(dF, Fx, -S1);
-        const double rFy = (DIM == 2) ? ld(b.Fy, k) - fma(dF, Fy, -S2) : 0.0;
-        const double rT = ld(b.T, k) - fma(ph.c_v, T, -ex);
-        st(vnew.E, k, E);
-        st(vnew.Fx, k, Fx);
-        if (DIM == 2) st(vnew.Fy, k, Fy);
-        st(vnew.T, k, T);
-        stf(base.E, k, (float)E);
-        stf(base.Fx, k, (float)Fx);
-        if (DIM == 2) stf(base.Fy, k, (float)Fy);
-        stf(base.T, k, (float)T);
-        stf(r32.E, k, (float)rE);
-        stf(r32.Fx, k, (float)rFx);
-        if (DIM == 2) stf(r32.Fy, k, (float)rFy);
-        stf(r32.T, k, (float)rT);
-        const double ic = 1.0 / ph.c;
-        q = fma(rE, rE, fma(rFx * ic, rFx * ic, fma(rFy * ic, rFy * ic, rT * rT)));
-    }
-    if (partials) {
-        for (int off = 32; off > 0; off >>= 1) q += __shfl_xor(q, off, 64);
-        if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = q;
-        __syncthreads();
-        if (threadIdx.x == 0) partials[xcd_block()] = (red[0] + red[1]) + (red[2] + red[3]);
-    }
+    if (mx_cell(L.nx, L.ny, L.sh, k, i, j)) q = mx_resid_cell<DIM>(ph, L, eta, v, d, b, vnew, base, r32, k, i, j);
+    if (partials) mx_block_partial(q, partials + xcd_block());
 }
 
 // ---------------------------------------------------------------------------
@@ -147,14 +157,10 @@ __global__ __launch_bounds__(kBlock32) void k_mx_resid(Phys ph, Lvl L, double et
 //   x: (beta M + gamma (D(w + x) - D(w))) = rhs + gamma dS(d);  out = d + omega (x - d).
 // d.E == nullptr means d = 0 (first sweep of a cycle: dS = 0, no reads of d).
 template <int DIM>
-__global__ __launch_bounds__(kBlock32) void k_mx_sweep(Phys ph, Lvl32 L, CSoa32 w, CSoa32 d, CSoa32 rhs, float beta,
-                                                       float gamma, float omega, Soa32 out,
-                                                       const int* __restrict__ active)
+__device__ __forceinline__ void mx_sweep_cell(const Phys& ph, const Lvl32& L, const CSoa32& w, const CSoa32& d,
+                                              const CSoa32& rhs, float beta, float gamma, float omega,
+                                              const Soa32& out, uint32_t k, int i, int j)
 {
-    if (*active == 0) return;
-    uint32_t k;
-    int i, j;
-    if (!mx_cell(L.nx, L.ny, L.sh, k, i, j)) return;
     float S0 = 0.0f, S1 = 0.0f, S2 = 0.0f;
     if (d.E) offdiag_inc<DIM>(ph, L, w, d, i, j, k, S0, S1, S2);
     const double QE = fmaf(gamma, S0, ldf(rhs.E, k));
@@ -170,6 +176,18 @@ __global__ __launch_bounds__(kBlock32) void k_mx_sweep(Phys ph, Lvl32 L, CSoa32 
     stf(out.Fx, k, fmaf(omega, xFx - dFx, dFx));
     if (DIM == 2) stf(out.Fy, k, fmaf(omega, xFy - dFy, dFy));
     stf(out.T, k, fmaf(omega, xT - dT, dT));
+}
+
+template <int DIM>
+__global__ __launch_bounds__(kBlock32) void k_mx_sweep(Phys ph, Lvl32 L, CSoa32 w, CSoa32 d, CSoa32 rhs, float beta,
+                                                       float gamma, float omega, Soa32 out,
+                                                       const int* __restrict__ active)
+{
+    if (*active == 0) return;
+    uint32_t k;
+    int i, j;
+    if (!mx_cell(L.nx, L.ny, L.sh, k, i, j)) return;
+    mx_sweep_cell<DIM>(ph, L, w, d, rhs, beta, gamma, omega, out, k, i, j);
 }
 
 // Increment of A for one cell: N(d) = (D(w + d) - D(w)) - dS(d).
@@ -357,13 +375,10 @@ __global__ __launch_bounds__(kBlock32) void k_mx_prolong(Phys ph, int nx, int ny
 }
 
 template <int DIM>
-__global__ __launch_bounds__(kBlock32) void k_mx_prolong_fine(Phys ph, int nx, int ny, int sh, int px, int py,
-                                                              double eta, CSoa v, CSoa32 e, CSoa32 ec, CSoa32 dc,
-                                                              Soa32 out, const int* __restrict__ active)
+__device__ __forceinline__ void mx_prolong_fine_cell(const Phys& ph, int nx, int ny, int sh, int px, int py,
+                                                     double eta, const CSoa& v, const CSoa32& e, const CSoa32& ec,
+                                                     const CSoa32& dc, const Soa32& out, uint32_t k, bool live)
 {
-    const bool live = active[mx_lane_zero()] != 0;
-    const uint32_t k = (uint32_t)xcd_block() * kBlock32 + threadIdx.x;
-    if (k >= (uint32_t)nx * (uint32_t)ny) return;
     float c0, c1, c2, c3;
     coarse_corr<DIM>(nx, ny, sh, px, py, ec, dc, k, c0, c1, c2, c3);
     const float eE = ldf(e.E, k), eFx = ldf(e.Fx, k), eFy = (DIM == 2) ? ldf(e.Fy, k) : 0.0f, eT = ldf(e.T, k);
@@ -377,6 +392,17 @@ __global__ __launch_bounds__(kBlock32) void k_mx_prolong_fine(Phys ph, int nx, i
     stf(out.Fx, k, (float)fma(th, (double)c1, (double)eFx));
     if (DIM == 2) stf(out.Fy, k, (float)fma(th, (double)c2, (double)eFy));
     stf(out.T, k, (float)fma(th, (double)c3, (double)eT));
+}
+
+template <int DIM>
+__global__ __launch_bounds__(kBlock32) void k_mx_prolong_fine(Phys ph, int nx, int ny, int sh, int px, int py,
+                                                              double eta, CSoa v, CSoa32 e, CSoa32 ec, CSoa32 dc,
+                                                              Soa32 out, const int* __restrict__ active)
+{
+    const bool live = active[mx_lane_zero()] != 0;
+    const uint32_t k = (uint32_t)xcd_block() * kBlock32 + threadIdx.x;
+    if (k >= (uint32_t)nx * (uint32_t)ny) return;
+    mx_prolong_fine_cell<DIM>(ph, nx, ny, sh, px, py, eta, v, e, ec, dc, out, k, live);
 }
 
 // FP32 restriction of NF fields (base, correction, residual of a level) for
@@ -471,12 +497,8 @@ __device__ __forceinline__ Soa32 mx_tail_pseudo(const TailArgs32& A, const TailL
 }
 
 template <int DIM>
-__global__ __launch_bounds__(256) void k_mx_tail(const TailArgs32* __restrict__ Ap, double dtau,
-                                                  const double* __restrict__ dtau_dev, const int* __restrict__ active)
+__device__ __forceinline__ void mx_tail_body(const TailArgs32& A, float dt)
 {
-    const float dt = (float)*dtau_dev;
-    if (*active == 0) return;
-    const TailArgs32& A = *Ap;
     unsigned in_e2 = 0;
     auto cur = [&](int l) { return ((in_e2 >> l) & 1u) ? A.lev[l].e2 : A.lev[l].e; };
     auto set = [&](int l, const Soa32& s) {
@@ -537,10 +559,162 @@ __global__ __launch_bounds__(256) void k_mx_tail(const TailArgs32* __restrict__ 
     }
 }
 
+template <int DIM>
+__global__ __launch_bounds__(256) void k_mx_tail(const TailArgs32* __restrict__ Ap, double dtau,
+                                                  const double* __restrict__ dtau_dev, const int* __restrict__ active)
+{
+    const float dt = (float)*dtau_dev;
+    if (*active == 0) return;
+    mx_tail_body<DIM>(*Ap, dt);
+}
+
 __global__ __launch_bounds__(kBlock32) void k_to_f32(int64_t n, const double* __restrict__ a, float* __restrict__ b)
 {
     const int64_t k = (int64_t)blockIdx.x * kBlock32 + threadIdx.x;
     if (k < n) b[k] = (float)a[k];
+}
+
+// ===========================================================================
+// Batched mixed-precision kernels (2-D): the same per-cell bodies over work
+// lists of (problem, 256-cell tile), each problem with its own control.  The
+// FP64 state of a problem is in x1 when ctrl->flip is set (its residual
+// kernel writes the partner buffer once per executed cycle).
+__device__ __forceinline__ const Soa32& pickA(const BSlot32& s, int sel) { return sel == 0 ? s.dA : s.dB; }
+__device__ __forceinline__ const Soa32& pick32(const BSlot32& s, int sel)
+{
+    return sel == 0 ? s.d : (sel == 1 ? s.e : s.e2);
+}
+// Final iterate of level l + 1 as seen by the prolongation into level l: the
+// tail's result or the coarsest level's pre-smoothing (both in e) at the
+// deepest level a problem smooths on the grid, else its post-smoothing (e2).
+__device__ __forceinline__ const Soa32& coarse_final(const BProb& pb, const BSlot32& c, int level)
+{
+    const int top = pb.lt < pb.L - 1 ? pb.lt : pb.L - 1;
+    return (level + 1 == top) ? c.e : c.e2;
+}
+
+// Residual with the pending correction (pend_sel; none on a step's first cycle).
+__global__ __launch_bounds__(kBlock32) void kbm_resid(const BProb* __restrict__ P, const BSlot* __restrict__ S,
+                                                      const BSlot32* __restrict__ S32,
+                                                      const uint32_t* __restrict__ wl, int nwl, int pend_sel)
+{
+    M1_BATCH_LOOP(wl, nwl)
+    const BSlot& s = S[p * kMaxLevels];
+    const BSlot32& s32 = S32[p * kMaxLevels];
+    const bool fl = pb.ctrl->flip != 0;
+    const CSoa32 d = (pb.ctrl->cycles < 0) ? CSoa32{} : cs(pickA(s32, pend_sel));
+    double q = 0.0;
+    if (k < (uint32_t)s.L.nx * (uint32_t)s.L.ny) {
+        int i, j;
+        ij_of(s.L.nx, s.L.sh, k, i, j);
+        q = mx_resid_cell<2>(pb.ph, s.L, pb.eta, cs(fl ? s.x1 : s.x0), d, cs(s.b), fl ? s.x0 : s.x1, s32.base, s32.r32,
+                             k, i, j);
+    }
+    mx_block_partial(q, pb.partials + tile);
+    }
+}
+
+__global__ __launch_bounds__(kBlock32) void kbm_sweep(const BProb* __restrict__ P, const BSlot32* __restrict__ S32,
+                                                      const uint32_t* __restrict__ wl, int nwl, int in_sel,
+                                                      int out_sel, int from_zero)
+{
+    M1_BATCH_LOOP(wl, nwl)
+    const BSlot32& s = S32[p * kMaxLevels];
+    if (k >= (uint32_t)s.L.nx * (uint32_t)s.L.ny) continue;
+    int i, j;
+    ij_of(s.L.nx, s.L.sh, k, i, j);
+    mx_sweep_cell<2>(pb.ph, s.L, cs(s.base), from_zero ? CSoa32{} : cs(pickA(s, in_sel)), cs(s.r32), 0.0f, 1.0f,
+                     (float)pb.omega, pickA(s, out_sel), k, i, j);
+    }
+}
+
+// level 0: rho0 = r32 - N(d) (d = pickA(in_sel)); level >= 1: rho = g - N(pick32(in_sel)).
+__global__ __launch_bounds__(kBlock32) void kbm_apply(const BProb* __restrict__ P, const BSlot32* __restrict__ S32,
+                                                      const uint32_t* __restrict__ wl, int nwl, int level, int in_sel)
+{
+    M1_BATCH_LOOP(wl, nwl)
+    const BSlot32& s = S32[p * kMaxLevels + level];
+    if (k >= (uint32_t)s.L.nx * (uint32_t)s.L.ny) continue;
+    int i, j;
+    ij_of(s.L.nx, s.L.sh, k, i, j);
+    if (level == 0) mx_apply_cell<2>(pb.ph, s.L, cs(s.base), cs(pickA(s, in_sel)), cs(s.r32), -1.0f, s.rho0, k, i, j);
+    else mx_apply_cell<2>(pb.ph, s.L, cs(s.w), cs(pick32(s, in_sel)), cs(s.g), -1.0f, s.rho, k, i, j);
+    }
+}
+
+// Into `level`: base w, correction d and R(rho) from level-1 (level 1: the
+// finest base32, pickA(d0_sel), rho0; deeper: w, the pre-smoothed e, rho).
+__global__ __launch_bounds__(kBlock32) void kbm_restrict(const BProb* __restrict__ P, const BSlot32* __restrict__ S32,
+                                                         const uint32_t* __restrict__ wl, int nwl, int level,
+                                                         int d0_sel)
+{
+    M1_BATCH_LOOP(wl, nwl)
+    const BSlot32& c = S32[p * kMaxLevels + level];
+    const BSlot32& f = S32[p * kMaxLevels + level - 1];
+    if (k >= (uint32_t)c.L.nx * (uint32_t)c.L.ny) continue;
+    const Soa32& w = (level == 1) ? f.base : f.w;
+    const Soa32& d = (level == 1) ? pickA(f, d0_sel) : f.e;
+    const Soa32& r = (level == 1) ? f.rho0 : f.rho;
+    const float* in[12] = {w.E, w.Fx, w.Fy, w.T, d.E, d.Fx, d.Fy, d.T, r.E, r.Fx, r.Fy, r.T};
+    float* out[12] = {c.w.E, c.w.Fx, c.w.Fy, c.w.T, c.d.E, c.d.Fx, c.d.Fy, c.d.T, c.g.E, c.g.Fx, c.g.Fy, c.g.T};
+    mx_restrict_cell<2, 12>(f.L.nx, f.L.ny, f.L.sh, pb.px, pb.py, in, out, k);
+    }
+}
+
+__global__ __launch_bounds__(kBlock32) void kbm_pseudo(const BProb* __restrict__ P, const BSlot32* __restrict__ S32,
+                                                       const uint32_t* __restrict__ wl, int nwl, int level,
+                                                       int in_sel, int out_sel, int first)
+{
+    M1_BATCH_LOOP(wl, nwl)
+    const BSlot32& s = S32[p * kMaxLevels + level];
+    if (k >= (uint32_t)s.L.nx * (uint32_t)s.L.ny) continue;
+    int i, j;
+    ij_of(s.L.nx, s.L.sh, k, i, j);
+    const float dt = (float)pb.ctrl->dtau;
+    if (first)
+        mx_pseudo_cell<2, true>(pb.ph, s.L, cs(s.w), s.g, cs(pick32(s, in_sel)), pick32(s, out_sel), dt,
+                                (float)pb.reach, pb.local, k, i, j);
+    else
+        mx_pseudo_cell<2, false>(pb.ph, s.L, cs(s.w), s.g, cs(pick32(s, in_sel)), pick32(s, out_sel), dt,
+                                 (float)pb.reach, pb.local, k, i, j);
+    }
+}
+
+// Correction of `level` >= 1 from level+1, in place on the pre-smoothed e.
+__global__ __launch_bounds__(kBlock32) void kbm_prolong(const BProb* __restrict__ P, const BSlot32* __restrict__ S32,
+                                                        const uint32_t* __restrict__ wl, int nwl, int level)
+{
+    M1_BATCH_LOOP(wl, nwl)
+    const BSlot32& f = S32[p * kMaxLevels + level];
+    const BSlot32& c = S32[p * kMaxLevels + level + 1];
+    if (k >= (uint32_t)f.L.nx * (uint32_t)f.L.ny) continue;
+    mx_prolong_cell<2>(pb.ph, f.L.nx, f.L.ny, f.L.sh, pb.px, pb.py, (float)pb.eta, cs(f.w), cs(f.e),
+                       cs(coarse_final(pb, c, level)), cs(c.d), f.e, k);
+    }
+}
+
+// Finest-level correction of pickA(e_sel) in place, admissibility against the FP64 state.
+__global__ __launch_bounds__(kBlock32) void kbm_prolong_fine(const BProb* __restrict__ P, const BSlot* __restrict__ S,
+                                                             const BSlot32* __restrict__ S32,
+                                                             const uint32_t* __restrict__ wl, int nwl, int e_sel)
+{
+    M1_BATCH_LOOP(wl, nwl)
+    const BSlot& s = S[p * kMaxLevels];
+    const BSlot32& f = S32[p * kMaxLevels];
+    const BSlot32& c = S32[p * kMaxLevels + 1];
+    if (k >= (uint32_t)s.L.nx * (uint32_t)s.L.ny) continue;
+    const Soa32& e = pickA(f, e_sel);
+    mx_prolong_fine_cell<2>(pb.ph, s.L.nx, s.L.ny, s.L.sh, pb.px, pb.py, pb.eta, cs(pb.ctrl->flip ? s.x1 : s.x0),
+                            cs(e), cs(coarse_final(pb, c, 0)), cs(c.d), e, k, true);
+    }
+}
+
+// One block per problem with a tail: the bottom of its V-cycle.
+__global__ __launch_bounds__(256) void kbm_tail(const BProb* __restrict__ P, const int* __restrict__ plist)
+{
+    const BProb& pb = P[plist[blockIdx.x]];
+    if (pb.ctrl->active == 0) return;
+    mx_tail_body<2>(*pb.tail32, (float)pb.ctrl->dtau);
 }
 
 // ===========================================================================
@@ -615,6 +789,53 @@ void launch_mx_tail(hipStream_t st, int dim, const TailArgs32* args_dev, double 
 void launch_to_f32(hipStream_t st, int64_t n, const double* a, float* b)
 {
     hipLaunchKernelGGL(k_to_f32, dim3(nblk(n)), dim3(kBlock32), 0, st, n, a, b);
+}
+
+static unsigned bmgrid(int nwl) { return (unsigned)(nwl < 1 ? 1 : (nwl > 16384 ? 16384 : nwl)); }
+
+void launch_bm_resid(hipStream_t st, const BProb* P, const BSlot* S, const BSlot32* S32, const uint32_t* wl, int nwl,
+                     int pend_sel)
+{
+    if (nwl > 0) hipLaunchKernelGGL(kbm_resid, dim3(bmgrid(nwl)), dim3(kBlock32), 0, st, P, S, S32, wl, nwl, pend_sel);
+}
+void launch_bm_sweep(hipStream_t st, const BProb* P, const BSlot32* S32, const uint32_t* wl, int nwl, int in_sel,
+                     int out_sel, int from_zero)
+{
+    if (nwl > 0)
+        hipLaunchKernelGGL(kbm_sweep, dim3(bmgrid(nwl)), dim3(kBlock32), 0, st, P, S32, wl, nwl, in_sel, out_sel,
+                           from_zero);
+}
+void launch_bm_apply(hipStream_t st, const BProb* P, const BSlot32* S32, const uint32_t* wl, int nwl, int level,
+                     int in_sel)
+{
+    if (nwl > 0) hipLaunchKernelGGL(kbm_apply, dim3(bmgrid(nwl)), dim3(kBlock32), 0, st, P, S32, wl, nwl, level, in_sel);
+}
+void launch_bm_restrict(hipStream_t st, const BProb* P, const BSlot32* S32, const uint32_t* wl, int nwl, int level,
+                        int d0_sel)
+{
+    if (nwl > 0)
+        hipLaunchKernelGGL(kbm_restrict, dim3(bmgrid(nwl)), dim3(kBlock32), 0, st, P, S32, wl, nwl, level, d0_sel);
+}
+void launch_bm_pseudo(hipStream_t st, const BProb* P, const BSlot32* S32, const uint32_t* wl, int nwl, int level,
+                      int in_sel, int out_sel, int first)
+{
+    if (nwl > 0)
+        hipLaunchKernelGGL(kbm_pseudo, dim3(bmgrid(nwl)), dim3(kBlock32), 0, st, P, S32, wl, nwl, level, in_sel,
+                           out_sel, first);
+}
+void launch_bm_prolong(hipStream_t st, const BProb* P, const BSlot32* S32, const uint32_t* wl, int nwl, int level)
+{
+    if (nwl > 0) hipLaunchKernelGGL(kbm_prolong, dim3(bmgrid(nwl)), dim3(kBlock32), 0, st, P, S32, wl, nwl, level);
+}
+void launch_bm_prolong_fine(hipStream_t st, const BProb* P, const BSlot* S, const BSlot32* S32, const uint32_t* wl,
+                            int nwl, int e_sel)
+{
+    if (nwl > 0)
+        hipLaunchKernelGGL(kbm_prolong_fine, dim3(bmgrid(nwl)), dim3(kBlock32), 0, st, P, S, S32, wl, nwl, e_sel);
+}
+void launch_bm_tail(hipStream_t st, const BProb* P, const int* plist, int np)
+{
+    if (np > 0) hipLaunchKernelGGL(kbm_tail, dim3(np), dim3(256), 0, st, P, plist);
 }
 
 }  // namespace m1

@@ -31,21 +31,23 @@ def problems(n, sides=(64, 128, 256)):
     return out
 
 
-def alone(prob, v, sig, nsteps):
-    P = binding.Plan(prob, to_dev(sig), PARAMS)
+def alone(prob, v, sig, nsteps, params=PARAMS):
+    P = binding.Plan(prob, to_dev(sig), params)
     vd = to_dev(v)
     info = P.step(vd, nsteps)
     return to_host(vd), info
 
 
-@pytest.mark.parametrize("arena_mb", [4096, 24])
-def test_batch_matches_alone(arena_mb):
-    announce("batch vs alone, arena MB", arena_mb)
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("arena", ["large", "tight"])
+def test_batch_matches_alone(precision, arena):
+    announce("batch vs alone", precision, arena)
+    params = dict(PARAMS, precision=precision)
     cases = problems(9)
-    E = binding.Engine(arena_mb << 20, PARAMS, max_requests=64)
-    need = max(binding.Engine.request_bytes(p, PARAMS) for p, _, _, _ in cases)
-    if arena_mb == 24:
-        assert 2 * need < (arena_mb << 20) < 3 * need, "arena meant to hold only two large requests at once"
+    need = max(binding.Engine.request_bytes(p, params) for p, _, _, _ in cases)
+    # tight: room for two of the largest requests at once, so the others queue
+    arena_bytes = (4096 << 20) if arena == "large" else int(2.5 * need) + (2 << 20)
+    E = binding.Engine(arena_bytes, params, max_requests=64)
     states, tickets = [], []
     for prob, v, sig, ns in cases:
         vd = to_dev(v)
@@ -62,7 +64,7 @@ def test_batch_matches_alone(arena_mb):
         assert rounds < 5000
     for (prob, v, sig, ns), vd, t in zip(cases, states, tickets):
         info = E.poll(t)
-        ref, info_a = alone(prob, v, sig, ns)
+        ref, info_a = alone(prob, v, sig, ns, params)
         assert info["status"] == 0 and info["steps_done"] == ns
         assert info["cycles"] == info_a["cycles"], (info["cycles"], info_a["cycles"])
         np.testing.assert_array_equal(to_host(vd), ref)
@@ -89,15 +91,35 @@ def test_batch_budget_cancel_and_arguments():
     assert info is not None and info["status"] == 6
     got = to_host(vd)
     assert np.all(got[0] > 0) and np.all(got[3] > 0)
+    # mixed precision: a cancelled request's FP64 state may sit in the partner
+    # buffer; it must come back to the caller's arrays, finite and admissible
+    params = dict(PARAMS, precision="mixed")
+    E2 = binding.Engine(64 << 20, params, max_requests=8)
+    v0 = v.copy()
+    vd = to_dev(v0)
+    t = E2.submit(prob, to_dev(sig), vd, 20)
+    E2.run(3)
+    E2.run(2)
+    E2.cancel(t)
+    E2.run(1)
+    info = E2.poll(t)
+    assert info is not None and info["status"] == 6 and info["cycles"] > 0
+    got = to_host(vd)
+    assert np.all(np.isfinite(got)) and np.all(got[0] > 0) and np.all(got[3] > 0)
+    assert np.all(np.hypot(got[1], got[2]) <= prob["c"] * got[0] * (1 + 1e-12))
+    assert not np.array_equal(got, v0)
 
 
-def test_serving_loop_matches_alone():
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_serving_loop_matches_alone(precision):
     """Requests submitted while others are on the GPU (the library's serving
     thread drives the rounds) are admitted as memory frees up, overlap on the
     device, and each result equals solving it alone, bitwise."""
-    announce("serving loop vs alone")
+    announce("serving loop vs alone", precision)
+    params = dict(PARAMS, precision=precision)
     cases = problems(7)
-    E = binding.Engine(24 << 20, PARAMS, max_requests=64)
+    need = max(binding.Engine.request_bytes(p, params) for p, _, _, _ in cases)
+    E = binding.Engine(int(2.5 * need) + (2 << 20), params, max_requests=64)
     E.serve_start(2)
     states, tickets = [], []
     for k, (prob, v, sig, ns) in enumerate(cases):
@@ -112,7 +134,7 @@ def test_serving_loop_matches_alone():
     # some request was admitted while an earlier one was still running
     assert any(tm[k][1] < max(tm[j][2] for j in range(k)) for k in range(1, len(tm)))
     for (prob, v, sig, ns), vd, info in zip(cases, states, infos):
-        ref, info_a = alone(prob, v, sig, ns)
+        ref, info_a = alone(prob, v, sig, ns, params)
         assert info["status"] == 0 and info["steps_done"] == ns
         assert info["cycles"] == info_a["cycles"]
         np.testing.assert_array_equal(to_host(vd), ref)
@@ -123,4 +145,4 @@ def test_serving_loop_matches_alone():
     t = E.submit(prob, to_dev(sig), vd, ns)
     assert E.wait(t)["status"] == 0
     E.serve_stop()
-    np.testing.assert_array_equal(to_host(vd), alone(prob, v, sig, ns)[0])
+    np.testing.assert_array_equal(to_host(vd), alone(prob, v, sig, ns, params)[0])
