@@ -157,6 +157,7 @@ struct m1_plan {
     m1::TailArgs* dtail = nullptr; // device copy of the tail description (workspace)
     int lt = 0;                    // first level run by the single-workgroup tail (L: none)
     bool mixed = false;
+    bool tiled = true;  // LDS-tiled smoothing legs where the level shape allows (M1_TILED=0 turns them off)
     Soa32 base32{}, r32{}, dA{}, dB{}, rho0{};  // mixed: finest-level FP32 buffers
     m1::TailArgs32* dtail32 = nullptr;           // mixed: device copy of the tail description
 };
@@ -230,6 +231,13 @@ int64_t tail_cells()
 {
     const char* e = std::getenv("M1_TAIL_CELLS");
     return e ? std::atoll(e) : 256;
+}
+
+// Largest level (cells) smoothed by the LDS-tiled kernels (M1_TILED_MAX_CELLS).
+int64_t tiled_max_cells()
+{
+    const char* e = std::getenv("M1_TILED_MAX_CELLS");
+    return e ? std::atoll(e) : 65536;
 }
 
 void fill_level_params(m1_plan& P)
@@ -349,19 +357,32 @@ void vcycle_impl(m1_plan& P, Soa& cur, Soa& other, const Gate& G, bool control =
     if (P.L == 1) return;
     m1::launch_apply(P.st, P.dim, P.ph, P.lev[0].L, cs(cur), cs(P.b), -1.0, P.rfine, nullptr, G.active);
     std::vector<Soa> ul(P.L);
+    // levels smoothed by one LDS-tiled launch per leg: R(rbar) goes to rb, which the
+    // down leg reads while it writes the FAS right-hand side into f
+    // (only up to tiled_max_cells: larger levels stream well as one launch per step, and the halo
+    // work and the large LDS blocks of the tiled form cost more than the launches it saves)
+    std::vector<char> tiled(P.L, 0);
+    for (int l = 1; l < std::min(P.lt, P.L); ++l)
+        tiled[l] = P.tiled && P.lev[l].n <= tiled_max_cells() && m1::smooth_tb_fits(P.dim, P.lev[l].L, p.pseudo_steps);
     ul[0] = cur;
     Soa rb_prev = P.rfine;
     for (int l = 1; l < P.L; ++l) {
         LevelBuf& c = P.lev[l];
         const LevelBuf& f = P.lev[l - 1];
-        m1::launch_restrict(P.st, P.dim, f.nx, f.ny, P.px, P.py, fields2(ul[l - 1], rb_prev, c.v, c.f, P.dim),
-                            G.active);
+        m1::launch_restrict(P.st, P.dim, f.nx, f.ny, P.px, P.py,
+                            fields2(ul[l - 1], rb_prev, c.v, tiled[l] ? c.rb : c.f, P.dim), G.active);
         if (l == P.lt) {  // the rest of the cycle below (and including) level lt
             m1::launch_tail(P.st, P.dim, P.dtail, G.dtau, G.dtau_dev, G.active);
             ul[l] = c.u;
             break;
         }
-        ul[l] = pseudo_smooth(P, l, G, c.v, true);  // also forms f = A(v) + R(rbar)
+        if (tiled[l]) {
+            m1::launch_smooth_tb(P.st, P.ph, c.L, p.pseudo_steps, false, cs(c.rb), c.f, cs(c.v), c.u, G.dtau_dev,
+                                 P.reach, p.pseudo_local, CSoa{}, CSoa{}, P.px, P.py, p.eta, G.active);
+            ul[l] = c.u;
+        } else {
+            ul[l] = pseudo_smooth(P, l, G, c.v, true);  // also forms f = A(v) + R(rbar)
+        }
         if (l < P.L - 1) {
             m1::launch_apply(P.st, P.dim, P.ph, c.L, cs(ul[l]), cs(c.f), -1.0, c.rb, nullptr, G.active);
             rb_prev = c.rb;
@@ -370,7 +391,14 @@ void vcycle_impl(m1_plan& P, Soa& cur, Soa& other, const Gate& G, bool control =
     const int top = std::min(P.lt, P.L - 1);
     for (int l = top - 1; l >= 0; --l) {
         const LevelBuf& c = P.lev[l + 1];
-        const LevelBuf& f = P.lev[l];
+        LevelBuf& f = P.lev[l];
+        if (tiled[l]) {  // prolongation, projection and the post-smoothing in one launch
+            const Soa out = same(ul[l], f.u) ? f.u2 : f.u;
+            m1::launch_smooth_tb(P.st, P.ph, f.L, p.pseudo_steps, true, cs(f.f), f.f, cs(ul[l]), out, G.dtau_dev,
+                                 P.reach, p.pseudo_local, cs(ul[l + 1]), cs(c.v), P.px, P.py, p.eta, G.active);
+            ul[l] = out;
+            continue;
+        }
         m1::launch_prolong_project(P.st, P.dim, P.ph, f.nx, f.ny, P.px, P.py, p.eta, cs(ul[l]), cs(ul[l + 1]),
                                    cs(c.v), ul[l], G.active);
         if (l == 0) {
@@ -632,6 +660,10 @@ m1_status m1_plan_create(const m1_grid* g, const m1_params* p, const m1_opacity*
     ta.reach = P->reach;
     ta.eta = p->eta;
     P->mixed = p->precision == M1_MIXED;
+    {
+        const char* e = std::getenv("M1_TILED");
+        P->tiled = p->nu_l == 1 && !(e && e[0] == '0');
+    }
     const bool tail_ok = P->L <= m1::kMaxLevels && p->nu_l == 1;
     if (!tail_ok) P->lt = P->L;  // the tail fuses exactly one Jacobi sweep per pseudo-time step
     for (int l = 0; l < P->L && l < m1::kMaxLevels; ++l) {

@@ -70,6 +70,38 @@ __device__ __forceinline__ double relax_cell(const Phys& ph, const Lvl& L, const
 //   f holds the restricted residual on entry and the FAS right-hand side
 //   f = A(v_l) + R(rbar) is formed here and written back (A(v) = D(v) - S(v),
 //   S(v) being needed for the sweep anyway).
+// The arithmetic of one pseudo-time step for one cell, from its values: u,
+// the off-diagonal sum S(u), kappa_a/s, and f (with FIRST: R(rbar) on entry,
+// the FAS right-hand side on return).  Returns the new u and, for further
+// sweeps, M u~ (t) and g.
+template <int DIM, bool FIRST>
+__device__ __forceinline__ void pseudo_core(const Phys& ph, const Lvl& L, double uE, double uFx, double uFy, double uT,
+                                            double S0, double S1, double S2, double ka, double ks, double& fE,
+                                            double& fFx, double& fFy, double& fT, double dtau, double reach,
+                                            int local, double& E, double& Fx, double& Fy, double& T, double& tE,
+                                            double& tFx, double& tFy, double& tT, double& g)
+{
+    if (FIRST) {
+        const double T2 = uT * uT;
+        const double ex = ka * fma(-ph.a_r * T2, T2, uE);
+        const double dF = L.a + ka + ks;
+        fE += fma(L.a, uE, ex) - S0;
+        fFx += fma(dF, uFx, -S1);
+        fFy += fma(dF, uFy, -S2);
+        fT += fma(ph.c_v, uT, -ex);
+    }
+    const double sE = fE, sFx = fFx, sFy = fFy, sT = fT / ph.c_v;
+    const double ts = ray_len(ph.c2, uE, uFx, uFy, uT, sE, sFx, sFy, sT);
+    const double tau = fmin(dtau, ts * reach);
+    tE = fma(tau, sE, uE);
+    tFx = fma(tau, sFx, uFx);
+    tFy = fma(tau, sFy, uFy);
+    tT = ph.c_v * fma(tau, sT, uT);
+    g = local ? tau : dtau;
+    local_solve(1.0, g, L.a, ka, ks, ph.c_v, ph.a_r, fma(g, S0, tE), fma(g, S1, tFx), fma(g, S2, tFy), tT, uT, E, Fx,
+                Fy, T);
+}
+
 template <int DIM, bool FIRST = false>
 __device__ __forceinline__ void pseudo_cell(const Phys& ph, const Lvl& L, const CSoa& fin, const Soa& fout,
                                             const CSoa& u, const Soa& out, double dtau, double reach, int local,
@@ -80,31 +112,16 @@ __device__ __forceinline__ void pseudo_cell(const Phys& ph, const Lvl& L, const 
     offdiag<DIM>(ph, L, u, i, j, k, S0, S1, S2);
     const double ka = L.cdt * ld(L.sa, k), ks = L.cdt * ld(L.ss, k);
     double fE = ld(fin.E, k), fFx = ld(fin.Fx, k), fFy = (DIM == 2) ? ld(fin.Fy, k) : 0.0, fT = ld(fin.T, k);
-    if (FIRST) {
-        const double T2 = uT * uT;
-        const double ex = ka * fma(-ph.a_r * T2, T2, uE);
-        const double dF = L.a + ka + ks;
-        fE += fma(L.a, uE, ex) - S0;
-        fFx += fma(dF, uFx, -S1);
-        fFy += fma(dF, uFy, -S2);
-        fT += fma(ph.c_v, uT, -ex);
-        if (live) {
-            st(fout.E, k, fE);
-            st(fout.Fx, k, fFx);
-            if (DIM == 2) st(fout.Fy, k, fFy);
-            st(fout.T, k, fT);
-        }
-    }
-    const double sE = fE, sFx = fFx, sFy = fFy, sT = fT / ph.c_v;
-    const double ts = ray_len(ph.c2, uE, uFx, uFy, uT, sE, sFx, sFy, sT);
-    const double tau = fmin(dtau, ts * reach);
-    const double tE = fma(tau, sE, uE), tFx = fma(tau, sFx, uFx), tFy = fma(tau, sFy, uFy);
-    const double tT = ph.c_v * fma(tau, sT, uT);
-    const double g = local ? tau : dtau;
-    double E, Fx, Fy, T;
-    local_solve(1.0, g, L.a, ka, ks, ph.c_v, ph.a_r, fma(g, S0, tE), fma(g, S1, tFx), fma(g, S2, tFy), tT, uT, E, Fx,
-                Fy, T);
+    double E, Fx, Fy, T, tE, tFx, tFy, tT, g;
+    pseudo_core<DIM, FIRST>(ph, L, uE, uFx, uFy, uT, S0, S1, S2, ka, ks, fE, fFx, fFy, fT, dtau, reach, local, E, Fx,
+                            Fy, T, tE, tFx, tFy, tT, g);
     if (!live) return;
+    if (FIRST) {
+        st(fout.E, k, fE);
+        st(fout.Fx, k, fFx);
+        if (DIM == 2) st(fout.Fy, k, fFy);
+        st(fout.T, k, fT);
+    }
     st(out.E, k, E);
     st(out.Fx, k, Fx);
     if (DIM == 2) st(out.Fy, k, Fy);
@@ -247,15 +264,14 @@ __device__ __forceinline__ void pweights(int i, int nc, bool periodic, int idx[2
     w[1] = 0.5;
 }
 
-// Correction with admissibility (eq. prolongatedSol):
-//   w = u + P(uc - vc); out = w if admissible, else u + eta min(tau*(u, w - u), 1) (w - u).
+// Correction with admissibility (eq. prolongatedSol) of fine cell (i, j) with
+// state u:  w = u + P(uc - vc); w if admissible, else
+// u + eta min(tau*(u, w - u), 1) (w - u).
 template <int DIM>
-__device__ __forceinline__ void prolong_cell(const Phys& ph, int nx, int ny, int sh, int px, int py, double eta,
-                                             const CSoa& u, const CSoa& uc, const CSoa& vc, const Soa& out, uint32_t k,
-                                             bool live = true)
+__device__ __forceinline__ void prolong_value(const Phys& ph, int nx, int ny, int px, int py, double eta, int i, int j,
+                                              double uE, double uFx, double uFy, double uT, const CSoa& uc,
+                                              const CSoa& vc, double& wE, double& wFx, double& wFy, double& wT)
 {
-    int i, j;
-    ij_of(nx, sh, k, i, j);
     const int nxc = nx / 2, nyc = (DIM == 2) ? ny / 2 : 1;
     int ix[2], iy[2] = {0, 0};
     double wx[2], wy[2] = {1.0, 0.0};
@@ -275,8 +291,10 @@ __device__ __forceinline__ void prolong_cell(const Phys& ph, int nx, int ny, int
             e3 = fma(w, ld(uc.T, kc) - ld(vc.T, kc), e3);
         }
     }
-    const double uE = ld(u.E, k), uFx = ld(u.Fx, k), uFy = (DIM == 2) ? ld(u.Fy, k) : 0.0, uT = ld(u.T, k);
-    double wE = uE + e0, wFx = uFx + e1, wFy = uFy + e2, wT = uT + e3;
+    wE = uE + e0;
+    wFx = uFx + e1;
+    wFy = uFy + e2;
+    wT = uT + e3;
     if (!admissible(ph.c2, wE, wFx, wFy, wT)) {
         const double th = eta * fmin(ray_len(ph.c2, uE, uFx, uFy, uT, e0, e1, e2, e3), 1.0);
         wE = fma(th, e0, uE);
@@ -284,6 +302,18 @@ __device__ __forceinline__ void prolong_cell(const Phys& ph, int nx, int ny, int
         wFy = fma(th, e2, uFy);
         wT = fma(th, e3, uT);
     }
+}
+
+template <int DIM>
+__device__ __forceinline__ void prolong_cell(const Phys& ph, int nx, int ny, int sh, int px, int py, double eta,
+                                             const CSoa& u, const CSoa& uc, const CSoa& vc, const Soa& out, uint32_t k,
+                                             bool live = true)
+{
+    int i, j;
+    ij_of(nx, sh, k, i, j);
+    const double uE = ld(u.E, k), uFx = ld(u.Fx, k), uFy = (DIM == 2) ? ld(u.Fy, k) : 0.0, uT = ld(u.T, k);
+    double wE, wFx, wFy, wT;
+    prolong_value<DIM>(ph, nx, ny, px, py, eta, i, j, uE, uFx, uFy, uT, uc, vc, wE, wFx, wFy, wT);
     if (!live) return;
     st(out.E, k, wE);
     st(out.Fx, k, wFx);

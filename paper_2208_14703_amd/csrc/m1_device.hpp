@@ -133,23 +133,21 @@ __device__ __forceinline__ void add_y(double k, double c, double c2, double sgn,
 }
 
 // ---------------------------------------------------------------------------
-// Neighbour (ghost) state for side `side` (0 x-, 1 x+, 2 y-, 3 y+).  `inside`
-// tells whether the neighbour index kn is in the domain; otherwise the side's
-// boundary rule applies (kn is then the periodic wrap, kc the cell itself).
-// Branch-free: the load always happens (from kn or kc) and the boundary rule
-// is applied by selects, so the four neighbours' loads are all in flight at once.
-template <int DIM>
-__device__ __forceinline__ void nb_state(const Phys& ph, int side, bool inside, uint32_t kn, uint32_t kc,
-                                         const CSoa& v, double& e, double& fx, double& fy)
+// Boundary rule of side `side` (0 x-, 1 x+, 2 y-, 3 y+) applied to the values
+// loaded for that neighbour: inside the domain (or across a periodic side) they
+// are the neighbour's own; at another side they were loaded from the cell
+// itself and become its ghost (Neumann copy, reflective mirror of the normal
+// flux, Dirichlet wall state).  Exact arithmetic selects (x 1, x 0 of a finite
+// value, x -1), so that callers can load unconditionally.
+__device__ __forceinline__ bool is_ghost(const Phys& ph, int side, bool inside)
+{
+    return !inside && ph.bc[side] != BC_PERIODIC;
+}
+__device__ __forceinline__ void ghost_rule(const Phys& ph, int side, bool inside, double le, double lfx, double lfy,
+                                           double& e, double& fx, double& fy)
 {
     const int kind = ph.bc[side];
-    const bool ghost = !inside && kind != BC_PERIODIC;
-    const uint32_t k = ghost ? kc : kn;
-    const double le = ld(v.E, k), lfx = ld(v.Fx, k), lfy = (DIM == 2) ? ld(v.Fy, k) : 0.0;
-    // keep = 1 (own or wrapped value) or 0 (Dirichlet wall value); sx, sy = -1
-    // flip the normal flux at a reflective wall.  The loaded values are always
-    // used, so the compiler cannot sink the loads into per-lane branches; every
-    // product is exact (x 1, x 0 of a finite value, x -1).
+    const bool ghost = is_ghost(ph, side, inside);
     const bool dir = ghost && kind == BC_DIRICHLET;
     const bool flip = ghost && kind == BC_REFLECTIVE;
     const double keep = dir ? 0.0 : 1.0;
@@ -157,6 +155,18 @@ __device__ __forceinline__ void nb_state(const Phys& ph, int side, bool inside, 
     e = fma(keep, le, dir ? ph.bcE[side] : 0.0);
     fx = fma(sx, lfx, dir ? ph.bcFx[side] : 0.0);
     fy = fma(sy, lfy, dir ? ph.bcFy[side] : 0.0);
+}
+
+// Neighbour state for side `side`: kn is the neighbour's index (the periodic
+// wrap across a domain side), kc the cell's own.  The loads always happen, so
+// the four neighbours' loads are in flight at once.
+template <int DIM>
+__device__ __forceinline__ void nb_state(const Phys& ph, int side, bool inside, uint32_t kn, uint32_t kc,
+                                         const CSoa& v, double& e, double& fx, double& fy)
+{
+    const uint32_t k = is_ghost(ph, side, inside) ? kc : kn;
+    const double le = ld(v.E, k), lfx = ld(v.Fx, k), lfy = (DIM == 2) ? ld(v.Fy, k) : 0.0;
+    ghost_rule(ph, side, inside, le, lfx, lfy, e, fx, fy);
 }
 
 // Off-diagonal sum S = L_x(v_{i-1}) + R_x(v_{i+1}) [+ L_y(v_{j-1}) + R_y(v_{j+1})] of cell (i,j).

@@ -200,6 +200,139 @@ __global__ __launch_bounds__(kBlock) void k_check_sigma(int64_t n, const double*
 __global__ void k_ctrl_init(Ctrl* ctrl, Ctrl init) { *ctrl = init; }
 
 // ===========================================================================
+// LDS-tiled smoothing of one coarse level (2-D): all m pseudo-time steps of a
+// smoothing leg in one launch.  A block owns a 16x16 tile and loads it with a
+// halo of M = m cells; step s recomputes the region M - s cells around the
+// tile, so no step needs another block's result (temporal blocking; the halo
+// work is redundant).  Down leg: the first step forms the FAS right-hand side
+// from R(rbar), read from `fr` and written to `f` (other tiles still read fr).
+// Up leg: the load applies the prolongation and projection from level l + 1
+// (uc, vc) to the level's pre-smoothed iterate `u`.  The per-cell arithmetic is
+// that of the one-step kernels, so the results are the same to the bit.
+// Requires nx, ny multiples of 16, at least 32; u and out distinct.
+constexpr int kTbTile = 16;
+constexpr int kTbThreads = 512;
+
+template <int M, bool UP>
+__global__ __launch_bounds__(kTbThreads) void k_smooth_tb(Phys ph, Lvl L, CSoa fr, Soa f, CSoa u, Soa out,
+                                                           const double* __restrict__ dtau_dev, double reach,
+                                                           int local, CSoa uc, CSoa vc, int px, int py, double eta,
+                                                           const int* __restrict__ active)
+{
+    constexpr int W = kTbTile + 2 * M, NC = W * W;
+    __shared__ double sE[2][NC], sFx[2][NC], sFy[2][NC], sT[2][NC];
+    __shared__ double qE[NC], qFx[NC], qFy[NC], qT[NC], qa[NC], qs[NC];
+    const uint32_t z = lane_zero();
+    const double dt = dtau_dev[z];
+    const bool live = active[z] != 0;
+    const int ntx = L.nx / kTbTile;
+    const int b = (int)xcd_block();
+    const int bx = b % ntx, by = b / ntx;
+    const int x0 = bx * kTbTile - M, y0 = by * kTbTile - M;
+    // global cell of region point (li, lj), wrapped across periodic sides; false outside a non-periodic side
+    auto gcell = [&](int li, int lj, int& gi, int& gj) {
+        gi = x0 + li;
+        gj = y0 + lj;
+        if (gi < 0 || gi >= L.nx) {
+            if (!px) return false;
+            gi = gi < 0 ? gi + L.nx : gi - L.nx;
+        }
+        if (gj < 0 || gj >= L.ny) {
+            if (!py) return false;
+            gj = gj < 0 ? gj + L.ny : gj - L.ny;
+        }
+        return true;
+    };
+    for (int c = threadIdx.x; c < NC; c += kTbThreads) {
+        int gi, gj;
+        if (!gcell(c % W, c / W, gi, gj)) continue;
+        const uint32_t k = (uint32_t)gj * (uint32_t)L.nx + (uint32_t)gi;
+        double e = ld(u.E, k), fx = ld(u.Fx, k), fy = ld(u.Fy, k), t = ld(u.T, k);
+        if (UP) {
+            double we, wfx, wfy, wt;
+            prolong_value<2>(ph, L.nx, L.ny, px, py, eta, gi, gj, e, fx, fy, t, uc, vc, we, wfx, wfy, wt);
+            e = we;
+            fx = wfx;
+            fy = wfy;
+            t = wt;
+        }
+        sE[0][c] = e;
+        sFx[0][c] = fx;
+        sFy[0][c] = fy;
+        sT[0][c] = t;
+        qE[c] = ld(fr.E, k);
+        qFx[c] = ld(fr.Fx, k);
+        qFy[c] = ld(fr.Fy, k);
+        qT[c] = ld(fr.T, k);
+        qa[c] = ld(L.sa, k);
+        qs[c] = ld(L.ss, k);
+    }
+    __syncthreads();
+    int cur = 0;
+#pragma unroll 1
+    for (int s = 1; s <= M; ++s) {
+        const int nw = W - 2 * s, n = nw * nw;
+        const bool first = !UP && s == 1;
+        for (int q = threadIdx.x; q < n; q += kTbThreads) {
+            const int li = s + q % nw, lj = s + q / nw;
+            int gi, gj;
+            if (!gcell(li, lj, gi, gj)) continue;
+            const int c = lj * W + li;
+            double S0 = 0.0, S1 = 0.0, S2 = 0.0, e, fx, fy;
+            int kn = is_ghost(ph, 0, gi > 0) ? c : c - 1;
+            ghost_rule(ph, 0, gi > 0, sE[cur][kn], sFx[cur][kn], sFy[cur][kn], e, fx, fy);
+            add_x(L.kx, ph.c, ph.c2, +1.0, e, fx, fy, S0, S1, S2);
+            kn = is_ghost(ph, 1, gi < L.nx - 1) ? c : c + 1;
+            ghost_rule(ph, 1, gi < L.nx - 1, sE[cur][kn], sFx[cur][kn], sFy[cur][kn], e, fx, fy);
+            add_x(L.kx, ph.c, ph.c2, -1.0, e, fx, fy, S0, S1, S2);
+            kn = is_ghost(ph, 2, gj > 0) ? c : c - W;
+            ghost_rule(ph, 2, gj > 0, sE[cur][kn], sFx[cur][kn], sFy[cur][kn], e, fx, fy);
+            add_y(L.ky, ph.c, ph.c2, +1.0, e, fx, fy, S0, S1, S2);
+            kn = is_ghost(ph, 3, gj < L.ny - 1) ? c : c + W;
+            ghost_rule(ph, 3, gj < L.ny - 1, sE[cur][kn], sFx[cur][kn], sFy[cur][kn], e, fx, fy);
+            add_y(L.ky, ph.c, ph.c2, -1.0, e, fx, fy, S0, S1, S2);
+            const double ka = L.cdt * qa[c], ks = L.cdt * qs[c];
+            double f0 = qE[c], f1 = qFx[c], f2 = qFy[c], f3 = qT[c];
+            double E, Fx, Fy, T, tE, tFx, tFy, tT, g;
+            if (first) {
+                pseudo_core<2, true>(ph, L, sE[cur][c], sFx[cur][c], sFy[cur][c], sT[cur][c], S0, S1, S2, ka, ks, f0,
+                                     f1, f2, f3, dt, reach, local, E, Fx, Fy, T, tE, tFx, tFy, tT, g);
+                qE[c] = f0;
+                qFx[c] = f1;
+                qFy[c] = f2;
+                qT[c] = f3;
+                if (live && li >= M && li < M + kTbTile && lj >= M && lj < M + kTbTile) {
+                    const uint32_t k = (uint32_t)gj * (uint32_t)L.nx + (uint32_t)gi;
+                    st(f.E, k, f0);
+                    st(f.Fx, k, f1);
+                    st(f.Fy, k, f2);
+                    st(f.T, k, f3);
+                }
+            } else {
+                pseudo_core<2, false>(ph, L, sE[cur][c], sFx[cur][c], sFy[cur][c], sT[cur][c], S0, S1, S2, ka, ks, f0,
+                                      f1, f2, f3, dt, reach, local, E, Fx, Fy, T, tE, tFx, tFy, tT, g);
+            }
+            sE[cur ^ 1][c] = E;
+            sFx[cur ^ 1][c] = Fx;
+            sFy[cur ^ 1][c] = Fy;
+            sT[cur ^ 1][c] = T;
+        }
+        __syncthreads();
+        cur ^= 1;
+    }
+    if (!live) return;
+    for (int q = threadIdx.x; q < kTbTile * kTbTile; q += kTbThreads) {
+        const int ti = q % kTbTile, tj = q / kTbTile;
+        const int c = (M + tj) * W + M + ti;
+        const uint32_t k = (uint32_t)(by * kTbTile + tj) * (uint32_t)L.nx + (uint32_t)(bx * kTbTile + ti);
+        st(out.E, k, sE[cur][c]);
+        st(out.Fx, k, sFx[cur][c]);
+        st(out.Fy, k, sFy[cur][c]);
+        st(out.T, k, sT[cur][c]);
+    }
+}
+
+// ===========================================================================
 // Batched kernels: persistent grid-stride loops over a work list of
 // (problem, tile) entries; every problem carries its own level data, cycle
 // control (dtau, stop flag) and norm partials.  Buffer selectors are the same
@@ -550,6 +683,32 @@ void launch_check_state(hipStream_t st, int dim, int64_t n, double c, CSoa v, un
 void launch_check_sigma(hipStream_t st, int64_t n, const double* sa, const double* ss, unsigned long long* bad)
 {
     hipLaunchKernelGGL(k_check_sigma, dim3(nblocks(n)), dim3(kBlock), 0, st, n, sa, ss, bad);
+}
+
+bool smooth_tb_fits(int dim, const Lvl& L, int m)
+{
+    return dim == 2 && m >= 1 && m <= 3 && L.nx % kTbTile == 0 && L.ny % kTbTile == 0 && L.nx >= 2 * kTbTile &&
+           L.ny >= 2 * kTbTile;
+}
+
+void launch_smooth_tb(hipStream_t st, const Phys& ph, const Lvl& L, int m, bool up, CSoa fr, Soa f, CSoa u, Soa out,
+                      const double* dtau_dev, double reach, int local, CSoa uc, CSoa vc, int px, int py, double eta,
+                      const int* active)
+{
+    const dim3 g((unsigned)((L.nx / kTbTile) * (L.ny / kTbTile))), b(kTbThreads);
+#define M1_TB(MM)                                                                                                    \
+    do {                                                                                                             \
+        if (up)                                                                                                      \
+            hipLaunchKernelGGL((k_smooth_tb<MM, true>), g, b, 0, st, ph, L, fr, f, u, out, dtau_dev, reach, local, \
+                               uc, vc, px, py, eta, active);                                                         \
+        else                                                                                                         \
+            hipLaunchKernelGGL((k_smooth_tb<MM, false>), g, b, 0, st, ph, L, fr, f, u, out, dtau_dev, reach, local, \
+                               uc, vc, px, py, eta, active);                                                         \
+    } while (0)
+    if (m == 1) M1_TB(1);
+    else if (m == 2) M1_TB(2);
+    else M1_TB(3);
+#undef M1_TB
 }
 
 }  // namespace m1
