@@ -62,7 +62,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="hotwall", choices=["hotwall", "lognormal", "serve"])
+    ap.add_argument("--workload", default="hotwall", choices=["hotwall", "lognormal", "batch", "serve"])
     ap.add_argument("--n", type=int, default=0, help="grid side (default: the workload's own)")
     ap.add_argument("--precision", default=None, choices=["fp64", "mixed"],
                     help="default: fp64 for hotwall, mixed for lognormal")
@@ -311,6 +311,15 @@ def main():
                           "dtype": "f64" if args.serve_precision == "fp64" else "f64+f32",
                           "data": "synthetic", "config": {"workload": SERVE_DESC, "arena_gb": args.arena_gb},
                           "rates": legs}), flush=True)
+        return
+
+    if args.workload == "batch":
+        leg = batch_leg(torch, args.batch)
+        best = leg["mixed"]
+        print(json.dumps({"metric": METRIC, "value": best["solves_per_s"], "unit": "solves/s", "n_gpus": 1,
+                          "steps": 1, "warmup": 1, "ms_per_step": round(best["wall_s"] * 1e3, 2),
+                          "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64+f32",
+                          "data": "synthetic", "config": {"workload": leg["workload"]}, "batched": leg}), flush=True)
         return
 
     if args.workload == "lognormal":

@@ -155,6 +155,8 @@ struct m1_plan {
     m1::Ctrl* dfix = nullptr;      // always-live control for single operations (active = 1, settable dtau)
     m1::Ctrl* hctrl = nullptr;     // pinned host copy
     m1::TailArgs* dtail = nullptr; // device copy of the tail description (workspace)
+    m1::TailArgs hta{};            // host source of that copy (kept: the upload may still be in flight)
+    m1::TailArgs32 hta32{};
     int lt = 0;                    // first level run by the single-workgroup tail (L: none)
     bool mixed = false;
     bool tiled = true;  // LDS-tiled smoothing legs where the level shape allows (M1_TILED=0 turns them off)
@@ -597,8 +599,11 @@ size_t m1_workspace_bytes(const m1_grid* g, const m1_params* p)
     return (c.off + kAlign - 1) / kAlign * kAlign;
 }
 
-m1_status m1_plan_create(const m1_grid* g, const m1_params* p, const m1_opacity* op, void* workspace,
-                         size_t workspace_bytes, void* stream, m1_plan** out)
+// Plan set-up.  With `wait` the opacity check and all uploads are complete on
+// return; without it the plan is returned at once and the caller synchronises
+// the stream and then tests *hbad (== ULLONG_MAX: opacities valid) before use.
+static m1_status plan_setup(const m1_grid* g, const m1_params* p, const m1_opacity* op, void* workspace,
+                            size_t workspace_bytes, void* stream, bool wait, m1_plan** out)
 {
     if (!out) return M1_ERR_ARG;
     *out = nullptr;
@@ -699,9 +704,11 @@ m1_status m1_plan_create(const m1_grid* g, const m1_params* p, const m1_opacity*
         m1::launch_check_sigma(P->st, n0, op->sigma_a, op->sigma_s, P->dbad);
         st = hip_status(hipMemcpyAsync(P->hbad, P->dbad, sizeof(unsigned long long), hipMemcpyDeviceToHost, P->st));
     }
-    if (st == M1_OK) st = hip_status(hipStreamSynchronize(P->st));
-    if (st == M1_OK) st = last_launch();
-    if (st == M1_OK && *P->hbad != ULLONG_MAX) st = M1_ERR_ARG;
+    if (wait) {
+        if (st == M1_OK) st = hip_status(hipStreamSynchronize(P->st));
+        if (st == M1_OK) st = last_launch();
+        if (st == M1_OK && *P->hbad != ULLONG_MAX) st = M1_ERR_ARG;
+    }
     for (int l = 1; st == M1_OK && l < P->L; ++l) {
         m1::Fields F{};
         F.in[0] = P->lev[l - 1].sa;
@@ -717,16 +724,27 @@ m1_status m1_plan_create(const m1_grid* g, const m1_params* p, const m1_opacity*
         m1::launch_to_f32(P->st, P->lev[l].n, P->lev[l].ss, P->lev[l].ss32);
         st = last_launch();
     }
-    if (st == M1_OK) st = hip_status(hipMemcpyAsync(P->dtail, &ta, sizeof(ta), hipMemcpyHostToDevice, P->st));
+    P->hta = ta;
+    P->hta32 = ta32;
+    if (st == M1_OK)
+        st = hip_status(hipMemcpyAsync(P->dtail, &P->hta, sizeof(ta), hipMemcpyHostToDevice, P->st));
     if (st == M1_OK && P->mixed)
-        st = hip_status(hipMemcpyAsync(P->dtail32, &ta32, sizeof(ta32), hipMemcpyHostToDevice, P->st));
-    if (st == M1_OK) st = hip_status(hipStreamSynchronize(P->st));
+        st = hip_status(hipMemcpyAsync(P->dtail32, &P->hta32, sizeof(ta32), hipMemcpyHostToDevice, P->st));
+    if (st == M1_OK && wait) st = hip_status(hipStreamSynchronize(P->st));
+    if (st == M1_OK) st = last_launch();
     if (st != M1_OK) {
+        (void)hipStreamSynchronize(P->st);
         m1_plan_destroy(P);
         return st;
     }
     *out = P;
     return M1_OK;
+}
+
+m1_status m1_plan_create(const m1_grid* g, const m1_params* p, const m1_opacity* op, void* workspace,
+                         size_t workspace_bytes, void* stream, m1_plan** out)
+{
+    return plan_setup(g, p, op, workspace, workspace_bytes, stream, true, out);
 }
 
 void m1_plan_destroy(m1_plan* P)
@@ -1012,7 +1030,12 @@ struct m1_engine {
     std::mutex qmu;                   // pending queue and ticket table
     std::mutex rmu;                   // one round at a time
     std::deque<m1_req*> pending;
+    // Requests in the device tables, in table order.  A request that leaves becomes a null
+    // entry: its control stays inactive in its freed (not yet reused) workspace, so the
+    // tables stay valid without a rebuild until the next admission or compaction.
     std::vector<m1_req*> running;
+    int live = 0;
+    int64_t live_tiles = 0, dead_tiles = 0;
     std::unordered_map<uint64_t, m1_req*> reqs;
     uint64_t next = 1;
     bool dirty = true;
@@ -1103,14 +1126,17 @@ void finish(m1_engine& E, m1_req* R, m1_status st)
     E.done_cv.notify_all();
 }
 
-// FIFO admission: take pending requests while their workspace fits.
+// FIFO admission: take pending requests while their workspace fits.  Their
+// plans are set up without waiting; one synchronisation then checks every new
+// request's opacities (a bad one leaves with M1_ERR_ARG before any cycle runs).
 void admit(m1_engine& E)
 {
+    std::vector<m1_req*> fresh;
     for (;;) {
         m1_req* R = nullptr;
         {
             std::lock_guard<std::mutex> g(E.qmu);
-            if (E.pending.empty() || (int)E.running.size() >= E.maxp) return;
+            if (E.pending.empty() || E.live + (int)fresh.size() >= E.maxp) break;
             R = E.pending.front();
             if (R->cancel) {
                 E.pending.pop_front();
@@ -1121,14 +1147,23 @@ void admit(m1_engine& E)
                 continue;
             }
             size_t off;
-            if (!pool_alloc(E, R->ws_bytes, off)) return;
+            if (!pool_alloc(E, R->ws_bytes, off)) break;
             R->ws_off = off;
             E.pending.pop_front();
         }
-        m1_status st = m1_plan_create(&R->grid, &R->params, &R->op, E.arena + E.pool_off + R->ws_off, R->ws_bytes,
-                                      E.st, &R->plan);
+        m1_status st = plan_setup(&R->grid, &R->params, &R->op, E.arena + E.pool_off + R->ws_off, R->ws_bytes, E.st,
+                                  false, &R->plan);
         if (st != M1_OK) {
             finish(E, R, st);
+            continue;
+        }
+        fresh.push_back(R);
+    }
+    if (fresh.empty()) return;
+    const bool ok = hipStreamSynchronize(E.st) == hipSuccess && hipGetLastError() == hipSuccess;
+    for (m1_req* R : fresh) {
+        if (!ok || *R->plan->hbad != ULLONG_MAX) {
+            finish(E, R, ok ? M1_ERR_ARG : M1_ERR_DEVICE);
             continue;
         }
         R->t_admit = now_s();
@@ -1138,6 +1173,7 @@ void admit(m1_engine& E)
             R->state = REQ_RUNNING;
         }
         E.running.push_back(R);
+        ++E.live;
         E.dirty = true;
     }
 }
@@ -1146,6 +1182,10 @@ void admit(m1_engine& E)
 // and the work lists of every level operation.
 m1_status rebuild(m1_engine& E)
 {
+    E.running.erase(std::remove(E.running.begin(), E.running.end(), nullptr), E.running.end());
+    E.dead_tiles = 0;
+    E.live_tiles = 0;
+    for (const m1_req* R : E.running) E.live_tiles += (R->plan->lev[0].n + 255) / 256;
     const int np = (int)E.running.size();
     std::vector<m1::BProb> hp(np);
     std::vector<m1::BSlot> hs((size_t)np * m1::kMaxLevels);
@@ -1483,13 +1523,13 @@ m1_status m1_batch_run(m1_engine* E, int32_t cycles, int32_t* n_running, int32_t
     std::lock_guard<std::mutex> lk(E->rmu);
     admit(*E);
     m1_status st = M1_OK;
-    if (!E->running.empty()) {
+    if (E->live > 0) {
         if (E->dirty) st = rebuild(*E);
         if (st != M1_OK) return st;
         // step starts: b, |b| and a fresh control per starting problem (state back in x0 first)
         std::vector<int> init;
         for (int i = 0; i < (int)E->running.size(); ++i)
-            if (E->running[i]->need_init) {
+            if (E->running[i] && E->running[i]->need_init) {
                 init.push_back(i);
                 E->running[i]->need_init = false;
             }
@@ -1513,11 +1553,11 @@ m1_status m1_batch_run(m1_engine* E, int32_t cycles, int32_t* n_running, int32_t
             hipStreamSynchronize(E->st) != hipSuccess || hipGetLastError() != hipSuccess)
             return M1_ERR_DEVICE;
         // retire: cancelled, failed and completed requests leave with their state in x0
-        std::vector<m1_req*> keep;
-        std::vector<std::pair<m1_req*, m1_status>> done;
-        std::vector<int> back;  // running indices whose state must be copied back from x1
+        std::vector<std::pair<int, m1_status>> done;
+        std::vector<int> back;  // table indices whose state must be copied back from x1
         for (int i = 0; i < np; ++i) {
             m1_req* R = E->running[i];
+            if (!R) continue;
             const m1::Ctrl& h = E->hCtrl[i];
             bool cancel;
             {
@@ -1544,25 +1584,39 @@ m1_status m1_batch_run(m1_engine* E, int32_t cycles, int32_t* n_running, int32_t
                 if (!leaves) R->need_init = true;
             }
             if (leaves) {
-                done.push_back({R, out});
+                done.push_back({i, out});
                 if (h.flip) back.push_back(i);
-            } else {
-                keep.push_back(R);
             }
         }
         if (!back.empty()) {
             st = fine_tiles(*E, back);
             if (st != M1_OK) return st;
             m1::launch_b_flip_copy(E->st, E->dP, E->dS, E->dWL2, (int)E->hwl2.size());
-            if (hipStreamSynchronize(E->st) != hipSuccess || hipGetLastError() != hipSuccess) return M1_ERR_DEVICE;
         }
-        for (auto& d : done) finish(*E, d.first, d.second);
-        if (keep.size() != E->running.size()) E->dirty = true;
-        E->running.swap(keep);
+        bool stop = false;  // a cancelled request may leave mid-step: stop its kernels before its entry goes dead
+        for (auto& d : done)
+            if (E->hCtrl[d.first].active) {
+                m1::launch_ctrl_init(E->st, E->running[d.first]->plan->dctrl, m1::Ctrl{});
+                stop = true;
+            }
+        if ((!back.empty() || stop) &&
+            (hipStreamSynchronize(E->st) != hipSuccess || hipGetLastError() != hipSuccess))
+            return M1_ERR_DEVICE;
+        for (auto& d : done) {
+            m1_req* R = E->running[d.first];
+            const int64_t t = (R->plan->lev[0].n + 255) / 256;
+            finish(*E, R, d.second);
+            E->running[d.first] = nullptr;
+            --E->live;
+            E->live_tiles -= t;
+            E->dead_tiles += t;
+        }
+        // compact once dead entries would cost more block iterations than live ones
+        if (E->dead_tiles > E->live_tiles) E->dirty = true;
     }
-    E->n_run.store((int)E->running.size());
+    E->n_run.store(E->live);
     std::lock_guard<std::mutex> g(E->qmu);
-    if (n_running) *n_running = (int32_t)E->running.size();
+    if (n_running) *n_running = (int32_t)E->live;
     if (n_pending) *n_pending = (int32_t)E->pending.size();
     return M1_OK;
 }

@@ -12,6 +12,7 @@
 // device pseudo-time step `dtau_dev` (both always valid pointers), so that
 // whole V-cycles can be enqueued ahead of the host's convergence check.
 #include <algorithm>
+#include <cstdlib>
 #include <cfloat>
 
 #include "m1_cells.hpp"
@@ -565,7 +566,18 @@ void launch_apply(hipStream_t st, int dim, const Phys& ph, const Lvl& L, CSoa v,
     M1_DISPATCH(dim, k_apply, apply_blocks(L), ph, L, v, X, sgn, out, partials, active);
 }
 
-static unsigned bgrid(int nwl) { return (unsigned)std::max(1, std::min(nwl, 16384)); }
+// Blocks of a batched launch: one per work-list entry up to a cap (M1_BATCH_GRID, default 16384); above
+// it each block walks several entries.
+int batch_grid_cap()
+{
+    static const int cap = [] {
+        const char* e = std::getenv("M1_BATCH_GRID");
+        const int v = e ? std::atoi(e) : 16384;
+        return v > 0 ? v : 16384;
+    }();
+    return cap;
+}
+static unsigned bgrid(int nwl) { return (unsigned)std::max(1, std::min(nwl, batch_grid_cap())); }
 
 void launch_b_relax(hipStream_t st, const BProb* P, const BSlot* S, const uint32_t* wl, int nwl, int in_x1, int norm)
 {

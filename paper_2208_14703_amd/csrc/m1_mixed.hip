@@ -791,7 +791,7 @@ void launch_to_f32(hipStream_t st, int64_t n, const double* a, float* b)
     hipLaunchKernelGGL(k_to_f32, dim3(nblk(n)), dim3(kBlock32), 0, st, n, a, b);
 }
 
-static unsigned bmgrid(int nwl) { return (unsigned)(nwl < 1 ? 1 : (nwl > 16384 ? 16384 : nwl)); }
+static unsigned bmgrid(int nwl) { return (unsigned)(nwl < 1 ? 1 : (nwl > batch_grid_cap() ? batch_grid_cap() : nwl)); }
 
 void launch_bm_resid(hipStream_t st, const BProb* P, const BSlot* S, const BSlot32* S32, const uint32_t* wl, int nwl,
                      int pend_sel)

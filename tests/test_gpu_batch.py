@@ -91,6 +91,18 @@ def test_batch_budget_cancel_and_arguments():
     assert info is not None and info["status"] == 6
     got = to_host(vd)
     assert np.all(got[0] > 0) and np.all(got[3] > 0)
+    # a request with an invalid opacity leaves with M1_ERR_ARG before any cycle touches its state,
+    # while a valid one admitted in the same round runs normally
+    bad_sig = sig.copy()
+    bad_sig[0, 3, 5] = -1.0
+    vb = to_dev(v)
+    vg = to_dev(v)
+    tb = E.submit(prob, to_dev(bad_sig), vb, 2)
+    tg = E.submit(prob, to_dev(sig), vg, 1)
+    assert E.wait(tb)["status"] == 1
+    assert E.wait(tg)["status"] == 0
+    np.testing.assert_array_equal(to_host(vb), v)
+    assert not np.array_equal(to_host(vg), v)
     # mixed precision: a cancelled request's FP64 state may sit in the partner
     # buffer; it must come back to the caller's arrays, finite and admissible
     params = dict(PARAMS, precision="mixed")
