@@ -12,7 +12,7 @@ solves, bracketed by device synchronisation. value = cells * implicit steps / wa
 time, in millions (Mcell-updates/s).
 
 The same JSON line also carries:
-- roofline: the finest-level Jacobi sweep kernel k_relax<2>, timed with HIP events on the
+- roofline: the finest-level Jacobi sweep kernel k_relax<2, false, true>, timed with HIP events on the
   solver's stream, at 112 algorithmic bytes per cell.
 - traffic: the kernel's FETCH_SIZE + WRITE_SIZE counter bytes per launch, scaled by the same
   counters on a plain copy of known size. They are read from the counter summary under
@@ -380,7 +380,7 @@ def main():
     traffic = read_traffic(cells) if args.workload == "hotwall" and precision == "fp64" else None
     out["roofline"] = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                        "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                       "kernel": "k_relax<2> (finest-level FP64 Jacobi sweep)",
+                       "kernel": "k_relax<2, false, true> (finest-level FP64 Jacobi sweep)",
                        "algorithmic_bytes_per_launch": SWEEP_BYTES_PER_CELL * cells,
                        "avg_launch_us": round(t_sweep * 1e6, 2)}
     if not args.no_cpu_baseline:

@@ -55,18 +55,26 @@ __device__ __forceinline__ bool cell_of(const Lvl& L, uint32_t& k, int& i, int& 
     return true;
 }
 
-// Jacobi sweep; with partials != nullptr it also writes the block partials of
-// |b - A(u)|^2 of its input (finest level, beta = 0, gamma = 1 only).
-template <int DIM>
+// Jacobi sweep; NORM (the finest level's first sweep of a cycle, beta = 0,
+// gamma = 1) also writes the block partials of |b - A(u)|^2 of its input.  Two
+// instantiations: the plain sweep needs fewer registers (more waves in flight).
+// FINE: the finest level's sweep (beta = 0, gamma = 1, no per-cell gamma) with
+// those constants folded in (exact folds, so the results are unchanged).
+template <int DIM, bool NORM, bool FINE>
 __global__ __launch_bounds__(kBlock) void k_relax(Phys ph, Lvl L, CSoa rhs, const double* __restrict__ gcell,
                                                   double beta, double gamma, double omega, CSoa u, Soa out,
                                                   double* __restrict__ partials, const int* __restrict__ active)
 {
     if (*active == 0) return;
+    if (FINE) {
+        gcell = nullptr;
+        beta = 0.0;
+        gamma = 1.0;
+    }
     uint32_t k;
     int i, j;
     const bool in = cell_of(L, k, i, j);
-    if (!partials) {
+    if (!NORM) {
         if (in) relax_cell<DIM>(ph, L, rhs, gcell, beta, gamma, omega, u, out, k, i, j);
         return;
     }
@@ -343,8 +351,9 @@ __global__ __launch_bounds__(kTbThreads) void k_smooth_tb(Phys ph, Lvl L, CSoa f
 __device__ __forceinline__ const Soa& pick(const BSlot& s, int sel) { return sel == 0 ? s.v : (sel == 1 ? s.u : s.u2); }
 
 
+template <bool NORM>
 __global__ __launch_bounds__(kBlock) void kb_relax(const BProb* __restrict__ P, const BSlot* __restrict__ S,
-                                                   const uint32_t* __restrict__ wl, int nwl, int in_x1, int norm)
+                                                   const uint32_t* __restrict__ wl, int nwl, int in_x1)
 {
     M1_BATCH_LOOP(wl, nwl)
     const BSlot& s = S[p * kMaxLevels];
@@ -353,7 +362,7 @@ __global__ __launch_bounds__(kBlock) void kb_relax(const BProb* __restrict__ P, 
     const bool inside = k < (uint32_t)s.L.nx * (uint32_t)s.L.ny;
     int i = 0, j = 0;
     if (inside) ij_of(s.L.nx, s.L.sh, k, i, j);
-    if (!norm) {
+    if (!NORM) {
         if (inside) relax_cell<2>(pb.ph, s.L, cs(s.b), nullptr, 0.0, 1.0, pb.omega, cs(in), out, k, i, j);
         continue;
     }
@@ -547,8 +556,20 @@ __global__ void kb_gather_ctrl(const BProb* __restrict__ P, int np, Ctrl* __rest
 void launch_relax(hipStream_t st, int dim, const Phys& ph, const Lvl& L, CSoa rhs, const double* gcell, double beta,
                   double gamma, double omega, CSoa u, Soa out, double* partials, const int* active)
 {
-    M1_DISPATCH(dim, k_relax, nblocks((int64_t)L.nx * L.ny), ph, L, rhs, gcell, beta, gamma, omega, u, out, partials,
-                active);
+    const dim3 g(nblocks((int64_t)L.nx * L.ny)), b(kBlock);
+    const bool fine = !gcell && beta == 0.0 && gamma == 1.0;
+#define M1_RELAX(D, N, F)                                                                                             \
+    hipLaunchKernelGGL((k_relax<D, N, F>), g, b, 0, st, ph, L, rhs, gcell, beta, gamma, omega, u, out, partials, active)
+    if (dim == 2) {
+        if (partials) M1_RELAX(2, true, true);
+        else if (fine) M1_RELAX(2, false, true);
+        else M1_RELAX(2, false, false);
+    } else {
+        if (partials) M1_RELAX(1, true, true);
+        else if (fine) M1_RELAX(1, false, true);
+        else M1_RELAX(1, false, false);
+    }
+#undef M1_RELAX
 }
 
 void launch_pseudo(hipStream_t st, int dim, const Phys& ph, const Lvl& L, Soa f, CSoa u, Soa out, double dtau,
@@ -581,7 +602,9 @@ static unsigned bgrid(int nwl) { return (unsigned)std::max(1, std::min(nwl, batc
 
 void launch_b_relax(hipStream_t st, const BProb* P, const BSlot* S, const uint32_t* wl, int nwl, int in_x1, int norm)
 {
-    if (nwl > 0) hipLaunchKernelGGL(kb_relax, dim3(bgrid(nwl)), dim3(kBlock), 0, st, P, S, wl, nwl, in_x1, norm);
+    if (nwl <= 0) return;
+    if (norm) hipLaunchKernelGGL(kb_relax<true>, dim3(bgrid(nwl)), dim3(kBlock), 0, st, P, S, wl, nwl, in_x1);
+    else hipLaunchKernelGGL(kb_relax<false>, dim3(bgrid(nwl)), dim3(kBlock), 0, st, P, S, wl, nwl, in_x1);
 }
 void launch_b_norm_control(hipStream_t st, const BProb* P, const int* plist, int np, int mixed)
 {
