@@ -374,6 +374,7 @@ def main():
         "time_to_rtol_ms_per_time_step": round(ms_per_step / run["steps"], 3),
         "cycles_per_time_step": cycles / run["steps"], "solver_status": infos[-1]["status"],
         "final_rel_residual": infos[-1]["rel_residual"],
+        "launch_shapes": {k: binding.tune_get(k) for k in binding.TUNE_ENV},
     }
     t_sweep = sweep_timing(torch, plan, b, v_init.clone(), args.reps)
     achieved = SWEEP_BYTES_PER_CELL * cells / t_sweep / 1e9

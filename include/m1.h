@@ -182,6 +182,29 @@ m1_status m1_prolong_project(m1_plan* plan, int32_t level, const m1_state* u, co
 /* Wait for all work enqueued on the plan's stream. */
 m1_status m1_sync(m1_plan* plan);
 
+/* ---- launch-shape settings ----------------------------------------------------
+ * Process-wide settings of how the cycle is launched (environment variables
+ * M1_TAIL_CELLS, M1_TILED_MAX_CELLS, M1_GRAPHS, M1_BATCH_GRID give the initial
+ * values).  None of them changes any result: every launch shape runs the same
+ * per-cell arithmetic.  Keys:
+ *   "tail_cells"       levels of at most this many cells run in one workgroup
+ *                      (default 256; read when a plan is created);
+ *   "tiled_max_cells"  largest level whose smoothing legs run as one LDS-tiled
+ *                      launch each (2-D, sides multiples of 16; default 65536;
+ *                      0 = none; read when a plan is created);
+ *   "graphs"           1: m1_step and engine rounds replay their V-cycles from
+ *                      hipGraph recordings (made on first use per set of state
+ *                      buffers, resp. once the engine's resident set has been
+ *                      the same for a round); 0: launches are enqueued one by
+ *                      one (default 0; read when a plan or engine is created);
+ *   "batch_grid"       most blocks of one batched launch (default 16384; read
+ *                      at each launch, and when a V-cycle is recorded).
+ * m1_tune_set: M1_ERR_ARG for an unknown key or a value out of range.
+ * m1_tune_get: the current value, -1 for an unknown key.  The autotuner
+ * (paper_2208_14703_amd/autotune.py) times candidates and stores its choice. */
+m1_status m1_tune_set(const char* key, int64_t value);
+int64_t m1_tune_get(const char* key);
+
 /* ---- batched and served solves ------------------------------------------------
  * An engine advances many independent problems (requests) together.  Each
  * request is one 2-D problem (grid, opacity, state, number of implicit steps);
@@ -205,7 +228,8 @@ size_t m1_engine_request_bytes(const m1_grid* g, const m1_params* p);
 /* Engine over `arena` (device memory, 256-byte aligned, `arena_bytes` long;
  * owned by the caller, must outlive the engine).  `p` fixes the smoothing
  * structure every request must share (nu0, pseudo_steps (odd), sub_steps,
- * pseudo_local, omega, eta, nu_l = 1, precision M1_FP64); per-request
+ * pseudo_local, omega, eta, nu_l = 1, precision: M1_FP64 or M1_MIXED, each
+ * request's result equal to the bit to its single-problem solve); per-request
  * tolerances (rtol, max_cycles, dtau settings) may differ.  At most
  * `max_requests` requests are resident at once.  stream: hipStream_t.        */
 m1_status m1_engine_create(const m1_params* p, void* arena, size_t arena_bytes, int32_t max_requests, void* stream,

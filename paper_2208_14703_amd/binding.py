@@ -117,13 +117,43 @@ def lib():
         L.m1_batch_release.argtypes = [vp, ctypes.c_uint64]
         L.m1_serve_start.argtypes = [vp, ctypes.c_int32]
         L.m1_serve_stop.argtypes = [vp]
+        L.m1_tune_set.argtypes = [ctypes.c_char_p, ctypes.c_int64]
+        L.m1_tune_set.restype = ctypes.c_int
+        L.m1_tune_get.argtypes = [ctypes.c_char_p]
+        L.m1_tune_get.restype = ctypes.c_int64
         for name in ("m1_plan_create", "m1_residual", "m1_vcycle", "m1_step", "m1_apply_A", "m1_sweep",
                      "m1_pseudo_step", "m1_restrict", "m1_prolong_project", "m1_sync", "m1_level_dims",
                      "m1_engine_create", "m1_batch_submit", "m1_batch_run", "m1_batch_poll", "m1_batch_wait",
                      "m1_batch_cancel", "m1_batch_times", "m1_batch_release", "m1_serve_start", "m1_serve_stop"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
+        _apply_stored_tuning(L)
     return _lib
+
+
+TUNE_ENV = {"tail_cells": "M1_TAIL_CELLS", "tiled_max_cells": "M1_TILED_MAX_CELLS", "graphs": "M1_GRAPHS",
+            "batch_grid": "M1_BATCH_GRID"}
+
+
+def _apply_stored_tuning(L):
+    """Launch-shape settings the autotuner stored for this device (environment variables take precedence)."""
+    import torch
+    if not torch.cuda.is_available():
+        return
+    from . import autotune
+    settings = autotune.load(autotune.device_key()) or {}
+    for key, value in settings.items():
+        if key in TUNE_ENV and os.environ.get(TUNE_ENV[key]) is None:
+            L.m1_tune_set(key.encode(), int(value))
+
+
+def tune_set(key: str, value: int):
+    """Set a launch-shape setting (m1_tune_set); applies to plans and engines created afterwards."""
+    _check(lib().m1_tune_set(key.encode(), int(value)), "m1_tune_set")
+
+
+def tune_get(key: str) -> int:
+    return int(lib().m1_tune_get(key.encode()))
 
 
 def _check(status: int, what: str):

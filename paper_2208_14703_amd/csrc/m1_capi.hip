@@ -3,6 +3,8 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
+#include <string>
 #include <initializer_list>
 #include <utility>
 #include <cfloat>
@@ -160,8 +162,21 @@ struct m1_plan {
     int lt = 0;                    // first level run by the single-workgroup tail (L: none)
     bool mixed = false;
     bool tiled = true;  // LDS-tiled smoothing legs where the level shape allows (M1_TILED=0 turns them off)
+    int64_t tiled_max = 0;  // ... on levels of at most this many cells
     Soa32 base32{}, r32{}, dA{}, dB{}, rho0{};  // mixed: finest-level FP32 buffers
     m1::TailArgs32* dtail32 = nullptr;           // mixed: device copy of the tail description
+    // m1_step's V-cycles replayed from hipGraph recordings, keyed by the buffers a cycle starts from
+    struct CycleGraph {
+        const double *in_cur, *in_other;
+        const float* in_pend;  // mixed, after the first cycle: the correction the cycle applies
+        bool first;
+        Soa cur, other;  // where the cycle leaves the state and its partner
+        Soa32 pend;
+        hipGraphExec_t exec;
+    };
+    bool graphs = false;
+    hipStream_t cap = nullptr;  // private stream, only ever used for recording
+    std::vector<CycleGraph> cyc;
 };
 
 namespace {
@@ -229,18 +244,31 @@ void carve(m1_plan& P, Carver& c, const std::vector<int>& nxs, const std::vector
 }
 
 // Levels with at most this many cells run inside the single-workgroup tail kernel.
-int64_t tail_cells()
+// Launch-shape settings (m1_tune_set): read when a plan or engine is created.
+// Environment variables give the initial values.  None of them changes results.
+struct Tuning {
+    std::atomic<int64_t> tail_cells{256};          // levels of at most this many cells run in the one-workgroup tail
+    std::atomic<int64_t> tiled_max_cells{65536};   // largest level smoothed by the LDS-tiled legs
+    std::atomic<int64_t> graphs{0};                // replay V-cycles from hipGraph recordings
+    Tuning()
+    {
+        if (const char* e = std::getenv("M1_GRAPHS")) graphs = std::atoll(e) != 0;
+        if (const char* e = std::getenv("M1_TAIL_CELLS")) tail_cells = std::atoll(e);
+        if (const char* e = std::getenv("M1_TILED_MAX_CELLS")) tiled_max_cells = std::atoll(e);
+        if (const char* e = std::getenv("M1_BATCH_GRID")) {
+            const int v = std::atoi(e);
+            if (v > 0) m1::set_batch_grid_cap(v);
+        }
+    }
+};
+Tuning& tuning()
 {
-    const char* e = std::getenv("M1_TAIL_CELLS");
-    return e ? std::atoll(e) : 256;
+    static Tuning t;
+    return t;
 }
-
-// Largest level (cells) smoothed by the LDS-tiled kernels (M1_TILED_MAX_CELLS).
-int64_t tiled_max_cells()
-{
-    const char* e = std::getenv("M1_TILED_MAX_CELLS");
-    return e ? std::atoll(e) : 65536;
-}
+int64_t tail_cells() { return tuning().tail_cells.load(); }
+int64_t tiled_max_cells() { return tuning().tiled_max_cells.load(); }
+bool use_graphs() { return tuning().graphs.load() != 0; }
 
 void fill_level_params(m1_plan& P)
 {
@@ -365,7 +393,7 @@ void vcycle_impl(m1_plan& P, Soa& cur, Soa& other, const Gate& G, bool control =
     // work and the large LDS blocks of the tiled form cost more than the launches it saves)
     std::vector<char> tiled(P.L, 0);
     for (int l = 1; l < std::min(P.lt, P.L); ++l)
-        tiled[l] = P.tiled && P.lev[l].n <= tiled_max_cells() && m1::smooth_tb_fits(P.dim, P.lev[l].L, p.pseudo_steps);
+        tiled[l] = P.tiled && P.lev[l].n <= P.tiled_max && m1::smooth_tb_fits(P.dim, P.lev[l].L, p.pseudo_steps);
     ul[0] = cur;
     Soa rb_prev = P.rfine;
     for (int l = 1; l < P.L; ++l) {
@@ -509,6 +537,68 @@ void mx_vcycle(m1_plan& P, Soa& cur64, Soa& other64, const Gate& G, bool control
     m1::launch_mx_prolong_fine(P.st, P.dim, P.ph, f0.nx, f0.ny, P.px, P.py, p.eta, cs(cur64), cs(el[0]), cs(el[1]),
                                cs(P.lev[1].d), el[0], G.active);
     pend = sweeps(el[0], p.nu0, false);
+}
+
+// ---- recorded launch sequences (hipGraph) -----------------------------------
+// Record what `enqueue` launches on the stream in `*slot` into an executable
+// graph: during the recording the slot holds the private stream `cap` (created
+// on first use), so nothing runs and the caller's stream is untouched.
+template <class F>
+m1_status record(hipStream_t* slot, hipStream_t& cap, F&& enqueue, hipGraphExec_t* out)
+{
+    *out = nullptr;
+    if (!cap && hipStreamCreateWithFlags(&cap, hipStreamNonBlocking) != hipSuccess) return M1_ERR_DEVICE;
+    const hipStream_t saved = *slot;
+    *slot = cap;
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+        enqueue();
+        const hipError_t launch = hipGetLastError();
+        e = hipStreamEndCapture(cap, &g);
+        if (e == hipSuccess) e = launch;
+    }
+    *slot = saved;
+    if (e == hipSuccess) e = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
+    if (g) (void)hipGraphDestroy(g);
+    return hip_status(e);
+}
+
+void drop_cycle_graphs(m1_plan& P)
+{
+    if (P.cyc.empty()) return;
+    (void)hipStreamSynchronize(P.st);
+    for (auto& c : P.cyc) (void)hipGraphExecDestroy(c.exec);
+    P.cyc.clear();
+}
+
+// One controlled V-cycle of a time step, replayed from its recording (made on
+// first use for these buffers).  Every launch of a cycle is fixed by the plan
+// and the buffers it starts from: the cycle control, dtau and stop flag are
+// read by the kernels from device memory.
+m1_status graph_cycle(m1_plan& P, Soa& cur, Soa& other, Soa32& pend, const Gate& G, bool first)
+{
+    const bool f = P.mixed && first;
+    const float* pk = (P.mixed && !first) ? pend.E : nullptr;
+    m1_plan::CycleGraph* hit = nullptr;
+    for (auto& c : P.cyc)
+        if (c.in_cur == cur.E && c.in_other == other.E && c.in_pend == pk && c.first == f) hit = &c;
+    if (!hit) {
+        if (P.cyc.size() >= 8) drop_cycle_graphs(P);  // state buffers of earlier calls
+        m1_plan::CycleGraph c{cur.E, other.E, pk, f, cur, other, pend, nullptr};
+        const m1_status s = record(&P.st, P.cap, [&] {
+            if (P.mixed) mx_vcycle(P, c.cur, c.other, G, true, first, c.pend);
+            else vcycle_impl(P, c.cur, c.other, G, true);
+        }, &c.exec);
+        if (s != M1_OK) return s;
+        P.cyc.push_back(c);
+        hit = &P.cyc.back();
+    }
+    if (hipGraphLaunch(hit->exec, P.st) != hipSuccess) return M1_ERR_DEVICE;
+    cur = hit->cur;
+    other = hit->other;
+    pend = hit->pend;
+    return M1_OK;
 }
 
 // |b + sgn A_0(v)| (sgn = -1: the residual; 0: |b|) into P.dscal[0] (device)
@@ -668,6 +758,8 @@ static m1_status plan_setup(const m1_grid* g, const m1_params* p, const m1_opaci
     {
         const char* e = std::getenv("M1_TILED");
         P->tiled = p->nu_l == 1 && !(e && e[0] == '0');
+        P->tiled_max = tiled_max_cells();
+        P->graphs = use_graphs();
     }
     const bool tail_ok = P->L <= m1::kMaxLevels && p->nu_l == 1;
     if (!tail_ok) P->lt = P->L;  // the tail fuses exactly one Jacobi sweep per pseudo-time step
@@ -750,6 +842,8 @@ m1_status m1_plan_create(const m1_grid* g, const m1_params* p, const m1_opacity*
 void m1_plan_destroy(m1_plan* P)
 {
     if (!P) return;
+    drop_cycle_graphs(*P);
+    if (P->cap) (void)hipStreamDestroy(P->cap);
     if (P->hpin) (void)hipHostFree(P->hpin);
     delete P;
 }
@@ -870,8 +964,14 @@ m1_status m1_step(m1_plan* P, m1_state* v, int32_t nsteps, m1_info* info)
         for (;;) {
             const int todo = std::min(chunk, p.max_cycles + 1 - enqueued);
             for (int c = 0; c < todo; ++c) {
-                if (P->mixed) mx_vcycle(*P, cur, other, G, true, enqueued + c == 0, pend);
-                else vcycle_impl(*P, cur, other, G, true);
+                if (P->graphs) {
+                    const m1_status s = graph_cycle(*P, cur, other, pend, G, enqueued + c == 0);
+                    if (s != M1_OK) return s;
+                } else if (P->mixed) {
+                    mx_vcycle(*P, cur, other, G, true, enqueued + c == 0, pend);
+                } else {
+                    vcycle_impl(*P, cur, other, G, true);
+                }
             }
             enqueued += todo;
             if (hipMemcpyAsync(P->hctrl, P->dctrl, sizeof(m1::Ctrl), hipMemcpyDeviceToHost, P->st) != hipSuccess ||
@@ -970,6 +1070,29 @@ m1_status m1_prolong_project(m1_plan* P, int32_t level, const m1_state* u, const
     return last_launch();
 }
 
+m1_status m1_tune_set(const char* key, int64_t value)
+{
+    if (!key || value < 0) return M1_ERR_ARG;
+    const std::string k(key);
+    if (k == "tail_cells") tuning().tail_cells = value;
+    else if (k == "tiled_max_cells") tuning().tiled_max_cells = value;
+    else if (k == "graphs" && value <= 1) tuning().graphs = value;
+    else if (k == "batch_grid" && value >= 1 && value <= (int64_t(1) << 24)) m1::set_batch_grid_cap((int)value);
+    else return M1_ERR_ARG;
+    return M1_OK;
+}
+
+int64_t m1_tune_get(const char* key)
+{
+    if (!key) return -1;
+    const std::string k(key);
+    if (k == "tail_cells") return tuning().tail_cells.load();
+    if (k == "tiled_max_cells") return tuning().tiled_max_cells.load();
+    if (k == "graphs") return tuning().graphs.load();
+    if (k == "batch_grid") return m1::batch_grid_cap();
+    return -1;
+}
+
 }  // extern "C"
 
 // ============================================================================
@@ -1048,6 +1171,12 @@ struct m1_engine {
     int Lmax = 1;
     std::vector<uint32_t> hwl, hwl2;
     std::vector<int> hpl;
+    // one V-cycle of all running problems replayed from a hipGraph recording, made once the
+    // tables have stayed the same for a round and dropped when they are rebuilt
+    bool graphs = false;
+    hipStream_t cap = nullptr;  // private stream, only ever used for recording
+    hipGraphExec_t cyc = nullptr;
+    int same_rounds = 0;
     // serving loop
     int device = 0;
     std::thread server;
@@ -1182,6 +1311,11 @@ void admit(m1_engine& E)
 // and the work lists of every level operation.
 m1_status rebuild(m1_engine& E)
 {
+    if (E.cyc) {  // every round ends synchronised: the recording is not in flight
+        (void)hipGraphExecDestroy(E.cyc);
+        E.cyc = nullptr;
+    }
+    E.same_rounds = 0;
     E.running.erase(std::remove(E.running.begin(), E.running.end(), nullptr), E.running.end());
     E.dead_tiles = 0;
     E.live_tiles = 0;
@@ -1432,6 +1566,7 @@ m1_status m1_engine_create(const m1_params* p, void* arena, size_t arena_bytes, 
     if (!E) return M1_ERR_DEVICE;
     E->params = *p;
     E->mixed = p->precision == M1_MIXED;
+    E->graphs = use_graphs();
     E->st = static_cast<hipStream_t>(stream);
     E->arena = static_cast<char*>(arena);
     E->arena_bytes = arena_bytes;
@@ -1483,6 +1618,8 @@ void m1_engine_destroy(m1_engine* E)
         delete kv.second;
     }
     if (E->hCtrl) (void)hipHostFree(E->hCtrl);
+    if (E->cyc) (void)hipGraphExecDestroy(E->cyc);
+    if (E->cap) (void)hipStreamDestroy(E->cap);
     delete E;
 }
 
@@ -1543,10 +1680,24 @@ m1_status m1_batch_run(m1_engine* E, int32_t cycles, int32_t* n_running, int32_t
             m1::launch_b_init_tiles(E->st, E->dP, E->dS, E->dWL2, (int)E->hwl2.size());
             m1::launch_b_init_ctrl(E->st, E->dP, E->dS, dinit, (int)init.size());
         }
-        for (int c = 0; c < cycles; ++c) {
-            if (E->mixed) bm_vcycle(*E);
-            else b_vcycle(*E);
+        const bool replay = E->graphs && E->same_rounds > 0;
+        if (replay && !E->cyc) {
+            st = record(&E->st, E->cap, [&] {
+                if (E->mixed) bm_vcycle(*E);
+                else b_vcycle(*E);
+            }, &E->cyc);
+            if (st != M1_OK) return st;
         }
+        for (int c = 0; c < cycles; ++c) {
+            if (replay) {
+                if (hipGraphLaunch(E->cyc, E->st) != hipSuccess) return M1_ERR_DEVICE;
+            } else if (E->mixed) {
+                bm_vcycle(*E);
+            } else {
+                b_vcycle(*E);
+            }
+        }
+        ++E->same_rounds;
         const int np = (int)E->running.size();
         m1::launch_b_gather_ctrl(E->st, E->dP, np, E->dCtrl);
         if (hipMemcpyAsync(E->hCtrl, E->dCtrl, sizeof(m1::Ctrl) * np, hipMemcpyDeviceToHost, E->st) != hipSuccess ||

@@ -137,6 +137,7 @@ struct BProb {
 
 // mixed precision (m1_mixed.hip)
 int batch_grid_cap();
+void set_batch_grid_cap(int cap);
 // batched FP64 kernels (m1_kernels.hip); `wl` is a work list of nwl entries,
 // `plist` a list of problem indices
 void launch_b_relax(hipStream_t st, const BProb* P, const BSlot* S, const uint32_t* wl, int nwl, int in_x1, int norm);

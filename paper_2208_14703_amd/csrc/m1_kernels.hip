@@ -12,7 +12,7 @@
 // device pseudo-time step `dtau_dev` (both always valid pointers), so that
 // whole V-cycles can be enqueued ahead of the host's convergence check.
 #include <algorithm>
-#include <cstdlib>
+#include <atomic>
 #include <cfloat>
 
 #include "m1_cells.hpp"
@@ -369,6 +369,7 @@ __global__ __launch_bounds__(kBlock) void kb_relax(const BProb* __restrict__ P, 
     double q = 0.0;
     if (inside) q = relax_cell<2, true>(pb.ph, s.L, cs(s.b), nullptr, 0.0, 1.0, pb.omega, cs(in), out, k, i, j);
     block_partial(q, pb.partials + tile);
+    __syncthreads();  // the next tile of this block reuses the reduction slots
     }
 }
 
@@ -496,6 +497,7 @@ __global__ __launch_bounds__(kBlock) void kb_init_tiles(const BProb* __restrict_
             q = fma(E, E, fma(fx, fx, fma(fy, fy, bT * bT)));
         }
         block_partial(q, pb.partials + tile);
+        __syncthreads();  // the next tile of this block reuses the reduction slots
     }
 }
 
@@ -587,17 +589,11 @@ void launch_apply(hipStream_t st, int dim, const Phys& ph, const Lvl& L, CSoa v,
     M1_DISPATCH(dim, k_apply, apply_blocks(L), ph, L, v, X, sgn, out, partials, active);
 }
 
-// Blocks of a batched launch: one per work-list entry up to a cap (M1_BATCH_GRID, default 16384); above
-// it each block walks several entries.
-int batch_grid_cap()
-{
-    static const int cap = [] {
-        const char* e = std::getenv("M1_BATCH_GRID");
-        const int v = e ? std::atoi(e) : 16384;
-        return v > 0 ? v : 16384;
-    }();
-    return cap;
-}
+// Blocks of a batched launch: one per work-list entry up to a cap (tuning key
+// "batch_grid"); above it each block walks several entries.
+static std::atomic<int> g_batch_grid{16384};
+int batch_grid_cap() { return g_batch_grid.load(std::memory_order_relaxed); }
+void set_batch_grid_cap(int cap) { g_batch_grid.store(cap, std::memory_order_relaxed); }
 static unsigned bgrid(int nwl) { return (unsigned)std::max(1, std::min(nwl, batch_grid_cap())); }
 
 void launch_b_relax(hipStream_t st, const BProb* P, const BSlot* S, const uint32_t* wl, int nwl, int in_x1, int norm)

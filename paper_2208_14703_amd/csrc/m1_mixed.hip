@@ -611,6 +611,7 @@ __global__ __launch_bounds__(kBlock32) void kbm_resid(const BProb* __restrict__ 
                              k, i, j);
     }
     mx_block_partial(q, pb.partials + tile);
+    __syncthreads();  // the next tile of this block reuses the reduction slots
     }
 }
 

@@ -78,3 +78,26 @@ def test_one_dimensional_grid_validation():
     assert L.m1_workspace_bytes(ctypes.byref(g), ctypes.byref(p)) > 0
     g.ny = 2
     assert L.m1_workspace_bytes(ctypes.byref(g), ctypes.byref(p)) == 0
+
+
+def test_tuning_settings_round_trip():
+    """Launch-shape settings: known keys round-trip, unknown keys and bad values are rejected (host only)."""
+    from paper_2208_14703_amd import binding
+    L = binding.lib()
+    for key in ("tail_cells", "tiled_max_cells", "batch_grid"):
+        old = binding.tune_get(key)
+        assert old > 0
+        binding.tune_set(key, old + 1)
+        assert binding.tune_get(key) == old + 1
+        binding.tune_set(key, old)
+        assert binding.tune_get(key) == old
+    g = binding.tune_get("graphs")
+    assert g in (0, 1)
+    binding.tune_set("graphs", 1 - g)
+    assert binding.tune_get("graphs") == 1 - g
+    binding.tune_set("graphs", g)
+    assert L.m1_tune_set(b"graphs", 2) == 1
+    assert L.m1_tune_set(b"no_such_key", 5) == 1
+    assert L.m1_tune_get(b"no_such_key") == -1
+    assert L.m1_tune_set(b"tail_cells", -1) == 1
+    assert L.m1_tune_set(b"batch_grid", 0) == 1

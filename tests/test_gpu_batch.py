@@ -158,3 +158,44 @@ def test_serving_loop_matches_alone(precision):
     assert E.wait(t)["status"] == 0
     E.serve_stop()
     np.testing.assert_array_equal(to_host(vd), alone(prob, v, sig, ns, params)[0])
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_launch_shape_settings_do_not_change_results(precision):
+    """The autotuner's settings (m1_tune_set) only move work between launches:
+    a plain solve with the tail and tiled bounds moved across its levels, and a
+    batched run whose grid cap makes every block loop over many tiles, give
+    the default settings' results to the bit."""
+    announce("launch shapes", precision)
+    params = dict(PARAMS, precision=precision)
+    keys = ("tail_cells", "tiled_max_cells", "batch_grid")
+    saved = {key: binding.tune_get(key) for key in keys}
+    prob, v, sig = inputs.random_problem(41, 2, 96, 80, cfl=100.0, block=8)
+    cases = problems(4)
+    need = sum(binding.Engine.request_bytes(p, params) for p, _, _, _ in cases)
+    settings = [dict(saved), dict(tail_cells=64, tiled_max_cells=0, batch_grid=7),
+                dict(tail_cells=1024, tiled_max_cells=262144, batch_grid=64)]
+    outs = []
+    try:
+        for st in settings:
+            for key in keys:
+                binding.tune_set(key, st[key])
+            one, info = alone(prob, v, sig, 2, params)
+            assert info["status"] == 0
+            E = binding.Engine(need + (16 << 20), params, max_requests=8)
+            states, tickets = [], []
+            for p, bv, bs, ns in cases:
+                vd = to_dev(bv)
+                states.append(vd)
+                tickets.append(E.submit(p, to_dev(bs), vd, ns))
+            infos = [E.wait(t) for t in tickets]
+            assert all(i["status"] == 0 for i in infos)
+            outs.append((one, info["cycles"], [to_host(x) for x in states], [i["cycles"] for i in infos]))
+    finally:
+        for key in keys:
+            binding.tune_set(key, saved[key])
+    for one, cyc, batch, bcyc in outs[1:]:
+        np.testing.assert_array_equal(one, outs[0][0])
+        assert cyc == outs[0][1] and bcyc == outs[0][3]
+        for a, b in zip(batch, outs[0][2]):
+            np.testing.assert_array_equal(a, b)
