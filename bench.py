@@ -12,8 +12,9 @@ solves, bracketed by device synchronisation. value = cells * implicit steps / wa
 time, in millions (Mcell-updates/s).
 
 The same JSON line also carries:
-- roofline: the finest-level Jacobi sweep kernel k_relax<2, false, true>, timed with HIP events on the
-  solver's stream, at 112 algorithmic bytes per cell.
+- roofline: the finest-level Jacobi sweep kernel (k_relax_lds<rows, false>, the LDS-staged
+  sweep, or k_relax<2, false, true> when the staged sweep is off), timed with HIP events on
+  the solver's stream, at 112 algorithmic bytes per cell.
 - traffic: the kernel's FETCH_SIZE + WRITE_SIZE counter bytes per launch, scaled by the same
   counters on a plain copy of known size. They are read from the counter summary under
   profiles/, and are null when the kernel sources have changed since it was taken.
@@ -53,7 +54,16 @@ METRIC = "Mcell-updates/s + time to 1e-8 residual; batched solves/s with p50/p99
 HBM_PEAK_GBS = 8000.0
 SWEEP_BYTES_PER_CELL = 112  # v (E,Fx,Fy,T) 32 + b 32 + sigma 16 read, v' 32 written
 SOLVER = dict(omega=0.8, levels=0)
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_relax_hotwall1024_traffic.txt")
+def sweep_kernel():
+    """Name of the finest-level sweep kernel that m1_sweep launches under the current settings."""
+    rows = binding.tune_get("sweep_rows")
+    return f"k_relax_lds<{rows}, false>" if rows > 0 else "k_relax<2, false, true>"
+
+
+def traffic_file():
+    rows = binding.tune_get("sweep_rows")
+    name = f"k_relax_lds{rows}" if rows > 0 else "k_relax"
+    return os.path.join(ROOT, "profiles", f"{name}_hotwall1024_traffic.txt")
 COPY_ELEMS = 1 << 27  # 1 GiB of float64 per copy launch
 
 
@@ -85,11 +95,12 @@ def parse():
 def read_traffic(cells: int):
     """Counter bytes per k_relax launch from the committed summary, if the kernel is unchanged."""
     try:
-        kv = dict(line.split(":", 1) for line in open(TRAFFIC_FILE) if ":" in line and not line.startswith(" "))
+        kv = dict(line.split(":", 1) for line in open(traffic_file()) if ":" in line and not line.startswith(" "))
     except OSError:
         return None
     kv = {k.strip(): v.strip() for k, v in kv.items()}
-    if kv.get("sources_sha256") != sources_hash() or int(kv.get("cells", -1)) != cells:
+    if (kv.get("sources_sha256") != sources_hash() or int(kv.get("cells", -1)) != cells
+            or kv.get("kernel") != sweep_kernel()):
         return None
     return float(kv["traffic_bytes_per_launch"])
 
@@ -381,7 +392,7 @@ def main():
     traffic = read_traffic(cells) if args.workload == "hotwall" and precision == "fp64" else None
     out["roofline"] = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                        "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                       "kernel": "k_relax<2, false, true> (finest-level FP64 Jacobi sweep)",
+                       "kernel": f"{sweep_kernel()} (finest-level FP64 Jacobi sweep)",
                        "algorithmic_bytes_per_launch": SWEEP_BYTES_PER_CELL * cells,
                        "avg_launch_us": round(t_sweep * 1e6, 2)}
     if not args.no_cpu_baseline:

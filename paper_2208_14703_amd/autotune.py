@@ -6,13 +6,14 @@ The launch-shape settings do not change results: every launch shape runs the
 same per-cell arithmetic, and the tuner checks that each candidate reproduces
 the default's result bit for bit. It picks, by coordinate descent on measured
 time:
+  * sweep_rows: tile rows of the LDS-staged finest-level sweep (0: unstaged);
   * tail_cells: levels of at most this many cells run in one workgroup;
   * tiled_max_cells: largest level whose smoothing legs run as one LDS-tiled
     launch each;
   * graphs: V-cycles replayed from hipGraph recordings, or enqueued launch by
     launch;
   * batch_grid: most blocks of one batched launch.
-tail_cells and tiled_max_cells are timed on one time step of the hot-wall
+sweep_rows, tail_cells and tiled_max_cells are timed on one time step of the hot-wall
 problem (side n), batch_grid on the batched engine over `batch` problems of the
 batched workload, graphs on both (sum of the two times).
 With --write the choice is stored in tuning.json beside this file, keyed by the
@@ -32,6 +33,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 TUNING_FILE = os.path.join(HERE, "tuning.json")
 
 CANDIDATES = {
+    "sweep_rows": [0, 4, 8, 16],
     "tail_cells": [64, 256, 1024],
     "tiled_max_cells": [0, 4096, 16384, 65536, 262144],
     "graphs": [0, 1],

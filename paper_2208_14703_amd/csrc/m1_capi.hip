@@ -253,6 +253,7 @@ struct Tuning {
     Tuning()
     {
         if (const char* e = std::getenv("M1_GRAPHS")) graphs = std::atoll(e) != 0;
+        if (const char* e = std::getenv("M1_SWEEP_ROWS")) (void)m1::set_sweep_rows(std::atoi(e));
         if (const char* e = std::getenv("M1_TAIL_CELLS")) tail_cells = std::atoll(e);
         if (const char* e = std::getenv("M1_TILED_MAX_CELLS")) tiled_max_cells = std::atoll(e);
         if (const char* e = std::getenv("M1_BATCH_GRID")) {
@@ -427,6 +428,15 @@ void vcycle_impl(m1_plan& P, Soa& cur, Soa& other, const Gate& G, bool control =
             m1::launch_smooth_tb(P.st, P.ph, f.L, p.pseudo_steps, true, cs(f.f), f.f, cs(ul[l]), out, G.dtau_dev,
                                  P.reach, p.pseudo_local, cs(ul[l + 1]), cs(c.v), P.px, P.py, p.eta, G.active);
             ul[l] = out;
+            continue;
+        }
+        if (l == 0 && P.dim == 2 && p.nu0 > 0 &&
+            m1::launch_relax_lds(P.st, P.ph, f.L, cs(P.b), p.omega, cs(ul[0]), other, G.active, cs(ul[1]), cs(c.v),
+                                 P.px, P.py, p.eta)) {
+            // correction, projection and the first post-sweep in one launch
+            cur = other;
+            other = ul[0];
+            fine_sweeps(P, cur, other, p.nu0 - 1, G);
             continue;
         }
         m1::launch_prolong_project(P.st, P.dim, P.ph, f.nx, f.ny, P.px, P.py, p.eta, cs(ul[l]), cs(ul[l + 1]),
@@ -1077,6 +1087,7 @@ m1_status m1_tune_set(const char* key, int64_t value)
     if (k == "tail_cells") tuning().tail_cells = value;
     else if (k == "tiled_max_cells") tuning().tiled_max_cells = value;
     else if (k == "graphs" && value <= 1) tuning().graphs = value;
+    else if (k == "sweep_rows" && value <= 16 && m1::set_sweep_rows((int)value)) {}
     else if (k == "batch_grid" && value >= 1 && value <= (int64_t(1) << 24)) m1::set_batch_grid_cap((int)value);
     else return M1_ERR_ARG;
     return M1_OK;
@@ -1089,6 +1100,7 @@ int64_t m1_tune_get(const char* key)
     if (k == "tail_cells") return tuning().tail_cells.load();
     if (k == "tiled_max_cells") return tuning().tiled_max_cells.load();
     if (k == "graphs") return tuning().graphs.load();
+    if (k == "sweep_rows") return m1::sweep_rows();
     if (k == "batch_grid") return m1::batch_grid_cap();
     return -1;
 }

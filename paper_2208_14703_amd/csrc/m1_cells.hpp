@@ -16,23 +16,22 @@ namespace m1 {
 // With NORM (only for the finest-level sweep, beta = 0, gamma = 1) the cell's
 // share of |b - A(u)|^2 of the INPUT u is returned: b - A(u) = B - D(u), where
 // B = b + S(u) is formed for the update anyway.
-template <int DIM, bool NORM = false>
-__device__ __forceinline__ double relax_cell(const Phys& ph, const Lvl& L, const CSoa& rhs, const double* gcell,
-                                             double beta, double gamma, double omega, const CSoa& u, const Soa& out,
-                                             uint32_t k, int i, int j)
+// The update of relax_cell from the cell's off-diagonal sum S and its own
+// state: u.T is Tin, the other components come from cen(0..2) (E, Fx, Fy),
+// called only where needed.  Shared by every form of the sweep.
+template <int DIM, bool NORM, class Cen>
+__device__ __forceinline__ double relax_update(const Phys& ph, const Lvl& L, const CSoa& rhs, double g, double beta,
+                                               double omega, double S0, double S1, double S2, double Tin, Cen cen,
+                                               const Soa& out, uint32_t k)
 {
-    double S0, S1, S2;
-    offdiag<DIM>(ph, L, u, i, j, k, S0, S1, S2);
-    const double g = gcell ? ld(gcell, k) : gamma;
     const double BE = fma(g, S0, ld(rhs.E, k));
     const double BFx = fma(g, S1, ld(rhs.Fx, k));
     const double BFy = (DIM == 2) ? fma(g, S2, ld(rhs.Fy, k)) : 0.0;
     const double BT = ld(rhs.T, k);
     const double ka = L.cdt * ld(L.sa, k), ks = L.cdt * ld(L.ss, k);
-    const double Tin = ld(u.T, k);
     double q = 0.0;
     if (NORM) {
-        const double Ein = ld(u.E, k), Fxin = ld(u.Fx, k), Fyin = (DIM == 2) ? ld(u.Fy, k) : 0.0;
+        const double Ein = cen(0), Fxin = cen(1), Fyin = (DIM == 2) ? cen(2) : 0.0;
         const double T2 = Tin * Tin;
         const double ex = ka * fma(-ph.a_r * T2, T2, Ein);  // ka (E - a_r T^4)
         const double dF = L.a + ka + ks;
@@ -45,11 +44,11 @@ __device__ __forceinline__ double relax_cell(const Phys& ph, const Lvl& L, const
     double E, Fx, Fy, T;
     local_solve(beta, g, L.a, ka, ks, ph.c_v, ph.a_r, BE, BFx, BFy, BT, Tin, E, Fx, Fy, T);
     if (omega != 1.0) {
-        const double Ein = ld(u.E, k), Fxin = ld(u.Fx, k);
+        const double Ein = cen(0), Fxin = cen(1);
         E = fma(omega, E - Ein, Ein);
         Fx = fma(omega, Fx - Fxin, Fxin);
         if (DIM == 2) {
-            const double Fyin = ld(u.Fy, k);
+            const double Fyin = cen(2);
             Fy = fma(omega, Fy - Fyin, Fyin);
         }
         T = fma(omega, T - Tin, Tin);
@@ -59,6 +58,19 @@ __device__ __forceinline__ double relax_cell(const Phys& ph, const Lvl& L, const
     if (DIM == 2) st(out.Fy, k, Fy);
     st(out.T, k, T);
     return q;
+}
+
+template <int DIM, bool NORM = false>
+__device__ __forceinline__ double relax_cell(const Phys& ph, const Lvl& L, const CSoa& rhs, const double* gcell,
+                                             double beta, double gamma, double omega, const CSoa& u, const Soa& out,
+                                             uint32_t k, int i, int j)
+{
+    double S0, S1, S2;
+    offdiag<DIM>(ph, L, u, i, j, k, S0, S1, S2);
+    const double g = gcell ? ld(gcell, k) : gamma;
+    const double Tin = ld(u.T, k);
+    auto cen = [&](int f) { return ld(f == 0 ? u.E : (f == 1 ? u.Fx : u.Fy), k); };
+    return relax_update<DIM, NORM>(ph, L, rhs, g, beta, omega, S0, S1, S2, Tin, cen, out, k);
 }
 
 // One pseudo-time step (Algorithm 3) of M du/dtau + A(u) = f, fused:

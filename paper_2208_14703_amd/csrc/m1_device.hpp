@@ -108,28 +108,40 @@ __device__ __forceinline__ C2P closure(double c, double c2, double E, double Fx,
     return o;
 }
 
-// Add sgn-side x contribution: sgn = +1 for L_x (left neighbour), -1 for R_x (right):
+// The rows of c^2 P of a state: Gxx = c^2 Pxx, Gxy = c^2 Pxy, Gyy = c^2 Pyy.
+__device__ __forceinline__ double p_xx(const C2P& p, double Fx) { return fma(p.r3 * Fx, Fx, p.iso); }
+__device__ __forceinline__ double p_xy(const C2P& p, double Fx, double Fy) { return p.r3 * Fx * Fy; }
+__device__ __forceinline__ double p_yy(const C2P& p, double Fy) { return fma(p.r3 * Fy, Fy, p.iso); }
+
+// Add sgn-side x contribution of a neighbour whose c^2 P row is (Gxx, Gxy):
+// sgn = +1 for L_x (left neighbour), -1 for R_x (right):
 //   k (cE + sgn Fx,  c Fx + sgn c^2 Pxx,  c Fy + sgn c^2 Pxy)
-__device__ __forceinline__ void add_x(double k, double c, double c2, double sgn, double E, double Fx, double Fy,
-                                      double& S0, double& S1, double& S2)
+__device__ __forceinline__ void acc_x(double k, double c, double sgn, double E, double Fx, double Fy, double Gxx,
+                                      double Gxy, double& S0, double& S1, double& S2)
 {
-    const C2P p = closure(c, c2, E, Fx, Fy);
-    const double Gxx = fma(p.r3 * Fx, Fx, p.iso);
-    const double Gxy = p.r3 * Fx * Fy;
     S0 = fma(k, fma(sgn, Fx, c * E), S0);
     S1 = fma(k, fma(sgn, Gxx, c * Fx), S1);
     S2 = fma(k, fma(sgn, Gxy, c * Fy), S2);
 }
 // y contribution: k (cE + sgn Fy,  c Fx + sgn c^2 Pxy,  c Fy + sgn c^2 Pyy)
+__device__ __forceinline__ void acc_y(double k, double c, double sgn, double E, double Fx, double Fy, double Gxy,
+                                      double Gyy, double& S0, double& S1, double& S2)
+{
+    S0 = fma(k, fma(sgn, Fy, c * E), S0);
+    S1 = fma(k, fma(sgn, Gxy, c * Fx), S1);
+    S2 = fma(k, fma(sgn, Gyy, c * Fy), S2);
+}
+__device__ __forceinline__ void add_x(double k, double c, double c2, double sgn, double E, double Fx, double Fy,
+                                      double& S0, double& S1, double& S2)
+{
+    const C2P p = closure(c, c2, E, Fx, Fy);
+    acc_x(k, c, sgn, E, Fx, Fy, p_xx(p, Fx), p_xy(p, Fx, Fy), S0, S1, S2);
+}
 __device__ __forceinline__ void add_y(double k, double c, double c2, double sgn, double E, double Fx, double Fy,
                                       double& S0, double& S1, double& S2)
 {
     const C2P p = closure(c, c2, E, Fx, Fy);
-    const double Gxy = p.r3 * Fx * Fy;
-    const double Gyy = fma(p.r3 * Fy, Fy, p.iso);
-    S0 = fma(k, fma(sgn, Fy, c * E), S0);
-    S1 = fma(k, fma(sgn, Gxy, c * Fx), S1);
-    S2 = fma(k, fma(sgn, Gyy, c * Fy), S2);
+    acc_y(k, c, sgn, E, Fx, Fy, p_xy(p, Fx, Fy), p_yy(p, Fy), S0, S1, S2);
 }
 
 // ---------------------------------------------------------------------------

@@ -138,6 +138,15 @@ struct BProb {
 // mixed precision (m1_mixed.hip)
 int batch_grid_cap();
 void set_batch_grid_cap(int cap);
+// rows of the LDS-staged finest sweep's 64-wide tile (0: one-cell-per-thread sweep)
+int sweep_rows();
+bool set_sweep_rows(int rows);
+// LDS-staged finest-level sweep (2-D, beta = 0, gamma = 1, no norm); with uc.E
+// non-null the gathered states are first corrected from level 1 (uc, vc) and
+// projected, as by launch_prolong_project.  false (nothing launched) when the
+// staged sweep is switched off.
+bool launch_relax_lds(hipStream_t st, const Phys& ph, const Lvl& L, CSoa rhs, double omega, CSoa u, Soa out,
+                      const int* active, CSoa uc, CSoa vc, int px, int py, double eta);
 // batched FP64 kernels (m1_kernels.hip); `wl` is a work list of nwl entries,
 // `plist` a list of problem indices
 void launch_b_relax(hipStream_t st, const BProb* P, const BSlot* S, const uint32_t* wl, int nwl, int in_x1, int norm);

@@ -83,6 +83,96 @@ __global__ __launch_bounds__(kBlock) void k_relax(Phys ph, Lvl L, CSoa rhs, cons
     block_partial(q, partials + xcd_block());
 }
 
+// Finest-level Jacobi sweep (2-D, without the norm) staged through LDS.  A
+// block owns a 64 x TY tile.  The states of the tile and of its one-cell halo
+// (boundary rule or periodic image applied) are loaded once and the closure of
+// each is evaluated once; E, F and the rows of c^2 P go to LDS, and each cell
+// sums its four neighbours' fluxes from there instead of evaluating four
+// closures of its own.  Every cell's arithmetic, and its order, is that of
+// relax_cell, so the results are the same to the bit.
+// UP: the first sweep after the coarse-grid correction, fused with it: every
+// gathered state is first corrected from the coarse level and projected
+// (prolong_value, as k_prolong_project), so the corrected state is never
+// stored; the sweep proceeds from it.
+constexpr int kLdsTX = 64;
+
+template <int TY, bool UP>
+__global__ __launch_bounds__(kLdsTX * TY) void k_relax_lds(Phys ph, Lvl L, CSoa rhs, double omega, CSoa u, Soa out,
+                                                          const int* __restrict__ active, CSoa uc, CSoa vc, int px,
+                                                          int py, double eta)
+{
+    static_assert(kLdsTX * TY >= 2 * kLdsTX + 2 * TY, "the halo needs 2 rows and 2 columns of threads");
+    constexpr int W = kLdsTX + 2, N = W * (TY + 2);
+    __shared__ double qE[N], qFx[N], qFy[N], qXX[N], qXY[N], qYY[N], qT[UP ? N : 1];
+    if (*active == 0) return;
+    const int ntx = (L.nx + kLdsTX - 1) / kLdsTX;
+    const int b = (int)xcd_block();
+    const int i0 = (b % ntx) * kLdsTX, j0 = (b / ntx) * TY;
+    const int t = threadIdx.x;
+    const bool perx = ph.bc[0] == BC_PERIODIC, pery = ph.bc[2] == BC_PERIODIC;
+    // region point (li, lj), li in [-1, 64], lj in [-1, TY]; points outside the
+    // domain take the boundary rule of their side applied to the adjacent cell
+    // (or the periodic image); corners and points past a ragged edge are unused
+    auto gather = [&](int li, int lj) {
+        int gi = i0 + li, gj = j0 + lj, side = 0;
+        const bool ox = gi < 0 || gi >= L.nx, oy = gj < 0 || gj >= L.ny;
+        const bool need = gi <= L.nx && gj <= L.ny && !(ox && oy);
+        if (ox) {
+            side = gi < 0 ? 0 : 1;
+            gi = perx ? (gi < 0 ? gi + L.nx : gi - L.nx) : (gi < 0 ? 0 : L.nx - 1);
+        }
+        if (oy) {
+            side = gj < 0 ? 2 : 3;
+            gj = pery ? (gj < 0 ? gj + L.ny : gj - L.ny) : (gj < 0 ? 0 : L.ny - 1);
+        }
+        double e = 0.0, fx = 0.0, fy = 0.0, xx = 0.0, xy = 0.0, yy = 0.0, tt = 0.0;
+        if (need) {
+            const uint32_t k = (uint32_t)gj * (uint32_t)L.nx + (uint32_t)gi;
+            double le = ld(u.E, k), lfx = ld(u.Fx, k), lfy = ld(u.Fy, k);
+            if (UP) {
+                double wE, wFx, wFy;
+                prolong_value<2>(ph, L.nx, L.ny, px, py, eta, gi, gj, le, lfx, lfy, ld(u.T, k), uc, vc, wE, wFx, wFy,
+                                 tt);
+                le = wE;
+                lfx = wFx;
+                lfy = wFy;
+            }
+            ghost_rule(ph, side, !(ox || oy), le, lfx, lfy, e, fx, fy);
+            const C2P p = closure(ph.c, ph.c2, e, fx, fy);
+            xx = p_xx(p, fx);
+            xy = p_xy(p, fx, fy);
+            yy = p_yy(p, fy);
+        }
+        const int c = (lj + 1) * W + li + 1;
+        qE[c] = e;
+        qFx[c] = fx;
+        qFy[c] = fy;
+        qXX[c] = xx;
+        qXY[c] = xy;
+        qYY[c] = yy;
+        if (UP) qT[c] = tt;
+    };
+    gather(t % kLdsTX, t / kLdsTX);  // the tile
+    if (t < 2 * kLdsTX) {            // halo rows below and above
+        gather(t % kLdsTX, t < kLdsTX ? -1 : TY);
+    } else if (t < 2 * kLdsTX + 2 * TY) {  // halo columns left and right
+        const int q = t - 2 * kLdsTX;
+        gather(q < TY ? -1 : kLdsTX, q % TY);
+    }
+    __syncthreads();
+    const int li = t % kLdsTX, lj = t / kLdsTX, i = i0 + li, j = j0 + lj;
+    if (i >= L.nx || j >= L.ny) return;
+    const uint32_t k = (uint32_t)j * (uint32_t)L.nx + (uint32_t)i;
+    const int c = (lj + 1) * W + li + 1;
+    double S0 = 0.0, S1 = 0.0, S2 = 0.0;  // the order of offdiag: x-, x+, y-, y+
+    acc_x(L.kx, ph.c, +1.0, qE[c - 1], qFx[c - 1], qFy[c - 1], qXX[c - 1], qXY[c - 1], S0, S1, S2);
+    acc_x(L.kx, ph.c, -1.0, qE[c + 1], qFx[c + 1], qFy[c + 1], qXX[c + 1], qXY[c + 1], S0, S1, S2);
+    acc_y(L.ky, ph.c, +1.0, qE[c - W], qFx[c - W], qFy[c - W], qXY[c - W], qYY[c - W], S0, S1, S2);
+    acc_y(L.ky, ph.c, -1.0, qE[c + W], qFx[c + W], qFy[c + W], qXY[c + W], qYY[c + W], S0, S1, S2);
+    auto cen = [&](int f) { return f == 0 ? qE[c] : (f == 1 ? qFx[c] : qFy[c]); };
+    relax_update<2, false>(ph, L, rhs, 1.0, 0.0, omega, S0, S1, S2, UP ? qT[c] : ld(u.T, k), cen, out, k);
+}
+
 // One pseudo-time step; `first`: also form the FAS right-hand side in f (u = v_l).
 template <int DIM>
 __global__ __launch_bounds__(kBlock) void k_pseudo(Phys ph, Lvl L, Soa f, CSoa u, Soa out, double dtau,
@@ -555,11 +645,48 @@ __global__ void kb_gather_ctrl(const BProb* __restrict__ P, int np, Ctrl* __rest
         else hipLaunchKernelGGL(KERNEL<1>, dim3(GRID), dim3(kBlock), 0, st, __VA_ARGS__);            \
     } while (0)
 
+static std::atomic<int> g_sweep_rows{4};
+int sweep_rows() { return g_sweep_rows.load(std::memory_order_relaxed); }
+bool set_sweep_rows(int rows)
+{
+    if (rows != 0 && rows != 4 && rows != 8 && rows != 16) return false;
+    g_sweep_rows.store(rows, std::memory_order_relaxed);
+    return true;
+}
+
+bool launch_relax_lds(hipStream_t st, const Phys& ph, const Lvl& L, CSoa rhs, double omega, CSoa u, Soa out,
+                      const int* active, CSoa uc, CSoa vc, int px, int py, double eta)
+{
+    const int rows = sweep_rows();
+    if (rows == 0) return false;
+    const unsigned ntx = (unsigned)((L.nx + kLdsTX - 1) / kLdsTX), nty = (unsigned)((L.ny + rows - 1) / rows);
+    const dim3 gl(ntx * nty), bl(kLdsTX * rows);
+    const bool up = uc.E != nullptr;
+#define M1_RELAX_LDS(R, U)                                                                                            \
+    hipLaunchKernelGGL((k_relax_lds<R, U>), gl, bl, 0, st, ph, L, rhs, omega, u, out, active, uc, vc, px, py, eta)
+    if (rows == 4) {
+        if (up) M1_RELAX_LDS(4, true);
+        else M1_RELAX_LDS(4, false);
+    } else if (rows == 8) {
+        if (up) M1_RELAX_LDS(8, true);
+        else M1_RELAX_LDS(8, false);
+    } else {
+        if (up) M1_RELAX_LDS(16, true);
+        else M1_RELAX_LDS(16, false);
+    }
+#undef M1_RELAX_LDS
+    return true;
+}
+
 void launch_relax(hipStream_t st, int dim, const Phys& ph, const Lvl& L, CSoa rhs, const double* gcell, double beta,
                   double gamma, double omega, CSoa u, Soa out, double* partials, const int* active)
 {
     const dim3 g(nblocks((int64_t)L.nx * L.ny)), b(kBlock);
     const bool fine = !gcell && beta == 0.0 && gamma == 1.0;
+    if (dim == 2 && fine && !partials && sweep_rows() > 0) {
+        launch_relax_lds(st, ph, L, rhs, omega, u, out, active, CSoa{}, CSoa{}, 0, 0, 0.0);
+        return;
+    }
 #define M1_RELAX(D, N, F)                                                                                             \
     hipLaunchKernelGGL((k_relax<D, N, F>), g, b, 0, st, ph, L, rhs, gcell, beta, gamma, omega, u, out, partials, active)
     if (dim == 2) {

@@ -97,6 +97,12 @@ def test_tuning_settings_round_trip():
     assert binding.tune_get("graphs") == 1 - g
     binding.tune_set("graphs", g)
     assert L.m1_tune_set(b"graphs", 2) == 1
+    r = binding.tune_get("sweep_rows")
+    for rows in (0, 4, 8, 16):
+        binding.tune_set("sweep_rows", rows)
+        assert binding.tune_get("sweep_rows") == rows
+    binding.tune_set("sweep_rows", r)
+    assert L.m1_tune_set(b"sweep_rows", 5) == 1 and binding.tune_get("sweep_rows") == r
     assert L.m1_tune_set(b"no_such_key", 5) == 1
     assert L.m1_tune_get(b"no_such_key") == -1
     assert L.m1_tune_set(b"tail_cells", -1) == 1

@@ -65,6 +65,32 @@ def test_apply_and_sweep_parity(dim, nx, ny, bcs):
     assert norm == pytest.approx(o.norm(ro), rel=1e-12)
 
 
+@pytest.mark.parametrize("nx,ny", [(100, 37), (64, 64), (1, 1), (3, 5), (130, 70), (65, 9), (64, 17)])
+@pytest.mark.parametrize("bcs", ["periodic", "mixed", "wall"])
+def test_lds_sweep_matches_one_cell_sweep(nx, ny, bcs):
+    """The LDS-staged finest sweep (64 x rows tiles, every closure evaluated
+    once) gives the one-cell-per-thread sweep's result to the bit: ragged tiles
+    in both directions, one-cell domains, every kind of side."""
+    announce("lds sweep", nx, ny, bcs)
+    kinds = BC_SETS[bcs]
+    prob, v, sig = inputs.random_problem(4, 2, nx, ny, bc_kinds=kinds, cfl=40.0, fmax=1.0)
+    b = oracle.Oracle(prob, sig).rhs(inputs.random_problem(5, 2, nx, ny, bc_kinds=kinds, cfl=40.0)[1])
+    vd, bd = to_dev(v), to_dev(b)
+    old = binding.tune_get("sweep_rows")
+    try:
+        res = {}
+        for rows in (0, 4, 8, 16):
+            binding.tune_set("sweep_rows", rows)
+            for omega in (1.0, OMEGA):
+                P = plan_for(prob, sig, levels=1, omega=omega)
+                res[rows, omega] = to_host(P.sweep(bd, vd))
+    finally:
+        binding.tune_set("sweep_rows", old)
+    for rows in (4, 8, 16):
+        for omega in (1.0, OMEGA):
+            np.testing.assert_array_equal(res[rows, omega], res[0, omega])
+
+
 @pytest.mark.parametrize("dim,n", [(2, 64), (1, 512)])
 @pytest.mark.parametrize("local", [1, 0])
 def test_pseudo_step_parity(dim, n, local):
