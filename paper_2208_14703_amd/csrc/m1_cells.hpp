@@ -114,14 +114,15 @@ __device__ __forceinline__ void pseudo_core(const Phys& ph, const Lvl& L, double
                 Fy, T);
 }
 
-template <int DIM, bool FIRST = false>
-__device__ __forceinline__ void pseudo_cell(const Phys& ph, const Lvl& L, const CSoa& fin, const Soa& fout,
-                                            const CSoa& u, const Soa& out, double dtau, double reach, int local,
-                                            const Soa& rs, double* gs, uint32_t k, int i, int j, bool live = true)
+// The rest of a pseudo-time step of one cell from its state and its
+// off-diagonal sum S: stores (gated on `live`) the new state, with FIRST the
+// FAS right-hand side, and with gs the values further sweeps need.
+template <int DIM, bool FIRST>
+__device__ __forceinline__ void pseudo_update(const Phys& ph, const Lvl& L, const CSoa& fin, const Soa& fout,
+                                              double uE, double uFx, double uFy, double uT, double S0, double S1,
+                                              double S2, const Soa& out, double dtau, double reach, int local,
+                                              const Soa& rs, double* gs, uint32_t k, bool live)
 {
-    const double uE = ld(u.E, k), uFx = ld(u.Fx, k), uFy = (DIM == 2) ? ld(u.Fy, k) : 0.0, uT = ld(u.T, k);
-    double S0, S1, S2;
-    offdiag<DIM>(ph, L, u, i, j, k, S0, S1, S2);
     const double ka = L.cdt * ld(L.sa, k), ks = L.cdt * ld(L.ss, k);
     double fE = ld(fin.E, k), fFx = ld(fin.Fx, k), fFy = (DIM == 2) ? ld(fin.Fy, k) : 0.0, fT = ld(fin.T, k);
     double E, Fx, Fy, T, tE, tFx, tFy, tT, g;
@@ -147,15 +148,26 @@ __device__ __forceinline__ void pseudo_cell(const Phys& ph, const Lvl& L, const 
     }
 }
 
+template <int DIM, bool FIRST = false>
+__device__ __forceinline__ void pseudo_cell(const Phys& ph, const Lvl& L, const CSoa& fin, const Soa& fout,
+                                            const CSoa& u, const Soa& out, double dtau, double reach, int local,
+                                            const Soa& rs, double* gs, uint32_t k, int i, int j, bool live = true)
+{
+    const double uE = ld(u.E, k), uFx = ld(u.Fx, k), uFy = (DIM == 2) ? ld(u.Fy, k) : 0.0, uT = ld(u.T, k);
+    double S0, S1, S2;
+    offdiag<DIM>(ph, L, u, i, j, k, S0, S1, S2);
+    pseudo_update<DIM, FIRST>(ph, L, fin, fout, uE, uFx, uFy, uT, S0, S1, S2, out, dtau, reach, local, rs, gs, k,
+                              live);
+}
+
 // out = X + sgn A(v) (X.E == nullptr: out = sgn A(v)); out stored when out.E
 // is set.  Returns r_E^2 + (r_F/c)^2 + r_T^2 of the result (norm contribution).
+// The rest of apply_cell from the cell's state and off-diagonal sum S.
 template <int DIM>
-__device__ __forceinline__ double apply_cell(const Phys& ph, const Lvl& L, const CSoa& v, const CSoa& X, double sgn,
-                                             const Soa& out, uint32_t k, int i, int j, bool live = true)
+__device__ __forceinline__ double apply_update(const Phys& ph, const Lvl& L, double E, double Fx, double Fy, double T,
+                                               double S0, double S1, double S2, const CSoa& X, double sgn,
+                                               const Soa& out, uint32_t k, bool live)
 {
-    double S0, S1, S2;
-    offdiag<DIM>(ph, L, v, i, j, k, S0, S1, S2);
-    const double E = ld(v.E, k), Fx = ld(v.Fx, k), Fy = (DIM == 2) ? ld(v.Fy, k) : 0.0, T = ld(v.T, k);
     const double ka = L.cdt * ld(L.sa, k), ks = L.cdt * ld(L.ss, k);
     const double T2 = T * T;
     const double ex = ka * fma(-ph.a_r * T2, T2, E);  // ka (E - a_r T^4)
@@ -179,6 +191,16 @@ __device__ __forceinline__ double apply_cell(const Phys& ph, const Lvl& L, const
     const double ic = 1.0 / ph.c;
     const double fx = rFx * ic, fy = (DIM == 2) ? rFy * ic : 0.0;
     return fma(rE, rE, fma(fx, fx, fma(fy, fy, rT * rT)));
+}
+
+template <int DIM>
+__device__ __forceinline__ double apply_cell(const Phys& ph, const Lvl& L, const CSoa& v, const CSoa& X, double sgn,
+                                             const Soa& out, uint32_t k, int i, int j, bool live = true)
+{
+    double S0, S1, S2;
+    offdiag<DIM>(ph, L, v, i, j, k, S0, S1, S2);
+    const double E = ld(v.E, k), Fx = ld(v.Fx, k), Fy = (DIM == 2) ? ld(v.Fy, k) : 0.0, T = ld(v.T, k);
+    return apply_update<DIM>(ph, L, E, Fx, Fy, T, S0, S1, S2, X, sgn, out, k, live);
 }
 
 // Full-weighting weights along one axis (1/4, 1/2, 1/4 on fine 2I-1, 2I, 2I+1):

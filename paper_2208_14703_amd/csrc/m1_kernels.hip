@@ -83,32 +83,32 @@ __global__ __launch_bounds__(kBlock) void k_relax(Phys ph, Lvl L, CSoa rhs, cons
     block_partial(q, partials + xcd_block());
 }
 
-// Finest-level Jacobi sweep (2-D, without the norm) staged through LDS.  A
-// block owns a 64 x TY tile.  The states of the tile and of its one-cell halo
-// (boundary rule or periodic image applied) are loaded once and the closure of
-// each is evaluated once; E, F and the rows of c^2 P go to LDS, and each cell
-// sums its four neighbours' fluxes from there instead of evaluating four
-// closures of its own.  Every cell's arithmetic, and its order, is that of
-// relax_cell, so the results are the same to the bit.
-// UP: the first sweep after the coarse-grid correction, fused with it: every
-// gathered state is first corrected from the coarse level and projected
-// (prolong_value, as k_prolong_project), so the corrected state is never
-// stored; the sweep proceeds from it.
+// ---------------------------------------------------------------------------
+// LDS-staged 2-D stencil kernels.  A block owns a 64 x TY tile.  The states of
+// the tile and of its one-cell halo (boundary rule or periodic image applied)
+// are loaded once and the closure of each is evaluated once; E, F and the rows
+// of c^2 P go to LDS, and each cell sums its four neighbours' fluxes from there
+// instead of evaluating four closures of its own.  Every cell's arithmetic,
+// and its order, is that of the one-cell-per-thread kernels (the sums of
+// offdiag via acc_x/acc_y, the updates relax_update/pseudo_update), so the
+// results are the same to the bit.
 constexpr int kLdsTX = 64;
 
+template <int TY>
+struct LdsTile {
+    static constexpr int W = kLdsTX + 2, N = W * (TY + 2);
+    double E[N], Fx[N], Fy[N], XX[N], XY[N], YY[N];
+};
+
+// Stage the tile at (i0, j0) of state u.  UP: each gathered state is first
+// corrected from the coarse level (uc, vc) and projected (prolong_value, as
+// k_prolong_project) and its temperature kept in qT.
 template <int TY, bool UP>
-__global__ __launch_bounds__(kLdsTX * TY) void k_relax_lds(Phys ph, Lvl L, CSoa rhs, double omega, CSoa u, Soa out,
-                                                          const int* __restrict__ active, CSoa uc, CSoa vc, int px,
-                                                          int py, double eta)
+__device__ __forceinline__ void stage_tile(LdsTile<TY>& q, double* qT, const Phys& ph, const Lvl& L, const CSoa& u,
+                                           int i0, int j0, const CSoa& uc, const CSoa& vc, int px, int py, double eta)
 {
     static_assert(kLdsTX * TY >= 2 * kLdsTX + 2 * TY, "the halo needs 2 rows and 2 columns of threads");
-    constexpr int W = kLdsTX + 2, N = W * (TY + 2);
-    __shared__ double qE[N], qFx[N], qFy[N], qXX[N], qXY[N], qYY[N], qT[UP ? N : 1];
-    if (*active == 0) return;
-    const int ntx = (L.nx + kLdsTX - 1) / kLdsTX;
-    const int b = (int)xcd_block();
-    const int i0 = (b % ntx) * kLdsTX, j0 = (b / ntx) * TY;
-    const int t = threadIdx.x;
+    constexpr int W = LdsTile<TY>::W;
     const bool perx = ph.bc[0] == BC_PERIODIC, pery = ph.bc[2] == BC_PERIODIC;
     // region point (li, lj), li in [-1, 64], lj in [-1, TY]; points outside the
     // domain take the boundary rule of their side applied to the adjacent cell
@@ -144,33 +144,91 @@ __global__ __launch_bounds__(kLdsTX * TY) void k_relax_lds(Phys ph, Lvl L, CSoa 
             yy = p_yy(p, fy);
         }
         const int c = (lj + 1) * W + li + 1;
-        qE[c] = e;
-        qFx[c] = fx;
-        qFy[c] = fy;
-        qXX[c] = xx;
-        qXY[c] = xy;
-        qYY[c] = yy;
+        q.E[c] = e;
+        q.Fx[c] = fx;
+        q.Fy[c] = fy;
+        q.XX[c] = xx;
+        q.XY[c] = xy;
+        q.YY[c] = yy;
         if (UP) qT[c] = tt;
     };
+    const int t = threadIdx.x;
     gather(t % kLdsTX, t / kLdsTX);  // the tile
     if (t < 2 * kLdsTX) {            // halo rows below and above
         gather(t % kLdsTX, t < kLdsTX ? -1 : TY);
     } else if (t < 2 * kLdsTX + 2 * TY) {  // halo columns left and right
-        const int q = t - 2 * kLdsTX;
-        gather(q < TY ? -1 : kLdsTX, q % TY);
+        const int r = t - 2 * kLdsTX;
+        gather(r < TY ? -1 : kLdsTX, r % TY);
     }
+}
+
+// Off-diagonal sum of the cell at LDS index c, in the order of offdiag: x-, x+, y-, y+.
+template <int TY>
+__device__ __forceinline__ void tile_sums(const LdsTile<TY>& q, const Lvl& L, double c_light, int c, double& S0,
+                                          double& S1, double& S2)
+{
+    constexpr int W = LdsTile<TY>::W;
+    S0 = S1 = S2 = 0.0;
+    acc_x(L.kx, c_light, +1.0, q.E[c - 1], q.Fx[c - 1], q.Fy[c - 1], q.XX[c - 1], q.XY[c - 1], S0, S1, S2);
+    acc_x(L.kx, c_light, -1.0, q.E[c + 1], q.Fx[c + 1], q.Fy[c + 1], q.XX[c + 1], q.XY[c + 1], S0, S1, S2);
+    acc_y(L.ky, c_light, +1.0, q.E[c - W], q.Fx[c - W], q.Fy[c - W], q.XY[c - W], q.YY[c - W], S0, S1, S2);
+    acc_y(L.ky, c_light, -1.0, q.E[c + W], q.Fx[c + W], q.Fy[c + W], q.XY[c + W], q.YY[c + W], S0, S1, S2);
+}
+
+__device__ __forceinline__ void tile_origin(const Lvl& L, int ty, int& i0, int& j0)
+{
+    const int ntx = (L.nx + kLdsTX - 1) / kLdsTX;
+    const int b = (int)xcd_block();
+    i0 = (b % ntx) * kLdsTX;
+    j0 = (b / ntx) * ty;
+}
+
+// Finest-level Jacobi sweep (beta = 0, gamma = 1, no norm).  UP: the first
+// sweep after the coarse-grid correction, fused with it: the corrected state
+// is never stored, the sweep proceeds from it.
+template <int TY, bool UP>
+__global__ __launch_bounds__(kLdsTX * TY) void k_relax_lds(Phys ph, Lvl L, CSoa rhs, double omega, CSoa u, Soa out,
+                                                          const int* __restrict__ active, CSoa uc, CSoa vc, int px,
+                                                          int py, double eta)
+{
+    constexpr int W = LdsTile<TY>::W;
+    __shared__ LdsTile<TY> q;
+    __shared__ double qT[UP ? LdsTile<TY>::N : 1];
+    if (*active == 0) return;
+    int i0, j0;
+    tile_origin(L, TY, i0, j0);
+    stage_tile<TY, UP>(q, qT, ph, L, u, i0, j0, uc, vc, px, py, eta);
     __syncthreads();
-    const int li = t % kLdsTX, lj = t / kLdsTX, i = i0 + li, j = j0 + lj;
+    const int li = threadIdx.x % kLdsTX, lj = threadIdx.x / kLdsTX, i = i0 + li, j = j0 + lj;
     if (i >= L.nx || j >= L.ny) return;
     const uint32_t k = (uint32_t)j * (uint32_t)L.nx + (uint32_t)i;
     const int c = (lj + 1) * W + li + 1;
-    double S0 = 0.0, S1 = 0.0, S2 = 0.0;  // the order of offdiag: x-, x+, y-, y+
-    acc_x(L.kx, ph.c, +1.0, qE[c - 1], qFx[c - 1], qFy[c - 1], qXX[c - 1], qXY[c - 1], S0, S1, S2);
-    acc_x(L.kx, ph.c, -1.0, qE[c + 1], qFx[c + 1], qFy[c + 1], qXX[c + 1], qXY[c + 1], S0, S1, S2);
-    acc_y(L.ky, ph.c, +1.0, qE[c - W], qFx[c - W], qFy[c - W], qXY[c - W], qYY[c - W], S0, S1, S2);
-    acc_y(L.ky, ph.c, -1.0, qE[c + W], qFx[c + W], qFy[c + W], qXY[c + W], qYY[c + W], S0, S1, S2);
-    auto cen = [&](int f) { return f == 0 ? qE[c] : (f == 1 ? qFx[c] : qFy[c]); };
+    double S0, S1, S2;
+    tile_sums<TY>(q, L, ph.c, c, S0, S1, S2);
+    auto cen = [&](int f) { return f == 0 ? q.E[c] : (f == 1 ? q.Fx[c] : q.Fy[c]); };
     relax_update<2, false>(ph, L, rhs, 1.0, 0.0, omega, S0, S1, S2, UP ? qT[c] : ld(u.T, k), cen, out, k);
+}
+
+// out = X + sgn A(v) without norm partials (as k_apply, 2-D); stores gated on
+// the stop flag, read together with the data.
+template <int TY>
+__global__ __launch_bounds__(kLdsTX * TY) void k_apply_lds(Phys ph, Lvl L, CSoa v, CSoa X, double sgn, Soa out,
+                                                          const int* __restrict__ active)
+{
+    constexpr int W = LdsTile<TY>::W;
+    __shared__ LdsTile<TY> q;
+    const bool live = active[lane_zero()] != 0;
+    int i0, j0;
+    tile_origin(L, TY, i0, j0);
+    stage_tile<TY, false>(q, nullptr, ph, L, v, i0, j0, CSoa{}, CSoa{}, 0, 0, 0.0);
+    __syncthreads();
+    const int li = threadIdx.x % kLdsTX, lj = threadIdx.x / kLdsTX, i = i0 + li, j = j0 + lj;
+    if (i >= L.nx || j >= L.ny) return;
+    const uint32_t k = (uint32_t)j * (uint32_t)L.nx + (uint32_t)i;
+    const int c = (lj + 1) * W + li + 1;
+    double S0, S1, S2;
+    tile_sums<TY>(q, L, ph.c, c, S0, S1, S2);
+    apply_update<2>(ph, L, q.E[c], q.Fx[c], q.Fy[c], ld(v.T, k), S0, S1, S2, X, sgn, out, k, live);
 }
 
 // One pseudo-time step; `first`: also form the FAS right-hand side in f (u = v_l).
@@ -713,6 +771,15 @@ unsigned apply_blocks(const Lvl& L) { return nblocks((int64_t)L.nx * L.ny); }
 void launch_apply(hipStream_t st, int dim, const Phys& ph, const Lvl& L, CSoa v, CSoa X, double sgn, Soa out,
                   double* partials, const int* active)
 {
+    const int rows = sweep_rows();
+    if (dim == 2 && !partials && out.E && rows > 0) {
+        const unsigned ntx = (unsigned)((L.nx + kLdsTX - 1) / kLdsTX), nty = (unsigned)((L.ny + rows - 1) / rows);
+        const dim3 gl(ntx * nty), bl(kLdsTX * rows);
+        if (rows == 4) hipLaunchKernelGGL(k_apply_lds<4>, gl, bl, 0, st, ph, L, v, X, sgn, out, active);
+        else if (rows == 8) hipLaunchKernelGGL(k_apply_lds<8>, gl, bl, 0, st, ph, L, v, X, sgn, out, active);
+        else hipLaunchKernelGGL(k_apply_lds<16>, gl, bl, 0, st, ph, L, v, X, sgn, out, active);
+        return;
+    }
     M1_DISPATCH(dim, k_apply, apply_blocks(L), ph, L, v, X, sgn, out, partials, active);
 }
 
