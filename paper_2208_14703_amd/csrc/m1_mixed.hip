@@ -156,19 +156,18 @@ __global__ __launch_bounds__(kBlock32) void k_mx_resid(Phys ph, Lvl L, double et
 // Relaxed Jacobi sweep on the correction (any level, beta M + gamma N = rhs):
 //   x: (beta M + gamma (D(w + x) - D(w))) = rhs + gamma dS(d);  out = d + omega (x - d).
 // d.E == nullptr means d = 0 (first sweep of a cycle: dS = 0, no reads of d).
+// The rest of the sweep of one cell from its off-diagonal increment S and its
+// correction (dE, dFx, dFy, dT).
 template <int DIM>
-__device__ __forceinline__ void mx_sweep_cell(const Phys& ph, const Lvl32& L, const CSoa32& w, const CSoa32& d,
-                                              const CSoa32& rhs, float beta, float gamma, float omega,
-                                              const Soa32& out, uint32_t k, int i, int j)
+__device__ __forceinline__ void mx_sweep_update(const Phys& ph, const Lvl32& L, const CSoa32& w, const CSoa32& rhs,
+                                                float beta, float gamma, float omega, float S0, float S1, float S2,
+                                                float dE, float dFx, float dFy, float dT, const Soa32& out,
+                                                uint32_t k)
 {
-    float S0 = 0.0f, S1 = 0.0f, S2 = 0.0f;
-    if (d.E) offdiag_inc<DIM>(ph, L, w, d, i, j, k, S0, S1, S2);
     const double QE = fmaf(gamma, S0, ldf(rhs.E, k));
     const double QFx = fmaf(gamma, S1, ldf(rhs.Fx, k));
     const double QFy = (DIM == 2) ? fmaf(gamma, S2, ldf(rhs.Fy, k)) : 0.0;
     const double QT = ldf(rhs.T, k);
-    const float dE = d.E ? ldf(d.E, k) : 0.0f, dFx = d.E ? ldf(d.Fx, k) : 0.0f;
-    const float dFy = (DIM == 2 && d.E) ? ldf(d.Fy, k) : 0.0f, dT = d.E ? ldf(d.T, k) : 0.0f;
     const double ka = (double)L.cdt * ldf(L.sa, k), ks = (double)L.cdt * ldf(L.ss, k);
     float xE, xFx, xFy, xT;
     local_solve_inc(beta, gamma, L.a, ka, ks, ph.c_v, ph.a_r, QE, QFx, QFy, QT, ldf(w.T, k), dT, xE, xFx, xFy, xT);
@@ -176,6 +175,93 @@ __device__ __forceinline__ void mx_sweep_cell(const Phys& ph, const Lvl32& L, co
     stf(out.Fx, k, fmaf(omega, xFx - dFx, dFx));
     if (DIM == 2) stf(out.Fy, k, fmaf(omega, xFy - dFy, dFy));
     stf(out.T, k, fmaf(omega, xT - dT, dT));
+}
+
+template <int DIM>
+__device__ __forceinline__ void mx_sweep_cell(const Phys& ph, const Lvl32& L, const CSoa32& w, const CSoa32& d,
+                                              const CSoa32& rhs, float beta, float gamma, float omega,
+                                              const Soa32& out, uint32_t k, int i, int j)
+{
+    float S0 = 0.0f, S1 = 0.0f, S2 = 0.0f;
+    if (d.E) offdiag_inc<DIM>(ph, L, w, d, i, j, k, S0, S1, S2);
+    const float dE = d.E ? ldf(d.E, k) : 0.0f, dFx = d.E ? ldf(d.Fx, k) : 0.0f;
+    const float dFy = (DIM == 2 && d.E) ? ldf(d.Fy, k) : 0.0f, dT = d.E ? ldf(d.T, k) : 0.0f;
+    mx_sweep_update<DIM>(ph, L, w, rhs, beta, gamma, omega, S0, S1, S2, dE, dFx, dFy, dT, out, k);
+}
+
+// ---------------------------------------------------------------------------
+// LDS-staged sweep on the correction (2-D, d given): a block owns a 64 x TY
+// tile; the base and correction of the tile and its one-cell halo are loaded
+// once (boundary rule or periodic image applied) and the c^2 P increment of
+// each is evaluated once; cells sum their neighbours' contributions from LDS.
+// The arithmetic of every cell, and its order, is that of mx_sweep_cell.
+constexpr int kMxTX = 64;
+
+template <int TY>
+__global__ __launch_bounds__(kMxTX * TY) void k_mx_sweep_lds(Phys ph, Lvl32 L, CSoa32 w, CSoa32 d, CSoa32 rhs,
+                                                            float beta, float gamma, float omega, Soa32 out,
+                                                            const int* __restrict__ active)
+{
+    static_assert(kMxTX * TY >= 2 * kMxTX + 2 * TY, "the halo needs 2 rows and 2 columns of threads");
+    constexpr int W = kMxTX + 2, N = W * (TY + 2);
+    __shared__ float qe[N], qgx[N], qgy[N], qxx[N], qxy[N], qyy[N];
+    if (*active == 0) return;
+    const int ntx = (L.nx + kMxTX - 1) / kMxTX;
+    const int b = (int)xcd_block();
+    const int i0 = (b % ntx) * kMxTX, j0 = (b / ntx) * TY;
+    const float c = (float)ph.c, c2 = (float)ph.c2;
+    const bool perx = ph.bc[0] == BC_PERIODIC, pery = ph.bc[2] == BC_PERIODIC;
+    auto gather = [&](int li, int lj) {
+        int gi = i0 + li, gj = j0 + lj, side = 0;
+        const bool ox = gi < 0 || gi >= L.nx, oy = gj < 0 || gj >= L.ny;
+        const bool need = gi <= L.nx && gj <= L.ny && !(ox && oy);
+        if (ox) {
+            side = gi < 0 ? 0 : 1;
+            gi = perx ? (gi < 0 ? gi + L.nx : gi - L.nx) : (gi < 0 ? 0 : L.nx - 1);
+        }
+        if (oy) {
+            side = gj < 0 ? 2 : 3;
+            gj = pery ? (gj < 0 ? gj + L.ny : gj - L.ny) : (gj < 0 ? 0 : L.ny - 1);
+        }
+        float e = 0.0f, gx = 0.0f, gy = 0.0f;
+        DP p{0.0f, 0.0f, 0.0f};
+        if (need) {
+            const uint32_t k = (uint32_t)gj * (uint32_t)L.nx + (uint32_t)gi;
+            float E, Fx, Fy;
+            ghost_inc(ph, side, !(ox || oy), ldf(w.E, k), ldf(w.Fx, k), ldf(w.Fy, k), ldf(d.E, k), ldf(d.Fx, k),
+                      ldf(d.Fy, k), E, Fx, Fy, e, gx, gy);
+            p = closure_inc(c, c2, E, Fx, Fy, e, gx, gy);
+        }
+        const int q = (lj + 1) * W + li + 1;
+        qe[q] = e;
+        qgx[q] = gx;
+        qgy[q] = gy;
+        qxx[q] = p.xx;
+        qxy[q] = p.xy;
+        qyy[q] = p.yy;
+    };
+    const int t = threadIdx.x;
+    gather(t % kMxTX, t / kMxTX);
+    if (t < 2 * kMxTX) {
+        gather(t % kMxTX, t < kMxTX ? -1 : TY);
+    } else if (t < 2 * kMxTX + 2 * TY) {
+        const int r = t - 2 * kMxTX;
+        gather(r < TY ? -1 : kMxTX, r % TY);
+    }
+    __syncthreads();
+    const int li = t % kMxTX, lj = t / kMxTX, i = i0 + li, j = j0 + lj;
+    if (i >= L.nx || j >= L.ny) return;
+    const uint32_t k = (uint32_t)j * (uint32_t)L.nx + (uint32_t)i;
+    const int q = (lj + 1) * W + li + 1;
+    float S0 = 0.0f, S1 = 0.0f, S2 = 0.0f;  // the order of offdiag_inc: x-, x+, y-, y+
+    auto nb = [&](int n, float kk, float sgn, bool xdir) {
+        acc_inc(kk, sgn, xdir, c, qe[n], qgx[n], qgy[n], DP{qxx[n], qxy[n], qyy[n]}, S0, S1, S2);
+    };
+    nb(q - 1, L.kx, +1.0f, true);
+    nb(q + 1, L.kx, -1.0f, true);
+    nb(q - W, L.ky, +1.0f, false);
+    nb(q + W, L.ky, -1.0f, false);
+    mx_sweep_update<2>(ph, L, w, rhs, beta, gamma, omega, S0, S1, S2, qe[q], qgx[q], qgy[q], ldf(d.T, k), out, k);
 }
 
 template <int DIM>
@@ -734,6 +820,18 @@ void launch_mx_resid(hipStream_t st, int dim, const Phys& ph, const Lvl& L, doub
 void launch_mx_sweep(hipStream_t st, int dim, const Phys& ph, const Lvl32& L, CSoa32 w, CSoa32 d, CSoa32 rhs,
                      float beta, float gamma, float omega, Soa32 out, const int* active)
 {
+    const int rows = sweep_rows();
+    if (dim == 2 && d.E && rows > 0) {
+        const unsigned ntx = (unsigned)((L.nx + kMxTX - 1) / kMxTX), nty = (unsigned)((L.ny + rows - 1) / rows);
+        const dim3 gl(ntx * nty), bl(kMxTX * rows);
+#define M1_MX_SWEEP_LDS(R)                                                                                            \
+    hipLaunchKernelGGL(k_mx_sweep_lds<R>, gl, bl, 0, st, ph, L, w, d, rhs, beta, gamma, omega, out, active)
+        if (rows == 4) M1_MX_SWEEP_LDS(4);
+        else if (rows == 8) M1_MX_SWEEP_LDS(8);
+        else M1_MX_SWEEP_LDS(16);
+#undef M1_MX_SWEEP_LDS
+        return;
+    }
     MX_DISPATCH(dim, k_mx_sweep, nblk((int64_t)L.nx * L.ny), ph, L, w, d, rhs, beta, gamma, omega, out, active);
 }
 

@@ -93,19 +93,27 @@ __device__ __forceinline__ DP closure_inc(float c, float c2, float E, float Fx, 
     return o;
 }
 
-// Ghost of a neighbour in increment form: the base ghost follows the boundary
-// rule of the side; the correction ghost is its linear part (0 for Dirichlet).
-// Branch-free like nb_state: unconditional loads, exact arithmetic selects.
-template <int DIM>
-__device__ __forceinline__ void nb_inc(const Phys& ph, int side, bool inside, uint32_t kn, uint32_t kc,
-                                       const CSoa32& w, const CSoa32& d, float& E, float& Fx, float& Fy, float& e,
-                                       float& gx, float& gy)
+// Add the sgn-side contribution of a neighbour with correction (e, gx, gy) and
+// c^2 P increment p to the increment of the off-diagonal sum (x or y side).
+__device__ __forceinline__ void acc_inc(float kk, float sgn, bool xdir, float c, float e, float gx, float gy,
+                                        const DP& p, float& S0, float& S1, float& S2)
+{
+    const float G0 = xdir ? gx : gy;
+    const float G1 = xdir ? p.xx : p.xy;
+    const float G2 = xdir ? p.xy : p.yy;
+    S0 = fmaf(kk, fmaf(sgn, G0, c * e), S0);
+    S1 = fmaf(kk, fmaf(sgn, G1, c * gx), S1);
+    S2 = fmaf(kk, fmaf(sgn, G2, c * gy), S2);
+}
+
+// The boundary rule of side `side` in increment form, applied to loaded values
+// (identity inside the domain and across periodic sides).
+__device__ __forceinline__ void ghost_inc(const Phys& ph, int side, bool inside, float lE, float lFx, float lFy,
+                                          float le, float lgx, float lgy, float& E, float& Fx, float& Fy, float& e,
+                                          float& gx, float& gy)
 {
     const int kind = ph.bc[side];
     const bool ghost = !inside && kind != BC_PERIODIC;
-    const uint32_t k = ghost ? kc : kn;
-    const float lE = ldf(w.E, k), lFx = ldf(w.Fx, k), lFy = (DIM == 2) ? ldf(w.Fy, k) : 0.0f;
-    const float le = ldf(d.E, k), lgx = ldf(d.Fx, k), lgy = (DIM == 2) ? ldf(d.Fy, k) : 0.0f;
     const bool dir = ghost && kind == BC_DIRICHLET;
     const bool flip = ghost && kind == BC_REFLECTIVE;
     const float keep = dir ? 0.0f : 1.0f;
@@ -118,6 +126,22 @@ __device__ __forceinline__ void nb_inc(const Phys& ph, int side, bool inside, ui
     gy = sy * lgy;
 }
 
+// Ghost of a neighbour in increment form: the base ghost follows the boundary
+// rule of the side; the correction ghost is its linear part (0 for Dirichlet).
+// Branch-free like nb_state: unconditional loads, exact arithmetic selects.
+template <int DIM>
+__device__ __forceinline__ void nb_inc(const Phys& ph, int side, bool inside, uint32_t kn, uint32_t kc,
+                                       const CSoa32& w, const CSoa32& d, float& E, float& Fx, float& Fy, float& e,
+                                       float& gx, float& gy)
+{
+    const bool ghost = !inside && ph.bc[side] != BC_PERIODIC;
+    const uint32_t k = ghost ? kc : kn;
+    const float lE = ldf(w.E, k), lFx = ldf(w.Fx, k), lFy = (DIM == 2) ? ldf(w.Fy, k) : 0.0f;
+    const float le = ldf(d.E, k), lgx = ldf(d.Fx, k), lgy = (DIM == 2) ? ldf(d.Fy, k) : 0.0f;
+    ghost_inc(ph, side, inside, lE, lFx, lFy, le, lgx, lgy, E, Fx, Fy, e, gx, gy);
+}
+
+
 // Increment of the off-diagonal sum, dS = S(w + d) - S(w).
 template <int DIM>
 __device__ __forceinline__ void offdiag_inc(const Phys& ph, const Lvl32& L, const CSoa32& w, const CSoa32& d, int i,
@@ -127,13 +151,7 @@ __device__ __forceinline__ void offdiag_inc(const Phys& ph, const Lvl32& L, cons
     float E, Fx, Fy, e, gx, gy;
     S0 = S1 = S2 = 0.0f;
     auto add = [&](float kk, float sgn, bool xdir) {
-        const DP p = closure_inc(c, c2, E, Fx, Fy, e, gx, gy);
-        const float G0 = xdir ? gx : gy;
-        const float G1 = xdir ? p.xx : p.xy;
-        const float G2 = xdir ? p.xy : p.yy;
-        S0 = fmaf(kk, fmaf(sgn, G0, c * e), S0);
-        S1 = fmaf(kk, fmaf(sgn, G1, c * gx), S1);
-        S2 = fmaf(kk, fmaf(sgn, G2, c * gy), S2);
+        acc_inc(kk, sgn, xdir, c, e, gx, gy, closure_inc(c, c2, E, Fx, Fy, e, gx, gy), S0, S1, S2);
     };
     const uint32_t wx = (uint32_t)(L.nx - 1);
     nb_inc<DIM>(ph, 0, i > 0, i > 0 ? k - 1 : k + wx, k, w, d, E, Fx, Fy, e, gx, gy);
