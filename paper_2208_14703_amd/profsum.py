@@ -4,6 +4,11 @@
       Per-kernel calls, total and average duration from <dir>/*_kernel_stats.csv,
       plus the traced span and busy time from *_kernel_trace.csv.
 
+  python -m paper_2208_14703_amd.profsum levels <dir> [--per NAME] [--top N] [--cmd "..."]
+      Kernel time grouped by (kernel, grid size) from *_kernel_trace.csv, i.e. per
+      level of the hierarchy; with --per, also per call of kernel NAME (for
+      instance the once-per-V-cycle norm kernel: time per V-cycle).
+
   python -m paper_2208_14703_amd.profsum traffic --fetch <dir> --write <dir> --kernel NAME
           --copy NAME --copy-bytes B --cells N --bytes-per-cell K [--cmd "..."]
       Turns FETCH_SIZE and WRITE_SIZE (KiB per dispatch, from two separate
@@ -60,6 +65,26 @@ def stats(d: str, top: int, cmd: str):
               f"{short(r['Name'])}")
 
 
+def levels(d: str, per: str, top: int, cmd: str):
+    tr = list(csv.DictReader(open(_one(d, "_kernel_trace.csv"))))
+    groups = collections.defaultdict(list)
+    for r in tr:
+        groups[(short(r["Kernel_Name"]), int(r["Grid_Size_X"]))].append(
+            (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-3)
+    nper = sum(len(v) for (k, _), v in groups.items() if per and k.endswith(per)) if per else 0
+    busy = sum(sum(v) for v in groups.values())
+    print(f"command: {cmd}")
+    head = f"kernel time by (kernel, grid threads); busy {busy * 1e-3:.2f} ms"
+    if nper:
+        head += f"; {nper} calls of {per}: {busy / nper:.2f} us per call"
+    print(head)
+    print(f"{'calls':>8} {'total ms':>10} {'avg us':>9} {'us/' + (per or '-'):>16} {'grid':>10}  kernel")
+    out = sorted(groups.items(), key=lambda kv: -sum(kv[1]))
+    for (name, grid), v in out[:top]:
+        pc = f"{sum(v) / nper:16.2f}" if nper else f"{'':>16}"
+        print(f"{len(v):8d} {sum(v) * 1e-3:10.2f} {sum(v) / len(v):9.2f} {pc} {grid:10d}  {name}")
+
+
 def counter_per_dispatch(d: str, counter: str):
     """Average counter value per dispatch, keyed by short kernel name."""
     rows = list(csv.DictReader(open(_one(d, "_counter_collection.csv"))))
@@ -112,6 +137,11 @@ def main():
     s.add_argument("dir")
     s.add_argument("--top", type=int, default=25)
     s.add_argument("--cmd", default="")
+    lv = sub.add_parser("levels")
+    lv.add_argument("dir")
+    lv.add_argument("--per", default="")
+    lv.add_argument("--top", type=int, default=30)
+    lv.add_argument("--cmd", default="")
     t = sub.add_parser("traffic")
     t.add_argument("--fetch", required=True)
     t.add_argument("--write", required=True)
@@ -125,6 +155,8 @@ def main():
     a = ap.parse_args()
     if a.what == "stats":
         stats(a.dir, a.top, a.cmd)
+    elif a.what == "levels":
+        levels(a.dir, a.per, a.top, a.cmd)
     else:
         traffic(a)
 

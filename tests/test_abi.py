@@ -107,3 +107,15 @@ def test_tuning_settings_round_trip():
     assert L.m1_tune_get(b"no_such_key") == -1
     assert L.m1_tune_set(b"tail_cells", -1) == 1
     assert L.m1_tune_set(b"batch_grid", 0) == 1
+
+
+def test_autotuner_builtin_values_match_the_library():
+    """The autotuner starts from the library's built-in launch shapes (no GPU:
+    nothing stored is applied, and no M1_* variable is set in the test run)."""
+    import os
+    from paper_2208_14703_amd import autotune, binding
+    binding.lib()
+    for key, val in autotune.BUILTIN.items():
+        if os.environ.get(binding.TUNE_ENV[key]) is None:
+            assert binding.tune_get(key) == val, key
+    assert set(autotune.BUILTIN) == set(binding.TUNE_ENV) == set(autotune.CANDIDATES)
