@@ -151,7 +151,8 @@ struct m1_plan {
     int npart = 0;
     double* dscal = nullptr;
     unsigned long long* dbad = nullptr;
-    double* hpin = nullptr;
+    double* hpin = nullptr;        // pinned host words: a scalar, the bad-cell index, the control copy
+    bool own_hpin = true;          // false: borrowed from an engine (not freed with the plan)
     unsigned long long* hbad = nullptr;
     m1::Ctrl* dctrl = nullptr;     // device cycle control (workspace)
     m1::Ctrl* dfix = nullptr;      // always-live control for single operations (active = 1, settable dtau)
@@ -702,8 +703,12 @@ size_t m1_workspace_bytes(const m1_grid* g, const m1_params* p)
 // Plan set-up.  With `wait` the opacity check and all uploads are complete on
 // return; without it the plan is returned at once and the caller synchronises
 // the stream and then tests *hbad (== ULLONG_MAX: opacities valid) before use.
+// Pinned host words a plan needs (hpin); an engine lends each resident request one such slot.
+constexpr size_t kHostSlot = (64 + sizeof(m1::Ctrl) + 63) / 64 * 64;
+
 static m1_status plan_setup(const m1_grid* g, const m1_params* p, const m1_opacity* op, void* workspace,
-                            size_t workspace_bytes, void* stream, bool wait, m1_plan** out)
+                            size_t workspace_bytes, void* stream, bool wait, m1_plan** out,
+                            void* host_slot = nullptr)
 {
     if (!out) return M1_ERR_ARG;
     *out = nullptr;
@@ -740,7 +745,10 @@ static m1_status plan_setup(const m1_grid* g, const m1_params* p, const m1_opaci
     P->lev[0].ss = const_cast<double*>(op->sigma_s);
     fill_level_params(*P);
 
-    if (hipHostMalloc((void**)&P->hpin, 64 + sizeof(m1::Ctrl), hipHostMallocDefault) != hipSuccess) {
+    if (host_slot) {
+        P->hpin = static_cast<double*>(host_slot);
+        P->own_hpin = false;
+    } else if (hipHostMalloc((void**)&P->hpin, kHostSlot, hipHostMallocDefault) != hipSuccess) {
         delete P;
         return M1_ERR_DEVICE;
     }
@@ -854,7 +862,7 @@ void m1_plan_destroy(m1_plan* P)
     if (!P) return;
     drop_cycle_graphs(*P);
     if (P->cap) (void)hipStreamDestroy(P->cap);
-    if (P->hpin) (void)hipHostFree(P->hpin);
+    if (P->hpin && P->own_hpin) (void)hipHostFree(P->hpin);
     delete P;
 }
 
@@ -1142,6 +1150,7 @@ struct m1_req {
     size_t ws_off = 0, ws_bytes = 0;
     m1_plan* plan = nullptr;
     bool need_init = true, cancel = false;
+    int slot = -1;  // the engine's pinned host slot lent to the plan
     double t_submit = 0.0, t_admit = 0.0, t_done = 0.0;
 };
 
@@ -1161,6 +1170,8 @@ struct m1_engine {
     int* dPL = nullptr;
     m1::Ctrl* dCtrl = nullptr;
     m1::Ctrl* hCtrl = nullptr;
+    char* hslots = nullptr;           // pinned host words lent to the resident requests' plans
+    std::vector<int> free_slots;
     std::map<size_t, size_t> free_;  // pool offset -> size
     std::mutex qmu;                   // pending queue and ticket table
     std::mutex rmu;                   // one round at a time
@@ -1259,6 +1270,10 @@ void finish(m1_engine& E, m1_req* R, m1_status st)
         m1_plan_destroy(R->plan);
         R->plan = nullptr;
     }
+    if (R->slot >= 0) {
+        E.free_slots.push_back(R->slot);
+        R->slot = -1;
+    }
     pool_free(E, R->ws_off, R->ws_bytes);
     {
         std::lock_guard<std::mutex> g(E.qmu);
@@ -1292,8 +1307,10 @@ void admit(m1_engine& E)
             R->ws_off = off;
             E.pending.pop_front();
         }
+        R->slot = E.free_slots.back();  // at most maxp requests are resident: a slot is free
+        E.free_slots.pop_back();
         m1_status st = plan_setup(&R->grid, &R->params, &R->op, E.arena + E.pool_off + R->ws_off, R->ws_bytes, E.st,
-                                  false, &R->plan);
+                                  false, &R->plan, E.hslots + (size_t)R->slot * kHostSlot);
         if (st != M1_OK) {
             finish(E, R, st);
             continue;
@@ -1616,6 +1633,12 @@ m1_status m1_engine_create(const m1_params* p, void* arena, size_t arena_bytes, 
         delete E;
         return M1_ERR_DEVICE;
     }
+    if (hipHostMalloc((void**)&E->hslots, kHostSlot * (size_t)max_requests, hipHostMallocDefault) != hipSuccess) {
+        (void)hipHostFree(E->hCtrl);
+        delete E;
+        return M1_ERR_DEVICE;
+    }
+    for (int i = max_requests - 1; i >= 0; --i) E->free_slots.push_back(i);
     *out = E;
     return M1_OK;
 }
@@ -1630,6 +1653,7 @@ void m1_engine_destroy(m1_engine* E)
         delete kv.second;
     }
     if (E->hCtrl) (void)hipHostFree(E->hCtrl);
+    if (E->hslots) (void)hipHostFree(E->hslots);
     if (E->cyc) (void)hipGraphExecDestroy(E->cyc);
     if (E->cap) (void)hipStreamDestroy(E->cap);
     delete E;
