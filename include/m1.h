@@ -243,7 +243,8 @@ void m1_engine_destroy(m1_engine* e);
 /* Queue a request of `nsteps` implicit steps on state `v` (device arrays,
  * caller-owned, updated in place; v and the opacity must outlive the request).
  * p == NULL uses the engine's parameters.  M1_ERR_BUDGET if the request can
- * never fit in the arena, M1_ERR_ARG if it is not 2-D or not compatible.     */
+ * never fit in the arena, M1_ERR_ARG if it is not 2-D, not compatible, or
+ * larger than 2^28 cells (2^20 work tiles of its finest level).             */
 m1_status m1_batch_submit(m1_engine* e, const m1_grid* g, const m1_params* p, const m1_opacity* op, m1_state* v,
                           int32_t nsteps, uint64_t* ticket);
 /* One round: admit waiting requests that fit, start pending time steps, run

@@ -1189,6 +1189,8 @@ struct m1_engine {
         int off = 0, n = 0;
     };
     List fine;
+    List fine2;    // 64 x rows tiles of the finest levels for the staged sweep (rows == 0: none)
+    int rows = 0;
     std::vector<List> restr, pdown, up;
     int n_all = 0, n_tail = 0;
     int Lmax = 1;
@@ -1259,6 +1261,11 @@ bool batch_compatible(const m1_engine& E, const m1_grid* g, const m1_params* p)
         return false;
     std::vector<int> nxs, nys;
     if (!level_dims(*g, *p, nxs, nys) || nxs.size() < 2 || (int)nxs.size() > m1::kMaxLevels) return false;
+    // a work-list entry holds the tile index in kTileBits bits: 256-cell tiles, and 64 x 4 tiles (the
+    // staged sweep's most numerous), of the finest level must fit
+    const int64_t n = (int64_t)nxs[0] * nys[0];
+    const int64_t t2 = (int64_t)((nxs[0] + 63) / 64) * ((nys[0] + 3) / 4);
+    if (std::max((n + 255) / 256, t2) > (int64_t(1) << m1::kTileBits)) return false;
     return true;
 }
 
@@ -1434,6 +1441,17 @@ m1_status rebuild(m1_engine& E)
         return L;
     };
     E.fine = make([](const m1_plan&) { return true; }, 0);
+    E.rows = m1::sweep_rows();
+    E.fine2 = {};
+    E.fine2.off = (int)E.hwl.size();
+    if (E.rows > 0) {
+        for (int i = 0; i < np; ++i) {
+            const LevelBuf& lv = E.running[i]->plan->lev[0];
+            const uint32_t nt = (uint32_t)((lv.nx + 63) / 64) * (uint32_t)((lv.ny + E.rows - 1) / E.rows);
+            for (uint32_t t = 0; t < nt; ++t) E.hwl.push_back(((uint32_t)i << m1::kTileBits) | t);
+        }
+    }
+    E.fine2.n = (int)E.hwl.size() - E.fine2.off;
     E.restr.assign(E.Lmax, {});
     E.pdown.assign(E.Lmax, {});
     E.up.assign(E.Lmax, {});
@@ -1493,7 +1511,8 @@ void b_vcycle(m1_engine& E)
     const uint32_t* wl = E.dWL;
     int in_x1 = 0;
     for (int s = 0; s < nu0; ++s) {
-        m1::launch_b_relax(E.st, E.dP, E.dS, wl + E.fine.off, E.fine.n, in_x1, s == 0);
+        if (s > 0 && E.rows > 0) m1::launch_b_relax_lds(E.st, E.dP, E.dS, wl + E.fine2.off, E.fine2.n, in_x1, E.rows);
+        else m1::launch_b_relax(E.st, E.dP, E.dS, wl + E.fine.off, E.fine.n, in_x1, s == 0);
         if (s == 0) m1::launch_b_norm_control(E.st, E.dP, E.dPL, E.n_all, 0);
         in_x1 ^= 1;
     }
@@ -1523,7 +1542,8 @@ void b_vcycle(m1_engine& E)
         }
     }
     for (int s = 0; s < nu0; ++s) {
-        m1::launch_b_relax(E.st, E.dP, E.dS, wl + E.fine.off, E.fine.n, in_x1, 0);
+        if (E.rows > 0) m1::launch_b_relax_lds(E.st, E.dP, E.dS, wl + E.fine2.off, E.fine2.n, in_x1, E.rows);
+        else m1::launch_b_relax(E.st, E.dP, E.dS, wl + E.fine.off, E.fine.n, in_x1, 0);
         in_x1 ^= 1;
     }
 }
@@ -1542,7 +1562,10 @@ void bm_vcycle(m1_engine& E)
     int d = 1;
     for (int s = 0; s < nu0; ++s) {
         const int out = d ^ 1;
-        m1::launch_bm_sweep(E.st, E.dP, E.dS32, wl + E.fine.off, E.fine.n, d, out, s == 0);
+        if (s > 0 && E.rows > 0)
+            m1::launch_bm_sweep_lds(E.st, E.dP, E.dS32, wl + E.fine2.off, E.fine2.n, d, out, E.rows);
+        else
+            m1::launch_bm_sweep(E.st, E.dP, E.dS32, wl + E.fine.off, E.fine.n, d, out, s == 0);
         d = out;
     }
     const int d0 = d;
@@ -1571,7 +1594,8 @@ void bm_vcycle(m1_engine& E)
     d = d0;
     for (int s = 0; s < nu0; ++s) {
         const int out = d ^ 1;
-        m1::launch_bm_sweep(E.st, E.dP, E.dS32, wl + E.fine.off, E.fine.n, d, out, 0);
+        if (E.rows > 0) m1::launch_bm_sweep_lds(E.st, E.dP, E.dS32, wl + E.fine2.off, E.fine2.n, d, out, E.rows);
+        else m1::launch_bm_sweep(E.st, E.dP, E.dS32, wl + E.fine.off, E.fine.n, d, out, 0);
         d = out;
     }
 }

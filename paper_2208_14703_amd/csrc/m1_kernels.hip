@@ -499,6 +499,41 @@ __global__ __launch_bounds__(kTbThreads) void k_smooth_tb(Phys ph, Lvl L, CSoa f
 __device__ __forceinline__ const Soa& pick(const BSlot& s, int sel) { return sel == 0 ? s.v : (sel == 1 ? s.u : s.u2); }
 
 
+// Batched LDS-staged finest-level sweep (no norm): work-list entries are the
+// 64 x TY tiles of each problem's finest level (row-major tile index); the
+// staging and the arithmetic are those of k_relax_lds.
+template <int TY>
+__global__ __launch_bounds__(kLdsTX * TY) void kb_relax_lds(const BProb* __restrict__ P, const BSlot* __restrict__ S,
+                                                           const uint32_t* __restrict__ wl, int nwl, int in_x1)
+{
+    constexpr int W = LdsTile<TY>::W;
+    __shared__ LdsTile<TY> q;
+    for (int w_ = blockIdx.x; w_ < nwl; w_ += gridDim.x) {
+        const uint32_t item = wl[w_];
+        const int p = (int)(item >> kTileBits);
+        const uint32_t tile = item & ((1u << kTileBits) - 1u);
+        const BProb& pb = P[p];
+        if (pb.ctrl->active == 0) continue;
+        const BSlot& s = S[p * kMaxLevels];
+        const Soa& in = in_x1 ? s.x1 : s.x0;
+        const Soa& out = in_x1 ? s.x0 : s.x1;
+        const uint32_t ntx = (uint32_t)((s.L.nx + kLdsTX - 1) / kLdsTX);
+        const int i0 = (int)(tile % ntx) * kLdsTX, j0 = (int)(tile / ntx) * TY;
+        stage_tile<TY, false>(q, nullptr, pb.ph, s.L, cs(in), i0, j0, CSoa{}, CSoa{}, 0, 0, 0.0);
+        __syncthreads();
+        const int li = threadIdx.x % kLdsTX, lj = threadIdx.x / kLdsTX, i = i0 + li, j = j0 + lj;
+        if (i < s.L.nx && j < s.L.ny) {
+            const uint32_t k = (uint32_t)j * (uint32_t)s.L.nx + (uint32_t)i;
+            const int c = (lj + 1) * W + li + 1;
+            double S0, S1, S2;
+            tile_sums<TY>(q, s.L, pb.ph.c, c, S0, S1, S2);
+            auto cen = [&](int f) { return f == 0 ? q.E[c] : (f == 1 ? q.Fx[c] : q.Fy[c]); };
+            relax_update<2, false>(pb.ph, s.L, cs(s.b), 1.0, 0.0, pb.omega, S0, S1, S2, ld(in.T, k), cen, out, k);
+        }
+        __syncthreads();  // the next tile of this block reuses the LDS
+    }
+}
+
 template <bool NORM>
 __global__ __launch_bounds__(kBlock) void kb_relax(const BProb* __restrict__ P, const BSlot* __restrict__ S,
                                                    const uint32_t* __restrict__ wl, int nwl, int in_x1)
@@ -789,6 +824,16 @@ static std::atomic<int> g_batch_grid{16384};
 int batch_grid_cap() { return g_batch_grid.load(std::memory_order_relaxed); }
 void set_batch_grid_cap(int cap) { g_batch_grid.store(cap, std::memory_order_relaxed); }
 static unsigned bgrid(int nwl) { return (unsigned)std::max(1, std::min(nwl, batch_grid_cap())); }
+
+void launch_b_relax_lds(hipStream_t st, const BProb* P, const BSlot* S, const uint32_t* wl, int nwl, int in_x1,
+                        int rows)
+{
+    if (nwl <= 0) return;
+    const dim3 g(bgrid(nwl)), b(kLdsTX * rows);
+    if (rows == 4) hipLaunchKernelGGL(kb_relax_lds<4>, g, b, 0, st, P, S, wl, nwl, in_x1);
+    else if (rows == 8) hipLaunchKernelGGL(kb_relax_lds<8>, g, b, 0, st, P, S, wl, nwl, in_x1);
+    else hipLaunchKernelGGL(kb_relax_lds<16>, g, b, 0, st, P, S, wl, nwl, in_x1);
+}
 
 void launch_b_relax(hipStream_t st, const BProb* P, const BSlot* S, const uint32_t* wl, int nwl, int in_x1, int norm)
 {

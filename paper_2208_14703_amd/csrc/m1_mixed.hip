@@ -198,17 +198,19 @@ __device__ __forceinline__ void mx_sweep_cell(const Phys& ph, const Lvl32& L, co
 constexpr int kMxTX = 64;
 
 template <int TY>
-__global__ __launch_bounds__(kMxTX * TY) void k_mx_sweep_lds(Phys ph, Lvl32 L, CSoa32 w, CSoa32 d, CSoa32 rhs,
-                                                            float beta, float gamma, float omega, Soa32 out,
-                                                            const int* __restrict__ active)
+struct MxTile {
+    static constexpr int W = kMxTX + 2, N = W * (TY + 2);
+    float e[N], gx[N], gy[N], xx[N], xy[N], yy[N];
+};
+
+// Stage the 64 x TY tile at (i0, j0): correction (after the boundary rule) and
+// c^2 P increment of every tile and halo point.
+template <int TY>
+__device__ __forceinline__ void mx_stage_tile(MxTile<TY>& q, const Phys& ph, const Lvl32& L, const CSoa32& w,
+                                              const CSoa32& d, int i0, int j0)
 {
     static_assert(kMxTX * TY >= 2 * kMxTX + 2 * TY, "the halo needs 2 rows and 2 columns of threads");
-    constexpr int W = kMxTX + 2, N = W * (TY + 2);
-    __shared__ float qe[N], qgx[N], qgy[N], qxx[N], qxy[N], qyy[N];
-    if (*active == 0) return;
-    const int ntx = (L.nx + kMxTX - 1) / kMxTX;
-    const int b = (int)xcd_block();
-    const int i0 = (b % ntx) * kMxTX, j0 = (b / ntx) * TY;
+    constexpr int W = MxTile<TY>::W;
     const float c = (float)ph.c, c2 = (float)ph.c2;
     const bool perx = ph.bc[0] == BC_PERIODIC, pery = ph.bc[2] == BC_PERIODIC;
     auto gather = [&](int li, int lj) {
@@ -232,13 +234,13 @@ __global__ __launch_bounds__(kMxTX * TY) void k_mx_sweep_lds(Phys ph, Lvl32 L, C
                       ldf(d.Fy, k), E, Fx, Fy, e, gx, gy);
             p = closure_inc(c, c2, E, Fx, Fy, e, gx, gy);
         }
-        const int q = (lj + 1) * W + li + 1;
-        qe[q] = e;
-        qgx[q] = gx;
-        qgy[q] = gy;
-        qxx[q] = p.xx;
-        qxy[q] = p.xy;
-        qyy[q] = p.yy;
+        const int n = (lj + 1) * W + li + 1;
+        q.e[n] = e;
+        q.gx[n] = gx;
+        q.gy[n] = gy;
+        q.xx[n] = p.xx;
+        q.xy[n] = p.xy;
+        q.yy[n] = p.yy;
     };
     const int t = threadIdx.x;
     gather(t % kMxTX, t / kMxTX);
@@ -248,20 +250,47 @@ __global__ __launch_bounds__(kMxTX * TY) void k_mx_sweep_lds(Phys ph, Lvl32 L, C
         const int r = t - 2 * kMxTX;
         gather(r < TY ? -1 : kMxTX, r % TY);
     }
-    __syncthreads();
-    const int li = t % kMxTX, lj = t / kMxTX, i = i0 + li, j = j0 + lj;
+}
+
+// The sweep of this thread's cell of a staged tile (nothing outside the grid).
+template <int TY>
+__device__ __forceinline__ void mx_tile_sweep(const MxTile<TY>& q, const Phys& ph, const Lvl32& L, const CSoa32& w,
+                                              const CSoa32& d, const CSoa32& rhs, float beta, float gamma,
+                                              float omega, const Soa32& out, int i0, int j0)
+{
+    constexpr int W = MxTile<TY>::W;
+    const int li = threadIdx.x % kMxTX, lj = threadIdx.x / kMxTX, i = i0 + li, j = j0 + lj;
     if (i >= L.nx || j >= L.ny) return;
     const uint32_t k = (uint32_t)j * (uint32_t)L.nx + (uint32_t)i;
-    const int q = (lj + 1) * W + li + 1;
+    const int n = (lj + 1) * W + li + 1;
+    const float c = (float)ph.c;
     float S0 = 0.0f, S1 = 0.0f, S2 = 0.0f;  // the order of offdiag_inc: x-, x+, y-, y+
-    auto nb = [&](int n, float kk, float sgn, bool xdir) {
-        acc_inc(kk, sgn, xdir, c, qe[n], qgx[n], qgy[n], DP{qxx[n], qxy[n], qyy[n]}, S0, S1, S2);
+    auto nb = [&](int m, float kk, float sgn, bool xdir) {
+        acc_inc(kk, sgn, xdir, c, q.e[m], q.gx[m], q.gy[m], DP{q.xx[m], q.xy[m], q.yy[m]}, S0, S1, S2);
     };
-    nb(q - 1, L.kx, +1.0f, true);
-    nb(q + 1, L.kx, -1.0f, true);
-    nb(q - W, L.ky, +1.0f, false);
-    nb(q + W, L.ky, -1.0f, false);
-    mx_sweep_update<2>(ph, L, w, rhs, beta, gamma, omega, S0, S1, S2, qe[q], qgx[q], qgy[q], ldf(d.T, k), out, k);
+    nb(n - 1, L.kx, +1.0f, true);
+    nb(n + 1, L.kx, -1.0f, true);
+    nb(n - W, L.ky, +1.0f, false);
+    nb(n + W, L.ky, -1.0f, false);
+    mx_sweep_update<2>(ph, L, w, rhs, beta, gamma, omega, S0, S1, S2, q.e[n], q.gx[n], q.gy[n], ldf(d.T, k), out, k);
+}
+
+// LDS-staged sweep on the correction (2-D, d given): a block owns a 64 x TY
+// tile; see mx_stage_tile.  The arithmetic of every cell, and its order, is
+// that of mx_sweep_cell.
+template <int TY>
+__global__ __launch_bounds__(kMxTX * TY) void k_mx_sweep_lds(Phys ph, Lvl32 L, CSoa32 w, CSoa32 d, CSoa32 rhs,
+                                                            float beta, float gamma, float omega, Soa32 out,
+                                                            const int* __restrict__ active)
+{
+    __shared__ MxTile<TY> q;
+    if (*active == 0) return;
+    const int ntx = (L.nx + kMxTX - 1) / kMxTX;
+    const int b = (int)xcd_block();
+    const int i0 = (b % ntx) * kMxTX, j0 = (b / ntx) * TY;
+    mx_stage_tile<TY>(q, ph, L, w, d, i0, j0);
+    __syncthreads();
+    mx_tile_sweep<TY>(q, ph, L, w, d, rhs, beta, gamma, omega, out, i0, j0);
 }
 
 template <int DIM>
@@ -715,6 +744,32 @@ __global__ __launch_bounds__(kBlock32) void kbm_sweep(const BProb* __restrict__ 
     }
 }
 
+// Batched staged correction sweep (d given): work-list entries are the 64 x TY
+// tiles of each problem's finest level.
+template <int TY>
+__global__ __launch_bounds__(kMxTX * TY) void kbm_sweep_lds(const BProb* __restrict__ P,
+                                                           const BSlot32* __restrict__ S32,
+                                                           const uint32_t* __restrict__ wl, int nwl, int in_sel,
+                                                           int out_sel)
+{
+    __shared__ MxTile<TY> q;
+    for (int w_ = blockIdx.x; w_ < nwl; w_ += gridDim.x) {
+        const uint32_t item = wl[w_];
+        const int p = (int)(item >> kTileBits);
+        const uint32_t tile = item & ((1u << kTileBits) - 1u);
+        const BProb& pb = P[p];
+        if (pb.ctrl->active == 0) continue;
+        const BSlot32& s = S32[p * kMaxLevels];
+        const uint32_t ntx = (uint32_t)((s.L.nx + kMxTX - 1) / kMxTX);
+        const int i0 = (int)(tile % ntx) * kMxTX, j0 = (int)(tile / ntx) * TY;
+        mx_stage_tile<TY>(q, pb.ph, s.L, cs(s.base), cs(pickA(s, in_sel)), i0, j0);
+        __syncthreads();
+        mx_tile_sweep<TY>(q, pb.ph, s.L, cs(s.base), cs(pickA(s, in_sel)), cs(s.r32), 0.0f, 1.0f, (float)pb.omega,
+                          pickA(s, out_sel), i0, j0);
+        __syncthreads();  // the next tile of this block reuses the LDS
+    }
+}
+
 // level 0: rho0 = r32 - N(d) (d = pickA(in_sel)); level >= 1: rho = g - N(pick32(in_sel)).
 __global__ __launch_bounds__(kBlock32) void kbm_apply(const BProb* __restrict__ P, const BSlot32* __restrict__ S32,
                                                       const uint32_t* __restrict__ wl, int nwl, int level, int in_sel)
@@ -897,6 +952,16 @@ void launch_bm_resid(hipStream_t st, const BProb* P, const BSlot* S, const BSlot
 {
     if (nwl > 0) hipLaunchKernelGGL(kbm_resid, dim3(bmgrid(nwl)), dim3(kBlock32), 0, st, P, S, S32, wl, nwl, pend_sel);
 }
+void launch_bm_sweep_lds(hipStream_t st, const BProb* P, const BSlot32* S32, const uint32_t* wl, int nwl, int in_sel,
+                         int out_sel, int rows)
+{
+    if (nwl <= 0) return;
+    const dim3 g(bmgrid(nwl)), b(kMxTX * rows);
+    if (rows == 4) hipLaunchKernelGGL(kbm_sweep_lds<4>, g, b, 0, st, P, S32, wl, nwl, in_sel, out_sel);
+    else if (rows == 8) hipLaunchKernelGGL(kbm_sweep_lds<8>, g, b, 0, st, P, S32, wl, nwl, in_sel, out_sel);
+    else hipLaunchKernelGGL(kbm_sweep_lds<16>, g, b, 0, st, P, S32, wl, nwl, in_sel, out_sel);
+}
+
 void launch_bm_sweep(hipStream_t st, const BProb* P, const BSlot32* S32, const uint32_t* wl, int nwl, int in_sel,
                      int out_sel, int from_zero)
 {
