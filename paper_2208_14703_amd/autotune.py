@@ -8,13 +8,15 @@ the default's result bit for bit. It picks, by coordinate descent on measured
 time (a candidate replaces the library's default only when it is faster by more
 than `margin`, so that timing noise does not move the settings):
   * sweep_rows: tile rows of the LDS-staged finest-level sweep (0: unstaged);
+  * residual_restrict: the finest residual restricted as it is formed (1) or
+    stored and restricted by a second launch (0);
   * tail_cells: levels of at most this many cells run in one workgroup;
   * tiled_max_cells: largest level whose smoothing legs run as one LDS-tiled
     launch each;
   * graphs: V-cycles replayed from hipGraph recordings, or enqueued launch by
     launch;
   * batch_grid: most blocks of one batched launch.
-sweep_rows, tail_cells and tiled_max_cells are timed on one time step of the hot-wall
+sweep_rows, residual_restrict, tail_cells and tiled_max_cells are timed on one time step of the hot-wall
 problem (side n), batch_grid on the batched engine over `batch` problems of the
 batched workload, graphs on both (sum of the two times).
 With --write the choice is stored in tuning.json beside this file, keyed by the
@@ -35,13 +37,15 @@ TUNING_FILE = os.path.join(HERE, "tuning.json")
 
 CANDIDATES = {
     "sweep_rows": [0, 4, 8, 16],
+    "residual_restrict": [1, 0],
     "tail_cells": [64, 256, 1024],
     "tiled_max_cells": [0, 4096, 16384, 65536, 262144],
     "graphs": [0, 1],
     "batch_grid": [4096, 16384, 65536],
 }
 # the library's built-in values (what m1_tune_get returns before any setting)
-BUILTIN = {"sweep_rows": 4, "tail_cells": 256, "tiled_max_cells": 65536, "graphs": 0, "batch_grid": 16384}
+BUILTIN = {"sweep_rows": 4, "residual_restrict": 1, "tail_cells": 256, "tiled_max_cells": 65536, "graphs": 0,
+           "batch_grid": 16384}
 SOLVER = dict(omega=0.8, levels=0, rtol=1e-8, max_cycles=20000)
 
 

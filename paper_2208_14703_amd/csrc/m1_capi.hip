@@ -255,6 +255,7 @@ struct Tuning {
     {
         if (const char* e = std::getenv("M1_GRAPHS")) graphs = std::atoll(e) != 0;
         if (const char* e = std::getenv("M1_SWEEP_ROWS")) (void)m1::set_sweep_rows(std::atoi(e));
+        if (const char* e = std::getenv("M1_RESIDUAL_RESTRICT")) m1::set_residual_restrict(std::atoi(e));
         if (const char* e = std::getenv("M1_TAIL_CELLS")) tail_cells = std::atoll(e);
         if (const char* e = std::getenv("M1_TILED_MAX_CELLS")) tiled_max_cells = std::atoll(e);
         if (const char* e = std::getenv("M1_BATCH_GRID")) {
@@ -387,7 +388,9 @@ void vcycle_impl(m1_plan& P, Soa& cur, Soa& other, const Gate& G, bool control =
     const m1_params& p = P.params;
     fine_sweeps(P, cur, other, p.nu0, G, control);
     if (P.L == 1) return;
-    m1::launch_apply(P.st, P.dim, P.ph, P.lev[0].L, cs(cur), cs(P.b), -1.0, P.rfine, nullptr, G.active);
+    // the finest residual is restricted as it is formed (one launch) unless switched off
+    const bool fused = P.dim == 2 && m1::residual_restrict();
+    if (!fused) m1::launch_apply(P.st, P.dim, P.ph, P.lev[0].L, cs(cur), cs(P.b), -1.0, P.rfine, nullptr, G.active);
     std::vector<Soa> ul(P.L);
     // levels smoothed by one LDS-tiled launch per leg: R(rbar) goes to rb, which the
     // down leg reads while it writes the FAS right-hand side into f
@@ -401,8 +404,12 @@ void vcycle_impl(m1_plan& P, Soa& cur, Soa& other, const Gate& G, bool control =
     for (int l = 1; l < P.L; ++l) {
         LevelBuf& c = P.lev[l];
         const LevelBuf& f = P.lev[l - 1];
-        m1::launch_restrict(P.st, P.dim, f.nx, f.ny, P.px, P.py,
-                            fields2(ul[l - 1], rb_prev, c.v, tiled[l] ? c.rb : c.f, P.dim), G.active);
+        if (l == 1 && fused)
+            m1::launch_residual_restrict(P.st, P.ph, f.L, cs(ul[0]), cs(P.b), -1.0, P.px, P.py, c.v,
+                                         tiled[l] ? c.rb : c.f, G.active);
+        else
+            m1::launch_restrict(P.st, P.dim, f.nx, f.ny, P.px, P.py,
+                                fields2(ul[l - 1], rb_prev, c.v, tiled[l] ? c.rb : c.f, P.dim), G.active);
         if (l == P.lt) {  // the rest of the cycle below (and including) level lt
             m1::launch_tail(P.st, P.dim, P.dtail, G.dtau, G.dtau_dev, G.active);
             ul[l] = c.u;
@@ -517,7 +524,9 @@ void mx_vcycle(m1_plan& P, Soa& cur64, Soa& other64, const Gate& G, bool control
         pend = d;
         return;
     }
-    m1::launch_mx_apply(P.st, P.dim, P.ph, f0.L32, cs(P.base32), cs(d), cs(P.r32), -1.0f, P.rho0, G.active);
+    const bool fused = P.dim == 2 && m1::residual_restrict();  // rho0 restricted as it is formed
+    if (!fused)
+        m1::launch_mx_apply(P.st, P.dim, P.ph, f0.L32, cs(P.base32), cs(d), cs(P.r32), -1.0f, P.rho0, G.active);
     std::vector<Soa32> el(P.L);
     el[0] = d;
     const Soa32* wprev = &P.base32;
@@ -525,8 +534,12 @@ void mx_vcycle(m1_plan& P, Soa& cur64, Soa& other64, const Gate& G, bool control
     for (int l = 1; l < P.L; ++l) {
         LevelBuf& c = P.lev[l];
         const LevelBuf& fl = P.lev[l - 1];
-        m1::launch_mx_restrict(P.st, P.dim, fl.nx, fl.ny, P.px, P.py,
-                               fields32({{wprev, &c.w}, {&el[l - 1], &c.d}, {rprev, &c.gg}}, P.dim), G.active);
+        if (l == 1 && fused)
+            m1::launch_mx_residual_restrict(P.st, P.ph, f0.L32, cs(P.base32), cs(d), cs(P.r32), -1.0f, P.px, P.py,
+                                            c.w, c.d, c.gg, G.active);
+        else
+            m1::launch_mx_restrict(P.st, P.dim, fl.nx, fl.ny, P.px, P.py,
+                                   fields32({{wprev, &c.w}, {&el[l - 1], &c.d}, {rprev, &c.gg}}, P.dim), G.active);
         if (l == P.lt) {  // the rest of the cycle below (and including) level lt in one workgroup
             m1::launch_mx_tail(P.st, P.dim, P.dtail32, G.dtau, G.dtau_dev, G.active);
             el[l] = c.e;
@@ -1096,6 +1109,7 @@ m1_status m1_tune_set(const char* key, int64_t value)
     else if (k == "tiled_max_cells") tuning().tiled_max_cells = value;
     else if (k == "graphs" && value <= 1) tuning().graphs = value;
     else if (k == "sweep_rows" && value <= 16 && m1::set_sweep_rows((int)value)) {}
+    else if (k == "residual_restrict" && value <= 1) m1::set_residual_restrict((int)value);
     else if (k == "batch_grid" && value >= 1 && value <= (int64_t(1) << 24)) m1::set_batch_grid_cap((int)value);
     else return M1_ERR_ARG;
     return M1_OK;
@@ -1109,6 +1123,7 @@ int64_t m1_tune_get(const char* key)
     if (k == "tiled_max_cells") return tuning().tiled_max_cells.load();
     if (k == "graphs") return tuning().graphs.load();
     if (k == "sweep_rows") return m1::sweep_rows();
+    if (k == "residual_restrict") return m1::residual_restrict();
     if (k == "batch_grid") return m1::batch_grid_cap();
     return -1;
 }

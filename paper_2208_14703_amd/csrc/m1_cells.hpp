@@ -162,26 +162,36 @@ __device__ __forceinline__ void pseudo_cell(const Phys& ph, const Lvl& L, const 
 
 // out = X + sgn A(v) (X.E == nullptr: out = sgn A(v)); out stored when out.E
 // is set.  Returns r_E^2 + (r_F/c)^2 + r_T^2 of the result (norm contribution).
-// The rest of apply_cell from the cell's state and off-diagonal sum S.
+// X + sgn A(v) of one cell from its state and off-diagonal sum S (X.E null: sgn A(v)).
 template <int DIM>
-__device__ __forceinline__ double apply_update(const Phys& ph, const Lvl& L, double E, double Fx, double Fy, double T,
-                                               double S0, double S1, double S2, const CSoa& X, double sgn,
-                                               const Soa& out, uint32_t k, bool live)
+__device__ __forceinline__ void apply_values(const Phys& ph, const Lvl& L, double E, double Fx, double Fy, double T,
+                                             double S0, double S1, double S2, const CSoa& X, double sgn, uint32_t k,
+                                             double& rE, double& rFx, double& rFy, double& rT)
 {
     const double ka = L.cdt * ld(L.sa, k), ks = L.cdt * ld(L.ss, k);
     const double T2 = T * T;
     const double ex = ka * fma(-ph.a_r * T2, T2, E);  // ka (E - a_r T^4)
     const double dF = L.a + ka + ks;
-    double rE = sgn * (fma(L.a, E, ex) - S0);
-    double rFx = sgn * fma(dF, Fx, -S1);
-    double rFy = sgn * fma(dF, Fy, -S2);
-    double rT = sgn * fma(ph.c_v, T, -ex);
+    rE = sgn * (fma(L.a, E, ex) - S0);
+    rFx = sgn * fma(dF, Fx, -S1);
+    rFy = sgn * fma(dF, Fy, -S2);
+    rT = sgn * fma(ph.c_v, T, -ex);
     if (X.E) {
         rE += ld(X.E, k);
         rFx += ld(X.Fx, k);
         if (DIM == 2) rFy += ld(X.Fy, k);
         rT += ld(X.T, k);
     }
+}
+
+// The rest of apply_cell from the cell's state and off-diagonal sum S.
+template <int DIM>
+__device__ __forceinline__ double apply_update(const Phys& ph, const Lvl& L, double E, double Fx, double Fy, double T,
+                                               double S0, double S1, double S2, const CSoa& X, double sgn,
+                                               const Soa& out, uint32_t k, bool live)
+{
+    double rE, rFx, rFy, rT;
+    apply_values<DIM>(ph, L, E, Fx, Fy, T, S0, S1, S2, X, sgn, k, rE, rFx, rFy, rT);
     if (out.E && live) {
         st(out.E, k, rE);
         st(out.Fx, k, rFx);

@@ -277,6 +277,24 @@ __device__ __forceinline__ bool admissible(double c2, double E, double Fx, doubl
     return E > 0.0 && T > 0.0 && fma(Fx, Fx, Fy * Fy) <= c2 * E * E;
 }
 
+// Fine coordinate g on an axis of n cells: the cell read (src), whether the
+// point is the ghost beyond a non-periodic side, whether it is used at all.
+__device__ __forceinline__ void rc_axis(int g, int n, bool per, int& src, bool& ghost, bool& need)
+{
+    src = g;
+    ghost = false;
+    need = true;
+    if (g >= 0 && g < n) return;
+    if (per) {
+        src = ((g % n) + n) % n;
+    } else if (g == -1 || g == n) {
+        src = g < 0 ? 0 : n - 1;
+        ghost = true;
+    } else {
+        need = false;
+    }
+}
+
 // XCD-aware block order: hardware hands consecutive blocks to the 8 XCDs round
 // robin; remap so that each XCD walks one contiguous band of the grid and the
 // stencil halo rows it needs stay in its own L2.

@@ -141,6 +141,12 @@ void set_batch_grid_cap(int cap);
 // rows of the LDS-staged finest sweep's 64-wide tile (0: one-cell-per-thread sweep)
 int sweep_rows();
 bool set_sweep_rows(int rows);
+// finest-level residual fused with the restriction to level 1 (launch shape; 0: two kernels)
+int residual_restrict();
+void set_residual_restrict(int on);
+// 2-D: coarse (vc, rc) = R(u), R(X + sgn A(u)) of the fine level L, without storing the fine residual
+void launch_residual_restrict(hipStream_t st, const Phys& ph, const Lvl& L, CSoa u, CSoa X, double sgn, int px, int py,
+                              Soa vc, Soa rc, const int* active);
 // LDS-staged finest-level sweep (2-D, beta = 0, gamma = 1, no norm); with uc.E
 // non-null the gathered states are first corrected from level 1 (uc, vc) and
 // projected, as by launch_prolong_project.  false (nothing launched) when the
@@ -171,6 +177,9 @@ void launch_mx_resid(hipStream_t st, int dim, const Phys& ph, const Lvl& L, doub
                      Soa vnew, Soa32 base, Soa32 r32, double* partials, const int* active);
 void launch_mx_sweep(hipStream_t st, int dim, const Phys& ph, const Lvl32& L, CSoa32 w, CSoa32 d, CSoa32 rhs,
                      float beta, float gamma, float omega, Soa32 out, const int* active);
+// 2-D: coarse (wc, dc, gc) = R(w), R(d), R(X + sgn N_w(d)) of the fine level L, without storing rho
+void launch_mx_residual_restrict(hipStream_t st, const Phys& ph, const Lvl32& L, CSoa32 w, CSoa32 d, CSoa32 X,
+                                 float sgn, int px, int py, Soa32 wc, Soa32 dc, Soa32 gc, const int* active);
 void launch_mx_apply(hipStream_t st, int dim, const Phys& ph, const Lvl32& L, CSoa32 w, CSoa32 d, CSoa32 X, float sgn,
                      Soa32 out, const int* active);
 void launch_mx_pseudo(hipStream_t st, int dim, const Phys& ph, const Lvl32& L, CSoa32 w, Soa32 g, CSoa32 e,

@@ -231,6 +231,121 @@ __global__ __launch_bounds__(kLdsTX * TY) void k_apply_lds(Phys ph, Lvl L, CSoa 
     apply_update<2>(ph, L, q.E[c], q.Fx[c], q.Fy[c], ld(v.T, k), S0, S1, S2, X, sgn, out, k, live);
 }
 
+// ---------------------------------------------------------------------------
+// Finest-level residual fused with the restriction to level 1 (2-D).  A block
+// owns a 32 x 4 tile of coarse cells, i.e. the fine cells 2I-1 .. 2I+1 of each
+// coarse I of the tile.  It stages the fine states of the region around them
+// (per axis wrapped where periodic, else the ghost one cell beyond the side),
+// evaluating each closure once; computes the residual X + sgn A(u) of the
+// fine cells the restriction reads (a point dropped at a non-periodic side
+// reads the clamped cell, as restrict_cell does); and restricts u and the
+// residual into (vc, rc) with the weights and the order of restrict_cell.
+// The fine residual is never stored and u is read once.
+constexpr int kRcW = 32, kRcH = 4;                       // coarse tile
+constexpr int kRsW = 2 * kRcW + 3, kRsH = 2 * kRcH + 3;  // staged fine offsets -2 .. 2 kRc
+constexpr int kRrW = 2 * kRcW + 1, kRrH = 2 * kRcH + 1;  // residual offsets -1 .. 2 kRc - 1
+constexpr int kRcThreads = 512;
+
+
+__global__ __launch_bounds__(kRcThreads) void k_residual_restrict(Phys ph, Lvl L, CSoa u, CSoa X, double sgn, int px,
+                                                                  int py, Soa vc, Soa rc,
+                                                                  const int* __restrict__ active)
+{
+    constexpr int NS = kRsW * kRsH, NR = kRrW * kRrH;
+    __shared__ double sE[NS], sFx[NS], sFy[NS], sT[NS], sXX[NS], sXY[NS], sYY[NS];
+    __shared__ double qE[NR], qFx[NR], qFy[NR], qT[NR];
+    const bool live = active[lane_zero()] != 0;
+    const int nxc = L.nx / 2, nyc = L.ny / 2;
+    const int ntx = (nxc + kRcW - 1) / kRcW;
+    const int b = (int)xcd_block();
+    const int I0 = (b % ntx) * kRcW, J0 = (b / ntx) * kRcH;
+    const int fi0 = 2 * I0, fj0 = 2 * J0;
+    for (int q = threadIdx.x; q < NS; q += kRcThreads) {
+        const int gi = fi0 + q % kRsW - 2, gj = fj0 + q / kRsW - 2;
+        int si, sj;
+        bool hx, hy, nx_, ny_;
+        rc_axis(gi, L.nx, px != 0, si, hx, nx_);
+        rc_axis(gj, L.ny, py != 0, sj, hy, ny_);
+        double e = 0.0, fx = 0.0, fy = 0.0, t = 0.0, xx = 0.0, xy = 0.0, yy = 0.0;
+        if (nx_ && ny_ && !(hx && hy)) {
+            const int side = hx ? (gi < 0 ? 0 : 1) : (hy ? (gj < 0 ? 2 : 3) : 0);
+            const uint32_t k = (uint32_t)sj * (uint32_t)L.nx + (uint32_t)si;
+            ghost_rule(ph, side, !(hx || hy), ld(u.E, k), ld(u.Fx, k), ld(u.Fy, k), e, fx, fy);
+            t = ld(u.T, k);
+            const C2P p = closure(ph.c, ph.c2, e, fx, fy);
+            xx = p_xx(p, fx);
+            xy = p_xy(p, fx, fy);
+            yy = p_yy(p, fy);
+        }
+        sE[q] = e;
+        sFx[q] = fx;
+        sFy[q] = fy;
+        sT[q] = t;
+        sXX[q] = xx;
+        sXY[q] = xy;
+        sYY[q] = yy;
+    }
+    __syncthreads();
+    // staged index of the cell a residual point (fine offsets ri, rj) reads
+    auto centre = [&](int ri, int rj) {
+        if (fi0 + ri < 0 && !px) ri += 1;
+        if (fj0 + rj < 0 && !py) rj += 1;
+        return (rj + 2) * kRsW + ri + 2;
+    };
+    for (int q = threadIdx.x; q < NR; q += kRcThreads) {
+        const int ri = q % kRrW - 1, rj = q / kRrW - 1;
+        const int gi = fi0 + ri, gj = fj0 + rj;
+        double rE = 0.0, rFx = 0.0, rFy = 0.0, rT = 0.0;
+        if (gi < L.nx && gj < L.ny) {  // points past the grid belong to no coarse cell
+            const int c = centre(ri, rj);
+            const int si = gi < 0 ? (px ? gi + L.nx : 0) : gi, sj = gj < 0 ? (py ? gj + L.ny : 0) : gj;
+            const uint32_t k = (uint32_t)sj * (uint32_t)L.nx + (uint32_t)si;
+            double S0 = 0.0, S1 = 0.0, S2 = 0.0;  // the order of offdiag: x-, x+, y-, y+
+            acc_x(L.kx, ph.c, +1.0, sE[c - 1], sFx[c - 1], sFy[c - 1], sXX[c - 1], sXY[c - 1], S0, S1, S2);
+            acc_x(L.kx, ph.c, -1.0, sE[c + 1], sFx[c + 1], sFy[c + 1], sXX[c + 1], sXY[c + 1], S0, S1, S2);
+            acc_y(L.ky, ph.c, +1.0, sE[c - kRsW], sFx[c - kRsW], sFy[c - kRsW], sXY[c - kRsW], sYY[c - kRsW], S0,
+                  S1, S2);
+            acc_y(L.ky, ph.c, -1.0, sE[c + kRsW], sFx[c + kRsW], sFy[c + kRsW], sXY[c + kRsW], sYY[c + kRsW], S0,
+                  S1, S2);
+            apply_values<2>(ph, L, sE[c], sFx[c], sFy[c], sT[c], S0, S1, S2, X, sgn, k, rE, rFx, rFy, rT);
+        }
+        qE[q] = rE;
+        qFx[q] = rFx;
+        qFy[q] = rFy;
+        qT[q] = rT;
+    }
+    __syncthreads();
+    if (threadIdx.x >= kRcW * kRcH) return;
+    const int ci = threadIdx.x % kRcW, cj = threadIdx.x / kRcW, I = I0 + ci, J = J0 + cj;
+    if (I >= nxc || J >= nyc || !live) return;
+    int ix[3], iy[3];
+    double wx[3], wy[3];
+    rweights(I, L.nx, px != 0, ix, wx);
+    rweights(J, L.ny, py != 0, iy, wy);
+    // fine cell 2I-1+a, 2J-1+b: residual index (2cj+b) kRrW + 2ci+a, staged cell centre(2ci+a-1, 2cj+b-1)
+    auto restrict8 = [&](const double* src, bool staged, double* dst) {
+        double s = 0.0;
+#pragma unroll
+        for (int bb = 0; bb < 3; ++bb) {
+            double v[3];
+#pragma unroll
+            for (int a = 0; a < 3; ++a)
+                v[a] = staged ? src[centre(2 * ci + a - 1, 2 * cj + bb - 1)] : src[(2 * cj + bb) * kRrW + 2 * ci + a];
+            const double t = fma(wx[2], v[2], fma(wx[1], v[1], wx[0] * v[0]));
+            s = fma(wy[bb], t, s);
+        }
+        st(dst, (uint32_t)J * (uint32_t)nxc + (uint32_t)I, s);
+    };
+    restrict8(sE, true, vc.E);
+    restrict8(sFx, true, vc.Fx);
+    restrict8(sFy, true, vc.Fy);
+    restrict8(sT, true, vc.T);
+    restrict8(qE, false, rc.E);
+    restrict8(qFx, false, rc.Fx);
+    restrict8(qFy, false, rc.Fy);
+    restrict8(qT, false, rc.T);
+}
+
 // One pseudo-time step; `first`: also form the FAS right-hand side in f (u = v_l).
 template <int DIM>
 __global__ __launch_bounds__(kBlock) void k_pseudo(Phys ph, Lvl L, Soa f, CSoa u, Soa out, double dtau,
@@ -802,6 +917,20 @@ void launch_pseudo(hipStream_t st, int dim, const Phys& ph, const Lvl& L, Soa f,
 }
 
 unsigned apply_blocks(const Lvl& L) { return nblocks((int64_t)L.nx * L.ny); }
+
+static std::atomic<int> g_residual_restrict{1};
+int residual_restrict() { return g_residual_restrict.load(std::memory_order_relaxed); }
+void set_residual_restrict(int on) { g_residual_restrict.store(on ? 1 : 0, std::memory_order_relaxed); }
+
+void launch_residual_restrict(hipStream_t st, const Phys& ph, const Lvl& L, CSoa u, CSoa X, double sgn, int px, int py,
+                              Soa vc, Soa rc, const int* active)
+{
+    const int nxc = L.nx / 2, nyc = L.ny / 2;
+    if (nxc < 1 || nyc < 1) return;
+    const unsigned nb = (unsigned)((nxc + kRcW - 1) / kRcW) * (unsigned)((nyc + kRcH - 1) / kRcH);
+    hipLaunchKernelGGL(k_residual_restrict, dim3(nb), dim3(kRcThreads), 0, st, ph, L, u, X, sgn, px, py, vc, rc,
+                       active);
+}
 
 void launch_apply(hipStream_t st, int dim, const Phys& ph, const Lvl& L, CSoa v, CSoa X, double sgn, Soa out,
                   double* partials, const int* active)

@@ -305,6 +305,20 @@ __global__ __launch_bounds__(kBlock32) void k_mx_sweep(Phys ph, Lvl32 L, CSoa32 
     mx_sweep_cell<DIM>(ph, L, w, d, rhs, beta, gamma, omega, out, k, i, j);
 }
 
+// N(d) of one cell from its off-diagonal increment S, base temperature and correction.
+__device__ __forceinline__ void n_from_sums(const Phys& ph, const Lvl32& L, float S0, float S1, float S2, float wT,
+                                            float dE, float dFx, float dFy, float dT, uint32_t k, float& NE,
+                                            float& NFx, float& NFy, float& NT)
+{
+    const double ka = (double)L.cdt * ldf(L.sa, k), ks = (double)L.cdt * ldf(L.ss, k);
+    float DE, DFx, DFy, DT;
+    diag_inc(L.a, ka, ks, ph.c_v, ph.a_r, wT, dE, dFx, dFy, dT, DE, DFx, DFy, DT);
+    NE = DE - S0;
+    NFx = DFx - S1;
+    NFy = DFy - S2;
+    NT = DT;
+}
+
 // Increment of A for one cell: N(d) = (D(w + d) - D(w)) - dS(d).
 template <int DIM>
 __device__ __forceinline__ void n_inc(const Phys& ph, const Lvl32& L, const CSoa32& w, const CSoa32& d, uint32_t k,
@@ -312,14 +326,8 @@ __device__ __forceinline__ void n_inc(const Phys& ph, const Lvl32& L, const CSoa
 {
     float S0, S1, S2;
     offdiag_inc<DIM>(ph, L, w, d, i, j, k, S0, S1, S2);
-    const double ka = (double)L.cdt * ldf(L.sa, k), ks = (double)L.cdt * ldf(L.ss, k);
-    float DE, DFx, DFy, DT;
-    diag_inc(L.a, ka, ks, ph.c_v, ph.a_r, ldf(w.T, k), ldf(d.E, k), ldf(d.Fx, k), (DIM == 2) ? ldf(d.Fy, k) : 0.0f,
-             ldf(d.T, k), DE, DFx, DFy, DT);
-    NE = DE - S0;
-    NFx = DFx - S1;
-    NFy = DFy - S2;
-    NT = DT;
+    n_from_sums(ph, L, S0, S1, S2, ldf(w.T, k), ldf(d.E, k), ldf(d.Fx, k), (DIM == 2) ? ldf(d.Fy, k) : 0.0f,
+                ldf(d.T, k), k, NE, NFx, NFy, NT);
 }
 
 // out = X + sgn N(d).
@@ -522,6 +530,31 @@ __global__ __launch_bounds__(kBlock32) void k_mx_prolong_fine(Phys ph, int nx, i
 
 // FP32 restriction of NF fields (base, correction, residual of a level) for
 // coarse cell k: full weighting, all values gathered before the sums.
+// FP32 full-weighting weights of coarse cell c (as rweights): fine 2c-1 .. 2c+1;
+// off a non-periodic side the point is clamped with weight 0, the rest renormalised.
+__device__ __forceinline__ void rweights32(int c, int nf, bool per, int* idx, float* w)
+{
+    float sum = 0.0f;
+    for (int m = 0; m < 3; ++m) {
+        const float base = (m == 1) ? 0.5f : 0.25f;
+        int f = 2 * c - 1 + m;
+        float wm = base;
+        if (f < 0 || f >= nf) {
+            if (per) {
+                f = f < 0 ? f + nf : f - nf;
+            } else {
+                f = f < 0 ? 0 : nf - 1;
+                wm = 0.0f;
+            }
+        }
+        idx[m] = f;
+        w[m] = wm;
+        sum += wm;
+    }
+    if (sum != 1.0f)
+        for (int m = 0; m < 3; ++m) w[m] /= sum;
+}
+
 template <int DIM, int NF>
 __device__ __forceinline__ void mx_restrict_cell(int nxf, int nyf, int shf, int px, int py, const float* const* in,
                                                  float* const* out, uint32_t k, bool live = true)
@@ -531,29 +564,8 @@ __device__ __forceinline__ void mx_restrict_cell(int nxf, int nyf, int shf, int 
     ij_of(nxc, shf > 0 ? shf - 1 : -1, k, I, J);
     int ix[3], iy[3] = {0, 0, 0};
     float wx[3], wy[3] = {1.0f, 0.0f, 0.0f};
-    auto weights = [](int c, int nf, bool per, int* idx, float* w) {
-        float sum = 0.0f;
-        for (int m = 0; m < 3; ++m) {
-            const float base = (m == 1) ? 0.5f : 0.25f;
-            int f = 2 * c - 1 + m;
-            float wm = base;
-            if (f < 0 || f >= nf) {
-                if (per) {
-                    f = f < 0 ? f + nf : f - nf;
-                } else {
-                    f = f < 0 ? 0 : nf - 1;
-                    wm = 0.0f;
-                }
-            }
-            idx[m] = f;
-            w[m] = wm;
-            sum += wm;
-        }
-        if (sum != 1.0f)
-            for (int m = 0; m < 3; ++m) w[m] /= sum;
-    };
-    weights(I, nxf, px != 0, ix, wx);
-    if (DIM == 2) weights(J, nyf, py != 0, iy, wy);
+    rweights32(I, nxf, px != 0, ix, wx);
+    if (DIM == 2) rweights32(J, nyf, py != 0, iy, wy);
     constexpr int NB = (DIM == 2) ? 3 : 1;
     uint32_t off[NB * 3];
 #pragma unroll
@@ -744,6 +756,129 @@ __global__ __launch_bounds__(kBlock32) void kbm_sweep(const BProb* __restrict__ 
     }
 }
 
+// ---------------------------------------------------------------------------
+// Finest-level residual of the correction equation fused with the restriction
+// to level 1 (2-D): rho = X + sgn N_w(d) is formed in LDS for the fine cells
+// the 3x3 stencils of a 32 x 4 coarse tile read, and w, d and rho are
+// restricted into (wc, dc, gc) with the weights and order of mx_restrict_cell.
+// The geometry is that of k_residual_restrict (FP64 path).
+constexpr int kMrCW = 32, kMrCH = 4;
+constexpr int kMrSW = 2 * kMrCW + 3, kMrSH = 2 * kMrCH + 3, kMrRW = 2 * kMrCW + 1, kMrRH = 2 * kMrCH + 1;
+constexpr int kMrThreads = 512;
+
+__global__ __launch_bounds__(kMrThreads) void k_mx_residual_restrict(Phys ph, Lvl32 L, CSoa32 w, CSoa32 d, CSoa32 X,
+                                                                     float sgn, int px, int py, Soa32 wc, Soa32 dc,
+                                                                     Soa32 gc, const int* __restrict__ active)
+{
+    constexpr int NS = kMrSW * kMrSH, NR = kMrRW * kMrRH;
+    __shared__ float sWE[NS], sWFx[NS], sWFy[NS], sWT[NS], sE[NS], sGx[NS], sGy[NS], sT[NS], sXX[NS], sXY[NS],
+        sYY[NS];
+    __shared__ float qE[NR], qFx[NR], qFy[NR], qT[NR];
+    const bool live = active[mx_lane_zero()] != 0;
+    const int nxc = L.nx / 2, nyc = L.ny / 2;
+    const int ntx = (nxc + kMrCW - 1) / kMrCW;
+    const int b = (int)xcd_block();
+    const int I0 = (b % ntx) * kMrCW, J0 = (b / ntx) * kMrCH;
+    const int fi0 = 2 * I0, fj0 = 2 * J0;
+    const float c = (float)ph.c, c2 = (float)ph.c2;
+    for (int q = threadIdx.x; q < NS; q += kMrThreads) {
+        const int gi = fi0 + q % kMrSW - 2, gj = fj0 + q / kMrSW - 2;
+        int si, sj;
+        bool hx, hy, nx_, ny_;
+        rc_axis(gi, L.nx, px != 0, si, hx, nx_);
+        rc_axis(gj, L.ny, py != 0, sj, hy, ny_);
+        float E = 0.0f, Fx = 0.0f, Fy = 0.0f, T = 0.0f, e = 0.0f, gx = 0.0f, gy = 0.0f, t = 0.0f;
+        DP p{0.0f, 0.0f, 0.0f};
+        if (nx_ && ny_ && !(hx && hy)) {
+            const int side = hx ? (gi < 0 ? 0 : 1) : (hy ? (gj < 0 ? 2 : 3) : 0);
+            const uint32_t k = (uint32_t)sj * (uint32_t)L.nx + (uint32_t)si;
+            ghost_inc(ph, side, !(hx || hy), ldf(w.E, k), ldf(w.Fx, k), ldf(w.Fy, k), ldf(d.E, k), ldf(d.Fx, k),
+                      ldf(d.Fy, k), E, Fx, Fy, e, gx, gy);
+            T = ldf(w.T, k);
+            t = ldf(d.T, k);
+            p = closure_inc(c, c2, E, Fx, Fy, e, gx, gy);
+        }
+        sWE[q] = E;
+        sWFx[q] = Fx;
+        sWFy[q] = Fy;
+        sWT[q] = T;
+        sE[q] = e;
+        sGx[q] = gx;
+        sGy[q] = gy;
+        sT[q] = t;
+        sXX[q] = p.xx;
+        sXY[q] = p.xy;
+        sYY[q] = p.yy;
+    }
+    __syncthreads();
+    auto centre = [&](int ri, int rj) {
+        if (fi0 + ri < 0 && !px) ri += 1;
+        if (fj0 + rj < 0 && !py) rj += 1;
+        return (rj + 2) * kMrSW + ri + 2;
+    };
+    for (int q = threadIdx.x; q < NR; q += kMrThreads) {
+        const int ri = q % kMrRW - 1, rj = q / kMrRW - 1;
+        const int gi = fi0 + ri, gj = fj0 + rj;
+        float oE = 0.0f, oFx = 0.0f, oFy = 0.0f, oT = 0.0f;
+        if (gi < L.nx && gj < L.ny) {
+            const int n = centre(ri, rj);
+            const int si = gi < 0 ? (px ? gi + L.nx : 0) : gi, sj = gj < 0 ? (py ? gj + L.ny : 0) : gj;
+            const uint32_t k = (uint32_t)sj * (uint32_t)L.nx + (uint32_t)si;
+            float S0 = 0.0f, S1 = 0.0f, S2 = 0.0f;  // the order of offdiag_inc: x-, x+, y-, y+
+            auto nb = [&](int m, float kk, float sg, bool xdir) {
+                acc_inc(kk, sg, xdir, c, sE[m], sGx[m], sGy[m], DP{sXX[m], sXY[m], sYY[m]}, S0, S1, S2);
+            };
+            nb(n - 1, L.kx, +1.0f, true);
+            nb(n + 1, L.kx, -1.0f, true);
+            nb(n - kMrSW, L.ky, +1.0f, false);
+            nb(n + kMrSW, L.ky, -1.0f, false);
+            float NE, NFx, NFy, NT;
+            n_from_sums(ph, L, S0, S1, S2, sWT[n], sE[n], sGx[n], sGy[n], sT[n], k, NE, NFx, NFy, NT);
+            oE = fmaf(sgn, NE, ldf(X.E, k));
+            oFx = fmaf(sgn, NFx, ldf(X.Fx, k));
+            oFy = fmaf(sgn, NFy, ldf(X.Fy, k));
+            oT = fmaf(sgn, NT, ldf(X.T, k));
+        }
+        qE[q] = oE;
+        qFx[q] = oFx;
+        qFy[q] = oFy;
+        qT[q] = oT;
+    }
+    __syncthreads();
+    if (threadIdx.x >= kMrCW * kMrCH) return;
+    const int ci = threadIdx.x % kMrCW, cj = threadIdx.x / kMrCW, I = I0 + ci, J = J0 + cj;
+    if (I >= nxc || J >= nyc || !live) return;
+    int ix[3], iy[3];
+    float wx[3], wy[3];
+    rweights32(I, L.nx, px != 0, ix, wx);
+    rweights32(J, L.ny, py != 0, iy, wy);
+    auto restrict12 = [&](const float* src, bool staged, float* dst) {
+        float s = 0.0f;
+#pragma unroll
+        for (int bb = 0; bb < 3; ++bb) {
+            float v[3];
+#pragma unroll
+            for (int a = 0; a < 3; ++a)
+                v[a] = staged ? src[centre(2 * ci + a - 1, 2 * cj + bb - 1)] : src[(2 * cj + bb) * kMrRW + 2 * ci + a];
+            const float t = fmaf(wx[2], v[2], fmaf(wx[1], v[1], wx[0] * v[0]));
+            s = fmaf(wy[bb], t, s);
+        }
+        stf(dst, (uint32_t)J * (uint32_t)nxc + (uint32_t)I, s);
+    };
+    restrict12(sWE, true, wc.E);
+    restrict12(sWFx, true, wc.Fx);
+    restrict12(sWFy, true, wc.Fy);
+    restrict12(sWT, true, wc.T);
+    restrict12(sE, true, dc.E);
+    restrict12(sGx, true, dc.Fx);
+    restrict12(sGy, true, dc.Fy);
+    restrict12(sT, true, dc.T);
+    restrict12(qE, false, gc.E);
+    restrict12(qFx, false, gc.Fx);
+    restrict12(qFy, false, gc.Fy);
+    restrict12(qT, false, gc.T);
+}
+
 // Batched staged correction sweep (d given): work-list entries are the 64 x TY
 // tiles of each problem's finest level.
 template <int TY>
@@ -888,6 +1023,16 @@ void launch_mx_sweep(hipStream_t st, int dim, const Phys& ph, const Lvl32& L, CS
         return;
     }
     MX_DISPATCH(dim, k_mx_sweep, nblk((int64_t)L.nx * L.ny), ph, L, w, d, rhs, beta, gamma, omega, out, active);
+}
+
+void launch_mx_residual_restrict(hipStream_t st, const Phys& ph, const Lvl32& L, CSoa32 w, CSoa32 d, CSoa32 X,
+                                 float sgn, int px, int py, Soa32 wc, Soa32 dc, Soa32 gc, const int* active)
+{
+    const int nxc = L.nx / 2, nyc = L.ny / 2;
+    if (nxc < 1 || nyc < 1) return;
+    const unsigned nb = (unsigned)((nxc + kMrCW - 1) / kMrCW) * (unsigned)((nyc + kMrCH - 1) / kMrCH);
+    hipLaunchKernelGGL(k_mx_residual_restrict, dim3(nb), dim3(kMrThreads), 0, st, ph, L, w, d, X, sgn, px, py, wc, dc,
+                       gc, active);
 }
 
 void launch_mx_apply(hipStream_t st, int dim, const Phys& ph, const Lvl32& L, CSoa32 w, CSoa32 d, CSoa32 X, float sgn,

@@ -91,6 +91,37 @@ def test_lds_sweep_matches_one_cell_sweep(nx, ny, bcs):
             np.testing.assert_array_equal(res[rows, omega], res[0, omega])
 
 
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("nx,ny", [(96, 80), (100, 36), (66, 10), (130, 70), (64, 64)])
+@pytest.mark.parametrize("bcs", ["periodic", "mixed", "wall"])
+def test_fused_residual_restriction_matches_two_kernels(nx, ny, bcs, precision):
+    """The finest residual restricted as it is formed (one launch) gives the
+    stored-then-restricted path's cycle to the bit: odd coarse sizes, ragged
+    coarse tiles, periodic wrap and dropped points at every kind of side; one
+    V-cycle and a whole time step."""
+    announce("fused residual/restriction", nx, ny, bcs, precision)
+    kinds = BC_SETS[bcs]
+    prob, v, sig = inputs.random_problem(6, 2, nx, ny, bc_kinds=kinds, cfl=60.0, fmax=0.9)
+    vn = inputs.random_problem(7, 2, nx, ny, bc_kinds=kinds, cfl=60.0, fmax=0.9)[1]
+    old = binding.tune_get("residual_restrict")
+    res = {}
+    try:
+        for on in (0, 1):
+            binding.tune_set("residual_restrict", on)
+            P = plan_for(prob, sig, rtol=1e-10, max_cycles=20000, precision=precision)
+            assert P.levels >= 2
+            vd = to_dev(v)
+            P.vcycle(vd, to_dev(vn), 1e-2)
+            w = to_dev(v)
+            info = P.step(w, 1)
+            res[on] = (to_host(vd), to_host(w), info["cycles"])
+    finally:
+        binding.tune_set("residual_restrict", old)
+    np.testing.assert_array_equal(res[1][0], res[0][0])
+    np.testing.assert_array_equal(res[1][1], res[0][1])
+    assert res[1][2] == res[0][2]
+
+
 @pytest.mark.parametrize("dim,n", [(2, 64), (1, 512)])
 @pytest.mark.parametrize("local", [1, 0])
 def test_pseudo_step_parity(dim, n, local):
