@@ -388,7 +388,7 @@ void vcycle_impl(m1_plan& P, Soa& cur, Soa& other, const Gate& G, bool control =
     const m1_params& p = P.params;
     fine_sweeps(P, cur, other, p.nu0, G, control);
     if (P.L == 1) return;
-    // the finest residual is restricted as it is formed (one launch) unless switched off
+    // residuals are restricted as they are formed (one launch per level) unless switched off
     const bool fused = P.dim == 2 && m1::residual_restrict();
     if (!fused) m1::launch_apply(P.st, P.dim, P.ph, P.lev[0].L, cs(cur), cs(P.b), -1.0, P.rfine, nullptr, G.active);
     std::vector<Soa> ul(P.L);
@@ -404,9 +404,9 @@ void vcycle_impl(m1_plan& P, Soa& cur, Soa& other, const Gate& G, bool control =
     for (int l = 1; l < P.L; ++l) {
         LevelBuf& c = P.lev[l];
         const LevelBuf& f = P.lev[l - 1];
-        if (l == 1 && fused)
-            m1::launch_residual_restrict(P.st, P.ph, f.L, cs(ul[0]), cs(P.b), -1.0, P.px, P.py, c.v,
-                                         tiled[l] ? c.rb : c.f, G.active);
+        if (fused)  // rbar = f - A(u) of level l - 1 (b on the finest) and both restrictions
+            m1::launch_residual_restrict(P.st, P.ph, f.L, cs(ul[l - 1]), l == 1 ? cs(P.b) : cs(f.f), -1.0, P.px,
+                                         P.py, c.v, tiled[l] ? c.rb : c.f, G.active);
         else
             m1::launch_restrict(P.st, P.dim, f.nx, f.ny, P.px, P.py,
                                 fields2(ul[l - 1], rb_prev, c.v, tiled[l] ? c.rb : c.f, P.dim), G.active);
@@ -422,7 +422,7 @@ void vcycle_impl(m1_plan& P, Soa& cur, Soa& other, const Gate& G, bool control =
         } else {
             ul[l] = pseudo_smooth(P, l, G, c.v, true);  // also forms f = A(v) + R(rbar)
         }
-        if (l < P.L - 1) {
+        if (l < P.L - 1 && !fused) {
             m1::launch_apply(P.st, P.dim, P.ph, c.L, cs(ul[l]), cs(c.f), -1.0, c.rb, nullptr, G.active);
             rb_prev = c.rb;
         }
@@ -534,9 +534,10 @@ void mx_vcycle(m1_plan& P, Soa& cur64, Soa& other64, const Gate& G, bool control
     for (int l = 1; l < P.L; ++l) {
         LevelBuf& c = P.lev[l];
         const LevelBuf& fl = P.lev[l - 1];
-        if (l == 1 && fused)
-            m1::launch_mx_residual_restrict(P.st, P.ph, f0.L32, cs(P.base32), cs(d), cs(P.r32), -1.0f, P.px, P.py,
-                                            c.w, c.d, c.gg, G.active);
+        if (fused)  // rho of level l - 1 (r - N(d) on the finest, g - N_w(e) below) and the restrictions
+            m1::launch_mx_residual_restrict(P.st, P.ph, fl.L32, cs(*wprev), cs(el[l - 1]),
+                                            l == 1 ? cs(P.r32) : cs(fl.gg), -1.0f, P.px, P.py, c.w, c.d, c.gg,
+                                            G.active);
         else
             m1::launch_mx_restrict(P.st, P.dim, fl.nx, fl.ny, P.px, P.py,
                                    fields32({{wprev, &c.w}, {&el[l - 1], &c.d}, {rprev, &c.gg}}, P.dim), G.active);
@@ -546,7 +547,7 @@ void mx_vcycle(m1_plan& P, Soa& cur64, Soa& other64, const Gate& G, bool control
             break;
         }
         el[l] = mx_pseudo_smooth(P, l, G, c.d, true);  // forms g = N_w(d) + R(rho)
-        if (l < P.L - 1)
+        if (l < P.L - 1 && !fused)
             m1::launch_mx_apply(P.st, P.dim, P.ph, c.L32, cs(c.w), cs(el[l]), cs(c.gg), -1.0f, c.rho, G.active);
         wprev = &c.w;
         rprev = &c.rho;
