@@ -1207,7 +1207,8 @@ struct m1_engine {
     List fine;
     List fine2;    // 64 x rows tiles of the finest levels for the staged sweep (rows == 0: none)
     int rows = 0;
-    std::vector<List> restr, pdown, up;
+    bool fused = false;     // residuals formed and restricted in one launch per level (lists rr)
+    std::vector<List> restr, pdown, up, rr;
     int n_all = 0, n_tail = 0;
     int Lmax = 1;
     std::vector<uint32_t> hwl, hwl2;
@@ -1471,11 +1472,24 @@ m1_status rebuild(m1_engine& E)
     E.restr.assign(E.Lmax, {});
     E.pdown.assign(E.Lmax, {});
     E.up.assign(E.Lmax, {});
+    E.rr.assign(E.Lmax, {});
+    E.fused = m1::residual_restrict() != 0;
     for (int l = 0; l < E.Lmax; ++l) {
         auto top = [](const m1_plan& P) { return std::min(P.lt, P.L - 1); };
         if (l >= 1) {
             E.restr[l] = make([&](const m1_plan& P) { return l <= top(P); }, l);
             E.pdown[l] = make([&](const m1_plan& P) { return l < P.lt; }, l);
+            if (E.fused) {  // 32 x 4 tiles of level l for the fused residual-restriction
+                E.rr[l].off = (int)E.hwl.size();
+                for (int i = 0; i < np; ++i) {
+                    const m1_plan& P = *E.running[i]->plan;
+                    if (l >= P.L || l > top(P)) continue;
+                    const LevelBuf& lv = P.lev[l];
+                    const uint32_t nt = (uint32_t)((lv.nx + 31) / 32) * (uint32_t)((lv.ny + 3) / 4);
+                    for (uint32_t t = 0; t < nt; ++t) E.hwl.push_back(((uint32_t)i << m1::kTileBits) | t);
+                }
+                E.rr[l].n = (int)E.hwl.size() - E.rr[l].off;
+            }
         }
         E.up[l] = make([&](const m1_plan& P) { return l < top(P); }, l);
     }
@@ -1532,16 +1546,19 @@ void b_vcycle(m1_engine& E)
         if (s == 0) m1::launch_b_norm_control(E.st, E.dP, E.dPL, E.n_all, 0);
         in_x1 ^= 1;
     }
-    m1::launch_b_apply(E.st, E.dP, E.dS, wl + E.up[0].off, E.up[0].n, 0, in_x1);
+    if (!E.fused) m1::launch_b_apply(E.st, E.dP, E.dS, wl + E.up[0].off, E.up[0].n, 0, in_x1);
     for (int l = 1; l < E.Lmax; ++l) {
-        m1::launch_b_restrict(E.st, E.dP, E.dS, wl + E.restr[l].off, E.restr[l].n, l, l == 1 ? in_x1 : 1);
+        if (E.fused)
+            m1::launch_b_residual_restrict(E.st, E.dP, E.dS, wl + E.rr[l].off, E.rr[l].n, l, l == 1 ? in_x1 : 1);
+        else
+            m1::launch_b_restrict(E.st, E.dP, E.dS, wl + E.restr[l].off, E.restr[l].n, l, l == 1 ? in_x1 : 1);
         int in = 0;
         for (int k = 0; k < m; ++k) {
             const int out = (in == 1) ? 2 : 1;
             m1::launch_b_pseudo(E.st, E.dP, E.dS, wl + E.pdown[l].off, E.pdown[l].n, l, in, out, k == 0);
             in = out;
         }
-        m1::launch_b_apply(E.st, E.dP, E.dS, wl + E.up[l].off, E.up[l].n, l, 1);
+        if (!E.fused) m1::launch_b_apply(E.st, E.dP, E.dS, wl + E.up[l].off, E.up[l].n, l, 1);
     }
     m1::launch_b_tail(E.st, E.dP, E.dPL + E.n_all, E.n_tail);
     for (int l = E.Lmax - 2; l >= 0; --l) {
@@ -1585,16 +1602,17 @@ void bm_vcycle(m1_engine& E)
         d = out;
     }
     const int d0 = d;
-    m1::launch_bm_apply(E.st, E.dP, E.dS32, wl + E.up[0].off, E.up[0].n, 0, d0);
+    if (!E.fused) m1::launch_bm_apply(E.st, E.dP, E.dS32, wl + E.up[0].off, E.up[0].n, 0, d0);
     for (int l = 1; l < E.Lmax; ++l) {
-        m1::launch_bm_restrict(E.st, E.dP, E.dS32, wl + E.restr[l].off, E.restr[l].n, l, d0);
+        if (E.fused) m1::launch_bm_residual_restrict(E.st, E.dP, E.dS32, wl + E.rr[l].off, E.rr[l].n, l, d0);
+        else m1::launch_bm_restrict(E.st, E.dP, E.dS32, wl + E.restr[l].off, E.restr[l].n, l, d0);
         int in = 0;
         for (int k = 0; k < m; ++k) {
             const int out = (in == 1) ? 2 : 1;
             m1::launch_bm_pseudo(E.st, E.dP, E.dS32, wl + E.pdown[l].off, E.pdown[l].n, l, in, out, k == 0);
             in = out;
         }
-        m1::launch_bm_apply(E.st, E.dP, E.dS32, wl + E.up[l].off, E.up[l].n, l, 1);
+        if (!E.fused) m1::launch_bm_apply(E.st, E.dP, E.dS32, wl + E.up[l].off, E.up[l].n, l, 1);
     }
     m1::launch_bm_tail(E.st, E.dP, E.dPL + E.n_all, E.n_tail);
     for (int l = E.Lmax - 2; l >= 1; --l) {

@@ -155,6 +155,9 @@ bool launch_relax_lds(hipStream_t st, const Phys& ph, const Lvl& L, CSoa rhs, do
                       const int* active, CSoa uc, CSoa vc, int px, int py, double eta);
 // batched FP64 kernels (m1_kernels.hip); `wl` is a work list of nwl entries,
 // `plist` a list of problem indices
+// fused residual of level - 1 and restriction to `level` over a work list of 32 x 4 coarse tiles
+void launch_b_residual_restrict(hipStream_t st, const BProb* P, const BSlot* S, const uint32_t* wl, int nwl, int level,
+                                int in_sel);
 void launch_b_relax(hipStream_t st, const BProb* P, const BSlot* S, const uint32_t* wl, int nwl, int in_x1, int norm);
 // staged finest-level sweep over a work list of 64 x rows tiles (rows 4, 8 or 16)
 void launch_b_relax_lds(hipStream_t st, const BProb* P, const BSlot* S, const uint32_t* wl, int nwl, int in_x1,
@@ -202,6 +205,9 @@ void launch_bm_resid(hipStream_t st, const BProb* P, const BSlot* S, const BSlot
                      int pend_sel);
 void launch_bm_sweep(hipStream_t st, const BProb* P, const BSlot32* S32, const uint32_t* wl, int nwl, int in_sel,
                      int out_sel, int from_zero);
+// fused residual of level - 1 and restriction to `level` over a work list of 32 x 4 coarse tiles
+void launch_bm_residual_restrict(hipStream_t st, const BProb* P, const BSlot32* S32, const uint32_t* wl, int nwl,
+                                 int level, int d0_sel);
 // staged correction sweep (d given) over a work list of 64 x rows tiles of the finest levels
 void launch_bm_sweep_lds(hipStream_t st, const BProb* P, const BSlot32* S32, const uint32_t* wl, int nwl, int in_sel,
                          int out_sel, int rows);

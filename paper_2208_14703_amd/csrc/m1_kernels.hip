@@ -247,18 +247,21 @@ constexpr int kRrW = 2 * kRcW + 1, kRrH = 2 * kRcH + 1;  // residual offsets -1 
 constexpr int kRcThreads = 512;
 
 
-__global__ __launch_bounds__(kRcThreads) void k_residual_restrict(Phys ph, Lvl L, CSoa u, CSoa X, double sgn, int px,
-                                                                  int py, Soa vc, Soa rc,
-                                                                  const int* __restrict__ active)
+// LDS of one fused residual-restriction tile.
+struct RcLds {
+    static constexpr int NS = kRsW * kRsH, NR = kRrW * kRrH;
+    double sE[NS], sFx[NS], sFy[NS], sT[NS], sXX[NS], sXY[NS], sYY[NS];
+    double qE[NR], qFx[NR], qFy[NR], qT[NR];
+};
+
+// The fused residual and restriction of the coarse tile at (I0, J0) (all
+// threads of the block take part; no thread returns early).
+__device__ __forceinline__ void residual_restrict_tile(RcLds& sm, const Phys& ph, const Lvl& L, const CSoa& u,
+                                                       const CSoa& X, double sgn, int px, int py, const Soa& vc,
+                                                       const Soa& rc, int I0, int J0, bool live)
 {
-    constexpr int NS = kRsW * kRsH, NR = kRrW * kRrH;
-    __shared__ double sE[NS], sFx[NS], sFy[NS], sT[NS], sXX[NS], sXY[NS], sYY[NS];
-    __shared__ double qE[NR], qFx[NR], qFy[NR], qT[NR];
-    const bool live = active[lane_zero()] != 0;
+    constexpr int NS = RcLds::NS, NR = RcLds::NR;
     const int nxc = L.nx / 2, nyc = L.ny / 2;
-    const int ntx = (nxc + kRcW - 1) / kRcW;
-    const int b = (int)xcd_block();
-    const int I0 = (b % ntx) * kRcW, J0 = (b / ntx) * kRcH;
     const int fi0 = 2 * I0, fj0 = 2 * J0;
     for (int q = threadIdx.x; q < NS; q += kRcThreads) {
         const int gi = fi0 + q % kRsW - 2, gj = fj0 + q / kRsW - 2;
@@ -277,13 +280,13 @@ __global__ __launch_bounds__(kRcThreads) void k_residual_restrict(Phys ph, Lvl L
             xy = p_xy(p, fx, fy);
             yy = p_yy(p, fy);
         }
-        sE[q] = e;
-        sFx[q] = fx;
-        sFy[q] = fy;
-        sT[q] = t;
-        sXX[q] = xx;
-        sXY[q] = xy;
-        sYY[q] = yy;
+        sm.sE[q] = e;
+        sm.sFx[q] = fx;
+        sm.sFy[q] = fy;
+        sm.sT[q] = t;
+        sm.sXX[q] = xx;
+        sm.sXY[q] = xy;
+        sm.sYY[q] = yy;
     }
     __syncthreads();
     // staged index of the cell a residual point (fine offsets ri, rj) reads
@@ -301,50 +304,65 @@ __global__ __launch_bounds__(kRcThreads) void k_residual_restrict(Phys ph, Lvl L
             const int si = gi < 0 ? (px ? gi + L.nx : 0) : gi, sj = gj < 0 ? (py ? gj + L.ny : 0) : gj;
             const uint32_t k = (uint32_t)sj * (uint32_t)L.nx + (uint32_t)si;
             double S0 = 0.0, S1 = 0.0, S2 = 0.0;  // the order of offdiag: x-, x+, y-, y+
-            acc_x(L.kx, ph.c, +1.0, sE[c - 1], sFx[c - 1], sFy[c - 1], sXX[c - 1], sXY[c - 1], S0, S1, S2);
-            acc_x(L.kx, ph.c, -1.0, sE[c + 1], sFx[c + 1], sFy[c + 1], sXX[c + 1], sXY[c + 1], S0, S1, S2);
-            acc_y(L.ky, ph.c, +1.0, sE[c - kRsW], sFx[c - kRsW], sFy[c - kRsW], sXY[c - kRsW], sYY[c - kRsW], S0,
-                  S1, S2);
-            acc_y(L.ky, ph.c, -1.0, sE[c + kRsW], sFx[c + kRsW], sFy[c + kRsW], sXY[c + kRsW], sYY[c + kRsW], S0,
-                  S1, S2);
-            apply_values<2>(ph, L, sE[c], sFx[c], sFy[c], sT[c], S0, S1, S2, X, sgn, k, rE, rFx, rFy, rT);
+            acc_x(L.kx, ph.c, +1.0, sm.sE[c - 1], sm.sFx[c - 1], sm.sFy[c - 1], sm.sXX[c - 1], sm.sXY[c - 1], S0, S1,
+                  S2);
+            acc_x(L.kx, ph.c, -1.0, sm.sE[c + 1], sm.sFx[c + 1], sm.sFy[c + 1], sm.sXX[c + 1], sm.sXY[c + 1], S0, S1,
+                  S2);
+            acc_y(L.ky, ph.c, +1.0, sm.sE[c - kRsW], sm.sFx[c - kRsW], sm.sFy[c - kRsW], sm.sXY[c - kRsW],
+                  sm.sYY[c - kRsW], S0, S1, S2);
+            acc_y(L.ky, ph.c, -1.0, sm.sE[c + kRsW], sm.sFx[c + kRsW], sm.sFy[c + kRsW], sm.sXY[c + kRsW],
+                  sm.sYY[c + kRsW], S0, S1, S2);
+            apply_values<2>(ph, L, sm.sE[c], sm.sFx[c], sm.sFy[c], sm.sT[c], S0, S1, S2, X, sgn, k, rE, rFx, rFy, rT);
         }
-        qE[q] = rE;
-        qFx[q] = rFx;
-        qFy[q] = rFy;
-        qT[q] = rT;
+        sm.qE[q] = rE;
+        sm.qFx[q] = rFx;
+        sm.qFy[q] = rFy;
+        sm.qT[q] = rT;
     }
     __syncthreads();
-    if (threadIdx.x >= kRcW * kRcH) return;
     const int ci = threadIdx.x % kRcW, cj = threadIdx.x / kRcW, I = I0 + ci, J = J0 + cj;
-    if (I >= nxc || J >= nyc || !live) return;
-    int ix[3], iy[3];
-    double wx[3], wy[3];
-    rweights(I, L.nx, px != 0, ix, wx);
-    rweights(J, L.ny, py != 0, iy, wy);
-    // fine cell 2I-1+a, 2J-1+b: residual index (2cj+b) kRrW + 2ci+a, staged cell centre(2ci+a-1, 2cj+b-1)
-    auto restrict8 = [&](const double* src, bool staged, double* dst) {
-        double s = 0.0;
+    if (threadIdx.x < kRcW * kRcH && I < nxc && J < nyc && live) {
+        int ix[3], iy[3];
+        double wx[3], wy[3];
+        rweights(I, L.nx, px != 0, ix, wx);
+        rweights(J, L.ny, py != 0, iy, wy);
+        // fine cell 2I-1+a, 2J-1+b: residual index (2cj+b) kRrW + 2ci+a, staged cell centre(2ci+a-1, 2cj+b-1)
+        auto restrict8 = [&](const double* src, bool staged, double* dst) {
+            double s = 0.0;
 #pragma unroll
-        for (int bb = 0; bb < 3; ++bb) {
-            double v[3];
+            for (int bb = 0; bb < 3; ++bb) {
+                double v[3];
 #pragma unroll
-            for (int a = 0; a < 3; ++a)
-                v[a] = staged ? src[centre(2 * ci + a - 1, 2 * cj + bb - 1)] : src[(2 * cj + bb) * kRrW + 2 * ci + a];
-            const double t = fma(wx[2], v[2], fma(wx[1], v[1], wx[0] * v[0]));
-            s = fma(wy[bb], t, s);
-        }
-        st(dst, (uint32_t)J * (uint32_t)nxc + (uint32_t)I, s);
-    };
-    restrict8(sE, true, vc.E);
-    restrict8(sFx, true, vc.Fx);
-    restrict8(sFy, true, vc.Fy);
-    restrict8(sT, true, vc.T);
-    restrict8(qE, false, rc.E);
-    restrict8(qFx, false, rc.Fx);
-    restrict8(qFy, false, rc.Fy);
-    restrict8(qT, false, rc.T);
+                for (int a = 0; a < 3; ++a)
+                    v[a] = staged ? src[centre(2 * ci + a - 1, 2 * cj + bb - 1)]
+                                  : src[(2 * cj + bb) * kRrW + 2 * ci + a];
+                const double t = fma(wx[2], v[2], fma(wx[1], v[1], wx[0] * v[0]));
+                s = fma(wy[bb], t, s);
+            }
+            st(dst, (uint32_t)J * (uint32_t)nxc + (uint32_t)I, s);
+        };
+        restrict8(sm.sE, true, vc.E);
+        restrict8(sm.sFx, true, vc.Fx);
+        restrict8(sm.sFy, true, vc.Fy);
+        restrict8(sm.sT, true, vc.T);
+        restrict8(sm.qE, false, rc.E);
+        restrict8(sm.qFx, false, rc.Fx);
+        restrict8(sm.qFy, false, rc.Fy);
+        restrict8(sm.qT, false, rc.T);
+    }
 }
+
+__global__ __launch_bounds__(kRcThreads) void k_residual_restrict(Phys ph, Lvl L, CSoa u, CSoa X, double sgn, int px,
+                                                                  int py, Soa vc, Soa rc,
+                                                                  const int* __restrict__ active)
+{
+    __shared__ RcLds sm;
+    const bool live = active[lane_zero()] != 0;
+    const int ntx = (L.nx / 2 + kRcW - 1) / kRcW;
+    const int b = (int)xcd_block();
+    residual_restrict_tile(sm, ph, L, u, X, sgn, px, py, vc, rc, (b % ntx) * kRcW, (b / ntx) * kRcH, live);
+}
+
 
 // One pseudo-time step; `first`: also form the FAS right-hand side in f (u = v_l).
 template <int DIM>
@@ -612,6 +630,32 @@ __global__ __launch_bounds__(kTbThreads) void k_smooth_tb(Phys ph, Lvl L, CSoa f
 //   level 0: in_x1 picks x1 (else x0) as the current iterate;
 //   level >= 1: sel 0 = v, 1 = u, 2 = u2.
 __device__ __forceinline__ const Soa& pick(const BSlot& s, int sel) { return sel == 0 ? s.v : (sel == 1 ? s.u : s.u2); }
+
+// Batched: work-list entries are the 32 x 4 coarse tiles of level `level` of
+// each problem; level - 1's residual (b on the finest level, else the FAS
+// right-hand side f) is formed and restricted with the state into (v, f).
+__global__ __launch_bounds__(kRcThreads) void kb_residual_restrict(const BProb* __restrict__ P,
+                                                                   const BSlot* __restrict__ S,
+                                                                   const uint32_t* __restrict__ wl, int nwl,
+                                                                   int level, int in_sel)
+{
+    __shared__ RcLds sm;
+    for (int w_ = blockIdx.x; w_ < nwl; w_ += gridDim.x) {
+        const uint32_t item = wl[w_];
+        const int p = (int)(item >> kTileBits);
+        const uint32_t tile = item & ((1u << kTileBits) - 1u);
+        const BProb& pb = P[p];
+        if (pb.ctrl->active == 0) continue;
+        const BSlot& c = S[p * kMaxLevels + level];
+        const BSlot& f = S[p * kMaxLevels + level - 1];
+        const Soa& u = (level == 1) ? (in_sel ? f.x1 : f.x0) : pick(f, in_sel);
+        const Soa& X = (level == 1) ? f.b : f.f;
+        const uint32_t ntx = (uint32_t)((f.L.nx / 2 + kRcW - 1) / kRcW);
+        residual_restrict_tile(sm, pb.ph, f.L, cs(u), cs(X), -1.0, pb.px, pb.py, c.v, c.f,
+                               (int)(tile % ntx) * kRcW, (int)(tile / ntx) * kRcH, true);
+        __syncthreads();  // the next tile of this block reuses the LDS
+    }
+}
 
 
 // Batched LDS-staged finest-level sweep (no norm): work-list entries are the
@@ -932,6 +976,7 @@ void launch_residual_restrict(hipStream_t st, const Phys& ph, const Lvl& L, CSoa
                        active);
 }
 
+
 void launch_apply(hipStream_t st, int dim, const Phys& ph, const Lvl& L, CSoa v, CSoa X, double sgn, Soa out,
                   double* partials, const int* active)
 {
@@ -953,6 +998,14 @@ static std::atomic<int> g_batch_grid{16384};
 int batch_grid_cap() { return g_batch_grid.load(std::memory_order_relaxed); }
 void set_batch_grid_cap(int cap) { g_batch_grid.store(cap, std::memory_order_relaxed); }
 static unsigned bgrid(int nwl) { return (unsigned)std::max(1, std::min(nwl, batch_grid_cap())); }
+
+void launch_b_residual_restrict(hipStream_t st, const BProb* P, const BSlot* S, const uint32_t* wl, int nwl, int level,
+                                int in_sel)
+{
+    if (nwl > 0)
+        hipLaunchKernelGGL(kb_residual_restrict, dim3(bgrid(nwl)), dim3(kRcThreads), 0, st, P, S, wl, nwl, level,
+                           in_sel);
+}
 
 void launch_b_relax_lds(hipStream_t st, const BProb* P, const BSlot* S, const uint32_t* wl, int nwl, int in_x1,
                         int rows)

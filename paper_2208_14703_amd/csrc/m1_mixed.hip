@@ -711,6 +711,7 @@ __device__ __forceinline__ const Soa32& pick32(const BSlot32& s, int sel)
 {
     return sel == 0 ? s.d : (sel == 1 ? s.e : s.e2);
 }
+
 // Final iterate of level l + 1 as seen by the prolongation into level l: the
 // tail's result or the coarsest level's pre-smoothing (both in e) at the
 // deepest level a problem smooths on the grid, else its post-smoothing (e2).
@@ -766,19 +767,21 @@ constexpr int kMrCW = 32, kMrCH = 4;
 constexpr int kMrSW = 2 * kMrCW + 3, kMrSH = 2 * kMrCH + 3, kMrRW = 2 * kMrCW + 1, kMrRH = 2 * kMrCH + 1;
 constexpr int kMrThreads = 512;
 
-__global__ __launch_bounds__(kMrThreads) void k_mx_residual_restrict(Phys ph, Lvl32 L, CSoa32 w, CSoa32 d, CSoa32 X,
-                                                                     float sgn, int px, int py, Soa32 wc, Soa32 dc,
-                                                                     Soa32 gc, const int* __restrict__ active)
+struct MrLds {
+    static constexpr int NS = kMrSW * kMrSH, NR = kMrRW * kMrRH;
+    float sWE[NS], sWFx[NS], sWFy[NS], sWT[NS], sE[NS], sGx[NS], sGy[NS], sT[NS], sXX[NS], sXY[NS], sYY[NS];
+    float qE[NR], qFx[NR], qFy[NR], qT[NR];
+};
+
+// The fused residual and restriction of the coarse tile at (I0, J0) (all
+// threads of the block take part; no thread returns early).
+__device__ __forceinline__ void mx_residual_restrict_tile(MrLds& sm, const Phys& ph, const Lvl32& L, const CSoa32& w,
+                                                          const CSoa32& d, const CSoa32& X, float sgn, int px, int py,
+                                                          const Soa32& wc, const Soa32& dc, const Soa32& gc, int I0,
+                                                          int J0, bool live)
 {
-    constexpr int NS = kMrSW * kMrSH, NR = kMrRW * kMrRH;
-    __shared__ float sWE[NS], sWFx[NS], sWFy[NS], sWT[NS], sE[NS], sGx[NS], sGy[NS], sT[NS], sXX[NS], sXY[NS],
-        sYY[NS];
-    __shared__ float qE[NR], qFx[NR], qFy[NR], qT[NR];
-    const bool live = active[mx_lane_zero()] != 0;
+    constexpr int NS = MrLds::NS, NR = MrLds::NR;
     const int nxc = L.nx / 2, nyc = L.ny / 2;
-    const int ntx = (nxc + kMrCW - 1) / kMrCW;
-    const int b = (int)xcd_block();
-    const int I0 = (b % ntx) * kMrCW, J0 = (b / ntx) * kMrCH;
     const int fi0 = 2 * I0, fj0 = 2 * J0;
     const float c = (float)ph.c, c2 = (float)ph.c2;
     for (int q = threadIdx.x; q < NS; q += kMrThreads) {
@@ -798,17 +801,17 @@ __global__ __launch_bounds__(kMrThreads) void k_mx_residual_restrict(Phys ph, Lv
             t = ldf(d.T, k);
             p = closure_inc(c, c2, E, Fx, Fy, e, gx, gy);
         }
-        sWE[q] = E;
-        sWFx[q] = Fx;
-        sWFy[q] = Fy;
-        sWT[q] = T;
-        sE[q] = e;
-        sGx[q] = gx;
-        sGy[q] = gy;
-        sT[q] = t;
-        sXX[q] = p.xx;
-        sXY[q] = p.xy;
-        sYY[q] = p.yy;
+        sm.sWE[q] = E;
+        sm.sWFx[q] = Fx;
+        sm.sWFy[q] = Fy;
+        sm.sWT[q] = T;
+        sm.sE[q] = e;
+        sm.sGx[q] = gx;
+        sm.sGy[q] = gy;
+        sm.sT[q] = t;
+        sm.sXX[q] = p.xx;
+        sm.sXY[q] = p.xy;
+        sm.sYY[q] = p.yy;
     }
     __syncthreads();
     auto centre = [&](int ri, int rj) {
@@ -826,57 +829,98 @@ __global__ __launch_bounds__(kMrThreads) void k_mx_residual_restrict(Phys ph, Lv
             const uint32_t k = (uint32_t)sj * (uint32_t)L.nx + (uint32_t)si;
             float S0 = 0.0f, S1 = 0.0f, S2 = 0.0f;  // the order of offdiag_inc: x-, x+, y-, y+
             auto nb = [&](int m, float kk, float sg, bool xdir) {
-                acc_inc(kk, sg, xdir, c, sE[m], sGx[m], sGy[m], DP{sXX[m], sXY[m], sYY[m]}, S0, S1, S2);
+                acc_inc(kk, sg, xdir, c, sm.sE[m], sm.sGx[m], sm.sGy[m], DP{sm.sXX[m], sm.sXY[m], sm.sYY[m]}, S0, S1,
+                        S2);
             };
             nb(n - 1, L.kx, +1.0f, true);
             nb(n + 1, L.kx, -1.0f, true);
             nb(n - kMrSW, L.ky, +1.0f, false);
             nb(n + kMrSW, L.ky, -1.0f, false);
             float NE, NFx, NFy, NT;
-            n_from_sums(ph, L, S0, S1, S2, sWT[n], sE[n], sGx[n], sGy[n], sT[n], k, NE, NFx, NFy, NT);
+            n_from_sums(ph, L, S0, S1, S2, sm.sWT[n], sm.sE[n], sm.sGx[n], sm.sGy[n], sm.sT[n], k, NE, NFx, NFy, NT);
             oE = fmaf(sgn, NE, ldf(X.E, k));
             oFx = fmaf(sgn, NFx, ldf(X.Fx, k));
             oFy = fmaf(sgn, NFy, ldf(X.Fy, k));
             oT = fmaf(sgn, NT, ldf(X.T, k));
         }
-        qE[q] = oE;
-        qFx[q] = oFx;
-        qFy[q] = oFy;
-        qT[q] = oT;
+        sm.qE[q] = oE;
+        sm.qFx[q] = oFx;
+        sm.qFy[q] = oFy;
+        sm.qT[q] = oT;
     }
     __syncthreads();
-    if (threadIdx.x >= kMrCW * kMrCH) return;
     const int ci = threadIdx.x % kMrCW, cj = threadIdx.x / kMrCW, I = I0 + ci, J = J0 + cj;
-    if (I >= nxc || J >= nyc || !live) return;
-    int ix[3], iy[3];
-    float wx[3], wy[3];
-    rweights32(I, L.nx, px != 0, ix, wx);
-    rweights32(J, L.ny, py != 0, iy, wy);
-    auto restrict12 = [&](const float* src, bool staged, float* dst) {
-        float s = 0.0f;
+    if (threadIdx.x < kMrCW * kMrCH && I < nxc && J < nyc && live) {
+        int ix[3], iy[3];
+        float wx[3], wy[3];
+        rweights32(I, L.nx, px != 0, ix, wx);
+        rweights32(J, L.ny, py != 0, iy, wy);
+        auto restrict12 = [&](const float* src, bool staged, float* dst) {
+            float s = 0.0f;
 #pragma unroll
-        for (int bb = 0; bb < 3; ++bb) {
-            float v[3];
+            for (int bb = 0; bb < 3; ++bb) {
+                float v[3];
 #pragma unroll
-            for (int a = 0; a < 3; ++a)
-                v[a] = staged ? src[centre(2 * ci + a - 1, 2 * cj + bb - 1)] : src[(2 * cj + bb) * kMrRW + 2 * ci + a];
-            const float t = fmaf(wx[2], v[2], fmaf(wx[1], v[1], wx[0] * v[0]));
-            s = fmaf(wy[bb], t, s);
-        }
-        stf(dst, (uint32_t)J * (uint32_t)nxc + (uint32_t)I, s);
-    };
-    restrict12(sWE, true, wc.E);
-    restrict12(sWFx, true, wc.Fx);
-    restrict12(sWFy, true, wc.Fy);
-    restrict12(sWT, true, wc.T);
-    restrict12(sE, true, dc.E);
-    restrict12(sGx, true, dc.Fx);
-    restrict12(sGy, true, dc.Fy);
-    restrict12(sT, true, dc.T);
-    restrict12(qE, false, gc.E);
-    restrict12(qFx, false, gc.Fx);
-    restrict12(qFy, false, gc.Fy);
-    restrict12(qT, false, gc.T);
+                for (int a = 0; a < 3; ++a)
+                    v[a] = staged ? src[centre(2 * ci + a - 1, 2 * cj + bb - 1)]
+                                  : src[(2 * cj + bb) * kMrRW + 2 * ci + a];
+                const float t = fmaf(wx[2], v[2], fmaf(wx[1], v[1], wx[0] * v[0]));
+                s = fmaf(wy[bb], t, s);
+            }
+            stf(dst, (uint32_t)J * (uint32_t)nxc + (uint32_t)I, s);
+        };
+        restrict12(sm.sWE, true, wc.E);
+        restrict12(sm.sWFx, true, wc.Fx);
+        restrict12(sm.sWFy, true, wc.Fy);
+        restrict12(sm.sWT, true, wc.T);
+        restrict12(sm.sE, true, dc.E);
+        restrict12(sm.sGx, true, dc.Fx);
+        restrict12(sm.sGy, true, dc.Fy);
+        restrict12(sm.sT, true, dc.T);
+        restrict12(sm.qE, false, gc.E);
+        restrict12(sm.qFx, false, gc.Fx);
+        restrict12(sm.qFy, false, gc.Fy);
+        restrict12(sm.qT, false, gc.T);
+    }
+}
+
+__global__ __launch_bounds__(kMrThreads) void k_mx_residual_restrict(Phys ph, Lvl32 L, CSoa32 w, CSoa32 d, CSoa32 X,
+                                                                     float sgn, int px, int py, Soa32 wc, Soa32 dc,
+                                                                     Soa32 gc, const int* __restrict__ active)
+{
+    __shared__ MrLds sm;
+    const bool live = active[mx_lane_zero()] != 0;
+    const int ntx = (L.nx / 2 + kMrCW - 1) / kMrCW;
+    const int b = (int)xcd_block();
+    mx_residual_restrict_tile(sm, ph, L, w, d, X, sgn, px, py, wc, dc, gc, (b % ntx) * kMrCW, (b / ntx) * kMrCH,
+                              live);
+}
+
+// Batched: work-list entries are the 32 x 4 coarse tiles of level `level` of
+// each problem; level - 1's residual (r32 - N(d) on the finest level, else
+// g - N_w(e)) is formed and restricted with w and the correction into (w, d, g).
+__global__ __launch_bounds__(kMrThreads) void kbm_residual_restrict(const BProb* __restrict__ P,
+                                                                    const BSlot32* __restrict__ S32,
+                                                                    const uint32_t* __restrict__ wl, int nwl,
+                                                                    int level, int d0_sel)
+{
+    __shared__ MrLds sm;
+    for (int w_ = blockIdx.x; w_ < nwl; w_ += gridDim.x) {
+        const uint32_t item = wl[w_];
+        const int p = (int)(item >> kTileBits);
+        const uint32_t tile = item & ((1u << kTileBits) - 1u);
+        const BProb& pb = P[p];
+        if (pb.ctrl->active == 0) continue;
+        const BSlot32& c = S32[p * kMaxLevels + level];
+        const BSlot32& f = S32[p * kMaxLevels + level - 1];
+        const Soa32& w = (level == 1) ? f.base : f.w;
+        const Soa32& d = (level == 1) ? pickA(f, d0_sel) : f.e;
+        const Soa32& X = (level == 1) ? f.r32 : f.g;
+        const uint32_t ntx = (uint32_t)((f.L.nx / 2 + kMrCW - 1) / kMrCW);
+        mx_residual_restrict_tile(sm, pb.ph, f.L, cs(w), cs(d), cs(X), -1.0f, pb.px, pb.py, c.w, c.d, c.g,
+                                  (int)(tile % ntx) * kMrCW, (int)(tile / ntx) * kMrCH, true);
+        __syncthreads();  // the next tile of this block reuses the LDS
+    }
 }
 
 // Batched staged correction sweep (d given): work-list entries are the 64 x TY
@@ -1097,6 +1141,14 @@ void launch_bm_resid(hipStream_t st, const BProb* P, const BSlot* S, const BSlot
 {
     if (nwl > 0) hipLaunchKernelGGL(kbm_resid, dim3(bmgrid(nwl)), dim3(kBlock32), 0, st, P, S, S32, wl, nwl, pend_sel);
 }
+void launch_bm_residual_restrict(hipStream_t st, const BProb* P, const BSlot32* S32, const uint32_t* wl, int nwl,
+                                 int level, int d0_sel)
+{
+    if (nwl > 0)
+        hipLaunchKernelGGL(kbm_residual_restrict, dim3(bmgrid(nwl)), dim3(kMrThreads), 0, st, P, S32, wl, nwl, level,
+                           d0_sel);
+}
+
 void launch_bm_sweep_lds(hipStream_t st, const BProb* P, const BSlot32* S32, const uint32_t* wl, int nwl, int in_sel,
                          int out_sel, int rows)
 {
