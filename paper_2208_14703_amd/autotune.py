@@ -7,8 +7,9 @@ same per-cell arithmetic, and the tuner checks that each candidate reproduces
 the default's result bit for bit. It picks, by coordinate descent on measured
 time (a candidate replaces the library's default only when it is faster by more
 than `margin`, so that timing noise does not move the settings):
-  * sweep_rows: tile rows of the LDS-staged finest-level sweep (0: unstaged);
-  * residual_restrict: the finest residual restricted as it is formed (1) or
+  * sweep_rows, mx_sweep_rows: tile rows of the LDS-staged finest-level
+    sweeps in FP64 and in mixed precision (0: unstaged);
+  * residual_restrict: each level's residual restricted as it is formed (1) or
     stored and restricted by a second launch (0);
   * tail_cells: levels of at most this many cells run in one workgroup;
   * tiled_max_cells: largest level whose smoothing legs run as one LDS-tiled
@@ -16,9 +17,10 @@ than `margin`, so that timing noise does not move the settings):
   * graphs: V-cycles replayed from hipGraph recordings, or enqueued launch by
     launch;
   * batch_grid: most blocks of one batched launch.
-sweep_rows, residual_restrict, tail_cells and tiled_max_cells are timed on one time step of the hot-wall
-problem (side n), batch_grid on the batched engine over `batch` problems of the
-batched workload, graphs on both (sum of the two times).
+sweep_rows, residual_restrict, tail_cells and tiled_max_cells are timed on one
+time step of the hot-wall problem (side n); batch_grid and mx_sweep_rows on the
+batched engine over `batch` problems of the batched workload (in mixed
+precision); graphs on both (sum of the two times).
 With --write the choice is stored in tuning.json beside this file, keyed by the
 device's architecture and compute-unit count (device_key). binding.lib()
 applies it when the library is loaded on a device with that key.
@@ -37,6 +39,7 @@ TUNING_FILE = os.path.join(HERE, "tuning.json")
 
 CANDIDATES = {
     "sweep_rows": [0, 4, 8, 16],
+    "mx_sweep_rows": [0, 4, 8, 16],
     "residual_restrict": [1, 0],
     "tail_cells": [64, 256, 1024],
     "tiled_max_cells": [0, 4096, 16384, 65536, 262144],
@@ -44,8 +47,8 @@ CANDIDATES = {
     "batch_grid": [4096, 16384, 65536],
 }
 # the library's built-in values (what m1_tune_get returns before any setting)
-BUILTIN = {"sweep_rows": 4, "residual_restrict": 1, "tail_cells": 256, "tiled_max_cells": 65536, "graphs": 0,
-           "batch_grid": 16384}
+BUILTIN = {"sweep_rows": 4, "mx_sweep_rows": 4, "residual_restrict": 1, "tail_cells": 256, "tiled_max_cells": 65536,
+           "graphs": 0, "batch_grid": 16384}
 SOLVER = dict(omega=0.8, levels=0, rtol=1e-8, max_cycles=20000)
 
 
@@ -108,7 +111,7 @@ def tune(n: int = 1024, batch: int = 32, reps: int = 9, margin: float = 0.01, ve
         return t, [x.clone() for x in out]
 
     def measure(key):
-        if key == "batch_grid":
+        if key in ("batch_grid", "mx_sweep_rows"):
             return batched()
         if key == "graphs":
             t1, r1 = single()

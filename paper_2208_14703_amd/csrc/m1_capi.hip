@@ -255,6 +255,7 @@ struct Tuning {
     {
         if (const char* e = std::getenv("M1_GRAPHS")) graphs = std::atoll(e) != 0;
         if (const char* e = std::getenv("M1_SWEEP_ROWS")) (void)m1::set_sweep_rows(std::atoi(e));
+        if (const char* e = std::getenv("M1_MX_SWEEP_ROWS")) (void)m1::set_mx_sweep_rows(std::atoi(e));
         if (const char* e = std::getenv("M1_RESIDUAL_RESTRICT")) m1::set_residual_restrict(std::atoi(e));
         if (const char* e = std::getenv("M1_TAIL_CELLS")) tail_cells = std::atoll(e);
         if (const char* e = std::getenv("M1_TILED_MAX_CELLS")) tiled_max_cells = std::atoll(e);
@@ -1110,6 +1111,7 @@ m1_status m1_tune_set(const char* key, int64_t value)
     else if (k == "tiled_max_cells") tuning().tiled_max_cells = value;
     else if (k == "graphs" && value <= 1) tuning().graphs = value;
     else if (k == "sweep_rows" && value <= 16 && m1::set_sweep_rows((int)value)) {}
+    else if (k == "mx_sweep_rows" && value <= 16 && m1::set_mx_sweep_rows((int)value)) {}
     else if (k == "residual_restrict" && value <= 1) m1::set_residual_restrict((int)value);
     else if (k == "batch_grid" && value >= 1 && value <= (int64_t(1) << 24)) m1::set_batch_grid_cap((int)value);
     else return M1_ERR_ARG;
@@ -1124,6 +1126,7 @@ int64_t m1_tune_get(const char* key)
     if (k == "tiled_max_cells") return tuning().tiled_max_cells.load();
     if (k == "graphs") return tuning().graphs.load();
     if (k == "sweep_rows") return m1::sweep_rows();
+    if (k == "mx_sweep_rows") return m1::mx_sweep_rows();
     if (k == "residual_restrict") return m1::residual_restrict();
     if (k == "batch_grid") return m1::batch_grid_cap();
     return -1;
@@ -1458,7 +1461,7 @@ m1_status rebuild(m1_engine& E)
         return L;
     };
     E.fine = make([](const m1_plan&) { return true; }, 0);
-    E.rows = m1::sweep_rows();
+    E.rows = E.mixed ? m1::mx_sweep_rows() : m1::sweep_rows();
     E.fine2 = {};
     E.fine2.off = (int)E.hwl.size();
     if (E.rows > 0) {

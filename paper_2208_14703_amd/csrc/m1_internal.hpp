@@ -141,6 +141,9 @@ void set_batch_grid_cap(int cap);
 // rows of the LDS-staged finest sweep's 64-wide tile (0: one-cell-per-thread sweep)
 int sweep_rows();
 bool set_sweep_rows(int rows);
+// the same for the mixed-precision correction sweeps
+int mx_sweep_rows();
+bool set_mx_sweep_rows(int rows);
 // finest-level residual fused with the restriction to level 1 (launch shape; 0: two kernels)
 int residual_restrict();
 void set_residual_restrict(int on);

@@ -899,6 +899,14 @@ __global__ void kb_gather_ctrl(const BProb* __restrict__ P, int np, Ctrl* __rest
 
 static std::atomic<int> g_sweep_rows{4};
 int sweep_rows() { return g_sweep_rows.load(std::memory_order_relaxed); }
+static std::atomic<int> g_mx_sweep_rows{4};
+int mx_sweep_rows() { return g_mx_sweep_rows.load(std::memory_order_relaxed); }
+bool set_mx_sweep_rows(int rows)
+{
+    if (rows != 0 && rows != 4 && rows != 8 && rows != 16) return false;
+    g_mx_sweep_rows.store(rows, std::memory_order_relaxed);
+    return true;
+}
 bool set_sweep_rows(int rows)
 {
     if (rows != 0 && rows != 4 && rows != 8 && rows != 16) return false;

@@ -1054,7 +1054,7 @@ void launch_mx_resid(hipStream_t st, int dim, const Phys& ph, const Lvl& L, doub
 void launch_mx_sweep(hipStream_t st, int dim, const Phys& ph, const Lvl32& L, CSoa32 w, CSoa32 d, CSoa32 rhs,
                      float beta, float gamma, float omega, Soa32 out, const int* active)
 {
-    const int rows = sweep_rows();
+    const int rows = mx_sweep_rows();
     if (dim == 2 && d.E && rows > 0) {
         const unsigned ntx = (unsigned)((L.nx + kMxTX - 1) / kMxTX), nty = (unsigned)((L.ny + rows - 1) / rows);
         const dim3 gl(ntx * nty), bl(kMxTX * rows);
