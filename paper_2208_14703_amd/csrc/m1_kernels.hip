@@ -1,12 +1,15 @@
 // m1_kernels.hip -- stencil kernels of the implicit M1 multigrid (gfx950).
 //
-// Grid kernels run one thread per cell (256-thread blocks = 4 wave64s) over a
-// 1-D launch in the XCD-aware block order of m1::xcd_block(); cell (i,j) =
-// (t % nx, t / nx).  Fields are SoA FP64 arrays.  The work is a memory-bound
-// nonlinear 5-point stencil: no MFMA.  The per-cell bodies are __device__
-// functions shared by the grid kernels and by k_tail, which runs the whole
-// bottom of the V-cycle (every level small enough for one workgroup) in a
-// single launch with block barriers between the phases.
+// One-cell kernels run one thread per cell (256-thread blocks = 4 wave64s)
+// over a 1-D launch in the XCD-aware block order of m1::xcd_block(); cell
+// (i,j) = (t % nx, t / nx).  LDS-staged kernels (k_relax_lds, k_apply_lds,
+// k_residual_restrict) own 2-D tiles and evaluate each point's closure once;
+// k_smooth_tb runs a whole smoothing leg of a small level per launch.  Fields
+// are SoA FP64 arrays.  The work is a memory-bound nonlinear 5-point stencil:
+// no MFMA.  The per-cell bodies are __device__ functions shared by all these
+// kernels, the batched kernels and k_tail, which runs the whole bottom of the
+// V-cycle (every level small enough for one workgroup) in a single launch
+// with block barriers between the phases.
 //
 // Cycle kernels take a device flag `active` (no effect when it is 0) and a
 // device pseudo-time step `dtau_dev` (both always valid pointers), so that

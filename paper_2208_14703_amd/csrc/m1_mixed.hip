@@ -5,8 +5,10 @@
 //                FP64 admissibility projection, then r = b - A(v) in FP64 (the
 //                stopping norm), FP32 copies of the new base state and of r;
 //   k_mx_sweep   relaxed Jacobi sweeps on the correction d: D(v+d') - D(v) =
-//                r + S(v+d) - S(v);
-//   k_mx_apply   residual of the correction equation, rho = r - N_v(d);
+//                r + S(v+d) - S(v) (LDS-staged form k_mx_sweep_lds);
+//   k_mx_residual_restrict  residual of the correction equation,
+//                rho = r - N_v(d), restricted with v and d to level 1 as it is
+//                formed (k_mx_apply + k_mx_restrict when switched off);
 //   k_mx_prolong_fine  d += P(e - d_c) with the admissibility test of v + d in FP64.
 // Coarse levels carry a base w_l = R(w_{l-1}), a correction e_l and the
 // right-hand side g_l = N_w(R d) + R(rho) of the FAS correction equation
