@@ -25,17 +25,27 @@ import csv
 import glob
 import hashlib
 import os
+import re
 import sys
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 KERNEL_SOURCES = ["m1_kernels.hip", "m1_cells.hpp", "m1_device.hpp", "m1_internal.hpp"]
 
 
-def sources_hash() -> str:
+def code_only(text: str) -> str:
+    """C++ source without comments and whitespace (what the compiler sees of the kernels)."""
+    text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", " ", text)
+    return re.sub(r"\s+", "", text)
+
+
+def sources_hash(read=None) -> str:
+    """Hash of the kernel sources' code (comments and layout excluded)."""
     h = hashlib.sha256()
     for s in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, "paper_2208_14703_amd", "csrc", s), "rb") as f:
-            h.update(f.read())
+        path = os.path.join(ROOT, "paper_2208_14703_amd", "csrc", s)
+        text = read(s) if read else open(path, encoding="utf-8").read()
+        h.update(code_only(text).encode())
     return h.hexdigest()[:16]
 
 
