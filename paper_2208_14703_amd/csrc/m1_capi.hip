@@ -788,12 +788,9 @@ static m1_status plan_setup(const m1_grid* g, const m1_params* p, const m1_opaci
     ta.reach = P->reach;
     ta.eta = p->eta;
     P->mixed = p->precision == M1_MIXED;
-    {
-        const char* e = std::getenv("M1_TILED");
-        P->tiled = p->nu_l == 1 && !(e && e[0] == '0');
-        P->tiled_max = tiled_max_cells();
-        P->graphs = use_graphs();
-    }
+    P->tiled = p->nu_l == 1;  // the tiled legs fuse exactly one Jacobi sweep per pseudo-time step
+    P->tiled_max = tiled_max_cells();
+    P->graphs = use_graphs();
     const bool tail_ok = P->L <= m1::kMaxLevels && p->nu_l == 1;
     if (!tail_ok) P->lt = P->L;  // the tail fuses exactly one Jacobi sweep per pseudo-time step
     for (int l = 0; l < P->L && l < m1::kMaxLevels; ++l) {

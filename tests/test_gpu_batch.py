@@ -70,6 +70,37 @@ def test_batch_matches_alone(precision, arena):
         np.testing.assert_array_equal(to_host(vd), ref)
 
 
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_batch_ragged_shapes_match_alone(precision):
+    """Sides that are not multiples of the tile shapes (64 x rows for the
+    staged sweeps, 32 x 4 coarse cells for the fused residual-restriction),
+    odd coarse levels and every kind of side, batched together: each request
+    equals its solo solve to the bit."""
+    announce("batch ragged shapes", precision)
+    params = dict(PARAMS, precision=precision)
+    shapes = [(100, 36), (66, 10), (130, 70), (96, 80), (200, 28), (36, 132)]
+    kinds = [("periodic",) * 4, ("dirichlet", "reflective", "neumann", "reflective"),
+             ("dirichlet", "neumann", "periodic", "periodic"), ("reflective",) * 4]
+    cases = []
+    for k, (nx, ny) in enumerate(shapes):
+        prob, v, sig = inputs.random_problem(700 + k, 2, nx, ny, bc_kinds=kinds[k % len(kinds)], cfl=80.0,
+                                             log10_sa=(-3, 3), fmax=0.9, block=4)
+        cases.append((prob, v, sig, 1 + k % 2))
+    need = sum(binding.Engine.request_bytes(p, params) for p, _, _, _ in cases)
+    E = binding.Engine(need + (16 << 20), params, max_requests=16)
+    states, tickets = [], []
+    for prob, v, sig, ns in cases:
+        vd = to_dev(v)
+        states.append(vd)
+        tickets.append(E.submit(prob, to_dev(sig), vd, ns))
+    infos = [E.wait(t) for t in tickets]
+    for (prob, v, sig, ns), vd, info in zip(cases, states, infos):
+        ref, info_a = alone(prob, v, sig, ns, params)
+        assert info["status"] == 0 and info_a["status"] == 0
+        assert info["cycles"] == info_a["cycles"]
+        np.testing.assert_array_equal(to_host(vd), ref)
+
+
 def test_batch_budget_cancel_and_arguments():
     announce("batch: budget / cancel / args")
     E = binding.Engine(32 << 20, PARAMS, max_requests=8)

@@ -337,7 +337,7 @@ def test_deterministic():
 
 
 @pytest.mark.parametrize("bcs", ["periodic", "mixed", "wall"])
-def test_tiled_smoothing_legs_match_one_step_kernels(bcs, monkeypatch):
+def test_tiled_smoothing_legs_match_one_step_kernels(bcs):
     """The LDS-tiled smoothing legs give the one-step kernels' results to the
     bit.  96x64 is not a power of two and its 48x32 level is tiled while 24x16
     is not (12x8 runs in the tail); every kind of side.  The solution also
@@ -345,16 +345,20 @@ def test_tiled_smoothing_legs_match_one_step_kernels(bcs, monkeypatch):
     announce("tiled legs", bcs)
     prob, v, sig = inputs.random_problem(21, 2, 96, 64, bc_kinds=BC_SETS[bcs], cfl=50.0, block=8)
     res = {}
-    for tiled in ("1", "0"):
-        monkeypatch.setenv("M1_TILED", tiled)
-        P = plan_for(prob, sig, rtol=1e-12, max_cycles=20000)
-        assert P.level_dims(1) == (48, 32)
-        vd = to_dev(v)
-        info = P.step(vd, 2)
-        assert info["status"] == 0
-        res[tiled] = (to_host(vd), info)
-    np.testing.assert_array_equal(res["1"][0], res["0"][0])
-    assert res["1"][1]["cycles"] == res["0"][1]["cycles"]
+    old = binding.tune_get("tiled_max_cells")
+    try:
+        for tiled in (65536, 0):
+            binding.tune_set("tiled_max_cells", tiled)
+            P = plan_for(prob, sig, rtol=1e-12, max_cycles=20000)
+            assert P.level_dims(1) == (48, 32)
+            vd = to_dev(v)
+            info = P.step(vd, 2)
+            assert info["status"] == 0
+            res[tiled] = (to_host(vd), info)
+    finally:
+        binding.tune_set("tiled_max_cells", old)
+    np.testing.assert_array_equal(res[65536][0], res[0][0])
+    assert res[65536][1]["cycles"] == res[0][1]["cycles"]
     ref, info_o = oracle.Oracle(prob, sig).step(v, 2, oracle_params(rtol=1e-12, max_cycles=20000))
     assert info_o["status"] == 0
-    assert rel_err(res["1"][0], ref, prob["c"]) <= 1e-9
+    assert rel_err(res[65536][0], ref, prob["c"]) <= 1e-9
