@@ -1160,7 +1160,9 @@ struct m1_req {
     m1_params params{};
     m1_opacity op{};
     m1_state v{};
-    int nsteps = 0, steps_done = 0, cycles = 0, state = REQ_PENDING;
+    // state, status, progress, levels and times are read by clients (poll, wait,
+    // times) from other threads: they are written under the engine's qmu
+    int nsteps = 0, steps_done = 0, cycles = 0, state = REQ_PENDING, levels = 0;
     m1_status status = M1_OK;
     double rel = 0.0, r0 = 0.0, dtau = 0.0;
     size_t ws_off = 0, ws_bytes = 0;
@@ -1288,8 +1290,6 @@ bool batch_compatible(const m1_engine& E, const m1_grid* g, const m1_params* p)
 
 void finish(m1_engine& E, m1_req* R, m1_status st)
 {
-    R->status = st;
-    R->t_done = now_s();
     if (R->plan) {
         m1_plan_destroy(R->plan);
         R->plan = nullptr;
@@ -1301,6 +1301,8 @@ void finish(m1_engine& E, m1_req* R, m1_status st)
     pool_free(E, R->ws_off, R->ws_bytes);
     {
         std::lock_guard<std::mutex> g(E.qmu);
+        R->status = st;
+        R->t_done = now_s();
         R->state = REQ_DONE;
     }
     E.done_cv.notify_all();
@@ -1348,10 +1350,11 @@ void admit(m1_engine& E)
             finish(E, R, ok ? M1_ERR_ARG : M1_ERR_DEVICE);
             continue;
         }
-        R->t_admit = now_s();
         R->need_init = true;
         {
             std::lock_guard<std::mutex> g(E.qmu);
+            R->t_admit = now_s();
+            R->levels = R->plan->L;
             R->state = REQ_RUNNING;
         }
         E.running.push_back(R);
@@ -1804,29 +1807,28 @@ m1_status m1_batch_run(m1_engine* E, int32_t cycles, int32_t* n_running, int32_t
             m1_req* R = E->running[i];
             if (!R) continue;
             const m1::Ctrl& h = E->hCtrl[i];
-            bool cancel;
-            {
-                std::lock_guard<std::mutex> g(E->qmu);
-                cancel = R->cancel;
-            }
-            if (!h.active || cancel) {
-                R->cycles += std::max(h.cycles, 0);
-                R->rel = h.rel;
-                R->r0 = h.r0;
-                R->dtau = h.dtau;
-            }
             m1_status out = M1_OK;
             bool leaves = false;
-            if (cancel) {
-                out = M1_ERR_BUSY;
-                leaves = true;
-            } else if (!h.active && !h.conv) {
-                out = M1_ERR_NO_CONVERGENCE;
-                leaves = true;
-            } else if (!h.active) {
-                R->steps_done += 1;
-                leaves = R->steps_done >= R->nsteps;
-                if (!leaves) R->need_init = true;
+            {
+                std::lock_guard<std::mutex> g(E->qmu);
+                const bool cancel = R->cancel;
+                if (!h.active || cancel) {
+                    R->cycles += std::max(h.cycles, 0);
+                    R->rel = h.rel;
+                    R->r0 = h.r0;
+                    R->dtau = h.dtau;
+                }
+                if (cancel) {
+                    out = M1_ERR_BUSY;
+                    leaves = true;
+                } else if (!h.active && !h.conv) {
+                    out = M1_ERR_NO_CONVERGENCE;
+                    leaves = true;
+                } else if (!h.active) {
+                    R->steps_done += 1;
+                    leaves = R->steps_done >= R->nsteps;
+                    if (!leaves) R->need_init = true;
+                }
             }
             if (leaves) {
                 done.push_back({i, out});
@@ -1877,7 +1879,7 @@ m1_status m1_batch_poll(m1_engine* E, uint64_t ticket, m1_info* info)
         std::memset(info, 0, sizeof(*info));
         info->cycles = R->cycles;
         info->status = R->status;
-        info->levels = R->plan ? R->plan->L : 0;
+        info->levels = R->levels;
         info->steps_done = R->steps_done;
         info->r0 = R->r0;
         info->rel_residual = R->rel;

@@ -192,6 +192,48 @@ def test_serving_loop_matches_alone(precision):
 
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_serving_concurrent_clients(precision):
+    """Four client threads submit and wait at the same time while the
+    library's serving thread runs rounds (submit, poll and wait enter the
+    library from several threads at once; ctypes releases the GIL).  Every
+    request finishes and equals its solo solve, bitwise."""
+    import threading
+    announce("serving, concurrent clients", precision)
+    params = dict(PARAMS, precision=precision)
+    cases = problems(12)
+    need = max(binding.Engine.request_bytes(p, params) for p, _, _, _ in cases)
+    E = binding.Engine(int(3.5 * need) + (2 << 20), params, max_requests=64)
+    devs = [(to_dev(sig), to_dev(v)) for _, v, sig, _ in cases]
+    results, errors = [None] * len(cases), []
+
+    def client(idx):
+        try:
+            for k in idx:
+                prob, _, _, ns = cases[k]
+                t = E.submit(prob, devs[k][0], devs[k][1], ns)
+                time.sleep(0.002)
+                results[k] = E.wait(t)
+        except Exception as exc:  # reported by the main thread
+            errors.append(exc)
+
+    E.serve_start(2)
+    threads = [threading.Thread(target=client, args=(list(range(c, len(cases), 4)),), daemon=True) for c in range(4)]
+    for th in threads:
+        th.start()
+    for th in threads:
+        th.join(timeout=120)
+    alive = [th.is_alive() for th in threads]
+    E.serve_stop()
+    assert not errors, errors
+    assert not any(alive)
+    for k, (prob, v, sig, ns) in enumerate(cases):
+        ref, info_a = alone(prob, v, sig, ns, params)
+        assert results[k]["status"] == 0 and results[k]["steps_done"] == ns
+        assert results[k]["cycles"] == info_a["cycles"]
+        np.testing.assert_array_equal(to_host(devs[k][1]), ref)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
 def test_launch_shape_settings_do_not_change_results(precision):
     """The autotuner's settings (m1_tune_set) only move work between launches:
     a plain solve with the tail and tiled bounds moved across its levels, and a
