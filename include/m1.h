@@ -184,13 +184,18 @@ m1_status m1_sync(m1_plan* plan);
 
 /* ---- launch-shape settings ----------------------------------------------------
  * Process-wide settings of how the cycle is launched (environment variables
- * M1_SWEEP_ROWS, M1_MX_SWEEP_ROWS, M1_RESIDUAL_RESTRICT, M1_TAIL_CELLS,
+ * M1_SWEEP_ROWS, M1_PAIR_ROWS, M1_MX_SWEEP_ROWS, M1_RESIDUAL_RESTRICT, M1_TAIL_CELLS,
  * M1_TILED_MAX_CELLS, M1_GRAPHS, M1_BATCH_GRID give the initial values).  None of them changes any result: every launch
  * shape runs the same per-cell arithmetic.  Keys:
  *   "sweep_rows"       rows of the 64-wide tile of the LDS-staged finest-level
  *                      Jacobi sweep (2-D sweeps without the norm; 4, 8 or 16),
  *                      0 = one cell per thread without LDS (default 4; read at
  *                      each launch; engines read it when their tables are built);
+ *   "pair_rows"        rows of the 64-wide tile of the kernel that runs two
+ *                      consecutive finest-level sweeps of a cycle (2-D, without
+ *                      the norm) in one launch, the first sweep's iterate kept
+ *                      in LDS (4, 8 or 16); 0 = each sweep its own launch
+ *                      (default 8; read at each launch);
  *   "mx_sweep_rows"    the same for the mixed-precision correction sweeps;
  *   "residual_restrict" 1: the finest-level residual of a cycle is restricted
  *                      to level 1 as it is formed, in one launch (2-D);

@@ -9,6 +9,8 @@ time (a candidate replaces the library's default only when it is faster by more
 than `margin`, so that timing noise does not move the settings):
   * sweep_rows, mx_sweep_rows: tile rows of the LDS-staged finest-level
     sweeps in FP64 and in mixed precision (0: unstaged);
+  * pair_rows: tile rows of the FP64 kernel running two finest-level sweeps
+    in one launch (0: one launch per sweep);
   * residual_restrict: each level's residual restricted as it is formed (1) or
     stored and restricted by a second launch (0);
   * tail_cells: levels of at most this many cells run in one workgroup;
@@ -17,7 +19,7 @@ than `margin`, so that timing noise does not move the settings):
   * graphs: V-cycles replayed from hipGraph recordings, or enqueued launch by
     launch;
   * batch_grid: most blocks of one batched launch.
-sweep_rows, residual_restrict, tail_cells and tiled_max_cells are timed on one
+sweep_rows, pair_rows, residual_restrict, tail_cells and tiled_max_cells are timed on one
 time step of the hot-wall problem (side n); batch_grid and mx_sweep_rows on the
 batched engine over `batch` problems of the batched workload (in mixed
 precision); graphs on both (sum of the two times).
@@ -39,6 +41,7 @@ TUNING_FILE = os.path.join(HERE, "tuning.json")
 
 CANDIDATES = {
     "sweep_rows": [0, 4, 8, 16],
+    "pair_rows": [0, 4, 8, 16],
     "mx_sweep_rows": [0, 4, 8, 16],
     "residual_restrict": [1, 0],
     "tail_cells": [64, 256, 1024],
@@ -47,7 +50,7 @@ CANDIDATES = {
     "batch_grid": [4096, 16384, 65536],
 }
 # the library's built-in values (what m1_tune_get returns before any setting)
-BUILTIN = {"sweep_rows": 4, "mx_sweep_rows": 4, "residual_restrict": 1, "tail_cells": 256, "tiled_max_cells": 65536,
+BUILTIN = {"sweep_rows": 4, "pair_rows": 8, "mx_sweep_rows": 4, "residual_restrict": 1, "tail_cells": 256, "tiled_max_cells": 65536,
            "graphs": 0, "batch_grid": 16384}
 SOLVER = dict(omega=0.8, levels=0, rtol=1e-8, max_cycles=20000)
 

@@ -131,7 +131,7 @@ def lib():
     return _lib
 
 
-TUNE_ENV = {"sweep_rows": "M1_SWEEP_ROWS", "mx_sweep_rows": "M1_MX_SWEEP_ROWS",
+TUNE_ENV = {"sweep_rows": "M1_SWEEP_ROWS", "pair_rows": "M1_PAIR_ROWS", "mx_sweep_rows": "M1_MX_SWEEP_ROWS",
             "residual_restrict": "M1_RESIDUAL_RESTRICT", "tail_cells": "M1_TAIL_CELLS",
             "tiled_max_cells": "M1_TILED_MAX_CELLS", "graphs": "M1_GRAPHS", "batch_grid": "M1_BATCH_GRID"}
 

@@ -255,6 +255,7 @@ struct Tuning {
     {
         if (const char* e = std::getenv("M1_GRAPHS")) graphs = std::atoll(e) != 0;
         if (const char* e = std::getenv("M1_SWEEP_ROWS")) (void)m1::set_sweep_rows(std::atoi(e));
+        if (const char* e = std::getenv("M1_PAIR_ROWS")) (void)m1::set_pair_rows(std::atoi(e));
         if (const char* e = std::getenv("M1_MX_SWEEP_ROWS")) (void)m1::set_mx_sweep_rows(std::atoi(e));
         if (const char* e = std::getenv("M1_RESIDUAL_RESTRICT")) m1::set_residual_restrict(std::atoi(e));
         if (const char* e = std::getenv("M1_TAIL_CELLS")) tail_cells = std::atoll(e);
@@ -325,12 +326,19 @@ Gate fixed_gate(m1_plan& P, double dtau)
 void fine_sweeps(m1_plan& P, Soa& cur, Soa& other, int nu, const Gate& G, bool control = false)
 {
     const LevelBuf& f = P.lev[0];
-    for (int s = 0; s < nu; ++s) {
+    for (int s = 0; s < nu;) {
         const bool norm = control && s == 0;
+        if (!norm && nu - s >= 2 && P.dim == 2 &&
+            m1::launch_relax2_lds(P.st, P.ph, f.L, cs(P.b), P.params.omega, cs(cur), other, G.active)) {
+            std::swap(cur, other);  // two sweeps, one launch
+            s += 2;
+            continue;
+        }
         m1::launch_relax(P.st, P.dim, P.ph, f.L, cs(P.b), nullptr, 0.0, 1.0, P.params.omega, cs(cur), other,
                          norm ? P.partials : nullptr, G.active);
         if (norm) m1::launch_norm_control(P.st, P.partials, P.npart, P.dctrl);
         std::swap(cur, other);
+        ++s;
     }
 }
 
@@ -1108,6 +1116,7 @@ m1_status m1_tune_set(const char* key, int64_t value)
     else if (k == "tiled_max_cells") tuning().tiled_max_cells = value;
     else if (k == "graphs" && value <= 1) tuning().graphs = value;
     else if (k == "sweep_rows" && value <= 16 && m1::set_sweep_rows((int)value)) {}
+    else if (k == "pair_rows" && value <= 16 && m1::set_pair_rows((int)value)) {}
     else if (k == "mx_sweep_rows" && value <= 16 && m1::set_mx_sweep_rows((int)value)) {}
     else if (k == "residual_restrict" && value <= 1) m1::set_residual_restrict((int)value);
     else if (k == "batch_grid" && value >= 1 && value <= (int64_t(1) << 24)) m1::set_batch_grid_cap((int)value);
@@ -1123,6 +1132,7 @@ int64_t m1_tune_get(const char* key)
     if (k == "tiled_max_cells") return tuning().tiled_max_cells.load();
     if (k == "graphs") return tuning().graphs.load();
     if (k == "sweep_rows") return m1::sweep_rows();
+    if (k == "pair_rows") return m1::pair_rows();
     if (k == "mx_sweep_rows") return m1::mx_sweep_rows();
     if (k == "residual_restrict") return m1::residual_restrict();
     if (k == "batch_grid") return m1::batch_grid_cap();

@@ -18,11 +18,12 @@ namespace m1 {
 // B = b + S(u) is formed for the update anyway.
 // The update of relax_cell from the cell's off-diagonal sum S and its own
 // state: u.T is Tin, the other components come from cen(0..2) (E, Fx, Fy),
-// called only where needed.  Shared by every form of the sweep.
+// called only where needed.  relax_values returns the new state, relax_update
+// stores it at k of out.  Shared by every form of the sweep.
 template <int DIM, bool NORM, class Cen>
-__device__ __forceinline__ double relax_update(const Phys& ph, const Lvl& L, const CSoa& rhs, double g, double beta,
+__device__ __forceinline__ double relax_values(const Phys& ph, const Lvl& L, const CSoa& rhs, double g, double beta,
                                                double omega, double S0, double S1, double S2, double Tin, Cen cen,
-                                               const Soa& out, uint32_t k)
+                                               uint32_t k, double& E, double& Fx, double& Fy, double& T)
 {
     const double BE = fma(g, S0, ld(rhs.E, k));
     const double BFx = fma(g, S1, ld(rhs.Fx, k));
@@ -41,7 +42,6 @@ __device__ __forceinline__ double relax_update(const Phys& ph, const Lvl& L, con
         const double rT = BT - fma(ph.c_v, Tin, -ex);
         q = fma(rE, rE, fma(rFx, rFx, fma(rFy, rFy, rT * rT)));
     }
-    double E, Fx, Fy, T;
     local_solve(beta, g, L.a, ka, ks, ph.c_v, ph.a_r, BE, BFx, BFy, BT, Tin, E, Fx, Fy, T);
     if (omega != 1.0) {
         const double Ein = cen(0), Fxin = cen(1);
@@ -53,6 +53,16 @@ __device__ __forceinline__ double relax_update(const Phys& ph, const Lvl& L, con
         }
         T = fma(omega, T - Tin, Tin);
     }
+    return q;
+}
+
+template <int DIM, bool NORM, class Cen>
+__device__ __forceinline__ double relax_update(const Phys& ph, const Lvl& L, const CSoa& rhs, double g, double beta,
+                                               double omega, double S0, double S1, double S2, double Tin, Cen cen,
+                                               const Soa& out, uint32_t k)
+{
+    double E, Fx, Fy, T;
+    const double q = relax_values<DIM, NORM>(ph, L, rhs, g, beta, omega, S0, S1, S2, Tin, cen, k, E, Fx, Fy, T);
     st(out.E, k, E);
     st(out.Fx, k, Fx);
     if (DIM == 2) st(out.Fy, k, Fy);

@@ -141,6 +141,9 @@ void set_batch_grid_cap(int cap);
 // rows of the LDS-staged finest sweep's 64-wide tile (0: one-cell-per-thread sweep)
 int sweep_rows();
 bool set_sweep_rows(int rows);
+// rows of the 64-wide tile of the fused pair of finest sweeps (0: sweeps launched one by one)
+int pair_rows();
+bool set_pair_rows(int rows);
 // the same for the mixed-precision correction sweeps
 int mx_sweep_rows();
 bool set_mx_sweep_rows(int rows);
@@ -156,6 +159,10 @@ void launch_residual_restrict(hipStream_t st, const Phys& ph, const Lvl& L, CSoa
 // staged sweep is switched off.
 bool launch_relax_lds(hipStream_t st, const Phys& ph, const Lvl& L, CSoa rhs, double omega, CSoa u, Soa out,
                       const int* active, CSoa uc, CSoa vc, int px, int py, double eta);
+// two finest-level sweeps (2-D, beta = 0, gamma = 1, no norm) in one launch, u -> out
+// (distinct buffers); false (nothing launched) when the fused pair is switched off
+bool launch_relax2_lds(hipStream_t st, const Phys& ph, const Lvl& L, CSoa rhs, double omega, CSoa u, Soa out,
+                       const int* active);
 // batched FP64 kernels (m1_kernels.hip); `wl` is a work list of nwl entries,
 // `plist` a list of problem indices
 // fused residual of level - 1 and restriction to `level` over a work list of 32 x 4 coarse tiles

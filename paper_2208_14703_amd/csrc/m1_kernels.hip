@@ -235,6 +235,167 @@ __global__ __launch_bounds__(kLdsTX * TY) void k_apply_lds(Phys ph, Lvl L, CSoa 
 }
 
 // ---------------------------------------------------------------------------
+// Two finest-level Jacobi sweeps in one launch (temporal blocking).  A block
+// owns a 64 x TY tile of final cells.  It stages the states of the tile and of
+// a two-cell halo (with closures), runs the first sweep on the tile and its
+// one-cell ring, puts the ring points outside the domain through the boundary
+// rule of the cell they border, and runs the second sweep on the tile from
+// there.  The intermediate iterate never goes to memory: against two launches
+// this saves one read and one write of the state, of the right-hand side and
+// of the opacities per cell, for about 14 % more closures and sweeps (the
+// ring).  Every point's arithmetic is that of k_relax_lds, so the result is
+// the same to the bit as two sweeps of it.
+//
+// Which points are needed: the second sweep needs the first sweep's iterate on
+// the final cells and their four neighbours (a "plus" around the tile); the
+// first sweep needs the staged state on those and on their neighbours.  Points
+// off the domain on a periodic side are the periodic images (real cells, swept
+// like any other); on another side only the first layer exists, as a ghost of
+// the cell it borders (rc_axis).
+template <int TY>
+struct Lds2 {
+    static constexpr int W2 = kLdsTX + 4, N2 = W2 * (TY + 4);  // staged state: tile + 2-cell halo
+    static constexpr int W1 = kLdsTX + 2, N1 = W1 * (TY + 2);  // first sweep's iterate: tile + ring
+    double buf[6 * N2];  // E, Fx, Fy, XX, XY, YY; the iterate's arrays overwrite the staged ones
+};
+
+// Off-diagonal sum of the point at index c of a W-wide LDS region with arrays
+// f[0..5] = E, Fx, Fy, XX, XY, YY, in the order of tile_sums.
+template <int W>
+__device__ __forceinline__ void lds_sums(const double* const* f, const Lvl& L, double c_light, int c, double& S0,
+                                         double& S1, double& S2)
+{
+    S0 = S1 = S2 = 0.0;
+    acc_x(L.kx, c_light, +1.0, f[0][c - 1], f[1][c - 1], f[2][c - 1], f[3][c - 1], f[4][c - 1], S0, S1, S2);
+    acc_x(L.kx, c_light, -1.0, f[0][c + 1], f[1][c + 1], f[2][c + 1], f[3][c + 1], f[4][c + 1], S0, S1, S2);
+    acc_y(L.ky, c_light, +1.0, f[0][c - W], f[1][c - W], f[2][c - W], f[4][c - W], f[5][c - W], S0, S1, S2);
+    acc_y(L.ky, c_light, -1.0, f[0][c + W], f[1][c + W], f[2][c + W], f[4][c + W], f[5][c + W], S0, S1, S2);
+}
+
+__device__ __forceinline__ void lds_put(double* const* f, const Phys& ph, int c, double e, double fx, double fy)
+{
+    const C2P p = closure(ph.c, ph.c2, e, fx, fy);
+    f[0][c] = e;
+    f[1][c] = fx;
+    f[2][c] = fy;
+    f[3][c] = p_xx(p, fx);
+    f[4][c] = p_xy(p, fx, fy);
+    f[5][c] = p_yy(p, fy);
+}
+
+template <int TY>
+__global__ __launch_bounds__(kLdsTX * TY) void k_relax2_lds(Phys ph, Lvl L, CSoa rhs, double omega, CSoa u, Soa out,
+                                                           const int* __restrict__ active)
+{
+    using Q = Lds2<TY>;
+    constexpr int NT = kLdsTX * TY, NR = 2 * kLdsTX + 2 * TY;  // threads; ring points
+    static_assert(NR <= NT, "one ring point per thread");
+    __shared__ Q q;
+    if (*active == 0) return;
+    int i0, j0;
+    tile_origin(L, TY, i0, j0);
+    const bool perx = ph.bc[0] == BC_PERIODIC, pery = ph.bc[2] == BC_PERIODIC;
+    const int xe = min(i0 + kLdsTX, L.nx) - 1, ye = min(j0 + TY, L.ny) - 1;  // the last final cell
+    // the plus of half-widths (a, b) around the final cells holds (gi, gj)
+    auto plus = [&](int gi, int gj, int a, int b) {
+        return (gi >= i0 && gi <= xe && gj >= j0 - a && gj <= ye + a) ||
+               (gi >= i0 - a && gi <= xe + a && gj >= j0 && gj <= ye) ||
+               (b > 0 && gi >= i0 - b && gi <= xe + b && gj >= j0 - b && gj <= ye + b);
+    };
+    double* f2[6];
+    double* f1[6];
+    for (int a = 0; a < 6; ++a) {
+        f2[a] = q.buf + a * Q::N2;
+        f1[a] = q.buf + a * Q::N1;
+    }
+    // 1. stage the state (boundary rule on ghosts) and its closures
+    for (int p = threadIdx.x; p < Q::N2; p += NT) {
+        const int gi = i0 + p % Q::W2 - 2, gj = j0 + p / Q::W2 - 2;
+        int si, sj;
+        bool gx, gy, nx_, ny_;
+        rc_axis(gi, L.nx, perx, si, gx, nx_);
+        rc_axis(gj, L.ny, pery, sj, gy, ny_);
+        if (plus(gi, gj, 2, 1) && nx_ && ny_ && !(gx && gy)) {
+            const uint32_t k = (uint32_t)sj * (uint32_t)L.nx + (uint32_t)si;
+            const int side = gx ? (gi < 0 ? 0 : 1) : (gj < 0 ? 2 : 3);
+            double e, fx, fy;
+            ghost_rule(ph, side, !(gx || gy), ld(u.E, k), ld(u.Fx, k), ld(u.Fy, k), e, fx, fy);
+            lds_put(f2, ph, p, e, fx, fy);
+        } else {  // unused (corners, past a ragged edge)
+            for (int a = 0; a < 6; ++a) f2[a][p] = 0.0;
+        }
+    }
+    __syncthreads();
+    // 2. first sweep: item 0 is the thread's tile point, item 1 a ring point
+    const int t = threadIdx.x;
+    int li[2], lj[2], kind[2];  // kind: 0 unused, 1 swept, 2 ghost
+    int gsx[2], gsy[2];         // ghost: the cell it borders (global), and its side
+    double vE[2], vFx[2], vFy[2], vT[2];
+    li[0] = t % kLdsTX;
+    lj[0] = t / kLdsTX;
+    if (t < kLdsTX) li[1] = t, lj[1] = -1;
+    else if (t < 2 * kLdsTX) li[1] = t - kLdsTX, lj[1] = TY;
+    else if (t < 2 * kLdsTX + TY) li[1] = -1, lj[1] = t - 2 * kLdsTX;
+    else li[1] = kLdsTX, lj[1] = t - 2 * kLdsTX - TY;
+#pragma unroll
+    for (int m = 0; m < 2; ++m) {
+        kind[m] = 0;
+        vE[m] = vFx[m] = vFy[m] = vT[m] = 0.0;
+        gsx[m] = gsy[m] = 0;
+        if (m == 1 && t >= NR) continue;
+        const int gi = i0 + li[m], gj = j0 + lj[m];
+        if (!plus(gi, gj, 1, 0)) continue;
+        int si, sj;
+        bool gx, gy, nx_, ny_;
+        rc_axis(gi, L.nx, perx, si, gx, nx_);
+        rc_axis(gj, L.ny, pery, sj, gy, ny_);
+        if (gx || gy) {  // the plus holds no corner: only one side is off the domain
+            kind[m] = 2;
+            gsx[m] = si;
+            gsy[m] = sj;
+            continue;
+        }
+        kind[m] = 1;
+        const uint32_t k = (uint32_t)sj * (uint32_t)L.nx + (uint32_t)si;
+        const int c = (lj[m] + 2) * Q::W2 + li[m] + 2;
+        double S0, S1, S2;
+        lds_sums<Q::W2>(f2, L, ph.c, c, S0, S1, S2);
+        auto cen = [&](int f) { return f2[f][c]; };
+        relax_values<2, false>(ph, L, rhs, 1.0, 0.0, omega, S0, S1, S2, ld(u.T, k), cen, k, vE[m], vFx[m], vFy[m],
+                               vT[m]);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int m = 0; m < 2; ++m)
+        if (kind[m] == 1) lds_put(f1, ph, (lj[m] + 1) * Q::W1 + li[m] + 1, vE[m], vFx[m], vFy[m]);
+    // 3. ghosts of the iterate (only tiles on a non-periodic side have any)
+    const bool edge = (!perx && (i0 == 0 || xe == L.nx - 1)) || (!pery && (j0 == 0 || ye == L.ny - 1));
+    if (edge) {
+        __syncthreads();
+#pragma unroll
+        for (int m = 0; m < 2; ++m) {
+            if (kind[m] != 2) continue;
+            const int gi = i0 + li[m], gj = j0 + lj[m];
+            const int side = (gi < 0 || gi >= L.nx) ? (gi < 0 ? 0 : 1) : (gj < 0 ? 2 : 3);
+            const int cb = (gsy[m] - j0 + 1) * Q::W1 + gsx[m] - i0 + 1;
+            double e, fx, fy;
+            ghost_rule(ph, side, false, f1[0][cb], f1[1][cb], f1[2][cb], e, fx, fy);
+            lds_put(f1, ph, (lj[m] + 1) * Q::W1 + li[m] + 1, e, fx, fy);
+        }
+    }
+    __syncthreads();
+    // 4. second sweep on the final cells
+    const int i = i0 + li[0], j = j0 + lj[0];
+    if (i >= L.nx || j >= L.ny) return;
+    const uint32_t k = (uint32_t)j * (uint32_t)L.nx + (uint32_t)i;
+    const int c = (lj[0] + 1) * Q::W1 + li[0] + 1;
+    double S0, S1, S2;
+    lds_sums<Q::W1>(f1, L, ph.c, c, S0, S1, S2);
+    auto cen = [&](int f) { return f == 0 ? vE[0] : (f == 1 ? vFx[0] : vFy[0]); };
+    relax_update<2, false>(ph, L, rhs, 1.0, 0.0, omega, S0, S1, S2, vT[0], cen, out, k);
+}
+
+// ---------------------------------------------------------------------------
 // Finest-level residual fused with the restriction to level 1 (2-D).  A block
 // owns a 32 x 4 tile of coarse cells, i.e. the fine cells 2I-1 .. 2I+1 of each
 // coarse I of the tile.  It stages the fine states of the region around them
@@ -916,6 +1077,14 @@ bool set_sweep_rows(int rows)
     g_sweep_rows.store(rows, std::memory_order_relaxed);
     return true;
 }
+static std::atomic<int> g_pair_rows{8};
+int pair_rows() { return g_pair_rows.load(std::memory_order_relaxed); }
+bool set_pair_rows(int rows)
+{
+    if (rows != 0 && rows != 4 && rows != 8 && rows != 16) return false;
+    g_pair_rows.store(rows, std::memory_order_relaxed);
+    return true;
+}
 
 bool launch_relax_lds(hipStream_t st, const Phys& ph, const Lvl& L, CSoa rhs, double omega, CSoa u, Soa out,
                       const int* active, CSoa uc, CSoa vc, int px, int py, double eta)
@@ -938,6 +1107,19 @@ bool launch_relax_lds(hipStream_t st, const Phys& ph, const Lvl& L, CSoa rhs, do
         else M1_RELAX_LDS(16, false);
     }
 #undef M1_RELAX_LDS
+    return true;
+}
+
+bool launch_relax2_lds(hipStream_t st, const Phys& ph, const Lvl& L, CSoa rhs, double omega, CSoa u, Soa out,
+                       const int* active)
+{
+    const int rows = pair_rows();
+    if (rows == 0) return false;
+    const unsigned ntx = (unsigned)((L.nx + kLdsTX - 1) / kLdsTX), nty = (unsigned)((L.ny + rows - 1) / rows);
+    const dim3 gl(ntx * nty), bl(kLdsTX * rows);
+    if (rows == 4) hipLaunchKernelGGL(k_relax2_lds<4>, gl, bl, 0, st, ph, L, rhs, omega, u, out, active);
+    else if (rows == 8) hipLaunchKernelGGL(k_relax2_lds<8>, gl, bl, 0, st, ph, L, rhs, omega, u, out, active);
+    else hipLaunchKernelGGL(k_relax2_lds<16>, gl, bl, 0, st, ph, L, rhs, omega, u, out, active);
     return true;
 }
 

@@ -241,17 +241,18 @@ def test_launch_shape_settings_do_not_change_results(precision):
     the default settings' results to the bit."""
     announce("launch shapes", precision)
     params = dict(PARAMS, precision=precision)
-    keys = ("sweep_rows", "mx_sweep_rows", "residual_restrict", "tail_cells", "tiled_max_cells", "batch_grid")
+    keys = ("sweep_rows", "pair_rows", "mx_sweep_rows", "residual_restrict", "tail_cells", "tiled_max_cells",
+            "batch_grid")
     saved = {key: binding.tune_get(key) for key in keys}
     prob, v, sig = inputs.random_problem(41, 2, 96, 80, cfl=100.0, block=8)
     cases = problems(4)
     need = sum(binding.Engine.request_bytes(p, params) for p, _, _, _ in cases)
     settings = [dict(saved),
-                dict(sweep_rows=0, mx_sweep_rows=0, residual_restrict=0, tail_cells=64, tiled_max_cells=0,
-                     batch_grid=7),
-                dict(sweep_rows=16, mx_sweep_rows=8, residual_restrict=1, tail_cells=1024, tiled_max_cells=262144,
-                     batch_grid=64),
-                dict(saved, sweep_rows=4, mx_sweep_rows=16, residual_restrict=0)]
+                dict(sweep_rows=0, pair_rows=0, mx_sweep_rows=0, residual_restrict=0, tail_cells=64,
+                     tiled_max_cells=0, batch_grid=7),
+                dict(sweep_rows=16, pair_rows=16, mx_sweep_rows=8, residual_restrict=1, tail_cells=1024,
+                     tiled_max_cells=262144, batch_grid=64),
+                dict(saved, sweep_rows=4, pair_rows=4, mx_sweep_rows=16, residual_restrict=0)]
     outs = []
     try:
         for st in settings:
