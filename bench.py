@@ -12,9 +12,13 @@ solves, bracketed by device synchronisation. value = cells * implicit steps / wa
 time, in millions (Mcell-updates/s).
 
 The same JSON line also carries:
-- roofline: the finest-level Jacobi sweep kernel (k_relax_lds<rows, false>, the LDS-staged
-  sweep, or k_relax<2, false, true> when the staged sweep is off), timed with HIP events on
-  the solver's stream, at 112 algorithmic bytes per cell.
+- roofline: the finest-level Jacobi sweep kernel of the cycle, the solve's dominant kernel:
+  k_relax2_lds<rows> (two sweeps per launch, the first sweep's iterate kept in LDS), or with
+  that launch shape off k_relax_lds<rows, false> (the LDS-staged sweep) or k_relax<2, false,
+  true>. It is timed with HIP events on the solver's stream around m1_sweeps launches, at 112
+  algorithmic bytes per cell and sweep (the state, right-hand side and opacities read once and
+  the state written once per sweep): 224 per cell for the pair, whose own HBM traffic is about
+  half of that, since the intermediate iterate stays on chip.
 - traffic: the kernel's FETCH_SIZE + WRITE_SIZE counter bytes per launch, scaled by the same
   counters on a plain copy of known size. They are read from the counter summary under
   profiles/, and are null when the kernel sources have changed since it was taken.
@@ -54,15 +58,23 @@ METRIC = "Mcell-updates/s + time to 1e-8 residual; batched solves/s with p50/p99
 HBM_PEAK_GBS = 8000.0
 SWEEP_BYTES_PER_CELL = 112  # v (E,Fx,Fy,T) 32 + b 32 + sigma 16 read, v' 32 written
 SOLVER = dict(omega=0.8, levels=0)
+def sweeps_per_launch():
+    """Sweeps per launch of the finest-level sweep kernel the cycle runs (2 with the fused pair on)."""
+    return 2 if binding.tune_get("pair_rows") > 0 else 1
+
+
 def sweep_kernel():
-    """Name of the finest-level sweep kernel that m1_sweep launches under the current settings."""
-    rows = binding.tune_get("sweep_rows")
+    """Name of the finest-level sweep kernel that m1_sweeps(sweeps_per_launch()) launches under the current
+    settings: the fused pair, else the LDS-staged single sweep, else the one-cell sweep."""
+    pair, rows = binding.tune_get("pair_rows"), binding.tune_get("sweep_rows")
+    if pair > 0:
+        return f"k_relax2_lds<{pair}>"
     return f"k_relax_lds<{rows}, false>" if rows > 0 else "k_relax<2, false, true>"
 
 
 def traffic_file():
-    rows = binding.tune_get("sweep_rows")
-    name = f"k_relax_lds{rows}" if rows > 0 else "k_relax"
+    pair, rows = binding.tune_get("pair_rows"), binding.tune_get("sweep_rows")
+    name = f"k_relax2_lds{pair}" if pair > 0 else (f"k_relax_lds{rows}" if rows > 0 else "k_relax")
     return os.path.join(ROOT, "profiles", f"{name}_hotwall1024_traffic.txt")
 COPY_ELEMS = 1 << 27  # 1 GiB of float64 per copy launch
 
@@ -106,18 +118,21 @@ def read_traffic(cells: int):
 
 
 def sweep_timing(torch, plan, b, v, reps):
-    """Average duration of the finest-level sweep kernel: HIP events on the plan's stream."""
+    """Average duration of the finest-level sweep kernel: HIP events on the plan's stream around launches of
+    m1_sweeps with the kernel's sweeps per launch (one launch each)."""
     out = torch.empty_like(v)
+    n = sweeps_per_launch()
     for _ in range(3):
-        plan.sweep(b, v)
+        plan.sweeps(b, v, n)
     st = plan.stream
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record(st)
     src, dst = v.clone(), out
     L = binding.lib()
     for _ in range(reps):
-        binding._check(L.m1_sweep(plan.handle, binding.ctypes.byref(plan._st(b)), binding.ctypes.byref(plan._st(src)),
-                                  binding.ctypes.byref(plan._st(dst))), "m1_sweep")
+        binding._check(L.m1_sweeps(plan.handle, binding.ctypes.byref(plan._st(b)),
+                                   binding.ctypes.byref(plan._st(src)), binding.ctypes.byref(plan._st(dst)), n),
+                       "m1_sweeps")
         src, dst = dst, src
     e1.record(st)
     e1.synchronize()
@@ -354,9 +369,11 @@ def main():
     if args.profile == "sweeps":
         t_sweep = sweep_timing(torch, plan, b, v_init.clone(), args.reps)
         cp = copy_timing(torch)
-        print(json.dumps({"profile": "sweeps", "cells": cells, "sweep_avg_launch_us": round(t_sweep * 1e6, 2),
-                          "sweep_GB_per_s": round(SWEEP_BYTES_PER_CELL * cells / t_sweep / 1e9, 1), "copy": cp}),
-              flush=True)
+        alg = SWEEP_BYTES_PER_CELL * sweeps_per_launch() * cells
+        print(json.dumps({"profile": "sweeps", "kernel": sweep_kernel(), "cells": cells,
+                          "sweeps_per_launch": sweeps_per_launch(), "sweep_avg_launch_us": round(t_sweep * 1e6, 2),
+                          "algorithmic_bytes_per_launch": alg, "sweep_GB_per_s": round(alg / t_sweep / 1e9, 1),
+                          "copy": cp}), flush=True)
         return
 
     def one_solve():
@@ -388,12 +405,13 @@ def main():
         "launch_shapes": {k: binding.tune_get(k) for k in binding.TUNE_ENV},
     }
     t_sweep = sweep_timing(torch, plan, b, v_init.clone(), args.reps)
-    achieved = SWEEP_BYTES_PER_CELL * cells / t_sweep / 1e9
+    alg_bytes = SWEEP_BYTES_PER_CELL * sweeps_per_launch() * cells
+    achieved = alg_bytes / t_sweep / 1e9
     traffic = read_traffic(cells) if args.workload == "hotwall" and precision == "fp64" else None
     out["roofline"] = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                        "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                       "kernel": f"{sweep_kernel()} (finest-level FP64 Jacobi sweep)",
-                       "algorithmic_bytes_per_launch": SWEEP_BYTES_PER_CELL * cells,
+                       "kernel": f"{sweep_kernel()} (finest-level FP64 Jacobi sweeps, {sweeps_per_launch()} per launch)",
+                       "algorithmic_bytes_per_launch": alg_bytes,
                        "avg_launch_us": round(t_sweep * 1e6, 2)}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(prob, v0, sig, run, cycles / run["steps"], args.cpu_cycles)

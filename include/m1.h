@@ -168,6 +168,13 @@ m1_status m1_apply_A(m1_plan* plan, int32_t level, const m1_state* v, m1_state* 
 /* One relaxed Jacobi sweep of A_0(u) = b on the finest level (Algorithm 1 with
  * weight omega from the plan's params): v_out = v_in + omega (J(v_in) - v_in). */
 m1_status m1_sweep(m1_plan* plan, const m1_state* b, const m1_state* v_in, m1_state* v_out);
+/* nsweeps >= 1 such sweeps from v_in into v_out (v_in is not written), as the
+ * cycle runs them: two consecutive sweeps in one launch when the launch shape
+ * "pair_rows" is on (2-D), which gives the one-by-one sweeps' result to the
+ * bit.  v_out must not alias v_in or b.  Uses the plan's spare finest-level
+ * state as the other buffer: not concurrently with m1_vcycle/m1_step on the
+ * same plan.  M1_ERR_ARG for nsweeps < 1 or an invalid state. */
+m1_status m1_sweeps(m1_plan* plan, const m1_state* b, const m1_state* v_in, m1_state* v_out, int32_t nsweeps);
 /* One pseudo-time step (Algorithm 3) of M du/dtau + A_l(u) = f on level `level`
  * (level >= 1 in the cycle; any level accepted), from u_in to u_out.          */
 m1_status m1_pseudo_step(m1_plan* plan, int32_t level, double dtau, const m1_state* f, const m1_state* u_in,

@@ -98,6 +98,7 @@ def lib():
         L.m1_step.argtypes = [vp, P(m1_state), ctypes.c_int32, P(m1_info)]
         L.m1_apply_A.argtypes = [vp, ctypes.c_int32, P(m1_state), P(m1_state)]
         L.m1_sweep.argtypes = [vp, P(m1_state), P(m1_state), P(m1_state)]
+        L.m1_sweeps.argtypes = [vp, P(m1_state), P(m1_state), P(m1_state), ctypes.c_int32]
         L.m1_pseudo_step.argtypes = [vp, ctypes.c_int32, ctypes.c_double, P(m1_state), P(m1_state), P(m1_state)]
         L.m1_restrict.argtypes = [vp, ctypes.c_int32, P(m1_state), P(m1_state)]
         L.m1_prolong_project.argtypes = [vp, ctypes.c_int32, P(m1_state), P(m1_state), P(m1_state), P(m1_state)]
@@ -122,7 +123,7 @@ def lib():
         L.m1_tune_get.argtypes = [ctypes.c_char_p]
         L.m1_tune_get.restype = ctypes.c_int64
         for name in ("m1_plan_create", "m1_residual", "m1_vcycle", "m1_step", "m1_apply_A", "m1_sweep",
-                     "m1_pseudo_step", "m1_restrict", "m1_prolong_project", "m1_sync", "m1_level_dims",
+                     "m1_sweeps", "m1_pseudo_step", "m1_restrict", "m1_prolong_project", "m1_sync", "m1_level_dims",
                      "m1_engine_create", "m1_batch_submit", "m1_batch_run", "m1_batch_poll", "m1_batch_wait",
                      "m1_batch_cancel", "m1_batch_times", "m1_batch_release", "m1_serve_start", "m1_serve_stop"):
             getattr(L, name).restype = ctypes.c_int
@@ -284,6 +285,12 @@ class Plan:
         out = self.torch.zeros_like(v)
         _check(lib().m1_sweep(self.handle, ctypes.byref(self._st(b)), ctypes.byref(self._st(v)),
                               ctypes.byref(self._st(out))), "m1_sweep")
+        return out
+
+    def sweeps(self, b, v, n: int):
+        out = self.torch.zeros_like(v)
+        _check(lib().m1_sweeps(self.handle, ctypes.byref(self._st(b)), ctypes.byref(self._st(v)),
+                               ctypes.byref(self._st(out)), n), "m1_sweeps")
         return out
 
     def pseudo_step(self, level: int, dtau: float, f, u):

@@ -323,22 +323,26 @@ Gate fixed_gate(m1_plan& P, double dtau)
 // nu finest-level sweeps.  With `control` the first sweep also reduces the
 // residual norm of its input (the previous cycle's result) and the cycle
 // control then updates dtau / the stop flag before the rest of the cycle runs.
-void fine_sweeps(m1_plan& P, Soa& cur, Soa& other, int nu, const Gate& G, bool control = false)
+// One launch of finest-level sweeps of A_0(u) = b from `in` into `out`: two
+// (the fused pair) when `two` allows it and that launch shape is on, else one
+// (reducing the norm of `in` into `partials` when given).  Returns the count.
+int fine_launch(m1_plan& P, const CSoa& b, const CSoa& in, const Soa& out, bool two, double* partials,
+                const int* active)
 {
     const LevelBuf& f = P.lev[0];
+    if (two && !partials && P.dim == 2 && m1::launch_relax2_lds(P.st, P.ph, f.L, b, P.params.omega, in, out, active))
+        return 2;
+    m1::launch_relax(P.st, P.dim, P.ph, f.L, b, nullptr, 0.0, 1.0, P.params.omega, in, out, partials, active);
+    return 1;
+}
+
+void fine_sweeps(m1_plan& P, Soa& cur, Soa& other, int nu, const Gate& G, bool control = false)
+{
     for (int s = 0; s < nu;) {
         const bool norm = control && s == 0;
-        if (!norm && nu - s >= 2 && P.dim == 2 &&
-            m1::launch_relax2_lds(P.st, P.ph, f.L, cs(P.b), P.params.omega, cs(cur), other, G.active)) {
-            std::swap(cur, other);  // two sweeps, one launch
-            s += 2;
-            continue;
-        }
-        m1::launch_relax(P.st, P.dim, P.ph, f.L, cs(P.b), nullptr, 0.0, 1.0, P.params.omega, cs(cur), other,
-                         norm ? P.partials : nullptr, G.active);
+        s += fine_launch(P, cs(P.b), cs(cur), other, nu - s >= 2, norm ? P.partials : nullptr, G.active);
         if (norm) m1::launch_norm_control(P.st, P.partials, P.npart, P.dctrl);
         std::swap(cur, other);
-        ++s;
     }
 }
 
@@ -1070,6 +1074,27 @@ m1_status m1_sweep(m1_plan* P, const m1_state* b, const m1_state* v_in, m1_state
         return M1_ERR_ARG;
     m1::launch_relax(P->st, P->dim, P->ph, P->lev[0].L, cs(to_soa(b)), nullptr, 0.0, 1.0, P->params.omega,
                      cs(to_soa(v_in)), to_soa(v_out), nullptr, &P->dfix->active);
+    return last_launch();
+}
+
+m1_status m1_sweeps(m1_plan* P, const m1_state* b, const m1_state* v_in, m1_state* v_out, int32_t nsweeps)
+{
+    if (!P || nsweeps < 1 || !valid_state(P, b) || !valid_state(P, v_in) || !valid_state(P, v_out) ||
+        v_in->E == v_out->E || b->E == v_out->E)
+        return M1_ERR_ARG;
+    // launches alternate between v_out and the plan's spare finest-level state,
+    // starting with the one that makes the last launch write v_out
+    const bool pairs = P->dim == 2 && m1::pair_rows() > 0;
+    const int launches = pairs ? nsweeps / 2 + nsweeps % 2 : nsweeps;
+    const Soa out = to_soa(v_out);
+    Soa cur = launches % 2 ? out : P->tmp, other = launches % 2 ? P->tmp : out;
+    const CSoa rhs = cs(to_soa(b));
+    int s = fine_launch(*P, rhs, cs(to_soa(v_in)), cur, nsweeps >= 2, nullptr, &P->dfix->active);
+    while (s < nsweeps) {
+        s += fine_launch(*P, rhs, cs(cur), other, nsweeps - s >= 2, nullptr, &P->dfix->active);
+        std::swap(cur, other);
+    }
+    if (!same(cur, out)) m1::launch_copy(P->st, P->dim, P->lev[0].n, cs(cur), out);  // the setting changed meanwhile
     return last_launch();
 }
 

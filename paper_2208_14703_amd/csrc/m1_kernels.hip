@@ -283,8 +283,11 @@ __device__ __forceinline__ void lds_put(double* const* f, const Phys& ph, int c,
     f[5][c] = p_yy(p, fy);
 }
 
+// Six waves per SIMD (three 512-thread blocks per CU at 8 rows; 80 VGPRs, a few
+// values spilled to scratch) measured faster than the four the unconstrained
+// register count leaves room for: the phases are latency-bound.
 template <int TY>
-__global__ __launch_bounds__(kLdsTX * TY) void k_relax2_lds(Phys ph, Lvl L, CSoa rhs, double omega, CSoa u, Soa out,
+__global__ __launch_bounds__(kLdsTX * TY) __attribute__((amdgpu_waves_per_eu(6))) void k_relax2_lds(Phys ph, Lvl L, CSoa rhs, double omega, CSoa u, Soa out,
                                                            const int* __restrict__ active)
 {
     using Q = Lds2<TY>;

@@ -68,6 +68,9 @@ def test_workspace_size_and_host_validation():
                           None, ctypes.byref(h))
     assert st == 1
     assert L.m1_strerror(2).decode().startswith("state not admissible")
+    # operations on a null plan are argument errors, checked before anything is enqueued
+    assert L.m1_sweep(None, None, None, None) == 1
+    assert L.m1_sweeps(None, None, None, None, 2) == 1
 
 
 def test_one_dimensional_grid_validation():

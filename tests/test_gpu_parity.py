@@ -122,6 +122,34 @@ def test_sweep_pair_matches_two_sweeps(nx, ny, bcs):
         np.testing.assert_array_equal(x, res[0, nu0, omega])
 
 
+@pytest.mark.parametrize("nx,ny,bcs", [(100, 37, "mixed"), (64, 64, "periodic"), (130, 70, "wall"), (3, 5, "xper")])
+def test_sweeps_match_chained_sweeps(nx, ny, bcs):
+    """m1_sweeps(n) -- fused pairs, and one single sweep for odd n -- gives n
+    chained m1_sweep calls to the bit, with the pair launch on and off, and
+    leaves its input alone; two sweeps agree with the oracle's two sweeps."""
+    announce("sweeps", nx, ny, bcs)
+    kinds = BC_SETS.get(bcs, ("periodic", "periodic", "dirichlet", "reflective"))
+    prob, v, sig = inputs.random_problem(8, 2, nx, ny, bc_kinds=kinds, cfl=40.0, fmax=1.0)
+    o = oracle.Oracle(prob, sig)
+    b = o.rhs(inputs.random_problem(9, 2, nx, ny, bc_kinds=kinds, cfl=40.0)[1])
+    vd, bd = to_dev(v), to_dev(b)
+    P = plan_for(prob, sig, levels=1)
+    chain = [vd]
+    for _ in range(5):
+        chain.append(P.sweep(bd, chain[-1]))
+    old = binding.tune_get("pair_rows")
+    try:
+        for rows in (0, 8):
+            binding.tune_set("pair_rows", rows)
+            for n in range(1, 6):
+                np.testing.assert_array_equal(to_host(P.sweeps(bd, vd, n)), to_host(chain[n]))
+    finally:
+        binding.tune_set("pair_rows", old)
+    np.testing.assert_array_equal(to_host(vd), v)
+    two = o.sweep(b, o.sweep(b, v, OMEGA), OMEGA)
+    assert rel_err(to_host(chain[2]), two, prob["c"]) <= 2e-13
+
+
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 @pytest.mark.parametrize("nx,ny", [(96, 80), (100, 36), (66, 10), (130, 70), (64, 64)])
 @pytest.mark.parametrize("bcs", ["periodic", "mixed", "wall"])
