@@ -229,7 +229,16 @@ __device__ __forceinline__ void local_solve(double beta, double gamma, double a,
     }
     const double K = k * ar * fma(gamma, a, beta) * idE;
     const double Q = fma(k * BE, idE, BT);
-    const double Tup = fmin(Q / cT, sqrt(sqrt(Q / K)));
+    // Newton on g(t) = K t^4 + cT t - Q (convex, increasing for t > 0) from the
+    // guess Tg, clamped to an upper bound of the root, which is also the start
+    // when Tg is not below it.  The root is below both Q / cT and (Q / K)^(1/4);
+    // the bound takes them from the hardware reciprocal and reciprocal square
+    // root (measured relative error below 6e-8 each on gfx950) raised by 2^-12,
+    // which keeps it above the root, off the cell's dependent chain of exact
+    // divisions and square roots.  Newton reaches the same root from any upper
+    // bound; only the last bits of the stopping iterate may differ.
+    const double Tup = (1.0 + 0x1p-12) * fmin(Q * __builtin_amdgcn_rcp(cT),
+                                              __builtin_amdgcn_rsq(__builtin_amdgcn_rsq(Q * __builtin_amdgcn_rcp(K))));
     double t = (Tg > 0.0 && Tg < Tup) ? Tg : Tup;
     for (int it = 0; it < 64; ++it) {
         const double t2 = t * t;
