@@ -244,7 +244,10 @@ __device__ __forceinline__ void local_solve(double beta, double gamma, double a,
         const double t2 = t * t;
         const double g = fma(K * t2, t2, fma(cT, t, -Q));
         const double dg = fma(4.0 * K * t2, t, cT);
-        const double tn = fmin(fma(-g, rcp64(dg), t), Tup);
+        // the step uses the hardware reciprocal of g' unrefined: Newton corrects
+        // its relative error (< 6e-8) in the next iterate and converges to the
+        // same root, quadratically until that error dominates
+        const double tn = fmin(fma(-g, __builtin_amdgcn_rcp(dg), t), Tup);
         const bool done = fabs(tn - t) <= 1e-14 * tn;
         t = tn;
         if (done) break;

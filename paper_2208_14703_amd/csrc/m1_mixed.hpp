@@ -210,17 +210,22 @@ __device__ __forceinline__ void local_solve_inc(double beta, double gamma, doubl
     }
     const double K = k * ar * fma(gamma, a, beta) * idE;
     const double Q = fma(k * QE, idE, QT);
+    // upper bound of the increment's root, min(Q / cT, (T^4 + Q / K)^(1/4) - T),
+    // from the hardware reciprocal and reciprocal square root raised by 2^-12
+    // (still above the root; as in local_solve)
     double up = 0.0;
     if (Q > 0.0) {
         const double T2 = T * T;
-        up = fmin(Q / cT, sqrt(sqrt(fma(T2, T2, Q / K))) - T);
+        constexpr double raise = 1.0 + 0x1p-12;
+        const double r4 = __builtin_amdgcn_rsq(__builtin_amdgcn_rsq(fma(T2, T2, Q * __builtin_amdgcn_rcp(K))));
+        up = fmin(raise * (Q * __builtin_amdgcn_rcp(cT)), raise * r4 - T);
     }
     double x = (tg < up && T + tg > 0.0) ? tg : up;
     for (int it = 0; it < 64; ++it) {
         const double Tx = T + x;
         const double g = fma(K, quartic_inc(T, x), fma(cT, x, -Q));
         const double dg = fma(4.0 * K * Tx * Tx, Tx, cT);
-        const double xn = fmin(fma(-g, rcp64(dg), x), up);
+        const double xn = fmin(fma(-g, __builtin_amdgcn_rcp(dg), x), up);  // unrefined, as in local_solve
         const bool done = fabs(xn - x) <= 1e-13 * fmax(fabs(xn), 1e-30 * T) || fabs(xn - x) <= 1e-15 * T;
         x = xn;
         if (done) break;
