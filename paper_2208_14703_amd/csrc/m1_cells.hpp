@@ -112,7 +112,7 @@ __device__ __forceinline__ void pseudo_core(const Phys& ph, const Lvl& L, double
         fFy += fma(dF, uFy, -S2);
         fT += fma(ph.c_v, uT, -ex);
     }
-    const double sE = fE, sFx = fFx, sFy = fFy, sT = fT / ph.c_v;
+    const double sE = fE, sFx = fFx, sFy = fFy, sT = fT * rcp_nr(ph.c_v);
     const double ts = ray_len(ph.c2, uE, uFx, uFy, uT, sE, sFx, sFy, sT);
     const double tau = fmin(dtau, ts * reach);
     tE = fma(tau, sE, uE);
