@@ -198,10 +198,11 @@ m1_status m1_sync(m1_plan* plan);
  *                      Jacobi sweep (2-D sweeps without the norm; 4, 8 or 16),
  *                      0 = one cell per thread without LDS (default 4; read at
  *                      each launch; engines read it when their tables are built);
- *   "pair_rows"        rows of the 64-wide tile of the kernel that runs two
+ *   "pair_rows"        rows of the 64-wide tile of the kernels that run two
  *                      consecutive finest-level sweeps of a cycle (2-D, without
- *                      the norm) in one launch, the first sweep's iterate kept
- *                      in LDS (4, 8 or 16); 0 = each sweep its own launch
+ *                      the norm; FP64 sweeps and mixed-precision correction
+ *                      sweeps) in one launch, the first sweep's iterate kept in
+ *                      LDS (4, 8 or 16); 0 = each sweep its own launch
  *                      (default 8; read at each launch);
  *   "mx_sweep_rows"    the same for the mixed-precision correction sweeps;
  *   "residual_restrict" 1: the finest-level residual of a cycle is restricted

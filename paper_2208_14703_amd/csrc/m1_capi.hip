@@ -524,11 +524,19 @@ void mx_vcycle(m1_plan& P, Soa& cur64, Soa& other64, const Gate& G, bool control
     if (control) m1::launch_norm_control(P.st, P.partials, P.npart, P.dctrl);
     const float om = (float)p.omega;
     auto sweeps = [&](Soa32 d, int count, bool from_zero) {
-        for (int s = 0; s < count; ++s) {
+        for (int s = 0; s < count;) {
             const Soa32 out = same32(d, P.dA) ? P.dB : P.dA;
-            m1::launch_mx_sweep(P.st, P.dim, P.ph, f0.L32, cs(P.base32), (from_zero && s == 0) ? CSoa32{} : cs(d),
-                                cs(P.r32), 0.0f, 1.0f, om, out, G.active);
+            const bool zero = from_zero && s == 0;
+            if (!zero && count - s >= 2 && P.dim == 2 &&
+                m1::launch_mx_sweep2(P.st, P.ph, f0.L32, cs(P.base32), cs(d), cs(P.r32), om, out, G.active)) {
+                d = out;  // two sweeps, one launch
+                s += 2;
+                continue;
+            }
+            m1::launch_mx_sweep(P.st, P.dim, P.ph, f0.L32, cs(P.base32), zero ? CSoa32{} : cs(d), cs(P.r32), 0.0f,
+                                1.0f, om, out, G.active);
             d = out;
+            ++s;
         }
         return d;
     };

@@ -73,18 +73,6 @@ __device__ __forceinline__ void ij_of(int nx, int sh, uint32_t k, int& i, int& j
     }
 }
 
-// 1/x for positive finite x: the hardware estimate refined by two
-// Newton-Raphson steps y <- y + y (1 - x y), each squaring the relative error
-// (about 1 ulp at the end; not the correctly rounded quotient).
-__device__ __forceinline__ double rcp64(double x)
-{
-    double y = __builtin_amdgcn_rcp(x);
-    double e = fma(-x, y, 1.0);
-    y = fma(y, e, y);
-    e = fma(-x, y, 1.0);
-    return fma(y, e, y);
-}
-
 // Reciprocal and square root (x > 0) from the hardware approximations
 // (relative error < 6e-8 on gfx950) with one Newton correction each: a few
 // ulp (~4e-15 relative), at a fraction of the correctly rounded sequences'
@@ -232,12 +220,12 @@ __device__ __forceinline__ void local_solve(double beta, double gamma, double a,
                                             double& E, double& Fx, double& Fy, double& T)
 {
     const double dE = fma(gamma, a + ka, beta);
-    const double iF = rcp64(fma(gamma, ks, dE));
+    const double iF = rcp_nr(fma(gamma, ks, dE));
     Fx = BFx * iF;
     Fy = BFy * iF;
     const double k = gamma * ka;
     const double cT = (beta + gamma) * cv;
-    const double idE = rcp64(dE);
+    const double idE = rcp_nr(dE);
     if (k == 0.0) {
         T = BT / cT;
         E = BE * idE;

@@ -141,7 +141,8 @@ void set_batch_grid_cap(int cap);
 // rows of the LDS-staged finest sweep's 64-wide tile (0: one-cell-per-thread sweep)
 int sweep_rows();
 bool set_sweep_rows(int rows);
-// rows of the 64-wide tile of the fused pair of finest sweeps (0: sweeps launched one by one)
+// rows of the 64-wide tile of the fused pair of finest sweeps, FP64 and mixed
+// precision (0: sweeps launched one by one)
 int pair_rows();
 bool set_pair_rows(int rows);
 // the same for the mixed-precision correction sweeps
@@ -188,6 +189,10 @@ void launch_b_gather_ctrl(hipStream_t st, const BProb* P, int np, Ctrl* out);
 
 void launch_mx_resid(hipStream_t st, int dim, const Phys& ph, const Lvl& L, double eta, CSoa v, CSoa32 d, CSoa b,
                      Soa vnew, Soa32 base, Soa32 r32, double* partials, const int* active);
+// two mixed-precision correction sweeps (2-D, beta = 0, gamma = 1, d given) in one launch, d -> out;
+// false (nothing launched) when the pair launch shape is off
+bool launch_mx_sweep2(hipStream_t st, const Phys& ph, const Lvl32& L, CSoa32 w, CSoa32 d, CSoa32 rhs, float omega,
+                      Soa32 out, const int* active);
 void launch_mx_sweep(hipStream_t st, int dim, const Phys& ph, const Lvl32& L, CSoa32 w, CSoa32 d, CSoa32 rhs,
                      float beta, float gamma, float omega, Soa32 out, const int* active);
 // 2-D: coarse (wc, dc, gc) = R(w), R(d), R(X + sgn N_w(d)) of the fine level L, without storing rho

@@ -160,11 +160,12 @@ __global__ __launch_bounds__(kBlock32) void k_mx_resid(Phys ph, Lvl L, double et
 // d.E == nullptr means d = 0 (first sweep of a cycle: dS = 0, no reads of d).
 // The rest of the sweep of one cell from its off-diagonal increment S and its
 // correction (dE, dFx, dFy, dT).
+// mx_sweep_values returns the new correction, mx_sweep_update stores it at k of out.
 template <int DIM>
-__device__ __forceinline__ void mx_sweep_update(const Phys& ph, const Lvl32& L, const CSoa32& w, const CSoa32& rhs,
+__device__ __forceinline__ void mx_sweep_values(const Phys& ph, const Lvl32& L, const CSoa32& w, const CSoa32& rhs,
                                                 float beta, float gamma, float omega, float S0, float S1, float S2,
-                                                float dE, float dFx, float dFy, float dT, const Soa32& out,
-                                                uint32_t k)
+                                                float dE, float dFx, float dFy, float dT, uint32_t k, float& oE,
+                                                float& oFx, float& oFy, float& oT)
 {
     const double QE = fmaf(gamma, S0, ldf(rhs.E, k));
     const double QFx = fmaf(gamma, S1, ldf(rhs.Fx, k));
@@ -173,10 +174,23 @@ __device__ __forceinline__ void mx_sweep_update(const Phys& ph, const Lvl32& L, 
     const double ka = (double)L.cdt * ldf(L.sa, k), ks = (double)L.cdt * ldf(L.ss, k);
     float xE, xFx, xFy, xT;
     local_solve_inc(beta, gamma, L.a, ka, ks, ph.c_v, ph.a_r, QE, QFx, QFy, QT, ldf(w.T, k), dT, xE, xFx, xFy, xT);
-    stf(out.E, k, fmaf(omega, xE - dE, dE));
-    stf(out.Fx, k, fmaf(omega, xFx - dFx, dFx));
-    if (DIM == 2) stf(out.Fy, k, fmaf(omega, xFy - dFy, dFy));
-    stf(out.T, k, fmaf(omega, xT - dT, dT));
+    oE = fmaf(omega, xE - dE, dE);
+    oFx = fmaf(omega, xFx - dFx, dFx);
+    oFy = (DIM == 2) ? fmaf(omega, xFy - dFy, dFy) : 0.0f;
+    oT = fmaf(omega, xT - dT, dT);
+}
+template <int DIM>
+__device__ __forceinline__ void mx_sweep_update(const Phys& ph, const Lvl32& L, const CSoa32& w, const CSoa32& rhs,
+                                                float beta, float gamma, float omega, float S0, float S1, float S2,
+                                                float dE, float dFx, float dFy, float dT, const Soa32& out,
+                                                uint32_t k)
+{
+    float oE, oFx, oFy, oT;
+    mx_sweep_values<DIM>(ph, L, w, rhs, beta, gamma, omega, S0, S1, S2, dE, dFx, dFy, dT, k, oE, oFx, oFy, oT);
+    stf(out.E, k, oE);
+    stf(out.Fx, k, oFx);
+    if (DIM == 2) stf(out.Fy, k, oFy);
+    stf(out.T, k, oT);
 }
 
 template <int DIM>
@@ -293,6 +307,163 @@ __global__ __launch_bounds__(kMxTX * TY) void k_mx_sweep_lds(Phys ph, Lvl32 L, C
     mx_stage_tile<TY>(q, ph, L, w, d, i0, j0);
     __syncthreads();
     mx_tile_sweep<TY>(q, ph, L, w, d, rhs, beta, gamma, omega, out, i0, j0);
+}
+
+// Two correction sweeps (beta = 0, gamma = 1) in one launch, as k_relax2_lds
+// does for FP64: the block stages the base and the correction of its 64 x TY
+// tile and a two-cell halo (boundary rule on ghosts, the c^2 P increment of
+// each point once), runs the first sweep on the tile and its one-cell ring,
+// rebuilds the ring's ghosts from the cells they border (the base of such a
+// cell read again from memory, as the staging of a separate sweep would), and
+// runs the second sweep from LDS.  Every point's arithmetic is that of
+// k_mx_sweep_lds, so the result is two such sweeps' to the bit.
+template <int TY>
+struct MxLds2 {
+    static constexpr int W2 = kMxTX + 4, N2 = W2 * (TY + 4);  // staged: tile + 2-cell halo
+    static constexpr int W1 = kMxTX + 2, N1 = W1 * (TY + 2);  // first sweep's correction: tile + ring
+    float buf[9 * N2];  // e, gx, gy, xx, xy, yy and the base E, Fx, Fy; the iterate's six arrays overwrite them
+};
+
+// Off-diagonal increment of the point at index n of a W-wide LDS region with
+// arrays f[0..5] = e, gx, gy, xx, xy, yy, in the order of mx_tile_sweep.
+template <int W>
+__device__ __forceinline__ void mx_lds_sums(const float* const* f, const Lvl32& L, float c, int n, float& S0,
+                                            float& S1, float& S2)
+{
+    S0 = S1 = S2 = 0.0f;
+    auto nb = [&](int m, float kk, float sgn, bool xdir) {
+        acc_inc(kk, sgn, xdir, c, f[0][m], f[1][m], f[2][m], DP{f[3][m], f[4][m], f[5][m]}, S0, S1, S2);
+    };
+    nb(n - 1, L.kx, +1.0f, true);
+    nb(n + 1, L.kx, -1.0f, true);
+    nb(n - W, L.ky, +1.0f, false);
+    nb(n + W, L.ky, -1.0f, false);
+}
+
+__device__ __forceinline__ void mx_lds_put(float* const* f, int n, float e, float gx, float gy, const DP& p)
+{
+    f[0][n] = e;
+    f[1][n] = gx;
+    f[2][n] = gy;
+    f[3][n] = p.xx;
+    f[4][n] = p.xy;
+    f[5][n] = p.yy;
+}
+
+// Six waves per SIMD (three 512-thread blocks per CU at 8 rows; 80 VGPRs, three
+// values spilled): without the cap two blocks fit, and the pair measured slower
+// than two single sweeps.
+template <int TY>
+__global__ __launch_bounds__(kMxTX * TY) __attribute__((amdgpu_waves_per_eu(6))) void k_mx_sweep2_lds(Phys ph, Lvl32 L, CSoa32 w, CSoa32 d, CSoa32 rhs,
+                                                             float omega, Soa32 out, const int* __restrict__ active)
+{
+    using Q = MxLds2<TY>;
+    constexpr int NT = kMxTX * TY, NR = 2 * kMxTX + 2 * TY;  // threads; ring points
+    static_assert(NR <= NT, "one ring point per thread");
+    __shared__ Q q;
+    if (*active == 0) return;
+    const int ntx = (L.nx + kMxTX - 1) / kMxTX;
+    const int b = (int)xcd_block();
+    const int i0 = (b % ntx) * kMxTX, j0 = (b / ntx) * TY;
+    const float c = (float)ph.c, c2 = (float)ph.c2;
+    const bool perx = ph.bc[0] == BC_PERIODIC, pery = ph.bc[2] == BC_PERIODIC;
+    const int xe = min(i0 + kMxTX, L.nx) - 1, ye = min(j0 + TY, L.ny) - 1;  // the last final cell
+    // the plus of half-widths (a, b) around the final cells holds (gi, gj) (as in k_relax2_lds)
+    auto plus = [&](int gi, int gj, int a, int bb) {
+        return (gi >= i0 && gi <= xe && gj >= j0 - a && gj <= ye + a) ||
+               (gi >= i0 - a && gi <= xe + a && gj >= j0 && gj <= ye) ||
+               (bb > 0 && gi >= i0 - bb && gi <= xe + bb && gj >= j0 - bb && gj <= ye + bb);
+    };
+    float* f2[9];
+    float* f1[6];
+    for (int a = 0; a < 9; ++a) f2[a] = q.buf + a * Q::N2;
+    for (int a = 0; a < 6; ++a) f1[a] = q.buf + a * Q::N1;
+    // 1. stage base and correction (boundary rule on ghosts) and the increments
+    for (int p = threadIdx.x; p < Q::N2; p += NT) {
+        const int gi = i0 + p % Q::W2 - 2, gj = j0 + p / Q::W2 - 2;
+        int si, sj;
+        bool gx_, gy_, nx_, ny_;
+        rc_axis(gi, L.nx, perx, si, gx_, nx_);
+        rc_axis(gj, L.ny, pery, sj, gy_, ny_);
+        float e = 0.0f, gx = 0.0f, gy = 0.0f, E = 0.0f, Fx = 0.0f, Fy = 0.0f;
+        DP pp{0.0f, 0.0f, 0.0f};
+        if (plus(gi, gj, 2, 1) && nx_ && ny_ && !(gx_ && gy_)) {
+            const uint32_t k = (uint32_t)sj * (uint32_t)L.nx + (uint32_t)si;
+            const int side = gx_ ? (gi < 0 ? 0 : 1) : (gj < 0 ? 2 : 3);
+            ghost_inc(ph, side, !(gx_ || gy_), ldf(w.E, k), ldf(w.Fx, k), ldf(w.Fy, k), ldf(d.E, k), ldf(d.Fx, k),
+                      ldf(d.Fy, k), E, Fx, Fy, e, gx, gy);
+            pp = closure_inc(c, c2, E, Fx, Fy, e, gx, gy);
+        }
+        mx_lds_put(f2, p, e, gx, gy, pp);
+        f2[6][p] = E;
+        f2[7][p] = Fx;
+        f2[8][p] = Fy;
+    }
+    __syncthreads();
+    // 2. first sweep: item 0 is the thread's tile point, item 1 a ring point
+    const int t = threadIdx.x;
+    int li[2], lj[2], kind[2];  // kind: 0 unused, 1 swept, 2 ghost
+    int gsx[2], gsy[2];         // swept: the cell read; ghost: the cell it borders
+    float vE[2], vFx[2], vFy[2], vT[2], bE[2], bFx[2], bFy[2];
+    li[0] = t % kMxTX;
+    lj[0] = t / kMxTX;
+    if (t < kMxTX) li[1] = t, lj[1] = -1;
+    else if (t < 2 * kMxTX) li[1] = t - kMxTX, lj[1] = TY;
+    else if (t < 2 * kMxTX + TY) li[1] = -1, lj[1] = t - 2 * kMxTX;
+    else li[1] = kMxTX, lj[1] = t - 2 * kMxTX - TY;
+#pragma unroll
+    for (int m = 0; m < 2; ++m) {
+        kind[m] = 0;
+        gsx[m] = gsy[m] = 0;
+        vE[m] = vFx[m] = vFy[m] = vT[m] = bE[m] = bFx[m] = bFy[m] = 0.0f;
+        const int gi = i0 + li[m], gj = j0 + lj[m];
+        if ((m == 1 && t >= NR) || !plus(gi, gj, 1, 0)) continue;
+        bool gx_, gy_, nx_, ny_;
+        rc_axis(gi, L.nx, perx, gsx[m], gx_, nx_);
+        rc_axis(gj, L.ny, pery, gsy[m], gy_, ny_);
+        kind[m] = (gx_ || gy_) ? 2 : 1;  // the plus holds no corner: at most one side is off the domain
+        if (kind[m] != 1) continue;
+        const uint32_t k = (uint32_t)gsy[m] * (uint32_t)L.nx + (uint32_t)gsx[m];
+        const int n = (lj[m] + 2) * Q::W2 + li[m] + 2;
+        float S0, S1, S2;
+        mx_lds_sums<Q::W2>(f2, L, c, n, S0, S1, S2);
+        mx_sweep_values<2>(ph, L, w, rhs, 0.0f, 1.0f, omega, S0, S1, S2, f2[0][n], f2[1][n], f2[2][n], ldf(d.T, k), k,
+                           vE[m], vFx[m], vFy[m], vT[m]);
+        bE[m] = f2[6][n];
+        bFx[m] = f2[7][n];
+        bFy[m] = f2[8][n];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int m = 0; m < 2; ++m)
+        if (kind[m] == 1)
+            mx_lds_put(f1, (lj[m] + 1) * Q::W1 + li[m] + 1, vE[m], vFx[m], vFy[m],
+                       closure_inc(c, c2, bE[m], bFx[m], bFy[m], vE[m], vFx[m], vFy[m]));
+    // 3. ghosts of the iterate (only tiles on a non-periodic side have any)
+    const bool edge = (!perx && (i0 == 0 || xe == L.nx - 1)) || (!pery && (j0 == 0 || ye == L.ny - 1));
+    if (edge) {
+        __syncthreads();
+#pragma unroll
+        for (int m = 0; m < 2; ++m) {
+            if (kind[m] != 2) continue;
+            const int gi = i0 + li[m], gj = j0 + lj[m];
+            const int side = (gi < 0 || gi >= L.nx) ? (gi < 0 ? 0 : 1) : (gj < 0 ? 2 : 3);
+            const int cb = (gsy[m] - j0 + 1) * Q::W1 + gsx[m] - i0 + 1;
+            const uint32_t kb = (uint32_t)gsy[m] * (uint32_t)L.nx + (uint32_t)gsx[m];
+            float E, Fx, Fy, e, gx, gy;
+            ghost_inc(ph, side, false, ldf(w.E, kb), ldf(w.Fx, kb), ldf(w.Fy, kb), f1[0][cb], f1[1][cb], f1[2][cb], E,
+                      Fx, Fy, e, gx, gy);
+            mx_lds_put(f1, (lj[m] + 1) * Q::W1 + li[m] + 1, e, gx, gy, closure_inc(c, c2, E, Fx, Fy, e, gx, gy));
+        }
+    }
+    __syncthreads();
+    // 4. second sweep on the final cells
+    const int i = i0 + li[0], j = j0 + lj[0];
+    if (i >= L.nx || j >= L.ny) return;
+    const uint32_t k = (uint32_t)j * (uint32_t)L.nx + (uint32_t)i;
+    float S0, S1, S2;
+    mx_lds_sums<Q::W1>(f1, L, c, (lj[0] + 1) * Q::W1 + li[0] + 1, S0, S1, S2);
+    mx_sweep_update<2>(ph, L, w, rhs, 0.0f, 1.0f, omega, S0, S1, S2, vE[0], vFx[0], vFy[0], vT[0], out, k);
 }
 
 template <int DIM>
@@ -1069,6 +1240,19 @@ void launch_mx_sweep(hipStream_t st, int dim, const Phys& ph, const Lvl32& L, CS
         return;
     }
     MX_DISPATCH(dim, k_mx_sweep, nblk((int64_t)L.nx * L.ny), ph, L, w, d, rhs, beta, gamma, omega, out, active);
+}
+
+bool launch_mx_sweep2(hipStream_t st, const Phys& ph, const Lvl32& L, CSoa32 w, CSoa32 d, CSoa32 rhs, float omega,
+                      Soa32 out, const int* active)
+{
+    const int rows = pair_rows();
+    if (rows == 0 || !d.E) return false;
+    const unsigned ntx = (unsigned)((L.nx + kMxTX - 1) / kMxTX), nty = (unsigned)((L.ny + rows - 1) / rows);
+    const dim3 gl(ntx * nty), bl(kMxTX * rows);
+    if (rows == 4) hipLaunchKernelGGL(k_mx_sweep2_lds<4>, gl, bl, 0, st, ph, L, w, d, rhs, omega, out, active);
+    else if (rows == 8) hipLaunchKernelGGL(k_mx_sweep2_lds<8>, gl, bl, 0, st, ph, L, w, d, rhs, omega, out, active);
+    else hipLaunchKernelGGL(k_mx_sweep2_lds<16>, gl, bl, 0, st, ph, L, w, d, rhs, omega, out, active);
+    return true;
 }
 
 void launch_mx_residual_restrict(hipStream_t st, const Phys& ph, const Lvl32& L, CSoa32 w, CSoa32 d, CSoa32 X,

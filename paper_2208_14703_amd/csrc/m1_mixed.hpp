@@ -197,12 +197,12 @@ __device__ __forceinline__ void local_solve_inc(double beta, double gamma, doubl
                                                 double tg, float& xE, float& xFx, float& xFy, float& xT)
 {
     const double dE = fma(gamma, a + ka, beta);
-    const double iF = rcp64(fma(gamma, ks, dE));
+    const double iF = rcp_nr(fma(gamma, ks, dE));
     xFx = (float)(QFx * iF);
     xFy = (float)(QFy * iF);
     const double k = gamma * ka;
     const double cT = (beta + gamma) * cv;
-    const double idE = rcp64(dE);
+    const double idE = rcp_nr(dE);
     if (k == 0.0) {
         xT = (float)(QT / cT);
         xE = (float)(QE * idE);

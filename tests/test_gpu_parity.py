@@ -91,15 +91,18 @@ def test_lds_sweep_matches_one_cell_sweep(nx, ny, bcs):
             np.testing.assert_array_equal(res[rows, omega], res[0, omega])
 
 
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
 @pytest.mark.parametrize("nx,ny", [(100, 37), (64, 64), (1, 1), (3, 5), (130, 70), (65, 9), (64, 17), (200, 3)])
 @pytest.mark.parametrize("bcs", ["periodic", "mixed", "wall", "xper"])
-def test_sweep_pair_matches_two_sweeps(nx, ny, bcs):
+def test_sweep_pair_matches_two_sweeps(nx, ny, bcs, precision):
     """Two finest sweeps in one launch (the first sweep's iterate kept in LDS,
     its ring of ghosts rebuilt from it) give the sweeps launched one by one, to
-    the bit: one-level cycles of 2, 3 and 4 sweeps (one pair, a pair and a
-    single, two pairs) on ragged tiles, one-cell domains and every kind of side,
+    the bit, in FP64 and for the mixed-precision correction sweeps: one-level
+    cycles of 2, 3 and 4 sweeps (FP64: one pair, a pair and a single, two
+    pairs; mixed, whose first sweep starts from a zero correction: a single,
+    then pairs) on ragged tiles, one-cell domains and every kind of side,
     periodic in one direction only included."""
-    announce("sweep pair", nx, ny, bcs)
+    announce("sweep pair", nx, ny, bcs, precision)
     kinds = BC_SETS.get(bcs, ("periodic", "periodic", "dirichlet", "reflective"))
     prob, v, sig = inputs.random_problem(6, 2, nx, ny, bc_kinds=kinds, cfl=40.0, fmax=1.0)
     vn = inputs.random_problem(7, 2, nx, ny, bc_kinds=kinds, cfl=40.0)[1]
@@ -111,7 +114,7 @@ def test_sweep_pair_matches_two_sweeps(nx, ny, bcs):
             binding.tune_set("pair_rows", rows)
             for nu0 in (2, 3, 4):
                 for omega in (1.0, OMEGA):
-                    P = plan_for(prob, sig, levels=1, omega=omega, nu0=nu0)
+                    P = plan_for(prob, sig, levels=1, omega=omega, nu0=nu0, precision=precision)
                     vd = to_dev(v)
                     P.vcycle(vd, vnd, 0.5)
                     res[rows, nu0, omega] = to_host(vd)
