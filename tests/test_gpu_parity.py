@@ -125,6 +125,36 @@ def test_sweep_pair_matches_two_sweeps(nx, ny, bcs, precision):
         np.testing.assert_array_equal(x, res[0, nu0, omega])
 
 
+@pytest.mark.parametrize("omega", [1.0, OMEGA])
+def test_local_solve_extremes(omega):
+    """One sweep against the oracle, cell by cell, where the local Newton
+    solve is hardest: absorption opacity log-uniform over 1e-8 .. 1e8 per
+    cell (the quartic from linear- to T^4-dominated), temperatures over
+    1e-2 .. 1e2, and a right-hand side drawn independently, so that the
+    guess (the current temperature) is far below or far above the root and
+    the upper bound both starts and clamps the iteration.  Per-cell relative
+    error <= 1e-12 in E and T (F scaled by cE + |F|)."""
+    announce("local solve extremes", omega)
+    nx = ny = 96
+    prob, v, sig = inputs.random_problem(31, 2, nx, ny, cfl=50.0, block=1)
+    rng = np.random.default_rng(32)
+    sig[0] = 10.0 ** rng.uniform(-8.0, 8.0, size=(ny, nx))
+    v[3] = 10.0 ** rng.uniform(-2.0, 2.0, size=(ny, nx))
+    w = inputs.random_problem(33, 2, nx, ny, cfl=50.0, block=1)[1]
+    w[3] = 10.0 ** rng.uniform(-2.0, 2.0, size=(ny, nx))
+    o = oracle.Oracle(prob, sig)
+    b = o.rhs(w)
+    ref = o.sweep(b, v, omega)
+    P = plan_for(prob, sig, levels=1, omega=omega)
+    got = to_host(P.sweep(to_dev(b), to_dev(v)))
+    assert np.all(np.isfinite(got))
+    c = prob["c"]
+    eE = np.abs(got[0] - ref[0]) / np.abs(ref[0])
+    eF = np.abs(got[1:3] - ref[1:3]) / (c * np.abs(ref[0]) + np.abs(ref[1:3]))
+    eT = np.abs(got[3] - ref[3]) / np.abs(ref[3])
+    assert eE.max() <= 1e-12 and eF.max() <= 1e-12 and eT.max() <= 1e-12, (eE.max(), eF.max(), eT.max())
+
+
 @pytest.mark.parametrize("nx,ny,bcs", [(100, 37, "mixed"), (64, 64, "periodic"), (130, 70, "wall"), (3, 5, "xper")])
 def test_sweeps_match_chained_sweeps(nx, ny, bcs):
     """m1_sweeps(n) -- fused pairs, and one single sweep for odd n -- gives n
