@@ -226,7 +226,9 @@ __device__ __forceinline__ void local_solve_inc(double beta, double gamma, doubl
         const double g = fma(K, quartic_inc(T, x), fma(cT, x, -Q));
         const double dg = fma(4.0 * K * Tx * Tx, Tx, cT);
         const double xn = fmin(fma(-g, __builtin_amdgcn_rcp(dg), x), up);  // unrefined, as in local_solve
-        const bool done = fabs(xn - x) <= 1e-13 * fmax(fabs(xn), 1e-30 * T) || fabs(xn - x) <= 1e-15 * T;
+        // converged once the step is below 1e-7 of the increment or 1e-8 of T:
+        // the error left after it is ~1.5 s^2 / (T + x), far below FP32 rounding
+        const bool done = fabs(xn - x) <= 1e-7 * fmax(fabs(xn), 1e-30 * T) || fabs(xn - x) <= 1e-8 * T;
         x = xn;
         if (done) break;
     }
