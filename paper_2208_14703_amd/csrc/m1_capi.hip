@@ -969,8 +969,6 @@ m1_status m1_step(m1_plan* P, m1_state* v, int32_t nsteps, m1_info* info)
     m1_status status = M1_OK;
     int total = 0;
     double r0 = 0.0, rel = 0.0, dtau = p.dtau_im0;
-    // the iterate returns to the same buffer after a cycle unless it has an odd number of sweeps
-    const bool flips = (P->L == 1) && (p.nu0 % 2 == 1);
     for (int step = 0; step < nsteps && status == M1_OK; ++step) {
         m1::launch_make_rhs(P->st, P->dim, n0, P->grid.c_v, cs(user), P->b);
         double bnorm = 0.0;
@@ -1008,6 +1006,9 @@ m1_status m1_step(m1_plan* P, m1_state* v, int32_t nsteps, m1_info* info)
         // needed is enqueued.  The chunk follows the observed rate.
         Soa cur = user, other = P->tmp;
         Soa32 pend{};
+        // FP64: whether a cycle leaves the iterate in the other buffer (an odd
+        // number of finest-level launches), read off the first cycle enqueued
+        bool cycle_flips = false;
         int enqueued = 0, chunk = 2;
         double prev_rel = 1.0;
         int prev_cycles = 0;
@@ -1022,6 +1023,7 @@ m1_status m1_step(m1_plan* P, m1_state* v, int32_t nsteps, m1_info* info)
                 } else {
                     vcycle_impl(*P, cur, other, G, true);
                 }
+                if (enqueued + c == 0) cycle_flips = !same(cur, user);
             }
             enqueued += todo;
             if (hipMemcpyAsync(P->hctrl, P->dctrl, sizeof(m1::Ctrl), hipMemcpyDeviceToHost, P->st) != hipSuccess ||
@@ -1045,13 +1047,14 @@ m1_status m1_step(m1_plan* P, m1_state* v, int32_t nsteps, m1_info* info)
         total += h.cycles;
         rel = h.rel;
         dtau = h.dtau;
-        // with an odd number of sweeps per cycle the result sits in `user` after an even cycle count;
-        // in mixed precision every executed cycle (h.cycles + 1 of them, the last one only
-        // measuring) writes the FP64 state into the other buffer
+        // FP64: the result is the iterate after h.cycles full cycles (the last cycle
+        // enqueued only measured it), in `user` unless the cycles moved it an odd
+        // number of times; mixed precision: every executed cycle (h.cycles + 1 of
+        // them, the last one only measuring) writes the FP64 state into the other buffer
         Soa res = user;
         if (P->mixed) {
             if ((h.cycles + 1) % 2 == 1) res = P->tmp;
-        } else if (flips && (h.cycles % 2 == 1)) {
+        } else if (cycle_flips && (h.cycles % 2 == 1)) {
             res = P->tmp;
         }
         if (!same(res, user)) m1::launch_copy(P->st, P->dim, n0, cs(res), user);

@@ -125,6 +125,35 @@ def test_sweep_pair_matches_two_sweeps(nx, ny, bcs, precision):
         np.testing.assert_array_equal(x, res[0, nu0, omega])
 
 
+@pytest.mark.parametrize("levels,nu0,sweep_rows", [(1, 3, 4), (1, 2, 4), (1, 1, 4), (0, 2, 0), (0, 4, 0),
+                                                    (0, 3, 4), (0, 2, 4)])
+def test_step_result_with_and_without_sweep_pairs(levels, nu0, sweep_rows):
+    """m1_step returns the same result, to the bit and with the same cycle
+    counts, with the two-sweep launch on and off.  The launches per cycle
+    differ (one for two sweeps), so the buffer holding the iterate after a
+    cycle differs too: one-level cycles with odd and even sweep counts, and
+    full cycles with the correction not fused into the first post-sweep
+    (staged sweeps off) and even counts, over two steps."""
+    announce("step with sweep pairs", levels, nu0, sweep_rows)
+    prob, v, sig = inputs.random_problem(21, 2, 96, 80, cfl=2.0 if levels == 1 else 50.0, block=8)
+    old = {k: binding.tune_get(k) for k in ("pair_rows", "sweep_rows")}
+    try:
+        res = {}
+        for pair in (0, 8):
+            binding.tune_set("pair_rows", pair)
+            binding.tune_set("sweep_rows", sweep_rows)
+            P = plan_for(prob, sig, levels=levels, nu0=nu0, rtol=1e-8, max_cycles=20000)
+            vd = to_dev(v)
+            info = P.step(vd, 2)
+            res[pair] = (to_host(vd), info["cycles"], info["status"])
+    finally:
+        for k, val in old.items():
+            binding.tune_set(k, val)
+    assert res[0][2] == 0 and res[8][2] == 0
+    assert res[0][1] == res[8][1]
+    np.testing.assert_array_equal(res[8][0], res[0][0])
+
+
 @pytest.mark.parametrize("omega", [1.0, OMEGA])
 def test_local_solve_extremes(omega):
     """One sweep against the oracle, cell by cell, where the local Newton
