@@ -1638,7 +1638,10 @@ void bm_vcycle(m1_engine& E)
 {
     const int nu0 = E.params.nu0, m = E.params.pseudo_steps;
     const uint32_t* wl = E.dWL;
-    const int pend = (nu0 % 2 == 1) ? 1 : 0;  // where the post-sweeps leave the correction
+    // the correction the previous cycle left: its pre-sweeps started from buffer 1
+    // (the first one, from zero, writes buffer 0) and every sweep of either leg
+    // moved it, 2 nu0 moves in all, so it ends in buffer 1 whatever nu0
+    const int pend = 1;
     m1::launch_bm_resid(E.st, E.dP, E.dS, E.dS32, wl + E.fine.off, E.fine.n, pend);
     m1::launch_b_norm_control(E.st, E.dP, E.dPL, E.n_all, 1);
     int d = 1;

@@ -71,6 +71,31 @@ def test_batch_matches_alone(precision, arena):
 
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("nu0", [1, 2, 4])
+def test_batch_sweep_counts_match_alone(precision, nu0):
+    """Odd and even finest-level sweep counts (the default is 3): the engine's
+    cycles move the iterate (FP64) and the pending correction (mixed) between
+    their two buffers once per sweep, and every request still equals its solo
+    solve, bitwise, with the same cycle counts."""
+    announce("batch sweep counts", precision, nu0)
+    params = dict(PARAMS, precision=precision, nu0=nu0)
+    cases = problems(4)
+    need = sum(binding.Engine.request_bytes(p, params) for p, _, _, _ in cases)
+    E = binding.Engine(need + (16 << 20), params, max_requests=8)
+    states, tickets = [], []
+    for prob, v, sig, ns in cases:
+        vd = to_dev(v)
+        states.append(vd)
+        tickets.append(E.submit(prob, to_dev(sig), vd, ns))
+    infos = [E.wait(t) for t in tickets]
+    for (prob, v, sig, ns), vd, info in zip(cases, states, infos):
+        ref, info_a = alone(prob, v, sig, ns, params)
+        assert info["status"] == 0 and info_a["status"] == 0
+        assert info["cycles"] == info_a["cycles"], (info["cycles"], info_a["cycles"])
+        np.testing.assert_array_equal(to_host(vd), ref)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
 def test_batch_ragged_shapes_match_alone(precision):
     """Sides that are not multiples of the tile shapes (64 x rows for the
     staged sweeps, 32 x 4 coarse cells for the fused residual-restriction),
