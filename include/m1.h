@@ -92,7 +92,8 @@ typedef struct {
  *                 time its explicit sub-steps reached (consistent steady state);
  *                 0: dtau_im in every cell;
  *   precision     M1_FP64 or M1_MIXED (FP32 delta-form smoothing and coarse
- *                 levels, FP64 residual, projection and T^4 update);
+ *                 levels, FP64 residual, projection and T^4 update; M1_MIXED
+ *                 requires nu_l = 1: its coarse steps fuse one sweep);
  *   dtau_im0      initial implicit pseudo-time step (reset every time step);
  *   eps_inc/dec   adaptation thresholds (x1.1 above eps_inc, /2 below eps_dec);
  *   eta           fraction of the admissible ray used (sub-steps, projection);

@@ -99,6 +99,7 @@ bool valid_params(const m1_params* p)
         return false;
     if (p->dtau_rule != M1_DTAU_SIGNED && p->dtau_rule != M1_DTAU_LITERAL) return false;
     if (p->precision != M1_FP64 && p->precision != M1_MIXED) return false;
+    if (p->precision == M1_MIXED && p->nu_l != 1) return false;  // coarse correction steps fuse one sweep
     if (!(p->eta > 0.0 && p->eta < 1.0) || !(p->omega > 0.0 && p->omega <= 1.0) || !(p->rtol > 0.0)) return false;
     if (!(p->dtau_im0 > 0.0) || !(p->dtau_min > 0.0) || !(p->dtau_max >= p->dtau_min)) return false;
     return std::isfinite(p->eps_inc) && std::isfinite(p->eps_dec);

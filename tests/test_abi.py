@@ -55,6 +55,10 @@ def test_workspace_size_and_host_validation():
     assert L.m1_workspace_bytes(ctypes.byref(g), ctypes.byref(p2)) == 0
     p3 = binding.make_params(binding.default_params(levels=12))   # 1024 has only 9 levels down to side 4
     assert L.m1_workspace_bytes(ctypes.byref(g), ctypes.byref(p3)) == 0
+    p4 = binding.make_params(binding.default_params(precision="mixed", nu_l=2))  # mixed fuses one sweep per step
+    assert L.m1_workspace_bytes(ctypes.byref(g), ctypes.byref(p4)) == 0
+    p5 = binding.make_params(binding.default_params(precision="mixed"))
+    assert L.m1_workspace_bytes(ctypes.byref(g), ctypes.byref(p5)) > 0
     # plan creation rejects a too-small or misaligned workspace before touching it
     op = binding.m1_opacity(0x10000, 0x20000)
     h = ctypes.c_void_p()

@@ -77,3 +77,22 @@ def test_mixed_two_steps_and_single_cycle():
     P.vcycle(vd, vn, 0.1)
     after = P.residual(vd, vn)
     assert after < 0.5 * before
+
+
+@pytest.mark.parametrize("m,nu0", [(1, 3), (2, 3), (4, 3), (3, 2), (3, 1)])
+def test_mixed_smoothing_counts_reach_solution(m, nu0):
+    """Other smoothing counts than the paper's in mixed precision (coarse
+    pseudo-time steps m = 1, 2, 4; finest sweeps nu0 = 1, 2): the solve
+    reaches rtol 1e-11 and the oracle's converged solution, which does not
+    depend on the smoothing counts.  nu_l = 1 is required in mixed precision
+    and tested in the ABI checks."""
+    announce("mixed smoothing counts", m, nu0)
+    prob, v, sig = inputs.random_problem(12, 2, 64, 64, bc_kinds=("dirichlet", "reflective", "periodic", "periodic"),
+                                         cfl=50.0)
+    o = oracle.Oracle(prob, sig)
+    ref, _ = o.step(v, 1, oracle.make_params(omega=OMEGA, rtol=1e-13, max_cycles=20000))
+    got, info = solve(prob, v, sig, rtol=1e-11, precision="mixed", pseudo_steps=m, nu0=nu0, max_cycles=20000)
+    assert info["status"] == 0, info
+    b = o.rhs(v)
+    assert o.norm(o.residual(b, got)) / o.norm(o.residual(b, v)) <= 1.01e-11
+    assert rel_err(got, ref, prob["c"]) <= 5e-9

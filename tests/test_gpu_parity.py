@@ -308,6 +308,34 @@ def test_vcycle_parity(case):
         assert err <= 1e-11, (cyc, err)
 
 
+@pytest.mark.parametrize("m,nu_l,nu0,tiled", [(1, 1, 3, 1), (2, 1, 3, 1), (4, 1, 3, 1), (3, 2, 3, 1), (2, 2, 2, 1),
+                                              (3, 1, 2, 1), (1, 1, 1, 1), (2, 1, 3, 0), (3, 1, 2, 0)])
+def test_vcycle_parity_smoothing_counts(m, nu_l, nu0, tiled):
+    """Three V-cycles against the oracle's with other smoothing counts than
+    the paper's: pseudo-time steps per coarse smoothing m = 1, 2, 4, two
+    Jacobi sweeps per pseudo-time step, even and odd finest-level sweep
+    counts, with the one-launch smoothing legs (m <= 3) and without; each
+    count changes which buffers the legs end in."""
+    announce("vcycle smoothing counts", m, nu_l, nu0, tiled)
+    prob, v, sig = inputs.random_problem(7, 2, 128, 128, bc_kinds=BC_SETS["mixed"], cfl=80.0, block=8)
+    params = dict(pseudo_steps=m, nu_l=nu_l, nu0=nu0)
+    o = oracle.Oracle(prob, sig)
+    old = binding.tune_get("tiled_max_cells")
+    binding.tune_set("tiled_max_cells", 65536 if tiled else 0)
+    try:
+        P = plan_for(prob, sig, **params)  # the tiled bound is read when the plan is created
+    finally:
+        binding.tune_set("tiled_max_cells", old)
+    b = o.rhs(v)
+    vd, vn = to_dev(v), to_dev(v)
+    ref = v
+    for cyc, dtau in enumerate((1e-3, 0.3, 5.0)):
+        P.vcycle(vd, vn, dtau)
+        ref = o.vcycle(b, ref, dtau, params=oracle_params(**params))
+        err = rel_err(to_host(vd), ref, prob["c"])
+        assert err <= 1e-11, (cyc, err)
+
+
 # ------------------------------------------------------------------ converged solves
 @pytest.mark.parametrize("case", ["gauss256", "hot128", "logn128", "mixed64_2steps", "gauss256_jacobi"])
 def test_converged_step_parity(case):
