@@ -71,14 +71,15 @@ def test_batch_matches_alone(precision, arena):
 
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
-@pytest.mark.parametrize("nu0", [1, 2, 4])
-def test_batch_sweep_counts_match_alone(precision, nu0):
-    """Odd and even finest-level sweep counts (the default is 3): the engine's
-    cycles move the iterate (FP64) and the pending correction (mixed) between
-    their two buffers once per sweep, and every request still equals its solo
-    solve, bitwise, with the same cycle counts."""
-    announce("batch sweep counts", precision, nu0)
-    params = dict(PARAMS, precision=precision, nu0=nu0)
+@pytest.mark.parametrize("nu0,m", [(1, 3), (2, 3), (4, 3), (3, 1), (3, 5)])
+def test_batch_sweep_counts_match_alone(precision, nu0, m):
+    """Odd and even finest-level sweep counts (the default is 3) and other odd
+    pseudo-time step counts (the engine requires odd ones): the engine's cycles
+    move the iterate (FP64), the pending correction (mixed) and the coarse
+    iterates between their buffers once per sweep or step, and every request
+    still equals its solo solve, bitwise, with the same cycle counts."""
+    announce("batch sweep counts", precision, nu0, m)
+    params = dict(PARAMS, precision=precision, nu0=nu0, pseudo_steps=m)
     cases = problems(4)
     need = sum(binding.Engine.request_bytes(p, params) for p, _, _, _ in cases)
     E = binding.Engine(need + (16 << 20), params, max_requests=8)
