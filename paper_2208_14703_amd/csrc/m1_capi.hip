@@ -1255,6 +1255,9 @@ struct m1_engine {
     };
     List fine;
     List fine2;    // 64 x rows tiles of the finest levels for the staged sweep (rows == 0: none)
+    List fine3;    // 64 x prow tiles for two sweeps per launch (pairs only)
+    int prow = 0;  // tile rows of the pair kernel
+    bool pairs = false;  // FP64: consecutive finest sweeps run two per launch
     int rows = 0;
     bool fused = false;     // residuals formed and restricted in one launch per level (lists rr)
     std::vector<List> restr, pdown, up, rr;
@@ -1519,6 +1522,24 @@ m1_status rebuild(m1_engine& E)
         }
     }
     E.fine2.n = (int)E.hwl.size() - E.fine2.off;
+    // FP64, two sweeps per launch: the pre-sweeps take 1 + ceil((nu0 - 1) / 2) launches and the
+    // post-sweeps ceil(nu0 / 2), an even total (2k + 2 for nu0 = 2k + 1) for odd nu0 only, which keeps
+    // the cycle ending in the buffer it began from.  (The mixed engine keeps single sweeps: its pair
+    // measured no faster on the batched workload.)
+    E.prow = m1::pair_rows();
+    E.pairs = !E.mixed && E.prow > 0 && E.params.nu0 % 2 == 1;
+    E.fine3 = {};
+    if (E.pairs && E.prow == E.rows) {
+        E.fine3 = E.fine2;
+    } else if (E.pairs) {
+        E.fine3.off = (int)E.hwl.size();
+        for (int i = 0; i < np; ++i) {
+            const LevelBuf& lv = E.running[i]->plan->lev[0];
+            const uint32_t nt = (uint32_t)((lv.nx + 63) / 64) * (uint32_t)((lv.ny + E.prow - 1) / E.prow);
+            for (uint32_t t = 0; t < nt; ++t) E.hwl.push_back(((uint32_t)i << m1::kTileBits) | t);
+        }
+        E.fine3.n = (int)E.hwl.size() - E.fine3.off;
+    }
     E.restr.assign(E.Lmax, {});
     E.pdown.assign(E.Lmax, {});
     E.up.assign(E.Lmax, {});
@@ -1590,10 +1611,18 @@ void b_vcycle(m1_engine& E)
     const int nu0 = E.params.nu0, m = E.params.pseudo_steps;
     const uint32_t* wl = E.dWL;
     int in_x1 = 0;
-    for (int s = 0; s < nu0; ++s) {
-        if (s > 0 && E.rows > 0) m1::launch_b_relax_lds(E.st, E.dP, E.dS, wl + E.fine2.off, E.fine2.n, in_x1, E.rows);
-        else m1::launch_b_relax(E.st, E.dP, E.dS, wl + E.fine.off, E.fine.n, in_x1, s == 0);
-        if (s == 0) m1::launch_b_norm_control(E.st, E.dP, E.dPL, E.n_all, 0);
+    for (int s = 0; s < nu0;) {
+        if (s > 0 && E.pairs && nu0 - s >= 2) {
+            m1::launch_b_relax2_lds(E.st, E.dP, E.dS, wl + E.fine3.off, E.fine3.n, in_x1, E.prow);
+            s += 2;
+        } else {
+            if (s > 0 && E.rows > 0)
+                m1::launch_b_relax_lds(E.st, E.dP, E.dS, wl + E.fine2.off, E.fine2.n, in_x1, E.rows);
+            else
+                m1::launch_b_relax(E.st, E.dP, E.dS, wl + E.fine.off, E.fine.n, in_x1, s == 0);
+            if (s == 0) m1::launch_b_norm_control(E.st, E.dP, E.dPL, E.n_all, 0);
+            ++s;
+        }
         in_x1 ^= 1;
     }
     if (!E.fused) m1::launch_b_apply(E.st, E.dP, E.dS, wl + E.up[0].off, E.up[0].n, 0, in_x1);
@@ -1624,9 +1653,15 @@ void b_vcycle(m1_engine& E)
             }
         }
     }
-    for (int s = 0; s < nu0; ++s) {
-        if (E.rows > 0) m1::launch_b_relax_lds(E.st, E.dP, E.dS, wl + E.fine2.off, E.fine2.n, in_x1, E.rows);
-        else m1::launch_b_relax(E.st, E.dP, E.dS, wl + E.fine.off, E.fine.n, in_x1, 0);
+    for (int s = 0; s < nu0;) {
+        if (E.pairs && nu0 - s >= 2) {
+            m1::launch_b_relax2_lds(E.st, E.dP, E.dS, wl + E.fine3.off, E.fine3.n, in_x1, E.prow);
+            s += 2;
+        } else {
+            if (E.rows > 0) m1::launch_b_relax_lds(E.st, E.dP, E.dS, wl + E.fine2.off, E.fine2.n, in_x1, E.rows);
+            else m1::launch_b_relax(E.st, E.dP, E.dS, wl + E.fine.off, E.fine.n, in_x1, 0);
+            ++s;
+        }
         in_x1 ^= 1;
     }
 }

@@ -170,6 +170,9 @@ bool launch_relax2_lds(hipStream_t st, const Phys& ph, const Lvl& L, CSoa rhs, d
 void launch_b_residual_restrict(hipStream_t st, const BProb* P, const BSlot* S, const uint32_t* wl, int nwl, int level,
                                 int in_sel);
 void launch_b_relax(hipStream_t st, const BProb* P, const BSlot* S, const uint32_t* wl, int nwl, int in_x1, int norm);
+// two finest-level sweeps per launch over a work list of 64 x rows tiles (rows 4, 8 or 16)
+void launch_b_relax2_lds(hipStream_t st, const BProb* P, const BSlot* S, const uint32_t* wl, int nwl, int in_x1,
+                         int rows);
 // staged finest-level sweep over a work list of 64 x rows tiles (rows 4, 8 or 16)
 void launch_b_relax_lds(hipStream_t st, const BProb* P, const BSlot* S, const uint32_t* wl, int nwl, int in_x1,
                         int rows);

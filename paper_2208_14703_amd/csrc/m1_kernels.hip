@@ -283,20 +283,14 @@ __device__ __forceinline__ void lds_put(double* const* f, const Phys& ph, int c,
     f[5][c] = p_yy(p, fy);
 }
 
-// Six waves per SIMD (three 512-thread blocks per CU at 8 rows; 80 VGPRs, a few
-// values spilled to scratch) measured faster than the four the unconstrained
-// register count leaves room for: the phases are latency-bound.
+// The two sweeps of the tile at (i0, j0); every thread of the block calls it.
 template <int TY>
-__global__ __launch_bounds__(kLdsTX * TY) __attribute__((amdgpu_waves_per_eu(6))) void k_relax2_lds(Phys ph, Lvl L, CSoa rhs, double omega, CSoa u, Soa out,
-                                                           const int* __restrict__ active)
+__device__ __forceinline__ void relax2_tile(Lds2<TY>& q, const Phys& ph, const Lvl& L, const CSoa& rhs, double omega,
+                                            const CSoa& u, const Soa& out, int i0, int j0)
 {
     using Q = Lds2<TY>;
     constexpr int NT = kLdsTX * TY, NR = 2 * kLdsTX + 2 * TY;  // threads; ring points
     static_assert(NR <= NT, "one ring point per thread");
-    __shared__ Q q;
-    if (*active == 0) return;
-    int i0, j0;
-    tile_origin(L, TY, i0, j0);
     const bool perx = ph.bc[0] == BC_PERIODIC, pery = ph.bc[2] == BC_PERIODIC;
     const int xe = min(i0 + kLdsTX, L.nx) - 1, ye = min(j0 + TY, L.ny) - 1;  // the last final cell
     // the plus of half-widths (a, b) around the final cells holds (gi, gj)
@@ -389,13 +383,28 @@ __global__ __launch_bounds__(kLdsTX * TY) __attribute__((amdgpu_waves_per_eu(6))
     __syncthreads();
     // 4. second sweep on the final cells
     const int i = i0 + li[0], j = j0 + lj[0];
-    if (i >= L.nx || j >= L.ny) return;
-    const uint32_t k = (uint32_t)j * (uint32_t)L.nx + (uint32_t)i;
-    const int c = (lj[0] + 1) * Q::W1 + li[0] + 1;
-    double S0, S1, S2;
-    lds_sums<Q::W1>(f1, L, ph.c, c, S0, S1, S2);
-    auto cen = [&](int f) { return f == 0 ? vE[0] : (f == 1 ? vFx[0] : vFy[0]); };
-    relax_update<2, false>(ph, L, rhs, 1.0, 0.0, omega, S0, S1, S2, vT[0], cen, out, k);
+    if (i < L.nx && j < L.ny) {
+        const uint32_t k = (uint32_t)j * (uint32_t)L.nx + (uint32_t)i;
+        const int c = (lj[0] + 1) * Q::W1 + li[0] + 1;
+        double S0, S1, S2;
+        lds_sums<Q::W1>(f1, L, ph.c, c, S0, S1, S2);
+        auto cen = [&](int f) { return f == 0 ? vE[0] : (f == 1 ? vFx[0] : vFy[0]); };
+        relax_update<2, false>(ph, L, rhs, 1.0, 0.0, omega, S0, S1, S2, vT[0], cen, out, k);
+    }
+}
+
+// Six waves per SIMD (three 512-thread blocks per CU at 8 rows; 80 VGPRs, a few
+// values spilled to scratch) measured faster than the four the unconstrained
+// register count leaves room for: the phases are latency-bound.
+template <int TY>
+__global__ __launch_bounds__(kLdsTX * TY) __attribute__((amdgpu_waves_per_eu(6))) void k_relax2_lds(
+    Phys ph, Lvl L, CSoa rhs, double omega, CSoa u, Soa out, const int* __restrict__ active)
+{
+    __shared__ Lds2<TY> q;
+    if (*active == 0) return;
+    int i0, j0;
+    tile_origin(L, TY, i0, j0);
+    relax2_tile<TY>(q, ph, L, rhs, omega, u, out, i0, j0);
 }
 
 // ---------------------------------------------------------------------------
@@ -860,6 +869,31 @@ __global__ __launch_bounds__(kLdsTX * TY) void kb_relax_lds(const BProb* __restr
     }
 }
 
+// Two finest-level sweeps per launch over a work list of 64 x TY tiles: the
+// tile arithmetic of k_relax2_lds, per problem (x_in -> the other buffer).
+// Without k_relax2_lds's six-wave cap: in the work-list loop the cap spills
+// 18 values, and the batched run measured slower with it (931 vs 999 solves/s).
+template <int TY>
+__global__ __launch_bounds__(kLdsTX * TY) void kb_relax2_lds(
+    const BProb* __restrict__ P, const BSlot* __restrict__ S, const uint32_t* __restrict__ wl, int nwl, int in_x1)
+{
+    __shared__ Lds2<TY> q;
+    for (int w_ = blockIdx.x; w_ < nwl; w_ += gridDim.x) {
+        const uint32_t item = wl[w_];
+        const int p = (int)(item >> kTileBits);
+        const uint32_t tile = item & ((1u << kTileBits) - 1u);
+        const BProb& pb = P[p];
+        if (pb.ctrl->active == 0) continue;
+        const BSlot& s = S[p * kMaxLevels];
+        const Soa& in = in_x1 ? s.x1 : s.x0;
+        const Soa& out = in_x1 ? s.x0 : s.x1;
+        const uint32_t ntx = (uint32_t)((s.L.nx + kLdsTX - 1) / kLdsTX);
+        relax2_tile<TY>(q, pb.ph, s.L, cs(s.b), pb.omega, cs(in), out, (int)(tile % ntx) * kLdsTX,
+                        (int)(tile / ntx) * TY);
+        __syncthreads();  // the next tile of this block reuses the LDS
+    }
+}
+
 template <bool NORM>
 __global__ __launch_bounds__(kBlock) void kb_relax(const BProb* __restrict__ P, const BSlot* __restrict__ S,
                                                    const uint32_t* __restrict__ wl, int nwl, int in_x1)
@@ -1203,6 +1237,15 @@ void launch_b_residual_restrict(hipStream_t st, const BProb* P, const BSlot* S, 
                            in_sel);
 }
 
+void launch_b_relax2_lds(hipStream_t st, const BProb* P, const BSlot* S, const uint32_t* wl, int nwl, int in_x1,
+                         int rows)
+{
+    if (nwl <= 0) return;
+    const dim3 g(bgrid(nwl)), b(kLdsTX * rows);
+    if (rows == 4) hipLaunchKernelGGL(kb_relax2_lds<4>, g, b, 0, st, P, S, wl, nwl, in_x1);
+    else if (rows == 8) hipLaunchKernelGGL(kb_relax2_lds<8>, g, b, 0, st, P, S, wl, nwl, in_x1);
+    else hipLaunchKernelGGL(kb_relax2_lds<16>, g, b, 0, st, P, S, wl, nwl, in_x1);
+}
 void launch_b_relax_lds(hipStream_t st, const BProb* P, const BSlot* S, const uint32_t* wl, int nwl, int in_x1,
                         int rows)
 {

@@ -350,21 +350,15 @@ __device__ __forceinline__ void mx_lds_put(float* const* f, int n, float e, floa
     f[5][n] = p.yy;
 }
 
-// Six waves per SIMD (three 512-thread blocks per CU at 8 rows; 80 VGPRs, three
-// values spilled): without the cap two blocks fit, and the pair measured slower
-// than two single sweeps.
+// The two correction sweeps of the tile at (i0, j0); every thread of the block calls it.
 template <int TY>
-__global__ __launch_bounds__(kMxTX * TY) __attribute__((amdgpu_waves_per_eu(6))) void k_mx_sweep2_lds(Phys ph, Lvl32 L, CSoa32 w, CSoa32 d, CSoa32 rhs,
-                                                             float omega, Soa32 out, const int* __restrict__ active)
+__device__ __forceinline__ void mx_sweep2_tile(MxLds2<TY>& q, const Phys& ph, const Lvl32& L, const CSoa32& w,
+                                               const CSoa32& d, const CSoa32& rhs, float omega, const Soa32& out,
+                                               int i0, int j0)
 {
     using Q = MxLds2<TY>;
     constexpr int NT = kMxTX * TY, NR = 2 * kMxTX + 2 * TY;  // threads; ring points
     static_assert(NR <= NT, "one ring point per thread");
-    __shared__ Q q;
-    if (*active == 0) return;
-    const int ntx = (L.nx + kMxTX - 1) / kMxTX;
-    const int b = (int)xcd_block();
-    const int i0 = (b % ntx) * kMxTX, j0 = (b / ntx) * TY;
     const float c = (float)ph.c, c2 = (float)ph.c2;
     const bool perx = ph.bc[0] == BC_PERIODIC, pery = ph.bc[2] == BC_PERIODIC;
     const int xe = min(i0 + kMxTX, L.nx) - 1, ye = min(j0 + TY, L.ny) - 1;  // the last final cell
@@ -459,11 +453,26 @@ __global__ __launch_bounds__(kMxTX * TY) __attribute__((amdgpu_waves_per_eu(6)))
     __syncthreads();
     // 4. second sweep on the final cells
     const int i = i0 + li[0], j = j0 + lj[0];
-    if (i >= L.nx || j >= L.ny) return;
-    const uint32_t k = (uint32_t)j * (uint32_t)L.nx + (uint32_t)i;
-    float S0, S1, S2;
-    mx_lds_sums<Q::W1>(f1, L, c, (lj[0] + 1) * Q::W1 + li[0] + 1, S0, S1, S2);
-    mx_sweep_update<2>(ph, L, w, rhs, 0.0f, 1.0f, omega, S0, S1, S2, vE[0], vFx[0], vFy[0], vT[0], out, k);
+    if (i < L.nx && j < L.ny) {
+        const uint32_t k = (uint32_t)j * (uint32_t)L.nx + (uint32_t)i;
+        float S0, S1, S2;
+        mx_lds_sums<Q::W1>(f1, L, c, (lj[0] + 1) * Q::W1 + li[0] + 1, S0, S1, S2);
+        mx_sweep_update<2>(ph, L, w, rhs, 0.0f, 1.0f, omega, S0, S1, S2, vE[0], vFx[0], vFy[0], vT[0], out, k);
+    }
+}
+
+// Six waves per SIMD (three 512-thread blocks per CU at 8 rows; 80 VGPRs, three
+// values spilled): without the cap two blocks fit, and the pair measured slower
+// than two single sweeps.
+template <int TY>
+__global__ __launch_bounds__(kMxTX * TY) __attribute__((amdgpu_waves_per_eu(6))) void k_mx_sweep2_lds(
+    Phys ph, Lvl32 L, CSoa32 w, CSoa32 d, CSoa32 rhs, float omega, Soa32 out, const int* __restrict__ active)
+{
+    __shared__ MxLds2<TY> q;
+    if (*active == 0) return;
+    const int ntx = (L.nx + kMxTX - 1) / kMxTX;
+    const int b = (int)xcd_block();
+    mx_sweep2_tile<TY>(q, ph, L, w, d, rhs, omega, out, (b % ntx) * kMxTX, (b / ntx) * TY);
 }
 
 template <int DIM>
