@@ -4,7 +4,8 @@
 // over a 1-D launch in the XCD-aware block order of m1::xcd_block(); cell
 // (i,j) = (t % nx, t / nx).  LDS-staged kernels (k_relax_lds, k_apply_lds,
 // k_residual_restrict) own 2-D tiles and evaluate each point's closure once;
-// k_smooth_tb runs a whole smoothing leg of a small level per launch.  Fields
+// k_relax2_lds (and its batched form) runs two consecutive finest sweeps per
+// launch; k_smooth_tb runs a whole smoothing leg of a small level per launch.  Fields
 // are SoA FP64 arrays.  The work is a memory-bound nonlinear 5-point stencil:
 // no MFMA.  The per-cell bodies are __device__ functions shared by all these
 // kernels, the batched kernels and k_tail, which runs the whole bottom of the

@@ -5,7 +5,8 @@
 //                FP64 admissibility projection, then r = b - A(v) in FP64 (the
 //                stopping norm), FP32 copies of the new base state and of r;
 //   k_mx_sweep   relaxed Jacobi sweeps on the correction d: D(v+d') - D(v) =
-//                r + S(v+d) - S(v) (LDS-staged form k_mx_sweep_lds);
+//                r + S(v+d) - S(v) (LDS-staged form k_mx_sweep_lds; two
+//                consecutive sweeps per launch: k_mx_sweep2_lds);
 //   k_mx_residual_restrict  residual of the correction equation,
 //                rho = r - N_v(d), restricted with v and d to level 1 as it is
 //                formed (k_mx_apply + k_mx_restrict when switched off);
