@@ -318,7 +318,7 @@ SERVE_DESC = ("Poisson stream, side log-uniform in 64..2048, contrast 10^U[0,6],
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        print(json.dumps({"error": "the solver runs on one GPU; --gpus must be 1 (sharding across GPUs is not implemented)"}))
         sys.exit(2)
     import torch
     torch.cuda.init()
