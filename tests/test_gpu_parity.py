@@ -125,6 +125,37 @@ def test_sweep_pair_matches_two_sweeps(nx, ny, bcs, precision):
         np.testing.assert_array_equal(x, res[0, nu0, omega])
 
 
+@pytest.mark.parametrize("case", ["hot1024", "periodic1024x768"])
+def test_sweep_pair_full_size(case):
+    """At the benchmark's size (1024^2 hot wall: a Dirichlet wall and
+    reflective sides) and on a periodic 1024 x 768 grid, two and three
+    sweeps through m1_sweeps are the same to the bit with the pair launch off
+    and at 4, 8 and 16 tile rows."""
+    announce("sweep pair full size", case)
+    if case == "hot1024":
+        prob, v, sig, _ = inputs.hot_wall_2d(n=1024)
+        w = v.copy()
+        w[0] *= 1.5  # a right-hand side away from the state
+    else:
+        prob, v, sig = inputs.random_problem(41, 2, 1024, 768, cfl=100.0, block=32)
+        w = inputs.random_problem(42, 2, 1024, 768, cfl=100.0, block=32)[1]
+    b = w.copy()
+    b[3] *= prob["c_v"]
+    vd, bd = to_dev(v), to_dev(b)
+    P = plan_for(prob, sig, levels=1)
+    old = binding.tune_get("pair_rows")
+    try:
+        res = {}
+        for rows in (0, 4, 8, 16):
+            binding.tune_set("pair_rows", rows)
+            for n in (2, 3):
+                res[rows, n] = to_host(P.sweeps(bd, vd, n))
+    finally:
+        binding.tune_set("pair_rows", old)
+    for (rows, n), x in res.items():
+        np.testing.assert_array_equal(x, res[0, n])
+
+
 @pytest.mark.parametrize("levels,nu0,sweep_rows", [(1, 3, 4), (1, 2, 4), (1, 1, 4), (0, 2, 0), (0, 4, 0),
                                                     (0, 3, 4), (0, 2, 4)])
 def test_step_result_with_and_without_sweep_pairs(levels, nu0, sweep_rows):
