@@ -581,6 +581,13 @@ void mx_vcycle(m1_plan& P, Soa& cur64, Soa& other64, const Gate& G, bool control
                               cs(el[l + 1]), cs(c.d), el[l], G.active);
         el[l] = mx_pseudo_smooth(P, l, G, el[l], false);
     }
+    const Soa32 post = same32(el[0], P.dA) ? P.dB : P.dA;
+    if (P.dim == 2 && p.nu0 >= 1 &&
+        m1::launch_mx_prolong_sweep(P.st, P.ph, f0.L32, cs(P.base32), cs(cur64), cs(el[0]), cs(el[1]),
+                                    cs(P.lev[1].d), P.px, P.py, p.eta, cs(P.r32), om, post, G.active)) {
+        pend = sweeps(post, p.nu0 - 1, false);  // the first post-sweep ran with the correction
+        return;
+    }
     m1::launch_mx_prolong_fine(P.st, P.dim, P.ph, f0.nx, f0.ny, P.px, P.py, p.eta, cs(cur64), cs(el[0]), cs(el[1]),
                                cs(P.lev[1].d), el[0], G.active);
     pend = sweeps(el[0], p.nu0, false);

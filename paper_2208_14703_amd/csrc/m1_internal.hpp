@@ -210,6 +210,11 @@ void launch_mx_prolong(hipStream_t st, int dim, const Phys& ph, int nx, int ny, 
                        CSoa32 e, CSoa32 ec, CSoa32 dc, Soa32 out, const int* active);
 void launch_mx_prolong_fine(hipStream_t st, int dim, const Phys& ph, int nx, int ny, int px, int py, double eta,
                             CSoa v, CSoa32 e, CSoa32 ec, CSoa32 dc, Soa32 out, const int* active);
+// 2-D: the coarse correction of the finest level and the first post-smoothing
+// sweep in one launch (LDS-staged; false, nothing launched, when unstaged)
+bool launch_mx_prolong_sweep(hipStream_t st, const Phys& ph, const Lvl32& L, CSoa32 w, CSoa v, CSoa32 e, CSoa32 ec,
+                             CSoa32 dc, int px, int py, double eta, CSoa32 rhs, float omega, Soa32 out,
+                             const int* active);
 void launch_mx_restrict(hipStream_t st, int dim, int nxf, int nyf, int px, int py, const Fields32& F,
                         const int* active);
 void launch_mx_tail(hipStream_t st, int dim, const TailArgs32* args_dev, double dtau, const double* dtau_dev,

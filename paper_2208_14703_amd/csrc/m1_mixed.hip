@@ -10,7 +10,9 @@
 //   k_mx_residual_restrict  residual of the correction equation,
 //                rho = r - N_v(d), restricted with v and d to level 1 as it is
 //                formed (k_mx_apply + k_mx_restrict when switched off);
-//   k_mx_prolong_fine  d += P(e - d_c) with the admissibility test of v + d in FP64.
+//   k_mx_prolong_fine  d += P(e - d_c) with the admissibility test of v + d in FP64
+//                (when the sweeps are staged, fused with the first post-smoothing
+//                sweep: k_mx_prolong_sweep_lds).
 // Coarse levels carry a base w_l = R(w_{l-1}), a correction e_l and the
 // right-hand side g_l = N_w(R d) + R(rho) of the FAS correction equation
 // N_w(e) = g, smoothed by pseudo-time steps in increment form (k_mx_pseudo).
@@ -221,10 +223,12 @@ struct MxTile {
 };
 
 // Stage the 64 x TY tile at (i0, j0): correction (after the boundary rule) and
-// c^2 P increment of every tile and halo point.
-template <int TY>
-__device__ __forceinline__ void mx_stage_tile(MxTile<TY>& q, const Phys& ph, const Lvl32& L, const CSoa32& w,
-                                              const CSoa32& d, int i0, int j0)
+// c^2 P increment of every tile and halo point.  d_at(k, E, Fx, Fy, T) gives
+// the correction of cell k; returns the T correction of this thread's own cell
+// (0 outside the grid).
+template <int TY, class DAt>
+__device__ __forceinline__ float mx_stage_tile_at(MxTile<TY>& q, const Phys& ph, const Lvl32& L, const CSoa32& w,
+                                                  DAt&& d_at, int i0, int j0)
 {
     static_assert(kMxTX * TY >= 2 * kMxTX + 2 * TY, "the halo needs 2 rows and 2 columns of threads");
     constexpr int W = MxTile<TY>::W;
@@ -242,13 +246,14 @@ __device__ __forceinline__ void mx_stage_tile(MxTile<TY>& q, const Phys& ph, con
             side = gj < 0 ? 2 : 3;
             gj = pery ? (gj < 0 ? gj + L.ny : gj - L.ny) : (gj < 0 ? 0 : L.ny - 1);
         }
-        float e = 0.0f, gx = 0.0f, gy = 0.0f;
+        float e = 0.0f, gx = 0.0f, gy = 0.0f, dT = 0.0f;
         DP p{0.0f, 0.0f, 0.0f};
         if (need) {
             const uint32_t k = (uint32_t)gj * (uint32_t)L.nx + (uint32_t)gi;
-            float E, Fx, Fy;
-            ghost_inc(ph, side, !(ox || oy), ldf(w.E, k), ldf(w.Fx, k), ldf(w.Fy, k), ldf(d.E, k), ldf(d.Fx, k),
-                      ldf(d.Fy, k), E, Fx, Fy, e, gx, gy);
+            float E, Fx, Fy, dE, dFx, dFy;
+            d_at(k, dE, dFx, dFy, dT);
+            ghost_inc(ph, side, !(ox || oy), ldf(w.E, k), ldf(w.Fx, k), ldf(w.Fy, k), dE, dFx, dFy, E, Fx, Fy, e, gx,
+                      gy);
             p = closure_inc(c, c2, E, Fx, Fy, e, gx, gy);
         }
         const int n = (lj + 1) * W + li + 1;
@@ -258,22 +263,40 @@ __device__ __forceinline__ void mx_stage_tile(MxTile<TY>& q, const Phys& ph, con
         q.xx[n] = p.xx;
         q.xy[n] = p.xy;
         q.yy[n] = p.yy;
+        return dT;
     };
     const int t = threadIdx.x;
-    gather(t % kMxTX, t / kMxTX);
+    const float own = gather(t % kMxTX, t / kMxTX);
     if (t < 2 * kMxTX) {
         gather(t % kMxTX, t < kMxTX ? -1 : TY);
     } else if (t < 2 * kMxTX + 2 * TY) {
         const int r = t - 2 * kMxTX;
         gather(r < TY ? -1 : kMxTX, r % TY);
     }
+    return own;
+}
+
+template <int TY>
+__device__ __forceinline__ void mx_stage_tile(MxTile<TY>& q, const Phys& ph, const Lvl32& L, const CSoa32& w,
+                                              const CSoa32& d, int i0, int j0)
+{
+    (void)mx_stage_tile_at<TY>(
+        q, ph, L, w,
+        [&](uint32_t k, float& E, float& Fx, float& Fy, float& T) {
+            E = ldf(d.E, k);
+            Fx = ldf(d.Fx, k);
+            Fy = ldf(d.Fy, k);
+            T = 0.0f;  // the sweep reads its own cell's T correction itself
+        },
+        i0, j0);
 }
 
 // The sweep of this thread's cell of a staged tile (nothing outside the grid).
-template <int TY>
+// OWN_T: the cell's T correction is dT_own (else it is read from d).
+template <int TY, bool OWN_T = false>
 __device__ __forceinline__ void mx_tile_sweep(const MxTile<TY>& q, const Phys& ph, const Lvl32& L, const CSoa32& w,
                                               const CSoa32& d, const CSoa32& rhs, float beta, float gamma,
-                                              float omega, const Soa32& out, int i0, int j0)
+                                              float omega, const Soa32& out, int i0, int j0, float dT_own = 0.0f)
 {
     constexpr int W = MxTile<TY>::W;
     const int li = threadIdx.x % kMxTX, lj = threadIdx.x / kMxTX, i = i0 + li, j = j0 + lj;
@@ -289,7 +312,8 @@ __device__ __forceinline__ void mx_tile_sweep(const MxTile<TY>& q, const Phys& p
     nb(n + 1, L.kx, -1.0f, true);
     nb(n - W, L.ky, +1.0f, false);
     nb(n + W, L.ky, -1.0f, false);
-    mx_sweep_update<2>(ph, L, w, rhs, beta, gamma, omega, S0, S1, S2, q.e[n], q.gx[n], q.gy[n], ldf(d.T, k), out, k);
+    mx_sweep_update<2>(ph, L, w, rhs, beta, gamma, omega, S0, S1, S2, q.e[n], q.gx[n], q.gy[n],
+                       OWN_T ? dT_own : ldf(d.T, k), out, k);
 }
 
 // LDS-staged sweep on the correction (2-D, d given): a block owns a 64 x TY
@@ -680,10 +704,13 @@ __global__ __launch_bounds__(kBlock32) void k_mx_prolong(Phys ph, int nx, int ny
     mx_prolong_cell<DIM>(ph, nx, ny, sh, px, py, eta, w, e, ec, dc, out, k, live);
 }
 
+// The corrected correction of fine cell k: e + theta P(e_c - d_c), theta from
+// the admissibility test of v + e + P(e_c - d_c) in FP64.
 template <int DIM>
-__device__ __forceinline__ void mx_prolong_fine_cell(const Phys& ph, int nx, int ny, int sh, int px, int py,
-                                                     double eta, const CSoa& v, const CSoa32& e, const CSoa32& ec,
-                                                     const CSoa32& dc, const Soa32& out, uint32_t k, bool live)
+__device__ __forceinline__ void mx_prolong_fine_values(const Phys& ph, int nx, int ny, int sh, int px, int py,
+                                                       double eta, const CSoa& v, const CSoa32& e, const CSoa32& ec,
+                                                       const CSoa32& dc, uint32_t k, float& oE, float& oFx,
+                                                       float& oFy, float& oT)
 {
     float c0, c1, c2, c3;
     coarse_corr<DIM>(nx, ny, sh, px, py, ec, dc, k, c0, c1, c2, c3);
@@ -693,11 +720,24 @@ __device__ __forceinline__ void mx_prolong_fine_cell(const Phys& ph, int nx, int
     double th = 1.0;
     if (!admissible(ph.c2, sE + c0, sFx + c1, sFy + c2, sT + c3))
         th = eta * fmin(ray_len(ph.c2, sE, sFx, sFy, sT, c0, c1, c2, c3), 1.0);
+    oE = (float)fma(th, (double)c0, (double)eE);
+    oFx = (float)fma(th, (double)c1, (double)eFx);
+    oFy = (DIM == 2) ? (float)fma(th, (double)c2, (double)eFy) : 0.0f;
+    oT = (float)fma(th, (double)c3, (double)eT);
+}
+
+template <int DIM>
+__device__ __forceinline__ void mx_prolong_fine_cell(const Phys& ph, int nx, int ny, int sh, int px, int py,
+                                                     double eta, const CSoa& v, const CSoa32& e, const CSoa32& ec,
+                                                     const CSoa32& dc, const Soa32& out, uint32_t k, bool live)
+{
+    float E, Fx, Fy, T;
+    mx_prolong_fine_values<DIM>(ph, nx, ny, sh, px, py, eta, v, e, ec, dc, k, E, Fx, Fy, T);
     if (!live) return;
-    stf(out.E, k, (float)fma(th, (double)c0, (double)eE));
-    stf(out.Fx, k, (float)fma(th, (double)c1, (double)eFx));
-    if (DIM == 2) stf(out.Fy, k, (float)fma(th, (double)c2, (double)eFy));
-    stf(out.T, k, (float)fma(th, (double)c3, (double)eT));
+    stf(out.E, k, E);
+    stf(out.Fx, k, Fx);
+    if (DIM == 2) stf(out.Fy, k, Fy);
+    stf(out.T, k, T);
 }
 
 template <int DIM>
@@ -709,6 +749,32 @@ __global__ __launch_bounds__(kBlock32) void k_mx_prolong_fine(Phys ph, int nx, i
     const uint32_t k = (uint32_t)xcd_block() * kBlock32 + threadIdx.x;
     if (k >= (uint32_t)nx * (uint32_t)ny) return;
     mx_prolong_fine_cell<DIM>(ph, nx, ny, sh, px, py, eta, v, e, ec, dc, out, k, live);
+}
+
+// Coarse correction of the finest level fused with the first post-smoothing
+// correction sweep (2-D; beta = 0, gamma = 1): the staging of k_mx_sweep_lds
+// takes each tile and halo point's correction from mx_prolong_fine_values
+// instead of memory, so the corrected correction is never stored and the
+// result is k_mx_prolong_fine then k_mx_sweep_lds to the bit.
+template <int TY>
+__global__ __launch_bounds__(kMxTX * TY) void k_mx_prolong_sweep_lds(Phys ph, Lvl32 L, CSoa32 w, CSoa v, CSoa32 e,
+                                                                    CSoa32 ec, CSoa32 dc, int sh, int px, int py,
+                                                                    double eta, CSoa32 rhs, float omega, Soa32 out,
+                                                                    const int* __restrict__ active)
+{
+    __shared__ MxTile<TY> q;
+    if (*active == 0) return;
+    const int ntx = (L.nx + kMxTX - 1) / kMxTX;
+    const int b = (int)xcd_block();
+    const int i0 = (b % ntx) * kMxTX, j0 = (b / ntx) * TY;
+    const float dT = mx_stage_tile_at<TY>(
+        q, ph, L, w,
+        [&](uint32_t k, float& E, float& Fx, float& Fy, float& T) {
+            mx_prolong_fine_values<2>(ph, L.nx, L.ny, sh, px, py, eta, v, e, ec, dc, k, E, Fx, Fy, T);
+        },
+        i0, j0);
+    __syncthreads();
+    mx_tile_sweep<TY, true>(q, ph, L, w, CSoa32{}, rhs, 0.0f, 1.0f, omega, out, i0, j0, dT);
 }
 
 // FP32 restriction of NF fields (base, correction, residual of a level) for
@@ -1294,6 +1360,20 @@ void launch_mx_prolong(hipStream_t st, int dim, const Phys& ph, int nx, int ny, 
 {
     MX_DISPATCH(dim, k_mx_prolong, nblk((int64_t)nx * ny), ph, nx, ny, row_shift(nx), px, py, eta, w, e, ec, dc, out,
                 active);
+}
+
+bool launch_mx_prolong_sweep(hipStream_t st, const Phys& ph, const Lvl32& L, CSoa32 w, CSoa v, CSoa32 e, CSoa32 ec,
+                             CSoa32 dc, int px, int py, double eta, CSoa32 rhs, float omega, Soa32 out,
+                             const int* active)
+{
+    // staged when the mixed sweeps are; 64 x 8 tiles whatever their rows (the prolongation is recomputed on the
+    // halo: 8 rows measured faster than 4 or 16)
+    constexpr int rows = 8;
+    if (mx_sweep_rows() <= 0) return false;
+    const unsigned ntx = (unsigned)((L.nx + kMxTX - 1) / kMxTX), nty = (unsigned)((L.ny + rows - 1) / rows);
+    hipLaunchKernelGGL(k_mx_prolong_sweep_lds<rows>, dim3(ntx * nty), dim3(kMxTX * rows), 0, st, ph, L, w, v, e, ec,
+                       dc, row_shift(L.nx), px, py, eta, rhs, omega, out, active);
+    return true;
 }
 
 void launch_mx_prolong_fine(hipStream_t st, int dim, const Phys& ph, int nx, int ny, int px, int py, double eta,
