@@ -1262,6 +1262,7 @@ struct m1_engine {
     };
     List fine;
     List fine2;    // 64 x rows tiles of the finest levels for the staged sweep (rows == 0: none)
+    List fineU, fineN;  // FP64, staged: the fine2 tiles of problems with a coarse correction, and of the others
     List fine3;    // 64 x prow tiles for two sweeps per launch (pairs only)
     int prow = 0;  // tile rows of the pair kernel
     bool pairs = false;  // FP64: consecutive finest sweeps run two per launch
@@ -1529,6 +1530,21 @@ m1_status rebuild(m1_engine& E)
         }
     }
     E.fine2.n = (int)E.hwl.size() - E.fine2.off;
+    E.fineU = E.fineN = {};
+    if (!E.mixed && E.rows > 0) {
+        for (int u = 1; u >= 0; --u) {
+            m1_engine::List& L = u ? E.fineU : E.fineN;
+            L.off = (int)E.hwl.size();
+            for (int i = 0; i < np; ++i) {
+                const m1_plan& P = *E.running[i]->plan;
+                if ((std::min(P.lt, P.L - 1) > 0) != (u == 1)) continue;  // the predicate of up[0]
+                const LevelBuf& lv = P.lev[0];
+                const uint32_t nt = (uint32_t)((lv.nx + 63) / 64) * (uint32_t)((lv.ny + E.rows - 1) / E.rows);
+                for (uint32_t t = 0; t < nt; ++t) E.hwl.push_back(((uint32_t)i << m1::kTileBits) | t);
+            }
+            L.n = (int)E.hwl.size() - L.off;
+        }
+    }
     // FP64, two sweeps per launch: the pre-sweeps take 1 + ceil((nu0 - 1) / 2) launches and the
     // post-sweeps ceil(nu0 / 2), an even total (2k + 2 for nu0 = 2k + 1) for odd nu0 only, which keeps
     // the cycle ending in the buffer it began from.  (The mixed engine keeps single sweeps: its pair
@@ -1647,9 +1663,12 @@ void b_vcycle(m1_engine& E)
         if (!E.fused) m1::launch_b_apply(E.st, E.dP, E.dS, wl + E.up[l].off, E.up[l].n, l, 1);
     }
     m1::launch_b_tail(E.st, E.dP, E.dPL + E.n_all, E.n_tail);
+    // staged: the finest level's coarse correction runs with its first post-sweep (then pairs, which keeps
+    // the launch count of the post leg, ceil(nu0 / 2) for odd nu0)
+    const bool up_fused = E.rows > 0 && nu0 >= 1;
     for (int l = E.Lmax - 2; l >= 0; --l) {
         if (l == 0) {
-            m1::launch_b_prolong(E.st, E.dP, E.dS, wl + E.up[0].off, E.up[0].n, 0, in_x1, 0);
+            if (!up_fused) m1::launch_b_prolong(E.st, E.dP, E.dS, wl + E.up[0].off, E.up[0].n, 0, in_x1, 0);
         } else {
             m1::launch_b_prolong(E.st, E.dP, E.dS, wl + E.up[l].off, E.up[l].n, l, 1, 2);
             int in = 2;
@@ -1660,7 +1679,14 @@ void b_vcycle(m1_engine& E)
             }
         }
     }
-    for (int s = 0; s < nu0;) {
+    int s0 = 0;
+    if (up_fused) {
+        m1::launch_b_relax_lds(E.st, E.dP, E.dS, wl + E.fineU.off, E.fineU.n, in_x1, E.rows, true);
+        m1::launch_b_relax_lds(E.st, E.dP, E.dS, wl + E.fineN.off, E.fineN.n, in_x1, E.rows);
+        in_x1 ^= 1;
+        s0 = 1;
+    }
+    for (int s = s0; s < nu0;) {
         if (E.pairs && nu0 - s >= 2) {
             m1::launch_b_relax2_lds(E.st, E.dP, E.dS, wl + E.fine3.off, E.fine3.n, in_x1, E.prow);
             s += 2;

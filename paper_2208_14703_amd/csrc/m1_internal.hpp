@@ -175,7 +175,7 @@ void launch_b_relax2_lds(hipStream_t st, const BProb* P, const BSlot* S, const u
                          int rows);
 // staged finest-level sweep over a work list of 64 x rows tiles (rows 4, 8 or 16)
 void launch_b_relax_lds(hipStream_t st, const BProb* P, const BSlot* S, const uint32_t* wl, int nwl, int in_x1,
-                        int rows);
+                        int rows, bool up = false);
 void launch_b_norm_control(hipStream_t st, const BProb* P, const int* plist, int np, int mixed);
 void launch_b_apply(hipStream_t st, const BProb* P, const BSlot* S, const uint32_t* wl, int nwl, int level, int in_sel);
 void launch_b_restrict(hipStream_t st, const BProb* P, const BSlot* S, const uint32_t* wl, int nwl, int level,

@@ -837,13 +837,16 @@ __global__ __launch_bounds__(kRcThreads) void kb_residual_restrict(const BProb* 
 
 // Batched LDS-staged finest-level sweep (no norm): work-list entries are the
 // 64 x TY tiles of each problem's finest level (row-major tile index); the
-// staging and the arithmetic are those of k_relax_lds.
-template <int TY>
+// staging and the arithmetic are those of k_relax_lds.  UP: the first sweep
+// after the coarse-grid correction, fused with it as in k_relax_lds (the
+// entries are then those of problems with a coarse level).
+template <int TY, bool UP>
 __global__ __launch_bounds__(kLdsTX * TY) void kb_relax_lds(const BProb* __restrict__ P, const BSlot* __restrict__ S,
                                                            const uint32_t* __restrict__ wl, int nwl, int in_x1)
 {
     constexpr int W = LdsTile<TY>::W;
     __shared__ LdsTile<TY> q;
+    __shared__ double qT[UP ? LdsTile<TY>::N : 1];
     for (int w_ = blockIdx.x; w_ < nwl; w_ += gridDim.x) {
         const uint32_t item = wl[w_];
         const int p = (int)(item >> kTileBits);
@@ -855,7 +858,12 @@ __global__ __launch_bounds__(kLdsTX * TY) void kb_relax_lds(const BProb* __restr
         const Soa& out = in_x1 ? s.x0 : s.x1;
         const uint32_t ntx = (uint32_t)((s.L.nx + kLdsTX - 1) / kLdsTX);
         const int i0 = (int)(tile % ntx) * kLdsTX, j0 = (int)(tile / ntx) * TY;
-        stage_tile<TY, false>(q, nullptr, pb.ph, s.L, cs(in), i0, j0, CSoa{}, CSoa{}, 0, 0, 0.0);
+        if (UP) {
+            const BSlot& cl = S[p * kMaxLevels + 1];
+            stage_tile<TY, true>(q, qT, pb.ph, s.L, cs(in), i0, j0, cs(cl.u), cs(cl.v), pb.px, pb.py, pb.eta);
+        } else {
+            stage_tile<TY, false>(q, nullptr, pb.ph, s.L, cs(in), i0, j0, CSoa{}, CSoa{}, 0, 0, 0.0);
+        }
         __syncthreads();
         const int li = threadIdx.x % kLdsTX, lj = threadIdx.x / kLdsTX, i = i0 + li, j = j0 + lj;
         if (i < s.L.nx && j < s.L.ny) {
@@ -864,7 +872,8 @@ __global__ __launch_bounds__(kLdsTX * TY) void kb_relax_lds(const BProb* __restr
             double S0, S1, S2;
             tile_sums<TY>(q, s.L, pb.ph.c, c, S0, S1, S2);
             auto cen = [&](int f) { return f == 0 ? q.E[c] : (f == 1 ? q.Fx[c] : q.Fy[c]); };
-            relax_update<2, false>(pb.ph, s.L, cs(s.b), 1.0, 0.0, pb.omega, S0, S1, S2, ld(in.T, k), cen, out, k);
+            relax_update<2, false>(pb.ph, s.L, cs(s.b), 1.0, 0.0, pb.omega, S0, S1, S2, UP ? qT[c] : ld(in.T, k), cen,
+                                   out, k);
         }
         __syncthreads();  // the next tile of this block reuses the LDS
     }
@@ -1248,13 +1257,21 @@ void launch_b_relax2_lds(hipStream_t st, const BProb* P, const BSlot* S, const u
     else hipLaunchKernelGGL(kb_relax2_lds<16>, g, b, 0, st, P, S, wl, nwl, in_x1);
 }
 void launch_b_relax_lds(hipStream_t st, const BProb* P, const BSlot* S, const uint32_t* wl, int nwl, int in_x1,
-                        int rows)
+                        int rows, bool up)
 {
     if (nwl <= 0) return;
     const dim3 g(bgrid(nwl)), b(kLdsTX * rows);
-    if (rows == 4) hipLaunchKernelGGL(kb_relax_lds<4>, g, b, 0, st, P, S, wl, nwl, in_x1);
-    else if (rows == 8) hipLaunchKernelGGL(kb_relax_lds<8>, g, b, 0, st, P, S, wl, nwl, in_x1);
-    else hipLaunchKernelGGL(kb_relax_lds<16>, g, b, 0, st, P, S, wl, nwl, in_x1);
+#define M1_B_RELAX_LDS(R)                                                                                             \
+    if (up) hipLaunchKernelGGL((kb_relax_lds<R, true>), g, b, 0, st, P, S, wl, nwl, in_x1);                          \
+    else hipLaunchKernelGGL((kb_relax_lds<R, false>), g, b, 0, st, P, S, wl, nwl, in_x1)
+    if (rows == 4) {
+        M1_B_RELAX_LDS(4);
+    } else if (rows == 8) {
+        M1_B_RELAX_LDS(8);
+    } else {
+        M1_B_RELAX_LDS(16);
+    }
+#undef M1_B_RELAX_LDS
 }
 
 void launch_b_relax(hipStream_t st, const BProb* P, const BSlot* S, const uint32_t* wl, int nwl, int in_x1, int norm)
