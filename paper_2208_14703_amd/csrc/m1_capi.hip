@@ -519,11 +519,14 @@ void mx_vcycle(m1_plan& P, Soa& cur64, Soa& other64, const Gate& G, bool control
 {
     const m1_params& p = P.params;
     const LevelBuf& f0 = P.lev[0];
+    const float om = (float)p.omega;
+    // the first pre-sweep (from a zero correction, into dA) runs inside the residual launch
+    const bool zero_fused = p.nu0 >= 1;
     m1::launch_mx_resid(P.st, P.dim, P.ph, f0.L, p.eta, cs(cur64), first ? CSoa32{} : cs(pend), cs(P.b), other64,
-                        P.base32, P.r32, control ? P.partials : nullptr, G.active);
+                        P.base32, P.r32, control ? P.partials : nullptr, G.active, zero_fused ? &f0.L32 : nullptr, om,
+                        zero_fused ? P.dA : Soa32{});
     std::swap(cur64, other64);
     if (control) m1::launch_norm_control(P.st, P.partials, P.npart, P.dctrl);
-    const float om = (float)p.omega;
     auto sweeps = [&](Soa32 d, int count, bool from_zero) {
         for (int s = 0; s < count;) {
             const Soa32 out = same32(d, P.dA) ? P.dB : P.dA;
@@ -541,7 +544,7 @@ void mx_vcycle(m1_plan& P, Soa& cur64, Soa& other64, const Gate& G, bool control
         }
         return d;
     };
-    Soa32 d = sweeps(P.dB, p.nu0, true);
+    Soa32 d = zero_fused ? sweeps(P.dA, p.nu0 - 1, false) : sweeps(P.dB, p.nu0, true);
     if (P.L == 1) {
         pend = d;
         return;
@@ -1711,10 +1714,12 @@ void bm_vcycle(m1_engine& E)
     // (the first one, from zero, writes buffer 0) and every sweep of either leg
     // moved it, 2 nu0 moves in all, so it ends in buffer 1 whatever nu0
     const int pend = 1;
-    m1::launch_bm_resid(E.st, E.dP, E.dS, E.dS32, wl + E.fine.off, E.fine.n, pend);
+    // the first pre-sweep (from a zero correction, into buffer 0) runs inside the residual launch
+    const bool zero_fused = nu0 >= 1;
+    m1::launch_bm_resid(E.st, E.dP, E.dS, E.dS32, wl + E.fine.off, E.fine.n, pend, zero_fused);
     m1::launch_b_norm_control(E.st, E.dP, E.dPL, E.n_all, 1);
-    int d = 1;
-    for (int s = 0; s < nu0; ++s) {
+    int d = zero_fused ? 0 : 1;
+    for (int s = zero_fused ? 1 : 0; s < nu0; ++s) {
         const int out = d ^ 1;
         if (s > 0 && E.rows > 0)
             m1::launch_bm_sweep_lds(E.st, E.dP, E.dS32, wl + E.fine2.off, E.fine2.n, d, out, E.rows);

@@ -190,8 +190,10 @@ void launch_b_init_ctrl(hipStream_t st, const BProb* P, const BSlot* S, const in
 void launch_b_flip_copy(hipStream_t st, const BProb* P, const BSlot* S, const uint32_t* wl, int nwl);
 void launch_b_gather_ctrl(hipStream_t st, const BProb* P, int np, Ctrl* out);
 
+// zL, zd: also the cycle's first correction sweep (from d = 0; level zL, relaxation zomega) into zd
 void launch_mx_resid(hipStream_t st, int dim, const Phys& ph, const Lvl& L, double eta, CSoa v, CSoa32 d, CSoa b,
-                     Soa vnew, Soa32 base, Soa32 r32, double* partials, const int* active);
+                     Soa vnew, Soa32 base, Soa32 r32, double* partials, const int* active,
+                     const Lvl32* zL = nullptr, float zomega = 0.0f, Soa32 zd = {});
 // two mixed-precision correction sweeps (2-D, beta = 0, gamma = 1, d given) in one launch, d -> out;
 // false (nothing launched) when the pair launch shape is off
 bool launch_mx_sweep2(hipStream_t st, const Phys& ph, const Lvl32& L, CSoa32 w, CSoa32 d, CSoa32 rhs, float omega,
@@ -224,8 +226,9 @@ void launch_to_f32(hipStream_t st, int64_t n, const double* a, float* b);
 // batched mixed-precision kernels (m1_mixed.hip).  Fine-level selectors: the
 // FP64 state is x0 or x1 by ctrl->flip; sel 0/1 picks dA/dB.  Coarse levels:
 // sel 0 = d, 1 = e, 2 = e2.
+// zero: also the first pre-sweep (from a zero correction) into buffer 0
 void launch_bm_resid(hipStream_t st, const BProb* P, const BSlot* S, const BSlot32* S32, const uint32_t* wl, int nwl,
-                     int pend_sel);
+                     int pend_sel, int zero);
 void launch_bm_sweep(hipStream_t st, const BProb* P, const BSlot32* S32, const uint32_t* wl, int nwl, int in_sel,
                      int out_sel, int from_zero);
 // fused residual of level - 1 and restriction to `level` over a work list of 32 x 4 coarse tiles

@@ -3,7 +3,9 @@
 // Per V-cycle on the finest level:
 //   k_mx_resid   apply the pending FP32 correction to the FP64 state with the
 //                FP64 admissibility projection, then r = b - A(v) in FP64 (the
-//                stopping norm), FP32 copies of the new base state and of r;
+//                stopping norm), FP32 copies of the new base state and of r,
+//                and the cycle's first correction sweep (from d = 0, purely
+//                local);
 //   k_mx_sweep   relaxed Jacobi sweeps on the correction d: D(v+d') - D(v) =
 //                r + S(v+d) - S(v) (LDS-staged form k_mx_sweep_lds; two
 //                consecutive sweeps per launch: k_mx_sweep2_lds);
@@ -88,12 +90,42 @@ __device__ __forceinline__ void nb_upd64(const Phys& ph, double eta, int side, b
     Fy = fma(sy, lFy, dir ? ph.bcFy[side] : 0.0);
 }
 
+// Relaxed Jacobi update of the correction at one cell from its values: off-diagonal sums S, current
+// correction d, right-hand side r, FP32 opacities and base temperature.
+template <int DIM>
+__device__ __forceinline__ void mx_sweep_point(const Phys& ph, const Lvl32& L, float beta, float gamma, float omega,
+                                               float S0, float S1, float S2, float dE, float dFx, float dFy, float dT,
+                                               float rE, float rFx, float rFy, float rT, float sa, float ss, float wT,
+                                               float& oE, float& oFx, float& oFy, float& oT)
+{
+    const double QE = fmaf(gamma, S0, rE);
+    const double QFx = fmaf(gamma, S1, rFx);
+    const double QFy = (DIM == 2) ? fmaf(gamma, S2, rFy) : 0.0;
+    const double QT = rT;
+    const double ka = (double)L.cdt * sa, ks = (double)L.cdt * ss;
+    float xE, xFx, xFy, xT;
+    local_solve_inc(beta, gamma, L.a, ka, ks, ph.c_v, ph.a_r, QE, QFx, QFy, QT, wT, dT, xE, xFx, xFy, xT);
+    oE = fmaf(omega, xE - dE, dE);
+    oFx = fmaf(omega, xFx - dFx, dFx);
+    oFy = (DIM == 2) ? fmaf(omega, xFy - dFy, dFy) : 0.0f;
+    oT = fmaf(omega, xT - dT, dT);
+}
+
+// The first correction sweep of a cycle starts from d = 0: each cell needs only its own base temperature,
+// residual and opacities, which mx_resid_cell has in hand (as the FP32 values it stores, those the sweep would
+// read).  With z.d.E set, mx_resid_cell runs that sweep too and stores its result in z.d.
+struct MxZero {
+    Lvl32 L;
+    float omega;
+    Soa32 d;
+};
+
 // v_new = proj(v + d); r = b - A(v_new) (FP64); base32 = (float) v_new; r32 = (float) r.
 // Returns the cell's share of |r|^2.  v and v_new must not alias (neighbours read v).
 template <int DIM>
 __device__ __forceinline__ double mx_resid_cell(const Phys& ph, const Lvl& L, double eta, const CSoa& v,
                                                 const CSoa32& d, const CSoa& b, const Soa& vnew, const Soa32& base,
-                                                const Soa32& r32, uint32_t k, int i, int j)
+                                                const Soa32& r32, uint32_t k, int i, int j, const MxZero& z = {})
 {
     double S0 = 0.0, S1 = 0.0, S2 = 0.0, e, fx, fy;
     const uint32_t wx = (uint32_t)(L.nx - 1);
@@ -110,7 +142,8 @@ __device__ __forceinline__ double mx_resid_cell(const Phys& ph, const Lvl& L, do
     }
     double E, Fx, Fy, T;
     upd64<DIM>(ph, eta, v, d, k, E, Fx, Fy, T);
-    const double ka = L.cdt * ld(L.sa, k), ks = L.cdt * ld(L.ss, k);
+    const double sa = ld(L.sa, k), ss = ld(L.ss, k);
+    const double ka = L.cdt * sa, ks = L.cdt * ss;
     const double T2 = T * T;
     const double ex = ka * fma(-ph.a_r * T2, T2, E);
     const double dF = L.a + ka + ks;
@@ -130,6 +163,16 @@ __device__ __forceinline__ double mx_resid_cell(const Phys& ph, const Lvl& L, do
     stf(r32.Fx, k, (float)rFx);
     if (DIM == 2) stf(r32.Fy, k, (float)rFy);
     stf(r32.T, k, (float)rT);
+    if (z.d.E) {
+        float oE, oFx, oFy, oT;
+        mx_sweep_point<DIM>(ph, z.L, 0.0f, 1.0f, z.omega, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, (float)rE,
+                            (float)rFx, (DIM == 2) ? (float)rFy : 0.0f, (float)rT, (float)sa, (float)ss, (float)T, oE,
+                            oFx, oFy, oT);
+        stf(z.d.E, k, oE);
+        stf(z.d.Fx, k, oFx);
+        if (DIM == 2) stf(z.d.Fy, k, oFy);
+        stf(z.d.T, k, oT);
+    }
     const double ic = 1.0 / ph.c;
     return fma(rE, rE, fma(rFx * ic, rFx * ic, fma(rFy * ic, rFy * ic, rT * rT)));
 }
@@ -147,13 +190,13 @@ __device__ __forceinline__ void mx_block_partial(double q, double* dst)
 template <int DIM>
 __global__ __launch_bounds__(kBlock32) void k_mx_resid(Phys ph, Lvl L, double eta, CSoa v, CSoa32 d, CSoa b,
                                                        Soa vnew, Soa32 base, Soa32 r32, double* __restrict__ partials,
-                                                       const int* __restrict__ active)
+                                                       const int* __restrict__ active, MxZero z)
 {
     if (*active == 0) return;
     uint32_t k;
     int i, j;
     double q = 0.0;
-    if (mx_cell(L.nx, L.ny, L.sh, k, i, j)) q = mx_resid_cell<DIM>(ph, L, eta, v, d, b, vnew, base, r32, k, i, j);
+    if (mx_cell(L.nx, L.ny, L.sh, k, i, j)) q = mx_resid_cell<DIM>(ph, L, eta, v, d, b, vnew, base, r32, k, i, j, z);
     if (partials) mx_block_partial(q, partials + xcd_block());
 }
 
@@ -170,17 +213,9 @@ __device__ __forceinline__ void mx_sweep_values(const Phys& ph, const Lvl32& L, 
                                                 float dE, float dFx, float dFy, float dT, uint32_t k, float& oE,
                                                 float& oFx, float& oFy, float& oT)
 {
-    const double QE = fmaf(gamma, S0, ldf(rhs.E, k));
-    const double QFx = fmaf(gamma, S1, ldf(rhs.Fx, k));
-    const double QFy = (DIM == 2) ? fmaf(gamma, S2, ldf(rhs.Fy, k)) : 0.0;
-    const double QT = ldf(rhs.T, k);
-    const double ka = (double)L.cdt * ldf(L.sa, k), ks = (double)L.cdt * ldf(L.ss, k);
-    float xE, xFx, xFy, xT;
-    local_solve_inc(beta, gamma, L.a, ka, ks, ph.c_v, ph.a_r, QE, QFx, QFy, QT, ldf(w.T, k), dT, xE, xFx, xFy, xT);
-    oE = fmaf(omega, xE - dE, dE);
-    oFx = fmaf(omega, xFx - dFx, dFx);
-    oFy = (DIM == 2) ? fmaf(omega, xFy - dFy, dFy) : 0.0f;
-    oT = fmaf(omega, xT - dT, dT);
+    mx_sweep_point<DIM>(ph, L, beta, gamma, omega, S0, S1, S2, dE, dFx, dFy, dT, ldf(rhs.E, k), ldf(rhs.Fx, k),
+                        (DIM == 2) ? ldf(rhs.Fy, k) : 0.0f, ldf(rhs.T, k), ldf(L.sa, k), ldf(L.ss, k), ldf(w.T, k),
+                        oE, oFx, oFy, oT);
 }
 template <int DIM>
 __device__ __forceinline__ void mx_sweep_update(const Phys& ph, const Lvl32& L, const CSoa32& w, const CSoa32& rhs,
@@ -973,7 +1008,8 @@ __device__ __forceinline__ const Soa32& coarse_final(const BProb& pb, const BSlo
 // Residual with the pending correction (pend_sel; none on a step's first cycle).
 __global__ __launch_bounds__(kBlock32) void kbm_resid(const BProb* __restrict__ P, const BSlot* __restrict__ S,
                                                       const BSlot32* __restrict__ S32,
-                                                      const uint32_t* __restrict__ wl, int nwl, int pend_sel)
+                                                      const uint32_t* __restrict__ wl, int nwl, int pend_sel,
+                                                      int zero)
 {
     M1_BATCH_LOOP(wl, nwl)
     const BSlot& s = S[p * kMaxLevels];
@@ -984,8 +1020,9 @@ __global__ __launch_bounds__(kBlock32) void kbm_resid(const BProb* __restrict__ 
     if (k < (uint32_t)s.L.nx * (uint32_t)s.L.ny) {
         int i, j;
         ij_of(s.L.nx, s.L.sh, k, i, j);
+        const MxZero z = zero ? MxZero{s32.L, (float)pb.omega, pickA(s32, 0)} : MxZero{};
         q = mx_resid_cell<2>(pb.ph, s.L, pb.eta, cs(fl ? s.x1 : s.x0), d, cs(s.b), fl ? s.x0 : s.x1, s32.base, s32.r32,
-                             k, i, j);
+                             k, i, j, z);
     }
     mx_block_partial(q, pb.partials + tile);
     __syncthreads();  // the next tile of this block reuses the reduction slots
@@ -1295,9 +1332,13 @@ __global__ __launch_bounds__(256) void kbm_tail(const BProb* __restrict__ P, con
     } while (0)
 
 void launch_mx_resid(hipStream_t st, int dim, const Phys& ph, const Lvl& L, double eta, CSoa v, CSoa32 d, CSoa b,
-                     Soa vnew, Soa32 base, Soa32 r32, double* partials, const int* active)
+                     Soa vnew, Soa32 base, Soa32 r32, double* partials, const int* active, const Lvl32* zL,
+                     float zomega, Soa32 zd)
 {
-    MX_DISPATCH(dim, k_mx_resid, nblk((int64_t)L.nx * L.ny), ph, L, eta, v, d, b, vnew, base, r32, partials, active);
+    MxZero z{};
+    if (zL && zd.E) z = MxZero{*zL, zomega, zd};
+    MX_DISPATCH(dim, k_mx_resid, nblk((int64_t)L.nx * L.ny), ph, L, eta, v, d, b, vnew, base, r32, partials, active,
+                z);
 }
 
 void launch_mx_sweep(hipStream_t st, int dim, const Phys& ph, const Lvl32& L, CSoa32 w, CSoa32 d, CSoa32 rhs,
@@ -1413,9 +1454,10 @@ void launch_to_f32(hipStream_t st, int64_t n, const double* a, float* b)
 static unsigned bmgrid(int nwl) { return (unsigned)(nwl < 1 ? 1 : (nwl > batch_grid_cap() ? batch_grid_cap() : nwl)); }
 
 void launch_bm_resid(hipStream_t st, const BProb* P, const BSlot* S, const BSlot32* S32, const uint32_t* wl, int nwl,
-                     int pend_sel)
+                     int pend_sel, int zero)
 {
-    if (nwl > 0) hipLaunchKernelGGL(kbm_resid, dim3(bmgrid(nwl)), dim3(kBlock32), 0, st, P, S, S32, wl, nwl, pend_sel);
+    if (nwl > 0)
+        hipLaunchKernelGGL(kbm_resid, dim3(bmgrid(nwl)), dim3(kBlock32), 0, st, P, S, S32, wl, nwl, pend_sel, zero);
 }
 void launch_bm_residual_restrict(hipStream_t st, const BProb* P, const BSlot32* S32, const uint32_t* wl, int nwl,
                                  int level, int d0_sel)
