@@ -17,7 +17,8 @@
 //                sweep: k_mx_prolong_sweep_lds).
 // Coarse levels carry a base w_l = R(w_{l-1}), a correction e_l and the
 // right-hand side g_l = N_w(R d) + R(rho) of the FAS correction equation
-// N_w(e) = g, smoothed by pseudo-time steps in increment form (k_mx_pseudo).
+// N_w(e) = g, smoothed by pseudo-time steps in increment form (k_mx_pseudo;
+// LDS-staged on large levels: k_mx_pseudo_lds).
 #include "m1_internal.hpp"
 #include "m1_mixed.hpp"
 
@@ -603,15 +604,14 @@ __global__ __launch_bounds__(kBlock32) void k_mx_apply(Phys ph, Lvl32 L, CSoa32 
 // One pseudo-time step of M de/dtau + N_w(e) = g (Algorithm 3 in increment
 // form).  FIRST: e_in = d_l = R(correction above) and g holds R(rho) on entry;
 // g = N_w(d_l) + R(rho) is formed and stored.
+// The step at cell k from its off-diagonal sums S and its correction e.
 template <int DIM, bool FIRST>
-__device__ __forceinline__ void mx_pseudo_cell(const Phys& ph, const Lvl32& L, const CSoa32& w, const Soa32& g,
-                                               const CSoa32& e, const Soa32& out, float dt, float reach, int local,
-                                               uint32_t k, int i, int j, bool live = true)
+__device__ __forceinline__ void mx_pseudo_finish(const Phys& ph, const Lvl32& L, const CSoa32& w, const Soa32& g,
+                                                 const Soa32& out, float dt, float reach, int local, uint32_t k,
+                                                 float S0, float S1, float S2, float eE, float eFx, float eFy,
+                                                 float eT, bool live)
 {
     const float c2 = (float)ph.c2, cv = (float)ph.c_v;
-    float S0, S1, S2;
-    offdiag_inc<DIM>(ph, L, w, e, i, j, k, S0, S1, S2);
-    const float eE = ldf(e.E, k), eFx = ldf(e.Fx, k), eFy = (DIM == 2) ? ldf(e.Fy, k) : 0.0f, eT = ldf(e.T, k);
     const float wE = ldf(w.E, k), wFx = ldf(w.Fx, k), wFy = (DIM == 2) ? ldf(w.Fy, k) : 0.0f, wT = ldf(w.T, k);
     const double ka = (double)L.cdt * ldf(L.sa, k), ks = (double)L.cdt * ldf(L.ss, k);
     float gE = ldf(g.E, k), gFx = ldf(g.Fx, k), gFy = (DIM == 2) ? ldf(g.Fy, k) : 0.0f, gT = ldf(g.T, k);
@@ -645,6 +645,17 @@ __device__ __forceinline__ void mx_pseudo_cell(const Phys& ph, const Lvl32& L, c
     stf(out.T, k, xT);
 }
 
+template <int DIM, bool FIRST>
+__device__ __forceinline__ void mx_pseudo_cell(const Phys& ph, const Lvl32& L, const CSoa32& w, const Soa32& g,
+                                               const CSoa32& e, const Soa32& out, float dt, float reach, int local,
+                                               uint32_t k, int i, int j, bool live = true)
+{
+    float S0, S1, S2;
+    offdiag_inc<DIM>(ph, L, w, e, i, j, k, S0, S1, S2);
+    const float eE = ldf(e.E, k), eFx = ldf(e.Fx, k), eFy = (DIM == 2) ? ldf(e.Fy, k) : 0.0f, eT = ldf(e.T, k);
+    mx_pseudo_finish<DIM, FIRST>(ph, L, w, g, out, dt, reach, local, k, S0, S1, S2, eE, eFx, eFy, eT, live);
+}
+
 template <int DIM>
 __global__ __launch_bounds__(kBlock32) void k_mx_pseudo(Phys ph, Lvl32 L, CSoa32 w, Soa32 g, CSoa32 e, Soa32 out,
                                                         double dtau, const double* __restrict__ dtau_dev,
@@ -659,6 +670,45 @@ __global__ __launch_bounds__(kBlock32) void k_mx_pseudo(Phys ph, Lvl32 L, CSoa32
     if (!mx_cell(L.nx, L.ny, L.sh, k, i, j)) return;
     if (first) mx_pseudo_cell<DIM, true>(ph, L, w, g, e, out, dt, reach, local, k, i, j, live);
     else mx_pseudo_cell<DIM, false>(ph, L, w, g, e, out, dt, reach, local, k, i, j, live);
+}
+
+// LDS-staged pseudo-time step (2-D, large levels): the staging of
+// k_mx_sweep_lds (base and correction of a 64 x TY tile and its halo, the
+// c^2 P increment of each point once); each cell sums its neighbours'
+// increments from LDS in the order of offdiag_inc and finishes as
+// mx_pseudo_cell, so the result is that of k_mx_pseudo to the bit.  e and out
+// must not alias.
+constexpr int64_t kMxPseudoLdsCells = 65536;
+
+template <int TY, bool FIRST>
+__global__ __launch_bounds__(kMxTX * TY) void k_mx_pseudo_lds(Phys ph, Lvl32 L, CSoa32 w, Soa32 g, CSoa32 e, Soa32 out,
+                                                             const double* __restrict__ dtau_dev, float reach,
+                                                             int local, const int* __restrict__ active)
+{
+    constexpr int W = MxTile<TY>::W;
+    __shared__ MxTile<TY> q;
+    if (*active == 0) return;
+    const float dt = (float)*dtau_dev;
+    const int ntx = (L.nx + kMxTX - 1) / kMxTX;
+    const int b = (int)xcd_block();
+    const int i0 = (b % ntx) * kMxTX, j0 = (b / ntx) * TY;
+    mx_stage_tile<TY>(q, ph, L, w, e, i0, j0);
+    __syncthreads();
+    const int li = threadIdx.x % kMxTX, lj = threadIdx.x / kMxTX, i = i0 + li, j = j0 + lj;
+    if (i >= L.nx || j >= L.ny) return;
+    const uint32_t k = (uint32_t)j * (uint32_t)L.nx + (uint32_t)i;
+    const int n = (lj + 1) * W + li + 1;
+    const float c = (float)ph.c;
+    float S0 = 0.0f, S1 = 0.0f, S2 = 0.0f;  // the order of offdiag_inc: x-, x+, y-, y+
+    auto nb = [&](int m, float kk, float sgn, bool xdir) {
+        acc_inc(kk, sgn, xdir, c, q.e[m], q.gx[m], q.gy[m], DP{q.xx[m], q.xy[m], q.yy[m]}, S0, S1, S2);
+    };
+    nb(n - 1, L.kx, +1.0f, true);
+    nb(n + 1, L.kx, -1.0f, true);
+    nb(n - W, L.ky, +1.0f, false);
+    nb(n + W, L.ky, -1.0f, false);
+    mx_pseudo_finish<2, FIRST>(ph, L, w, g, out, dt, reach, local, k, S0, S1, S2, q.e[n], q.gx[n], q.gy[n],
+                               ldf(e.T, k), true);
 }
 
 // ---------------------------------------------------------------------------
@@ -1392,6 +1442,25 @@ void launch_mx_pseudo(hipStream_t st, int dim, const Phys& ph, const Lvl32& L, C
                       Soa32 out, double dtau, const double* dtau_dev, float reach, int local, int first,
                       const int* active)
 {
+    const int rows = mx_sweep_rows();
+    if (dim == 2 && rows > 0 && (int64_t)L.nx * L.ny >= kMxPseudoLdsCells) {
+        const unsigned ntx = (unsigned)((L.nx + kMxTX - 1) / kMxTX), nty = (unsigned)((L.ny + rows - 1) / rows);
+        const dim3 gl(ntx * nty), bl(kMxTX * rows);
+#define M1_MX_PSEUDO_LDS(R)                                                                                           \
+    do {                                                                                                              \
+        if (first)                                                                                                    \
+            hipLaunchKernelGGL((k_mx_pseudo_lds<R, true>), gl, bl, 0, st, ph, L, w, g, e, out, dtau_dev, reach, local, \
+                               active);                                                                               \
+        else                                                                                                          \
+            hipLaunchKernelGGL((k_mx_pseudo_lds<R, false>), gl, bl, 0, st, ph, L, w, g, e, out, dtau_dev, reach,       \
+                               local, active);                                                                        \
+    } while (0)
+        if (rows == 4) M1_MX_PSEUDO_LDS(4);
+        else if (rows == 8) M1_MX_PSEUDO_LDS(8);
+        else M1_MX_PSEUDO_LDS(16);
+#undef M1_MX_PSEUDO_LDS
+        return;
+    }
     MX_DISPATCH(dim, k_mx_pseudo, nblk((int64_t)L.nx * L.ny), ph, L, w, g, e, out, dtau, dtau_dev, reach, local,
                 first, active);
 }
