@@ -558,6 +558,39 @@ __global__ __launch_bounds__(kBlock) void k_pseudo(Phys ph, Lvl L, Soa f, CSoa u
     else pseudo_cell<DIM, false>(ph, L, cs(f), f, u, out, dt, reach, local, rs, gs, k, i, j, live);
 }
 
+// LDS-staged pseudo-time step (2-D, large levels): the staging of k_relax_lds
+// (state of a 64 x TY tile and its halo, closures once per point); each cell
+// sums its neighbours from LDS in the order of offdiag and finishes as
+// pseudo_cell, so the result is that of k_pseudo to the bit.  u and out must
+// not alias.  Used from 512 K cells up: the 512^2 step is latency-bound and
+// measured slightly slower staged.
+constexpr int64_t kPseudoLdsCells = 524288;
+
+template <int TY, bool FIRST>
+__global__ __launch_bounds__(kLdsTX * TY) void k_pseudo_lds(Phys ph, Lvl L, Soa f, CSoa u, Soa out,
+                                                           const double* __restrict__ dtau_dev, double reach,
+                                                           int local, Soa rs, double* __restrict__ gs,
+                                                           const int* __restrict__ active)
+{
+    constexpr int W = LdsTile<TY>::W;
+    __shared__ LdsTile<TY> q;
+    const uint32_t z = lane_zero();
+    const double dt = dtau_dev[z];
+    const bool live = active[z] != 0;
+    int i0, j0;
+    tile_origin(L, TY, i0, j0);
+    stage_tile<TY, false>(q, nullptr, ph, L, u, i0, j0, CSoa{}, CSoa{}, 0, 0, 0.0);
+    __syncthreads();
+    const int li = threadIdx.x % kLdsTX, lj = threadIdx.x / kLdsTX, i = i0 + li, j = j0 + lj;
+    if (i >= L.nx || j >= L.ny) return;
+    const uint32_t k = (uint32_t)j * (uint32_t)L.nx + (uint32_t)i;
+    const int c = (lj + 1) * W + li + 1;
+    double S0, S1, S2;
+    tile_sums<TY>(q, L, ph.c, c, S0, S1, S2);
+    pseudo_update<2, FIRST>(ph, L, cs(f), f, q.E[c], q.Fx[c], q.Fy[c], ld(u.T, k), S0, S1, S2, out, dt, reach, local,
+                            rs, gs, k, live);
+}
+
 template <int DIM>
 __global__ __launch_bounds__(kBlock) void k_apply(Phys ph, Lvl L, CSoa v, CSoa X, double sgn, Soa out,
                                                   double* __restrict__ partials, const int* __restrict__ active)
@@ -1196,6 +1229,25 @@ void launch_relax(hipStream_t st, int dim, const Phys& ph, const Lvl& L, CSoa rh
 void launch_pseudo(hipStream_t st, int dim, const Phys& ph, const Lvl& L, Soa f, CSoa u, Soa out, double dtau,
                    const double* dtau_dev, double reach, int local, int first, Soa rs, double* gs, const int* active)
 {
+    const int rows = sweep_rows();
+    if (dim == 2 && rows > 0 && (int64_t)L.nx * L.ny >= kPseudoLdsCells) {
+        const dim3 gl((unsigned)((L.nx + kLdsTX - 1) / kLdsTX) * (unsigned)((L.ny + rows - 1) / rows)),
+            bl(kLdsTX * rows);
+#define M1_PSEUDO_LDS(R)                                                                                             \
+    do {                                                                                                             \
+        if (first)                                                                                                   \
+            hipLaunchKernelGGL((k_pseudo_lds<R, true>), gl, bl, 0, st, ph, L, f, u, out, dtau_dev, reach, local, rs, \
+                               gs, active);                                                                          \
+        else                                                                                                         \
+            hipLaunchKernelGGL((k_pseudo_lds<R, false>), gl, bl, 0, st, ph, L, f, u, out, dtau_dev, reach, local,    \
+                               rs, gs, active);                                                                      \
+    } while (0)
+        if (rows == 4) M1_PSEUDO_LDS(4);
+        else if (rows == 8) M1_PSEUDO_LDS(8);
+        else M1_PSEUDO_LDS(16);
+#undef M1_PSEUDO_LDS
+        return;
+    }
     M1_DISPATCH(dim, k_pseudo, nblocks((int64_t)L.nx * L.ny), ph, L, f, u, out, dtau, dtau_dev, reach, local, first,
                 rs, gs, active);
 }

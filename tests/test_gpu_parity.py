@@ -542,3 +542,32 @@ def test_tiled_smoothing_legs_match_one_step_kernels(bcs):
     ref, info_o = oracle.Oracle(prob, sig).step(v, 2, oracle_params(rtol=1e-12, max_cycles=20000))
     assert info_o["status"] == 0
     assert rel_err(res[65536][0], ref, prob["c"]) <= 1e-9
+
+
+@pytest.mark.parametrize("bcs", ["periodic", "mixed", "wall", "xper"])
+def test_staged_pseudo_steps_match_one_cell(bcs):
+    """The LDS-staged coarse pseudo-time step (2-D levels of at least 512 K
+    cells, while the staged sweeps are on) gives the one-cell step's results
+    to the bit: whole 2048 x 1024 FP64 solves, whose 1024 x 512 level takes the
+    staged step, end in the same bits and cycles with sweep_rows 8 (staged)
+    and 0 (one cell per thread)."""
+    announce("staged pseudo steps", bcs)
+    kinds = BC_SETS.get(bcs, ("periodic", "periodic", "dirichlet", "reflective"))
+    prob, v, sig = inputs.random_problem(41, 2, 2048, 1024, bc_kinds=kinds, cfl=80.0, fmax=0.9)
+    old = {k: binding.tune_get(k) for k in ("sweep_rows", "tiled_max_cells")}
+    res = {}
+    try:
+        binding.tune_set("tiled_max_cells", 0)
+        for rows in (0, 8):
+            binding.tune_set("sweep_rows", rows)
+            P = plan_for(prob, sig, rtol=1e-9, max_cycles=400)
+            vd = to_dev(v)
+            info = P.step(vd, 2)
+            res[rows] = (to_host(vd), info)
+    finally:
+        for k, x in old.items():
+            binding.tune_set(k, x)
+    (a, ia), (b, ib) = res[0], res[8]
+    assert ia["status"] == 0, ia
+    assert (ia["cycles"], ia["rel_residual"]) == (ib["cycles"], ib["rel_residual"])
+    np.testing.assert_array_equal(a.view(np.int64), b.view(np.int64))
