@@ -677,8 +677,9 @@ __global__ __launch_bounds__(kBlock32) void k_mx_pseudo(Phys ph, Lvl32 L, CSoa32
 // c^2 P increment of each point once); each cell sums its neighbours'
 // increments from LDS in the order of offdiag_inc and finishes as
 // mx_pseudo_cell, so the result is that of k_mx_pseudo to the bit.  e and out
-// must not alias.
-constexpr int64_t kMxPseudoLdsCells = 65536;
+// must not alias.  Used from 512 K cells up, as the FP64 step (measured
+// slightly faster than staging the 256^2 and 512^2 levels too).
+constexpr int64_t kMxPseudoLdsCells = 524288;
 
 template <int TY, bool FIRST>
 __global__ __launch_bounds__(kMxTX * TY) void k_mx_pseudo_lds(Phys ph, Lvl32 L, CSoa32 w, Soa32 g, CSoa32 e, Soa32 out,

@@ -106,17 +106,17 @@ RESID_BCS = {
 }
 
 
-@pytest.mark.parametrize("nx,ny", [(256, 5), (512, 33), (64, 37), (16, 3), (1, 300), (128, 130), (4, 2), (512, 512)])
+@pytest.mark.parametrize("nx,ny", [(256, 5), (512, 33), (64, 37), (16, 3), (1, 300), (128, 130), (4, 2), (2048, 1024)])
 @pytest.mark.parametrize("bcs", ["periodic", "mixed", "wall", "xper"])
 def test_staged_mixed_sweeps_match_one_cell(nx, ny, bcs):
     """The LDS-staged mixed-precision kernels (single and paired sweeps, the
     correction fused with the first post-sweep, and the pseudo-time steps of
-    levels of at least 256^2 cells) give the one-cell kernels' results to the
+    levels of at least 512 K cells) give the one-cell kernels' results to the
     bit, signed zeros included: whole mixed solves with them on (mx_sweep_rows
     4) and off (0) take the same cycles and end in the same bits, on widths
     that divide or are multiples of a block, partial last tiles, one-column
-    domains, a 512^2 grid (its 256^2 level takes the staged steps) and every
-    kind of side."""
+    domains, a 2048 x 1024 grid (its 1024 x 512 level takes the staged steps)
+    and every kind of side."""
     announce("staged mixed sweeps", nx, ny, bcs)
     prob, v, sig = inputs.random_problem(21, 2, nx, ny, bc_kinds=RESID_BCS[bcs], cfl=40.0, fmax=1.0)
     old = binding.tune_get("mx_sweep_rows")
