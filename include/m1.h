@@ -132,14 +132,23 @@ const char* m1_strerror(m1_status s);
 /* Fill p with the paper's parameters (see m1_params). */
 void m1_default_params(m1_params* p);
 
-/* Bytes of device workspace a plan needs (0 on invalid arguments). */
+/* Bytes of device workspace a plan needs (0 on invalid arguments): the
+ * per-level storage of the FAS scheme (Sect. 4.2: on every coarse level the
+ * restricted state, the iterate, the right-hand side of the coarse problem,
+ * its residual and the opacities; Sect. 5.1 notes that these auxiliary
+ * vectors make the multigrid's memory grow with the number of levels), plus
+ * the finest level's right-hand side, partner state and residual, and (mixed
+ * precision) the FP32 copies.                                                 */
 size_t m1_workspace_bytes(const m1_grid* g, const m1_params* p);
 
-/* Build the level hierarchy (coarse opacities by full weighting of the fine
- * ones) inside `workspace` (device memory, 256-byte aligned, at least
- * m1_workspace_bytes bytes).  `stream` is a hipStream_t (NULL = default).
- * Opacities are validated (M1_ERR_ARG if negative or non-finite).  The plan
- * keeps pointers to `op` arrays and `workspace`; both must outlive it.        */
+/* Build the level hierarchy of Sect. 4.2 (each level halves both sides,
+ * spacing 2^l h; `levels` of them, or down to side 4) with coarse opacities
+ * by full weighting of the fine ones, inside `workspace` (device memory,
+ * 256-byte aligned, at least m1_workspace_bytes bytes).  `stream` is a
+ * hipStream_t (NULL = default).  Opacities are validated (M1_ERR_ARG if
+ * negative or non-finite).  The plan keeps pointers to `op` arrays and
+ * `workspace`; both must outlive it.  Returns M1_ERR_WORKSPACE for a missing,
+ * misaligned or short workspace; writes *out only on M1_OK.                 */
 m1_status m1_plan_create(const m1_grid* g, const m1_params* p, const m1_opacity* op, void* workspace,
                          size_t workspace_bytes, void* stream, m1_plan** out);
 void m1_plan_destroy(m1_plan* plan);
@@ -152,14 +161,26 @@ m1_status m1_level_dims(const m1_plan* plan, int32_t level, int32_t* nx, int32_t
  * residual fields to r_out when it is not NULL.                              */
 m1_status m1_residual(m1_plan* plan, const m1_state* v, const m1_state* vn, double* norm_out, m1_state* r_out);
 
-/* One V-cycle (Appendix A) of the time step whose initial state is `vn`,
- * updating the iterate `v` in place, with implicit pseudo-time step dtau.
- * Asynchronous.  v must not alias vn.                                        */
-m1_status m1_vcycle(m1_plan* plan, m1_state* v, const m1_state* vn, double dtau);
+/* One V-cycle of the overall algorithm (Appendix A, Algorithm 4: nu0 finest
+ * Jacobi sweeps, the FAS coarse problems of Sect. 4.2 in pseudo-time,
+ * Algorithm 3, the corrections of eq. prolongatedSol, nu0 sweeps again) of the
+ * time step whose initial state is `vn`, updating the iterate `v` in place,
+ * with implicit pseudo-time step dtau (> 0).  v must not alias vn.
+ * info == NULL: asynchronous (enqueued on the plan's stream).  Otherwise the
+ * call blocks and fills *info: cycles = 1, levels, dtau, r0 = |b - A(vn)| and
+ * rel_residual = |b - A(v)| / r0 of the updated iterate (norm of
+ * m1_residual; 0 when r0 = 0), status M1_OK.                                */
+m1_status m1_vcycle(m1_plan* plan, m1_state* v, const m1_state* vn, double dtau, m1_info* info);
 
-/* nsteps implicit Euler steps: v holds v^n on entry and v^{n+nsteps} on exit.
- * Each step runs V-cycles until the relative residual reaches rtol, adapting
- * dtau_im after every cycle.  Validates the input state first.  Blocks.       */
+/* nsteps implicit Euler steps (the overall algorithm of Appendix A,
+ * Algorithm 4): v holds v^n on entry and v^{n+nsteps} on exit.  Each step sets
+ * b = (E^n, F^n, C_v T^n), resets dtau_im to dtau_im0 and runs V-cycles until
+ * |b - A(v)| <= rtol |b - A(v^n)| (the relative residual of Sect. 5), adapting
+ * dtau_im after every cycle (x1.1 / 0.5 by eps_inc / eps_dec).  Validates the
+ * input state first: M1_ERR_NOT_ADMISSIBLE (info->first_bad_cell set, v
+ * untouched) if a cell is outside S = {E > 0, |F| <= cE, T > 0}.
+ * M1_ERR_NO_CONVERGENCE when a step reaches max_cycles (v then holds that
+ * step's last, admissible iterate).  Blocks; info (host) may be NULL.        */
 m1_status m1_step(m1_plan* plan, m1_state* v, int32_t nsteps, m1_info* info);
 
 /* ---- single operations of the cycle on one level (parity checks, custom drivers) ---- */

@@ -94,7 +94,7 @@ def lib():
         L.m1_plan_levels.argtypes = [vp]
         L.m1_level_dims.argtypes = [vp, ctypes.c_int32, P(ctypes.c_int32), P(ctypes.c_int32)]
         L.m1_residual.argtypes = [vp, P(m1_state), P(m1_state), P(ctypes.c_double), P(m1_state)]
-        L.m1_vcycle.argtypes = [vp, P(m1_state), P(m1_state), ctypes.c_double]
+        L.m1_vcycle.argtypes = [vp, P(m1_state), P(m1_state), ctypes.c_double, P(m1_info)]
         L.m1_step.argtypes = [vp, P(m1_state), ctypes.c_int32, P(m1_info)]
         L.m1_apply_A.argtypes = [vp, ctypes.c_int32, P(m1_state), P(m1_state)]
         L.m1_sweep.argtypes = [vp, P(m1_state), P(m1_state), P(m1_state)]
@@ -265,8 +265,11 @@ class Plan:
             raise M1Error(st, f"m1_step {out}")
         return out
 
-    def vcycle(self, v, vn, dtau: float):
-        _check(lib().m1_vcycle(self.handle, ctypes.byref(self._st(v)), ctypes.byref(self._st(vn)), dtau), "m1_vcycle")
+    def vcycle(self, v, vn, dtau: float, want_info: bool = False):
+        info = m1_info() if want_info else None
+        _check(lib().m1_vcycle(self.handle, ctypes.byref(self._st(v)), ctypes.byref(self._st(vn)), dtau,
+                               ctypes.byref(info) if want_info else None), "m1_vcycle")
+        return _info_dict(info) if want_info else None
 
     def residual(self, v, vn, want_r: bool = False):
         r = self.torch.zeros_like(v) if want_r else None

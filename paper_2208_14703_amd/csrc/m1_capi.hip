@@ -515,16 +515,21 @@ Soa32 mx_pseudo_smooth(m1_plan& P, int l, const Gate& G, Soa32 start, bool first
 // residual kernel, which writes the updated state into the partner buffer.
 // On return `pend` is this cycle's correction (applied by the next cycle or
 // by the caller).  With `control` the FP64 residual norm feeds the cycle control.
-void mx_vcycle(m1_plan& P, Soa& cur64, Soa& other64, const Gate& G, bool control, bool first, Soa32& pend)
+// False (nothing enqueued) if the buffers would alias.
+bool mx_vcycle(m1_plan& P, Soa& cur64, Soa& other64, const Gate& G, bool control, bool first, Soa32& pend)
 {
     const m1_params& p = P.params;
     const LevelBuf& f0 = P.lev[0];
     const float om = (float)p.omega;
-    // the first pre-sweep (from a zero correction, into dA) runs inside the residual launch
+    // The first pre-sweep (from a zero correction) runs inside the residual launch.  That launch reads the
+    // pending correction at every cell's neighbours, so the sweep writes the correction buffer the pending
+    // one is not in (where the previous cycle left it depends on nu0, the launch shapes and the level count).
     const bool zero_fused = p.nu0 >= 1;
-    m1::launch_mx_resid(P.st, P.dim, P.ph, f0.L, p.eta, cs(cur64), first ? CSoa32{} : cs(pend), cs(P.b), other64,
-                        P.base32, P.r32, control ? P.partials : nullptr, G.active, zero_fused ? &f0.L32 : nullptr, om,
-                        zero_fused ? P.dA : Soa32{});
+    const Soa32 z = (!first && same32(pend, P.dA)) ? P.dB : P.dA;
+    if (!m1::launch_mx_resid(P.st, P.dim, P.ph, f0.L, p.eta, cs(cur64), first ? CSoa32{} : cs(pend), cs(P.b),
+                             other64, P.base32, P.r32, control ? P.partials : nullptr, G.active,
+                             zero_fused ? &f0.L32 : nullptr, om, zero_fused ? z : Soa32{}))
+        return false;
     std::swap(cur64, other64);
     if (control) m1::launch_norm_control(P.st, P.partials, P.npart, P.dctrl);
     auto sweeps = [&](Soa32 d, int count, bool from_zero) {
@@ -544,10 +549,10 @@ void mx_vcycle(m1_plan& P, Soa& cur64, Soa& other64, const Gate& G, bool control
         }
         return d;
     };
-    Soa32 d = zero_fused ? sweeps(P.dA, p.nu0 - 1, false) : sweeps(P.dB, p.nu0, true);
+    Soa32 d = zero_fused ? sweeps(z, p.nu0 - 1, false) : sweeps(P.dB, p.nu0, true);
     if (P.L == 1) {
         pend = d;
-        return;
+        return true;
     }
     const bool fused = P.dim == 2 && m1::residual_restrict();  // rho0 restricted as it is formed
     if (!fused)
@@ -589,11 +594,12 @@ void mx_vcycle(m1_plan& P, Soa& cur64, Soa& other64, const Gate& G, bool control
         m1::launch_mx_prolong_sweep(P.st, P.ph, f0.L32, cs(P.base32), cs(cur64), cs(el[0]), cs(el[1]),
                                     cs(P.lev[1].d), P.px, P.py, p.eta, cs(P.r32), om, post, G.active)) {
         pend = sweeps(post, p.nu0 - 1, false);  // the first post-sweep ran with the correction
-        return;
+        return true;
     }
     m1::launch_mx_prolong_fine(P.st, P.dim, P.ph, f0.nx, f0.ny, P.px, P.py, p.eta, cs(cur64), cs(el[0]), cs(el[1]),
                                cs(P.lev[1].d), el[0], G.active);
     pend = sweeps(el[0], p.nu0, false);
+    return true;
 }
 
 // ---- recorded launch sequences (hipGraph) -----------------------------------
@@ -643,11 +649,14 @@ m1_status graph_cycle(m1_plan& P, Soa& cur, Soa& other, Soa32& pend, const Gate&
     if (!hit) {
         if (P.cyc.size() >= 8) drop_cycle_graphs(P);  // state buffers of earlier calls
         m1_plan::CycleGraph c{cur.E, other.E, pk, f, cur, other, pend, nullptr};
+        bool ok = true;
         const m1_status s = record(&P.st, P.cap, [&] {
-            if (P.mixed) mx_vcycle(P, c.cur, c.other, G, true, first, c.pend);
+            if (P.mixed) ok = mx_vcycle(P, c.cur, c.other, G, true, first, c.pend);
             else vcycle_impl(P, c.cur, c.other, G, true);
         }, &c.exec);
+        if (s == M1_OK && !ok) (void)hipGraphExecDestroy(c.exec);
         if (s != M1_OK) return s;
+        if (!ok) return M1_ERR_DEVICE;
         P.cyc.push_back(c);
         hit = &P.cyc.back();
     }
@@ -933,22 +942,42 @@ m1_status m1_residual(m1_plan* P, const m1_state* v, const m1_state* vn, double*
     return fine_norm(*P, to_soa(v), r_out ? to_soa(r_out) : Soa{}, norm_out);
 }
 
-m1_status m1_vcycle(m1_plan* P, m1_state* v, const m1_state* vn, double dtau)
+m1_status m1_vcycle(m1_plan* P, m1_state* v, const m1_state* vn, double dtau, m1_info* info)
 {
+    if (info) {
+        std::memset(info, 0, sizeof(*info));
+        info->first_bad_cell = -1;
+    }
     if (!P || !valid_state(P, v) || !valid_state(P, vn) || !(dtau > 0.0) || v->E == vn->E) return M1_ERR_ARG;
     m1::launch_make_rhs(P->st, P->dim, P->lev[0].n, P->grid.c_v, cs(to_soa(vn)), P->b);
     Soa user = to_soa(v), cur = user, other = P->tmp;
+    double r0 = 0.0;
+    if (info) {  // |b - A(v^n)|, the reference of the relative residual
+        const m1_status e = fine_norm(*P, to_soa(vn), Soa{}, &r0);
+        if (e != M1_OK) return e;
+    }
     if (P->mixed) {
         Soa32 pend{};
-        mx_vcycle(*P, cur, other, fixed_gate(*P, dtau), false, true, pend);
+        if (!mx_vcycle(*P, cur, other, fixed_gate(*P, dtau), false, true, pend)) return M1_ERR_DEVICE;
         // apply the correction: the state is now in tmp; write the update back to v
         m1::launch_mx_resid(P->st, P->dim, P->ph, P->lev[0].L, P->params.eta, cs(cur), cs(pend), cs(P->b), user,
                             P->base32, P->r32, nullptr, &P->dfix->active);
-        return last_launch();
+    } else {
+        vcycle_impl(*P, cur, other, fixed_gate(*P, dtau));
+        if (!same(cur, user)) m1::launch_copy(P->st, P->dim, P->lev[0].n, cs(cur), user);
     }
-    vcycle_impl(*P, cur, other, fixed_gate(*P, dtau));
-    if (!same(cur, user)) m1::launch_copy(P->st, P->dim, P->lev[0].n, cs(cur), user);
-    return last_launch();
+    m1_status st = last_launch();
+    if (st != M1_OK || !info) return st;
+    double r = 0.0;
+    st = fine_norm(*P, user, Soa{}, &r);
+    if (st != M1_OK) return st;
+    info->cycles = 1;
+    info->steps_done = 0;
+    info->levels = P->L;
+    info->r0 = r0;
+    info->rel_residual = r0 > 0.0 ? r / r0 : 0.0;
+    info->dtau = dtau;
+    return M1_OK;
 }
 
 m1_status m1_step(m1_plan* P, m1_state* v, int32_t nsteps, m1_info* info)
@@ -1030,7 +1059,7 @@ m1_status m1_step(m1_plan* P, m1_state* v, int32_t nsteps, m1_info* info)
                     const m1_status s = graph_cycle(*P, cur, other, pend, G, enqueued + c == 0);
                     if (s != M1_OK) return s;
                 } else if (P->mixed) {
-                    mx_vcycle(*P, cur, other, G, true, enqueued + c == 0, pend);
+                    if (!mx_vcycle(*P, cur, other, G, true, enqueued + c == 0, pend)) return M1_ERR_DEVICE;
                 } else {
                     vcycle_impl(*P, cur, other, G, true);
                 }

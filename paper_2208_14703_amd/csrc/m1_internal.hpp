@@ -191,7 +191,9 @@ void launch_b_flip_copy(hipStream_t st, const BProb* P, const BSlot* S, const ui
 void launch_b_gather_ctrl(hipStream_t st, const BProb* P, int np, Ctrl* out);
 
 // zL, zd: also the cycle's first correction sweep (from d = 0; level zL, relaxation zomega) into zd
-void launch_mx_resid(hipStream_t st, int dim, const Phys& ph, const Lvl& L, double eta, CSoa v, CSoa32 d, CSoa b,
+// (false, nothing launched: zd is the buffer of d -- the launch reads d at every cell's neighbours while the
+// fused sweep writes zd)
+bool launch_mx_resid(hipStream_t st, int dim, const Phys& ph, const Lvl& L, double eta, CSoa v, CSoa32 d, CSoa b,
                      Soa vnew, Soa32 base, Soa32 r32, double* partials, const int* active,
                      const Lvl32* zL = nullptr, float zomega = 0.0f, Soa32 zd = {});
 // two mixed-precision correction sweeps (2-D, beta = 0, gamma = 1, d given) in one launch, d -> out;

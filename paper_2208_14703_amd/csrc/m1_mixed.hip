@@ -1382,14 +1382,18 @@ __global__ __launch_bounds__(256) void kbm_tail(const BProb* __restrict__ P, con
         else hipLaunchKernelGGL(KERNEL<1>, dim3(GRID), dim3(kBlock32), 0, st, __VA_ARGS__);            \
     } while (0)
 
-void launch_mx_resid(hipStream_t st, int dim, const Phys& ph, const Lvl& L, double eta, CSoa v, CSoa32 d, CSoa b,
+bool launch_mx_resid(hipStream_t st, int dim, const Phys& ph, const Lvl& L, double eta, CSoa v, CSoa32 d, CSoa b,
                      Soa vnew, Soa32 base, Soa32 r32, double* partials, const int* active, const Lvl32* zL,
                      float zomega, Soa32 zd)
 {
     MxZero z{};
-    if (zL && zd.E) z = MxZero{*zL, zomega, zd};
+    if (zL && zd.E) {
+        if (d.E && d.E == zd.E) return false;
+        z = MxZero{*zL, zomega, zd};
+    }
     MX_DISPATCH(dim, k_mx_resid, nblk((int64_t)L.nx * L.ny), ph, L, eta, v, d, b, vnew, base, r32, partials, active,
                 z);
+    return true;
 }
 
 void launch_mx_sweep(hipStream_t st, int dim, const Phys& ph, const Lvl32& L, CSoa32 w, CSoa32 d, CSoa32 rhs,

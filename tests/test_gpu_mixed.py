@@ -132,3 +132,50 @@ def test_staged_mixed_sweeps_match_one_cell(nx, ny, bcs):
     assert ia["status"] in (0, 3) and np.all(np.isfinite(a)), ia
     assert (ia["status"], ia["cycles"], ia["rel_residual"]) == (ib["status"], ib["cycles"], ib["rel_residual"])
     np.testing.assert_array_equal(a.view(np.int64), b.view(np.int64))
+
+
+RACE_CASES = {
+    # one level, 1-D odd N: the only pre-sweep launch after the residual launch is none or a single sweep
+    "1d_odd_one_level": (dict(dim=1, n=33, cfl=4.0), dict(nu0=3)),
+    # one level, nu0 = 1: the cycle is the residual launch alone (its fused sweep)
+    "2d_one_level_nu1": (dict(dim=2, n=24, cfl=4.0), dict(levels=1, nu0=1)),
+    # one level, sweeps launched one by one
+    "2d_one_level_unpaired": (dict(dim=2, n=32, cfl=4.0), dict(levels=1), dict(pair_rows=0)),
+    # one-cell sweeps and paired sweeps with an even sweep count
+    "2d_even_nu0_pairs": (dict(dim=2, n=64, cfl=50.0), dict(nu0=2), dict(mx_sweep_rows=0, pair_rows=8)),
+}
+
+
+@pytest.mark.parametrize("case", sorted(RACE_CASES))
+def test_mixed_pending_correction_not_overwritten(case):
+    """The first correction sweep of a mixed cycle runs inside the FP64 residual
+    launch, which reads the previous cycle's correction at every cell's
+    neighbours: the sweep must write the other correction buffer.  Where the
+    previous correction ends depends on nu0, the launch shapes and the level
+    count; in these cases it ends in the buffer the fused sweep used to write.
+    The solve must reach the oracle's solution at the mixed bound and give the
+    same bits twice."""
+    spec = RACE_CASES[case]
+    geo, params = spec[0], spec[1]
+    shapes = spec[2] if len(spec) > 2 else {}
+    announce("mixed pending-correction buffer", case)
+    n = geo["n"]
+    bcs = ("periodic",) * 4 if geo["dim"] == 1 else ("dirichlet", "reflective", "periodic", "periodic")
+    prob, v, sig = inputs.random_problem(31, geo["dim"], n, 1 if geo["dim"] == 1 else n, bc_kinds=bcs,
+                                         cfl=geo["cfl"], block=4)
+    o = oracle.Oracle(prob, sig)
+    ref, _ = o.step(v, 2, oracle.make_params(omega=OMEGA, rtol=1e-13, max_cycles=200000, **params))
+    saved = {k: binding.tune_get(k) for k in shapes}
+    try:
+        for k, val in shapes.items():
+            binding.tune_set(k, val)
+        runs = [solve(prob, v, sig, steps=2, rtol=1e-12, precision="mixed", max_cycles=100000, **params)
+                for _ in range(2)]
+    finally:
+        for k, val in saved.items():
+            binding.tune_set(k, val)
+    (a, ia), (b, ib) = runs
+    assert ia["status"] == 0 and ia["steps_done"] == 2, ia
+    assert rel_err(a, ref, prob["c"]) <= 5e-10
+    assert ia["cycles"] == ib["cycles"]
+    np.testing.assert_array_equal(a.view(np.int64), b.view(np.int64))
