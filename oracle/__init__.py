@@ -89,6 +89,7 @@ def lib():
         L.or_sweep.argtypes = [gp, dp, ctypes.c_double, dp, dp, dp]
         L.or_restrict.argtypes = [gp, dp, ctypes.c_int32, dp]
         L.or_prolong.argtypes = [gp, dp, ctypes.c_int32, dp]
+        L.or_pseudo_time.argtypes = [gp, pp, ctypes.c_double, dp, dp, dp, dp]
         L.or_pseudo_step.argtypes = [gp, dp, pp, ctypes.c_double, dp, dp, dp]
         L.or_project.argtypes = [gp, pp, dp, dp, dp]
         L.or_coarse_grid.restype = Grid
@@ -215,6 +216,16 @@ class Oracle:
         self.L.or_pseudo_step(ctypes.byref(g), _p(s), ctypes.byref(p), dtau, _p(self._c(f)), _p(self._c(u)),
                               _p(out))
         return out
+
+    def pseudo_time(self, f, u, dtau, params=None, g=None):
+        """Explicit part of a pseudo-time step: each cell's pseudo time tau_i and u~."""
+        g = g or self.g
+        p = params or make_params()
+        taus = np.zeros((g.ny, g.nx))
+        ut = self._new(g=g)
+        self.L.or_pseudo_time(ctypes.byref(g), ctypes.byref(p), dtau, _p(self._c(f)), _p(self._c(u)), _p(taus),
+                              _p(ut))
+        return taus, ut
 
     def project(self, u, w, params=None, g=None):
         g = g or self.g

@@ -468,20 +468,14 @@ double or_ray(double c, const double w[4], const double s[4])
     return fmin(tau, r);
 }
 
-/* One pseudo-time step of Algorithm 3 for  M du/dtau + A(u) = f :
- * per cell, explicit sub-steps u~ <- u~ + dtau_ex M^{-1} f, each as long as
- * eta times the admissible length of the ray and never past dtau_im in total,
- * at most sub_steps of them, reaching the pseudo-time tau_i <= dtau_im; then
- * the implicit step (M + tau A)(u) = M u~ with nu_l Jacobi sweeps started from
- * u, where tau is each cell's own tau_i (pseudo_local = 1: the split step of
- * eq. (splitting) with a local step, whose steady state is A(u) = f in every
- * cell with tau_i > 0) or dtau_im everywhere (pseudo_local = 0, as printed).  */
-void or_pseudo_step(const or_grid* g, const double* sigma, const or_params* p, double dtau,
-                    const double* f, const double* u_in, double* u_out)
+/* The explicit part of one pseudo-time step (Algorithm 3): per cell, sub-steps
+ * u~ <- u~ + dtau_ex M^{-1} f from u, each eta times the admissible length of
+ * the ray left (or_ray), never past dtau in total, at most sub_steps of them.
+ * Writes each cell's pseudo time tau_i <= dtau and u~.                        */
+void or_pseudo_time(const or_grid* g, const or_params* p, double dtau, const double* f, const double* u_in,
+                    double* taus, double* u_tilde)
 {
     const size_t n = ncell(g);
-    double* rhs = dalloc(NFIELD * n);
-    double* taus = dalloc(n);
 #pragma omp parallel for schedule(static)
     for (int j = 0; j < g->ny; ++j) {
         for (int i = 0; i < g->nx; ++i) {
@@ -496,12 +490,27 @@ void or_pseudo_step(const or_grid* g, const double* sigma, const or_params* p, d
                 tau_ex += d;
             }
             taus[k] = tau_ex;
-            rhs[k] = w[0];
-            rhs[n + k] = w[1];
-            rhs[2 * n + k] = w[2];
-            rhs[3 * n + k] = g->c_v * w[3];
+            for (int m = 0; m < 4; ++m) u_tilde[m * n + k] = w[m];
         }
     }
+}
+
+/* One pseudo-time step of Algorithm 3 for  M du/dtau + A(u) = f :
+ * per cell, explicit sub-steps u~ <- u~ + dtau_ex M^{-1} f, each as long as
+ * eta times the admissible length of the ray and never past dtau_im in total,
+ * at most sub_steps of them, reaching the pseudo-time tau_i <= dtau_im; then
+ * the implicit step (M + tau A)(u) = M u~ with nu_l Jacobi sweeps started from
+ * u, where tau is each cell's own tau_i (pseudo_local = 1: the split step of
+ * eq. (splitting) with a local step, whose steady state is A(u) = f in every
+ * cell with tau_i > 0) or dtau_im everywhere (pseudo_local = 0, as printed).  */
+void or_pseudo_step(const or_grid* g, const double* sigma, const or_params* p, double dtau,
+                    const double* f, const double* u_in, double* u_out)
+{
+    const size_t n = ncell(g);
+    double* rhs = dalloc(NFIELD * n);
+    double* taus = dalloc(n);
+    or_pseudo_time(g, p, dtau, f, u_in, taus, rhs);
+    for (size_t k = 0; k < n; ++k) rhs[3 * n + k] *= g->c_v; /* M u~ */
     double* cur = dalloc(NFIELD * n);
     double* nxt = dalloc(NFIELD * n);
     memcpy(cur, u_in, NFIELD * n * sizeof(double));

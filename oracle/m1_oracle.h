@@ -69,6 +69,8 @@ void   or_sweep(const or_grid* g, const double* sigma, double omega, const doubl
                 double* v_out);
 void   or_restrict(const or_grid* fine, const double* x_fine, int32_t nfields, double* x_coarse);
 void   or_prolong(const or_grid* fine, const double* x_coarse, int32_t nfields, double* x_fine);
+void   or_pseudo_time(const or_grid* g, const or_params* p, double dtau, const double* f, const double* u_in,
+                      double* taus, double* u_tilde);
 void   or_pseudo_step(const or_grid* g, const double* sigma, const or_params* p, double dtau,
                       const double* f, const double* u_in, double* u_out);
 void   or_project(const or_grid* g, const or_params* p, const double* u, const double* w, double* out);
