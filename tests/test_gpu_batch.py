@@ -2,20 +2,48 @@
 one launch per level operation.  Each request must give exactly the result of
 solving it alone (same kernels, same per-request norms and controls), also
 when the arena is so small that requests queue and are admitted as others
-finish (continuous batching).  The alone-results are themselves checked
-against the oracle by the parity tests.
+finish (continuous batching).
+
+Every batched and served run also carries an anchor request solved to a tight
+tolerance (its own rtol; the engine lets tolerances differ per request), whose
+result is compared with the oracle's converged solution: relative 1e-10 in
+FP64, and the stated mixed-precision bound (5e-10 at rtol 1e-12).
 """
 import time
 
 import numpy as np
 import pytest
 
+import oracle
 from paper_2208_14703_amd import binding, inputs
-from tests.gpu_util import announce, to_dev, to_host
+from tests.gpu_util import announce, rel_err, to_dev, to_host
 
 pytestmark = pytest.mark.gpu
 
 PARAMS = dict(omega=0.8, rtol=1e-8)
+ANCHOR_RTOL = {"fp64": 1e-13, "mixed": 1e-12}
+ANCHOR_BOUND = {"fp64": 1e-10, "mixed": 5e-10}
+_anchor_ref = {}
+
+
+def anchor(precision, params=None):
+    """A 96 x 64 hot-wall problem of two steps with a tight per-request rtol."""
+    prob, v, sig = inputs.random_problem(77, 2, 96, 64, bc_kinds=("dirichlet", "reflective", "periodic", "periodic"),
+                                         cfl=100.0, log10_sa=(-3, 3), fmax=0.95, block=8)
+    p = dict(params or PARAMS, precision=precision, rtol=ANCHOR_RTOL[precision], max_cycles=20000)
+    return prob, v, sig, 2, p
+
+
+def check_anchor(prob, v, sig, ns, precision, got, info):
+    """The anchor request's result against the oracle's converged solution."""
+    assert info["status"] == 0 and info["steps_done"] == ns, info
+    if ns not in _anchor_ref:
+        o = oracle.Oracle(prob, sig)
+        _anchor_ref[ns], _ = o.step(v, ns, oracle.make_params(omega=PARAMS["omega"], rtol=1e-13, max_cycles=50000))
+    err = rel_err(got, _anchor_ref[ns], prob["c"])
+    print(f"anchor {precision}: cycles {info['cycles']} rel {info['rel_residual']:.3e} error vs oracle {err:.3e}",
+          flush=True)
+    assert err <= ANCHOR_BOUND[precision], (precision, err)
 
 
 def problems(n, sides=(64, 128, 256)):
@@ -53,6 +81,10 @@ def test_batch_matches_alone(precision, arena):
         vd = to_dev(v)
         states.append(vd)
         tickets.append(E.submit(prob, to_dev(sig), vd, ns))
+    ap, av, asg, ans, apar = anchor(precision)
+    avd = to_dev(av)
+    at = E.submit(ap, to_dev(asg), avd, ans, apar)
+    tickets.append(at)
     done = set()
     rounds = 0
     while len(done) < len(tickets):
@@ -62,6 +94,9 @@ def test_batch_matches_alone(precision, arena):
             if t not in done and E.poll(t) is not None:
                 done.add(t)
         assert rounds < 5000
+    ainfo = E.poll(at)
+    check_anchor(ap, av, asg, ans, precision, to_host(avd), ainfo)
+    np.testing.assert_array_equal(to_host(avd), alone(ap, av, asg, ans, apar)[0])
     for (prob, v, sig, ns), vd, t in zip(cases, states, tickets):
         info = E.poll(t)
         ref, info_a = alone(prob, v, sig, ns, params)
@@ -81,14 +116,20 @@ def test_batch_sweep_counts_match_alone(precision, nu0, m):
     announce("batch sweep counts", precision, nu0, m)
     params = dict(PARAMS, precision=precision, nu0=nu0, pseudo_steps=m)
     cases = problems(4)
-    need = sum(binding.Engine.request_bytes(p, params) for p, _, _, _ in cases)
+    ap, av, asg, ans, apar = anchor(precision, params)
+    need = sum(binding.Engine.request_bytes(p, params) for p, _, _, _ in cases + [(ap, 0, 0, 0)])
     E = binding.Engine(need + (16 << 20), params, max_requests=8)
     states, tickets = [], []
     for prob, v, sig, ns in cases:
         vd = to_dev(v)
         states.append(vd)
         tickets.append(E.submit(prob, to_dev(sig), vd, ns))
+    avd = to_dev(av)
+    at = E.submit(ap, to_dev(asg), avd, ans, apar)
     infos = [E.wait(t) for t in tickets]
+    ainfo = E.wait(at)  # the anchor takes more cycles than the others: wait before reading its state
+    check_anchor(ap, av, asg, ans, precision, to_host(avd), ainfo)
+    np.testing.assert_array_equal(to_host(avd), alone(ap, av, asg, ans, apar)[0])
     for (prob, v, sig, ns), vd, info in zip(cases, states, infos):
         ref, info_a = alone(prob, v, sig, ns, params)
         assert info["status"] == 0 and info_a["status"] == 0
@@ -191,13 +232,19 @@ def test_serving_loop_matches_alone(precision):
     E = binding.Engine(int(2.5 * need) + (2 << 20), params, max_requests=64)
     E.serve_start(2)
     states, tickets = [], []
+    ap, av, asg, ans, apar = anchor(precision)
+    avd = to_dev(av)
     for k, (prob, v, sig, ns) in enumerate(cases):
         vd = to_dev(v)
         sd = to_dev(sig)
         states.append(vd)
         tickets.append(E.submit(prob, sd, vd, ns))
+        if k == 2:
+            at = E.submit(ap, to_dev(asg), avd, ans, apar)
         time.sleep(0.01)
     infos = [E.wait(t) for t in tickets]
+    ainfo = E.wait(at)
+    check_anchor(ap, av, asg, ans, precision, to_host(avd), ainfo)
     E.serve_stop()
     tm = [E.times(t) for t in tickets]
     # some request was admitted while an earlier one was still running
@@ -242,16 +289,21 @@ def test_serving_concurrent_clients(precision):
         except Exception as exc:  # reported by the main thread
             errors.append(exc)
 
+    ap, av, asg, ans, apar = anchor(precision)
+    avd = to_dev(av)
     E.serve_start(2)
     threads = [threading.Thread(target=client, args=(list(range(c, len(cases), 4)),), daemon=True) for c in range(4)]
     for th in threads:
         th.start()
+    at = E.submit(ap, to_dev(asg), avd, ans, apar)
+    ainfo = E.wait(at)
     for th in threads:
         th.join(timeout=120)
     alive = [th.is_alive() for th in threads]
     E.serve_stop()
     assert not errors, errors
     assert not any(alive)
+    check_anchor(ap, av, asg, ans, precision, to_host(avd), ainfo)
     for k, (prob, v, sig, ns) in enumerate(cases):
         ref, info_a = alone(prob, v, sig, ns, params)
         assert results[k]["status"] == 0 and results[k]["steps_done"] == ns
