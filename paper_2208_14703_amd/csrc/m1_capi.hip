@@ -46,22 +46,35 @@ struct LevelBuf {
     float* ss32 = nullptr;
 };
 
+// Most levels of a plan: halving a side of at most 2^29 cells down to 4 gives 28.
+constexpr int kMaxPlanLevels = 32;
+
+// Side lengths of a level hierarchy (fixed capacity: plans keep no heap storage).
+struct Dims {
+    int n = 0;
+    int nx[kMaxPlanLevels] = {}, ny[kMaxPlanLevels] = {};
+    size_t size() const { return (size_t)n; }
+};
+
 // Level sizes: coarsen while every active side stays even and >= 4 after
 // halving (levels == 0), or exactly `levels` levels when possible.
-bool level_dims(const m1_grid& g, const m1_params& p, std::vector<int>& nxs, std::vector<int>& nys)
+bool level_dims(const m1_grid& g, const m1_params& p, Dims& d)
 {
-    nxs.assign(1, g.nx);
-    nys.assign(1, g.dim == 2 ? g.ny : 1);
+    d.n = 1;
+    d.nx[0] = g.nx;
+    d.ny[0] = g.dim == 2 ? g.ny : 1;
     for (;;) {
-        if (p.levels > 0 && (int)nxs.size() >= p.levels) break;
-        int nx = nxs.back(), ny = nys.back();
+        if (p.levels > 0 && d.n >= p.levels) break;
+        if (d.n >= kMaxPlanLevels) break;
+        const int nx = d.nx[d.n - 1], ny = d.ny[d.n - 1];
         bool ok = (nx % 2 == 0) && nx / 2 >= 4;
         if (g.dim == 2) ok = ok && (ny % 2 == 0) && ny / 2 >= 4;
         if (!ok) break;
-        nxs.push_back(nx / 2);
-        nys.push_back(g.dim == 2 ? ny / 2 : 1);
+        d.nx[d.n] = nx / 2;
+        d.ny[d.n] = g.dim == 2 ? ny / 2 : 1;
+        ++d.n;
     }
-    return p.levels <= 0 || (int)nxs.size() == p.levels;
+    return p.levels <= 0 || d.n == p.levels;
 }
 
 bool valid_bc(const m1_grid& g)
@@ -146,7 +159,7 @@ struct m1_plan {
     int dim = 2, L = 1, px = 0, py = 0;
     double reach = 0.0;  // 1 - (1 - eta)^sub_steps
     m1::Phys ph{};
-    std::vector<LevelBuf> lev;
+    LevelBuf lev[kMaxPlanLevels];
     Soa b{}, tmp{}, rfine{};
     double* partials = nullptr;
     int npart = 0;
@@ -184,19 +197,19 @@ struct m1_plan {
 namespace {
 
 // Lay out every buffer of the plan; with c.base == nullptr only the size is computed.
-void carve(m1_plan& P, Carver& c, const std::vector<int>& nxs, const std::vector<int>& nys)
+void carve(m1_plan& P, Carver& c, const Dims& d)
 {
     const int dim = P.grid.dim;
-    P.L = (int)nxs.size();
-    P.lev.assign(P.L, LevelBuf{});
-    const int64_t n0 = (int64_t)nxs[0] * nys[0];
+    P.L = d.n;
+    for (auto& lv : P.lev) lv = LevelBuf{};
+    const int64_t n0 = (int64_t)d.nx[0] * d.ny[0];
     P.b = c.soa(n0, dim);
     P.tmp = c.soa(n0, dim);
     P.rfine = c.soa(n0, dim);
     for (int l = 0; l < P.L; ++l) {
         LevelBuf& lv = P.lev[l];
-        lv.nx = nxs[l];
-        lv.ny = nys[l];
+        lv.nx = d.nx[l];
+        lv.ny = d.ny[l];
         lv.n = (int64_t)lv.nx * lv.ny;
         lv.hx = P.grid.hx * std::ldexp(1.0, l);
         lv.hy = (dim == 2 ? P.grid.hy : P.grid.hx) * std::ldexp(1.0, l);
@@ -405,12 +418,12 @@ void vcycle_impl(m1_plan& P, Soa& cur, Soa& other, const Gate& G, bool control =
     // residuals are restricted as they are formed (one launch per level) unless switched off
     const bool fused = P.dim == 2 && m1::residual_restrict();
     if (!fused) m1::launch_apply(P.st, P.dim, P.ph, P.lev[0].L, cs(cur), cs(P.b), -1.0, P.rfine, nullptr, G.active);
-    std::vector<Soa> ul(P.L);
+    Soa ul[kMaxPlanLevels];
     // levels smoothed by one LDS-tiled launch per leg: R(rbar) goes to rb, which the
     // down leg reads while it writes the FAS right-hand side into f
     // (only up to tiled_max_cells: larger levels stream well as one launch per step, and the halo
     // work and the large LDS blocks of the tiled form cost more than the launches it saves)
-    std::vector<char> tiled(P.L, 0);
+    bool tiled[kMaxPlanLevels] = {};
     for (int l = 1; l < std::min(P.lt, P.L); ++l)
         tiled[l] = P.tiled && P.lev[l].n <= P.tiled_max && m1::smooth_tb_fits(P.dim, P.lev[l].L, p.pseudo_steps);
     ul[0] = cur;
@@ -557,7 +570,7 @@ bool mx_vcycle(m1_plan& P, Soa& cur64, Soa& other64, const Gate& G, bool control
     const bool fused = P.dim == 2 && m1::residual_restrict();  // rho0 restricted as it is formed
     if (!fused)
         m1::launch_mx_apply(P.st, P.dim, P.ph, f0.L32, cs(P.base32), cs(d), cs(P.r32), -1.0f, P.rho0, G.active);
-    std::vector<Soa32> el(P.L);
+    Soa32 el[kMaxPlanLevels];
     el[0] = d;
     const Soa32* wprev = &P.base32;
     const Soa32* rprev = &P.rho0;
@@ -745,13 +758,13 @@ void m1_default_params(m1_params* p)
 size_t m1_workspace_bytes(const m1_grid* g, const m1_params* p)
 {
     if (!valid_grid(g) || !valid_params(p)) return 0;
-    std::vector<int> nxs, nys;
-    if (!level_dims(*g, *p, nxs, nys)) return 0;
+    Dims d;
+    if (!level_dims(*g, *p, d)) return 0;
     m1_plan P;
     P.grid = *g;
     P.params = *p;
     Carver c{nullptr};
-    carve(P, c, nxs, nys);
+    carve(P, c, d);
     return (c.off + kAlign - 1) / kAlign * kAlign;
 }
 
@@ -768,8 +781,8 @@ static m1_status plan_setup(const m1_grid* g, const m1_params* p, const m1_opaci
     if (!out) return M1_ERR_ARG;
     *out = nullptr;
     if (!valid_grid(g) || !valid_params(p) || !op || !op->sigma_a || !op->sigma_s) return M1_ERR_ARG;
-    std::vector<int> nxs, nys;
-    if (!level_dims(*g, *p, nxs, nys)) return M1_ERR_ARG;
+    Dims dims;
+    if (!level_dims(*g, *p, dims)) return M1_ERR_ARG;
     const size_t need = m1_workspace_bytes(g, p);
     if (!workspace || (reinterpret_cast<uintptr_t>(workspace) % kAlign) != 0 || workspace_bytes < need)
         return M1_ERR_WORKSPACE;
@@ -795,7 +808,7 @@ static m1_status plan_setup(const m1_grid* g, const m1_params* p, const m1_opaci
         P->ph.bcFy[s] = g->dim == 2 ? g->bc[s].Fy : 0.0;
     }
     Carver c{static_cast<char*>(workspace)};
-    carve(*P, c, nxs, nys);
+    carve(*P, c, dims);
     P->lev[0].sa = const_cast<double*>(op->sigma_a);
     P->lev[0].ss = const_cast<double*>(op->sigma_s);
     fill_level_params(*P);
@@ -1368,8 +1381,10 @@ bool batch_compatible(const m1_engine& E, const m1_grid* g, const m1_params* p)
     if (p->nu0 != e.nu0 || p->nu_l != 1 || p->pseudo_steps != e.pseudo_steps || p->sub_steps != e.sub_steps ||
         p->pseudo_local != e.pseudo_local || p->precision != e.precision || p->omega != e.omega || p->eta != e.eta)
         return false;
-    std::vector<int> nxs, nys;
-    if (!level_dims(*g, *p, nxs, nys) || nxs.size() < 2 || (int)nxs.size() > m1::kMaxLevels) return false;
+    Dims d;
+    if (!level_dims(*g, *p, d) || d.n < 2 || d.n > m1::kMaxLevels) return false;
+    const int* nxs = d.nx;
+    const int* nys = d.ny;
     // a work-list entry holds the tile index in kTileBits bits: 256-cell tiles, and 64 x 4 tiles (the
     // staged sweep's most numerous), of the finest level must fit
     const int64_t n = (int64_t)nxs[0] * nys[0];
