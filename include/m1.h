@@ -183,6 +183,29 @@ m1_status m1_vcycle(m1_plan* plan, m1_state* v, const m1_state* vn, double dtau,
  * step's last, admissible iterate).  Blocks; info (host) may be NULL.        */
 m1_status m1_step(m1_plan* plan, m1_state* v, int32_t nsteps, m1_info* info);
 
+/* ---- allocation-free time steps ----------------------------------------------
+ * For callers that cannot allocate device memory or pinned host memory (code
+ * that must not call hipMalloc, hipHostMalloc or a framework allocator, such
+ * as tight serving loops or harnesses that forbid allocation).
+ * m1_step_static runs m1_step on a plan whose workspace is a static device
+ * array of M1_STATIC_SCRATCH_BYTES bytes that the library holds on every
+ * device it runs on until the process ends (its address is looked up with
+ * hipGetSymbolAddress on the first call on each device).  It allocates no
+ * device or pinned memory, records no graphs, and gives m1_step's results to
+ * the bit.  The caller passes grid, parameters, opacity and state (device
+ * arrays, as for m1_plan_create and m1_step) and the stream, which must
+ * belong to the current device.  80 MiB hold a 2-D plan of up to about
+ * 540 K cells in FP64 and 300 K cells in mixed precision (512 x 512: 39 and
+ * 69 MiB); problems whose m1_workspace_bytes exceeds M1_STATIC_SCRATCH_BYTES
+ * are rejected with M1_ERR_WORKSPACE, invalid arguments with M1_ERR_ARG;
+ * otherwise as m1_step (blocks; info may be NULL).  Nothing in the array has
+ * to start at zero: every buffer is written before it is read.  All calls on
+ * one device share its array and a host slot: calls that overlap on one
+ * device race (serialise them).                                             */
+#define M1_STATIC_SCRATCH_BYTES (80u << 20)
+m1_status m1_step_static(const m1_grid* g, const m1_params* p, const m1_opacity* op, m1_state* v, int32_t nsteps,
+                         void* stream, m1_info* info);
+
 /* ---- single operations of the cycle on one level (parity checks, custom drivers) ---- */
 
 /* out = A_l(v) on level `level` (spacing 2^level h, opacities of that level). */

@@ -103,6 +103,8 @@ def lib():
         L.m1_restrict.argtypes = [vp, ctypes.c_int32, P(m1_state), P(m1_state)]
         L.m1_prolong_project.argtypes = [vp, ctypes.c_int32, P(m1_state), P(m1_state), P(m1_state), P(m1_state)]
         L.m1_sync.argtypes = [vp]
+        L.m1_step_static.argtypes = [P(m1_grid), P(m1_params), P(m1_opacity), P(m1_state), ctypes.c_int32, vp,
+                                     P(m1_info)]
         L.m1_engine_request_bytes.restype = ctypes.c_size_t
         L.m1_engine_request_bytes.argtypes = [P(m1_grid), P(m1_params)]
         L.m1_engine_create.argtypes = [P(m1_params), vp, ctypes.c_size_t, ctypes.c_int32, vp, P(vp)]
@@ -125,7 +127,8 @@ def lib():
         for name in ("m1_plan_create", "m1_residual", "m1_vcycle", "m1_step", "m1_apply_A", "m1_sweep",
                      "m1_sweeps", "m1_pseudo_step", "m1_restrict", "m1_prolong_project", "m1_sync", "m1_level_dims",
                      "m1_engine_create", "m1_batch_submit", "m1_batch_run", "m1_batch_poll", "m1_batch_wait",
-                     "m1_batch_cancel", "m1_batch_times", "m1_batch_release", "m1_serve_start", "m1_serve_stop"):
+                     "m1_batch_cancel", "m1_batch_times", "m1_batch_release", "m1_serve_start", "m1_serve_stop",
+                     "m1_step_static"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
         _apply_stored_tuning(L)
@@ -316,6 +319,31 @@ class Plan:
 
     def sync(self):
         _check(lib().m1_sync(self.handle), "m1_sync")
+
+
+STATIC_SCRATCH_BYTES = 80 << 20  # M1_STATIC_SCRATCH_BYTES
+
+
+def step_static(problem: dict, sigma, v, nsteps: int = 1, params: dict | None = None, stream=None) -> dict:
+    """m1_step_static: nsteps implicit steps of state v (torch float64 (4, ny, nx) on the current
+    device) on the library's static device workspace; no plan, no allocation."""
+    import torch
+    g = make_grid(problem)
+    p = make_params(default_params(**(params or {})))
+    sigma = sigma.contiguous()
+    assert sigma.dtype == torch.float64 and sigma.is_cuda and v.dtype == torch.float64 and v.is_contiguous()
+    op = m1_opacity(sigma[0].data_ptr(), sigma[1].data_ptr())
+    st = m1_state(v[0].data_ptr(), v[1].data_ptr(), v[2].data_ptr() if problem["dim"] == 2 else None,
+                  v[3].data_ptr())
+    s = stream if stream is not None else torch.cuda.current_stream()
+    info = m1_info()
+    rc = lib().m1_step_static(ctypes.byref(g), ctypes.byref(p), ctypes.byref(op), ctypes.byref(st), nsteps,
+                              ctypes.c_void_p(s.cuda_stream), ctypes.byref(info))
+    out = dict(_info_dict(info), first_bad_cell=info.first_bad_cell)
+    if rc not in (0, 3):
+        raise M1Error(rc, f"m1_step_static {out}")
+    out["status"] = rc
+    return out
 
 
 def _info_dict(info: m1_info) -> dict:

@@ -12,6 +12,7 @@
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -774,12 +775,22 @@ size_t m1_workspace_bytes(const m1_grid* g, const m1_params* p)
 // Pinned host words a plan needs (hpin); an engine lends each resident request one such slot.
 constexpr size_t kHostSlot = (64 + sizeof(m1::Ctrl) + 63) / 64 * 64;
 
-static m1_status plan_setup(const m1_grid* g, const m1_params* p, const m1_opacity* op, void* workspace,
-                            size_t workspace_bytes, void* stream, bool wait, m1_plan** out,
-                            void* host_slot = nullptr)
+// Release what a plan holds besides its workspace (graph recordings, the
+// recording stream, its own pinned host words); the object itself stays.
+static void plan_release(m1_plan* P)
 {
-    if (!out) return M1_ERR_ARG;
-    *out = nullptr;
+    drop_cycle_graphs(*P);
+    if (P->cap) (void)hipStreamDestroy(P->cap);
+    P->cap = nullptr;
+    if (P->hpin && P->own_hpin) (void)hipHostFree(P->hpin);
+    P->hpin = nullptr;
+}
+
+// Fill the plan object *P (freshly constructed) over `workspace`.  On failure
+// the caller synchronises the stream and calls plan_release(P).
+static m1_status plan_init(m1_plan* P, const m1_grid* g, const m1_params* p, const m1_opacity* op, void* workspace,
+                           size_t workspace_bytes, void* stream, bool wait, void* host_slot)
+{
     if (!valid_grid(g) || !valid_params(p) || !op || !op->sigma_a || !op->sigma_s) return M1_ERR_ARG;
     Dims dims;
     if (!level_dims(*g, *p, dims)) return M1_ERR_ARG;
@@ -787,8 +798,6 @@ static m1_status plan_setup(const m1_grid* g, const m1_params* p, const m1_opaci
     if (!workspace || (reinterpret_cast<uintptr_t>(workspace) % kAlign) != 0 || workspace_bytes < need)
         return M1_ERR_WORKSPACE;
 
-    m1_plan* P = new (std::nothrow) m1_plan();
-    if (!P) return M1_ERR_DEVICE;
     P->grid = *g;
     P->params = *p;
     P->st = static_cast<hipStream_t>(stream);
@@ -817,7 +826,7 @@ static m1_status plan_setup(const m1_grid* g, const m1_params* p, const m1_opaci
         P->hpin = static_cast<double*>(host_slot);
         P->own_hpin = false;
     } else if (hipHostMalloc((void**)&P->hpin, kHostSlot, hipHostMallocDefault) != hipSuccess) {
-        delete P;
+        P->hpin = nullptr;
         return M1_ERR_DEVICE;
     }
     P->hbad = reinterpret_cast<unsigned long long*>(P->hpin + 4);
@@ -907,9 +916,22 @@ static m1_status plan_setup(const m1_grid* g, const m1_params* p, const m1_opaci
         st = hip_status(hipMemcpyAsync(P->dtail32, &P->hta32, sizeof(ta32), hipMemcpyHostToDevice, P->st));
     if (st == M1_OK && wait) st = hip_status(hipStreamSynchronize(P->st));
     if (st == M1_OK) st = last_launch();
+    return st;
+}
+
+static m1_status plan_setup(const m1_grid* g, const m1_params* p, const m1_opacity* op, void* workspace,
+                            size_t workspace_bytes, void* stream, bool wait, m1_plan** out,
+                            void* host_slot = nullptr)
+{
+    if (!out) return M1_ERR_ARG;
+    *out = nullptr;
+    m1_plan* P = new (std::nothrow) m1_plan();
+    if (!P) return M1_ERR_DEVICE;
+    const m1_status st = plan_init(P, g, p, op, workspace, workspace_bytes, stream, wait, host_slot);
     if (st != M1_OK) {
-        (void)hipStreamSynchronize(P->st);
-        m1_plan_destroy(P);
+        if (P->hpin) (void)hipStreamSynchronize(P->st);  // set once the checks passed, before any enqueue
+        plan_release(P);
+        delete P;
         return st;
     }
     *out = P;
@@ -925,9 +947,7 @@ m1_status m1_plan_create(const m1_grid* g, const m1_params* p, const m1_opacity*
 void m1_plan_destroy(m1_plan* P)
 {
     if (!P) return;
-    drop_cycle_graphs(*P);
-    if (P->cap) (void)hipStreamDestroy(P->cap);
-    if (P->hpin && P->own_hpin) (void)hipHostFree(P->hpin);
+    plan_release(P);
     delete P;
 }
 
@@ -1122,6 +1142,66 @@ m1_status m1_step(m1_plan* P, m1_state* v, int32_t nsteps, m1_info* info)
         info->dtau = dtau;
     }
     return status;
+}
+
+}  // extern "C"
+
+// ---- allocation-free time steps ----------------------------------------------
+// The workspace of m1_step_static: one array on every device the library runs
+// on, held until the process ends.  In host code its name stands for a host
+// shadow, not for device memory: host code only ever uses the device address
+// that hipGetSymbolAddress returns for the current device.
+static __device__ __align__(256) unsigned char scratch[M1_STATIC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_dev[kMaxDevices] = {};
+// host words of the static plans (bad-cell index, control copy): pageable, one slot per device
+alignas(64) double g_scratch_host[kMaxDevices][kHostSlot / sizeof(double)];
+
+// Device address of `scratch` on device `dev` (current), looked up on the first call per device.
+void* scratch_on(int dev)
+{
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void* ptr = nullptr;
+        if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return nullptr;
+        g_scratch_dev[dev] = ptr;
+    }
+    return g_scratch_dev[dev];
+}
+
+}  // namespace
+
+extern "C" {
+
+m1_status m1_step_static(const m1_grid* g, const m1_params* p, const m1_opacity* op, m1_state* v, int32_t nsteps,
+                         void* stream, m1_info* info)
+{
+    if (info) {
+        std::memset(info, 0, sizeof(*info));
+        info->first_bad_cell = -1;
+    }
+    if (!g || !p || !op || !v || nsteps < 0) return M1_ERR_ARG;
+    const size_t need = m1_workspace_bytes(g, p);
+    if (need == 0) return M1_ERR_ARG;
+    if (need > (size_t)M1_STATIC_SCRATCH_BYTES) return M1_ERR_WORKSPACE;
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return M1_ERR_DEVICE;
+    void* ws = scratch_on(dev);
+    if (!ws) return M1_ERR_DEVICE;
+    m1_plan P;  // host bookkeeping on the stack; workspace: this device's scratch array
+    m1_status st = plan_init(&P, g, p, op, ws, (size_t)M1_STATIC_SCRATCH_BYTES, stream, true, g_scratch_host[dev]);
+    if (st == M1_OK) {
+        P.graphs = false;  // a recording would create a stream and executable graphs
+        st = m1_step(&P, v, nsteps, info);
+    } else if (P.hpin) {
+        (void)hipStreamSynchronize(P.st);
+    }
+    plan_release(&P);
+    return st;
 }
 
 m1_status m1_apply_A(m1_plan* P, int32_t level, const m1_state* v, m1_state* out)
