@@ -15,13 +15,20 @@ The same JSON line also carries:
 - roofline: the finest-level Jacobi sweep kernel of the cycle, the solve's dominant kernel:
   k_relax2_lds<rows> (two sweeps per launch, the first sweep's iterate kept in LDS), or with
   that launch shape off k_relax_lds<rows, false> (the LDS-staged sweep) or k_relax<2, false,
-  true>. It is timed with HIP events on the solver's stream around m1_sweeps launches, at 112
-  algorithmic bytes per cell and sweep (the state, right-hand side and opacities read once and
-  the state written once per sweep): 224 per cell for the pair, whose own HBM traffic is about
-  half of that, since the intermediate iterate stays on chip.
+  true>. It is timed with HIP events on the solver's stream around m1_sweeps launches on a
+  4096^2 FP64 plan (the inputs of the 4096^2 lognormal workload: a 1.9 GB working set, far
+  beyond the 256 MB Infinity Cache, so the kernel streams from HBM), at 112 algorithmic bytes
+  per cell and sweep (the state, right-hand side and opacities read once and the state written
+  once per sweep): 224 per cell for the pair, whose own HBM traffic is about half of that,
+  since the intermediate iterate stays on chip.
+- roofline_kernels: the same measurement for the single staged sweep and for the finest-level
+  residual fused with its restriction (k_residual_restrict, m1_residual_restrict: 96 bytes per
+  fine cell), both at 4096^2, and for the pair on the 1024^2 hot wall itself (cache-resident).
 - traffic: the kernel's FETCH_SIZE + WRITE_SIZE counter bytes per launch, scaled by the same
-  counters on a plain copy of known size. They are read from the counter summary under
-  profiles/, and are null when the kernel sources have changed since it was taken.
+  counters on a plain copy of known size. They are read from the counter summaries under
+  profiles/, and are null when the kernel sources have changed since they were taken.
+- c1 / c3: the 1-D Gaussian (N = 256, rtol 1e-10) and the 4096^2 lognormal single solve in
+  mixed precision (rtol 1e-8; with the FP64 solve of the same step beside it).
 - cpu_baseline: the FP64 CPU oracle on the host cores, over a bounded sample of V-cycles
   of the same workload.
 - batched: 256 independent problems of uneven size, seeded 1000+k, side log-uniform in
@@ -35,8 +42,8 @@ The same JSON line also carries:
 Other modes:
 - --workload lognormal: the 4096^2 single solve (mixed or fp64).
 - --workload serve: the serving sweep over arrival rates.
-- --profile sweeps: only the sweep kernel and a copy kernel of known size, for PMC counter
-  runs.
+- --profile kernels: only the 4096^2 kernel launches of the roofline entries and a copy kernel
+  of known size, for PMC counter runs.
 """
 from __future__ import annotations
 
@@ -57,6 +64,8 @@ from paper_2208_14703_amd.profsum import sources_hash  # noqa: E402
 METRIC = "Mcell-updates/s + time to 1e-8 residual; batched solves/s with p50/p99 latency"
 HBM_PEAK_GBS = 8000.0
 SWEEP_BYTES_PER_CELL = 112  # v (E,Fx,Fy,T) 32 + b 32 + sigma 16 read, v' 32 written
+RESID_BYTES_PER_CELL = 96   # u 32 + b 32 + sigma 16 read per fine cell; R(u) and R(r) (2 x 32 B) per 4 fine cells
+KERNEL_N = 4096             # side of the HBM-resident grid of the kernel measurements
 SOLVER = dict(omega=0.8, levels=0)
 def sweeps_per_launch():
     """Sweeps per launch of the finest-level sweep kernel the cycle runs (2 with the fused pair on)."""
@@ -72,10 +81,15 @@ def sweep_kernel():
     return f"k_relax_lds<{rows}, false>" if rows > 0 else "k_relax<2, false, true>"
 
 
-def traffic_file():
-    pair, rows = binding.tune_get("pair_rows"), binding.tune_get("sweep_rows")
-    name = f"k_relax2_lds{pair}" if pair > 0 else (f"k_relax_lds{rows}" if rows > 0 else "k_relax")
-    return os.path.join(ROOT, "profiles", f"{name}_hotwall1024_traffic.txt")
+def sweep_tag(pair):
+    rows = binding.tune_get("sweep_rows")
+    return f"k_relax2_lds{pair}" if pair > 0 else (f"k_relax_lds{rows}" if rows > 0 else "k_relax")
+
+
+def traffic_file(tag, workload):
+    return os.path.join(ROOT, "profiles", f"{tag}_{workload}_traffic.txt")
+
+
 COPY_ELEMS = 1 << 27  # 1 GiB of float64 per copy launch
 
 
@@ -96,47 +110,108 @@ def parse():
     ap.add_argument("--rates", default="50", help="comma-separated arrival rates (1/s) for serving")
     ap.add_argument("--arena-gb", type=float, default=64.0, help="engine HBM budget for serving")
     ap.add_argument("--serve-precision", default="mixed", choices=["fp64", "mixed"])
-    ap.add_argument("--profile", default="none", choices=["none", "sweeps"],
-                    help="sweeps: only sweep launches and a copy of known size (for counter runs)")
+    ap.add_argument("--profile", default="none", choices=["none", "kernels"],
+                    help="kernels: only the 4096^2 kernel launches and a copy of known size (for counter runs)")
     ap.add_argument("--reps", type=int, default=40, help="sweep launches timed for the roofline")
     ap.add_argument("--stream", default="own", choices=["own", "default"],
                     help="own: run on a created stream (default priority); default: the null stream")
     return ap.parse_args()
 
 
-def read_traffic(cells: int):
-    """Counter bytes per k_relax launch from the committed summary, if the kernel is unchanged."""
+def read_traffic(tag: str, workload: str, kernel: str, cells: int):
+    """Counter bytes per launch of `kernel` from the committed summary, if the kernel sources are unchanged."""
     try:
-        kv = dict(line.split(":", 1) for line in open(traffic_file()) if ":" in line and not line.startswith(" "))
+        kv = dict(line.split(":", 1) for line in open(traffic_file(tag, workload))
+                  if ":" in line and not line.startswith(" "))
     except OSError:
         return None
     kv = {k.strip(): v.strip() for k, v in kv.items()}
     if (kv.get("sources_sha256") != sources_hash() or int(kv.get("cells", -1)) != cells
-            or kv.get("kernel") != sweep_kernel()):
+            or kv.get("kernel") != kernel):
         return None
     return float(kv["traffic_bytes_per_launch"])
 
 
-def sweep_timing(torch, plan, b, v, reps):
-    """Average duration of the finest-level sweep kernel: HIP events on the plan's stream around launches of
-    m1_sweeps with the kernel's sweeps per launch (one launch each)."""
-    out = torch.empty_like(v)
-    n = sweeps_per_launch()
+def time_launches(torch, stream, launch, reps):
+    """Average time of one launch: HIP events on `stream` (the plan's) around `reps` back-to-back launches."""
     for _ in range(3):
-        plan.sweeps(b, v, n)
-    st = plan.stream
+        launch()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record(st)
-    src, dst = v.clone(), out
-    L = binding.lib()
+    e0.record(stream)
     for _ in range(reps):
+        launch()
+    e1.record(stream)
+    e1.synchronize()
+    return e0.elapsed_time(e1) / reps * 1e-3
+
+
+def sweep_launcher(plan, b, v, n):
+    """m1_sweeps(n) between two state buffers (one launch each for n = 1, or n = 2 with the pair on)."""
+    L = binding.lib()
+    bufs = [v.clone(), v.clone()]
+    k = [0]
+
+    def launch():
+        src, dst = bufs[k[0]], bufs[1 - k[0]]
         binding._check(L.m1_sweeps(plan.handle, binding.ctypes.byref(plan._st(b)),
                                    binding.ctypes.byref(plan._st(src)), binding.ctypes.byref(plan._st(dst)), n),
                        "m1_sweeps")
-        src, dst = dst, src
-    e1.record(st)
-    e1.synchronize()
-    return e0.elapsed_time(e1) / reps * 1e-3
+        k[0] ^= 1
+    return launch
+
+
+def residual_launcher(plan, b, u):
+    """m1_residual_restrict on the finest level: one launch of the fused residual and restriction."""
+    L = binding.lib()
+    vc, rc = plan.new_state(1), plan.new_state(1)
+    args = [binding.ctypes.byref(plan._st(x)) for x in (u, b, vc, rc)]
+
+    def launch():
+        binding._check(L.m1_residual_restrict(plan.handle, 0, *args), "m1_residual_restrict")
+    return launch
+
+
+def roofline_entry(kernel, what, bytes_per_launch, t, traffic, grid, residency):
+    achieved = bytes_per_launch / t / 1e9
+    return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": f"{kernel} ({what})",
+            "grid": grid, "residency": residency, "algorithmic_bytes_per_launch": bytes_per_launch,
+            "avg_launch_us": round(t * 1e6, 2)}
+
+
+def kernel_leg(torch, reps):
+    """The cycle's finest-level kernels timed on a 4096^2 FP64 plan (HBM-resident working set)."""
+    prob, v0, sig, _ = inputs.lognormal_2d(n=KERNEL_N)
+    cells = prob["nx"] * prob["ny"]
+    plan = binding.Plan(prob, binding.to_device(sig), dict(precision="fp64", **SOLVER))
+    v = binding.to_device(v0)
+    b = v.clone()
+    b[3] *= prob["c_v"]
+    grid = f"{prob['nx']}x{prob['ny']}"
+    res = "HBM (lognormal 4096^2 inputs; 1.9 GB working set, beyond the 256 MB Infinity Cache)"
+    out = []
+    pair = binding.tune_get("pair_rows")
+    if pair > 0:
+        t = time_launches(torch, plan.stream, sweep_launcher(plan, b, v, 2), reps)
+        k = sweep_kernel()
+        out.append(roofline_entry(k, "finest-level FP64 Jacobi sweeps, 2 per launch", 2 * SWEEP_BYTES_PER_CELL * cells,
+                                  t, read_traffic(sweep_tag(pair), "lognormal4096", k, cells), grid, res))
+    binding.tune_set("pair_rows", 0)
+    try:
+        t = time_launches(torch, plan.stream, sweep_launcher(plan, b, v, 1), reps)
+        k = sweep_kernel()
+        out.append(roofline_entry(k, "finest-level FP64 Jacobi sweep", SWEEP_BYTES_PER_CELL * cells, t,
+                                  read_traffic(sweep_tag(0), "lognormal4096", k, cells), grid, res))
+    finally:
+        binding.tune_set("pair_rows", pair)
+    if binding.tune_get("residual_restrict"):
+        t = time_launches(torch, plan.stream, residual_launcher(plan, b, v), reps)
+        k = "k_residual_restrict"
+        out.append(roofline_entry(k, "finest-level FP64 residual restricted as it is formed", RESID_BYTES_PER_CELL *
+                                  cells, t, read_traffic(k, "lognormal4096", k, cells), grid, res))
+    del plan
+    torch.cuda.empty_cache()
+    return out
 
 
 def copy_timing(torch, reps=10):
@@ -155,7 +230,7 @@ def copy_timing(torch, reps=10):
     return {"bytes": 16 * COPY_ELEMS, "avg_launch_us": round(t * 1e6, 2), "GB_per_s": round(16 * COPY_ELEMS / t / 1e9, 1)}
 
 
-def cpu_baseline(prob, v, sig, run, gpu_cycles_per_step, ncycles):
+def cpu_baseline(prob, v, sig, run, gpu_cycles_per_step, ncycles, c1=None):
     import oracle
     o = oracle.Oracle(prob, sig)
     p = oracle.make_params(rtol=run["rtol"], max_cycles=ncycles, **SOLVER)
@@ -165,11 +240,38 @@ def cpu_baseline(prob, v, sig, run, gpu_cycles_per_step, ncycles):
     per_cycle = dt / max(info["cycles"], 1)
     projected = per_cycle * gpu_cycles_per_step * run["steps"]
     cells = prob["nx"] * prob["ny"]
-    return {"value": round(cells * run["steps"] / projected / 1e6, 4), "unit": "Mcell-updates/s",
-            "cores": oracle.threads(), "kind": "oracle",
-            "sample": f"{info['cycles']} V-cycles of time step 1 of the same workload in {dt:.1f} s "
-                      f"({per_cycle:.3f} s/cycle), projected to the GPU's {gpu_cycles_per_step:.1f} cycles/step "
-                      f"x {run['steps']} steps (same algorithm, same cycle count)"}
+    out = {"value": round(cells * run["steps"] / projected / 1e6, 4), "unit": "Mcell-updates/s",
+           "cores": oracle.threads(), "kind": "oracle",
+           "sample": f"{info['cycles']} V-cycles of time step 1 of the same workload in {dt:.1f} s "
+                     f"({per_cycle:.3f} s/cycle), projected to the GPU's {gpu_cycles_per_step:.1f} cycles/step "
+                     f"x {run['steps']} steps (same algorithm, same cycle count)"}
+    if c1 is not None:
+        out["c1"] = c1_oracle(oracle, c1)
+    return out
+
+
+def c1_oracle(oracle, c1):
+    """The 1-D Gaussian solved whole by the oracle on one thread (its own time to rtol), and the GPU result's
+    error against the oracle's converged solution (rtol 1e-13)."""
+    prob, v, sig, run = inputs.gaussian_1d(n=256)
+    o = oracle.Oracle(prob, sig)
+    threads = oracle.threads()
+    oracle.set_threads(1)
+    try:
+        t0 = time.perf_counter()
+        _, info = o.step(v, run["steps"], oracle.make_params(rtol=run["rtol"], max_cycles=20000, **SOLVER))
+        dt = time.perf_counter() - t0
+        ref, _ = o.step(v, run["steps"], oracle.make_params(rtol=1e-13, max_cycles=20000, **SOLVER))
+    finally:
+        oracle.set_threads(threads)
+    got = c1.pop("result")
+    err = max(np.abs(got[0] - ref[0]).max() / np.abs(ref[0]).max(),
+              np.abs(got[1:3] - ref[1:3]).max() / (prob["c"] * np.abs(ref[0]).max()),
+              np.abs(got[3] - ref[3]).max() / np.abs(ref[3]).max())
+    return {"value": round(prob["nx"] * run["steps"] / dt / 1e6, 5), "unit": "Mcell-updates/s", "cores": 1,
+            "kind": "oracle", "time_to_rtol_ms": round(dt * 1e3, 3), "cycles": info["cycles"],
+            "sample": "the whole 1-D Gaussian solve (N = 256, rtol 1e-10) on one thread",
+            "gpu_error_vs_oracle": float(err)}
 
 
 def pct(x, q):
@@ -182,6 +284,54 @@ def state_rel(a, b, c=1.0):
     sE, sT = b[0].abs().max(), b[3].abs().max()
     return max(float((a[0] - b[0]).abs().max() / sE), float((a[1:3] - b[1:3]).abs().max() / (c * sE)),
                float((a[3] - b[3]).abs().max() / sT))
+
+
+def timed_solves(torch, plan, v_init, steps, reps):
+    """Median wall time of `reps` whole solves (state reset from v_init, synchronised around each)."""
+    v = torch.empty_like(v_init)
+    times, info = [], None
+    for k in range(reps + 1):
+        v.copy_(v_init)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        info = plan.step(v, steps)
+        torch.cuda.synchronize()
+        if k > 0:  # the first is a warm-up
+            times.append(time.perf_counter() - t0)
+    return float(np.median(times)), info, v
+
+
+def c1_leg(torch):
+    """The 1-D Gaussian workload (N = 256, one step to rtol 1e-10, FP64)."""
+    prob, v0, sig, run = inputs.gaussian_1d(n=256)
+    plan = binding.Plan(prob, binding.to_device(sig), dict(rtol=run["rtol"], max_cycles=20000, **SOLVER))
+    t, info, v = timed_solves(torch, plan, binding.to_device(v0), run["steps"], 5)
+    return {"workload": "1-D Gaussian, N=256 on [0,1], periodic, sigma_a=1, dt=50h/c, FP64, 1 step to rtol 1e-10",
+            "Mcell_updates_per_s": round(prob["nx"] * run["steps"] / t / 1e6, 4),
+            "time_to_rtol_ms": round(t * 1e3, 3), "cycles": info["cycles"], "levels": info["levels"],
+            "status": info["status"], "result": v.cpu().numpy()}
+
+
+def c3_leg(torch):
+    """The 4096^2 lognormal single solve in mixed precision, with the FP64 solve of the same step beside it."""
+    prob, v0, sig, run = inputs.lognormal_2d(n=4096)
+    cells = prob["nx"] * prob["ny"]
+    sd, vd = binding.to_device(sig), binding.to_device(v0)
+    out = {"workload": "lognormal 2-D 4096x4096, periodic, |F|=0.9cE, block opacity seed 2, 1 step, dt=100h/c, "
+                       "rtol 1e-8"}
+    res = {}
+    for prec, reps in (("mixed", 3), ("fp64", 1)):
+        plan = binding.Plan(prob, sd, dict(rtol=run["rtol"], max_cycles=20000, precision=prec, **SOLVER))
+        t, info, v = timed_solves(torch, plan, vd, run["steps"], reps)
+        res[prec] = v
+        out[prec] = {"Mcell_updates_per_s": round(cells * run["steps"] / t / 1e6, 2), "time_to_rtol_ms": round(t * 1e3, 2),
+                     "cycles": info["cycles"], "status": info["status"], "rel_residual": info["rel_residual"]}
+        del plan
+    out["mixed_speedup_vs_fp64"] = round(out["fp64"]["time_to_rtol_ms"] / out["mixed"]["time_to_rtol_ms"], 3)
+    out["max_rel_diff_mixed_vs_fp64"] = state_rel(res["mixed"], res["fp64"], prob["c"])
+    del res
+    torch.cuda.empty_cache()
+    return out
 
 
 # ---------------------------------------------------------------------------
@@ -366,14 +516,12 @@ def main():
     b = v_init.clone()
     b[3] *= prob["c_v"]
 
-    if args.profile == "sweeps":
-        t_sweep = sweep_timing(torch, plan, b, v_init.clone(), args.reps)
-        cp = copy_timing(torch)
-        alg = SWEEP_BYTES_PER_CELL * sweeps_per_launch() * cells
-        print(json.dumps({"profile": "sweeps", "kernel": sweep_kernel(), "cells": cells,
-                          "sweeps_per_launch": sweeps_per_launch(), "sweep_avg_launch_us": round(t_sweep * 1e6, 2),
-                          "algorithmic_bytes_per_launch": alg, "sweep_GB_per_s": round(alg / t_sweep / 1e9, 1),
-                          "copy": cp}), flush=True)
+    if args.profile == "kernels":
+        del plan
+        torch.cuda.empty_cache()
+        entries = kernel_leg(torch, args.reps)
+        print(json.dumps({"profile": "kernels", "cells": KERNEL_N * KERNEL_N, "kernels": entries,
+                          "copy": copy_timing(torch)}), flush=True)
         return
 
     def one_solve():
@@ -404,20 +552,27 @@ def main():
         "final_rel_residual": infos[-1]["rel_residual"],
         "launch_shapes": {k: binding.tune_get(k) for k in binding.TUNE_ENV},
     }
-    t_sweep = sweep_timing(torch, plan, b, v_init.clone(), args.reps)
-    alg_bytes = SWEEP_BYTES_PER_CELL * sweeps_per_launch() * cells
-    achieved = alg_bytes / t_sweep / 1e9
-    traffic = read_traffic(cells) if args.workload == "hotwall" and precision == "fp64" else None
-    out["roofline"] = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                       "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                       "kernel": f"{sweep_kernel()} (finest-level FP64 Jacobi sweeps, {sweeps_per_launch()} per launch)",
-                       "algorithmic_bytes_per_launch": alg_bytes,
-                       "avg_launch_us": round(t_sweep * 1e6, 2)}
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(prob, v0, sig, run, cycles / run["steps"], args.cpu_cycles)
+    # the workload's own finest sweep (cache-resident at 1024^2), then the kernels at an HBM-resident size
+    t_own = time_launches(torch, plan.stream, sweep_launcher(plan, b, v_init, sweeps_per_launch()), args.reps)
+    own = roofline_entry(sweep_kernel(), f"finest-level FP64 Jacobi sweeps, {sweeps_per_launch()} per launch",
+                         SWEEP_BYTES_PER_CELL * sweeps_per_launch() * cells, t_own, None, f"{prob['nx']}x{prob['ny']}",
+                         "Infinity Cache (the sweep's working set, 112 B/cell, fits in its 256 MB)"
+                         if SWEEP_BYTES_PER_CELL * cells < (256 << 20) else "HBM")
+    del plan
+    torch.cuda.empty_cache()
+    kernels = kernel_leg(torch, args.reps)
+    out["roofline"] = kernels[0]
+    out["roofline_kernels"] = kernels[1:] + [own]
+    c1 = None
     if args.workload == "hotwall" and not args.no_extras:
-        del plan
-        torch.cuda.empty_cache()
+        c1 = c1_leg(torch)
+        out["c3"] = c3_leg(torch)
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(prob, v0, sig, run, cycles / run["steps"], args.cpu_cycles, c1)
+    if c1 is not None:
+        c1.pop("result", None)
+        out["c1"] = c1
+    if args.workload == "hotwall" and not args.no_extras:
         out["batched"] = batch_leg(torch, args.batch)
         torch.cuda.empty_cache()
         out["serving"] = {"workload": SERVE_DESC, **serve_leg(torch, args.requests, float(args.rates.split(",")[0]),

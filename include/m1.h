@@ -226,6 +226,17 @@ m1_status m1_pseudo_step(m1_plan* plan, int32_t level, double dtau, const m1_sta
                          m1_state* u_out);
 /* Full-weighting restriction (Sect. 4.2) of a state from `level` to level+1.  */
 m1_status m1_restrict(m1_plan* plan, int32_t level, const m1_state* fine, m1_state* coarse);
+/* Residual of level `level` and its restriction, as the downward leg of a
+ * V-cycle forms them (Appendix A, Algorithm 4): r = rhs - A_l(u) (eq.
+ * defResidual, with the level's opacities and spacing), then the full-
+ * weighting restriction (Sect. 4.2, eq. restrictionOperator) of u into vc and
+ * of r into rc (level+1 arrays).  In 2-D with the launch shape
+ * "residual_restrict" on (default) r is never stored; otherwise it is written
+ * to the plan's residual buffer of that level first (not concurrently with
+ * m1_vcycle/m1_step on the same plan).  M1_ERR_ARG unless 0 <= level <
+ * levels - 1.                                                                */
+m1_status m1_residual_restrict(m1_plan* plan, int32_t level, const m1_state* u, const m1_state* rhs, m1_state* vc,
+                               m1_state* rc);
 /* Correction of `level` from level+1 with admissibility (eq. prolongatedSol):
  * w = u + P(uc - vc); out = w where admissible, else u + eta tau*(u, w-u) (w-u).
  * out may alias u.                                                           */

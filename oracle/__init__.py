@@ -100,6 +100,7 @@ def lib():
         L.or_step.restype = ctypes.c_int32
         L.or_step.argtypes = [gp, dp, pp, dp, ctypes.c_int32, ctypes.POINTER(Info), dp, ctypes.c_int32]
         L.or_threads.restype = ctypes.c_int32
+        L.or_set_threads.argtypes = [ctypes.c_int32]
         _lib = L
     return _lib
 
@@ -283,3 +284,8 @@ def admissible(c, w):
 
 def threads() -> int:
     return lib().or_threads()
+
+
+def set_threads(n: int) -> None:
+    """Threads of the oracle's parallel loops from now on."""
+    lib().or_set_threads(int(n))

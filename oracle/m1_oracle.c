@@ -44,6 +44,16 @@ int32_t or_threads(void)
 #endif
 }
 
+/* Threads of the oracle's parallel row loops from now on (n >= 1). */
+void or_set_threads(int32_t n)
+{
+#ifdef _OPENMP
+    if (n >= 1) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 /* ------------------------------------------------------------------------- */
 /* M1 closure, Sect. 2.1 (closure relation): P = ((1-chi)/2 I + (3chi-1)/2 n n) E,
  * chi(f) = (3 + 4 f^2) / (5 + 2 sqrt(4 - 3 f^2)), n = F/|F|, f = |F|/(cE).     */

@@ -83,6 +83,7 @@ void   or_vcycle(const or_grid* g, const double* sigma, const or_params* p, doub
 int32_t or_step(const or_grid* g, const double* sigma, const or_params* p, double* v, int32_t nsteps,
                 or_info* info, double* history, int32_t history_len);
 int32_t or_threads(void);
+void   or_set_threads(int32_t n);
 
 #ifdef __cplusplus
 }

@@ -102,6 +102,7 @@ def lib():
         L.m1_pseudo_step.argtypes = [vp, ctypes.c_int32, ctypes.c_double, P(m1_state), P(m1_state), P(m1_state)]
         L.m1_restrict.argtypes = [vp, ctypes.c_int32, P(m1_state), P(m1_state)]
         L.m1_prolong_project.argtypes = [vp, ctypes.c_int32, P(m1_state), P(m1_state), P(m1_state), P(m1_state)]
+        L.m1_residual_restrict.argtypes = [vp, ctypes.c_int32, P(m1_state), P(m1_state), P(m1_state), P(m1_state)]
         L.m1_sync.argtypes = [vp]
         L.m1_step_static.argtypes = [P(m1_grid), P(m1_params), P(m1_opacity), P(m1_state), ctypes.c_int32, vp,
                                      P(m1_info)]
@@ -128,7 +129,7 @@ def lib():
                      "m1_sweeps", "m1_pseudo_step", "m1_restrict", "m1_prolong_project", "m1_sync", "m1_level_dims",
                      "m1_engine_create", "m1_batch_submit", "m1_batch_run", "m1_batch_poll", "m1_batch_wait",
                      "m1_batch_cancel", "m1_batch_times", "m1_batch_release", "m1_serve_start", "m1_serve_stop",
-                     "m1_step_static"):
+                     "m1_step_static", "m1_residual_restrict"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
         _apply_stored_tuning(L)
@@ -310,6 +311,15 @@ class Plan:
         _check(lib().m1_restrict(self.handle, level, ctypes.byref(self._st(x)), ctypes.byref(self._st(out))),
                "m1_restrict")
         return out
+
+    def residual_restrict(self, level: int, u, rhs, vc=None, rc=None):
+        """R(u) and R(rhs - A_level(u)) on level + 1 (one launch in 2-D)."""
+        vc = self.new_state(level + 1) if vc is None else vc
+        rc = self.new_state(level + 1) if rc is None else rc
+        _check(lib().m1_residual_restrict(self.handle, level, ctypes.byref(self._st(u)), ctypes.byref(self._st(rhs)),
+                                          ctypes.byref(self._st(vc)), ctypes.byref(self._st(rc))),
+               "m1_residual_restrict")
+        return vc, rc
 
     def prolong_project(self, level: int, u, uc, vc, out=None):
         out = self.torch.zeros_like(u) if out is None else out

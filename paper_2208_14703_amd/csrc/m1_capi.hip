@@ -1265,6 +1265,26 @@ m1_status m1_restrict(m1_plan* P, int32_t level, const m1_state* fine, m1_state*
     return last_launch();
 }
 
+m1_status m1_residual_restrict(m1_plan* P, int32_t level, const m1_state* u, const m1_state* rhs, m1_state* vc,
+                               m1_state* rc)
+{
+    if (!P || level < 0 || level + 1 >= P->L || !valid_level_state(P, u) || !valid_level_state(P, rhs) ||
+        !valid_level_state(P, vc) || !valid_level_state(P, rc))
+        return M1_ERR_ARG;
+    const LevelBuf& f = P->lev[level];
+    const int* act = &P->dfix->active;
+    if (P->dim == 2 && m1::residual_restrict()) {
+        m1::launch_residual_restrict(P->st, P->ph, f.L, cs(to_soa(u)), cs(to_soa(rhs)), -1.0, P->px, P->py,
+                                     to_soa(vc), to_soa(rc), act);
+    } else {  // stored in the level's residual buffer, then restricted
+        const Soa r = level == 0 ? P->rfine : P->lev[level].rb;
+        m1::launch_apply(P->st, P->dim, P->ph, f.L, cs(to_soa(u)), cs(to_soa(rhs)), -1.0, r, nullptr, act);
+        m1::launch_restrict(P->st, P->dim, f.nx, f.ny, P->px, P->py,
+                            fields2(to_soa(u), r, to_soa(vc), to_soa(rc), P->dim), act);
+    }
+    return last_launch();
+}
+
 m1_status m1_prolong_project(m1_plan* P, int32_t level, const m1_state* u, const m1_state* uc, const m1_state* vc,
                              m1_state* out)
 {

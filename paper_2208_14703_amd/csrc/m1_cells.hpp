@@ -173,12 +173,14 @@ __device__ __forceinline__ void pseudo_cell(const Phys& ph, const Lvl& L, const 
 // out = X + sgn A(v) (X.E == nullptr: out = sgn A(v)); out stored when out.E
 // is set.  Returns r_E^2 + (r_F/c)^2 + r_T^2 of the result (norm contribution).
 // X + sgn A(v) of one cell from its state and off-diagonal sum S (X.E null: sgn A(v)).
+// The same from the cell's opacities (sa, ss) and X (x: null when X.E is null), loaded by the caller.
 template <int DIM>
-__device__ __forceinline__ void apply_values(const Phys& ph, const Lvl& L, double E, double Fx, double Fy, double T,
-                                             double S0, double S1, double S2, const CSoa& X, double sgn, uint32_t k,
-                                             double& rE, double& rFx, double& rFy, double& rT)
+__device__ __forceinline__ void apply_values_from(const Phys& ph, const Lvl& L, double E, double Fx, double Fy,
+                                                  double T, double S0, double S1, double S2, double sa, double ss,
+                                                  const double* x, double sgn, double& rE, double& rFx, double& rFy,
+                                                  double& rT)
 {
-    const double ka = L.cdt * ld(L.sa, k), ks = L.cdt * ld(L.ss, k);
+    const double ka = L.cdt * sa, ks = L.cdt * ss;
     const double T2 = T * T;
     const double ex = ka * fma(-ph.a_r * T2, T2, E);  // ka (E - a_r T^4)
     const double dF = L.a + ka + ks;
@@ -186,12 +188,28 @@ __device__ __forceinline__ void apply_values(const Phys& ph, const Lvl& L, doubl
     rFx = sgn * fma(dF, Fx, -S1);
     rFy = sgn * fma(dF, Fy, -S2);
     rT = sgn * fma(ph.c_v, T, -ex);
-    if (X.E) {
-        rE += ld(X.E, k);
-        rFx += ld(X.Fx, k);
-        if (DIM == 2) rFy += ld(X.Fy, k);
-        rT += ld(X.T, k);
+    if (x) {
+        rE += x[0];
+        rFx += x[1];
+        if (DIM == 2) rFy += x[2];
+        rT += x[3];
     }
+}
+
+template <int DIM>
+__device__ __forceinline__ void apply_values(const Phys& ph, const Lvl& L, double E, double Fx, double Fy, double T,
+                                             double S0, double S1, double S2, const CSoa& X, double sgn, uint32_t k,
+                                             double& rE, double& rFx, double& rFy, double& rT)
+{
+    double x[4] = {0.0, 0.0, 0.0, 0.0};
+    if (X.E) {
+        x[0] = ld(X.E, k);
+        x[1] = ld(X.Fx, k);
+        if (DIM == 2) x[2] = ld(X.Fy, k);
+        x[3] = ld(X.T, k);
+    }
+    apply_values_from<DIM>(ph, L, E, Fx, Fy, T, S0, S1, S2, ld(L.sa, k), ld(L.ss, k), X.E ? x : nullptr, sgn, rE, rFx,
+                           rFy, rT);
 }
 
 // The rest of apply_cell from the cell's state and off-diagonal sum S.

@@ -424,12 +424,18 @@ constexpr int kRrW = 2 * kRcW + 1, kRrH = 2 * kRcH + 1;  // residual offsets -1 
 constexpr int kRcThreads = 512;
 
 
-// LDS of one fused residual-restriction tile.
+// LDS of one fused residual-restriction tile: the staged fine states (E, F)
+// and their closures; once every residual is formed, the residual of point q
+// goes to (sXX, sXY, sYY, qT)[q] (the closure arrays are no longer read).
+// Temperatures are not staged: each residual point loads its own with its
+// right-hand side and opacities, and the restriction of T reads them from the
+// cache.  That keeps a block at 40 KB.
 struct RcLds {
     static constexpr int NS = kRsW * kRsH, NR = kRrW * kRrH;
-    double sE[NS], sFx[NS], sFy[NS], sT[NS], sXX[NS], sXY[NS], sYY[NS];
-    double qE[NR], qFx[NR], qFy[NR], qT[NR];
+    double sE[NS], sFx[NS], sFy[NS], sXX[NS], sXY[NS], sYY[NS];
+    double qT[NR];
 };
+static_assert(RcLds::NR <= RcLds::NS, "residuals are kept in the closure arrays");
 
 // The fused residual and restriction of the coarse tile at (I0, J0) (all
 // threads of the block take part; no thread returns early).
@@ -438,20 +444,45 @@ __device__ __forceinline__ void residual_restrict_tile(RcLds& sm, const Phys& ph
                                                        const Soa& rc, int I0, int J0, bool live)
 {
     constexpr int NS = RcLds::NS, NR = RcLds::NR;
+    constexpr int RPT = (NR + kRcThreads - 1) / kRcThreads;  // residual points per thread
     const int nxc = L.nx / 2, nyc = L.ny / 2;
     const int fi0 = 2 * I0, fj0 = 2 * J0;
+    // Each residual point's own loads (opacities, right-hand side, temperature) are issued first, so that
+    // their latency overlaps the staging.  A point dropped at a non-periodic side reads the clamped cell.
+    double own[RPT][7];
+    bool has[RPT];
+#pragma unroll
+    for (int it = 0; it < RPT; ++it) {
+        const int q = threadIdx.x + it * kRcThreads;
+        const int gi = fi0 + q % kRrW - 1, gj = fj0 + q / kRrW - 1;
+        has[it] = q < NR && gi < L.nx && gj < L.ny;  // points past the grid belong to no coarse cell
+#pragma unroll
+        for (int m = 0; m < 7; ++m) own[it][m] = 0.0;
+        if (has[it]) {
+            const int si = gi < 0 ? (px ? gi + L.nx : 0) : gi, sj = gj < 0 ? (py ? gj + L.ny : 0) : gj;
+            const uint32_t k = (uint32_t)sj * (uint32_t)L.nx + (uint32_t)si;
+            own[it][0] = ld(L.sa, k);
+            own[it][1] = ld(L.ss, k);
+            own[it][2] = ld(u.T, k);
+            if (X.E) {
+                own[it][3] = ld(X.E, k);
+                own[it][4] = ld(X.Fx, k);
+                own[it][5] = ld(X.Fy, k);
+                own[it][6] = ld(X.T, k);
+            }
+        }
+    }
     for (int q = threadIdx.x; q < NS; q += kRcThreads) {
         const int gi = fi0 + q % kRsW - 2, gj = fj0 + q / kRsW - 2;
         int si, sj;
         bool hx, hy, nx_, ny_;
         rc_axis(gi, L.nx, px != 0, si, hx, nx_);
         rc_axis(gj, L.ny, py != 0, sj, hy, ny_);
-        double e = 0.0, fx = 0.0, fy = 0.0, t = 0.0, xx = 0.0, xy = 0.0, yy = 0.0;
+        double e = 0.0, fx = 0.0, fy = 0.0, xx = 0.0, xy = 0.0, yy = 0.0;
         if (nx_ && ny_ && !(hx && hy)) {
             const int side = hx ? (gi < 0 ? 0 : 1) : (hy ? (gj < 0 ? 2 : 3) : 0);
             const uint32_t k = (uint32_t)sj * (uint32_t)L.nx + (uint32_t)si;
             ghost_rule(ph, side, !(hx || hy), ld(u.E, k), ld(u.Fx, k), ld(u.Fy, k), e, fx, fy);
-            t = ld(u.T, k);
             const C2P p = closure(ph.c, ph.c2, e, fx, fy);
             xx = p_xx(p, fx);
             xy = p_xy(p, fx, fy);
@@ -460,7 +491,6 @@ __device__ __forceinline__ void residual_restrict_tile(RcLds& sm, const Phys& ph
         sm.sE[q] = e;
         sm.sFx[q] = fx;
         sm.sFy[q] = fy;
-        sm.sT[q] = t;
         sm.sXX[q] = xx;
         sm.sXY[q] = xy;
         sm.sYY[q] = yy;
@@ -472,14 +502,13 @@ __device__ __forceinline__ void residual_restrict_tile(RcLds& sm, const Phys& ph
         if (fj0 + rj < 0 && !py) rj += 1;
         return (rj + 2) * kRsW + ri + 2;
     };
-    for (int q = threadIdx.x; q < NR; q += kRcThreads) {
-        const int ri = q % kRrW - 1, rj = q / kRrW - 1;
-        const int gi = fi0 + ri, gj = fj0 + rj;
+    double res[RPT][4];
+#pragma unroll
+    for (int it = 0; it < RPT; ++it) {
+        const int q = threadIdx.x + it * kRcThreads;
         double rE = 0.0, rFx = 0.0, rFy = 0.0, rT = 0.0;
-        if (gi < L.nx && gj < L.ny) {  // points past the grid belong to no coarse cell
-            const int c = centre(ri, rj);
-            const int si = gi < 0 ? (px ? gi + L.nx : 0) : gi, sj = gj < 0 ? (py ? gj + L.ny : 0) : gj;
-            const uint32_t k = (uint32_t)sj * (uint32_t)L.nx + (uint32_t)si;
+        if (has[it]) {
+            const int c = centre(q % kRrW - 1, q / kRrW - 1);
             double S0 = 0.0, S1 = 0.0, S2 = 0.0;  // the order of offdiag: x-, x+, y-, y+
             acc_x(L.kx, ph.c, +1.0, sm.sE[c - 1], sm.sFx[c - 1], sm.sFy[c - 1], sm.sXX[c - 1], sm.sXY[c - 1], S0, S1,
                   S2);
@@ -489,43 +518,70 @@ __device__ __forceinline__ void residual_restrict_tile(RcLds& sm, const Phys& ph
                   sm.sYY[c - kRsW], S0, S1, S2);
             acc_y(L.ky, ph.c, -1.0, sm.sE[c + kRsW], sm.sFx[c + kRsW], sm.sFy[c + kRsW], sm.sXY[c + kRsW],
                   sm.sYY[c + kRsW], S0, S1, S2);
-            apply_values<2>(ph, L, sm.sE[c], sm.sFx[c], sm.sFy[c], sm.sT[c], S0, S1, S2, X, sgn, k, rE, rFx, rFy, rT);
+            apply_values_from<2>(ph, L, sm.sE[c], sm.sFx[c], sm.sFy[c], own[it][2], S0, S1, S2, own[it][0],
+                                 own[it][1], X.E ? &own[it][3] : nullptr, sgn, rE, rFx, rFy, rT);
         }
-        sm.qE[q] = rE;
-        sm.qFx[q] = rFx;
-        sm.qFy[q] = rFy;
-        sm.qT[q] = rT;
+        res[it][0] = rE;
+        res[it][1] = rFx;
+        res[it][2] = rFy;
+        res[it][3] = rT;
+    }
+    __syncthreads();  // every closure has been read
+#pragma unroll
+    for (int it = 0; it < RPT; ++it) {
+        const int q = threadIdx.x + it * kRcThreads;
+        if (q < NR) {
+            sm.sXX[q] = res[it][0];
+            sm.sXY[q] = res[it][1];
+            sm.sYY[q] = res[it][2];
+            sm.qT[q] = res[it][3];
+        }
     }
     __syncthreads();
-    const int ci = threadIdx.x % kRcW, cj = threadIdx.x / kRcW, I = I0 + ci, J = J0 + cj;
-    if (threadIdx.x < kRcW * kRcH && I < nxc && J < nyc && live) {
+    // restriction: the 8 fields of the tile's coarse cells, two per thread (a wave-uniform pair of fields)
+    constexpr int NC = kRcW * kRcH;
+    static_assert(kRcThreads == 4 * NC, "four groups of threads, two restricted fields each");
+    const int cc = threadIdx.x % NC, grp = threadIdx.x / NC;
+    const int ci = cc % kRcW, cj = cc / kRcW, I = I0 + ci, J = J0 + cj;
+    if (I < nxc && J < nyc && live) {
         int ix[3], iy[3];
         double wx[3], wy[3];
         rweights(I, L.nx, px != 0, ix, wx);
         rweights(J, L.ny, py != 0, iy, wy);
-        // fine cell 2I-1+a, 2J-1+b: residual index (2cj+b) kRrW + 2ci+a, staged cell centre(2ci+a-1, 2cj+b-1)
-        auto restrict8 = [&](const double* src, bool staged, double* dst) {
+        // fine cell 2I-1+a, 2J-1+b: residual index (2cj+b) kRrW + 2ci+a, staged cell centre(2ci+a-1, 2cj+b-1),
+        // global cell (ix[a], iy[b]); all three name the cells restrict_cell reads, in its order
+        auto restrict9 = [&](auto&& value, double* dst) {
             double s = 0.0;
 #pragma unroll
             for (int bb = 0; bb < 3; ++bb) {
                 double v[3];
 #pragma unroll
-                for (int a = 0; a < 3; ++a)
-                    v[a] = staged ? src[centre(2 * ci + a - 1, 2 * cj + bb - 1)]
-                                  : src[(2 * cj + bb) * kRrW + 2 * ci + a];
+                for (int a = 0; a < 3; ++a) v[a] = value(a, bb);
                 const double t = fma(wx[2], v[2], fma(wx[1], v[1], wx[0] * v[0]));
                 s = fma(wy[bb], t, s);
             }
             st(dst, (uint32_t)J * (uint32_t)nxc + (uint32_t)I, s);
         };
-        restrict8(sm.sE, true, vc.E);
-        restrict8(sm.sFx, true, vc.Fx);
-        restrict8(sm.sFy, true, vc.Fy);
-        restrict8(sm.sT, true, vc.T);
-        restrict8(sm.qE, false, rc.E);
-        restrict8(sm.qFx, false, rc.Fx);
-        restrict8(sm.qFy, false, rc.Fy);
-        restrict8(sm.qT, false, rc.T);
+        auto staged = [&](const double* src) {
+            return [&, src](int a, int bb) { return src[centre(2 * ci + a - 1, 2 * cj + bb - 1)]; };
+        };
+        auto resid = [&](const double* src) {
+            return [&, src](int a, int bb) { return src[(2 * cj + bb) * kRrW + 2 * ci + a]; };
+        };
+        if (grp == 0) {
+            restrict9(staged(sm.sE), vc.E);
+            restrict9(staged(sm.sFx), vc.Fx);
+        } else if (grp == 1) {
+            restrict9(staged(sm.sFy), vc.Fy);
+            restrict9([&](int a, int bb) { return ld(u.T, (uint32_t)iy[bb] * (uint32_t)L.nx + (uint32_t)ix[a]); },
+                      vc.T);
+        } else if (grp == 2) {
+            restrict9(resid(sm.sXX), rc.E);
+            restrict9(resid(sm.sXY), rc.Fx);
+        } else {
+            restrict9(resid(sm.sYY), rc.Fy);
+            restrict9(resid(sm.qT), rc.T);
+        }
     }
 }
 
@@ -844,7 +900,8 @@ __device__ __forceinline__ const Soa& pick(const BSlot& s, int sel) { return sel
 // Batched: work-list entries are the 32 x 4 coarse tiles of level `level` of
 // each problem; level - 1's residual (b on the finest level, else the FAS
 // right-hand side f) is formed and restricted with the state into (v, f).
-__global__ __launch_bounds__(kRcThreads) void kb_residual_restrict(const BProb* __restrict__ P,
+__global__ __launch_bounds__(kRcThreads) void kb_residual_restrict(
+    const BProb* __restrict__ P,
                                                                    const BSlot* __restrict__ S,
                                                                    const uint32_t* __restrict__ wl, int nwl,
                                                                    int level, int in_sel)

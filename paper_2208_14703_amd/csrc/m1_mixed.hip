@@ -549,17 +549,25 @@ __global__ __launch_bounds__(kBlock32) void k_mx_sweep(Phys ph, Lvl32 L, CSoa32 
 }
 
 // N(d) of one cell from its off-diagonal increment S, base temperature and correction.
-__device__ __forceinline__ void n_from_sums(const Phys& ph, const Lvl32& L, float S0, float S1, float S2, float wT,
-                                            float dE, float dFx, float dFy, float dT, uint32_t k, float& NE,
-                                            float& NFx, float& NFy, float& NT)
+// The same from the cell's opacities (sa, ss), loaded by the caller.
+__device__ __forceinline__ void n_from_sums_with(const Phys& ph, const Lvl32& L, float S0, float S1, float S2,
+                                                 float wT, float dE, float dFx, float dFy, float dT, float sa,
+                                                 float ss, float& NE, float& NFx, float& NFy, float& NT)
 {
-    const double ka = (double)L.cdt * ldf(L.sa, k), ks = (double)L.cdt * ldf(L.ss, k);
+    const double ka = (double)L.cdt * sa, ks = (double)L.cdt * ss;
     float DE, DFx, DFy, DT;
     diag_inc(L.a, ka, ks, ph.c_v, ph.a_r, wT, dE, dFx, dFy, dT, DE, DFx, DFy, DT);
     NE = DE - S0;
     NFx = DFx - S1;
     NFy = DFy - S2;
     NT = DT;
+}
+
+__device__ __forceinline__ void n_from_sums(const Phys& ph, const Lvl32& L, float S0, float S1, float S2, float wT,
+                                            float dE, float dFx, float dFy, float dT, uint32_t k, float& NE,
+                                            float& NFx, float& NFy, float& NT)
+{
+    n_from_sums_with(ph, L, S0, S1, S2, wT, dE, dFx, dFy, dT, ldf(L.sa, k), ldf(L.ss, k), NE, NFx, NFy, NT);
 }
 
 // Increment of A for one cell: N(d) = (D(w + d) - D(w)) - dS(d).
@@ -1104,11 +1112,15 @@ constexpr int kMrCW = 32, kMrCH = 4;
 constexpr int kMrSW = 2 * kMrCW + 3, kMrSH = 2 * kMrCH + 3, kMrRW = 2 * kMrCW + 1, kMrRH = 2 * kMrCH + 1;
 constexpr int kMrThreads = 512;
 
+// LDS of one tile: the staged base states, corrections and closure increments;
+// once every residual is formed, the residual of point q goes to
+// (sXX, sXY, sYY, qT)[q] (the closure increments are no longer read).
 struct MrLds {
     static constexpr int NS = kMrSW * kMrSH, NR = kMrRW * kMrRH;
     float sWE[NS], sWFx[NS], sWFy[NS], sWT[NS], sE[NS], sGx[NS], sGy[NS], sT[NS], sXX[NS], sXY[NS], sYY[NS];
-    float qE[NR], qFx[NR], qFy[NR], qT[NR];
+    float qT[NR];
 };
+static_assert(MrLds::NR <= MrLds::NS, "residuals are kept in the closure arrays");
 
 // The fused residual and restriction of the coarse tile at (I0, J0) (all
 // threads of the block take part; no thread returns early).
@@ -1118,9 +1130,31 @@ __device__ __forceinline__ void mx_residual_restrict_tile(MrLds& sm, const Phys&
                                                           int J0, bool live)
 {
     constexpr int NS = MrLds::NS, NR = MrLds::NR;
+    constexpr int RPT = (NR + kMrThreads - 1) / kMrThreads;  // residual points per thread
     const int nxc = L.nx / 2, nyc = L.ny / 2;
     const int fi0 = 2 * I0, fj0 = 2 * J0;
     const float c = (float)ph.c, c2 = (float)ph.c2;
+    // each residual point's own loads (opacities, right-hand side) first, to overlap the staging
+    float own[RPT][6];
+    bool has[RPT];
+#pragma unroll
+    for (int it = 0; it < RPT; ++it) {
+        const int q = threadIdx.x + it * kMrThreads;
+        const int gi = fi0 + q % kMrRW - 1, gj = fj0 + q / kMrRW - 1;
+        has[it] = q < NR && gi < L.nx && gj < L.ny;
+#pragma unroll
+        for (int m = 0; m < 6; ++m) own[it][m] = 0.0f;
+        if (has[it]) {
+            const int si = gi < 0 ? (px ? gi + L.nx : 0) : gi, sj = gj < 0 ? (py ? gj + L.ny : 0) : gj;
+            const uint32_t k = (uint32_t)sj * (uint32_t)L.nx + (uint32_t)si;
+            own[it][0] = ldf(L.sa, k);
+            own[it][1] = ldf(L.ss, k);
+            own[it][2] = ldf(X.E, k);
+            own[it][3] = ldf(X.Fx, k);
+            own[it][4] = ldf(X.Fy, k);
+            own[it][5] = ldf(X.T, k);
+        }
+    }
     for (int q = threadIdx.x; q < NS; q += kMrThreads) {
         const int gi = fi0 + q % kMrSW - 2, gj = fj0 + q / kMrSW - 2;
         int si, sj;
@@ -1156,14 +1190,13 @@ __device__ __forceinline__ void mx_residual_restrict_tile(MrLds& sm, const Phys&
         if (fj0 + rj < 0 && !py) rj += 1;
         return (rj + 2) * kMrSW + ri + 2;
     };
-    for (int q = threadIdx.x; q < NR; q += kMrThreads) {
-        const int ri = q % kMrRW - 1, rj = q / kMrRW - 1;
-        const int gi = fi0 + ri, gj = fj0 + rj;
+    float res[RPT][4];
+#pragma unroll
+    for (int it = 0; it < RPT; ++it) {
+        const int q = threadIdx.x + it * kMrThreads;
         float oE = 0.0f, oFx = 0.0f, oFy = 0.0f, oT = 0.0f;
-        if (gi < L.nx && gj < L.ny) {
-            const int n = centre(ri, rj);
-            const int si = gi < 0 ? (px ? gi + L.nx : 0) : gi, sj = gj < 0 ? (py ? gj + L.ny : 0) : gj;
-            const uint32_t k = (uint32_t)sj * (uint32_t)L.nx + (uint32_t)si;
+        if (has[it]) {
+            const int n = centre(q % kMrRW - 1, q / kMrRW - 1);
             float S0 = 0.0f, S1 = 0.0f, S2 = 0.0f;  // the order of offdiag_inc: x-, x+, y-, y+
             auto nb = [&](int m, float kk, float sg, bool xdir) {
                 acc_inc(kk, sg, xdir, c, sm.sE[m], sm.sGx[m], sm.sGy[m], DP{sm.sXX[m], sm.sXY[m], sm.sYY[m]}, S0, S1,
@@ -1174,20 +1207,36 @@ __device__ __forceinline__ void mx_residual_restrict_tile(MrLds& sm, const Phys&
             nb(n - kMrSW, L.ky, +1.0f, false);
             nb(n + kMrSW, L.ky, -1.0f, false);
             float NE, NFx, NFy, NT;
-            n_from_sums(ph, L, S0, S1, S2, sm.sWT[n], sm.sE[n], sm.sGx[n], sm.sGy[n], sm.sT[n], k, NE, NFx, NFy, NT);
-            oE = fmaf(sgn, NE, ldf(X.E, k));
-            oFx = fmaf(sgn, NFx, ldf(X.Fx, k));
-            oFy = fmaf(sgn, NFy, ldf(X.Fy, k));
-            oT = fmaf(sgn, NT, ldf(X.T, k));
+            n_from_sums_with(ph, L, S0, S1, S2, sm.sWT[n], sm.sE[n], sm.sGx[n], sm.sGy[n], sm.sT[n], own[it][0],
+                             own[it][1], NE, NFx, NFy, NT);
+            oE = fmaf(sgn, NE, own[it][2]);
+            oFx = fmaf(sgn, NFx, own[it][3]);
+            oFy = fmaf(sgn, NFy, own[it][4]);
+            oT = fmaf(sgn, NT, own[it][5]);
         }
-        sm.qE[q] = oE;
-        sm.qFx[q] = oFx;
-        sm.qFy[q] = oFy;
-        sm.qT[q] = oT;
+        res[it][0] = oE;
+        res[it][1] = oFx;
+        res[it][2] = oFy;
+        res[it][3] = oT;
+    }
+    __syncthreads();  // every closure increment has been read
+#pragma unroll
+    for (int it = 0; it < RPT; ++it) {
+        const int q = threadIdx.x + it * kMrThreads;
+        if (q < NR) {
+            sm.sXX[q] = res[it][0];
+            sm.sXY[q] = res[it][1];
+            sm.sYY[q] = res[it][2];
+            sm.qT[q] = res[it][3];
+        }
     }
     __syncthreads();
-    const int ci = threadIdx.x % kMrCW, cj = threadIdx.x / kMrCW, I = I0 + ci, J = J0 + cj;
-    if (threadIdx.x < kMrCW * kMrCH && I < nxc && J < nyc && live) {
+    // restriction: the 12 fields of the tile's coarse cells, three per thread (a wave-uniform triple of fields)
+    constexpr int NC = kMrCW * kMrCH;
+    static_assert(kMrThreads == 4 * NC, "four groups of threads, three restricted fields each");
+    const int cc = threadIdx.x % NC, grp = threadIdx.x / NC;
+    const int ci = cc % kMrCW, cj = cc / kMrCW, I = I0 + ci, J = J0 + cj;
+    if (I < nxc && J < nyc && live) {
         int ix[3], iy[3];
         float wx[3], wy[3];
         rweights32(I, L.nx, px != 0, ix, wx);
@@ -1206,18 +1255,23 @@ __device__ __forceinline__ void mx_residual_restrict_tile(MrLds& sm, const Phys&
             }
             stf(dst, (uint32_t)J * (uint32_t)nxc + (uint32_t)I, s);
         };
-        restrict12(sm.sWE, true, wc.E);
-        restrict12(sm.sWFx, true, wc.Fx);
-        restrict12(sm.sWFy, true, wc.Fy);
-        restrict12(sm.sWT, true, wc.T);
-        restrict12(sm.sE, true, dc.E);
-        restrict12(sm.sGx, true, dc.Fx);
-        restrict12(sm.sGy, true, dc.Fy);
-        restrict12(sm.sT, true, dc.T);
-        restrict12(sm.qE, false, gc.E);
-        restrict12(sm.qFx, false, gc.Fx);
-        restrict12(sm.qFy, false, gc.Fy);
-        restrict12(sm.qT, false, gc.T);
+        if (grp == 0) {
+            restrict12(sm.sWE, true, wc.E);
+            restrict12(sm.sWFx, true, wc.Fx);
+            restrict12(sm.sWFy, true, wc.Fy);
+        } else if (grp == 1) {
+            restrict12(sm.sWT, true, wc.T);
+            restrict12(sm.sE, true, dc.E);
+            restrict12(sm.sGx, true, dc.Fx);
+        } else if (grp == 2) {
+            restrict12(sm.sGy, true, dc.Fy);
+            restrict12(sm.sT, true, dc.T);
+            restrict12(sm.sXX, false, gc.E);
+        } else {
+            restrict12(sm.sXY, false, gc.Fx);
+            restrict12(sm.sYY, false, gc.Fy);
+            restrict12(sm.qT, false, gc.T);
+        }
     }
 }
 

@@ -315,6 +315,42 @@ def test_restrict_and_prolong_project_parity(dim, n, bcs):
     assert rel_err(got, ref, prob["c"]) <= 1e-13
 
 
+@pytest.mark.parametrize("dim,nx,ny", [(2, 96, 80), (2, 136, 72), (2, 64, 64), (1, 512, 1)])
+@pytest.mark.parametrize("bcs", ["periodic", "mixed", "wall"])
+def test_residual_restriction_parity(dim, nx, ny, bcs):
+    """m1_residual_restrict against the oracle's restriction of u and of
+    rhs - A_l(u), on the finest level (rhs = b) and on level 1 (its own
+    opacities and spacing), fused (one launch) and stored-then-restricted."""
+    announce("residual restriction", dim, nx, ny, bcs)
+    prob, v, sig = inputs.random_problem(8, dim, nx, ny, bc_kinds=BC_SETS[bcs], cfl=60.0, fmax=0.95)
+    o = oracle.Oracle(prob, sig)
+    rng = np.random.default_rng(9)
+    u = v.copy()  # another admissible state: E and F scaled together (f unchanged), T perturbed
+    u[:3] *= np.exp(rng.normal(size=u[0].shape) * 0.2)
+    u[3] *= np.exp(rng.normal(size=u[0].shape) * 0.1)
+    b = o.rhs(v)
+    g1, sig1 = o.coarse_grid(), o.restrict(sig)
+    u1 = o.restrict(u)
+    f1 = o.apply_A(o.restrict(v), sigma=sig1, g=g1) + rng.normal(size=u1.shape) * np.abs(u1).max()
+    if dim == 1:
+        f1[2] = 0.0
+    refs = [(o.restrict(u), o.restrict(b - o.apply_A(u))),
+            (o.restrict(u1, g=g1), o.restrict(f1 - o.apply_A(u1, sigma=sig1, g=g1), g=g1))]
+    old = binding.tune_get("residual_restrict")
+    try:
+        for fused in (1, 0):
+            binding.tune_set("residual_restrict", fused)
+            P = plan_for(prob, sig)
+            assert P.levels >= 3
+            for level, (uu, rhs) in enumerate(((u, b), (u1, f1))):
+                vc, rc = P.residual_restrict(level, to_dev(uu), to_dev(rhs))
+                assert rel_err(to_host(vc), refs[level][0], prob["c"]) <= 1e-14
+                rscale = np.abs(refs[level][1]).max()
+                assert np.abs(to_host(rc) - refs[level][1]).max() <= 1e-12 * rscale, (fused, level)
+    finally:
+        binding.tune_set("residual_restrict", old)
+
+
 # ------------------------------------------------------------------ one V-cycle
 @pytest.mark.parametrize("case", ["hot64", "logn64", "gauss256", "mixed32x64"])
 def test_vcycle_parity(case):
