@@ -49,18 +49,32 @@ typedef enum {
     M1_ERR_BUDGET = 7           /* request larger than the engine's HBM budget */
 } m1_status;
 
-typedef enum { M1_BC_PERIODIC = 0, M1_BC_REFLECTIVE = 1, M1_BC_NEUMANN = 2, M1_BC_DIRICHLET = 3 } m1_bc_kind;
+typedef enum {
+    M1_BC_PERIODIC = 0,
+    M1_BC_REFLECTIVE = 1,
+    M1_BC_NEUMANN = 2,
+    M1_BC_DIRICHLET = 3,
+    M1_BC_INFLOW = 4
+} m1_bc_kind;
 typedef enum { M1_FP64 = 0, M1_MIXED = 1 } m1_precision;
 typedef enum { M1_DTAU_SIGNED = 0, M1_DTAU_LITERAL = 1 } m1_dtau_rule;
+typedef enum { M1_SMOOTH_JACOBI = 0, M1_SMOOTH_RBGS = 1 } m1_smoother;
 
 /* Boundary condition of one side.  Ghost state of the neighbour outside the
  * domain: PERIODIC wraps; REFLECTIVE mirrors the adjacent cell with its normal
  * flux negated; NEUMANN copies the adjacent cell; DIRICHLET uses (E, Fx, Fy),
- * which must be admissible.  Periodic sides come in pairs (x-/x+, y-/y+).   */
+ * which must be admissible (|F| <= cE up to a relative 1e-12); INFLOW uses
+ * (E, Fx, Fy) for the boundary cells whose centres lie in [lo, hi] (fractions
+ * of the side's length from its low-coordinate end, 0 <= lo <= hi <= 1: cell a
+ * of n when lo n <= a + 1/2 <= hi n) and the isotropic state (Eo > 0, F = 0)
+ * elsewhere, on every level (a beam entering through part of a side into
+ * ambient radiation, Sect. 5.1).  lo, hi and Eo are read for INFLOW only.  Periodic sides come in pairs (x-/x+,
+ * y-/y+).                                                                    */
 typedef struct {
     int32_t kind;
     int32_t pad_;
     double E, Fx, Fy;
+    double lo, hi, Eo;
 } m1_bc;
 
 /* Discrete problem: the data of the implicit HLL system (Sect. 2.2) plus the
@@ -91,6 +105,11 @@ typedef struct {
  *   pseudo_local  1: the implicit pseudo-time step of each cell uses the pseudo
  *                 time its explicit sub-steps reached (consistent steady state);
  *                 0: dtau_im in every cell;
+ *   smoother      finest-level sweeps: M1_SMOOTH_JACOBI (Algorithm 1) or
+ *                 M1_SMOOTH_RBGS, red-black nonlinear Gauss-Seidel (the
+ *                 alternative of Sect. 6.3): the cells with i + j even take
+ *                 the relaxed Jacobi update, then the others the update of
+ *                 that state (FP64 plans only; not in engines);
  *   precision     M1_FP64 or M1_MIXED (FP32 delta-form smoothing and coarse
  *                 levels, FP64 residual, projection and T^4 update; M1_MIXED
  *                 requires nu_l = 1: its coarse steps fuse one sweep);
@@ -102,7 +121,7 @@ typedef struct {
  *   omega         relaxation of the finest-level sweeps: u <- u + omega (J(u) - u);
  *                 1 is Algorithm 1, 0 < omega <= 1 keeps admissibility.      */
 typedef struct {
-    int32_t levels, nu0, nu_l, pseudo_steps, sub_steps, max_cycles, dtau_rule, pseudo_local, precision, pad_;
+    int32_t levels, nu0, nu_l, pseudo_steps, sub_steps, max_cycles, dtau_rule, pseudo_local, precision, smoother;
     double dtau_im0, eps_inc, eps_dec, eta, rtol, dtau_min, dtau_max, omega;
 } m1_params;
 

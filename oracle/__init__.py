@@ -21,8 +21,9 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "m1_oracle.c")
 _LIB = os.path.join(_HERE, "libm1oracle.so")
 
-BC = {"periodic": 0, "reflective": 1, "neumann": 2, "dirichlet": 3}
+BC = {"periodic": 0, "reflective": 1, "neumann": 2, "dirichlet": 3, "inflow": 4}
 DTAU_RULE = {"signed": 0, "literal": 1}
+SMOOTHER = {"jacobi": 0, "rbgs": 1}
 
 
 class Grid(ctypes.Structure):
@@ -32,6 +33,7 @@ class Grid(ctypes.Structure):
         ("a_r", ctypes.c_double), ("c_v", ctypes.c_double),
         ("bc_kind", ctypes.c_int32 * 4),
         ("bc_E", ctypes.c_double * 4), ("bc_Fx", ctypes.c_double * 4), ("bc_Fy", ctypes.c_double * 4),
+        ("bc_lo", ctypes.c_double * 4), ("bc_hi", ctypes.c_double * 4), ("bc_Eo", ctypes.c_double * 4),
     ]
 
 
@@ -40,6 +42,7 @@ class Params(ctypes.Structure):
         ("levels", ctypes.c_int32), ("nu0", ctypes.c_int32), ("nu_l", ctypes.c_int32),
         ("pseudo_steps", ctypes.c_int32), ("sub_steps", ctypes.c_int32), ("max_cycles", ctypes.c_int32),
         ("dtau_rule", ctypes.c_int32), ("pseudo_local", ctypes.c_int32),
+        ("smoother", ctypes.c_int32), ("pad_", ctypes.c_int32),
         ("dtau_im0", ctypes.c_double), ("eps_inc", ctypes.c_double), ("eps_dec", ctypes.c_double),
         ("eta", ctypes.c_double), ("rtol", ctypes.c_double), ("dtau_min", ctypes.c_double),
         ("dtau_max", ctypes.c_double), ("omega", ctypes.c_double),
@@ -87,6 +90,7 @@ def lib():
         L.or_norm.argtypes = [gp, dp]
         L.or_jacobi.argtypes = [gp, dp, ctypes.c_double, ctypes.c_double, dp, dp, dp, dp]
         L.or_sweep.argtypes = [gp, dp, ctypes.c_double, dp, dp, dp]
+        L.or_rb_sweep.argtypes = [gp, dp, ctypes.c_double, dp, dp, dp]
         L.or_restrict.argtypes = [gp, dp, ctypes.c_int32, dp]
         L.or_prolong.argtypes = [gp, dp, ctypes.c_int32, dp]
         L.or_pseudo_time.argtypes = [gp, pp, ctypes.c_double, dp, dp, dp, dp]
@@ -101,6 +105,10 @@ def lib():
         L.or_step.argtypes = [gp, dp, pp, dp, ctypes.c_int32, ctypes.POINTER(Info), dp, ctypes.c_int32]
         L.or_threads.restype = ctypes.c_int32
         L.or_set_threads.argtypes = [ctypes.c_int32]
+        L.or_wave_speeds.argtypes = [ctypes.c_double, dp, ctypes.c_int, dp, dp]
+        L.or_explicit_step.argtypes = [gp, ctypes.c_int, dp, dp]
+        L.or_explicit_run.restype = ctypes.c_int32
+        L.or_explicit_run.argtypes = [gp, ctypes.c_int, dp, ctypes.c_int32, ctypes.c_double]
         _lib = L
     return _lib
 
@@ -119,6 +127,7 @@ def make_grid(problem: dict) -> Grid:
     for s, bc in enumerate(problem["bc"]):
         g.bc_kind[s] = BC[bc["kind"]]
         g.bc_E[s], g.bc_Fx[s], g.bc_Fy[s] = bc.get("E", 0.0), bc.get("Fx", 0.0), bc.get("Fy", 0.0)
+        g.bc_lo[s], g.bc_hi[s], g.bc_Eo[s] = bc.get("lo", 0.0), bc.get("hi", 1.0), bc.get("Eo", 0.0)
     return g
 
 
@@ -129,12 +138,12 @@ def make_params(**kw) -> Params:
     (omega=1), with the local pseudo-time step reading (pseudo_local=1).
     """
     d = dict(levels=0, nu0=3, nu_l=1, pseudo_steps=3, sub_steps=4, max_cycles=10000, dtau_rule="signed",
-             pseudo_local=1, dtau_im0=1e-3, eps_inc=0.05, eps_dec=0.0, eta=0.9, rtol=1e-10, dtau_min=1e-6,
-             dtau_max=1e6, omega=1.0)
+             pseudo_local=1, smoother="jacobi", dtau_im0=1e-3, eps_inc=0.05, eps_dec=0.0, eta=0.9, rtol=1e-10,
+             dtau_min=1e-6, dtau_max=1e6, omega=1.0)
     d.update(kw)
     p = Params()
     for k, v in d.items():
-        setattr(p, k, DTAU_RULE[v] if k == "dtau_rule" else v)
+        setattr(p, k, DTAU_RULE[v] if k == "dtau_rule" else SMOOTHER[v] if k == "smoother" else v)
     return p
 
 
@@ -191,6 +200,12 @@ class Oracle:
         self.L.or_sweep(ctypes.byref(self.g), _p(self.sigma), omega, _p(self._c(b)), _p(self._c(v)), _p(out))
         return out
 
+    def rb_sweep(self, b, v, omega=1.0):
+        """One red-black Gauss-Seidel sweep (red: i + j even, first)."""
+        out = self._new()
+        self.L.or_rb_sweep(ctypes.byref(self.g), _p(self.sigma), omega, _p(self._c(b)), _p(self._c(v)), _p(out))
+        return out
+
     def coarse_grid(self, g=None):
         return self.L.or_coarse_grid(ctypes.byref(g or self.g))
 
@@ -235,6 +250,27 @@ class Oracle:
         self.L.or_project(ctypes.byref(g), ctypes.byref(p), _p(self._c(u)), _p(self._c(w)), _p(out))
         return out
 
+    def explicit_step(self, v, hll=True, dt=None):
+        """One explicit step (HLL with the M1 wave speeds, or Rusanov) of the homogeneous system."""
+        g = self._grid_dt(dt)
+        out = self._new()
+        self.L.or_explicit_step(ctypes.byref(g), int(hll), _p(self._c(v)), _p(out))
+        return out
+
+    def explicit_run(self, v, hll=True, dt=None, max_steps=100000, tol=1e-12):
+        """Explicit steps to a steady state (largest change of E in a step <= tol max E)."""
+        g = self._grid_dt(dt)
+        v = self._c(v).copy()
+        steps = self.L.or_explicit_run(ctypes.byref(g), int(hll), _p(v), max_steps, tol)
+        return v, steps
+
+    def _grid_dt(self, dt):
+        if dt is None:
+            return self.g
+        g = Grid.from_buffer_copy(self.g)
+        g.dt = dt
+        return g
+
     def num_levels(self, params=None):
         return self.L.or_num_levels(ctypes.byref(self.g), ctypes.byref(params or make_params()))
 
@@ -276,6 +312,13 @@ def local_solve(beta, gamma, a, ka, ks, cv, ar, B):
 
 def ray(c, w, s):
     return lib().or_ray(c, _p(np.ascontiguousarray(w, dtype=np.float64)), _p(np.ascontiguousarray(s, dtype=np.float64)))
+
+
+def wave_speeds(c, U, axis=0):
+    """Smallest and largest wave speed of the M1 flux along `axis` at U = (E, Fx, Fy)."""
+    lm, lp = ctypes.c_double(), ctypes.c_double()
+    lib().or_wave_speeds(c, _p(np.ascontiguousarray(U[:3], dtype=np.float64)), axis, ctypes.byref(lm), ctypes.byref(lp))
+    return lm.value, lp.value
 
 
 def admissible(c, w):

@@ -53,6 +53,17 @@ def _pad(U, prob):
             P[(0,) + dst[1:]] = bc["E"]
             P[(1,) + dst[1:]] = bc["Fx"]
             P[(2,) + dst[1:]] = bc["Fy"]
+        elif kind == "inflow":  # wall state where the boundary cell's centre is in [lo, hi] of the side, else (Eo, 0)
+            P[(0,) + dst[1:]] = bc["Eo"]
+            P[(1,) + dst[1:]] = 0.0
+            P[(2,) + dst[1:]] = 0.0
+            n = ny if side < 2 else nx
+            centres = (np.arange(n) + 0.5) / n
+            on = (centres >= bc["lo"]) & (centres <= bc["hi"])
+            for q, key in enumerate(("E", "Fx", "Fy")):
+                row = P[(q,) + dst[1:]]
+                row[on] = bc[key]
+                P[(q,) + dst[1:]] = row
         else:
             raise ValueError(kind)
     return P

@@ -87,7 +87,10 @@ int or_admissible(double c, const double w[4])
 /* ------------------------------------------------------------------------- */
 /* Ghost / neighbour state (E, Fx, Fy) of cell (i,j) in direction (di,dj).
  * Periodic: wrap; reflective: the cell itself with the normal flux negated;
- * Neumann: the cell itself; Dirichlet: the fixed wall state of that side.   */
+ * Neumann: the cell itself; Dirichlet: the fixed wall state of that side;
+ * inflow: the wall state for the boundary cells whose centres lie in the
+ * side's [lo, hi] (fractions of its length), the isotropic state (Eo, F = 0)
+ * elsewhere.                                                                 */
 static void neighbour(const or_grid* g, const double* v, int i, int j, int di, int dj, double U[3])
 {
     const size_t n = ncell(g);
@@ -109,6 +112,20 @@ static void neighbour(const or_grid* g, const double* v, int i, int j, int di, i
             U[2] = v[2 * n + k];
             if (side < 2) U[1] = -U[1];
             else U[2] = -U[2];
+            return;
+        }
+        case OR_BC_INFLOW: {
+            const int along = side < 2 ? j : i, len = side < 2 ? g->ny : g->nx;
+            const double centre = along + 0.5;
+            if (centre >= g->bc_lo[side] * len && centre <= g->bc_hi[side] * len) {
+                U[0] = g->bc_E[side];
+                U[1] = g->bc_Fx[side];
+                U[2] = g->bc_Fy[side];
+            } else {
+                U[0] = g->bc_Eo[side];
+                U[1] = 0.0;
+                U[2] = 0.0;
+            }
             return;
         }
         case OR_BC_NEUMANN: {
@@ -325,6 +342,36 @@ void or_sweep(const or_grid* g, const double* sigma, double omega, const double*
     or_jacobi(g, sigma, 0.0, 1.0, NULL, b, v_in, v_out);
     if (omega != 1.0)
         for (size_t k = 0; k < NFIELD * n; ++k) v_out[k] = (1.0 - omega) * v_in[k] + omega * v_out[k];
+}
+
+/* Red-black nonlinear Gauss-Seidel sweep, the alternative to the Jacobi
+ * smoother of Sect. 6.3: the "red" cells (i + j even) take the relaxed Jacobi
+ * update of v_in, then the "black" cells (i + j odd) take the relaxed Jacobi
+ * update of that intermediate state.  Where every neighbour of a cell has the
+ * other colour (sides of even length or not periodic), each half is the
+ * Gauss-Seidel update of one colour.  Each cell's update is the local solve
+ * of a Jacobi sweep with admissible neighbours, so the argument of Prop. 1
+ * keeps every state admissible.                                              */
+void or_rb_sweep(const or_grid* g, const double* sigma, double omega, const double* b, const double* v_in,
+                 double* v_out)
+{
+    const size_t n = ncell(g);
+    double* J = dalloc(NFIELD * n);
+    double* mid = dalloc(NFIELD * n);
+    or_sweep(g, sigma, omega, b, v_in, J);
+    for (int j = 0; j < g->ny; ++j)
+        for (int i = 0; i < g->nx; ++i) {
+            const size_t k = (size_t)j * g->nx + i;
+            for (int m = 0; m < NFIELD; ++m) mid[m * n + k] = ((i + j) % 2 == 0) ? J[m * n + k] : v_in[m * n + k];
+        }
+    or_sweep(g, sigma, omega, b, mid, J);
+    for (int j = 0; j < g->ny; ++j)
+        for (int i = 0; i < g->nx; ++i) {
+            const size_t k = (size_t)j * g->nx + i;
+            for (int m = 0; m < NFIELD; ++m) v_out[m * n + k] = ((i + j) % 2 == 1) ? J[m * n + k] : mid[m * n + k];
+        }
+    free(J);
+    free(mid);
 }
 
 /* ------------------------------------------------------------------------- */
@@ -583,15 +630,16 @@ int32_t or_num_levels(const or_grid* g, const or_params* p)
     return L;
 }
 
-static void sweeps(const or_grid* g, const double* sigma, double omega, const double* b, const double* v0, int nu,
-                   double* out)
+static void sweeps(const or_grid* g, const double* sigma, double omega, int smoother, const double* b,
+                   const double* v0, int nu, double* out)
 {
     const size_t n = ncell(g);
     double* cur = dalloc(NFIELD * n);
     double* nxt = dalloc(NFIELD * n);
     memcpy(cur, v0, NFIELD * n * sizeof(double));
     for (int s = 0; s < nu; ++s) {
-        or_sweep(g, sigma, omega, b, cur, nxt);
+        if (smoother == OR_SMOOTH_RBGS) or_rb_sweep(g, sigma, omega, b, cur, nxt);
+        else or_sweep(g, sigma, omega, b, cur, nxt);
         double* t = cur;
         cur = nxt;
         nxt = t;
@@ -648,7 +696,7 @@ void or_vcycle(const or_grid* g, const double* sigma, const or_params* p, double
         }
     }
 
-    sweeps(&G[0], S[0], p->omega, b, v, p->nu0, U[0]);
+    sweeps(&G[0], S[0], p->omega, p->smoother, b, v, p->nu0, U[0]);
     if (L > 1) {
         double* rbar = dalloc(NFIELD * ncell(&G[0]));
         or_residual(&G[0], S[0], b, U[0], rbar);
@@ -681,7 +729,7 @@ void or_vcycle(const or_grid* g, const double* sigma, const or_params* p, double
             free(e);
             free(w);
             double* t = dalloc(NFIELD * n);
-            if (l == 0) sweeps(&G[0], S[0], p->omega, b, U[0], p->nu0, t);
+            if (l == 0) sweeps(&G[0], S[0], p->omega, p->smoother, b, U[0], p->nu0, t);
             else pseudo_smooth(&G[l], S[l], p, dtau, Fr[l], U[l], t);
             memcpy(U[l], t, NFIELD * n * sizeof(double));
             free(t);
@@ -776,4 +824,124 @@ int32_t or_step(const or_grid* g, const double* sigma, const or_params* p, doubl
     free(r);
     free(nv);
     return status;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Explicit reference solver of the homogeneous M1 system (Sect. 2.2 with no
+ * sources; the explicit HLL scheme the paper compares against in Sect. 5).  */
+
+/* Smallest and largest eigenvalue of the Jacobian of the directional flux
+ * (axis 0: x, 1: y) of the M1 system at U = (E, F): with f = |F|/(cE),
+ * s = sqrt(4 - 3 f^2) and mu the cosine between F and the axis,
+ *   lambda = c (f mu -+ sqrt(2/3 (4 - 3 f^2 - s) + 2 mu^2 (2 - f^2 - s))) / s,
+ * the wave speeds of the M1 model in closed form (the eigenvalues the HLL
+ * speeds of Sect. 2.2 come from; they lie in [-c, c]).                       */
+void or_wave_speeds(double c, const double U[3], int axis, double* lm, double* lp)
+{
+    const double normF = sqrt(U[1] * U[1] + U[2] * U[2]);
+    double f = normF / (c * U[0]);
+    if (f > 1.0) f = 1.0;
+    const double mu = normF > 0.0 ? (axis == 0 ? U[1] : U[2]) / normF : 0.0;
+    const double s = sqrt(4.0 - 3.0 * f * f);
+    double rad = 2.0 / 3.0 * (4.0 - 3.0 * f * f - s) + 2.0 * mu * mu * (2.0 - f * f - s);
+    if (rad < 0.0) rad = 0.0; /* rounding at f = 1 */
+    const double r = sqrt(rad);
+    *lm = c * (f * mu - r) / s;
+    *lp = c * (f * mu + r) / s;
+}
+
+/* Directional physical flux G_axis(U). */
+static void phys_flux(double c, const double U[3], int axis, double G[3])
+{
+    double P[3];
+    or_closure(U[0], U[1], U[2], c, P);
+    if (axis == 0) {
+        G[0] = U[1];
+        G[1] = c * c * P[0];
+        G[2] = c * c * P[1];
+    } else {
+        G[0] = U[2];
+        G[1] = c * c * P[1];
+        G[2] = c * c * P[2];
+    }
+}
+
+/* Numerical flux between the states UL (low side) and UR (high side) along
+ * `axis`: HLL with speeds lm = min(lambda-(UL), lambda-(UR)) and
+ * lp = max(lambda+(UL), lambda+(UR)) (hll = 1), or the speeds -c and c, the
+ * Rusanov flux the implicit scheme uses (hll = 0).                            */
+static void num_flux(double c, const double UL[3], const double UR[3], int axis, int hll, double H[3])
+{
+    double GL[3], GR[3], lm = -c, lp = c;
+    phys_flux(c, UL, axis, GL);
+    phys_flux(c, UR, axis, GR);
+    if (hll) {
+        double a, b, a2, b2;
+        or_wave_speeds(c, UL, axis, &a, &b);
+        or_wave_speeds(c, UR, axis, &a2, &b2);
+        lm = fmin(a, a2);
+        lp = fmax(b, b2);
+    }
+    if (lm >= 0.0) {
+        for (int m = 0; m < 3; ++m) H[m] = GL[m];
+    } else if (lp <= 0.0) {
+        for (int m = 0; m < 3; ++m) H[m] = GR[m];
+    } else {
+        for (int m = 0; m < 3; ++m) H[m] = (lp * GL[m] - lm * GR[m] + lp * lm * (UR[m] - UL[m])) / (lp - lm);
+    }
+}
+
+/* One explicit Euler step of dU/dt + div G(U) = 0 (E and F; T is left as it
+ * is) with the grid's dt, from v into out: finite volumes with the numerical
+ * flux above at every face, boundary faces taking the ghost state of the
+ * boundary rule (periodic, reflective, Neumann, Dirichlet, inflow).  Stable
+ * and admissible for c dt (1/hx + 1/hy) <= 1.                                */
+void or_explicit_step(const or_grid* g, int hll, const double* v, double* out)
+{
+    const size_t n = ncell(g);
+#pragma omp parallel for schedule(static)
+    for (int j = 0; j < g->ny; ++j) {
+        for (int i = 0; i < g->nx; ++i) {
+            const size_t k = (size_t)j * g->nx + i;
+            double U[3] = {v[k], v[n + k], v[2 * n + k]}, N[3], H[3], d[3] = {0.0, 0.0, 0.0};
+            neighbour(g, v, i, j, -1, 0, N); /* face i-1/2 */
+            num_flux(g->c, N, U, 0, hll, H);
+            for (int m = 0; m < 3; ++m) d[m] += H[m] / g->hx;
+            neighbour(g, v, i, j, +1, 0, N); /* face i+1/2 */
+            num_flux(g->c, U, N, 0, hll, H);
+            for (int m = 0; m < 3; ++m) d[m] -= H[m] / g->hx;
+            if (g->dim == 2) {
+                neighbour(g, v, i, j, 0, -1, N);
+                num_flux(g->c, N, U, 1, hll, H);
+                for (int m = 0; m < 3; ++m) d[m] += H[m] / g->hy;
+                neighbour(g, v, i, j, 0, +1, N);
+                num_flux(g->c, U, N, 1, hll, H);
+                for (int m = 0; m < 3; ++m) d[m] -= H[m] / g->hy;
+            }
+            for (int m = 0; m < 3; ++m) out[m * n + k] = U[m] + g->dt * d[m];
+            out[3 * n + k] = v[3 * n + k];
+        }
+    }
+}
+
+/* Explicit steps from v (updated in place) until the largest change of E in a
+ * step is at most tol times the largest E, or max_steps.  Returns the steps. */
+int32_t or_explicit_run(const or_grid* g, int hll, double* v, int32_t max_steps, double tol)
+{
+    const size_t n = ncell(g);
+    double* nv = dalloc(NFIELD * n);
+    int32_t s = 0;
+    while (s < max_steps) {
+        or_explicit_step(g, hll, v, nv);
+        ++s;
+        double dmax = 0.0, emax = 0.0;
+        for (size_t k = 0; k < n; ++k) {
+            dmax = fmax(dmax, fabs(nv[k] - v[k]));
+            emax = fmax(emax, fabs(nv[k]));
+        }
+        memcpy(v, nv, NFIELD * n * sizeof(double));
+        if (dmax <= tol * emax) break;
+    }
+    free(nv);
+    return s;
 }

@@ -23,14 +23,17 @@
 extern "C" {
 #endif
 
-enum { OR_BC_PERIODIC = 0, OR_BC_REFLECTIVE = 1, OR_BC_NEUMANN = 2, OR_BC_DIRICHLET = 3 };
+enum { OR_BC_PERIODIC = 0, OR_BC_REFLECTIVE = 1, OR_BC_NEUMANN = 2, OR_BC_DIRICHLET = 3, OR_BC_INFLOW = 4 };
 enum { OR_DTAU_SIGNED = 0, OR_DTAU_LITERAL = 1 };
+enum { OR_SMOOTH_JACOBI = 0, OR_SMOOTH_RBGS = 1 };
 
 typedef struct {
     int32_t dim, nx, ny, pad_;
     double hx, hy, dt, c, a_r, c_v;
     int32_t bc_kind[4];              /* sides x-, x+, y-, y+ */
-    double bc_E[4], bc_Fx[4], bc_Fy[4]; /* Dirichlet ghost state per side */
+    double bc_E[4], bc_Fx[4], bc_Fy[4]; /* Dirichlet / inflow ghost state per side */
+    double bc_lo[4], bc_hi[4];          /* inflow segment of each side, as fractions of its length */
+    double bc_Eo[4];                    /* inflow sides: energy of the isotropic ghost outside the segment */
 } or_grid;
 
 typedef struct {
@@ -42,6 +45,8 @@ typedef struct {
     int32_t max_cycles;
     int32_t dtau_rule;     /* OR_DTAU_SIGNED or OR_DTAU_LITERAL */
     int32_t pseudo_local;  /* 1: implicit pseudo-time step uses each cell's own tau_i; 0: dtau_im everywhere */
+    int32_t smoother;      /* finest-level sweeps: OR_SMOOTH_JACOBI or OR_SMOOTH_RBGS (red-black Gauss-Seidel) */
+    int32_t pad_;
     double dtau_im0, eps_inc, eps_dec, eta, rtol, dtau_min, dtau_max;
     double omega;          /* relaxation weight of the finest-level Jacobi sweeps (1 = Algorithm 1) */
 } or_params;
@@ -67,6 +72,8 @@ void   or_jacobi(const or_grid* g, const double* sigma, double beta, double gamm
                  const double* rhs, const double* v_in, double* v_out);
 void   or_sweep(const or_grid* g, const double* sigma, double omega, const double* b, const double* v_in,
                 double* v_out);
+void   or_rb_sweep(const or_grid* g, const double* sigma, double omega, const double* b, const double* v_in,
+                   double* v_out);
 void   or_restrict(const or_grid* fine, const double* x_fine, int32_t nfields, double* x_coarse);
 void   or_prolong(const or_grid* fine, const double* x_coarse, int32_t nfields, double* x_fine);
 void   or_pseudo_time(const or_grid* g, const or_params* p, double dtau, const double* f, const double* u_in,
@@ -83,6 +90,11 @@ void   or_vcycle(const or_grid* g, const double* sigma, const or_params* p, doub
 int32_t or_step(const or_grid* g, const double* sigma, const or_params* p, double* v, int32_t nsteps,
                 or_info* info, double* history, int32_t history_len);
 int32_t or_threads(void);
+
+/* explicit reference of the homogeneous system (HLL with the M1 wave speeds, or Rusanov) */
+void   or_wave_speeds(double c, const double U[3], int axis, double* lm, double* lp);
+void   or_explicit_step(const or_grid* g, int hll, const double* v, double* out);
+int32_t or_explicit_run(const or_grid* g, int hll, double* v, int32_t max_steps, double tol);
 void   or_set_threads(int32_t n);
 
 #ifdef __cplusplus

@@ -21,9 +21,10 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "_lib", "libm1mg.so")
 
-BC = {"periodic": 0, "reflective": 1, "neumann": 2, "dirichlet": 3}
+BC = {"periodic": 0, "reflective": 1, "neumann": 2, "dirichlet": 3, "inflow": 4}
 PRECISION = {"fp64": 0, "mixed": 1}
 DTAU_RULE = {"signed": 0, "literal": 1}
+SMOOTHER = {"jacobi": 0, "rbgs": 1}
 STATUS = {0: "M1_OK", 1: "M1_ERR_ARG", 2: "M1_ERR_NOT_ADMISSIBLE", 3: "M1_ERR_NO_CONVERGENCE", 4: "M1_ERR_WORKSPACE",
           5: "M1_ERR_DEVICE", 6: "M1_ERR_BUSY", 7: "M1_ERR_BUDGET"}
 
@@ -36,7 +37,7 @@ class M1Error(RuntimeError):
 
 class m1_bc(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int32), ("pad_", ctypes.c_int32), ("E", ctypes.c_double), ("Fx", ctypes.c_double),
-                ("Fy", ctypes.c_double)]
+                ("Fy", ctypes.c_double), ("lo", ctypes.c_double), ("hi", ctypes.c_double), ("Eo", ctypes.c_double)]
 
 
 class m1_grid(ctypes.Structure):
@@ -47,7 +48,7 @@ class m1_grid(ctypes.Structure):
 
 class m1_params(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int32) for n in ("levels", "nu0", "nu_l", "pseudo_steps", "sub_steps", "max_cycles",
-                                              "dtau_rule", "pseudo_local", "precision", "pad_")] + \
+                                              "dtau_rule", "pseudo_local", "precision", "smoother")] + \
                [(n, ctypes.c_double) for n in ("dtau_im0", "eps_inc", "eps_dec", "eta", "rtol", "dtau_min",
                                                "dtau_max", "omega")]
 
@@ -175,6 +176,7 @@ def make_grid(problem: dict) -> m1_grid:
     for s, bc in enumerate(problem["bc"]):
         g.bc[s].kind = BC[bc["kind"]]
         g.bc[s].E, g.bc[s].Fx, g.bc[s].Fy = bc.get("E", 0.0), bc.get("Fx", 0.0), bc.get("Fy", 0.0)
+        g.bc[s].lo, g.bc[s].hi, g.bc[s].Eo = bc.get("lo", 0.0), bc.get("hi", 1.0), bc.get("Eo", 0.0)
     return g
 
 
@@ -182,9 +184,10 @@ def default_params(**kw) -> dict:
     """The paper's solver parameters (see m1_params in include/m1.h), updated with kw."""
     p = m1_params()
     lib().m1_default_params(ctypes.byref(p))
-    d = {name: getattr(p, name) for name, _ in m1_params._fields_ if name != "pad_"}
+    d = {name: getattr(p, name) for name, _ in m1_params._fields_}
     d["dtau_rule"] = "signed"
     d["precision"] = "fp64"
+    d["smoother"] = "jacobi"
     d.update(kw)
     return d
 
@@ -196,6 +199,8 @@ def make_params(d: dict) -> m1_params:
             v = PRECISION[v] if isinstance(v, str) else v
         elif k == "dtau_rule":
             v = DTAU_RULE[v] if isinstance(v, str) else v
+        elif k == "smoother":
+            v = SMOOTHER[v] if isinstance(v, str) else v
         setattr(p, k, v)
     return p
 

@@ -82,11 +82,13 @@ bool valid_bc(const m1_grid& g)
 {
     for (int s = 0; s < (g.dim == 2 ? 4 : 2); ++s) {
         const m1_bc& b = g.bc[s];
-        if (b.kind < M1_BC_PERIODIC || b.kind > M1_BC_DIRICHLET) return false;
-        if (b.kind == M1_BC_DIRICHLET) {
+        if (b.kind < M1_BC_PERIODIC || b.kind > M1_BC_INFLOW) return false;
+        if (b.kind == M1_BC_DIRICHLET || b.kind == M1_BC_INFLOW) {  // an admissible wall state (|F| = cE allowed)
             if (!(std::isfinite(b.E) && std::isfinite(b.Fx) && std::isfinite(b.Fy) && b.E > 0.0)) return false;
-            if (std::sqrt(b.Fx * b.Fx + (g.dim == 2 ? b.Fy * b.Fy : 0.0)) > g.c * b.E) return false;
+            if (std::sqrt(b.Fx * b.Fx + (g.dim == 2 ? b.Fy * b.Fy : 0.0)) > g.c * b.E * (1.0 + 1e-12)) return false;
         }
+        if (b.kind == M1_BC_INFLOW && !(b.lo >= 0.0 && b.lo <= b.hi && b.hi <= 1.0 && b.Eo > 0.0 && std::isfinite(b.Eo)))
+            return false;
     }
     if ((g.bc[0].kind == M1_BC_PERIODIC) != (g.bc[1].kind == M1_BC_PERIODIC)) return false;
     if (g.dim == 2 && (g.bc[2].kind == M1_BC_PERIODIC) != (g.bc[3].kind == M1_BC_PERIODIC)) return false;
@@ -114,6 +116,8 @@ bool valid_params(const m1_params* p)
     if (p->dtau_rule != M1_DTAU_SIGNED && p->dtau_rule != M1_DTAU_LITERAL) return false;
     if (p->precision != M1_FP64 && p->precision != M1_MIXED) return false;
     if (p->precision == M1_MIXED && p->nu_l != 1) return false;  // coarse correction steps fuse one sweep
+    if (p->smoother != M1_SMOOTH_JACOBI && p->smoother != M1_SMOOTH_RBGS) return false;
+    if (p->smoother == M1_SMOOTH_RBGS && p->precision != M1_FP64) return false;
     if (!(p->eta > 0.0 && p->eta < 1.0) || !(p->omega > 0.0 && p->omega <= 1.0) || !(p->rtol > 0.0)) return false;
     if (!(p->dtau_im0 > 0.0) || !(p->dtau_min > 0.0) || !(p->dtau_max >= p->dtau_min)) return false;
     return std::isfinite(p->eps_inc) && std::isfinite(p->eps_dec);
@@ -290,10 +294,22 @@ int64_t tail_cells() { return tuning().tail_cells.load(); }
 int64_t tiled_max_cells() { return tuning().tiled_max_cells.load(); }
 bool use_graphs() { return tuning().graphs.load() != 0; }
 
+// Boundary cells a (counted along a side of n cells) whose centres (a + 1/2)/n lie in [lo, hi]:
+// a in [s0, s1).  Only inflow sides have any.
+void inflow_cells(const m1_bc& b, int n, int& s0, int& s1)
+{
+    s0 = s1 = 0;
+    if (b.kind != M1_BC_INFLOW) return;
+    s0 = std::max(0, (int)std::ceil(b.lo * n - 0.5));
+    s1 = std::min(n, (int)std::floor(b.hi * n - 0.5) + 1);
+    if (s1 < s0) s1 = s0;
+}
+
 void fill_level_params(m1_plan& P)
 {
     const m1_grid& g = P.grid;
-    for (LevelBuf& lv : P.lev) {
+    for (int l = 0; l < P.L; ++l) {
+        LevelBuf& lv = P.lev[l];
         lv.L.nx = lv.nx;
         lv.L.ny = lv.ny;
         lv.L.sh = m1::row_shift(lv.nx);
@@ -304,8 +320,17 @@ void fill_level_params(m1_plan& P)
         lv.L.cdt = g.c * g.dt;
         lv.L.sa = lv.sa;
         lv.L.ss = lv.ss;
+        for (int sd = 0; sd < 4; ++sd) {
+            const bool on = g.dim == 2 || sd < 2;
+            if (on) inflow_cells(g.bc[sd], sd < 2 ? lv.ny : lv.nx, lv.L.sg0[sd], lv.L.sg1[sd]);
+            else lv.L.sg0[sd] = lv.L.sg1[sd] = 0;
+        }
         lv.L32 = m1::Lvl32{lv.nx, lv.ny, lv.L.sh, (float)lv.L.kx, (float)lv.L.ky, (float)lv.L.a, (float)lv.L.cdt, lv.sa32,
-                           lv.ss32};
+                           lv.ss32, {}, {}};
+        for (int sd = 0; sd < 4; ++sd) {
+            lv.L32.sg0[sd] = lv.L.sg0[sd];
+            lv.L32.sg1[sd] = lv.L.sg1[sd];
+        }
     }
 }
 
@@ -345,6 +370,11 @@ int fine_launch(m1_plan& P, const CSoa& b, const CSoa& in, const Soa& out, bool 
                 const int* active)
 {
     const LevelBuf& f = P.lev[0];
+    if (P.params.smoother == M1_SMOOTH_RBGS) {  // red cells into the plan's finest residual buffer, then black
+        m1::launch_relax_colour(P.st, P.dim, P.ph, f.L, b, P.params.omega, 0, in, P.rfine, partials, active);
+        m1::launch_relax_colour(P.st, P.dim, P.ph, f.L, b, P.params.omega, 1, cs(P.rfine), out, nullptr, active);
+        return 1;
+    }
     if (two && !partials && P.dim == 2 && m1::launch_relax2_lds(P.st, P.ph, f.L, b, P.params.omega, in, out, active))
         return 2;
     m1::launch_relax(P.st, P.dim, P.ph, f.L, b, nullptr, 0.0, 1.0, P.params.omega, in, out, partials, active);
@@ -466,7 +496,7 @@ void vcycle_impl(m1_plan& P, Soa& cur, Soa& other, const Gate& G, bool control =
             ul[l] = out;
             continue;
         }
-        if (l == 0 && P.dim == 2 && p.nu0 > 0 &&
+        if (l == 0 && P.dim == 2 && p.nu0 > 0 && p.smoother == M1_SMOOTH_JACOBI &&
             m1::launch_relax_lds(P.st, P.ph, f.L, cs(P.b), p.omega, cs(ul[0]), other, G.active, cs(ul[1]), cs(c.v),
                                  P.px, P.py, p.eta)) {
             // correction, projection and the first post-sweep in one launch
@@ -815,6 +845,7 @@ static m1_status plan_init(m1_plan* P, const m1_grid* g, const m1_params* p, con
         P->ph.bcE[s] = g->bc[s].E;
         P->ph.bcFx[s] = g->bc[s].Fx;
         P->ph.bcFy[s] = g->dim == 2 ? g->bc[s].Fy : 0.0;
+        P->ph.bcEo[s] = g->bc[s].kind == M1_BC_INFLOW ? g->bc[s].Eo : 0.0;
     }
     Carver c{static_cast<char*>(workspace)};
     carve(*P, c, dims);
@@ -1216,8 +1247,7 @@ m1_status m1_sweep(m1_plan* P, const m1_state* b, const m1_state* v_in, m1_state
 {
     if (!P || !valid_state(P, b) || !valid_state(P, v_in) || !valid_state(P, v_out) || v_in->E == v_out->E)
         return M1_ERR_ARG;
-    m1::launch_relax(P->st, P->dim, P->ph, P->lev[0].L, cs(to_soa(b)), nullptr, 0.0, 1.0, P->params.omega,
-                     cs(to_soa(v_in)), to_soa(v_out), nullptr, &P->dfix->active);
+    fine_launch(*P, cs(to_soa(b)), cs(to_soa(v_in)), to_soa(v_out), false, nullptr, &P->dfix->active);
     return last_launch();
 }
 
@@ -1228,7 +1258,7 @@ m1_status m1_sweeps(m1_plan* P, const m1_state* b, const m1_state* v_in, m1_stat
         return M1_ERR_ARG;
     // launches alternate between v_out and the plan's spare finest-level state,
     // starting with the one that makes the last launch write v_out
-    const bool pairs = P->dim == 2 && m1::pair_rows() > 0;
+    const bool pairs = P->dim == 2 && m1::pair_rows() > 0 && P->params.smoother == M1_SMOOTH_JACOBI;
     const int launches = pairs ? nsweeps / 2 + nsweeps % 2 : nsweeps;
     const Soa out = to_soa(v_out);
     Soa cur = launches % 2 ? out : P->tmp, other = launches % 2 ? P->tmp : out;
@@ -1478,7 +1508,8 @@ bool batch_compatible(const m1_engine& E, const m1_grid* g, const m1_params* p)
 {
     if (!valid_grid(g) || !valid_params(p) || g->dim != 2) return false;
     const m1_params& e = E.params;
-    if (p->nu0 != e.nu0 || p->nu_l != 1 || p->pseudo_steps != e.pseudo_steps || p->sub_steps != e.sub_steps ||
+    if (p->nu0 != e.nu0 || p->nu_l != 1 || p->smoother != e.smoother || p->pseudo_steps != e.pseudo_steps ||
+        p->sub_steps != e.sub_steps ||
         p->pseudo_local != e.pseudo_local || p->precision != e.precision || p->omega != e.omega || p->eta != e.eta)
         return false;
     Dims d;
@@ -1916,7 +1947,7 @@ m1_status m1_engine_create(const m1_params* p, void* arena, size_t arena_bytes, 
     if (!out) return M1_ERR_ARG;
     *out = nullptr;
     if (!valid_params(p) || max_requests < 1 || max_requests > (1 << (32 - m1::kTileBits)) ||
-        p->pseudo_steps % 2 == 0 || p->nu_l != 1)
+        p->pseudo_steps % 2 == 0 || p->nu_l != 1 || p->smoother != M1_SMOOTH_JACOBI)
         return M1_ERR_ARG;
     if (!arena || (reinterpret_cast<uintptr_t>(arena) % kAlign) != 0) return M1_ERR_WORKSPACE;
     m1_engine* E = new (std::nothrow) m1_engine();

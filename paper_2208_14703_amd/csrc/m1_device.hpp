@@ -13,13 +13,14 @@
 
 namespace m1 {
 
-enum BcKind : int { BC_PERIODIC = 0, BC_REFLECTIVE = 1, BC_NEUMANN = 2, BC_DIRICHLET = 3 };
+enum BcKind : int { BC_PERIODIC = 0, BC_REFLECTIVE = 1, BC_NEUMANN = 2, BC_DIRICHLET = 3, BC_INFLOW = 4 };
 
 // Physics and boundary data shared by every level.
 struct Phys {
     double c, c2, a_r, c_v;
     int bc[4];  // x-, x+, y-, y+
     double bcE[4], bcFx[4], bcFy[4];
+    double bcEo[4];  // inflow sides: energy of the isotropic ghost outside the segment
 };
 
 // One grid level as seen by a kernel.  Cells are numbered k = j nx + i in
@@ -32,6 +33,7 @@ struct Lvl {
     double cdt;     // c dt  (kappa = c dt sigma)
     const double* sa;
     const double* ss;
+    int sg0[4], sg1[4];  // inflow sides: boundary cells sg0 <= along < sg1 take the wall state (else empty)
 };
 
 struct Soa {
@@ -153,22 +155,31 @@ __device__ __forceinline__ void add_y(double k, double c, double c2, double sgn,
 // loaded for that neighbour: inside the domain (or across a periodic side) they
 // are the neighbour's own; at another side they were loaded from the cell
 // itself and become its ghost (Neumann copy, reflective mirror of the normal
-// flux, Dirichlet wall state).  Exact arithmetic selects (x 1, x 0 of a finite
-// value, x -1), so that callers can load unconditionally.
+// flux, Dirichlet wall state; on an inflow side the wall state on the cells
+// of its segment, `seg`, and the isotropic state (Eo, 0) elsewhere).  Exact arithmetic
+// selects (x 1, x 0 of a finite value, x -1), so that callers can load
+// unconditionally.
 __device__ __forceinline__ bool is_ghost(const Phys& ph, int side, bool inside)
 {
     return !inside && ph.bc[side] != BC_PERIODIC;
 }
-__device__ __forceinline__ void ghost_rule(const Phys& ph, int side, bool inside, double le, double lfx, double lfy,
-                                           double& e, double& fx, double& fy)
+// Whether boundary cell number `along` (counted along side `side`) lies in the side's inflow segment.
+template <class LV>
+__device__ __forceinline__ bool in_seg(const LV& L, int side, int along)
+{
+    return along >= L.sg0[side] && along < L.sg1[side];
+}
+__device__ __forceinline__ void ghost_rule(const Phys& ph, int side, bool inside, bool seg, double le, double lfx,
+                                           double lfy, double& e, double& fx, double& fy)
 {
     const int kind = ph.bc[side];
     const bool ghost = is_ghost(ph, side, inside);
-    const bool dir = ghost && kind == BC_DIRICHLET;
+    const bool amb = ghost && kind == BC_INFLOW && !seg;
+    const bool dir = ghost && (kind == BC_DIRICHLET || (kind == BC_INFLOW && seg));
     const bool flip = ghost && kind == BC_REFLECTIVE;
-    const double keep = dir ? 0.0 : 1.0;
+    const double keep = (dir || amb) ? 0.0 : 1.0;
     const double sx = (flip && side < 2) ? -keep : keep, sy = (flip && side >= 2) ? -keep : keep;
-    e = fma(keep, le, dir ? ph.bcE[side] : 0.0);
+    e = fma(keep, le, dir ? ph.bcE[side] : (amb ? ph.bcEo[side] : 0.0));
     fx = fma(sx, lfx, dir ? ph.bcFx[side] : 0.0);
     fy = fma(sy, lfy, dir ? ph.bcFy[side] : 0.0);
 }
@@ -177,12 +188,12 @@ __device__ __forceinline__ void ghost_rule(const Phys& ph, int side, bool inside
 // wrap across a domain side), kc the cell's own.  The loads always happen, so
 // the four neighbours' loads are in flight at once.
 template <int DIM>
-__device__ __forceinline__ void nb_state(const Phys& ph, int side, bool inside, uint32_t kn, uint32_t kc,
+__device__ __forceinline__ void nb_state(const Phys& ph, int side, bool inside, bool seg, uint32_t kn, uint32_t kc,
                                          const CSoa& v, double& e, double& fx, double& fy)
 {
     const uint32_t k = is_ghost(ph, side, inside) ? kc : kn;
     const double le = ld(v.E, k), lfx = ld(v.Fx, k), lfy = (DIM == 2) ? ld(v.Fy, k) : 0.0;
-    ghost_rule(ph, side, inside, le, lfx, lfy, e, fx, fy);
+    ghost_rule(ph, side, inside, seg, le, lfx, lfy, e, fx, fy);
 }
 
 // Off-diagonal sum S = L_x(v_{i-1}) + R_x(v_{i+1}) [+ L_y(v_{j-1}) + R_y(v_{j+1})] of cell (i,j).
@@ -193,15 +204,15 @@ __device__ __forceinline__ void offdiag(const Phys& ph, const Lvl& L, const CSoa
     double e, fx, fy;
     S0 = S1 = S2 = 0.0;
     const uint32_t wx = (uint32_t)(L.nx - 1);
-    nb_state<DIM>(ph, 0, i > 0, i > 0 ? k - 1 : k + wx, k, v, e, fx, fy);
+    nb_state<DIM>(ph, 0, i > 0, in_seg(L, 0, j), i > 0 ? k - 1 : k + wx, k, v, e, fx, fy);
     add_x(L.kx, ph.c, ph.c2, +1.0, e, fx, fy, S0, S1, S2);
-    nb_state<DIM>(ph, 1, i < L.nx - 1, i < L.nx - 1 ? k + 1 : k - wx, k, v, e, fx, fy);
+    nb_state<DIM>(ph, 1, i < L.nx - 1, in_seg(L, 1, j), i < L.nx - 1 ? k + 1 : k - wx, k, v, e, fx, fy);
     add_x(L.kx, ph.c, ph.c2, -1.0, e, fx, fy, S0, S1, S2);
     if (DIM == 2) {
         const uint32_t nx = (uint32_t)L.nx, wrap = (uint32_t)(L.ny - 1) * nx;
-        nb_state<DIM>(ph, 2, j > 0, j > 0 ? k - nx : k + wrap, k, v, e, fx, fy);
+        nb_state<DIM>(ph, 2, j > 0, in_seg(L, 2, i), j > 0 ? k - nx : k + wrap, k, v, e, fx, fy);
         add_y(L.ky, ph.c, ph.c2, +1.0, e, fx, fy, S0, S1, S2);
-        nb_state<DIM>(ph, 3, j < L.ny - 1, j < L.ny - 1 ? k + nx : k - wrap, k, v, e, fx, fy);
+        nb_state<DIM>(ph, 3, j < L.ny - 1, in_seg(L, 3, i), j < L.ny - 1 ? k + nx : k - wrap, k, v, e, fx, fy);
         add_y(L.ky, ph.c, ph.c2, -1.0, e, fx, fy, S0, S1, S2);
     }
 }

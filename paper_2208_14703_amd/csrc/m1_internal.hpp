@@ -54,6 +54,10 @@ struct TailArgs {
     TailLevel lev[kMaxLevels];
 };
 
+// one colour of a red-black Gauss-Seidel sweep (cells with (i + j) % 2 == colour updated, the others copied);
+// with partials, the residual norm of u over all cells
+void launch_relax_colour(hipStream_t st, int dim, const Phys& ph, const Lvl& L, CSoa rhs, double omega, int colour,
+                         CSoa u, Soa out, double* partials, const int* active);
 void launch_relax(hipStream_t st, int dim, const Phys& ph, const Lvl& L, CSoa rhs, const double* gcell, double beta,
                   double gamma, double omega, CSoa u, Soa out, double* partials, const int* active);
 void launch_pseudo(hipStream_t st, int dim, const Phys& ph, const Lvl& L, Soa f, CSoa u, Soa out, double dtau,

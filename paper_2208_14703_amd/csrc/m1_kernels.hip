@@ -87,6 +87,45 @@ __global__ __launch_bounds__(kBlock) void k_relax(Phys ph, Lvl L, CSoa rhs, cons
     block_partial(q, partials + xcd_block());
 }
 
+// One colour of a red-black Gauss-Seidel sweep of the finest level: the cells
+// with (i + j) % 2 == colour take the relaxed Jacobi update of u (relax_values,
+// the arithmetic of every sweep), the others keep their state.  With NORM every
+// cell also adds its residual of u to the block partial (the first half of a
+// cycle's first sweep measures the previous result).
+template <int DIM, bool NORM>
+__global__ __launch_bounds__(kBlock) void k_relax_colour(Phys ph, Lvl L, CSoa rhs, double omega, int colour, CSoa u,
+                                                         Soa out, double* __restrict__ partials,
+                                                         const int* __restrict__ active)
+{
+    if (*active == 0) return;
+    uint32_t k;
+    int i, j;
+    const bool in = cell_of(L, k, i, j);
+    double q = 0.0;
+    if (in) {
+        const bool mine = ((i + j) & 1) == colour;
+        double E = ld(u.E, k), Fx = ld(u.Fx, k), Fy = (DIM == 2) ? ld(u.Fy, k) : 0.0, T = ld(u.T, k);
+        if (mine || NORM) {
+            double S0, S1, S2, nE, nFx, nFy, nT;
+            offdiag<DIM>(ph, L, u, i, j, k, S0, S1, S2);
+            const double Ein = E, Fxin = Fx, Fyin = Fy;
+            auto cen = [&](int f) { return f == 0 ? Ein : (f == 1 ? Fxin : Fyin); };
+            q = relax_values<DIM, NORM>(ph, L, rhs, 1.0, 0.0, omega, S0, S1, S2, T, cen, k, nE, nFx, nFy, nT);
+            if (mine) {
+                E = nE;
+                Fx = nFx;
+                Fy = nFy;
+                T = nT;
+            }
+        }
+        st(out.E, k, E);
+        st(out.Fx, k, Fx);
+        if (DIM == 2) st(out.Fy, k, Fy);
+        st(out.T, k, T);
+    }
+    if (NORM) block_partial(q, partials + xcd_block());
+}
+
 // ---------------------------------------------------------------------------
 // LDS-staged 2-D stencil kernels.  A block owns a 64 x TY tile.  The states of
 // the tile and of its one-cell halo (boundary rule or periodic image applied)
@@ -141,7 +180,7 @@ __device__ __forceinline__ void stage_tile(LdsTile<TY>& q, double* qT, const Phy
                 lfx = wFx;
                 lfy = wFy;
             }
-            ghost_rule(ph, side, !(ox || oy), le, lfx, lfy, e, fx, fy);
+            ghost_rule(ph, side, !(ox || oy), in_seg(L, side, side < 2 ? gj : gi), le, lfx, lfy, e, fx, fy);
             const C2P p = closure(ph.c, ph.c2, e, fx, fy);
             xx = p_xx(p, fx);
             xy = p_xy(p, fx, fy);
@@ -317,7 +356,8 @@ __device__ __forceinline__ void relax2_tile(Lds2<TY>& q, const Phys& ph, const L
             const uint32_t k = (uint32_t)sj * (uint32_t)L.nx + (uint32_t)si;
             const int side = gx ? (gi < 0 ? 0 : 1) : (gj < 0 ? 2 : 3);
             double e, fx, fy;
-            ghost_rule(ph, side, !(gx || gy), ld(u.E, k), ld(u.Fx, k), ld(u.Fy, k), e, fx, fy);
+            ghost_rule(ph, side, !(gx || gy), in_seg(L, side, side < 2 ? sj : si), ld(u.E, k), ld(u.Fx, k),
+                       ld(u.Fy, k), e, fx, fy);
             lds_put(f2, ph, p, e, fx, fy);
         } else {  // unused (corners, past a ragged edge)
             for (int a = 0; a < 6; ++a) f2[a][p] = 0.0;
@@ -377,7 +417,8 @@ __device__ __forceinline__ void relax2_tile(Lds2<TY>& q, const Phys& ph, const L
             const int side = (gi < 0 || gi >= L.nx) ? (gi < 0 ? 0 : 1) : (gj < 0 ? 2 : 3);
             const int cb = (gsy[m] - j0 + 1) * Q::W1 + gsx[m] - i0 + 1;
             double e, fx, fy;
-            ghost_rule(ph, side, false, f1[0][cb], f1[1][cb], f1[2][cb], e, fx, fy);
+            ghost_rule(ph, side, false, in_seg(L, side, side < 2 ? gsy[m] : gsx[m]), f1[0][cb], f1[1][cb], f1[2][cb],
+                       e, fx, fy);
             lds_put(f1, ph, (lj[m] + 1) * Q::W1 + li[m] + 1, e, fx, fy);
         }
     }
@@ -482,7 +523,8 @@ __device__ __forceinline__ void residual_restrict_tile(RcLds& sm, const Phys& ph
         if (nx_ && ny_ && !(hx && hy)) {
             const int side = hx ? (gi < 0 ? 0 : 1) : (hy ? (gj < 0 ? 2 : 3) : 0);
             const uint32_t k = (uint32_t)sj * (uint32_t)L.nx + (uint32_t)si;
-            ghost_rule(ph, side, !(hx || hy), ld(u.E, k), ld(u.Fx, k), ld(u.Fy, k), e, fx, fy);
+            ghost_rule(ph, side, !(hx || hy), in_seg(L, side, side < 2 ? sj : si), ld(u.E, k), ld(u.Fx, k),
+                       ld(u.Fy, k), e, fx, fy);
             const C2P p = closure(ph.c, ph.c2, e, fx, fy);
             xx = p_xx(p, fx);
             xy = p_xy(p, fx, fy);
@@ -836,16 +878,16 @@ __global__ __launch_bounds__(kTbThreads) void k_smooth_tb(Phys ph, Lvl L, CSoa f
             const int c = lj * W + li;
             double S0 = 0.0, S1 = 0.0, S2 = 0.0, e, fx, fy;
             int kn = is_ghost(ph, 0, gi > 0) ? c : c - 1;
-            ghost_rule(ph, 0, gi > 0, sE[cur][kn], sFx[cur][kn], sFy[cur][kn], e, fx, fy);
+            ghost_rule(ph, 0, gi > 0, in_seg(L, 0, gj), sE[cur][kn], sFx[cur][kn], sFy[cur][kn], e, fx, fy);
             add_x(L.kx, ph.c, ph.c2, +1.0, e, fx, fy, S0, S1, S2);
             kn = is_ghost(ph, 1, gi < L.nx - 1) ? c : c + 1;
-            ghost_rule(ph, 1, gi < L.nx - 1, sE[cur][kn], sFx[cur][kn], sFy[cur][kn], e, fx, fy);
+            ghost_rule(ph, 1, gi < L.nx - 1, in_seg(L, 1, gj), sE[cur][kn], sFx[cur][kn], sFy[cur][kn], e, fx, fy);
             add_x(L.kx, ph.c, ph.c2, -1.0, e, fx, fy, S0, S1, S2);
             kn = is_ghost(ph, 2, gj > 0) ? c : c - W;
-            ghost_rule(ph, 2, gj > 0, sE[cur][kn], sFx[cur][kn], sFy[cur][kn], e, fx, fy);
+            ghost_rule(ph, 2, gj > 0, in_seg(L, 2, gi), sE[cur][kn], sFx[cur][kn], sFy[cur][kn], e, fx, fy);
             add_y(L.ky, ph.c, ph.c2, +1.0, e, fx, fy, S0, S1, S2);
             kn = is_ghost(ph, 3, gj < L.ny - 1) ? c : c + W;
-            ghost_rule(ph, 3, gj < L.ny - 1, sE[cur][kn], sFx[cur][kn], sFy[cur][kn], e, fx, fy);
+            ghost_rule(ph, 3, gj < L.ny - 1, in_seg(L, 3, gi), sE[cur][kn], sFx[cur][kn], sFy[cur][kn], e, fx, fy);
             add_y(L.ky, ph.c, ph.c2, -1.0, e, fx, fy, S0, S1, S2);
             const double ka = L.cdt * qa[c], ks = L.cdt * qs[c];
             double f0 = qE[c], f1 = qFx[c], f2 = qFy[c], f3 = qT[c];
@@ -1281,6 +1323,22 @@ void launch_relax(hipStream_t st, int dim, const Phys& ph, const Lvl& L, CSoa rh
         else M1_RELAX(1, false, false);
     }
 #undef M1_RELAX
+}
+
+void launch_relax_colour(hipStream_t st, int dim, const Phys& ph, const Lvl& L, CSoa rhs, double omega, int colour,
+                         CSoa u, Soa out, double* partials, const int* active)
+{
+    const dim3 g(nblocks((int64_t)L.nx * L.ny)), b(kBlock);
+#define M1_RELAX_C(D, N)                                                                                              \
+    hipLaunchKernelGGL((k_relax_colour<D, N>), g, b, 0, st, ph, L, rhs, omega, colour, u, out, partials, active)
+    if (dim == 2) {
+        if (partials) M1_RELAX_C(2, true);
+        else M1_RELAX_C(2, false);
+    } else {
+        if (partials) M1_RELAX_C(1, true);
+        else M1_RELAX_C(1, false);
+    }
+#undef M1_RELAX_C
 }
 
 void launch_pseudo(hipStream_t st, int dim, const Phys& ph, const Lvl& L, Soa f, CSoa u, Soa out, double dtau,

@@ -75,20 +75,12 @@ __device__ __forceinline__ void upd64(const Phys& ph, double eta, const CSoa& v,
 }
 
 template <int DIM>
-__device__ __forceinline__ void nb_upd64(const Phys& ph, double eta, int side, bool inside, uint32_t kn, uint32_t kc,
-                                         const CSoa& v, const CSoa32& d, double& E, double& Fx, double& Fy)
+__device__ __forceinline__ void nb_upd64(const Phys& ph, double eta, int side, bool inside, bool seg, uint32_t kn,
+                                         uint32_t kc, const CSoa& v, const CSoa32& d, double& E, double& Fx, double& Fy)
 {
-    const int kind = ph.bc[side];
-    const bool ghost = !inside && kind != BC_PERIODIC;
     double lE, lFx, lFy, T;
-    upd64<DIM>(ph, eta, v, d, ghost ? kc : kn, lE, lFx, lFy, T);
-    const bool dir = ghost && kind == BC_DIRICHLET;
-    const bool flip = ghost && kind == BC_REFLECTIVE;
-    const double keep = dir ? 0.0 : 1.0;
-    const double sx = (flip && side < 2) ? -keep : keep, sy = (flip && side >= 2) ? -keep : keep;
-    E = fma(keep, lE, dir ? ph.bcE[side] : 0.0);
-    Fx = fma(sx, lFx, dir ? ph.bcFx[side] : 0.0);
-    Fy = fma(sy, lFy, dir ? ph.bcFy[side] : 0.0);
+    upd64<DIM>(ph, eta, v, d, is_ghost(ph, side, inside) ? kc : kn, lE, lFx, lFy, T);
+    ghost_rule(ph, side, inside, seg, lE, lFx, lFy, E, Fx, Fy);
 }
 
 // Relaxed Jacobi update of the correction at one cell from its values: off-diagonal sums S, current
@@ -130,15 +122,15 @@ __device__ __forceinline__ double mx_resid_cell(const Phys& ph, const Lvl& L, do
 {
     double S0 = 0.0, S1 = 0.0, S2 = 0.0, e, fx, fy;
     const uint32_t wx = (uint32_t)(L.nx - 1);
-    nb_upd64<DIM>(ph, eta, 0, i > 0, i > 0 ? k - 1 : k + wx, k, v, d, e, fx, fy);
+    nb_upd64<DIM>(ph, eta, 0, i > 0, in_seg(L, 0, j), i > 0 ? k - 1 : k + wx, k, v, d, e, fx, fy);
     add_x(L.kx, ph.c, ph.c2, +1.0, e, fx, fy, S0, S1, S2);
-    nb_upd64<DIM>(ph, eta, 1, i < L.nx - 1, i < L.nx - 1 ? k + 1 : k - wx, k, v, d, e, fx, fy);
+    nb_upd64<DIM>(ph, eta, 1, i < L.nx - 1, in_seg(L, 1, j), i < L.nx - 1 ? k + 1 : k - wx, k, v, d, e, fx, fy);
     add_x(L.kx, ph.c, ph.c2, -1.0, e, fx, fy, S0, S1, S2);
     if (DIM == 2) {
         const uint32_t nx = (uint32_t)L.nx, wrap = (uint32_t)(L.ny - 1) * nx;
-        nb_upd64<DIM>(ph, eta, 2, j > 0, j > 0 ? k - nx : k + wrap, k, v, d, e, fx, fy);
+        nb_upd64<DIM>(ph, eta, 2, j > 0, in_seg(L, 2, i), j > 0 ? k - nx : k + wrap, k, v, d, e, fx, fy);
         add_y(L.ky, ph.c, ph.c2, +1.0, e, fx, fy, S0, S1, S2);
-        nb_upd64<DIM>(ph, eta, 3, j < L.ny - 1, j < L.ny - 1 ? k + nx : k - wrap, k, v, d, e, fx, fy);
+        nb_upd64<DIM>(ph, eta, 3, j < L.ny - 1, in_seg(L, 3, i), j < L.ny - 1 ? k + nx : k - wrap, k, v, d, e, fx, fy);
         add_y(L.ky, ph.c, ph.c2, -1.0, e, fx, fy, S0, S1, S2);
     }
     double E, Fx, Fy, T;
@@ -288,8 +280,8 @@ __device__ __forceinline__ float mx_stage_tile_at(MxTile<TY>& q, const Phys& ph,
             const uint32_t k = (uint32_t)gj * (uint32_t)L.nx + (uint32_t)gi;
             float E, Fx, Fy, dE, dFx, dFy;
             d_at(k, dE, dFx, dFy, dT);
-            ghost_inc(ph, side, !(ox || oy), ldf(w.E, k), ldf(w.Fx, k), ldf(w.Fy, k), dE, dFx, dFy, E, Fx, Fy, e, gx,
-                      gy);
+            ghost_inc(ph, side, !(ox || oy), in_seg(L, side, side < 2 ? gj : gi), ldf(w.E, k), ldf(w.Fx, k),
+                      ldf(w.Fy, k), dE, dFx, dFy, E, Fx, Fy, e, gx, gy);
             p = closure_inc(c, c2, E, Fx, Fy, e, gx, gy);
         }
         const int n = (lj + 1) * W + li + 1;
@@ -445,8 +437,8 @@ __device__ __forceinline__ void mx_sweep2_tile(MxLds2<TY>& q, const Phys& ph, co
         if (plus(gi, gj, 2, 1) && nx_ && ny_ && !(gx_ && gy_)) {
             const uint32_t k = (uint32_t)sj * (uint32_t)L.nx + (uint32_t)si;
             const int side = gx_ ? (gi < 0 ? 0 : 1) : (gj < 0 ? 2 : 3);
-            ghost_inc(ph, side, !(gx_ || gy_), ldf(w.E, k), ldf(w.Fx, k), ldf(w.Fy, k), ldf(d.E, k), ldf(d.Fx, k),
-                      ldf(d.Fy, k), E, Fx, Fy, e, gx, gy);
+            ghost_inc(ph, side, !(gx_ || gy_), in_seg(L, side, side < 2 ? sj : si), ldf(w.E, k), ldf(w.Fx, k),
+                      ldf(w.Fy, k), ldf(d.E, k), ldf(d.Fx, k), ldf(d.Fy, k), E, Fx, Fy, e, gx, gy);
             pp = closure_inc(c, c2, E, Fx, Fy, e, gx, gy);
         }
         mx_lds_put(f2, p, e, gx, gy, pp);
@@ -506,8 +498,8 @@ __device__ __forceinline__ void mx_sweep2_tile(MxLds2<TY>& q, const Phys& ph, co
             const int cb = (gsy[m] - j0 + 1) * Q::W1 + gsx[m] - i0 + 1;
             const uint32_t kb = (uint32_t)gsy[m] * (uint32_t)L.nx + (uint32_t)gsx[m];
             float E, Fx, Fy, e, gx, gy;
-            ghost_inc(ph, side, false, ldf(w.E, kb), ldf(w.Fx, kb), ldf(w.Fy, kb), f1[0][cb], f1[1][cb], f1[2][cb], E,
-                      Fx, Fy, e, gx, gy);
+            ghost_inc(ph, side, false, in_seg(L, side, side < 2 ? gsy[m] : gsx[m]), ldf(w.E, kb), ldf(w.Fx, kb),
+                      ldf(w.Fy, kb), f1[0][cb], f1[1][cb], f1[2][cb], E, Fx, Fy, e, gx, gy);
             mx_lds_put(f1, (lj[m] + 1) * Q::W1 + li[m] + 1, e, gx, gy, closure_inc(c, c2, E, Fx, Fy, e, gx, gy));
         }
     }
@@ -1166,8 +1158,8 @@ __device__ __forceinline__ void mx_residual_restrict_tile(MrLds& sm, const Phys&
         if (nx_ && ny_ && !(hx && hy)) {
             const int side = hx ? (gi < 0 ? 0 : 1) : (hy ? (gj < 0 ? 2 : 3) : 0);
             const uint32_t k = (uint32_t)sj * (uint32_t)L.nx + (uint32_t)si;
-            ghost_inc(ph, side, !(hx || hy), ldf(w.E, k), ldf(w.Fx, k), ldf(w.Fy, k), ldf(d.E, k), ldf(d.Fx, k),
-                      ldf(d.Fy, k), E, Fx, Fy, e, gx, gy);
+            ghost_inc(ph, side, !(hx || hy), in_seg(L, side, side < 2 ? sj : si), ldf(w.E, k), ldf(w.Fx, k),
+                      ldf(w.Fy, k), ldf(d.E, k), ldf(d.Fx, k), ldf(d.Fy, k), E, Fx, Fy, e, gx, gy);
             T = ldf(w.T, k);
             t = ldf(d.T, k);
             p = closure_inc(c, c2, E, Fx, Fy, e, gx, gy);

@@ -46,6 +46,7 @@ struct Lvl32 {
     float kx, ky, a, cdt;
     const float* sa;
     const float* ss;
+    int sg0[4], sg1[4];  // inflow segments, as in Lvl
 };
 
 // Increment of the closure, c^2 dP = c^2 (P(U + dU) - P(U)), for a base
@@ -108,17 +109,18 @@ __device__ __forceinline__ void acc_inc(float kk, float sgn, bool xdir, float c,
 
 // The boundary rule of side `side` in increment form, applied to loaded values
 // (identity inside the domain and across periodic sides).
-__device__ __forceinline__ void ghost_inc(const Phys& ph, int side, bool inside, float lE, float lFx, float lFy,
-                                          float le, float lgx, float lgy, float& E, float& Fx, float& Fy, float& e,
-                                          float& gx, float& gy)
+__device__ __forceinline__ void ghost_inc(const Phys& ph, int side, bool inside, bool seg, float lE, float lFx,
+                                          float lFy, float le, float lgx, float lgy, float& E, float& Fx, float& Fy,
+                                          float& e, float& gx, float& gy)
 {
     const int kind = ph.bc[side];
     const bool ghost = !inside && kind != BC_PERIODIC;
-    const bool dir = ghost && kind == BC_DIRICHLET;
+    const bool amb = ghost && kind == BC_INFLOW && !seg;
+    const bool dir = ghost && (kind == BC_DIRICHLET || (kind == BC_INFLOW && seg));
     const bool flip = ghost && kind == BC_REFLECTIVE;
-    const float keep = dir ? 0.0f : 1.0f;
+    const float keep = (dir || amb) ? 0.0f : 1.0f;
     const float sx = (flip && side < 2) ? -keep : keep, sy = (flip && side >= 2) ? -keep : keep;
-    E = fmaf(keep, lE, dir ? (float)ph.bcE[side] : 0.0f);
+    E = fmaf(keep, lE, dir ? (float)ph.bcE[side] : (amb ? (float)ph.bcEo[side] : 0.0f));
     Fx = fmaf(sx, lFx, dir ? (float)ph.bcFx[side] : 0.0f);
     Fy = fmaf(sy, lFy, dir ? (float)ph.bcFy[side] : 0.0f);
     e = keep * le;
@@ -130,7 +132,7 @@ __device__ __forceinline__ void ghost_inc(const Phys& ph, int side, bool inside,
 // rule of the side; the correction ghost is its linear part (0 for Dirichlet).
 // Branch-free like nb_state: unconditional loads, exact arithmetic selects.
 template <int DIM>
-__device__ __forceinline__ void nb_inc(const Phys& ph, int side, bool inside, uint32_t kn, uint32_t kc,
+__device__ __forceinline__ void nb_inc(const Phys& ph, int side, bool inside, bool seg, uint32_t kn, uint32_t kc,
                                        const CSoa32& w, const CSoa32& d, float& E, float& Fx, float& Fy, float& e,
                                        float& gx, float& gy)
 {
@@ -138,7 +140,7 @@ __device__ __forceinline__ void nb_inc(const Phys& ph, int side, bool inside, ui
     const uint32_t k = ghost ? kc : kn;
     const float lE = ldf(w.E, k), lFx = ldf(w.Fx, k), lFy = (DIM == 2) ? ldf(w.Fy, k) : 0.0f;
     const float le = ldf(d.E, k), lgx = ldf(d.Fx, k), lgy = (DIM == 2) ? ldf(d.Fy, k) : 0.0f;
-    ghost_inc(ph, side, inside, lE, lFx, lFy, le, lgx, lgy, E, Fx, Fy, e, gx, gy);
+    ghost_inc(ph, side, inside, seg, lE, lFx, lFy, le, lgx, lgy, E, Fx, Fy, e, gx, gy);
 }
 
 
@@ -154,15 +156,15 @@ __device__ __forceinline__ void offdiag_inc(const Phys& ph, const Lvl32& L, cons
         acc_inc(kk, sgn, xdir, c, e, gx, gy, closure_inc(c, c2, E, Fx, Fy, e, gx, gy), S0, S1, S2);
     };
     const uint32_t wx = (uint32_t)(L.nx - 1);
-    nb_inc<DIM>(ph, 0, i > 0, i > 0 ? k - 1 : k + wx, k, w, d, E, Fx, Fy, e, gx, gy);
+    nb_inc<DIM>(ph, 0, i > 0, in_seg(L, 0, j), i > 0 ? k - 1 : k + wx, k, w, d, E, Fx, Fy, e, gx, gy);
     add(L.kx, +1.0f, true);
-    nb_inc<DIM>(ph, 1, i < L.nx - 1, i < L.nx - 1 ? k + 1 : k - wx, k, w, d, E, Fx, Fy, e, gx, gy);
+    nb_inc<DIM>(ph, 1, i < L.nx - 1, in_seg(L, 1, j), i < L.nx - 1 ? k + 1 : k - wx, k, w, d, E, Fx, Fy, e, gx, gy);
     add(L.kx, -1.0f, true);
     if (DIM == 2) {
         const uint32_t nx = (uint32_t)L.nx, wrap = (uint32_t)(L.ny - 1) * nx;
-        nb_inc<DIM>(ph, 2, j > 0, j > 0 ? k - nx : k + wrap, k, w, d, E, Fx, Fy, e, gx, gy);
+        nb_inc<DIM>(ph, 2, j > 0, in_seg(L, 2, i), j > 0 ? k - nx : k + wrap, k, w, d, E, Fx, Fy, e, gx, gy);
         add(L.ky, +1.0f, false);
-        nb_inc<DIM>(ph, 3, j < L.ny - 1, j < L.ny - 1 ? k + nx : k - wrap, k, w, d, E, Fx, Fy, e, gx, gy);
+        nb_inc<DIM>(ph, 3, j < L.ny - 1, in_seg(L, 3, i), j < L.ny - 1 ? k + nx : k - wrap, k, w, d, E, Fx, Fy, e, gx, gy);
         add(L.ky, -1.0f, false);
     }
 }

@@ -128,6 +128,50 @@ def lognormal_2d(n: int = 4096, seed: int = 2, cfl: float = 100.0, block: int = 
     return prob, v, sig, dict(steps=1, rtol=1e-8)
 
 
+def beam_2d(n: int = 128, cfl: float = 2000.0, t0: float = 0.3, t_beam: float = 1.0):
+    """The beam of Sect. 5.1: free streaming (no opacity) on [-1, 1]^2 with n x n cells.
+
+    Temperatures are in units of 1000 K with a_r = c = 1: the ambient radiation
+    has T_r = 0.3 (300 K), E = a_r T_r^4, F = 0; a beam of T_r = 1 (1000 K) with
+    reduced flux f = 1 at 45 degrees enters through x = -1, y in [-0.875, -0.75]
+    (the fractions [0.0625, 0.125] of that side); the rest of that side holds the
+    ambient radiation (its ghost is (E_0, 0)), and the other sides copy the
+    adjacent cell (outflow).  The gas, with no
+    opacity, is decoupled (T = 1).  dt = cfl h / c: one implicit step of
+    cfl 2000 reaches the steady state.
+    """
+    e_beam = t_beam ** 4
+    f = e_beam / np.sqrt(2.0)  # |F| = c E at 45 degrees (c = 1)
+    bc = [dict(kind="inflow", E=e_beam, Fx=f, Fy=f, lo=0.0625, hi=0.125, Eo=t0 ** 4)] + [dict(kind="neumann")] * 3
+    prob = grid_problem(2, n, n, cfl, bc, length=2.0)
+    v = np.zeros((4, n, n))
+    v[0] = t0 ** 4
+    v[3] = 1.0
+    return prob, v, np.zeros((2, n, n)), dict(steps=1, rtol=1e-8)
+
+
+def riemann_2d(n: int = 256, cfl: float = 2000.0, t0: float = 1.0):
+    """The periodic 2-D Riemann problem of Sect. 5.2 on [0, 1]^2 with n x n cells.
+
+    T_r = t0 (1000 K in units of 1000 K) everywhere, so E = a_r t0^4, and
+    F = (1 - 1e-8) c E F_hat with F_hat = (1, 0) in the lower-left quadrant,
+    (0, -1) lower-right, (0, 1) upper-left and (-1, 0) upper-right; no opacity,
+    periodic sides, dt = cfl h / c.
+    """
+    prob = grid_problem(2, n, n, cfl, bc_all("periodic"))
+    E = t0 ** 4
+    a = (1.0 - 1e-8) * prob["c"] * E
+    h = n // 2
+    v = np.zeros((4, n, n))
+    v[0] = E
+    v[3] = 1.0
+    v[1, :h, :h] = a    # lower-left: +x
+    v[2, :h, h:] = -a   # lower-right: -y
+    v[2, h:, :h] = a    # upper-left: +y
+    v[1, h:, h:] = -a   # upper-right: -x
+    return prob, v, np.zeros((2, n, n)), dict(steps=1, rtol=5e-3)
+
+
 def batch_problem(k: int, sides=(64, 128, 256, 512), cfl: float = 100.0, block: int = 32):
     """Problem k of the batched workload, seeded with 1000 + k.
 
