@@ -4,7 +4,10 @@ Default line (the headline workload): the 2-D hot-wall problem.
 - Grid: 1024 x 1024 cells on [0,1]^2, dt = 100 h/c.
 - Opacity: piecewise constant on 32x32 blocks, log10 sigma_a ~ U[-2,2], sigma_s ~ U[0,1].
 - Boundaries: a hot Dirichlet wall at x = 0, reflective elsewhere.
-- Solver: plain FP64, 10 implicit Euler steps, each run to relative residual 1e-8.
+- Solver: plain FP64, 10 implicit Euler steps, each run to relative residual 1e-8, with the
+  paper's smoothing counts (3 finest sweeps before and after, 3 coarse pseudo-time steps) and
+  L_max = 6 levels (coarsest 32^2), the fastest depth of a measured L_max sweep (the solution
+  does not depend on it; config.levels reports it).
 
 One benchmark "step" solves the whole workload (all 10 implicit steps) from the same
 initial state, already resident in HBM. The timed region covers exactly --steps such
@@ -67,6 +70,11 @@ SWEEP_BYTES_PER_CELL = 112  # v (E,Fx,Fy,T) 32 + b 32 + sigma 16 read, v' 32 wri
 RESID_BYTES_PER_CELL = 96   # u 32 + b 32 + sigma 16 read per fine cell; R(u) and R(r) (2 x 32 B) per 4 fine cells
 KERNEL_N = 4096             # side of the HBM-resident grid of the kernel measurements
 SOLVER = dict(omega=0.8, levels=0)
+# Levels (L_max, the paper's own tuning knob: its timing table is a sweep of it) of the two single-problem
+# workloads: the fastest depth of a measured sweep. Solutions do not depend on it; cycle counts do.
+# Hot wall 1024^2: 6 levels (coarsest 32^2) 181 ms per solve, against 191 (7), 201 (8), 209 (9, to side 4) and
+# 700 (5, 2661 cycles). Lognormal 4096^2: 7 levels (coarsest 64^2).
+WORKLOAD_LEVELS = {"hotwall": 6, "lognormal": 7}
 def sweeps_per_launch():
     """Sweeps per launch of the finest-level sweep kernel the cycle runs (2 with the fused pair on)."""
     return 2 if binding.tune_get("pair_rows") > 0 else 1
@@ -100,6 +108,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="hotwall", choices=["hotwall", "lognormal", "batch", "serve"])
     ap.add_argument("--n", type=int, default=0, help="grid side (default: the workload's own)")
+    ap.add_argument("--levels", type=int, default=-1,
+                    help="L_max of the hot-wall/lognormal solve (default: the workload's measured fastest; 0: to side 4)")
     ap.add_argument("--precision", default=None, choices=["fp64", "mixed"],
                     help="default: fp64 for hotwall, mixed for lognormal")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -230,10 +240,10 @@ def copy_timing(torch, reps=10):
     return {"bytes": 16 * COPY_ELEMS, "avg_launch_us": round(t * 1e6, 2), "GB_per_s": round(16 * COPY_ELEMS / t / 1e9, 1)}
 
 
-def cpu_baseline(prob, v, sig, run, gpu_cycles_per_step, ncycles, c1=None):
+def cpu_baseline(prob, v, sig, run, gpu_cycles_per_step, ncycles, levels, c1=None):
     import oracle
     o = oracle.Oracle(prob, sig)
-    p = oracle.make_params(rtol=run["rtol"], max_cycles=ncycles, **SOLVER)
+    p = oracle.make_params(rtol=run["rtol"], max_cycles=ncycles, **dict(SOLVER, levels=levels))
     t0 = time.perf_counter()
     _, info = o.step(v, 1, p)
     dt = time.perf_counter() - t0
@@ -321,11 +331,13 @@ def c3_leg(torch):
                        "rtol 1e-8"}
     res = {}
     for prec, reps in (("mixed", 3), ("fp64", 1)):
-        plan = binding.Plan(prob, sd, dict(rtol=run["rtol"], max_cycles=20000, precision=prec, **SOLVER))
+        plan = binding.Plan(prob, sd, dict(rtol=run["rtol"], max_cycles=20000, precision=prec,
+                                           **dict(SOLVER, levels=WORKLOAD_LEVELS["lognormal"])))
         t, info, v = timed_solves(torch, plan, vd, run["steps"], reps)
         res[prec] = v
         out[prec] = {"Mcell_updates_per_s": round(cells * run["steps"] / t / 1e6, 2), "time_to_rtol_ms": round(t * 1e3, 2),
-                     "cycles": info["cycles"], "status": info["status"], "rel_residual": info["rel_residual"]}
+                     "cycles": info["cycles"], "levels": info["levels"], "status": info["status"],
+                     "rel_residual": info["rel_residual"]}
         del plan
     out["mixed_speedup_vs_fp64"] = round(out["fp64"]["time_to_rtol_ms"] / out["mixed"]["time_to_rtol_ms"], 3)
     out["max_rel_diff_mixed_vs_fp64"] = state_rel(res["mixed"], res["fp64"], prob["c"])
@@ -511,7 +523,9 @@ def main():
     cells = prob["nx"] * prob["ny"]
     dev_sig = binding.to_device(sig)
     v_init = binding.to_device(v0)
-    plan = binding.Plan(prob, dev_sig, dict(rtol=run["rtol"], max_cycles=20000, precision=precision, **SOLVER))
+    levels = WORKLOAD_LEVELS[args.workload] if args.levels < 0 else args.levels
+    plan = binding.Plan(prob, dev_sig, dict(rtol=run["rtol"], max_cycles=20000, precision=precision,
+                                            **dict(SOLVER, levels=levels)))
     v = torch.empty_like(v_init)
     b = v_init.clone()
     b[3] *= prob["c_v"]
@@ -568,7 +582,7 @@ def main():
         c1 = c1_leg(torch)
         out["c3"] = c3_leg(torch)
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(prob, v0, sig, run, cycles / run["steps"], args.cpu_cycles, c1)
+        out["cpu_baseline"] = cpu_baseline(prob, v0, sig, run, cycles / run["steps"], args.cpu_cycles, levels, c1)
     if c1 is not None:
         c1.pop("result", None)
         out["c1"] = c1
