@@ -24,6 +24,7 @@ _LIB = os.path.join(_HERE, "libm1oracle.so")
 BC = {"periodic": 0, "reflective": 1, "neumann": 2, "dirichlet": 3, "inflow": 4}
 DTAU_RULE = {"signed": 0, "literal": 1}
 SMOOTHER = {"jacobi": 0, "rbgs": 1}
+CYCLE = {"V": 0, "W": 1, "F": 2}
 
 
 class Grid(ctypes.Structure):
@@ -42,7 +43,7 @@ class Params(ctypes.Structure):
         ("levels", ctypes.c_int32), ("nu0", ctypes.c_int32), ("nu_l", ctypes.c_int32),
         ("pseudo_steps", ctypes.c_int32), ("sub_steps", ctypes.c_int32), ("max_cycles", ctypes.c_int32),
         ("dtau_rule", ctypes.c_int32), ("pseudo_local", ctypes.c_int32),
-        ("smoother", ctypes.c_int32), ("pad_", ctypes.c_int32),
+        ("smoother", ctypes.c_int32), ("cycle", ctypes.c_int32),
         ("dtau_im0", ctypes.c_double), ("eps_inc", ctypes.c_double), ("eps_dec", ctypes.c_double),
         ("eta", ctypes.c_double), ("rtol", ctypes.c_double), ("dtau_min", ctypes.c_double),
         ("dtau_max", ctypes.c_double), ("omega", ctypes.c_double),
@@ -101,6 +102,7 @@ def lib():
         L.or_num_levels.restype = ctypes.c_int32
         L.or_num_levels.argtypes = [gp, pp]
         L.or_vcycle.argtypes = [gp, dp, pp, ctypes.c_double, dp, dp, dp]
+        L.or_cycle.argtypes = [gp, dp, pp, ctypes.c_int32, ctypes.c_double, dp, dp, dp]
         L.or_step.restype = ctypes.c_int32
         L.or_step.argtypes = [gp, dp, pp, dp, ctypes.c_int32, ctypes.POINTER(Info), dp, ctypes.c_int32]
         L.or_threads.restype = ctypes.c_int32
@@ -138,12 +140,13 @@ def make_params(**kw) -> Params:
     (omega=1), with the local pseudo-time step reading (pseudo_local=1).
     """
     d = dict(levels=0, nu0=3, nu_l=1, pseudo_steps=3, sub_steps=4, max_cycles=10000, dtau_rule="signed",
-             pseudo_local=1, smoother="jacobi", dtau_im0=1e-3, eps_inc=0.05, eps_dec=0.0, eta=0.9, rtol=1e-10,
+             pseudo_local=1, smoother="jacobi", cycle="V", dtau_im0=1e-3, eps_inc=0.05, eps_dec=0.0, eta=0.9, rtol=1e-10,
              dtau_min=1e-6, dtau_max=1e6, omega=1.0)
     d.update(kw)
     p = Params()
     for k, v in d.items():
-        setattr(p, k, DTAU_RULE[v] if k == "dtau_rule" else SMOOTHER[v] if k == "smoother" else v)
+        setattr(p, k, DTAU_RULE[v] if k == "dtau_rule" else SMOOTHER[v] if k == "smoother" else
+                CYCLE[v] if k == "cycle" else v)
     return p
 
 
@@ -279,6 +282,14 @@ class Oracle:
         out = self._new()
         self.L.or_vcycle(ctypes.byref(self.g), _p(self.sigma), ctypes.byref(p), dtau, _p(self._c(b)),
                          _p(self._c(v)), _p(out))
+        return out
+
+    def cycle(self, b, v, dtau, kind, params=None):
+        """One cycle of the recursive form (kind "V", "W" or "F")."""
+        p = params or make_params()
+        out = self._new()
+        self.L.or_cycle(ctypes.byref(self.g), _p(self.sigma), ctypes.byref(p), CYCLE[kind], dtau, _p(self._c(b)),
+                        _p(self._c(v)), _p(out))
         return out
 
     def step(self, v, nsteps=1, params=None, history_len=100000):

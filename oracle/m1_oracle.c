@@ -674,8 +674,8 @@ static void pseudo_smooth(const or_grid* g, const double* sigma, const or_params
  *            steps from v_l, rbar_l = f_l - A_l(u_l);
  *   upward:  u_l <- projected(u_l + P(u_{l+1} - v_{l+1})), then the same
  *            smoothing again (nu0 sweeps on the finest level).              */
-void or_vcycle(const or_grid* g, const double* sigma, const or_params* p, double dtau, const double* b,
-               const double* v, double* out)
+static void vcycle_loop(const or_grid* g, const double* sigma, const or_params* p, double dtau, const double* b,
+                        const double* v, double* out)
 {
     const int L = or_num_levels(g, p);
     or_grid* G = (or_grid*)malloc(sizeof(or_grid) * L);
@@ -747,6 +747,128 @@ void or_vcycle(const or_grid* g, const double* sigma, const or_params* p, double
     free(Fr);
     free(S);
     free(G);
+}
+
+/* The cycle of Sect. 4 written recursively over the coarse problems, for the
+ * other cycle shapes Sect. 6.3 names.  coarse_visit(l) takes the FAS problem
+ * A_l(u) = f_l of level l from u: m pseudo-time steps (Algorithm 3); above the
+ * coarsest level, the residual and the iterate restricted to level l+1, its
+ * problem visited once (V), twice (W), or by an F-cycle then a V-cycle (F),
+ * the correction with admissibility (eq. prolongatedSol) and m pseudo-time
+ * steps again.  The finest level is the same with nu0 Jacobi sweeps in place
+ * of the pseudo-time steps.  With kind V this is or_vcycle's cycle.          */
+typedef struct {
+    int L;
+    or_grid* G;
+    double **S, **U, **V, **F;
+} cyc_levels;
+
+static void coarse_visit(const cyc_levels* c, const or_params* p, double dtau, int l, int kind);
+
+/* restrict u_l and its residual rhs_l - A_l(u_l) to level l+1: v_{l+1}, f_{l+1} = A(v_{l+1}) + R(residual) */
+static void descend(const cyc_levels* c, int l, const double* rhs)
+{
+    const size_t n = ncell(&c->G[l]), nc = ncell(&c->G[l + 1]);
+    double* rb = dalloc(NFIELD * n);
+    double* rr = dalloc(NFIELD * nc);
+    or_apply_A(&c->G[l], c->S[l], c->U[l], rb);
+    for (size_t k = 0; k < NFIELD * n; ++k) rb[k] = rhs[k] - rb[k];
+    or_restrict(&c->G[l], c->U[l], NFIELD, c->V[l + 1]);
+    or_restrict(&c->G[l], rb, NFIELD, rr);
+    or_apply_A(&c->G[l + 1], c->S[l + 1], c->V[l + 1], c->F[l + 1]);
+    for (size_t k = 0; k < NFIELD * nc; ++k) c->F[l + 1][k] += rr[k];
+    memcpy(c->U[l + 1], c->V[l + 1], NFIELD * nc * sizeof(double));
+    free(rb);
+    free(rr);
+}
+
+/* visit level l+1 as `kind` prescribes, then correct u_l */
+static void visit_and_correct(const cyc_levels* c, const or_params* p, double dtau, int l, int kind)
+{
+    if (kind == OR_CYCLE_F) {
+        coarse_visit(c, p, dtau, l + 1, OR_CYCLE_F);
+        coarse_visit(c, p, dtau, l + 1, OR_CYCLE_V);
+    } else {
+        const int times = (kind == OR_CYCLE_W) ? 2 : 1;
+        for (int t = 0; t < times; ++t) coarse_visit(c, p, dtau, l + 1, kind);
+    }
+    const size_t n = ncell(&c->G[l]), nc = ncell(&c->G[l + 1]);
+    double* e = dalloc(NFIELD * nc);
+    double* w = dalloc(NFIELD * n);
+    for (size_t k = 0; k < NFIELD * nc; ++k) e[k] = c->U[l + 1][k] - c->V[l + 1][k];
+    or_prolong(&c->G[l], e, NFIELD, w);
+    for (size_t k = 0; k < NFIELD * n; ++k) w[k] += c->U[l][k];
+    or_project(&c->G[l], p, c->U[l], w, c->U[l]);
+    free(e);
+    free(w);
+}
+
+static void coarse_visit(const cyc_levels* c, const or_params* p, double dtau, int l, int kind)
+{
+    const size_t n = ncell(&c->G[l]);
+    double* t = dalloc(NFIELD * n);
+    pseudo_smooth(&c->G[l], c->S[l], p, dtau, c->F[l], c->U[l], t);
+    memcpy(c->U[l], t, NFIELD * n * sizeof(double));
+    if (l < c->L - 1) {
+        descend(c, l, c->F[l]);
+        visit_and_correct(c, p, dtau, l, kind);
+        pseudo_smooth(&c->G[l], c->S[l], p, dtau, c->F[l], c->U[l], t);
+        memcpy(c->U[l], t, NFIELD * n * sizeof(double));
+    }
+    free(t);
+}
+
+void or_cycle(const or_grid* g, const double* sigma, const or_params* p, int32_t kind, double dtau, const double* b,
+              const double* v, double* out)
+{
+    cyc_levels c;
+    c.L = or_num_levels(g, p);
+    c.G = (or_grid*)malloc(sizeof(or_grid) * c.L);
+    c.S = (double**)calloc(c.L, sizeof(double*));
+    c.U = (double**)calloc(c.L, sizeof(double*));
+    c.V = (double**)calloc(c.L, sizeof(double*));
+    c.F = (double**)calloc(c.L, sizeof(double*));
+    c.G[0] = *g;
+    c.S[0] = (double*)sigma;
+    for (int l = 1; l < c.L; ++l) {
+        c.G[l] = or_coarse_grid(&c.G[l - 1]);
+        c.S[l] = dalloc(2 * ncell(&c.G[l]));
+        or_restrict(&c.G[l - 1], c.S[l - 1], 2, c.S[l]); /* coarse opacity by full weighting */
+    }
+    for (int l = 0; l < c.L; ++l) {
+        c.U[l] = dalloc(NFIELD * ncell(&c.G[l]));
+        c.V[l] = dalloc(NFIELD * ncell(&c.G[l]));
+        c.F[l] = dalloc(NFIELD * ncell(&c.G[l]));
+    }
+    sweeps(&c.G[0], c.S[0], p->omega, p->smoother, b, v, p->nu0, c.U[0]);
+    if (c.L > 1) {
+        double* t = dalloc(NFIELD * ncell(g));
+        descend(&c, 0, b);
+        visit_and_correct(&c, p, dtau, 0, kind);
+        sweeps(&c.G[0], c.S[0], p->omega, p->smoother, b, c.U[0], p->nu0, t);
+        memcpy(c.U[0], t, NFIELD * ncell(g) * sizeof(double));
+        free(t);
+    }
+    memcpy(out, c.U[0], NFIELD * ncell(g) * sizeof(double));
+    for (int l = 0; l < c.L; ++l) {
+        free(c.U[l]);
+        free(c.V[l]);
+        free(c.F[l]);
+        if (l > 0) free(c.S[l]);
+    }
+    free(c.G);
+    free(c.S);
+    free(c.U);
+    free(c.V);
+    free(c.F);
+}
+
+/* One cycle of the shape p->cycle (V: the loop form above). */
+void or_vcycle(const or_grid* g, const double* sigma, const or_params* p, double dtau, const double* b,
+               const double* v, double* out)
+{
+    if (p->cycle == OR_CYCLE_V) vcycle_loop(g, sigma, p, dtau, b, v, out);
+    else or_cycle(g, sigma, p, p->cycle, dtau, b, v, out);
 }
 
 /* Pseudo-time step adaptation after each cycle (Appendix A): grow by 1.1 when

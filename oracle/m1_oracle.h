@@ -26,6 +26,7 @@ extern "C" {
 enum { OR_BC_PERIODIC = 0, OR_BC_REFLECTIVE = 1, OR_BC_NEUMANN = 2, OR_BC_DIRICHLET = 3, OR_BC_INFLOW = 4 };
 enum { OR_DTAU_SIGNED = 0, OR_DTAU_LITERAL = 1 };
 enum { OR_SMOOTH_JACOBI = 0, OR_SMOOTH_RBGS = 1 };
+enum { OR_CYCLE_V = 0, OR_CYCLE_W = 1, OR_CYCLE_F = 2 };
 
 typedef struct {
     int32_t dim, nx, ny, pad_;
@@ -46,7 +47,7 @@ typedef struct {
     int32_t dtau_rule;     /* OR_DTAU_SIGNED or OR_DTAU_LITERAL */
     int32_t pseudo_local;  /* 1: implicit pseudo-time step uses each cell's own tau_i; 0: dtau_im everywhere */
     int32_t smoother;      /* finest-level sweeps: OR_SMOOTH_JACOBI or OR_SMOOTH_RBGS (red-black Gauss-Seidel) */
-    int32_t pad_;
+    int32_t cycle;         /* OR_CYCLE_V, OR_CYCLE_W or OR_CYCLE_F */
     double dtau_im0, eps_inc, eps_dec, eta, rtol, dtau_min, dtau_max;
     double omega;          /* relaxation weight of the finest-level Jacobi sweeps (1 = Algorithm 1) */
 } or_params;
@@ -87,6 +88,8 @@ or_grid or_coarse_grid(const or_grid* g);
 int32_t or_num_levels(const or_grid* g, const or_params* p);
 void   or_vcycle(const or_grid* g, const double* sigma, const or_params* p, double dtau,
                  const double* b, const double* v, double* out);
+void   or_cycle(const or_grid* g, const double* sigma, const or_params* p, int32_t kind, double dtau,
+                const double* b, const double* v, double* out);
 int32_t or_step(const or_grid* g, const double* sigma, const or_params* p, double* v, int32_t nsteps,
                 or_info* info, double* history, int32_t history_len);
 int32_t or_threads(void);
