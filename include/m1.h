@@ -59,6 +59,7 @@ typedef enum {
 typedef enum { M1_FP64 = 0, M1_MIXED = 1 } m1_precision;
 typedef enum { M1_DTAU_SIGNED = 0, M1_DTAU_LITERAL = 1 } m1_dtau_rule;
 typedef enum { M1_SMOOTH_JACOBI = 0, M1_SMOOTH_RBGS = 1 } m1_smoother;
+typedef enum { M1_CYCLE_V = 0, M1_CYCLE_W = 1, M1_CYCLE_F = 2 } m1_cycle;
 
 /* Boundary condition of one side.  Ghost state of the neighbour outside the
  * domain: PERIODIC wraps; REFLECTIVE mirrors the adjacent cell with its normal
@@ -110,6 +111,14 @@ typedef struct {
  *                 alternative of Sect. 6.3): the cells with i + j even take
  *                 the relaxed Jacobi update, then the others the update of
  *                 that state (FP64 plans only; not in engines);
+ *   cycle         shape of the multigrid cycle: M1_CYCLE_V (Appendix A's
+ *                 V-cycle), M1_CYCLE_W (each coarse problem below the finest
+ *                 visited twice per visit of the level above) or M1_CYCLE_F
+ *                 (an F-cycle of the coarse problem, then a V-cycle of it);
+ *                 the alternatives of Sect. 6.3.  Every visit of a coarse
+ *                 level runs the pseudo-time smoothing of Algorithm 3 before
+ *                 and after its correction (the coarsest: once per visit).
+ *                 W and F: FP64 plans only, not in engines;
  *   precision     M1_FP64 or M1_MIXED (FP32 delta-form smoothing and coarse
  *                 levels, FP64 residual, projection and T^4 update; M1_MIXED
  *                 requires nu_l = 1: its coarse steps fuse one sweep);
@@ -122,6 +131,7 @@ typedef struct {
  *                 1 is Algorithm 1, 0 < omega <= 1 keeps admissibility.      */
 typedef struct {
     int32_t levels, nu0, nu_l, pseudo_steps, sub_steps, max_cycles, dtau_rule, pseudo_local, precision, smoother;
+    int32_t cycle, pad_;
     double dtau_im0, eps_inc, eps_dec, eta, rtol, dtau_min, dtau_max, omega;
 } m1_params;
 

@@ -118,6 +118,8 @@ bool valid_params(const m1_params* p)
     if (p->precision == M1_MIXED && p->nu_l != 1) return false;  // coarse correction steps fuse one sweep
     if (p->smoother != M1_SMOOTH_JACOBI && p->smoother != M1_SMOOTH_RBGS) return false;
     if (p->smoother == M1_SMOOTH_RBGS && p->precision != M1_FP64) return false;
+    if (p->cycle != M1_CYCLE_V && p->cycle != M1_CYCLE_W && p->cycle != M1_CYCLE_F) return false;
+    if (p->cycle != M1_CYCLE_V && p->precision != M1_FP64) return false;  // the recursion is FP64 only
     if (!(p->eta > 0.0 && p->eta < 1.0) || !(p->omega > 0.0 && p->omega <= 1.0) || !(p->rtol > 0.0)) return false;
     if (!(p->dtau_im0 > 0.0) || !(p->dtau_min > 0.0) || !(p->dtau_max >= p->dtau_min)) return false;
     return std::isfinite(p->eps_inc) && std::isfinite(p->eps_dec);
@@ -516,6 +518,76 @@ void vcycle_impl(m1_plan& P, Soa& cur, Soa& other, const Gate& G, bool control =
     }
 }
 
+// ---- W- and F-cycles (Sect. 6.3) --------------------------------------------
+// The cycle written as a recursion over the coarse problems, every level by
+// grid kernels (no tail, no tiled legs): a visit of level l smooths its FAS
+// problem in pseudo time (Algorithm 3), restricts the iterate and its residual
+// to level l + 1, visits that level once (V), twice (W) or by an F-cycle then a
+// V-cycle (F), corrects with admissibility (eq. prolongatedSol) and smooths
+// again; the coarsest level is smoothed once per visit.
+
+// v_{l+1} = R(u) and R(rhs - A_l(u)) into level l + 1 (its f, which the first
+// pseudo-time step of the next visit turns into A(v_{l+1}) + R(rbar)).
+void descend(m1_plan& P, int l, const Soa& u, const Gate& G)
+{
+    const LevelBuf& f = P.lev[l];
+    LevelBuf& c = P.lev[l + 1];
+    const CSoa rhs = l == 0 ? cs(P.b) : cs(f.f);
+    if (P.dim == 2 && m1::residual_restrict()) {
+        m1::launch_residual_restrict(P.st, P.ph, f.L, cs(u), rhs, -1.0, P.px, P.py, c.v, c.f, G.active);
+        return;
+    }
+    const Soa r = l == 0 ? P.rfine : f.rb;
+    m1::launch_apply(P.st, P.dim, P.ph, f.L, cs(u), rhs, -1.0, r, nullptr, G.active);
+    m1::launch_restrict(P.st, P.dim, f.nx, f.ny, P.px, P.py, fields2(u, r, c.v, c.f, P.dim), G.active);
+}
+
+Soa coarse_visit(m1_plan& P, int l, int kind, const Gate& G, Soa u, bool first);
+
+// Visit level l + 1 as `kind` prescribes, then u <- projected(u + P(u_{l+1} - v_{l+1})) in place.
+void visit_and_correct(m1_plan& P, int l, int kind, const Gate& G, const Soa& u)
+{
+    const LevelBuf& c = P.lev[l + 1];
+    const LevelBuf& f = P.lev[l];
+    Soa uc;
+    if (kind == M1_CYCLE_F) {
+        uc = coarse_visit(P, l + 1, M1_CYCLE_F, G, c.v, true);
+        uc = coarse_visit(P, l + 1, M1_CYCLE_V, G, uc, false);
+    } else {
+        uc = coarse_visit(P, l + 1, kind, G, c.v, true);
+        if (kind == M1_CYCLE_W) uc = coarse_visit(P, l + 1, kind, G, uc, false);
+    }
+    m1::launch_prolong_project(P.st, P.dim, P.ph, f.nx, f.ny, P.px, P.py, P.params.eta, cs(u), cs(uc), cs(c.v), u,
+                               G.active);
+}
+
+// One visit of coarse level l from the iterate u (v_l on the first visit of a
+// descent, whose first pseudo-time step forms f = A(v_l) + R(rbar)).
+Soa coarse_visit(m1_plan& P, int l, int kind, const Gate& G, Soa u, bool first)
+{
+    u = pseudo_smooth(P, l, G, u, first);
+    if (l == P.L - 1) return u;
+    descend(P, l, u, G);
+    visit_and_correct(P, l, kind, G, u);
+    return pseudo_smooth(P, l, G, u, false);
+}
+
+void rcycle_impl(m1_plan& P, Soa& cur, Soa& other, const Gate& G, bool control)
+{
+    fine_sweeps(P, cur, other, P.params.nu0, G, control);
+    if (P.L == 1) return;
+    descend(P, 0, cur, G);
+    visit_and_correct(P, 0, P.params.cycle, G, cur);
+    fine_sweeps(P, cur, other, P.params.nu0, G);
+}
+
+// One cycle of the plan's shape.
+void cycle_impl(m1_plan& P, Soa& cur, Soa& other, const Gate& G, bool control = false)
+{
+    if (P.params.cycle == M1_CYCLE_V) vcycle_impl(P, cur, other, G, control);
+    else rcycle_impl(P, cur, other, G, control);
+}
+
 // ---- mixed precision -------------------------------------------------------
 m1::Fields32 fields32(std::initializer_list<std::pair<const Soa32*, const Soa32*>> pairs, int dim)
 {
@@ -696,7 +768,7 @@ m1_status graph_cycle(m1_plan& P, Soa& cur, Soa& other, Soa32& pend, const Gate&
         bool ok = true;
         const m1_status s = record(&P.st, P.cap, [&] {
             if (P.mixed) ok = mx_vcycle(P, c.cur, c.other, G, true, first, c.pend);
-            else vcycle_impl(P, c.cur, c.other, G, true);
+            else cycle_impl(P, c.cur, c.other, G, true);
         }, &c.exec);
         if (s == M1_OK && !ok) (void)hipGraphExecDestroy(c.exec);
         if (s != M1_OK) return s;
@@ -884,7 +956,8 @@ static m1_status plan_init(m1_plan* P, const m1_grid* g, const m1_params* p, con
     P->tiled = p->nu_l == 1;  // the tiled legs fuse exactly one Jacobi sweep per pseudo-time step
     P->tiled_max = tiled_max_cells();
     P->graphs = use_graphs();
-    const bool tail_ok = P->L <= m1::kMaxLevels && p->nu_l == 1;
+    if (p->cycle != M1_CYCLE_V) P->tiled = false;  // the recursion runs every level by grid kernels
+    const bool tail_ok = P->L <= m1::kMaxLevels && p->nu_l == 1 && p->cycle == M1_CYCLE_V;
     if (!tail_ok) P->lt = P->L;  // the tail fuses exactly one Jacobi sweep per pseudo-time step
     for (int l = 0; l < P->L && l < m1::kMaxLevels; ++l) {
         const LevelBuf& lv = P->lev[l];
@@ -1027,7 +1100,7 @@ m1_status m1_vcycle(m1_plan* P, m1_state* v, const m1_state* vn, double dtau, m1
         m1::launch_mx_resid(P->st, P->dim, P->ph, P->lev[0].L, P->params.eta, cs(cur), cs(pend), cs(P->b), user,
                             P->base32, P->r32, nullptr, &P->dfix->active);
     } else {
-        vcycle_impl(*P, cur, other, fixed_gate(*P, dtau));
+        cycle_impl(*P, cur, other, fixed_gate(*P, dtau));
         if (!same(cur, user)) m1::launch_copy(P->st, P->dim, P->lev[0].n, cs(cur), user);
     }
     m1_status st = last_launch();
@@ -1125,7 +1198,7 @@ m1_status m1_step(m1_plan* P, m1_state* v, int32_t nsteps, m1_info* info)
                 } else if (P->mixed) {
                     if (!mx_vcycle(*P, cur, other, G, true, enqueued + c == 0, pend)) return M1_ERR_DEVICE;
                 } else {
-                    vcycle_impl(*P, cur, other, G, true);
+                    cycle_impl(*P, cur, other, G, true);
                 }
                 if (enqueued + c == 0) cycle_flips = !same(cur, user);
             }
@@ -1508,7 +1581,8 @@ bool batch_compatible(const m1_engine& E, const m1_grid* g, const m1_params* p)
 {
     if (!valid_grid(g) || !valid_params(p) || g->dim != 2) return false;
     const m1_params& e = E.params;
-    if (p->nu0 != e.nu0 || p->nu_l != 1 || p->smoother != e.smoother || p->pseudo_steps != e.pseudo_steps ||
+    if (p->nu0 != e.nu0 || p->nu_l != 1 || p->smoother != e.smoother || p->cycle != e.cycle ||
+        p->pseudo_steps != e.pseudo_steps ||
         p->sub_steps != e.sub_steps ||
         p->pseudo_local != e.pseudo_local || p->precision != e.precision || p->omega != e.omega || p->eta != e.eta)
         return false;
@@ -1947,7 +2021,7 @@ m1_status m1_engine_create(const m1_params* p, void* arena, size_t arena_bytes, 
     if (!out) return M1_ERR_ARG;
     *out = nullptr;
     if (!valid_params(p) || max_requests < 1 || max_requests > (1 << (32 - m1::kTileBits)) ||
-        p->pseudo_steps % 2 == 0 || p->nu_l != 1 || p->smoother != M1_SMOOTH_JACOBI)
+        p->pseudo_steps % 2 == 0 || p->nu_l != 1 || p->smoother != M1_SMOOTH_JACOBI || p->cycle != M1_CYCLE_V)
         return M1_ERR_ARG;
     if (!arena || (reinterpret_cast<uintptr_t>(arena) % kAlign) != 0) return M1_ERR_WORKSPACE;
     m1_engine* E = new (std::nothrow) m1_engine();
