@@ -25,6 +25,7 @@ BC = {"periodic": 0, "reflective": 1, "neumann": 2, "dirichlet": 3, "inflow": 4}
 DTAU_RULE = {"signed": 0, "literal": 1}
 SMOOTHER = {"jacobi": 0, "rbgs": 1}
 CYCLE = {"V": 0, "W": 1, "F": 2}
+TRANSFER = {"full": 0, "mean": 1}
 
 
 class Grid(ctypes.Structure):
@@ -43,7 +44,8 @@ class Params(ctypes.Structure):
         ("levels", ctypes.c_int32), ("nu0", ctypes.c_int32), ("nu_l", ctypes.c_int32),
         ("pseudo_steps", ctypes.c_int32), ("sub_steps", ctypes.c_int32), ("max_cycles", ctypes.c_int32),
         ("dtau_rule", ctypes.c_int32), ("pseudo_local", ctypes.c_int32),
-        ("smoother", ctypes.c_int32), ("cycle", ctypes.c_int32),
+        ("smoother", ctypes.c_int32), ("cycle", ctypes.c_int32), ("transfer", ctypes.c_int32),
+        ("pad2_", ctypes.c_int32),
         ("dtau_im0", ctypes.c_double), ("eps_inc", ctypes.c_double), ("eps_dec", ctypes.c_double),
         ("eta", ctypes.c_double), ("rtol", ctypes.c_double), ("dtau_min", ctypes.c_double),
         ("dtau_max", ctypes.c_double), ("omega", ctypes.c_double),
@@ -94,6 +96,8 @@ def lib():
         L.or_rb_sweep.argtypes = [gp, dp, ctypes.c_double, dp, dp, dp]
         L.or_restrict.argtypes = [gp, dp, ctypes.c_int32, dp]
         L.or_prolong.argtypes = [gp, dp, ctypes.c_int32, dp]
+        L.or_restrict_t.argtypes = [gp, dp, ctypes.c_int32, dp, ctypes.c_int32]
+        L.or_prolong_t.argtypes = [gp, dp, ctypes.c_int32, dp, ctypes.c_int32]
         L.or_pseudo_time.argtypes = [gp, pp, ctypes.c_double, dp, dp, dp, dp]
         L.or_pseudo_step.argtypes = [gp, dp, pp, ctypes.c_double, dp, dp, dp]
         L.or_project.argtypes = [gp, pp, dp, dp, dp]
@@ -140,13 +144,13 @@ def make_params(**kw) -> Params:
     (omega=1), with the local pseudo-time step reading (pseudo_local=1).
     """
     d = dict(levels=0, nu0=3, nu_l=1, pseudo_steps=3, sub_steps=4, max_cycles=10000, dtau_rule="signed",
-             pseudo_local=1, smoother="jacobi", cycle="V", dtau_im0=1e-3, eps_inc=0.05, eps_dec=0.0, eta=0.9, rtol=1e-10,
+             pseudo_local=1, smoother="jacobi", cycle="V", transfer="full", dtau_im0=1e-3, eps_inc=0.05, eps_dec=0.0, eta=0.9, rtol=1e-10,
              dtau_min=1e-6, dtau_max=1e6, omega=1.0)
     d.update(kw)
     p = Params()
     for k, v in d.items():
         setattr(p, k, DTAU_RULE[v] if k == "dtau_rule" else SMOOTHER[v] if k == "smoother" else
-                CYCLE[v] if k == "cycle" else v)
+                CYCLE[v] if k == "cycle" else TRANSFER[v] if k == "transfer" else v)
     return p
 
 
@@ -212,19 +216,21 @@ class Oracle:
     def coarse_grid(self, g=None):
         return self.L.or_coarse_grid(ctypes.byref(g or self.g))
 
-    def restrict(self, x, g=None):
+    def restrict(self, x, g=None, transfer="full"):
+        """Restriction to the next coarser grid: full weighting (Sect. 4.2) or the 2^d-cell mean."""
         g = g or self.g
         x = self._c(x)
         cg = self.coarse_grid(g)
         out = np.zeros((x.shape[0], cg.ny, cg.nx))
-        self.L.or_restrict(ctypes.byref(g), _p(x), x.shape[0], _p(out))
+        self.L.or_restrict_t(ctypes.byref(g), _p(x), x.shape[0], _p(out), TRANSFER[transfer])
         return out
 
-    def prolong(self, xc, g=None):
+    def prolong(self, xc, g=None, transfer="full"):
+        """Prolongation from the next coarser grid: linear (Sect. 4.2) or piecewise constant."""
         g = g or self.g
         xc = self._c(xc)
         out = np.zeros((xc.shape[0], g.ny, g.nx))
-        self.L.or_prolong(ctypes.byref(g), _p(xc), xc.shape[0], _p(out))
+        self.L.or_prolong_t(ctypes.byref(g), _p(xc), xc.shape[0], _p(out), TRANSFER[transfer])
         return out
 
     def pseudo_step(self, f, u, dtau, params=None, sigma=None, g=None):

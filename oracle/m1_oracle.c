@@ -437,7 +437,27 @@ or_grid or_coarse_grid(const or_grid* g)
     return c;
 }
 
-void or_restrict(const or_grid* fine, const double* x_fine, int32_t nfields, double* x_coarse)
+/* The alternative pair of Sect. 6.3 (the transfer operators are named there as
+ * a choice that changes the speed, not the solution): coarse cell I is the
+ * union of fine cells 2I and 2I+1 along each axis; the prolongation gives both
+ * the coarse value (piecewise constant), and R = 2^-d P^T is the mean of the
+ * 2^d fine cells.                                                             */
+static int mean_w1d(int I, int idx[3], double w[3])
+{
+    idx[0] = 2 * I;
+    idx[1] = 2 * I + 1;
+    w[0] = w[1] = 0.5;
+    return 2;
+}
+
+static int const_w1d(int i, int idx[2], double w[2])
+{
+    idx[0] = i / 2;
+    w[0] = 1.0;
+    return 1;
+}
+
+void or_restrict_t(const or_grid* fine, const double* x_fine, int32_t nfields, double* x_coarse, int32_t transfer)
 {
     or_grid cg = or_coarse_grid(fine);
     const size_t nf = ncell(fine), nc = ncell(&cg);
@@ -447,9 +467,12 @@ void or_restrict(const or_grid* fine, const double* x_fine, int32_t nfields, dou
         for (int I = 0; I < cg.nx; ++I) {
             int ix[3], iy[3];
             double wx[3], wy[3];
-            int cx = restrict_w1d(I, fine->nx, px, ix, wx), cy;
+            int cx, cy;
+            if (transfer == OR_TRANSFER_MEAN) cx = mean_w1d(I, ix, wx);
+            else cx = restrict_w1d(I, fine->nx, px, ix, wx);
             if (fine->dim == 2) {
-                cy = restrict_w1d(J, fine->ny, py, iy, wy);
+                if (transfer == OR_TRANSFER_MEAN) cy = mean_w1d(J, iy, wy);
+                else cy = restrict_w1d(J, fine->ny, py, iy, wy);
             } else {
                 cy = 1;
                 iy[0] = 0;
@@ -466,7 +489,7 @@ void or_restrict(const or_grid* fine, const double* x_fine, int32_t nfields, dou
     }
 }
 
-void or_prolong(const or_grid* fine, const double* x_coarse, int32_t nfields, double* x_fine)
+void or_prolong_t(const or_grid* fine, const double* x_coarse, int32_t nfields, double* x_fine, int32_t transfer)
 {
     or_grid cg = or_coarse_grid(fine);
     const size_t nf = ncell(fine), nc = ncell(&cg);
@@ -476,9 +499,12 @@ void or_prolong(const or_grid* fine, const double* x_coarse, int32_t nfields, do
         for (int i = 0; i < fine->nx; ++i) {
             int ix[2], iy[2];
             double wx[2], wy[2];
-            int cx = prolong_w1d(i, cg.nx, px, ix, wx), cy;
+            int cx, cy;
+            if (transfer == OR_TRANSFER_MEAN) cx = const_w1d(i, ix, wx);
+            else cx = prolong_w1d(i, cg.nx, px, ix, wx);
             if (fine->dim == 2) {
-                cy = prolong_w1d(j, cg.ny, py, iy, wy);
+                if (transfer == OR_TRANSFER_MEAN) cy = const_w1d(j, iy, wy);
+                else cy = prolong_w1d(j, cg.ny, py, iy, wy);
             } else {
                 cy = 1;
                 iy[0] = 0;
@@ -493,6 +519,16 @@ void or_prolong(const or_grid* fine, const double* x_coarse, int32_t nfields, do
             }
         }
     }
+}
+
+void or_restrict(const or_grid* fine, const double* x_fine, int32_t nfields, double* x_coarse)
+{
+    or_restrict_t(fine, x_fine, nfields, x_coarse, OR_TRANSFER_FULL);
+}
+
+void or_prolong(const or_grid* fine, const double* x_coarse, int32_t nfields, double* x_fine)
+{
+    or_prolong_t(fine, x_coarse, nfields, x_fine, OR_TRANSFER_FULL);
 }
 
 /* ------------------------------------------------------------------------- */
@@ -686,7 +722,7 @@ static void vcycle_loop(const or_grid* g, const double* sigma, const or_params* 
     S[0] = (double*)sigma;
     for (int l = 1; l < L; ++l) {
         S[l] = dalloc(2 * ncell(&G[l]));
-        or_restrict(&G[l - 1], S[l - 1], 2, S[l]); /* coarse opacity by full weighting */
+        or_restrict_t(&G[l - 1], S[l - 1], 2, S[l], p->transfer); /* coarse opacity by the same restriction */
     }
     for (int l = 0; l < L; ++l) {
         U[l] = dalloc(NFIELD * ncell(&G[l]));
@@ -703,8 +739,8 @@ static void vcycle_loop(const or_grid* g, const double* sigma, const or_params* 
         for (int l = 1; l < L; ++l) {
             const size_t n = ncell(&G[l]);
             double* rr = dalloc(NFIELD * n);
-            or_restrict(&G[l - 1], U[l - 1], NFIELD, V[l]);
-            or_restrict(&G[l - 1], rbar, NFIELD, rr);
+            or_restrict_t(&G[l - 1], U[l - 1], NFIELD, V[l], p->transfer);
+            or_restrict_t(&G[l - 1], rbar, NFIELD, rr, p->transfer);
             or_apply_A(&G[l], S[l], V[l], Fr[l]);
             for (size_t k = 0; k < NFIELD * n; ++k) Fr[l][k] += rr[k];
             free(rr);
@@ -723,7 +759,7 @@ static void vcycle_loop(const or_grid* g, const double* sigma, const or_params* 
             double* e = dalloc(NFIELD * nc);
             double* w = dalloc(NFIELD * n);
             for (size_t k = 0; k < NFIELD * nc; ++k) e[k] = U[l + 1][k] - V[l + 1][k];
-            or_prolong(&G[l], e, NFIELD, w);
+            or_prolong_t(&G[l], e, NFIELD, w, p->transfer);
             for (size_t k = 0; k < NFIELD * n; ++k) w[k] += U[l][k];
             or_project(&G[l], p, U[l], w, U[l]);
             free(e);
@@ -758,7 +794,7 @@ static void vcycle_loop(const or_grid* g, const double* sigma, const or_params* 
  * steps again.  The finest level is the same with nu0 Jacobi sweeps in place
  * of the pseudo-time steps.  With kind V this is or_vcycle's cycle.          */
 typedef struct {
-    int L;
+    int L, transfer;
     or_grid* G;
     double **S, **U, **V, **F;
 } cyc_levels;
@@ -773,8 +809,8 @@ static void descend(const cyc_levels* c, int l, const double* rhs)
     double* rr = dalloc(NFIELD * nc);
     or_apply_A(&c->G[l], c->S[l], c->U[l], rb);
     for (size_t k = 0; k < NFIELD * n; ++k) rb[k] = rhs[k] - rb[k];
-    or_restrict(&c->G[l], c->U[l], NFIELD, c->V[l + 1]);
-    or_restrict(&c->G[l], rb, NFIELD, rr);
+    or_restrict_t(&c->G[l], c->U[l], NFIELD, c->V[l + 1], c->transfer);
+    or_restrict_t(&c->G[l], rb, NFIELD, rr, c->transfer);
     or_apply_A(&c->G[l + 1], c->S[l + 1], c->V[l + 1], c->F[l + 1]);
     for (size_t k = 0; k < NFIELD * nc; ++k) c->F[l + 1][k] += rr[k];
     memcpy(c->U[l + 1], c->V[l + 1], NFIELD * nc * sizeof(double));
@@ -796,7 +832,7 @@ static void visit_and_correct(const cyc_levels* c, const or_params* p, double dt
     double* e = dalloc(NFIELD * nc);
     double* w = dalloc(NFIELD * n);
     for (size_t k = 0; k < NFIELD * nc; ++k) e[k] = c->U[l + 1][k] - c->V[l + 1][k];
-    or_prolong(&c->G[l], e, NFIELD, w);
+    or_prolong_t(&c->G[l], e, NFIELD, w, c->transfer);
     for (size_t k = 0; k < NFIELD * n; ++k) w[k] += c->U[l][k];
     or_project(&c->G[l], p, c->U[l], w, c->U[l]);
     free(e);
@@ -823,6 +859,7 @@ void or_cycle(const or_grid* g, const double* sigma, const or_params* p, int32_t
 {
     cyc_levels c;
     c.L = or_num_levels(g, p);
+    c.transfer = p->transfer;
     c.G = (or_grid*)malloc(sizeof(or_grid) * c.L);
     c.S = (double**)calloc(c.L, sizeof(double*));
     c.U = (double**)calloc(c.L, sizeof(double*));
@@ -833,7 +870,7 @@ void or_cycle(const or_grid* g, const double* sigma, const or_params* p, int32_t
     for (int l = 1; l < c.L; ++l) {
         c.G[l] = or_coarse_grid(&c.G[l - 1]);
         c.S[l] = dalloc(2 * ncell(&c.G[l]));
-        or_restrict(&c.G[l - 1], c.S[l - 1], 2, c.S[l]); /* coarse opacity by full weighting */
+        or_restrict_t(&c.G[l - 1], c.S[l - 1], 2, c.S[l], p->transfer); /* coarse opacity by the same restriction */
     }
     for (int l = 0; l < c.L; ++l) {
         c.U[l] = dalloc(NFIELD * ncell(&c.G[l]));

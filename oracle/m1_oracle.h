@@ -27,6 +27,7 @@ enum { OR_BC_PERIODIC = 0, OR_BC_REFLECTIVE = 1, OR_BC_NEUMANN = 2, OR_BC_DIRICH
 enum { OR_DTAU_SIGNED = 0, OR_DTAU_LITERAL = 1 };
 enum { OR_SMOOTH_JACOBI = 0, OR_SMOOTH_RBGS = 1 };
 enum { OR_CYCLE_V = 0, OR_CYCLE_W = 1, OR_CYCLE_F = 2 };
+enum { OR_TRANSFER_FULL = 0, OR_TRANSFER_MEAN = 1 };
 
 typedef struct {
     int32_t dim, nx, ny, pad_;
@@ -48,6 +49,9 @@ typedef struct {
     int32_t pseudo_local;  /* 1: implicit pseudo-time step uses each cell's own tau_i; 0: dtau_im everywhere */
     int32_t smoother;      /* finest-level sweeps: OR_SMOOTH_JACOBI or OR_SMOOTH_RBGS (red-black Gauss-Seidel) */
     int32_t cycle;         /* OR_CYCLE_V, OR_CYCLE_W or OR_CYCLE_F */
+    int32_t transfer;      /* OR_TRANSFER_FULL (full weighting, Sect. 4.2) or OR_TRANSFER_MEAN (2^d-cell mean,
+                              piecewise-constant prolongation) */
+    int32_t pad2_;
     double dtau_im0, eps_inc, eps_dec, eta, rtol, dtau_min, dtau_max;
     double omega;          /* relaxation weight of the finest-level Jacobi sweeps (1 = Algorithm 1) */
 } or_params;
@@ -77,6 +81,8 @@ void   or_rb_sweep(const or_grid* g, const double* sigma, double omega, const do
                    double* v_out);
 void   or_restrict(const or_grid* fine, const double* x_fine, int32_t nfields, double* x_coarse);
 void   or_prolong(const or_grid* fine, const double* x_coarse, int32_t nfields, double* x_fine);
+void   or_restrict_t(const or_grid* fine, const double* x_fine, int32_t nfields, double* x_coarse, int32_t transfer);
+void   or_prolong_t(const or_grid* fine, const double* x_coarse, int32_t nfields, double* x_fine, int32_t transfer);
 void   or_pseudo_time(const or_grid* g, const or_params* p, double dtau, const double* f, const double* u_in,
                       double* taus, double* u_tilde);
 void   or_pseudo_step(const or_grid* g, const double* sigma, const or_params* p, double dtau,
