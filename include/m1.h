@@ -60,6 +60,7 @@ typedef enum { M1_FP64 = 0, M1_MIXED = 1 } m1_precision;
 typedef enum { M1_DTAU_SIGNED = 0, M1_DTAU_LITERAL = 1 } m1_dtau_rule;
 typedef enum { M1_SMOOTH_JACOBI = 0, M1_SMOOTH_RBGS = 1 } m1_smoother;
 typedef enum { M1_CYCLE_V = 0, M1_CYCLE_W = 1, M1_CYCLE_F = 2 } m1_cycle;
+typedef enum { M1_TRANSFER_FULL = 0, M1_TRANSFER_MEAN = 1 } m1_transfer;
 
 /* Boundary condition of one side.  Ghost state of the neighbour outside the
  * domain: PERIODIC wraps; REFLECTIVE mirrors the adjacent cell with its normal
@@ -119,6 +120,13 @@ typedef struct {
  *                 level runs the pseudo-time smoothing of Algorithm 3 before
  *                 and after its correction (the coarsest: once per visit).
  *                 W and F: FP64 plans only, not in engines;
+ *   transfer      grid-transfer operators: M1_TRANSFER_FULL (Sect. 4.2: linear
+ *                 prolongation, full-weighting restriction R = 2^-d P^T) or
+ *                 M1_TRANSFER_MEAN (coarse cell I is fine cells 2I, 2I+1 per
+ *                 axis: piecewise-constant prolongation and R = 2^-d P^T, the
+ *                 mean of the 2^d children; Sect. 6.3 leaves the operators
+ *                 open).  Also restricts the coarse opacities.  MEAN: FP64
+ *                 plans only, not in engines;
  *   precision     M1_FP64 or M1_MIXED (FP32 delta-form smoothing and coarse
  *                 levels, FP64 residual, projection and T^4 update; M1_MIXED
  *                 requires nu_l = 1: its coarse steps fuse one sweep);
@@ -131,7 +139,7 @@ typedef struct {
  *                 1 is Algorithm 1, 0 < omega <= 1 keeps admissibility.      */
 typedef struct {
     int32_t levels, nu0, nu_l, pseudo_steps, sub_steps, max_cycles, dtau_rule, pseudo_local, precision, smoother;
-    int32_t cycle, pad_;
+    int32_t cycle, transfer;
     double dtau_im0, eps_inc, eps_dec, eta, rtol, dtau_min, dtau_max, omega;
 } m1_params;
 
@@ -253,21 +261,24 @@ m1_status m1_sweeps(m1_plan* plan, const m1_state* b, const m1_state* v_in, m1_s
  * (level >= 1 in the cycle; any level accepted), from u_in to u_out.          */
 m1_status m1_pseudo_step(m1_plan* plan, int32_t level, double dtau, const m1_state* f, const m1_state* u_in,
                          m1_state* u_out);
-/* Full-weighting restriction (Sect. 4.2) of a state from `level` to level+1.  */
+/* Restriction (Sect. 4.2: full weighting; with M1_TRANSFER_MEAN the 2^d-cell
+ * mean) of a state from `level` to level+1.                                  */
 m1_status m1_restrict(m1_plan* plan, int32_t level, const m1_state* fine, m1_state* coarse);
 /* Residual of level `level` and its restriction, as the downward leg of a
  * V-cycle forms them (Appendix A, Algorithm 4): r = rhs - A_l(u) (eq.
- * defResidual, with the level's opacities and spacing), then the full-
- * weighting restriction (Sect. 4.2, eq. restrictionOperator) of u into vc and
- * of r into rc (level+1 arrays).  In 2-D with the launch shape
- * "residual_restrict" on (default) r is never stored; otherwise it is written
+ * defResidual, with the level's opacities and spacing), then the plan's
+ * restriction (Sect. 4.2, eq. restrictionOperator, or the 2^d-cell mean) of u
+ * into vc and of r into rc (level+1 arrays).  In 2-D with full weighting and
+ * the launch shape "residual_restrict" on (default) r is never stored; otherwise it is written
  * to the plan's residual buffer of that level first (not concurrently with
  * m1_vcycle/m1_step on the same plan).  M1_ERR_ARG unless 0 <= level <
  * levels - 1.                                                                */
 m1_status m1_residual_restrict(m1_plan* plan, int32_t level, const m1_state* u, const m1_state* rhs, m1_state* vc,
                                m1_state* rc);
 /* Correction of `level` from level+1 with admissibility (eq. prolongatedSol):
- * w = u + P(uc - vc); out = w where admissible, else u + eta tau*(u, w-u) (w-u).
+ * w = u + P(uc - vc), P the plan's prolongation (linear, eq.
+ * prolongationOperator, or piecewise constant); out = w where admissible,
+ * else u + eta tau*(u, w-u) (w-u).
  * out may alias u.                                                           */
 m1_status m1_prolong_project(m1_plan* plan, int32_t level, const m1_state* u, const m1_state* uc,
                              const m1_state* vc, m1_state* out);

@@ -26,6 +26,7 @@ PRECISION = {"fp64": 0, "mixed": 1}
 DTAU_RULE = {"signed": 0, "literal": 1}
 SMOOTHER = {"jacobi": 0, "rbgs": 1}
 CYCLE = {"V": 0, "W": 1, "F": 2}
+TRANSFER = {"full": 0, "mean": 1}
 STATUS = {0: "M1_OK", 1: "M1_ERR_ARG", 2: "M1_ERR_NOT_ADMISSIBLE", 3: "M1_ERR_NO_CONVERGENCE", 4: "M1_ERR_WORKSPACE",
           5: "M1_ERR_DEVICE", 6: "M1_ERR_BUSY", 7: "M1_ERR_BUDGET"}
 
@@ -50,7 +51,7 @@ class m1_grid(ctypes.Structure):
 class m1_params(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int32) for n in ("levels", "nu0", "nu_l", "pseudo_steps", "sub_steps", "max_cycles",
                                               "dtau_rule", "pseudo_local", "precision", "smoother", "cycle",
-                                              "pad_")] + \
+                                              "transfer")] + \
                [(n, ctypes.c_double) for n in ("dtau_im0", "eps_inc", "eps_dec", "eta", "rtol", "dtau_min",
                                                "dtau_max", "omega")]
 
@@ -191,6 +192,7 @@ def default_params(**kw) -> dict:
     d["precision"] = "fp64"
     d["smoother"] = "jacobi"
     d["cycle"] = "V"
+    d["transfer"] = "full"
     d.update(kw)
     return d
 
@@ -206,6 +208,8 @@ def make_params(d: dict) -> m1_params:
             v = SMOOTHER[v] if isinstance(v, str) else v
         elif k == "cycle":
             v = CYCLE[v] if isinstance(v, str) else v
+        elif k == "transfer":
+            v = TRANSFER[v] if isinstance(v, str) else v
         setattr(p, k, v)
     return p
 

@@ -18,6 +18,7 @@
 
 #include "../../include/m1.h"
 #include "m1_internal.hpp"
+#include "m1_transfer.hpp"
 
 namespace {
 
@@ -120,6 +121,8 @@ bool valid_params(const m1_params* p)
     if (p->smoother == M1_SMOOTH_RBGS && p->precision != M1_FP64) return false;
     if (p->cycle != M1_CYCLE_V && p->cycle != M1_CYCLE_W && p->cycle != M1_CYCLE_F) return false;
     if (p->cycle != M1_CYCLE_V && p->precision != M1_FP64) return false;  // the recursion is FP64 only
+    if (p->transfer != M1_TRANSFER_FULL && p->transfer != M1_TRANSFER_MEAN) return false;
+    if (p->transfer != M1_TRANSFER_FULL && p->precision != M1_FP64) return false;
     if (!(p->eta > 0.0 && p->eta < 1.0) || !(p->omega > 0.0 && p->omega <= 1.0) || !(p->rtol > 0.0)) return false;
     if (!(p->dtau_im0 > 0.0) || !(p->dtau_min > 0.0) || !(p->dtau_max >= p->dtau_min)) return false;
     return std::isfinite(p->eps_inc) && std::isfinite(p->eps_dec);
@@ -518,6 +521,29 @@ void vcycle_impl(m1_plan& P, Soa& cur, Soa& other, const Gate& G, bool control =
     }
 }
 
+// ---- the plan's transfer operators ------------------------------------------
+// Full weighting and linear prolongation (Sect. 4.2), or the cell-agglomeration
+// pair (the 2^d-cell mean and the piecewise-constant prolongation).
+bool mean_transfer(const m1_plan& P) { return P.params.transfer == M1_TRANSFER_MEAN; }
+
+void plan_restrict(m1_plan& P, int l, const m1::Fields& F, const int* active)
+{
+    const LevelBuf& f = P.lev[l];
+    if (mean_transfer(P)) m1::launch_restrict_mean(P.st, P.dim, f.nx, f.ny, F, active);
+    else m1::launch_restrict(P.st, P.dim, f.nx, f.ny, P.px, P.py, F, active);
+}
+
+// out = u + P(uc - vc) on level l with the admissibility correction (eq. prolongatedSol)
+void plan_prolong_project(m1_plan& P, int l, const CSoa& u, const CSoa& uc, const CSoa& vc, const Soa& out,
+                          const int* active)
+{
+    const LevelBuf& f = P.lev[l];
+    if (mean_transfer(P))
+        m1::launch_prolong_const_project(P.st, P.dim, P.ph, f.nx, f.ny, P.params.eta, u, uc, vc, out, active);
+    else
+        m1::launch_prolong_project(P.st, P.dim, P.ph, f.nx, f.ny, P.px, P.py, P.params.eta, u, uc, vc, out, active);
+}
+
 // ---- W- and F-cycles (Sect. 6.3) --------------------------------------------
 // The cycle written as a recursion over the coarse problems, every level by
 // grid kernels (no tail, no tiled legs): a visit of level l smooths its FAS
@@ -533,13 +559,13 @@ void descend(m1_plan& P, int l, const Soa& u, const Gate& G)
     const LevelBuf& f = P.lev[l];
     LevelBuf& c = P.lev[l + 1];
     const CSoa rhs = l == 0 ? cs(P.b) : cs(f.f);
-    if (P.dim == 2 && m1::residual_restrict()) {
+    if (P.dim == 2 && m1::residual_restrict() && !mean_transfer(P)) {
         m1::launch_residual_restrict(P.st, P.ph, f.L, cs(u), rhs, -1.0, P.px, P.py, c.v, c.f, G.active);
         return;
     }
     const Soa r = l == 0 ? P.rfine : f.rb;
     m1::launch_apply(P.st, P.dim, P.ph, f.L, cs(u), rhs, -1.0, r, nullptr, G.active);
-    m1::launch_restrict(P.st, P.dim, f.nx, f.ny, P.px, P.py, fields2(u, r, c.v, c.f, P.dim), G.active);
+    plan_restrict(P, l, fields2(u, r, c.v, c.f, P.dim), G.active);
 }
 
 Soa coarse_visit(m1_plan& P, int l, int kind, const Gate& G, Soa u, bool first);
@@ -557,8 +583,7 @@ void visit_and_correct(m1_plan& P, int l, int kind, const Gate& G, const Soa& u)
         uc = coarse_visit(P, l + 1, kind, G, c.v, true);
         if (kind == M1_CYCLE_W) uc = coarse_visit(P, l + 1, kind, G, uc, false);
     }
-    m1::launch_prolong_project(P.st, P.dim, P.ph, f.nx, f.ny, P.px, P.py, P.params.eta, cs(u), cs(uc), cs(c.v), u,
-                               G.active);
+    plan_prolong_project(P, l, cs(u), cs(uc), cs(c.v), u, G.active);
 }
 
 // One visit of coarse level l from the iterate u (v_l on the first visit of a
@@ -581,10 +606,10 @@ void rcycle_impl(m1_plan& P, Soa& cur, Soa& other, const Gate& G, bool control)
     fine_sweeps(P, cur, other, P.params.nu0, G);
 }
 
-// One cycle of the plan's shape.
+// One cycle of the plan's shape (the V-cycle with full weighting has its own fused form).
 void cycle_impl(m1_plan& P, Soa& cur, Soa& other, const Gate& G, bool control = false)
 {
-    if (P.params.cycle == M1_CYCLE_V) vcycle_impl(P, cur, other, G, control);
+    if (P.params.cycle == M1_CYCLE_V && !mean_transfer(P)) vcycle_impl(P, cur, other, G, control);
     else rcycle_impl(P, cur, other, G, control);
 }
 
@@ -956,8 +981,10 @@ static m1_status plan_init(m1_plan* P, const m1_grid* g, const m1_params* p, con
     P->tiled = p->nu_l == 1;  // the tiled legs fuse exactly one Jacobi sweep per pseudo-time step
     P->tiled_max = tiled_max_cells();
     P->graphs = use_graphs();
-    if (p->cycle != M1_CYCLE_V) P->tiled = false;  // the recursion runs every level by grid kernels
-    const bool tail_ok = P->L <= m1::kMaxLevels && p->nu_l == 1 && p->cycle == M1_CYCLE_V;
+    // the recursion (other shapes, other transfers) runs every level by grid kernels
+    const bool fused_form = p->cycle == M1_CYCLE_V && p->transfer == M1_TRANSFER_FULL;
+    if (!fused_form) P->tiled = false;
+    const bool tail_ok = P->L <= m1::kMaxLevels && p->nu_l == 1 && fused_form;
     if (!tail_ok) P->lt = P->L;  // the tail fuses exactly one Jacobi sweep per pseudo-time step
     for (int l = 0; l < P->L && l < m1::kMaxLevels; ++l) {
         const LevelBuf& lv = P->lev[l];
@@ -1004,7 +1031,7 @@ static m1_status plan_init(m1_plan* P, const m1_grid* g, const m1_params* p, con
         F.out[0] = P->lev[l].sa;
         F.out[1] = P->lev[l].ss;
         F.n = 2;
-        m1::launch_restrict(P->st, P->dim, P->lev[l - 1].nx, P->lev[l - 1].ny, P->px, P->py, F, &P->dfix->active);
+        plan_restrict(*P, l - 1, F, &P->dfix->active);  // coarse opacities by the plan's restriction
         st = last_launch();
     }
     for (int l = 0; st == M1_OK && P->mixed && l < P->L; ++l) {
@@ -1362,9 +1389,7 @@ m1_status m1_restrict(m1_plan* P, int32_t level, const m1_state* fine, m1_state*
 {
     if (!P || level < 0 || level + 1 >= P->L || !valid_level_state(P, fine) || !valid_level_state(P, coarse))
         return M1_ERR_ARG;
-    const LevelBuf& f = P->lev[level];
-    m1::launch_restrict(P->st, P->dim, f.nx, f.ny, P->px, P->py,
-                        fields2(to_soa(fine), Soa{}, to_soa(coarse), Soa{}, P->dim), &P->dfix->active);
+    plan_restrict(*P, level, fields2(to_soa(fine), Soa{}, to_soa(coarse), Soa{}, P->dim), &P->dfix->active);
     return last_launch();
 }
 
@@ -1376,14 +1401,13 @@ m1_status m1_residual_restrict(m1_plan* P, int32_t level, const m1_state* u, con
         return M1_ERR_ARG;
     const LevelBuf& f = P->lev[level];
     const int* act = &P->dfix->active;
-    if (P->dim == 2 && m1::residual_restrict()) {
+    if (P->dim == 2 && m1::residual_restrict() && !mean_transfer(*P)) {
         m1::launch_residual_restrict(P->st, P->ph, f.L, cs(to_soa(u)), cs(to_soa(rhs)), -1.0, P->px, P->py,
                                      to_soa(vc), to_soa(rc), act);
     } else {  // stored in the level's residual buffer, then restricted
         const Soa r = level == 0 ? P->rfine : P->lev[level].rb;
         m1::launch_apply(P->st, P->dim, P->ph, f.L, cs(to_soa(u)), cs(to_soa(rhs)), -1.0, r, nullptr, act);
-        m1::launch_restrict(P->st, P->dim, f.nx, f.ny, P->px, P->py,
-                            fields2(to_soa(u), r, to_soa(vc), to_soa(rc), P->dim), act);
+        plan_restrict(*P, level, fields2(to_soa(u), r, to_soa(vc), to_soa(rc), P->dim), act);
     }
     return last_launch();
 }
@@ -1394,9 +1418,7 @@ m1_status m1_prolong_project(m1_plan* P, int32_t level, const m1_state* u, const
     if (!P || level < 0 || level + 1 >= P->L || !valid_level_state(P, u) || !valid_level_state(P, uc) ||
         !valid_level_state(P, vc) || !valid_level_state(P, out))
         return M1_ERR_ARG;
-    const LevelBuf& f = P->lev[level];
-    m1::launch_prolong_project(P->st, P->dim, P->ph, f.nx, f.ny, P->px, P->py, P->params.eta, cs(to_soa(u)),
-                               cs(to_soa(uc)), cs(to_soa(vc)), to_soa(out), &P->dfix->active);
+    plan_prolong_project(*P, level, cs(to_soa(u)), cs(to_soa(uc)), cs(to_soa(vc)), to_soa(out), &P->dfix->active);
     return last_launch();
 }
 
@@ -1582,6 +1604,7 @@ bool batch_compatible(const m1_engine& E, const m1_grid* g, const m1_params* p)
     if (!valid_grid(g) || !valid_params(p) || g->dim != 2) return false;
     const m1_params& e = E.params;
     if (p->nu0 != e.nu0 || p->nu_l != 1 || p->smoother != e.smoother || p->cycle != e.cycle ||
+        p->transfer != e.transfer ||
         p->pseudo_steps != e.pseudo_steps ||
         p->sub_steps != e.sub_steps ||
         p->pseudo_local != e.pseudo_local || p->precision != e.precision || p->omega != e.omega || p->eta != e.eta)
@@ -2021,7 +2044,8 @@ m1_status m1_engine_create(const m1_params* p, void* arena, size_t arena_bytes, 
     if (!out) return M1_ERR_ARG;
     *out = nullptr;
     if (!valid_params(p) || max_requests < 1 || max_requests > (1 << (32 - m1::kTileBits)) ||
-        p->pseudo_steps % 2 == 0 || p->nu_l != 1 || p->smoother != M1_SMOOTH_JACOBI || p->cycle != M1_CYCLE_V)
+        p->pseudo_steps % 2 == 0 || p->nu_l != 1 || p->smoother != M1_SMOOTH_JACOBI || p->cycle != M1_CYCLE_V ||
+        p->transfer != M1_TRANSFER_FULL)
         return M1_ERR_ARG;
     if (!arena || (reinterpret_cast<uintptr_t>(arena) % kAlign) != 0) return M1_ERR_WORKSPACE;
     m1_engine* E = new (std::nothrow) m1_engine();

@@ -1,4 +1,4 @@
-"""W- and F-cycles (Sect. 6.3) on the GPU against the oracle's.
+"""W- and F-cycles and the cell-agglomeration transfer pair (Sect. 6.3) on the GPU against the oracle.
 
 * One cycle at a time, three in a row with changing pseudo-time steps, on 2-D
   workloads of four and five levels, a 2-D side-condition mix, 1-D, with the
@@ -7,7 +7,11 @@
 * Converged time steps (rtol 1e-13) within 1e-10, with the cycle count of the
   oracle's up to a rounding flip of the last stopping test; the same step with
   recorded (hipGraph) cycles and with plain launches, bitwise.
-* W and F are FP64 only: mixed-precision plans and engines reject them.
+* The transfer pair (2^d-cell mean, piecewise-constant prolongation): the
+  restriction, the residual with its restriction and the correction with
+  projection on the finest and a coarse level (1e-14 / 1e-13), cycles of every
+  shape (1e-11) and converged steps (1e-10) against the oracle.
+* W, F and the pair are FP64 only: mixed-precision plans and engines reject them.
 """
 import ctypes
 
@@ -93,15 +97,81 @@ def test_converged_step_parity(kind, case):
     assert abs(cycles - info_o["cycles"]) <= 1
 
 
-@pytest.mark.parametrize("kind", ["W", "F"])
-def test_mixed_precision_and_engines_reject_w_and_f(kind):
-    announce("cycle rejections", kind)
+@pytest.mark.parametrize("kind,transfer", [("W", "full"), ("F", "full"), ("V", "mean")])
+def test_mixed_precision_and_engines_reject_w_f_and_the_pair(kind, transfer):
+    announce("cycle rejections", kind, transfer)
     prob, v, sig, _ = inputs.hot_wall_2d(n=64)
     with pytest.raises(binding.M1Error) as e:
-        binding.Plan(prob, to_dev(sig), dict(omega=OMEGA, cycle=kind, precision="mixed"))
+        binding.Plan(prob, to_dev(sig), dict(omega=OMEGA, cycle=kind, transfer=transfer, precision="mixed"))
     assert "M1_ERR_ARG" in str(e.value)
-    p = binding.make_params(binding.default_params(omega=OMEGA, cycle=kind))
+    p = binding.make_params(binding.default_params(omega=OMEGA, cycle=kind, transfer=transfer))
     arena = ctypes.c_void_p(256)  # never dereferenced: the parameters are checked first
     out = ctypes.c_void_p()
     st = binding.lib().m1_engine_create(ctypes.byref(p), arena, 1 << 20, 4, None, ctypes.byref(out))
     assert st == 1 and not out.value  # M1_ERR_ARG
+
+
+# ------------------------------------------------------------------ the cell-agglomeration transfer pair
+@pytest.mark.parametrize("case", ["mixed96x80", "gauss256"])
+def test_mean_transfer_operations(case):
+    announce("mean transfer operations", case)
+    prob, v, sig = case_problem(case)
+    o = oracle.Oracle(prob, sig)
+    P = binding.Plan(prob, to_dev(sig), dict(omega=OMEGA, transfer="mean"))
+    c = prob["c"]
+    rng = np.random.default_rng(5)
+    u = inputs.random_state(rng, prob["ny"], prob["nx"], c=c, fmax=0.9, dim=prob["dim"])
+    b = o.rhs(v)
+    g1 = o.coarse_grid()
+    s1 = o.restrict(sig, transfer="mean")
+    u1 = o.restrict(u, transfer="mean")
+    f1 = o.apply_A(u1, sigma=s1, g=g1) * 1.01
+    for level, (uu, rhs, g, s) in enumerate(((u, b, None, sig), (u1, f1, g1, s1))):
+        want = o.restrict(uu, g=g, transfer="mean")
+        assert rel_err(to_host(P.restrict(level, to_dev(uu))), want, c) <= 1e-15
+        vc, rc = P.residual_restrict(level, to_dev(uu), to_dev(rhs))
+        assert rel_err(to_host(vc), want, c) <= 1e-15
+        r = rhs - (o.apply_A(uu) if level == 0 else o.apply_A(uu, sigma=s, g=g))
+        rr = o.restrict(r, g=g, transfer="mean")
+        assert np.abs(to_host(rc) - rr).max() <= 1e-12 * np.abs(rr).max(), level
+        # correction with projection: a coarse change large enough to leave the admissible set somewhere
+        uc = want * (1.0 + 0.5 * rng.normal(size=want.shape))
+        wf = uu + o.prolong(uc - want, g=g, transfer="mean")
+        ref = o.project(uu, wf, oracle.make_params(), g=g)
+        got = to_host(P.prolong_project(level, to_dev(uu), to_dev(uc), to_dev(want)))
+        assert rel_err(got, ref, c) <= 1e-13, level
+
+
+@pytest.mark.parametrize("kind", ["V", "W", "F"])
+@pytest.mark.parametrize("case", ["logn128", "mixed96x80", "gauss256"])
+def test_mean_transfer_cycle_parity(kind, case):
+    announce("mean transfer cycle", kind, case)
+    prob, v, sig = case_problem(case)
+    o = oracle.Oracle(prob, sig)
+    params = dict(omega=OMEGA, cycle=kind, transfer="mean")
+    P = binding.Plan(prob, to_dev(sig), params)
+    b = o.rhs(v)
+    vd, vn = to_dev(v), to_dev(v)
+    ref = v
+    for cyc, dtau in enumerate((1e-3, 0.3, 5.0)):
+        P.vcycle(vd, vn, dtau)
+        ref = o.vcycle(b, ref, dtau, params=oracle.make_params(**params))
+        err = rel_err(to_host(vd), ref, prob["c"])
+        assert err <= 1e-11, (cyc, err)
+
+
+@pytest.mark.parametrize("kind", ["V", "W"])
+def test_mean_transfer_converged_step(kind):
+    announce("mean transfer step", kind)
+    prob, v, sig, _ = inputs.hot_wall_2d(n=128)
+    o = oracle.Oracle(prob, sig)
+    params = dict(omega=OMEGA, rtol=1e-13, max_cycles=40000, cycle=kind, transfer="mean")
+    ref, info_o = o.step(v, 1, oracle.make_params(**params))
+    assert info_o["status"] == 0
+    P = binding.Plan(prob, to_dev(sig), params)
+    vd = to_dev(v)
+    info = P.step(vd, 1)
+    assert info["status"] == 0 and info["rel_residual"] <= 1e-11, info
+    assert rel_err(to_host(vd), ref, prob["c"]) <= 1e-10
+    print(f"mean transfer, {kind}: cycles gpu/oracle {info['cycles']} {info_o['cycles']}", flush=True)
+    assert abs(info["cycles"] - info_o["cycles"]) <= 1
