@@ -19,6 +19,8 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "m1_oracle.c")
+_SRC3 = os.path.join(_HERE, "m1_oracle3.c")  # the three-dimensional method
+_FILES = ("m1_oracle.c", "m1_oracle.h", "m1_oracle3.c", "m1_oracle3.h")
 _LIB = os.path.join(_HERE, "libm1oracle.so")
 
 BC = {"periodic": 0, "reflective": 1, "neumann": 2, "dirichlet": 3, "inflow": 4}
@@ -61,9 +63,10 @@ class Info(ctypes.Structure):
 
 def build(force: bool = False) -> str:
     """Compile the oracle with gcc (always when ``force``)."""
-    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+    newest = max(os.path.getmtime(os.path.join(_HERE, f)) for f in _FILES)
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < newest:
         cmd = ["gcc", "-O2", "-std=c99", "-fopenmp", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared",
-               "-Wall", "-o", _LIB + ".tmp", _SRC, "-lm"]
+               "-Wall", "-o", _LIB + ".tmp", _SRC, _SRC3, "-lm"]
         subprocess.run(cmd, check=True)
         os.replace(_LIB + ".tmp", _LIB)
     return _LIB
@@ -349,3 +352,155 @@ def threads() -> int:
 def set_threads(n: int) -> None:
     """Threads of the oracle's parallel loops from now on."""
     lib().or_set_threads(int(n))
+
+
+# ---------------------------------------------------------------------------- three dimensions
+class Grid3(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32), ("pad_", ctypes.c_int32),
+                ("hx", ctypes.c_double), ("hy", ctypes.c_double), ("hz", ctypes.c_double), ("dt", ctypes.c_double),
+                ("c", ctypes.c_double), ("a_r", ctypes.c_double), ("c_v", ctypes.c_double),
+                ("bc_kind", ctypes.c_int32 * 6), ("bc_E", ctypes.c_double * 6), ("bc_Fx", ctypes.c_double * 6),
+                ("bc_Fy", ctypes.c_double * 6), ("bc_Fz", ctypes.c_double * 6)]
+
+
+_lib3 = None
+
+
+def lib3():
+    """The oracle library with the prototypes of its three-dimensional functions."""
+    global _lib3
+    if _lib3 is None:
+        L = lib()
+        dp = ctypes.POINTER(ctypes.c_double)
+        gp, pp = ctypes.POINTER(Grid3), ctypes.POINTER(Params)
+        L.or3_closure.argtypes = [ctypes.c_double] * 5 + [dp]
+        L.or3_apply_A.argtypes = [gp, dp, dp, dp]
+        L.or3_residual.argtypes = [gp, dp, dp, dp, dp]
+        L.or3_norm.restype = ctypes.c_double
+        L.or3_norm.argtypes = [gp, dp]
+        L.or3_sweep.argtypes = [gp, dp, ctypes.c_double, dp, dp, dp]
+        L.or3_pseudo_step.argtypes = [gp, dp, pp, ctypes.c_double, dp, dp, dp]
+        L.or3_project.argtypes = [gp, pp, dp, dp, dp]
+        L.or3_coarse_grid.restype = Grid3
+        L.or3_coarse_grid.argtypes = [gp]
+        L.or3_restrict.argtypes = [gp, dp, ctypes.c_int32, dp]
+        L.or3_prolong.argtypes = [gp, dp, ctypes.c_int32, dp]
+        L.or3_num_levels.restype = ctypes.c_int32
+        L.or3_num_levels.argtypes = [gp, pp]
+        L.or3_vcycle.argtypes = [gp, dp, pp, ctypes.c_double, dp, dp, dp]
+        L.or3_step.restype = ctypes.c_int32
+        L.or3_step.argtypes = [gp, dp, pp, dp, ctypes.c_int32, ctypes.POINTER(Info)]
+        _lib3 = L
+    return _lib3
+
+
+def make_grid3(prob: dict) -> Grid3:
+    g = Grid3()
+    for k in ("nx", "ny", "nz", "hx", "hy", "hz", "dt", "c", "a_r", "c_v"):
+        setattr(g, k, prob[k])
+    for s, bc in enumerate(prob["bc"]):
+        g.bc_kind[s] = BC[bc["kind"]]
+        g.bc_E[s] = bc.get("E", 0.0)
+        g.bc_Fx[s] = bc.get("Fx", 0.0)
+        g.bc_Fy[s] = bc.get("Fy", 0.0)
+        g.bc_Fz[s] = bc.get("Fz", 0.0)
+    return g
+
+
+class Oracle3:
+    """The three-dimensional oracle on one problem.  States have shape (5, nz, ny, nx): E, Fx, Fy, Fz, T;
+    opacities (2, nz, ny, nx): sigma_a, sigma_s."""
+
+    def __init__(self, prob: dict, sigma=None):
+        self.prob = prob
+        self.L = lib3()
+        self.g = make_grid3(prob)
+        shape = (prob["nz"], prob["ny"], prob["nx"])
+        self.sigma = np.ascontiguousarray(sigma if sigma is not None else np.zeros((2,) + shape), dtype=np.float64)
+
+    def _new(self, g=None):
+        g = g or self.g
+        return np.zeros((5, g.nz, g.ny, g.nx))
+
+    @staticmethod
+    def _c(x):
+        return np.ascontiguousarray(x, dtype=np.float64)
+
+    def coarse_grid(self, g=None):
+        return self.L.or3_coarse_grid(ctypes.byref(g or self.g))
+
+    def rhs(self, v):
+        b = self._c(v).copy()
+        b[4] *= self.prob["c_v"]
+        return b
+
+    def apply_A(self, v, sigma=None, g=None):
+        g = g or self.g
+        out = self._new(g)
+        s = self._c(self.sigma if sigma is None else sigma)
+        self.L.or3_apply_A(ctypes.byref(g), _p(s), _p(self._c(v)), _p(out))
+        return out
+
+    def residual(self, b, v):
+        out = self._new()
+        self.L.or3_residual(ctypes.byref(self.g), _p(self.sigma), _p(self._c(b)), _p(self._c(v)), _p(out))
+        return out
+
+    def norm(self, r, g=None):
+        return self.L.or3_norm(ctypes.byref(g or self.g), _p(self._c(r)))
+
+    def sweep(self, b, v, omega=1.0):
+        out = self._new()
+        self.L.or3_sweep(ctypes.byref(self.g), _p(self.sigma), omega, _p(self._c(b)), _p(self._c(v)), _p(out))
+        return out
+
+    def pseudo_step(self, f, u, dtau, params=None, sigma=None, g=None):
+        g = g or self.g
+        p = params or make_params()
+        out = self._new(g)
+        s = self._c(self.sigma if sigma is None else sigma)
+        self.L.or3_pseudo_step(ctypes.byref(g), _p(s), ctypes.byref(p), dtau, _p(self._c(f)), _p(self._c(u)),
+                               _p(out))
+        return out
+
+    def project(self, u, w, params=None, g=None):
+        g = g or self.g
+        p = params or make_params()
+        out = self._new(g)
+        self.L.or3_project(ctypes.byref(g), ctypes.byref(p), _p(self._c(u)), _p(self._c(w)), _p(out))
+        return out
+
+    def restrict(self, x, g=None):
+        g = g or self.g
+        x = self._c(x)
+        cg = self.coarse_grid(g)
+        out = np.zeros((x.shape[0], cg.nz, cg.ny, cg.nx))
+        self.L.or3_restrict(ctypes.byref(g), _p(x), x.shape[0], _p(out))
+        return out
+
+    def prolong(self, xc, g=None):
+        g = g or self.g
+        xc = self._c(xc)
+        out = np.zeros((xc.shape[0], g.nz, g.ny, g.nx))
+        self.L.or3_prolong(ctypes.byref(g), _p(xc), xc.shape[0], _p(out))
+        return out
+
+    def num_levels(self, params=None):
+        p = params or make_params()
+        return self.L.or3_num_levels(ctypes.byref(self.g), ctypes.byref(p))
+
+    def vcycle(self, b, v, dtau, params=None):
+        p = params or make_params()
+        out = self._new()
+        self.L.or3_vcycle(ctypes.byref(self.g), _p(self.sigma), ctypes.byref(p), dtau, _p(self._c(b)),
+                          _p(self._c(v)), _p(out))
+        return out
+
+    def step(self, v, nsteps=1, params=None):
+        p = params or make_params()
+        v = self._c(v).copy()
+        info = Info()
+        st = self.L.or3_step(ctypes.byref(self.g), _p(self.sigma), ctypes.byref(p), _p(v), nsteps,
+                             ctypes.byref(info))
+        return v, dict(status=st, cycles=info.cycles, levels=info.levels, r0=info.r0, rel_residual=info.rel_residual,
+                       dtau=info.dtau)

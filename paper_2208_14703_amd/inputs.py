@@ -219,3 +219,72 @@ def random_problem(seed: int, dim: int, nx: int, ny: int, bc_kinds=("periodic",)
     v = random_state(rng, ny_, nx, c=c, fmax=fmax, fixed_f=fixed_f, dim=dim)
     v[3] = rng.uniform(0.5, 1.5, size=(ny_, nx))
     return prob, v, sig
+
+
+# ---------------------------------------------------------------------------- three dimensions
+# A 3-D problem is a dict with keys nx, ny, nz, hx, hy, hz, dt, c, a_r, c_v and bc: six dicts {kind, E, Fx, Fy,
+# Fz} for the sides x-, x+, y-, y+, z-, z+.  States have shape (5, nz, ny, nx) holding E, Fx, Fy, Fz, T;
+# opacities (2, nz, ny, nx).
+def grid_problem3(nx: int, ny: int, nz: int, cfl: float, bc: list, c: float = 1.0, a_r: float = 1.0,
+                  c_v: float = 1.0, length: float = 1.0) -> dict:
+    """Uniform grid on [0, length]^3 with dt = cfl * hx / c."""
+    hx, hy, hz = length / nx, length / ny, length / nz
+    return dict(nx=nx, ny=ny, nz=nz, hx=hx, hy=hy, hz=hz, dt=cfl * hx / c, c=c, a_r=a_r, c_v=c_v,
+                bc=[dict(b) for b in bc])
+
+
+def block_opacity3(rng: np.random.Generator, nz: int, ny: int, nx: int, block: int, log10_sa: tuple,
+                   ss: tuple) -> np.ndarray:
+    """Piecewise-constant opacity on block^3 cells: all sigma_a blocks first (z, y, x order), then sigma_s."""
+    bz, by, bx = (max(1, -(-m // block)) for m in (nz, ny, nx))
+    la = rng.uniform(log10_sa[0], log10_sa[1], size=(bz, by, bx))
+    s = rng.uniform(ss[0], ss[1], size=(bz, by, bx))
+
+    def expand(a):
+        return np.repeat(np.repeat(np.repeat(a, block, axis=0), block, axis=1), block, axis=2)[:nz, :ny, :nx]
+
+    sig = np.empty((2, nz, ny, nx))
+    sig[0] = expand(10.0 ** la)
+    sig[1] = expand(s)
+    return sig
+
+
+def random_state3(rng: np.random.Generator, nz: int, ny: int, nx: int, c: float = 1.0, fmax: float = 0.95,
+                  fixed_f=None, T: float = 1.0) -> np.ndarray:
+    """Admissible 3-D state: E ~ lognormal(0,1), a direction uniform on the sphere, |F|/(cE) ~ U[0, fmax]."""
+    v = np.empty((5, nz, ny, nx))
+    v[0] = rng.lognormal(0.0, 1.0, size=(nz, ny, nx))
+    d = rng.normal(size=(3, nz, ny, nx))
+    d /= np.linalg.norm(d, axis=0)
+    f = np.full((nz, ny, nx), float(fixed_f)) if fixed_f is not None else rng.uniform(0.0, fmax, size=(nz, ny, nx))
+    v[1:4] = d * f * c * v[0]
+    v[4] = T
+    return v
+
+
+def random_problem3(seed: int, nx: int, ny: int, nz: int, bc_kinds=("periodic",) * 6, cfl: float = 20.0,
+                    log10_sa=(-2.0, 1.0), ss=(0.0, 1.0), fmax: float = 0.95, fixed_f=None, block: int = 2,
+                    c: float = 1.0, wall_E: float = 10.0):
+    """Small random 3-D problem for tests; Dirichlet sides get the wall state (wall_E, 0.3 c wall_E, 0, 0)."""
+    rng = _rng(seed)
+    bc = [dict(kind=k, E=wall_E, Fx=0.3 * c * wall_E, Fy=0.0, Fz=0.0) if k == "dirichlet" else dict(kind=k)
+          for k in bc_kinds]
+    prob = grid_problem3(nx, ny, nz, cfl, bc, c=c)
+    sig = block_opacity3(rng, nz, ny, nx, block, log10_sa, ss)
+    v = random_state3(rng, nz, ny, nx, c=c, fmax=fmax, fixed_f=fixed_f)
+    v[4] = rng.uniform(0.5, 1.5, size=(nz, ny, nx))
+    return prob, v, sig
+
+
+def hot_wall_3d(n: int = 256, seed: int = 1, cfl: float = 100.0, block: int = 8, steps: int = 10):
+    """The hot-wall problem in 3-D on [0,1]^3: n^3 cells, dt = 100 h/c, opacity piecewise constant on block^3
+    cells (log10 sigma_a ~ U[-2,2], sigma_s ~ U[0,1]), cold interior E = a_r, F = 0, T = 1, a Dirichlet wall
+    E = a_r*1e4, F = 0 at x = 0 and reflective sides elsewhere; implicit steps to relative residual 1e-8."""
+    bc = [dict(kind="dirichlet", E=1.0e4, Fx=0.0, Fy=0.0, Fz=0.0)] + [dict(kind="reflective") for _ in range(5)]
+    prob = grid_problem3(n, n, n, cfl, bc)
+    rng = _rng(seed)
+    sig = block_opacity3(rng, n, n, n, block, (-2.0, 2.0), (0.0, 1.0))
+    v = np.zeros((5, n, n, n))
+    v[0] = prob["a_r"]
+    v[4] = 1.0
+    return prob, v, sig, dict(steps=steps, rtol=1e-8)
