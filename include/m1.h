@@ -395,6 +395,82 @@ m1_status m1_serve_start(m1_engine* e, int32_t cycles);
  * m1_engine_destroy.                                                         */
 m1_status m1_serve_stop(m1_engine* e);
 
+/* ---- three dimensions ---------------------------------------------------------
+ * The method with d = 3: the paper writes its scheme in 1-D and says the
+ * extension to higher dimensions is direct (Sect. 2.2); its restriction is
+ * R = 2^-d P^T with d = 1, 2, 3 (Sect. 4.2).  Per axis the left/right operators
+ * of Sect. 3.1 with the directional flux (F_axis, c^2 P[., axis]) of the 3-D
+ * closure (Sect. 2.1), the implicit sources, the nonlinear Jacobi sweep
+ * (Algorithm 1), pseudo-time steps (Algorithm 3), the admissible correction
+ * (eq. prolongatedSol), trilinear prolongation with full weighting R, and the
+ * V-cycle / time-step driver of Appendix A.  FP64 plans with the V-cycle, full
+ * weighting, Jacobi smoothing and nu_l = 1 (other m1_params choices give
+ * M1_ERR_ARG); sides PERIODIC, REFLECTIVE, NEUMANN or DIRICHLET. */
+
+/* Side condition of a 3-D grid (kinds as m1_bc; (E, Fx, Fy, Fz) for DIRICHLET). */
+typedef struct {
+    int32_t kind;
+    int32_t pad_;
+    double E, Fx, Fy, Fz;
+} m1_bc3;
+
+/* 3-D discrete problem: nx*ny*nz cells (at most 2^29), cell sizes hx, hy, hz,
+ * the other data as m1_grid.  bc[] order: x-, x+, y-, y+, z-, z+.            */
+typedef struct {
+    int32_t nx, ny, nz, pad_;
+    double hx, hy, hz, dt, c, a_r, c_v;
+    m1_bc3 bc[6];
+} m1_grid3;
+
+/* 3-D state (E, Fx, Fy, Fz, T), device pointers, nx*ny*nz each, x fastest
+ * (cell (i, j, k) at (k ny + j) nx + i).  Opacities: m1_opacity over the same
+ * cells.                                                                      */
+typedef struct {
+    double *E, *Fx, *Fy, *Fz, *T;
+} m1_state3;
+
+typedef struct m1_plan3 m1_plan3;
+
+/* Bytes of device workspace of a 3-D plan (0 on invalid arguments): per coarse
+ * level the restricted state, two iterates, the FAS right-hand side, the
+ * residual and the opacities (Sect. 4.2); on the finest level the right-hand
+ * side, a partner state and the residual.                                   */
+size_t m1_workspace3_bytes(const m1_grid3* g, const m1_params* p);
+/* Hierarchy of Sect. 4.2 in 3-D: every side halved per level while all stay
+ * even and >= 8 (or `levels` levels), coarse opacities by full weighting;
+ * buffers carved from `workspace` (device, 256-byte aligned).  Opacities
+ * validated (M1_ERR_ARG if negative or non-finite); M1_ERR_WORKSPACE for a
+ * missing, misaligned or short workspace; `op` arrays and `workspace` must
+ * outlive the plan.                                                         */
+m1_status m1_plan3_create(const m1_grid3* g, const m1_params* p, const m1_opacity* op, void* workspace,
+                          size_t workspace_bytes, void* stream, m1_plan3** out);
+void m1_plan3_destroy(m1_plan3* plan);
+int32_t m1_plan3_levels(const m1_plan3* plan);
+m1_status m1_level3_dims(const m1_plan3* plan, int32_t level, int32_t* nx, int32_t* ny, int32_t* nz);
+/* out = A_l(v) on `level` (Sect. 3.1 with the implicit sources). */
+m1_status m1_apply3(m1_plan3* plan, int32_t level, const m1_state3* v, m1_state3* out);
+/* One relaxed Jacobi sweep (Algorithm 1) of A(u) = b on the finest level; v_out
+ * must not alias v_in.                                                        */
+m1_status m1_sweep3(m1_plan3* plan, const m1_state3* b, const m1_state3* v_in, m1_state3* v_out);
+/* One pseudo-time step (Algorithm 3) of M du/dtau + A_l(u) = f on `level`. */
+m1_status m1_pseudo_step3(m1_plan3* plan, int32_t level, double dtau, const m1_state3* f, const m1_state3* u_in,
+                          m1_state3* u_out);
+/* Full-weighting restriction (R = 2^-3 P^T) from `level` to level+1. */
+m1_status m1_restrict3(m1_plan3* plan, int32_t level, const m1_state3* fine, m1_state3* coarse);
+/* out = u + P(uc - vc) on `level` (trilinear P) with the admissibility
+ * correction of eq. prolongatedSol; out may alias u.                         */
+m1_status m1_prolong_project3(m1_plan3* plan, int32_t level, const m1_state3* u, const m1_state3* uc,
+                              const m1_state3* vc, m1_state3* out);
+/* r = b - A(v), b = (E^n, F^n, C_v T^n) of vn; the L2 norm of (r_E, r_F/c, r_T)
+ * to *norm_out (host; blocks), the fields to r_out when not NULL.            */
+m1_status m1_residual3(m1_plan3* plan, const m1_state3* v, const m1_state3* vn, double* norm_out, m1_state3* r_out);
+/* One V-cycle (Appendix A) of A(v) = b(vn) with pseudo-time step dtau, in place on v (v must not alias vn). */
+m1_status m1_vcycle3(m1_plan3* plan, m1_state3* v, const m1_state3* vn, double dtau);
+/* nsteps implicit Euler steps in place on v (Appendix A, Algorithm 4), as m1_step: cycles until the relative
+ * residual rtol or A's rounding level, dtau reset every step and adapted after every cycle; M1_ERR_NOT_ADMISSIBLE
+ * for a non-admissible input (info->first_bad_cell), M1_ERR_NO_CONVERGENCE after max_cycles.                   */
+m1_status m1_step3(m1_plan3* plan, m1_state3* v, int32_t nsteps, m1_info* info);
+
 #ifdef __cplusplus
 }
 #endif

@@ -60,6 +60,21 @@ class m1_state(ctypes.Structure):
     _fields_ = [("E", ctypes.c_void_p), ("Fx", ctypes.c_void_p), ("Fy", ctypes.c_void_p), ("T", ctypes.c_void_p)]
 
 
+class m1_bc3(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("pad_", ctypes.c_int32), ("E", ctypes.c_double), ("Fx", ctypes.c_double),
+                ("Fy", ctypes.c_double), ("Fz", ctypes.c_double)]
+
+
+class m1_grid3(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32), ("pad_", ctypes.c_int32),
+                ("hx", ctypes.c_double), ("hy", ctypes.c_double), ("hz", ctypes.c_double), ("dt", ctypes.c_double),
+                ("c", ctypes.c_double), ("a_r", ctypes.c_double), ("c_v", ctypes.c_double), ("bc", m1_bc3 * 6)]
+
+
+class m1_state3(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_void_p) for n in ("E", "Fx", "Fy", "Fz", "T")]
+
+
 class m1_opacity(ctypes.Structure):
     _fields_ = [("sigma_a", ctypes.c_void_p), ("sigma_s", ctypes.c_void_p)]
 
@@ -129,6 +144,25 @@ def lib():
         L.m1_tune_set.restype = ctypes.c_int
         L.m1_tune_get.argtypes = [ctypes.c_char_p]
         L.m1_tune_get.restype = ctypes.c_int64
+        L.m1_workspace3_bytes.restype = ctypes.c_size_t
+        L.m1_workspace3_bytes.argtypes = [P(m1_grid3), P(m1_params)]
+        L.m1_plan3_create.argtypes = [P(m1_grid3), P(m1_params), P(m1_opacity), vp, ctypes.c_size_t, vp, P(vp)]
+        L.m1_plan3_destroy.argtypes = [vp]
+        L.m1_plan3_levels.restype = ctypes.c_int32
+        L.m1_plan3_levels.argtypes = [vp]
+        L.m1_level3_dims.argtypes = [vp, ctypes.c_int32] + [P(ctypes.c_int32)] * 3
+        L.m1_apply3.argtypes = [vp, ctypes.c_int32, P(m1_state3), P(m1_state3)]
+        L.m1_sweep3.argtypes = [vp, P(m1_state3), P(m1_state3), P(m1_state3)]
+        L.m1_pseudo_step3.argtypes = [vp, ctypes.c_int32, ctypes.c_double, P(m1_state3), P(m1_state3), P(m1_state3)]
+        L.m1_restrict3.argtypes = [vp, ctypes.c_int32, P(m1_state3), P(m1_state3)]
+        L.m1_prolong_project3.argtypes = [vp, ctypes.c_int32, P(m1_state3), P(m1_state3), P(m1_state3),
+                                          P(m1_state3)]
+        L.m1_residual3.argtypes = [vp, P(m1_state3), P(m1_state3), P(ctypes.c_double), P(m1_state3)]
+        L.m1_vcycle3.argtypes = [vp, P(m1_state3), P(m1_state3), ctypes.c_double]
+        L.m1_step3.argtypes = [vp, P(m1_state3), ctypes.c_int32, P(m1_info)]
+        for name in ("m1_plan3_create", "m1_level3_dims", "m1_apply3", "m1_sweep3", "m1_pseudo_step3", "m1_restrict3",
+                     "m1_prolong_project3", "m1_residual3", "m1_vcycle3", "m1_step3"):
+            getattr(L, name).restype = ctypes.c_int
         for name in ("m1_plan_create", "m1_residual", "m1_vcycle", "m1_step", "m1_apply_A", "m1_sweep",
                      "m1_sweeps", "m1_pseudo_step", "m1_restrict", "m1_prolong_project", "m1_sync", "m1_level_dims",
                      "m1_engine_create", "m1_batch_submit", "m1_batch_run", "m1_batch_poll", "m1_batch_wait",
@@ -470,3 +504,117 @@ class Engine:
 def to_device(a: np.ndarray, device="cuda"):
     import torch
     return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).to(device)
+
+
+# ---------------------------------------------------------------------------- three dimensions
+def make_grid3(problem: dict) -> m1_grid3:
+    g = m1_grid3()
+    for k in ("nx", "ny", "nz", "hx", "hy", "hz", "dt", "c", "a_r", "c_v"):
+        setattr(g, k, problem[k])
+    for s, bc in enumerate(problem["bc"]):
+        g.bc[s].kind = BC[bc["kind"]]
+        g.bc[s].E = bc.get("E", 0.0)
+        g.bc[s].Fx = bc.get("Fx", 0.0)
+        g.bc[s].Fy = bc.get("Fy", 0.0)
+        g.bc[s].Fz = bc.get("Fz", 0.0)
+    return g
+
+
+class Plan3:
+    """A 3-D solver plan (m1_plan3_*): states are (5, nz, ny, nx) float64 tensors holding E, Fx, Fy, Fz, T."""
+
+    def __init__(self, problem: dict, sigma, params: dict | None = None, stream=None):
+        import torch
+        self.torch = torch
+        self.problem = problem
+        self.grid = make_grid3(problem)
+        self.params = make_params(default_params(**(params or {})))
+        L = lib()
+        self.sigma = sigma.contiguous()
+        assert self.sigma.dtype == torch.float64 and self.sigma.is_cuda
+        assert tuple(self.sigma.shape) == (2, problem["nz"], problem["ny"], problem["nx"])
+        nbytes = L.m1_workspace3_bytes(ctypes.byref(self.grid), ctypes.byref(self.params))
+        if nbytes == 0:
+            raise M1Error(1, "m1_workspace3_bytes")
+        self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.sigma.device)
+        base = self.workspace.data_ptr()
+        self.ws_ptr, self.ws_bytes = base + (-base) % 256, nbytes
+        op = m1_opacity(self.sigma[0].data_ptr(), self.sigma[1].data_ptr())
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.sigma.device)
+        h = ctypes.c_void_p()
+        _check(L.m1_plan3_create(ctypes.byref(self.grid), ctypes.byref(self.params), ctypes.byref(op),
+                                 ctypes.c_void_p(self.ws_ptr), self.ws_bytes, ctypes.c_void_p(self.stream.cuda_stream),
+                                 ctypes.byref(h)), "m1_plan3_create")
+        self.handle = h
+        self.levels = L.m1_plan3_levels(h)
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and _lib is not None:
+            _lib.m1_plan3_destroy(h)
+            self.handle = None
+
+    def level_dims(self, level: int):
+        d = [ctypes.c_int32() for _ in range(3)]
+        _check(lib().m1_level3_dims(self.handle, level, *[ctypes.byref(x) for x in d]), "m1_level3_dims")
+        return tuple(x.value for x in d)
+
+    def new_state(self, level: int = 0):
+        nx, ny, nz = self.level_dims(level)
+        return self.torch.zeros((5, nz, ny, nx), dtype=self.torch.float64, device=self.sigma.device)
+
+    def _st(self, t) -> m1_state3:
+        assert t.dtype == self.torch.float64 and t.is_cuda and t.is_contiguous() and t.shape[0] == 5
+        return m1_state3(*[t[q].data_ptr() for q in range(5)])
+
+    def step(self, v, nsteps: int = 1) -> dict:
+        info = m1_info()
+        st = lib().m1_step3(self.handle, ctypes.byref(self._st(v)), nsteps, ctypes.byref(info))
+        out = _info_dict(info)
+        out["status"] = st
+        out["first_bad_cell"] = info.first_bad_cell
+        if st not in (0, 3):
+            raise M1Error(st, f"m1_step3 {out}")
+        return out
+
+    def vcycle(self, v, vn, dtau: float):
+        _check(lib().m1_vcycle3(self.handle, ctypes.byref(self._st(v)), ctypes.byref(self._st(vn)), dtau),
+               "m1_vcycle3")
+
+    def residual(self, v, vn, want_r: bool = False):
+        r = self.torch.zeros_like(v) if want_r else None
+        norm = ctypes.c_double()
+        _check(lib().m1_residual3(self.handle, ctypes.byref(self._st(v)), ctypes.byref(self._st(vn)),
+                                  ctypes.byref(norm), ctypes.byref(self._st(r)) if want_r else None), "m1_residual3")
+        return (norm.value, r) if want_r else norm.value
+
+    def apply_A(self, level: int, v):
+        out = self.new_state(level)
+        _check(lib().m1_apply3(self.handle, level, ctypes.byref(self._st(v)), ctypes.byref(self._st(out))),
+               "m1_apply3")
+        return out
+
+    def sweep(self, b, v):
+        out = self.torch.zeros_like(v)
+        _check(lib().m1_sweep3(self.handle, ctypes.byref(self._st(b)), ctypes.byref(self._st(v)),
+                               ctypes.byref(self._st(out))), "m1_sweep3")
+        return out
+
+    def pseudo_step(self, level: int, dtau: float, f, u):
+        out = self.new_state(level)
+        _check(lib().m1_pseudo_step3(self.handle, level, dtau, ctypes.byref(self._st(f)), ctypes.byref(self._st(u)),
+                                     ctypes.byref(self._st(out))), "m1_pseudo_step3")
+        return out
+
+    def restrict(self, level: int, x):
+        out = self.new_state(level + 1)
+        _check(lib().m1_restrict3(self.handle, level, ctypes.byref(self._st(x)), ctypes.byref(self._st(out))),
+               "m1_restrict3")
+        return out
+
+    def prolong_project(self, level: int, u, uc, vc, out=None):
+        out = self.torch.zeros_like(u) if out is None else out
+        _check(lib().m1_prolong_project3(self.handle, level, ctypes.byref(self._st(u)), ctypes.byref(self._st(uc)),
+                                         ctypes.byref(self._st(vc)), ctypes.byref(self._st(out))),
+               "m1_prolong_project3")
+        return out

@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT_DIR = os.path.join(HERE, "_lib")
 LIB = os.path.join(OUT_DIR, "libm1mg.so")
-SOURCES = ["m1_kernels.hip", "m1_mixed.hip", "m1_transfer.hip", "m1_capi.hip"]
+SOURCES = ["m1_kernels.hip", "m1_mixed.hip", "m1_transfer.hip", "m1_kernels3.hip", "m1_capi.hip", "m1_capi3.hip"]
 ARCH = os.environ.get("M1_OFFLOAD_ARCH", "gfx950")
 
 FLAGS = [

@@ -126,3 +126,37 @@ def test_autotuner_builtin_values_match_the_library():
         if os.environ.get(binding.TUNE_ENV[key]) is None:
             assert binding.tune_get(key) == val, key
     assert set(autotune.BUILTIN) == set(binding.TUNE_ENV) == set(autotune.CANDIDATES)
+
+
+def test_workspace3_size_and_host_validation():
+    """The 3-D plans' host checks: workspace bytes of the level hierarchy, and 0 for the grids and parameter
+    choices they reject (nothing is enqueued)."""
+    L = binding.lib()
+    prob, _, _, _ = inputs.hot_wall_3d(n=64)
+    g = binding.make_grid3(prob)
+    p = binding.make_params(binding.default_params())
+    nbytes = L.m1_workspace3_bytes(ctypes.byref(g), ctypes.byref(p))
+    # finest: b, tmp, residual (15 fields); coarse levels (1/7 of the cells): 27 fields
+    assert 15 * 8 * 64 ** 3 < nbytes < 20 * 8 * 64 ** 3
+    pl = binding.make_params(binding.default_params(levels=4))  # 64 -> 32 -> 16 -> 8
+    assert 0 < L.m1_workspace3_bytes(ctypes.byref(g), ctypes.byref(pl)) < nbytes
+    pl = binding.make_params(binding.default_params(levels=5))  # side 4 is the coarsest level: 64 .. 4 is 5 levels
+    assert L.m1_workspace3_bytes(ctypes.byref(g), ctypes.byref(pl)) == nbytes
+    pl = binding.make_params(binding.default_params(levels=6))
+    assert L.m1_workspace3_bytes(ctypes.byref(g), ctypes.byref(pl)) == 0
+    for extra in (dict(precision="mixed"), dict(cycle="W"), dict(transfer="mean"), dict(nu_l=2),
+                  dict(smoother="rbgs"), dict(omega=1.5)):
+        q = binding.make_params(binding.default_params(**extra))
+        assert L.m1_workspace3_bytes(ctypes.byref(g), ctypes.byref(q)) == 0, extra
+    bad = binding.make_grid3(prob)
+    bad.bc[4].kind = 0  # periodic on one z side only
+    assert L.m1_workspace3_bytes(ctypes.byref(bad), ctypes.byref(p)) == 0
+    bad = binding.make_grid3(prob)
+    bad.bc[2].kind = 4  # inflow sides are 2-D only
+    assert L.m1_workspace3_bytes(ctypes.byref(bad), ctypes.byref(p)) == 0
+    bad = binding.make_grid3(prob)
+    bad.bc[0].Fx = 2.0 * bad.c * bad.bc[0].E  # a non-admissible wall state
+    assert L.m1_workspace3_bytes(ctypes.byref(bad), ctypes.byref(p)) == 0
+    bad = binding.make_grid3(prob)
+    bad.hz = 0.0
+    assert L.m1_workspace3_bytes(ctypes.byref(bad), ctypes.byref(p)) == 0
