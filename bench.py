@@ -32,6 +32,8 @@ The same JSON line also carries:
   profiles/, and are null when the kernel sources have changed since they were taken.
 - c1 / c3: the 1-D Gaussian (N = 256, rtol 1e-10) and the 4096^2 lognormal single solve in
   mixed precision (rtol 1e-8; with the FP64 solve of the same step beside it).
+- three_d: the hot wall in 3-D (256^3 cells, 10 implicit steps to 1e-8, FP64) through the 3-D plans, and
+  the roofline of their finest-level sweep kernel at 136 algorithmic bytes per cell.
 - cpu_baseline: the FP64 CPU oracle on the host cores, over a bounded sample of V-cycles
   of the same workload.
 - batched: 256 independent problems of uneven size, seeded 1000+k, side log-uniform in
@@ -346,6 +348,46 @@ def c3_leg(torch):
     return out
 
 
+SWEEP3_BYTES_PER_CELL = 136  # 3-D sweep: u (E, F, T) 40 + b 40 + sigma 16 read, u' 40 written
+
+
+def three_d_leg(torch, reps):
+    """The hot wall in 3-D (256^3 cells, 10 implicit steps to 1e-8, FP64, the deepest hierarchy), one timed
+    solve after a one-step warm-up, and the finest-level sweep kernel (m1_sweep3) timed with HIP events."""
+    prob, v0, sig, run = inputs.hot_wall_3d(n=256)
+    cells = prob["nx"] * prob["ny"] * prob["nz"]
+    sd, vd = binding.to_device(sig), binding.to_device(v0)
+    plan = binding.Plan3(prob, sd, dict(rtol=run["rtol"], max_cycles=20000, **SOLVER))
+    v = vd.clone()
+    plan.step(v, 1)
+    v.copy_(vd)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    info = plan.step(v, run["steps"])
+    torch.cuda.synchronize()
+    t = time.perf_counter() - t0
+    L = binding.lib()
+    b = vd.clone()
+    b[4] *= prob["c_v"]
+    bufs, k = [vd.clone(), vd.clone()], [0]
+
+    def launch():
+        binding._check(L.m1_sweep3(plan.handle, binding.ctypes.byref(plan._st(b)),
+                                   binding.ctypes.byref(plan._st(bufs[k[0]])),
+                                   binding.ctypes.byref(plan._st(bufs[1 - k[0]]))), "m1_sweep3")
+        k[0] ^= 1
+    tk = time_launches(torch, plan.stream, launch, reps)
+    kname = "k3_staged<1>" if binding.tune_get("stage3") >= 1 else "k3_relax"
+    out = {"workload": "hot wall 3-D 256^3, 10 implicit steps, dt=100h/c, 8^3 opacity blocks, FP64, rtol 1e-8",
+           "Mcell_updates_per_s": round(cells * run["steps"] / t / 1e6, 2), "time_to_rtol_ms": round(t * 1e3, 1),
+           "cycles": info["cycles"], "levels": info["levels"], "status": info["status"],
+           "roofline": roofline_entry(kname, "finest-level FP64 Jacobi sweep, 3-D", SWEEP3_BYTES_PER_CELL * cells, tk,
+                                      None, "256x256x256", "HBM (2.3 GB working set)")}
+    del plan, v, b, bufs
+    torch.cuda.empty_cache()
+    return out
+
+
 # ---------------------------------------------------------------------------
 # batched leg: many problems of uneven size
 # ---------------------------------------------------------------------------
@@ -593,6 +635,7 @@ def main():
     if args.workload == "hotwall" and not args.no_extras:
         c1 = c1_leg(torch)
         out["c3"] = c3_leg(torch)
+        out["three_d"] = three_d_leg(torch, args.reps)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(prob, v0, sig, run, cycles / run["steps"], args.cpu_cycles, levels, c1)
     if c1 is not None:

@@ -46,6 +46,20 @@ void launch3_relax(hipStream_t st, const Phys3& ph, const Lvl3& L, CSoa3 b, doub
 // sweep; reach = 1 - (1 - eta)^K; dtau from dtau_dev when not null.
 void launch3_pseudo(hipStream_t st, const Phys3& ph, const Lvl3& L, CSoa3 f, CSoa3 in, Soa3 out, double dtau,
                     const double* dtau_dev, double reach, int local, const int* active);
+// The same three operations staged (2.5-D blocking: closures of a 64 x 4 tile and its ring once per z-plane
+// in LDS), bitwise equal to the one-cell forms above; the apply form without the norm partials.  Launch
+// shape "stage3": 0 one-cell kernels only, 1 (default) staged finest-level sweeps, 2 every staged form; levels
+// narrower than kStage3MinNx keep the one-cell kernels (most of a 64-wide tile would idle).
+constexpr int kStage3MinNx = 32;
+bool stage3_fits(const Lvl3& L, bool sweep);
+void set_stage3(int mode);
+int stage3();
+void launch3_apply_staged(hipStream_t st, const Phys3& ph, const Lvl3& L, CSoa3 v, CSoa3 x, double sgn, Soa3 out,
+                          const int* active);
+void launch3_relax_staged(hipStream_t st, const Phys3& ph, const Lvl3& L, CSoa3 b, double omega, CSoa3 in,
+                          Soa3 out, const int* active);
+void launch3_pseudo_staged(hipStream_t st, const Phys3& ph, const Lvl3& L, CSoa3 f, CSoa3 in, Soa3 out,
+                           double dtau, const double* dtau_dev, double reach, int local, const int* active);
 // Full weighting R = 2^-3 P^T of the fields in F from a fine nxf x nyf x nzf level.
 void launch3_restrict(hipStream_t st, int nxf, int nyf, int nzf, int px, int py, int pz, const Fields& F,
                       const int* active);

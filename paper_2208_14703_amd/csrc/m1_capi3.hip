@@ -184,10 +184,36 @@ Gate3 fixed_gate3(m1_plan3& P, double dtau)
     return Gate3{dtau, &P.dfix->dtau, &P.dfix->active};
 }
 
+// The three stencil operations, staged where the level is wide enough (bitwise the one-cell forms).
+void relax3(m1_plan3& P, const m1::CSoa3& b, const m1::CSoa3& in, const m1::Soa3& out, const int* active)
+{
+    const m1::Lvl3& L = P.lev[0].L;
+    if (m1::stage3_fits(L, true)) m1::launch3_relax_staged(P.st, P.ph, L, b, P.params.omega, in, out, active);
+    else m1::launch3_relax(P.st, P.ph, L, b, P.params.omega, in, out, active);
+}
+
+void apply3(m1_plan3& P, int l, const m1::CSoa3& v, const m1::CSoa3& x, double sgn, const m1::Soa3& out,
+            const int* active)
+{
+    const m1::Lvl3& L = P.lev[l].L;
+    if (m1::stage3_fits(L, false)) m1::launch3_apply_staged(P.st, P.ph, L, v, x, sgn, out, active);
+    else m1::launch3_apply(P.st, P.ph, L, v, x, sgn, out, nullptr, active);
+}
+
+void pseudo3(m1_plan3& P, int l, const m1::CSoa3& f, const m1::CSoa3& in, const m1::Soa3& out, double dtau,
+             const double* dtau_dev, const int* active)
+{
+    const m1::Lvl3& L = P.lev[l].L;
+    if (m1::stage3_fits(L, false))
+        m1::launch3_pseudo_staged(P.st, P.ph, L, f, in, out, dtau, dtau_dev, P.reach, P.params.pseudo_local, active);
+    else
+        m1::launch3_pseudo(P.st, P.ph, L, f, in, out, dtau, dtau_dev, P.reach, P.params.pseudo_local, active);
+}
+
 void sweeps3(m1_plan3& P, m1::Soa3& cur, m1::Soa3& other, int nu, const Gate3& G)
 {
     for (int s = 0; s < nu; ++s) {
-        m1::launch3_relax(P.st, P.ph, P.lev[0].L, m1::cs3(P.b), P.params.omega, m1::cs3(cur), other, G.active);
+        relax3(P, m1::cs3(P.b), m1::cs3(cur), other, G.active);
         std::swap(cur, other);
     }
 }
@@ -199,8 +225,7 @@ m1::Soa3 smooth3(m1_plan3& P, int l, const Gate3& G, m1::Soa3 start)
     m1::Soa3 in = start;
     for (int m = 0; m < P.params.pseudo_steps; ++m) {
         const m1::Soa3 out = same3(in, c.u) ? c.u2 : c.u;
-        m1::launch3_pseudo(P.st, P.ph, c.L, m1::cs3(c.f), m1::cs3(in), out, G.dtau, G.dtau_dev, P.reach,
-                           P.params.pseudo_local, G.active);
+        pseudo3(P, l, m1::cs3(c.f), m1::cs3(in), out, G.dtau, G.dtau_dev, G.active);
         in = out;
     }
     return in;
@@ -238,16 +263,16 @@ void vcycle3(m1_plan3& P, m1::Soa3& cur, m1::Soa3& other, const Gate3& G)
     if (P.L == 1) return;
     m1::Soa3 ul[kMaxLevels3];
     ul[0] = cur;
-    m1::launch3_apply(P.st, P.ph, P.lev[0].L, m1::cs3(cur), m1::cs3(P.b), -1.0, P.rfine, nullptr, G.active);
+    apply3(P, 0, m1::cs3(cur), m1::cs3(P.b), -1.0, P.rfine, G.active);
     m1::Soa3 rprev = P.rfine;
     for (int l = 1; l < P.L; ++l) {
         Level3& c = P.lev[l];
         const Level3& f = P.lev[l - 1];
         m1::launch3_restrict(P.st, f.nx, f.ny, f.nz, P.px, P.py, P.pz, fields3(ul[l - 1], rprev, c.v, c.rb), G.active);
-        m1::launch3_apply(P.st, P.ph, c.L, m1::cs3(c.v), m1::cs3(c.rb), 1.0, c.f, nullptr, G.active);
+        apply3(P, l, m1::cs3(c.v), m1::cs3(c.rb), 1.0, c.f, G.active);
         ul[l] = smooth3(P, l, G, c.v);
         if (l < P.L - 1) {
-            m1::launch3_apply(P.st, P.ph, c.L, m1::cs3(ul[l]), m1::cs3(c.f), -1.0, c.rb, nullptr, G.active);
+            apply3(P, l, m1::cs3(ul[l]), m1::cs3(c.f), -1.0, c.rb, G.active);
             rprev = c.rb;
         }
     }
@@ -407,16 +432,14 @@ m1_status m1_level3_dims(const m1_plan3* P, int32_t level, int32_t* nx, int32_t*
 m1_status m1_apply3(m1_plan3* P, int32_t level, const m1_state3* v, m1_state3* out)
 {
     if (!level_ok(P, level) || !valid_state3(v) || !valid_state3(out)) return M1_ERR_ARG;
-    m1::launch3_apply(P->st, P->ph, P->lev[level].L, m1::cs3(soa3(v)), m1::CSoa3{}, 1.0, soa3(out), nullptr,
-                      &P->dfix->active);
+    apply3(*P, level, m1::cs3(soa3(v)), m1::CSoa3{}, 1.0, soa3(out), &P->dfix->active);
     return status_of(hipGetLastError());
 }
 
 m1_status m1_sweep3(m1_plan3* P, const m1_state3* b, const m1_state3* v_in, m1_state3* v_out)
 {
     if (!P || !valid_state3(b) || !valid_state3(v_in) || !valid_state3(v_out) || v_in->E == v_out->E) return M1_ERR_ARG;
-    m1::launch3_relax(P->st, P->ph, P->lev[0].L, m1::cs3(soa3(b)), P->params.omega, m1::cs3(soa3(v_in)), soa3(v_out),
-                      &P->dfix->active);
+    relax3(*P, m1::cs3(soa3(b)), m1::cs3(soa3(v_in)), soa3(v_out), &P->dfix->active);
     return status_of(hipGetLastError());
 }
 
@@ -427,8 +450,7 @@ m1_status m1_pseudo_step3(m1_plan3* P, int32_t level, double dtau, const m1_stat
         u_in->E == u_out->E)
         return M1_ERR_ARG;
     const Gate3 G = fixed_gate3(*P, dtau);
-    m1::launch3_pseudo(P->st, P->ph, P->lev[level].L, m1::cs3(soa3(f)), m1::cs3(soa3(u_in)), soa3(u_out), dtau,
-                       G.dtau_dev, P->reach, P->params.pseudo_local, G.active);
+    pseudo3(*P, level, m1::cs3(soa3(f)), m1::cs3(soa3(u_in)), soa3(u_out), dtau, G.dtau_dev, G.active);
     return status_of(hipGetLastError());
 }
 

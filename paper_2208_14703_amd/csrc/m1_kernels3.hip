@@ -12,6 +12,8 @@
 #include "m1_3d.hpp"
 #include "m1_cells.hpp"
 
+#include <atomic>
+
 namespace m1 {
 
 namespace {
@@ -104,31 +106,53 @@ __device__ __forceinline__ void nb3(const Phys3& ph, const Lvl3& L, const CSoa3&
     }
 }
 
-// Sum of the six off-diagonal operators of row k: x-, x+, y-, y+, z-, z+ (lower neighbour: L = k (cU + G),
-// upper: R = k (cU - G)), with c^2 P_ab = iso delta_ab + 3 r F_a F_b from the closure of the 2-D kernels.
+// The closure of one state as the directional fluxes use it: c^2 P_ab = iso delta_ab + r3 F_a F_b (the
+// arrangement of the 2-D kernels' closure).
+struct Rec3 {
+    double E, F[3], iso, r3;
+};
+
+__device__ __forceinline__ Rec3 rec3(const Phys3& ph, double E, double Fx, double Fy, double Fz)
+{
+    Rec3 R;
+    R.E = E;
+    R.F[0] = Fx;
+    R.F[1] = Fy;
+    R.F[2] = Fz;
+    const double F2 = fma(Fx, Fx, fma(Fy, Fy, Fz * Fz));
+    const double c2E2 = ph.c2 * E * E;
+    const double root = sqrt_nr(fmax(fma(4.0, c2E2, -3.0 * F2), c2E2));
+    const double r = ph.c * rcp_nr(fma(2.0 * ph.c, E, root));
+    R.iso = fma(-F2, r, ph.c2 * E * (1.0 / 3.0));
+    R.r3 = 3.0 * r;
+    return R;
+}
+
+// Add a neighbour's operator along `axis`: sgn = +1 for the lower neighbour (L = kk (cU + G)), -1 for the
+// upper one (R = kk (cU - G)), G = (F_axis, c^2 P[., axis]).
+__device__ __forceinline__ void add3(const Phys3& ph, double kk, double sgn, int axis, const Rec3& R, double S[4])
+{
+    const double Fa = R.F[axis];
+    S[0] = fma(kk, fma(sgn, Fa, ph.c * R.E), S[0]);
+#pragma unroll
+    for (int m = 0; m < 3; ++m) {
+        const double G = fma(R.r3 * R.F[m], Fa, m == axis ? R.iso : 0.0);
+        S[1 + m] = fma(kk, fma(sgn, G, ph.c * R.F[m]), S[1 + m]);
+    }
+}
+
+// Sum of the six off-diagonal operators of row k in the order x-, x+, y-, y+, z-, z+.
 __device__ __forceinline__ void offdiag3(const Phys3& ph, const Lvl3& L, const CSoa3& v, int i, int j, int l,
                                          uint32_t k, double S[4])
 {
     S[0] = S[1] = S[2] = S[3] = 0.0;
 #pragma unroll
     for (int dir = 0; dir < 6; ++dir) {
-        double E, F[3];
-        nb3(ph, L, v, i, j, l, k, dir, E, F[0], F[1], F[2]);
+        double E, Fx, Fy, Fz;
+        nb3(ph, L, v, i, j, l, k, dir, E, Fx, Fy, Fz);
         const int axis = dir >> 1;
-        const double sgn = (dir & 1) ? -1.0 : 1.0;
-        const double kk = axis == 0 ? L.kx : (axis == 1 ? L.ky : L.kz);
-        const double F2 = fma(F[0], F[0], fma(F[1], F[1], F[2] * F[2]));
-        const double c2E2 = ph.c2 * E * E;
-        const double root = sqrt_nr(fmax(fma(4.0, c2E2, -3.0 * F2), c2E2));
-        const double r = ph.c * rcp_nr(fma(2.0 * ph.c, E, root));
-        const double iso = fma(-F2, r, ph.c2 * E * (1.0 / 3.0)), r3 = 3.0 * r;
-        const double Fa = F[axis];
-        S[0] = fma(kk, fma(sgn, Fa, ph.c * E), S[0]);
-#pragma unroll
-        for (int m = 0; m < 3; ++m) {
-            const double G = fma(r3 * F[m], Fa, m == axis ? iso : 0.0);
-            S[1 + m] = fma(kk, fma(sgn, G, ph.c * F[m]), S[1 + m]);
-        }
+        add3(ph, axis == 0 ? L.kx : (axis == 1 ? L.ky : L.kz), (dir & 1) ? -1.0 : 1.0, axis,
+             rec3(ph, E, Fx, Fy, Fz), S);
     }
 }
 
@@ -141,6 +165,80 @@ __device__ __forceinline__ void local_solve3(double beta, double g, double a, do
     Fz = BFz * rcp_nr(fma(g, ks, fma(g, a + ka, beta)));
 }
 
+// ---- per-cell ends of the three operations, from the cell's state u and its off-diagonal sum S ----------
+// x + sgn A(u) (x.E null: sgn A(u)) into o; returns r_E^2 + |r_F/c|^2 + r_T^2 of o.
+__device__ __forceinline__ double fin_apply(const Phys3& ph, const Lvl3& L, const double u[5], const double S[4],
+                                            const CSoa3& x, double sgn, uint32_t k, double o[5])
+{
+    const double ka = L.cdt * ld(L.sa, k), ks = L.cdt * ld(L.ss, k);
+    const double T2 = u[4] * u[4];
+    const double ex = ka * fma(-ph.a_r * T2, T2, u[0]);  // ka (E - a_r T^4)
+    const double dF = L.a + ka + ks;
+    o[0] = sgn * (fma(L.a, u[0], ex) - S[0]);
+    o[1] = sgn * fma(dF, u[1], -S[1]);
+    o[2] = sgn * fma(dF, u[2], -S[2]);
+    o[3] = sgn * fma(dF, u[3], -S[3]);
+    o[4] = sgn * fma(ph.c_v, u[4], -ex);
+    if (x.E) {
+        o[0] += ld(x.E, k);
+        o[1] += ld(x.Fx, k);
+        o[2] += ld(x.Fy, k);
+        o[3] += ld(x.Fz, k);
+        o[4] += ld(x.T, k);
+    }
+    const double ic = 1.0 / ph.c;
+    const double a = o[1] * ic, b = o[2] * ic, c = o[3] * ic;
+    return fma(o[0], o[0], fma(a, a, fma(b, b, fma(c, c, o[4] * o[4]))));
+}
+
+// Relaxed Jacobi update of A(u) = b: u + omega (local_solve(b + S) - u).
+__device__ __forceinline__ void fin_relax(const Phys3& ph, const Lvl3& L, const double u[5], const double S[4],
+                                          const CSoa3& b, double omega, uint32_t k, double o[5])
+{
+    const double ka = L.cdt * ld(L.sa, k), ks = L.cdt * ld(L.ss, k);
+    local_solve3(0.0, 1.0, L.a, ka, ks, ph.c_v, ph.a_r, ld(b.E, k) + S[0], ld(b.Fx, k) + S[1], ld(b.Fy, k) + S[2],
+                 ld(b.Fz, k) + S[3], ld(b.T, k), u[4], o[0], o[1], o[2], o[3], o[4]);
+    if (omega != 1.0) {
+#pragma unroll
+        for (int q = 0; q < 5; ++q) o[q] = fma(omega, o[q] - u[q], u[q]);
+    }
+}
+
+// Pseudo-time step: s = M^{-1} f; tau_i = min(dtau, tau*(u, s) reach) (the pseudo time the explicit sub-steps
+// reach); u~ = u + tau_i s; one Jacobi sweep of (M + g A)(u) = M u~ from u, g = tau_i (local) or dtau.
+__device__ __forceinline__ void fin_pseudo(const Phys3& ph, const Lvl3& L, const double u[5], const double S[4],
+                                           const CSoa3& f, double dtau, double reach, int local, uint32_t k,
+                                           double o[5])
+{
+    const double ka = L.cdt * ld(L.sa, k), ks = L.cdt * ld(L.ss, k);
+    const double sE = ld(f.E, k), sFx = ld(f.Fx, k), sFy = ld(f.Fy, k), sFz = ld(f.Fz, k);
+    const double sT = ld(f.T, k) * rcp_nr(ph.c_v);
+    const double ts = ray3(ph.c2, u[0], u[1], u[2], u[3], u[4], sE, sFx, sFy, sFz, sT);
+    const double tau = fmin(dtau, ts * reach);
+    const double g = local ? tau : dtau;
+    local_solve3(1.0, g, L.a, ka, ks, ph.c_v, ph.a_r, fma(g, S[0], fma(tau, sE, u[0])),
+                 fma(g, S[1], fma(tau, sFx, u[1])), fma(g, S[2], fma(tau, sFy, u[2])),
+                 fma(g, S[3], fma(tau, sFz, u[3])), ph.c_v * fma(tau, sT, u[4]), u[4], o[0], o[1], o[2], o[3], o[4]);
+}
+
+__device__ __forceinline__ void st5(const Soa3& out, uint32_t k, const double o[5])
+{
+    st(out.E, k, o[0]);
+    st(out.Fx, k, o[1]);
+    st(out.Fy, k, o[2]);
+    st(out.Fz, k, o[3]);
+    st(out.T, k, o[4]);
+}
+
+__device__ __forceinline__ void load5(const CSoa3& v, uint32_t k, double u[5])
+{
+    u[0] = ld(v.E, k);
+    u[1] = ld(v.Fx, k);
+    u[2] = ld(v.Fy, k);
+    u[3] = ld(v.Fz, k);
+    u[4] = ld(v.T, k);
+}
+
 }  // namespace
 
 __global__ __launch_bounds__(kB3) void k3_apply(Phys3 ph, Lvl3 L, CSoa3 v, CSoa3 x, double sgn, Soa3 out,
@@ -151,37 +249,11 @@ __global__ __launch_bounds__(kB3) void k3_apply(Phys3 ph, Lvl3 L, CSoa3 v, CSoa3
     int i, j, l;
     double q = 0.0;
     if (cell3(L, k, i, j, l)) {
-        double S[4];
+        double S[4], u[5], o[5];
         offdiag3(ph, L, v, i, j, l, k, S);
-        const double E = ld(v.E, k), Fx = ld(v.Fx, k), Fy = ld(v.Fy, k), Fz = ld(v.Fz, k), T = ld(v.T, k);
-        const double ka = L.cdt * ld(L.sa, k), ks = L.cdt * ld(L.ss, k);
-        const double T2 = T * T;
-        const double ex = ka * fma(-ph.a_r * T2, T2, E);  // ka (E - a_r T^4)
-        const double dF = L.a + ka + ks;
-        double rE = sgn * (fma(L.a, E, ex) - S[0]);
-        double rFx = sgn * fma(dF, Fx, -S[1]);
-        double rFy = sgn * fma(dF, Fy, -S[2]);
-        double rFz = sgn * fma(dF, Fz, -S[3]);
-        double rT = sgn * fma(ph.c_v, T, -ex);
-        if (x.E) {
-            rE += ld(x.E, k);
-            rFx += ld(x.Fx, k);
-            rFy += ld(x.Fy, k);
-            rFz += ld(x.Fz, k);
-            rT += ld(x.T, k);
-        }
-        if (partials) {
-            const double ic = 1.0 / ph.c;
-            const double a = rFx * ic, b = rFy * ic, c = rFz * ic;
-            q = fma(rE, rE, fma(a, a, fma(b, b, fma(c, c, rT * rT))));
-        }
-        if (live && out.E) {
-            st(out.E, k, rE);
-            st(out.Fx, k, rFx);
-            st(out.Fy, k, rFy);
-            st(out.Fz, k, rFz);
-            st(out.T, k, rT);
-        }
+        load5(v, k, u);
+        q = fin_apply(ph, L, u, S, x, sgn, k, o);
+        if (live && out.E) st5(out, k, o);
     }
     if (partials) block_partial(q, partials + blockIdx.x);
 }
@@ -193,30 +265,13 @@ __global__ __launch_bounds__(kB3) void k3_relax(Phys3 ph, Lvl3 L, CSoa3 b, doubl
     uint32_t k;
     int i, j, l;
     if (!cell3(L, k, i, j, l)) return;
-    double S[4];
+    double S[4], uc[5], o[5];
     offdiag3(ph, L, u, i, j, l, k, S);
-    const double ka = L.cdt * ld(L.sa, k), ks = L.cdt * ld(L.ss, k);
-    const double uE = ld(u.E, k), uFx = ld(u.Fx, k), uFy = ld(u.Fy, k), uFz = ld(u.Fz, k), uT = ld(u.T, k);
-    double E, Fx, Fy, Fz, T;
-    local_solve3(0.0, 1.0, L.a, ka, ks, ph.c_v, ph.a_r, ld(b.E, k) + S[0], ld(b.Fx, k) + S[1], ld(b.Fy, k) + S[2],
-                 ld(b.Fz, k) + S[3], ld(b.T, k), uT, E, Fx, Fy, Fz, T);
-    if (omega != 1.0) {
-        E = fma(omega, E - uE, uE);
-        Fx = fma(omega, Fx - uFx, uFx);
-        Fy = fma(omega, Fy - uFy, uFy);
-        Fz = fma(omega, Fz - uFz, uFz);
-        T = fma(omega, T - uT, uT);
-    }
-    if (!live) return;
-    st(out.E, k, E);
-    st(out.Fx, k, Fx);
-    st(out.Fy, k, Fy);
-    st(out.Fz, k, Fz);
-    st(out.T, k, T);
+    load5(u, k, uc);
+    fin_relax(ph, L, uc, S, b, omega, k, o);
+    if (live) st5(out, k, o);
 }
 
-// Pseudo-time step: s = M^{-1} f; tau_i = min(dtau, tau*(u, s) reach) (the pseudo time the explicit sub-steps
-// reach); u~ = u + tau_i s; one Jacobi sweep of (M + g A)(u) = M u~ from u, g = tau_i (local) or dtau.
 __global__ __launch_bounds__(kB3) void k3_pseudo(Phys3 ph, Lvl3 L, CSoa3 f, CSoa3 u, Soa3 out, double dtau_h,
                                                  const double* __restrict__ dtau_dev, double reach, int local,
                                                  const int* __restrict__ active)
@@ -226,25 +281,158 @@ __global__ __launch_bounds__(kB3) void k3_pseudo(Phys3 ph, Lvl3 L, CSoa3 f, CSoa
     uint32_t k;
     int i, j, l;
     if (!cell3(L, k, i, j, l)) return;
-    double S[4];
+    double S[4], uc[5], o[5];
     offdiag3(ph, L, u, i, j, l, k, S);
-    const double ka = L.cdt * ld(L.sa, k), ks = L.cdt * ld(L.ss, k);
-    const double uE = ld(u.E, k), uFx = ld(u.Fx, k), uFy = ld(u.Fy, k), uFz = ld(u.Fz, k), uT = ld(u.T, k);
-    const double sE = ld(f.E, k), sFx = ld(f.Fx, k), sFy = ld(f.Fy, k), sFz = ld(f.Fz, k);
-    const double sT = ld(f.T, k) * rcp_nr(ph.c_v);
-    const double ts = ray3(ph.c2, uE, uFx, uFy, uFz, uT, sE, sFx, sFy, sFz, sT);
-    const double tau = fmin(dtau, ts * reach);
-    const double g = local ? tau : dtau;
-    double E, Fx, Fy, Fz, T;
-    local_solve3(1.0, g, L.a, ka, ks, ph.c_v, ph.a_r, fma(g, S[0], fma(tau, sE, uE)), fma(g, S[1], fma(tau, sFx, uFx)),
-                 fma(g, S[2], fma(tau, sFy, uFy)), fma(g, S[3], fma(tau, sFz, uFz)), ph.c_v * fma(tau, sT, uT), uT, E,
-                 Fx, Fy, Fz, T);
-    if (!live) return;
-    st(out.E, k, E);
-    st(out.Fx, k, Fx);
-    st(out.Fy, k, Fy);
-    st(out.Fz, k, Fz);
-    st(out.T, k, T);
+    load5(u, k, uc);
+    fin_pseudo(ph, L, uc, S, f, dtau, reach, local, k, o);
+    if (live) st5(out, k, o);
+}
+
+// ---- the same three operations staged: 2.5-D blocking ---------------------------------------------------
+// A block owns a 64 x 4 column of cells in x-y and marches through kSZ z-planes.  For each plane the
+// closures of the tile and of its one-cell ring (with the ghost rules at the sides) are evaluated once into
+// LDS; each thread keeps the closures of its own column's planes below and above in registers.  Every cell's
+// off-diagonal sum then adds the same six terms in the same order as the one-cell kernels, from the same
+// closure values, so the results are bitwise those of k3_apply / k3_relax / k3_pseudo.  About 1.5 closure
+// evaluations per cell instead of 6.
+namespace {
+
+constexpr int kSX = 64, kSY = 4, kSZ = 16, kSW = kSX + 2, kSH = kSY + 2, kSN = kSW * kSH, kRing = kSN - kSX * kSY;
+
+// Closure record of the neighbour position (gx, gy) of plane z: a cell, the ghost beyond an x or y side (by the
+// side's rule, as nb3), or (never read) a placeholder.
+__device__ __forceinline__ Rec3 plane_rec(const Phys3& ph, const Lvl3& L, const CSoa3& v, int gx, int gy, int z)
+{
+    const bool inX = gx >= 0 && gx < L.nx, inY = gy >= 0 && gy < L.ny;
+    int side = -1;
+    if (inX && inY) {
+        const uint32_t k = ((uint32_t)z * (uint32_t)L.ny + (uint32_t)gy) * (uint32_t)L.nx + (uint32_t)gx;
+        return rec3(ph, ld(v.E, k), ld(v.Fx, k), ld(v.Fy, k), ld(v.Fz, k));
+    }
+    if (inY && (gx == -1 || gx == L.nx)) side = gx < 0 ? 0 : 1;
+    else if (inX && (gy == -1 || gy == L.ny)) side = gy < 0 ? 2 : 3;
+    if (side < 0) {
+        Rec3 R{};
+        R.E = 1.0;
+        return R;
+    }
+    const int kind = ph.bc[side];
+    if (kind == BC_DIRICHLET) return rec3(ph, ph.bcE[side], ph.bcFx[side], ph.bcFy[side], ph.bcFz[side]);
+    int sx = gx, sy = gy;
+    if (side < 2) sx = kind == BC_PERIODIC ? (gx < 0 ? L.nx - 1 : 0) : (gx < 0 ? 0 : L.nx - 1);
+    else sy = kind == BC_PERIODIC ? (gy < 0 ? L.ny - 1 : 0) : (gy < 0 ? 0 : L.ny - 1);
+    const uint32_t k = ((uint32_t)z * (uint32_t)L.ny + (uint32_t)sy) * (uint32_t)L.nx + (uint32_t)sx;
+    Rec3 R = rec3(ph, ld(v.E, k), ld(v.Fx, k), ld(v.Fy, k), ld(v.Fz, k));
+    if (kind == BC_REFLECTIVE) {  // the normal component (constant indices: no private array in memory)
+        if (side < 2) R.F[0] = -R.F[0];
+        else R.F[1] = -R.F[1];
+    }
+    return R;
+}
+
+// Closure record of cell (i, j) in plane zz of its own column, or the ghost below z = 0 / above z = nz - 1.
+__device__ __forceinline__ Rec3 column_rec(const Phys3& ph, const Lvl3& L, const CSoa3& v, int i, int j, int zz)
+{
+    int z = zz, kind = -1;
+    if (zz < 0 || zz >= L.nz) {
+        const int side = zz < 0 ? 4 : 5;
+        kind = ph.bc[side];
+        if (kind == BC_DIRICHLET) return rec3(ph, ph.bcE[side], ph.bcFx[side], ph.bcFy[side], ph.bcFz[side]);
+        z = kind == BC_PERIODIC ? (zz < 0 ? L.nz - 1 : 0) : (zz < 0 ? 0 : L.nz - 1);
+    }
+    const uint32_t k = ((uint32_t)z * (uint32_t)L.ny + (uint32_t)j) * (uint32_t)L.nx + (uint32_t)i;
+    Rec3 R = rec3(ph, ld(v.E, k), ld(v.Fx, k), ld(v.Fy, k), ld(v.Fz, k));
+    if (kind == BC_REFLECTIVE) R.F[2] = -R.F[2];
+    return R;
+}
+
+}  // namespace
+
+struct StageArgs3 {
+    CSoa3 rhs;      // apply: x (nullable); relax: b; pseudo: f
+    double omega;   // relax
+    double sgn;     // apply
+    Soa3 out;
+    double dtau;    // pseudo (dtau_dev when set)
+    const double* dtau_dev;
+    double reach;
+    int local;
+};
+
+template <int MODE>  // 0: out = x + sgn A(u); 1: relaxed Jacobi sweep; 2: pseudo-time step
+__global__ __launch_bounds__(kB3) void k3_staged(Phys3 ph, Lvl3 L, CSoa3 u, StageArgs3 A,
+                                                 const int* __restrict__ active)
+{
+    __shared__ double sE[kSN], sF0[kSN], sF1[kSN], sF2[kSN], sI[kSN], sR[kSN];
+    const bool live = active[vzero3()] != 0;
+    const double dtau = (MODE == 2 && A.dtau_dev) ? A.dtau_dev[vzero3()] : A.dtau;
+    const int ntx = (L.nx + kSX - 1) / kSX, nty = (L.ny + kSY - 1) / kSY;
+    const int b = (int)xcd_block();
+    const int tz = b / (ntx * nty), rem = b - tz * ntx * nty, tyb = rem / ntx, txb = rem - tyb * ntx;
+    const int x0 = txb * kSX, y0 = tyb * kSY, z0 = tz * kSZ, z1 = min(z0 + kSZ, L.nz);
+    const int tx = threadIdx.x & (kSX - 1), ty = threadIdx.x / kSX;
+    const int i = x0 + tx, j = y0 + ty;
+    const bool own = i < L.nx && j < L.ny;
+    auto put = [&](int p, const Rec3& R) {
+        sE[p] = R.E;
+        sF0[p] = R.F[0];
+        sF1[p] = R.F[1];
+        sF2[p] = R.F[2];
+        sI[p] = R.iso;
+        sR[p] = R.r3;
+    };
+    auto get = [&](int p) {
+        Rec3 R;
+        R.E = sE[p];
+        R.F[0] = sF0[p];
+        R.F[1] = sF1[p];
+        R.F[2] = sF2[p];
+        R.iso = sI[p];
+        R.r3 = sR[p];
+        return R;
+    };
+    // the ring position this thread fills: rows above and below the tile, then the columns left and right
+    int rx = 0, ry = 0;
+    const int r = threadIdx.x;
+    if (r < kRing) {
+        if (r < 2 * kSX) {
+            rx = 1 + (r & (kSX - 1));
+            ry = r < kSX ? 0 : kSH - 1;
+        } else {
+            rx = ((r - 2 * kSX) & 1) ? kSW - 1 : 0;
+            ry = (r - 2 * kSX) >> 1;
+        }
+    }
+    Rec3 prev{}, cur{}, next{};
+    if (own) {
+        prev = column_rec(ph, L, u, i, j, z0 - 1);
+        cur = column_rec(ph, L, u, i, j, z0);
+    }
+    const int slot = (ty + 1) * kSW + tx + 1;
+    for (int z = z0; z < z1; ++z) {
+        if (own) next = column_rec(ph, L, u, i, j, z + 1);
+        __syncthreads();  // the previous plane's reads are done
+        put(slot, own ? cur : plane_rec(ph, L, u, i, j, z));
+        if (r < kRing) put(ry * kSW + rx, plane_rec(ph, L, u, x0 - 1 + rx, y0 - 1 + ry, z));
+        __syncthreads();
+        if (own) {
+            double S[4] = {0.0, 0.0, 0.0, 0.0};
+            add3(ph, L.kx, 1.0, 0, get(slot - 1), S);
+            add3(ph, L.kx, -1.0, 0, get(slot + 1), S);
+            add3(ph, L.ky, 1.0, 1, get(slot - kSW), S);
+            add3(ph, L.ky, -1.0, 1, get(slot + kSW), S);
+            add3(ph, L.kz, 1.0, 2, prev, S);
+            add3(ph, L.kz, -1.0, 2, next, S);
+            const uint32_t k = ((uint32_t)z * (uint32_t)L.ny + (uint32_t)j) * (uint32_t)L.nx + (uint32_t)i;
+            double uc[5] = {cur.E, cur.F[0], cur.F[1], cur.F[2], ld(u.T, k)}, o[5];
+            if (MODE == 0) (void)fin_apply(ph, L, uc, S, A.rhs, A.sgn, k, o);
+            else if (MODE == 1) fin_relax(ph, L, uc, S, A.rhs, A.omega, k, o);
+            else fin_pseudo(ph, L, uc, S, A.rhs, dtau, A.reach, A.local, k, o);
+            if (live && A.out.E) st5(A.out, k, o);
+        }
+        prev = cur;
+        cur = next;
+    }
 }
 
 namespace {
@@ -435,6 +623,56 @@ void launch3_pseudo(hipStream_t st, const Phys3& ph, const Lvl3& L, CSoa3 f, CSo
     const int64_t n = (int64_t)L.nx * L.ny * L.nz;
     hipLaunchKernelGGL(k3_pseudo, dim3(blocks3(n)), dim3(kB3), 0, st, ph, L, f, in, out, dtau, dtau_dev, reach, local,
                        active);
+}
+
+namespace {
+std::atomic<int> g_stage3{1};
+
+unsigned staged_blocks(const Lvl3& L)
+{
+    return (unsigned)(((L.nx + kSX - 1) / kSX) * ((L.ny + kSY - 1) / kSY) * ((L.nz + kSZ - 1) / kSZ));
+}
+}  // namespace
+
+void set_stage3(int mode) { g_stage3 = mode < 0 ? 0 : (mode > 2 ? 2 : mode); }
+int stage3() { return g_stage3.load(); }
+bool stage3_fits(const Lvl3& L, bool sweep)
+{
+    const int m = g_stage3.load();
+    return L.nx >= kStage3MinNx && (m == 2 || (m == 1 && sweep));
+}
+
+void launch3_apply_staged(hipStream_t st, const Phys3& ph, const Lvl3& L, CSoa3 v, CSoa3 x, double sgn, Soa3 out,
+                          const int* active)
+{
+    StageArgs3 A{};
+    A.rhs = x;
+    A.sgn = sgn;
+    A.out = out;
+    hipLaunchKernelGGL(k3_staged<0>, dim3(staged_blocks(L)), dim3(kB3), 0, st, ph, L, v, A, active);
+}
+
+void launch3_relax_staged(hipStream_t st, const Phys3& ph, const Lvl3& L, CSoa3 b, double omega, CSoa3 in,
+                          Soa3 out, const int* active)
+{
+    StageArgs3 A{};
+    A.rhs = b;
+    A.omega = omega;
+    A.out = out;
+    hipLaunchKernelGGL(k3_staged<1>, dim3(staged_blocks(L)), dim3(kB3), 0, st, ph, L, in, A, active);
+}
+
+void launch3_pseudo_staged(hipStream_t st, const Phys3& ph, const Lvl3& L, CSoa3 f, CSoa3 in, Soa3 out,
+                           double dtau, const double* dtau_dev, double reach, int local, const int* active)
+{
+    StageArgs3 A{};
+    A.rhs = f;
+    A.out = out;
+    A.dtau = dtau;
+    A.dtau_dev = dtau_dev;
+    A.reach = reach;
+    A.local = local;
+    hipLaunchKernelGGL(k3_staged<2>, dim3(staged_blocks(L)), dim3(kB3), 0, st, ph, L, in, A, active);
 }
 
 void launch3_restrict(hipStream_t st, int nxf, int nyf, int nzf, int px, int py, int pz, const Fields& F,

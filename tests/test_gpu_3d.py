@@ -150,3 +150,39 @@ def test_edge_cases():
                   dict(smoother="rbgs")):
         with pytest.raises(binding.M1Error):
             binding.Plan3(prob, to_dev(sig), dict(omega=OMEGA, **extra))
+
+
+STAGE_SHAPES = [(100, 6, 20, ALLKINDS), (70, 9, 17, ("periodic",) * 6), (64, 8, 16, MIXED),
+                (33, 5, 3, ("periodic", "periodic", "dirichlet", "neumann", "reflective", "dirichlet"))]
+
+
+@pytest.mark.parametrize("shape", range(len(STAGE_SHAPES)))
+def test_staged_operations_equal_the_one_cell_forms(shape):
+    """The staged (2.5-D blocked) apply, sweep and pseudo-time step give the one-cell kernels' bits on ragged
+    tiles, periodic and non-periodic sides and chunks of z-planes that do not divide the grid; whole steps give
+    the same bits and cycle counts."""
+    nx, ny, nz, bcs = STAGE_SHAPES[shape]
+    announce("3-D staged vs one-cell", nx, ny, nz)
+    prob, v, sig = inputs.random_problem3(40 + shape, nx, ny, nz, bc_kinds=bcs, cfl=30.0, log10_sa=(-3, 2),
+                                          wall_E=5.0)
+    rng = np.random.default_rng(shape)
+    u = inputs.random_state3(rng, nz, ny, nx, c=prob["c"], fmax=0.95)
+    u[4] = rng.uniform(0.5, 1.5, size=u[4].shape)
+    o = oracle.Oracle3(prob, sig)
+    b, f = o.rhs(v), o.apply_A(v) * 1.05
+    old = binding.tune_get("stage3")
+    res = {}
+    try:
+        for staged in (2, 0):  # every staged form, then none
+            binding.tune_set("stage3", staged)
+            P = binding.Plan3(prob, to_dev(sig), dict(omega=OMEGA, rtol=1e-12, max_cycles=5000))
+            vd = to_dev(v)
+            info = P.step(vd, 1)
+            res[staged] = (to_host(P.apply_A(0, to_dev(u))), to_host(P.sweep(to_dev(b), to_dev(u))),
+                           to_host(P.pseudo_step(0, 0.7, to_dev(f), to_dev(u))), to_host(vd), info["cycles"])
+    finally:
+        binding.tune_set("stage3", old)
+    for a, c in zip(res[2][:4], res[0][:4]):
+        np.testing.assert_array_equal(a, c)
+    assert res[2][4] == res[0][4]
+    assert rel3(res[2][1], o.sweep(b, u, OMEGA), prob["c"]) <= 1e-13
