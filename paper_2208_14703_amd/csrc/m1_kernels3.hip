@@ -639,7 +639,8 @@ int stage3() { return g_stage3.load(); }
 bool stage3_fits(const Lvl3& L, bool sweep)
 {
     const int m = g_stage3.load();
-    return L.nx >= kStage3MinNx && (m == 2 || (m == 1 && sweep));
+    const int64_t n = (int64_t)L.nx * L.ny * L.nz;
+    return L.nx >= kStage3MinNx && (m == 2 || (m == 1 && sweep && n >= kStage3MinCells));
 }
 
 void launch3_apply_staged(hipStream_t st, const Phys3& ph, const Lvl3& L, CSoa3 v, CSoa3 x, double sgn, Soa3 out,
