@@ -478,11 +478,16 @@ def serve_leg(torch, nreq: int, rate: float, arena_bytes: int, precision: str = 
     E.serve_start(4)
     t0 = time.perf_counter()
     tickets = []
+    peak = {"pool_in_use": 0, "resident": 0, "pending": 0}
     for i, r in enumerate(reqs):
         d = t0 + arr[i] - time.perf_counter()
         if d > 0:
             time.sleep(d)
         tickets.append(E.submit(r[0], sig_d[i], v_d[i], r[3]["steps"]))
+        if i % 8 == 7:  # the pool's use and the queue, sampled as requests arrive
+            m = E.memory()
+            peak = {k: max(peak[k], m[k]) for k in peak}
+            pool_bytes = m["pool_bytes"]
         if nreq >= 200 and (i + 1) % 100 == 0:
             print(f"[serve] rate {rate:g}/s: {i + 1} of {nreq} requests submitted", file=sys.stderr, flush=True)
     infos = [E.wait(t) for t in tickets]
@@ -519,6 +524,9 @@ def serve_leg(torch, nreq: int, rate: float, arena_bytes: int, precision: str = 
            "requests_per_s": round(nreq / span, 3), "Mcell_updates_per_s": round(cell_steps / span / 1e6, 2),
            "latency_p50_ms": round(pct(lat, 50) * 1e3, 1), "latency_p99_ms": round(pct(lat, 99) * 1e3, 1),
            "admitted_while_others_ran": overlapped, "all_converged": bool(ok), "wall_s": round(span, 2),
+           "hbm_pool_peak_gb": round(peak["pool_in_use"] / 2 ** 30, 2),
+           "hbm_pool_gb": round(pool_bytes / 2 ** 30, 2) if nreq >= 8 else None,
+           "peak_resident": peak["resident"], "peak_waiting": peak["pending"],
            "plain_fp64_one_request_at_a_time": plain}
     if nreq >= 200:
         print("[serve] " + json.dumps(out), file=sys.stderr, flush=True)

@@ -155,11 +155,17 @@ typedef struct {
 
 /* Result of m1_step.  cycles: total V-cycles over all steps; rel_residual and
  * r0: of the last step; first_bad_cell: index of the first non-admissible
- * input cell (or -1); status: as returned.                                   */
+ * input cell (or -1); status: as returned; stalled_cells: pseudo-time
+ * stalls over the call (m1_step, m1_step3; 0 elsewhere): coarse-level cell
+ * updates whose explicit sub-steps could not move because the state lies on
+ * the boundary of the admissible set and the source points out of it
+ * (tau* = 0 in Algorithm 3), so that the pseudo-time step left the cell
+ * unchanged.                                                                 */
 typedef struct {
     int32_t cycles, status, levels, steps_done;
     double r0, rel_residual, dtau;
     int64_t first_bad_cell;
+    int64_t stalled_cells;
 } m1_info;
 
 typedef struct m1_plan m1_plan;
@@ -284,6 +290,11 @@ m1_status m1_prolong_project(m1_plan* plan, int32_t level, const m1_state* u, co
                              const m1_state* vc, m1_state* out);
 /* Wait for all work enqueued on the plan's stream. */
 m1_status m1_sync(m1_plan* plan);
+/* Pseudo-time stalls (see m1_info.stalled_cells) counted on this plan since
+ * its creation, its last m1_step or the last reset: *count (host; blocks),
+ * then the counter is cleared when `reset` is nonzero.  Counts the coarse
+ * cycle's pseudo-time steps and m1_pseudo_step.                              */
+m1_status m1_stalls(m1_plan* plan, int64_t* count, int32_t reset);
 
 /* ---- launch-shape settings ----------------------------------------------------
  * Process-wide settings of how the cycle is launched (environment variables
@@ -379,6 +390,13 @@ m1_status m1_batch_cancel(m1_engine* e, uint64_t ticket);
 m1_status m1_batch_times(m1_engine* e, uint64_t ticket, double* t_submit, double* t_admit, double* t_done);
 /* Forget a finished request (frees its host record).                         */
 m1_status m1_batch_release(m1_engine* e, uint64_t ticket);
+
+/* HBM of the engine's request pool (the part of the arena that request
+ * workspaces are carved from; the rest holds the device tables): bytes in use
+ * and in total, and the numbers of resident and waiting requests (either
+ * pointer may be NULL).  Waits for a running round to end.                   */
+m1_status m1_engine_memory(m1_engine* e, size_t* pool_in_use, size_t* pool_bytes, int32_t* resident,
+                           int32_t* pending);
 
 /* Serving loop (continuous batching without a driving caller).  Starts one
  * host thread of the library that runs rounds of `cycles` V-cycles as long as

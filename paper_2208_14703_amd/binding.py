@@ -82,7 +82,7 @@ class m1_opacity(ctypes.Structure):
 class m1_info(ctypes.Structure):
     _fields_ = [("cycles", ctypes.c_int32), ("status", ctypes.c_int32), ("levels", ctypes.c_int32),
                 ("steps_done", ctypes.c_int32), ("r0", ctypes.c_double), ("rel_residual", ctypes.c_double),
-                ("dtau", ctypes.c_double), ("first_bad_cell", ctypes.c_int64)]
+                ("dtau", ctypes.c_double), ("first_bad_cell", ctypes.c_int64), ("stalled_cells", ctypes.c_int64)]
 
 
 _lib = None
@@ -123,6 +123,8 @@ def lib():
         L.m1_prolong_project.argtypes = [vp, ctypes.c_int32, P(m1_state), P(m1_state), P(m1_state), P(m1_state)]
         L.m1_residual_restrict.argtypes = [vp, ctypes.c_int32, P(m1_state), P(m1_state), P(m1_state), P(m1_state)]
         L.m1_sync.argtypes = [vp]
+        L.m1_stalls.argtypes = [vp, P(ctypes.c_int64), ctypes.c_int32]
+        L.m1_stalls.restype = ctypes.c_int
         L.m1_step_static.argtypes = [P(m1_grid), P(m1_params), P(m1_opacity), P(m1_state), ctypes.c_int32, vp,
                                      P(m1_info)]
         L.m1_engine_request_bytes.restype = ctypes.c_size_t
@@ -138,6 +140,9 @@ def lib():
         L.m1_batch_times.argtypes = [vp, ctypes.c_uint64, P(ctypes.c_double), P(ctypes.c_double),
                                      P(ctypes.c_double)]
         L.m1_batch_release.argtypes = [vp, ctypes.c_uint64]
+        L.m1_engine_memory.argtypes = [vp, P(ctypes.c_size_t), P(ctypes.c_size_t), P(ctypes.c_int32),
+                                       P(ctypes.c_int32)]
+        L.m1_engine_memory.restype = ctypes.c_int
         L.m1_serve_start.argtypes = [vp, ctypes.c_int32]
         L.m1_serve_stop.argtypes = [vp]
         L.m1_tune_set.argtypes = [ctypes.c_char_p, ctypes.c_int64]
@@ -312,7 +317,7 @@ class Plan:
         st = lib().m1_step(self.handle, ctypes.byref(self._st(v)), nsteps, ctypes.byref(info))
         out = {"status": st, "cycles": info.cycles, "levels": info.levels, "steps_done": info.steps_done,
                "r0": info.r0, "rel_residual": info.rel_residual, "dtau": info.dtau,
-               "first_bad_cell": info.first_bad_cell}
+               "first_bad_cell": info.first_bad_cell, "stalled_cells": info.stalled_cells}
         if st not in (0, 3):
             raise M1Error(st, f"m1_step {out}")
         return out
@@ -322,6 +327,12 @@ class Plan:
         _check(lib().m1_vcycle(self.handle, ctypes.byref(self._st(v)), ctypes.byref(self._st(vn)), dtau,
                                ctypes.byref(info) if want_info else None), "m1_vcycle")
         return _info_dict(info) if want_info else None
+
+    def stalls(self, reset: bool = False) -> int:
+        """Pseudo-time stalls counted on this plan since its creation, its last step or the last reset."""
+        n = ctypes.c_int64()
+        _check(lib().m1_stalls(self.handle, ctypes.byref(n), 1 if reset else 0), "m1_stalls")
+        return n.value
 
     def residual(self, v, vn, want_r: bool = False):
         r = self.torch.zeros_like(v) if want_r else None
@@ -406,7 +417,7 @@ def step_static(problem: dict, sigma, v, nsteps: int = 1, params: dict | None = 
 
 def _info_dict(info: m1_info) -> dict:
     return {"status": info.status, "cycles": info.cycles, "levels": info.levels, "steps_done": info.steps_done,
-            "r0": info.r0, "rel_residual": info.rel_residual, "dtau": info.dtau}
+            "r0": info.r0, "rel_residual": info.rel_residual, "dtau": info.dtau, "stalled_cells": info.stalled_cells}
 
 
 class Engine:
@@ -439,6 +450,14 @@ class Engine:
         if h is not None and _lib is not None:
             _lib.m1_engine_destroy(h)
             self.handle = None
+
+    def memory(self) -> dict:
+        """HBM of the request pool in use and in total, resident and waiting requests (m1_engine_memory)."""
+        used, total = ctypes.c_size_t(), ctypes.c_size_t()
+        res, pend = ctypes.c_int32(), ctypes.c_int32()
+        _check(lib().m1_engine_memory(self.handle, ctypes.byref(used), ctypes.byref(total), ctypes.byref(res),
+                                      ctypes.byref(pend)), "m1_engine_memory")
+        return {"pool_in_use": used.value, "pool_bytes": total.value, "resident": res.value, "pending": pend.value}
 
     @staticmethod
     def request_bytes(problem: dict, params: dict | None = None) -> int:

@@ -15,6 +15,7 @@ struct Phys3 {
     double c, c2, a_r, c_v;
     int bc[6];
     double bcE[6], bcFx[6], bcFy[6], bcFz[6];
+    unsigned long long* stalls;  // pseudo-time stall counter (device; may be null)
 };
 
 // One level: cells numbered k = (z ny + y) nx + x in 32 bits.

@@ -20,6 +20,7 @@
 #include "m1_internal.hpp"
 #include "m1_transfer.hpp"
 #include "m1_3d.hpp"
+#include "m1_trace.hpp"
 
 namespace {
 
@@ -176,6 +177,7 @@ struct m1_plan {
     int npart = 0;
     double* dscal = nullptr;
     unsigned long long* dbad = nullptr;
+    unsigned long long* dstall = nullptr;  // pseudo-time stalls since the last reset
     double* hpin = nullptr;        // pinned host words: a scalar, the bad-cell index, the control copy
     bool own_hpin = true;          // false: borrowed from an engine (not freed with the plan)
     unsigned long long* hbad = nullptr;
@@ -264,6 +266,7 @@ void carve(m1_plan& P, Carver& c, const Dims& d)
     P.dbad = reinterpret_cast<unsigned long long*>(c.take(1));
     P.dctrl = reinterpret_cast<m1::Ctrl*>(c.take((sizeof(m1::Ctrl) + 7) / 8));
     P.dfix = reinterpret_cast<m1::Ctrl*>(c.take((sizeof(m1::Ctrl) + 7) / 8));
+    P.dstall = reinterpret_cast<unsigned long long*>(c.take(1));
     P.dtail = reinterpret_cast<m1::TailArgs*>(c.take((sizeof(m1::TailArgs) + 7) / 8));
     if (P.params.precision == M1_MIXED)
         P.dtail32 = reinterpret_cast<m1::TailArgs32*>(c.take((sizeof(m1::TailArgs32) + 7) / 8));
@@ -947,6 +950,7 @@ static m1_status plan_init(m1_plan* P, const m1_grid* g, const m1_params* p, con
     }
     Carver c{static_cast<char*>(workspace)};
     carve(*P, c, dims);
+    P->ph.stalls = P->dstall;
     P->lev[0].sa = const_cast<double*>(op->sigma_a);
     P->lev[0].ss = const_cast<double*>(op->sigma_s);
     fill_level_params(*P);
@@ -1016,6 +1020,7 @@ static m1_status plan_init(m1_plan* P, const m1_grid* g, const m1_params* p, con
         m1::launch_ctrl_init(P->st, P->dctrl, m1::Ctrl{});  // stopped, state in x0
     }
     m1_status st = hip_status(hipMemsetAsync(P->dbad, 0xff, sizeof(unsigned long long), P->st));
+    if (st == M1_OK) st = hip_status(hipMemsetAsync(P->dstall, 0, sizeof(unsigned long long), P->st));
     if (st == M1_OK) {
         m1::launch_check_sigma(P->st, n0, op->sigma_a, op->sigma_s, P->dbad);
         st = hip_status(hipMemcpyAsync(P->hbad, P->dbad, sizeof(unsigned long long), hipMemcpyDeviceToHost, P->st));
@@ -1147,6 +1152,7 @@ m1_status m1_vcycle(m1_plan* P, m1_state* v, const m1_state* vn, double dtau, m1
 
 m1_status m1_step(m1_plan* P, m1_state* v, int32_t nsteps, m1_info* info)
 {
+    const m1::TraceRange trace("m1_step");
     if (info) {
         std::memset(info, 0, sizeof(*info));
         info->first_bad_cell = -1;
@@ -1157,7 +1163,9 @@ m1_status m1_step(m1_plan* P, m1_state* v, int32_t nsteps, m1_info* info)
     Soa user = to_soa(v);
     if (info) info->levels = P->L;
 
-    if (hipMemsetAsync(P->dbad, 0xff, sizeof(unsigned long long), P->st) != hipSuccess) return M1_ERR_DEVICE;
+    if (hipMemsetAsync(P->dbad, 0xff, sizeof(unsigned long long), P->st) != hipSuccess ||
+        hipMemsetAsync(P->dstall, 0, sizeof(unsigned long long), P->st) != hipSuccess)
+        return M1_ERR_DEVICE;
     m1::launch_check_state(P->st, P->dim, n0, P->grid.c, cs(user), P->dbad);
     if (hipMemcpyAsync(P->hbad, P->dbad, sizeof(unsigned long long), hipMemcpyDeviceToHost, P->st) != hipSuccess ||
         hipStreamSynchronize(P->st) != hipSuccess)
@@ -1175,6 +1183,7 @@ m1_status m1_step(m1_plan* P, m1_state* v, int32_t nsteps, m1_info* info)
     int total = 0;
     double r0 = 0.0, rel = 0.0, dtau = p.dtau_im0;
     for (int step = 0; step < nsteps && status == M1_OK; ++step) {
+        const m1::TraceRange trace_step("time step");
         m1::launch_make_rhs(P->st, P->dim, n0, P->grid.c_v, cs(user), P->b);
         double bnorm = 0.0;
         m1_status e = fine_norm(*P, user, Soa{}, &bnorm, 0.0);  // |b|
@@ -1265,15 +1274,31 @@ m1_status m1_step(m1_plan* P, m1_state* v, int32_t nsteps, m1_info* info)
         if (!same(res, user)) m1::launch_copy(P->st, P->dim, n0, cs(res), user);
         if (!h.conv) status = M1_ERR_NO_CONVERGENCE;
     }
-    if (hipStreamSynchronize(P->st) != hipSuccess) return M1_ERR_DEVICE;
+    auto* hstall = reinterpret_cast<unsigned long long*>(P->hpin + 2);
+    if (hipMemcpyAsync(hstall, P->dstall, sizeof(unsigned long long), hipMemcpyDeviceToHost, P->st) != hipSuccess ||
+        hipStreamSynchronize(P->st) != hipSuccess)
+        return M1_ERR_DEVICE;
     if (info) {
         info->cycles = total;
         info->status = status;
         info->r0 = r0;
         info->rel_residual = rel;
         info->dtau = dtau;
+        info->stalled_cells = (int64_t)*hstall;
     }
     return status;
+}
+
+m1_status m1_stalls(m1_plan* P, int64_t* count, int32_t reset)
+{
+    if (!P || !count) return M1_ERR_ARG;
+    auto* hstall = reinterpret_cast<unsigned long long*>(P->hpin + 2);
+    if (hipMemcpyAsync(hstall, P->dstall, sizeof(unsigned long long), hipMemcpyDeviceToHost, P->st) != hipSuccess ||
+        (reset && hipMemsetAsync(P->dstall, 0, sizeof(unsigned long long), P->st) != hipSuccess) ||
+        hipStreamSynchronize(P->st) != hipSuccess)
+        return M1_ERR_DEVICE;
+    *count = (int64_t)*hstall;
+    return M1_OK;
 }
 
 }  // extern "C"
@@ -2154,6 +2179,7 @@ m1_status m1_batch_run(m1_engine* E, int32_t cycles, int32_t* n_running, int32_t
 {
     if (!E || cycles < 1) return M1_ERR_ARG;
     std::lock_guard<std::mutex> lk(E->rmu);
+    const m1::TraceRange trace("engine round");
     admit(*E);
     m1_status st = M1_OK;
     if (E->live > 0) {
@@ -2264,6 +2290,23 @@ m1_status m1_batch_run(m1_engine* E, int32_t cycles, int32_t* n_running, int32_t
     std::lock_guard<std::mutex> g(E->qmu);
     if (n_running) *n_running = (int32_t)E->live;
     if (n_pending) *n_pending = (int32_t)E->pending.size();
+    return M1_OK;
+}
+
+m1_status m1_engine_memory(m1_engine* E, size_t* pool_in_use, size_t* pool_bytes, int32_t* resident,
+                           int32_t* pending)
+{
+    if (!E || !pool_in_use || !pool_bytes) return M1_ERR_ARG;
+    std::lock_guard<std::mutex> lk(E->rmu);  // the pool changes inside rounds
+    size_t free_bytes = 0;
+    for (const auto& f : E->free_) free_bytes += f.second;
+    *pool_bytes = E->pool_bytes;
+    *pool_in_use = E->pool_bytes - free_bytes;
+    if (resident) *resident = E->live;
+    if (pending) {
+        std::lock_guard<std::mutex> q(E->qmu);
+        *pending = (int32_t)E->pending.size();
+    }
     return M1_OK;
 }
 

@@ -16,6 +16,7 @@
 
 #include "m1.h"
 #include "m1_3d.hpp"
+#include "m1_trace.hpp"
 
 namespace {
 
@@ -46,6 +47,7 @@ struct m1_plan3 {
     int npart = 0;
     double* dscal = nullptr;
     unsigned long long* dbad = nullptr;
+    unsigned long long* dstall = nullptr;  // pseudo-time stalls of the last m1_step3
     m1::Ctrl* dctrl = nullptr;
     m1::Ctrl* dfix = nullptr;
     double* hpin = nullptr;  // pinned host slot: scalars, the bad-cell index and a control copy
@@ -149,6 +151,7 @@ size_t carve3(m1_plan3* P, char* base, int L, const int nx[], const int ny[], co
     double* partials = c.take(npart);
     double* dscal = c.take(8);
     double* dbad = c.take(1);
+    double* dstall = c.take(1);
     const int64_t nctrl = (int64_t)((sizeof(m1::Ctrl) + 7) / 8);
     double* dctrl = c.take(nctrl);
     double* dfix = c.take(nctrl);
@@ -157,6 +160,7 @@ size_t carve3(m1_plan3* P, char* base, int L, const int nx[], const int ny[], co
         P->npart = npart;
         P->dscal = dscal;
         P->dbad = reinterpret_cast<unsigned long long*>(dbad);
+        P->dstall = reinterpret_cast<unsigned long long*>(dstall);
         P->dctrl = reinterpret_cast<m1::Ctrl*>(dctrl);
         P->dfix = reinterpret_cast<m1::Ctrl*>(dfix);
     }
@@ -347,6 +351,7 @@ m1_status m1_plan3_create(const m1_grid3* g, const m1_params* p, const m1_opacit
         P->ph.bcFy[s] = g->bc[s].Fy;
         P->ph.bcFz[s] = g->bc[s].Fz;
     }
+    P->ph.stalls = P->dstall;
     P->px = g->bc[0].kind == M1_BC_PERIODIC;
     P->py = g->bc[2].kind == M1_BC_PERIODIC;
     P->pz = g->bc[4].kind == M1_BC_PERIODIC;
@@ -497,6 +502,7 @@ m1_status m1_vcycle3(m1_plan3* P, m1_state3* v, const m1_state3* vn, double dtau
 
 m1_status m1_step3(m1_plan3* P, m1_state3* v, int32_t nsteps, m1_info* info)
 {
+    const m1::TraceRange trace("m1_step3");
     if (info) {
         std::memset(info, 0, sizeof(*info));
         info->first_bad_cell = -1;
@@ -507,7 +513,9 @@ m1_status m1_step3(m1_plan3* P, m1_state3* v, int32_t nsteps, m1_info* info)
     const m1::Soa3 user = soa3(v);
     if (info) info->levels = P->L;
     auto* hbad = reinterpret_cast<unsigned long long*>(P->hpin + 4);
-    if (hipMemsetAsync(P->dbad, 0xff, sizeof(unsigned long long), P->st) != hipSuccess) return M1_ERR_DEVICE;
+    if (hipMemsetAsync(P->dbad, 0xff, sizeof(unsigned long long), P->st) != hipSuccess ||
+        hipMemsetAsync(P->dstall, 0, sizeof(unsigned long long), P->st) != hipSuccess)
+        return M1_ERR_DEVICE;
     m1::launch3_check_state(P->st, n0, P->grid.c, m1::cs3(user), P->dbad);
     if (hipMemcpyAsync(hbad, P->dbad, sizeof(unsigned long long), hipMemcpyDeviceToHost, P->st) != hipSuccess ||
         hipStreamSynchronize(P->st) != hipSuccess || hipGetLastError() != hipSuccess)
@@ -581,13 +589,17 @@ m1_status m1_step3(m1_plan3* P, m1_state3* v, int32_t nsteps, m1_info* info)
         if (!same3(res, user)) m1::launch3_copy(P->st, n0, m1::cs3(res), user);
         if (!h.conv) status = M1_ERR_NO_CONVERGENCE;
     }
-    if (hipStreamSynchronize(P->st) != hipSuccess) return M1_ERR_DEVICE;
+    auto* hstall = reinterpret_cast<unsigned long long*>(P->hpin + 2);
+    if (hipMemcpyAsync(hstall, P->dstall, sizeof(unsigned long long), hipMemcpyDeviceToHost, P->st) != hipSuccess ||
+        hipStreamSynchronize(P->st) != hipSuccess)
+        return M1_ERR_DEVICE;
     if (info) {
         info->cycles = total;
         info->status = status;
         info->r0 = r0;
         info->rel_residual = rel;
         info->dtau = dtau;
+        info->stalled_cells = (int64_t)*hstall;
     }
     return status;
 }

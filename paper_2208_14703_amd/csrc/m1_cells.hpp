@@ -101,7 +101,7 @@ __device__ __forceinline__ void pseudo_core(const Phys& ph, const Lvl& L, double
                                             double S0, double S1, double S2, double ka, double ks, double& fE,
                                             double& fFx, double& fFy, double& fT, double dtau, double reach,
                                             int local, double& E, double& Fx, double& Fy, double& T, double& tE,
-                                            double& tFx, double& tFy, double& tT, double& g)
+                                            double& tFx, double& tFy, double& tT, double& g, bool& stall)
 {
     if (FIRST) {
         const double T2 = uT * uT;
@@ -114,6 +114,7 @@ __device__ __forceinline__ void pseudo_core(const Phys& ph, const Lvl& L, double
     }
     const double sE = fE, sFx = fFx, sFy = fFy, sT = fT * rcp_nr(ph.c_v);
     const double ts = ray_len(ph.c2, uE, uFx, uFy, uT, sE, sFx, sFy, sT);
+    stall = ts == 0.0;
     const double tau = fmin(dtau, ts * reach);
     tE = fma(tau, sE, uE);
     tFx = fma(tau, sFx, uFx);
@@ -136,9 +137,11 @@ __device__ __forceinline__ void pseudo_update(const Phys& ph, const Lvl& L, cons
     const double ka = L.cdt * ld(L.sa, k), ks = L.cdt * ld(L.ss, k);
     double fE = ld(fin.E, k), fFx = ld(fin.Fx, k), fFy = (DIM == 2) ? ld(fin.Fy, k) : 0.0, fT = ld(fin.T, k);
     double E, Fx, Fy, T, tE, tFx, tFy, tT, g;
+    bool stall;
     pseudo_core<DIM, FIRST>(ph, L, uE, uFx, uFy, uT, S0, S1, S2, ka, ks, fE, fFx, fFy, fT, dtau, reach, local, E, Fx,
-                            Fy, T, tE, tFx, tFy, tT, g);
+                            Fy, T, tE, tFx, tFy, tT, g, stall);
     if (!live) return;
+    if (stall && ph.stalls) note_stall(ph.stalls);
     if (FIRST) {
         st(fout.E, k, fE);
         st(fout.Fx, k, fFx);

@@ -21,7 +21,18 @@ struct Phys {
     int bc[4];  // x-, x+, y-, y+
     double bcE[4], bcFx[4], bcFy[4];
     double bcEo[4];  // inflow sides: energy of the isotropic ghost outside the segment
+    unsigned long long* stalls;  // count of pseudo-time stalls (device counter; may be null)
 };
+
+// A pseudo-time stall: a cell whose explicit sub-steps cannot move (tau* = 0: the state is on the boundary of
+// the admissible set and the source points out of it), so its pseudo-time step leaves it unchanged.  Counted
+// with one vector atomic (the address goes through a per-lane zero offset).
+__device__ __forceinline__ void note_stall(unsigned long long* stalls)
+{
+    uint32_t z = 0;
+    asm("" : "+v"(z));
+    atomicAdd(stalls + z, 1ull);
+}
 
 // One grid level as seen by a kernel.  Cells are numbered k = j nx + i in
 // 32 bits (a level holds at most 2^29 cells, so byte offsets fit too).

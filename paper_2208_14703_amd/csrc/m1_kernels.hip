@@ -892,14 +892,16 @@ __global__ __launch_bounds__(kTbThreads) void k_smooth_tb(Phys ph, Lvl L, CSoa f
             const double ka = L.cdt * qa[c], ks = L.cdt * qs[c];
             double f0 = qE[c], f1 = qFx[c], f2 = qFy[c], f3 = qT[c];
             double E, Fx, Fy, T, tE, tFx, tFy, tT, g;
+            bool stall;
+            const bool own = li >= M && li < M + kTbTile && lj >= M && lj < M + kTbTile;  // not a halo copy
             if (first) {
                 pseudo_core<2, true>(ph, L, sE[cur][c], sFx[cur][c], sFy[cur][c], sT[cur][c], S0, S1, S2, ka, ks, f0,
-                                     f1, f2, f3, dt, reach, local, E, Fx, Fy, T, tE, tFx, tFy, tT, g);
+                                     f1, f2, f3, dt, reach, local, E, Fx, Fy, T, tE, tFx, tFy, tT, g, stall);
                 qE[c] = f0;
                 qFx[c] = f1;
                 qFy[c] = f2;
                 qT[c] = f3;
-                if (live && li >= M && li < M + kTbTile && lj >= M && lj < M + kTbTile) {
+                if (live && own) {
                     const uint32_t k = (uint32_t)gj * (uint32_t)L.nx + (uint32_t)gi;
                     st(f.E, k, f0);
                     st(f.Fx, k, f1);
@@ -908,8 +910,9 @@ __global__ __launch_bounds__(kTbThreads) void k_smooth_tb(Phys ph, Lvl L, CSoa f
                 }
             } else {
                 pseudo_core<2, false>(ph, L, sE[cur][c], sFx[cur][c], sFy[cur][c], sT[cur][c], S0, S1, S2, ka, ks, f0,
-                                      f1, f2, f3, dt, reach, local, E, Fx, Fy, T, tE, tFx, tFy, tT, g);
+                                      f1, f2, f3, dt, reach, local, E, Fx, Fy, T, tE, tFx, tFy, tT, g, stall);
             }
+            if (live && own && stall && ph.stalls) note_stall(ph.stalls);
             sE[cur ^ 1][c] = E;
             sFx[cur ^ 1][c] = Fx;
             sFy[cur ^ 1][c] = Fy;

@@ -208,12 +208,13 @@ __device__ __forceinline__ void fin_relax(const Phys3& ph, const Lvl3& L, const 
 // reach); u~ = u + tau_i s; one Jacobi sweep of (M + g A)(u) = M u~ from u, g = tau_i (local) or dtau.
 __device__ __forceinline__ void fin_pseudo(const Phys3& ph, const Lvl3& L, const double u[5], const double S[4],
                                            const CSoa3& f, double dtau, double reach, int local, uint32_t k,
-                                           double o[5])
+                                           double o[5], bool& stall)
 {
     const double ka = L.cdt * ld(L.sa, k), ks = L.cdt * ld(L.ss, k);
     const double sE = ld(f.E, k), sFx = ld(f.Fx, k), sFy = ld(f.Fy, k), sFz = ld(f.Fz, k);
     const double sT = ld(f.T, k) * rcp_nr(ph.c_v);
     const double ts = ray3(ph.c2, u[0], u[1], u[2], u[3], u[4], sE, sFx, sFy, sFz, sT);
+    stall = ts == 0.0;
     const double tau = fmin(dtau, ts * reach);
     const double g = local ? tau : dtau;
     local_solve3(1.0, g, L.a, ka, ks, ph.c_v, ph.a_r, fma(g, S[0], fma(tau, sE, u[0])),
@@ -284,8 +285,11 @@ __global__ __launch_bounds__(kB3) void k3_pseudo(Phys3 ph, Lvl3 L, CSoa3 f, CSoa
     double S[4], uc[5], o[5];
     offdiag3(ph, L, u, i, j, l, k, S);
     load5(u, k, uc);
-    fin_pseudo(ph, L, uc, S, f, dtau, reach, local, k, o);
-    if (live) st5(out, k, o);
+    bool stall;
+    fin_pseudo(ph, L, uc, S, f, dtau, reach, local, k, o, stall);
+    if (!live) return;
+    if (stall && ph.stalls) note_stall(ph.stalls);
+    st5(out, k, o);
 }
 
 // ---- the same three operations staged: 2.5-D blocking ---------------------------------------------------
@@ -425,9 +429,11 @@ __global__ __launch_bounds__(kB3) void k3_staged(Phys3 ph, Lvl3 L, CSoa3 u, Stag
             add3(ph, L.kz, -1.0, 2, next, S);
             const uint32_t k = ((uint32_t)z * (uint32_t)L.ny + (uint32_t)j) * (uint32_t)L.nx + (uint32_t)i;
             double uc[5] = {cur.E, cur.F[0], cur.F[1], cur.F[2], ld(u.T, k)}, o[5];
+            bool stall = false;
             if (MODE == 0) (void)fin_apply(ph, L, uc, S, A.rhs, A.sgn, k, o);
             else if (MODE == 1) fin_relax(ph, L, uc, S, A.rhs, A.omega, k, o);
-            else fin_pseudo(ph, L, uc, S, A.rhs, dtau, A.reach, A.local, k, o);
+            else fin_pseudo(ph, L, uc, S, A.rhs, dtau, A.reach, A.local, k, o, stall);
+            if (live && stall && ph.stalls) note_stall(ph.stalls);
             if (live && A.out.E) st5(A.out, k, o);
         }
         prev = cur;

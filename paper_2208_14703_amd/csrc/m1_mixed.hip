@@ -631,6 +631,7 @@ __device__ __forceinline__ void mx_pseudo_finish(const Phys& ph, const Lvl32& L,
     }
     const float sT = gT * rcp32(cv);
     const float ts = ray_len32(c2, wE + eE, wFx + eFx, wFy + eFy, wT + eT, gE, gFx, gFy, sT);
+    if (live && ts == 0.0f && ph.stalls) note_stall(ph.stalls);
     const float tau = fminf(dt, ts * reach);
     const float tE = fmaf(tau, gE, eE), tFx = fmaf(tau, gFx, eFx), tFy = fmaf(tau, gFy, eFy);
     const float tT = cv * fmaf(tau, sT, eT);
