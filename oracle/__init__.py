@@ -47,7 +47,7 @@ class Params(ctypes.Structure):
         ("pseudo_steps", ctypes.c_int32), ("sub_steps", ctypes.c_int32), ("max_cycles", ctypes.c_int32),
         ("dtau_rule", ctypes.c_int32), ("pseudo_local", ctypes.c_int32),
         ("smoother", ctypes.c_int32), ("cycle", ctypes.c_int32), ("transfer", ctypes.c_int32),
-        ("pad2_", ctypes.c_int32),
+        ("dtau_carry", ctypes.c_int32),
         ("dtau_im0", ctypes.c_double), ("eps_inc", ctypes.c_double), ("eps_dec", ctypes.c_double),
         ("eta", ctypes.c_double), ("rtol", ctypes.c_double), ("dtau_min", ctypes.c_double),
         ("dtau_max", ctypes.c_double), ("omega", ctypes.c_double),
@@ -144,10 +144,13 @@ def make_params(**kw) -> Params:
     """Oracle solver parameters.
 
     Defaults: the paper's nu0=3, m=3, nu_l=1, dtau_im=1e-3 and undamped Jacobi
-    (omega=1), with the local pseudo-time step reading (pseudo_local=1).
+    (omega=1), with the local pseudo-time step reading (pseudo_local=1) and
+    dtau_im carried from one time step into the next (dtau_carry=1: the overall
+    algorithm of Appendix A does not set it at the start of a time step; Sect. 5
+    gives only its initial value).
     """
     d = dict(levels=0, nu0=3, nu_l=1, pseudo_steps=3, sub_steps=4, max_cycles=10000, dtau_rule="signed",
-             pseudo_local=1, smoother="jacobi", cycle="V", transfer="full", dtau_im0=1e-3, eps_inc=0.05, eps_dec=0.0, eta=0.9, rtol=1e-10,
+             pseudo_local=1, smoother="jacobi", cycle="V", transfer="full", dtau_carry=1, dtau_im0=1e-3, eps_inc=0.05, eps_dec=0.0, eta=0.9, rtol=1e-10,
              dtau_min=1e-6, dtau_max=1e6, omega=1.0)
     d.update(kw)
     p = Params()

@@ -924,11 +924,15 @@ static double adapt_dtau(const or_params* p, double dtau, double r0, double rpre
     return dtau;
 }
 
-/* Implicit Euler time steps, each solved by V-cycles until
+/* Implicit Euler time steps, each solved by cycles until
  * |b - A(v)| <= rtol |b - A(v^n)| (relative residual of Sect. 5), with
  * b = (E^n, F^n, C_v T^n) and the initial guess v^n.  A residual at the
  * rounding level of evaluating A, 16 eps a |b| (a = 1 + c dt/hx + c dt/hy),
- * also counts as converged, so an exact solution takes zero cycles.
+ * also counts as converged, so an exact solution takes zero cycles.  The
+ * pseudo-time step dtau_im starts at dtau_im0 and is adapted after every cycle;
+ * the overall algorithm of Appendix A (one time step) does not set it among its
+ * first steps and Sect. 5 gives only its initial value, so with dtau_carry it
+ * runs on into the next time step (dtau_carry 0 restarts it at dtau_im0).
  * Returns 0 on success, 3 when max_cycles was reached (v then holds the last
  * iterate).                                                                 */
 int32_t or_step(const or_grid* g, const double* sigma, const or_params* p, double* v, int32_t nsteps, or_info* info,
@@ -943,7 +947,7 @@ int32_t or_step(const or_grid* g, const double* sigma, const or_params* p, doubl
     for (int step = 0; step < nsteps; ++step) {
         memcpy(b, v, NFIELD * n * sizeof(double));
         for (size_t k = 0; k < n; ++k) b[3 * n + k] = g->c_v * v[3 * n + k];
-        dtau = p->dtau_im0;
+        if (!p->dtau_carry) dtau = p->dtau_im0;
         or_residual(g, sigma, b, v, r);
         r0 = or_norm(g, r);
         const double floor_r = 16.0 * DBL_EPSILON * diag_a(g) * or_norm(g, b);

@@ -51,7 +51,9 @@ typedef struct {
     int32_t cycle;         /* OR_CYCLE_V, OR_CYCLE_W or OR_CYCLE_F */
     int32_t transfer;      /* OR_TRANSFER_FULL (full weighting, Sect. 4.2) or OR_TRANSFER_MEAN (2^d-cell mean,
                               piecewise-constant prolongation) */
-    int32_t pad2_;
+    int32_t dtau_carry;    /* 1: dtau_im runs on from one time step to the next (the overall algorithm of
+                              Appendix A does not set it at the start of a step; Sect. 5 gives its initial
+                              value); 0: reset to dtau_im0 at the start of every time step */
     double dtau_im0, eps_inc, eps_dec, eta, rtol, dtau_min, dtau_max;
     double omega;          /* relaxation weight of the finest-level Jacobi sweeps (1 = Algorithm 1) */
 } or_params;

@@ -531,7 +531,8 @@ void or3_vcycle(const or3_grid* g, const double* sigma, const or_params* p, doub
 }
 
 /* Time steps as or_step: b = (E^n, F^n, C_v T^n), cycles until rtol or the rounding floor
- * 16 eps a |b|, dtau reset to dtau_im0 each step and adapted after each cycle (Appendix A). */
+ * 16 eps a |b|, dtau starting from dtau_im0 (on every step when dtau_carry is 0) and adapted after each
+ * cycle (Appendix A). */
 int32_t or3_step(const or3_grid* g, const double* sigma, const or_params* p, double* v, int32_t nsteps, or_info* info)
 {
     const size_t n = ncell3(g);
@@ -543,7 +544,7 @@ int32_t or3_step(const or3_grid* g, const double* sigma, const or_params* p, dou
     for (int step = 0; step < nsteps; ++step) {
         memcpy(b, v, NF3 * n * sizeof(double));
         for (size_t c = 0; c < n; ++c) b[4 * n + c] = g->c_v * v[4 * n + c];
-        dtau = p->dtau_im0;
+        if (!p->dtau_carry) dtau = p->dtau_im0;
         or3_residual(g, sigma, b, v, r);
         r0 = or3_norm(g, r);
         const double floor_r = 16.0 * DBL_EPSILON * diag_a3(g) * or3_norm(g, b);

@@ -89,6 +89,24 @@ def test_converged_steps_reduce_to_2d(reduced):
     assert np.abs(g3[3]).max() <= 1e-13 * np.abs(g3[0]).max()
 
 
+@pytest.mark.parametrize("carry", [1, 0])
+def test_dtau_across_time_steps(carry):
+    """The overall algorithm (Appendix A) does not set the pseudo-time step at the
+    start of a time step: two steps in one call equal one step and then one more
+    started from the step the first ended with (carry=1), or from the initial
+    step again (carry=0)."""
+    prob, v, sig = inputs.random_problem3(606, 8, 8, 8, bc_kinds=ALLKINDS, cfl=30.0, log10_sa=(-3, 2))
+    o = oracle.Oracle3(prob, sig)
+    kw = dict(omega=0.8, rtol=1e-6, max_cycles=500, dtau_carry=carry)
+    both, i2 = o.step(v, 2, oracle.make_params(**kw))
+    one, i1 = o.step(v, 1, oracle.make_params(**kw))
+    dtau0 = i1["dtau"] if carry else 1e-3
+    two, i1b = o.step(one, 1, oracle.make_params(**kw, dtau_im0=dtau0))
+    assert i2["status"] == i1["status"] == i1b["status"] == 0 and i1["dtau"] > 1e-3
+    np.testing.assert_array_equal(both, two)
+    assert i2["cycles"] == i1["cycles"] + i1b["cycles"] and i2["dtau"] == i1b["dtau"]
+
+
 def test_sweep_is_the_local_solve_against_the_old_neighbours():
     """Algorithm 1: after a sweep each cell satisfies its own row of A(u) = b with its neighbours at the old
     iterate; checked with the operator A (pinned above) on the old state with one cell replaced."""

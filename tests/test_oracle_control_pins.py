@@ -7,7 +7,9 @@ against what the paper prints or against an independent construction:
 * pseudo-time step adaptation (Appendix A, Algorithm 4; Sect. 5: initial step
   1e-3): the time-step driver is written out again in the test from the printed
   rule -- x1.1 when the residual change exceeds eps_inc, /2 when it is below
-  eps_dec, reset at every time step -- with the oracle's V-cycle as a step, and
+  eps_dec, set to 1e-3 once before the first time step (the overall algorithm
+  does not set it at the start of a step) or, in the other reading, again at
+  every time step -- with the oracle's V-cycle as a step, and
   its iterates and final step must equal those of ``or_step``; both the signed
   reading and the literal |r_k - r_{k-1}| / r_0 form, with thresholds that make
   both branches fire;
@@ -59,14 +61,18 @@ def printed_rule(rule, dtau, r0, rprev, r, eps_inc, eps_dec, dmin, dmax):
     return min(max(dtau, dmin), dmax)
 
 
-def driver(o, v, nsteps, p, rule, max_cycles):
+def driver(o, v, nsteps, p, rule, max_cycles, carry=True):
     """The overall algorithm's time-step loop, written out from the paper with
-    the oracle's V-cycle, residual and norm as its steps."""
+    the oracle's V-cycle, residual and norm as its steps.  The pseudo-time step
+    is initialised once, before the time loop (carry); carry=False restarts it
+    at every time step."""
     v = v.copy()
     dtaus, rels = [], []
+    dtau = DTAU0
     for _ in range(nsteps):
         b = o.rhs(v)
-        dtau = DTAU0
+        if not carry:
+            dtau = DTAU0
         r0 = o.norm(o.residual(b, v))
         rprev = r0
         for _k in range(max_cycles):
@@ -105,21 +111,28 @@ def test_dtau_adaptation_follows_the_printed_rule(rule, eps_inc, eps_dec, both):
     assert np.any(np.isclose(ratios, SHRINK)) == both, ratios
 
 
-def test_dtau_is_reset_at_every_time_step():
+@pytest.mark.parametrize("carry", [1, 0])
+def test_dtau_across_time_steps(carry):
+    """carry=1: each time step's first cycle runs with the step the previous one
+    ended with; carry=0: with the initial step again."""
     prob, v, sig = inputs.random_problem(902, 2, 16, 16, cfl=30.0)
     o = oracle.Oracle(prob, sig)
-    p = oracle.make_params(omega=0.8, rtol=1e-6, max_cycles=500, eps_inc=0.05, eps_dec=0.0)
+    p = oracle.make_params(omega=0.8, rtol=1e-6, max_cycles=500, eps_inc=0.05, eps_dec=0.0, dtau_carry=carry)
     got, info = o.step(v, 3, p)
     assert info["status"] == 0
-    ref, dtau_ref, dtaus, rels = driver(o, v, 3, p, "signed", 500)
+    ref, dtau_ref, dtaus, rels = driver(o, v, 3, p, "signed", 500, carry=bool(carry))
     np.testing.assert_array_equal(got, ref)
     assert info["dtau"] == dtau_ref and info["cycles"] == len(dtaus)
-    # every step's first cycle ran with the initial step again
+    np.testing.assert_array_equal(info["history"], np.array(rels))
     starts = [0]
     for k in range(1, len(rels)):
         if rels[k - 1] <= p.rtol:
             starts.append(k)
-    assert len(starts) == 3 and all(dtaus[k] == DTAU0 for k in starts)
+    assert len(starts) == 3 and dtaus[0] == DTAU0
+    if carry:  # the step grew during the previous time step (eps_dec = 0 never halves it) and runs on
+        assert all(dtaus[k] > DTAU0 for k in starts[1:])
+    else:
+        assert all(dtaus[k] == DTAU0 for k in starts)
     assert any(d != DTAU0 for d in dtaus)
 
 
