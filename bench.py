@@ -74,9 +74,14 @@ KERNEL_N = 4096             # side of the HBM-resident grid of the kernel measur
 SOLVER = dict(omega=0.8, levels=0)
 # Levels (L_max, the paper's own tuning knob: its timing table is a sweep of it) of the two single-problem
 # workloads: the fastest depth of a measured sweep. Solutions do not depend on it; cycle counts do.
-# Hot wall 1024^2: 6 levels (coarsest 32^2) 181 ms per solve, against 191 (7), 201 (8), 209 (9, to side 4) and
-# 700 (5, 2661 cycles). Lognormal 4096^2: 7 levels (coarsest 64^2).
-WORKLOAD_LEVELS = {"hotwall": 6, "lognormal": 7}
+# Hot wall 1024^2, the pseudo-time step carried from step to step: 5 levels (coarsest 64^2) 112 ms per solve
+# (384 cycles), against 116 (6), 126 (7), 133 (8), 139 (9, to side 4) and 156 (4).  Restarted at every step
+# instead, 6 levels were fastest (196 ms, 611 cycles; 5 levels took 2661 cycles).  Lognormal 4096^2: 7 levels
+# (coarsest 64^2).
+WORKLOAD_LEVELS = {"hotwall": 5, "lognormal": 7}
+RESET_LEVELS = {"hotwall": 6, "lognormal": 7}  # the fastest depths with the step restarted at every time step
+
+
 def sweeps_per_launch():
     """Sweeps per launch of the finest-level sweep kernel the cycle runs (2 with the fused pair on)."""
     return 2 if binding.tune_get("pair_rows") > 0 else 1
@@ -371,6 +376,15 @@ def three_d_leg(torch, reps):
     b[4] *= prob["c_v"]
     bufs, k = [vd.clone(), vd.clone()], [0]
 
+    rplan = binding.Plan3(prob, sd, dict(rtol=run["rtol"], max_cycles=20000, **dict(SOLVER, dtau_carry=0)))
+    v.copy_(vd)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    i_reset = rplan.step(v, run["steps"])
+    torch.cuda.synchronize()
+    t_reset = time.perf_counter() - t0
+    del rplan
+
     def launch():
         binding._check(L.m1_sweep3(plan.handle, binding.ctypes.byref(plan._st(b)),
                                    binding.ctypes.byref(plan._st(bufs[k[0]])),
@@ -381,6 +395,8 @@ def three_d_leg(torch, reps):
     out = {"workload": "hot wall 3-D 256^3, 10 implicit steps, dt=100h/c, 8^3 opacity blocks, FP64, rtol 1e-8",
            "Mcell_updates_per_s": round(cells * run["steps"] / t / 1e6, 2), "time_to_rtol_ms": round(t * 1e3, 1),
            "cycles": info["cycles"], "levels": info["levels"], "status": info["status"],
+           "dtau_reset": {"time_to_rtol_ms": round(t_reset * 1e3, 1), "cycles": i_reset["cycles"],
+                          "status": i_reset["status"]},
            "roofline": roofline_entry(kname, "finest-level FP64 Jacobi sweep, 3-D", SWEEP3_BYTES_PER_CELL * cells, tk,
                                       None, "256x256x256", "HBM (2.3 GB working set)")}
     del plan, v, b, bufs
@@ -628,6 +644,17 @@ def main():
         "final_rel_residual": infos[-1]["rel_residual"],
         "launch_shapes": {k: binding.tune_get(k) for k in binding.TUNE_ENV},
     }
+    # the other reading of the pseudo-time step across time steps: restarted at 1e-3 in every time step
+    rlevels = RESET_LEVELS[args.workload] if args.levels < 0 else args.levels
+    rplan = binding.Plan(prob, dev_sig, dict(rtol=run["rtol"], max_cycles=20000, precision=precision,
+                                             **dict(SOLVER, levels=rlevels, dtau_carry=0)))
+    t_reset, i_reset, _ = timed_solves(torch, rplan, v_init, run["steps"], 2)
+    del rplan
+    out["dtau_reset"] = {"what": "the pseudo-time step restarted at 1e-3 in every time step (dtau_carry=0), "
+                                 f"{rlevels} levels",
+                         "value": round(cells * run["steps"] / t_reset / 1e6, 3),
+                         "ms_per_step": round(t_reset * 1e3, 3),
+                         "cycles_per_time_step": i_reset["cycles"] / run["steps"], "solver_status": i_reset["status"]}
     # the workload's own finest sweep (cache-resident at 1024^2), then the kernels at an HBM-resident size
     t_own = time_launches(torch, plan.stream, sweep_launcher(plan, b, v_init, sweeps_per_launch()), args.reps)
     own = roofline_entry(sweep_kernel(), f"finest-level FP64 Jacobi sweeps, {sweeps_per_launch()} per launch",

@@ -130,7 +130,13 @@ typedef struct {
  *   precision     M1_FP64 or M1_MIXED (FP32 delta-form smoothing and coarse
  *                 levels, FP64 residual, projection and T^4 update; M1_MIXED
  *                 requires nu_l = 1: its coarse steps fuse one sweep);
- *   dtau_im0      initial implicit pseudo-time step (reset every time step);
+ *   dtau_carry    1 (default): dtau_im runs on from one time step into the
+ *                 next within a call (Algorithm 4, the overall algorithm of
+ *                 Appendix A, does not set it at the start of a time step;
+ *                 Sect. 5 gives its initial value); 0: it restarts at dtau_im0
+ *                 at every time step.  A call always starts at dtau_im0; m1_info.dtau
+ *                 gives the value to start the next call with;
+ *   dtau_im0      initial implicit pseudo-time step (Sect. 5: 1e-3);
  *   eps_inc/dec   adaptation thresholds (x1.1 above eps_inc, /2 below eps_dec);
  *   eta           fraction of the admissible ray used (sub-steps, projection);
  *   rtol          stop when |b - A(v)| <= rtol |b - A(v^n)|;
@@ -139,7 +145,7 @@ typedef struct {
  *                 1 is Algorithm 1, 0 < omega <= 1 keeps admissibility.      */
 typedef struct {
     int32_t levels, nu0, nu_l, pseudo_steps, sub_steps, max_cycles, dtau_rule, pseudo_local, precision, smoother;
-    int32_t cycle, transfer;
+    int32_t cycle, transfer, dtau_carry, pad_;
     double dtau_im0, eps_inc, eps_dec, eta, rtol, dtau_min, dtau_max, omega;
 } m1_params;
 
@@ -217,9 +223,10 @@ m1_status m1_vcycle(m1_plan* plan, m1_state* v, const m1_state* vn, double dtau,
 
 /* nsteps implicit Euler steps (the overall algorithm of Appendix A,
  * Algorithm 4): v holds v^n on entry and v^{n+nsteps} on exit.  Each step sets
- * b = (E^n, F^n, C_v T^n), resets dtau_im to dtau_im0 and runs V-cycles until
- * |b - A(v)| <= rtol |b - A(v^n)| (the relative residual of Sect. 5), adapting
- * dtau_im after every cycle (x1.1 / 0.5 by eps_inc / eps_dec).  Validates the
+ * b = (E^n, F^n, C_v T^n) and runs cycles until |b - A(v)| <= rtol |b - A(v^n)|
+ * (the relative residual of Sect. 5), adapting dtau_im after every cycle
+ * (x1.1 / 0.5 by eps_inc / eps_dec).  dtau_im starts at dtau_im0 and, with
+ * dtau_carry, runs on from step to step; without it, every step restarts it.  Validates the
  * input state first: M1_ERR_NOT_ADMISSIBLE (info->first_bad_cell set, v
  * untouched) if a cell is outside S = {E > 0, |F| <= cE, T > 0}.
  * M1_ERR_NO_CONVERGENCE when a step reaches max_cycles (v then holds that
@@ -238,8 +245,8 @@ m1_status m1_step(m1_plan* plan, m1_state* v, int32_t nsteps, m1_info* info);
  * the bit.  The caller passes grid, parameters, opacity and state (device
  * arrays, as for m1_plan_create and m1_step) and the stream, which must
  * belong to the current device.  80 MiB hold a 2-D plan of up to about
- * 540 K cells in FP64 and 300 K cells in mixed precision (512 x 512: 39 and
- * 69 MiB); problems whose m1_workspace_bytes exceeds M1_STATIC_SCRATCH_BYTES
+ * 540 K cells in FP64 and 290 K cells in mixed precision (512 x 512: 39 and
+ * 71 MiB); problems whose m1_workspace_bytes exceeds M1_STATIC_SCRATCH_BYTES
  * are rejected with M1_ERR_WORKSPACE, invalid arguments with M1_ERR_ARG;
  * otherwise as m1_step (blocks; info may be NULL).  Nothing in the array has
  * to start at zero: every buffer is written before it is read.  All calls on
@@ -485,7 +492,7 @@ m1_status m1_residual3(m1_plan3* plan, const m1_state3* v, const m1_state3* vn, 
 /* One V-cycle (Appendix A) of A(v) = b(vn) with pseudo-time step dtau, in place on v (v must not alias vn). */
 m1_status m1_vcycle3(m1_plan3* plan, m1_state3* v, const m1_state3* vn, double dtau);
 /* nsteps implicit Euler steps in place on v (Appendix A, Algorithm 4), as m1_step: cycles until the relative
- * residual rtol or A's rounding level, dtau reset every step and adapted after every cycle; M1_ERR_NOT_ADMISSIBLE
+ * residual rtol or A's rounding level, dtau carried from step to step (dtau_carry) and adapted after every cycle; M1_ERR_NOT_ADMISSIBLE
  * for a non-admissible input (info->first_bad_cell), M1_ERR_NO_CONVERGENCE after max_cycles.                   */
 m1_status m1_step3(m1_plan3* plan, m1_state3* v, int32_t nsteps, m1_info* info);
 

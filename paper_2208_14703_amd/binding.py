@@ -51,7 +51,7 @@ class m1_grid(ctypes.Structure):
 class m1_params(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int32) for n in ("levels", "nu0", "nu_l", "pseudo_steps", "sub_steps", "max_cycles",
                                               "dtau_rule", "pseudo_local", "precision", "smoother", "cycle",
-                                              "transfer")] + \
+                                              "transfer", "dtau_carry", "pad_")] + \
                [(n, ctypes.c_double) for n in ("dtau_im0", "eps_inc", "eps_dec", "eta", "rtol", "dtau_min",
                                                "dtau_max", "omega")]
 

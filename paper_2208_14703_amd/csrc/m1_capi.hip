@@ -43,9 +43,9 @@ struct LevelBuf {
     double* sa = nullptr;
     double* ss = nullptr;
     // mixed precision (FP32): base w, restricted correction d, iterates e/e2,
-    // right-hand side g, residual rho, opacities
+    // right-hand side g, residual rho, source of the explicit sub-steps fr, opacities
     m1::Lvl32 L32{};
-    Soa32 w{}, d{}, e{}, e2{}, gg{}, rho{};
+    Soa32 w{}, d{}, e{}, e2{}, gg{}, rho{}, fr{};
     float* sa32 = nullptr;
     float* ss32 = nullptr;
 };
@@ -127,6 +127,7 @@ bool valid_params(const m1_params* p)
     if (p->transfer != M1_TRANSFER_FULL && p->precision != M1_FP64) return false;
     if (!(p->eta > 0.0 && p->eta < 1.0) || !(p->omega > 0.0 && p->omega <= 1.0) || !(p->rtol > 0.0)) return false;
     if (!(p->dtau_im0 > 0.0) || !(p->dtau_min > 0.0) || !(p->dtau_max >= p->dtau_min)) return false;
+    if (p->dtau_carry != 0 && p->dtau_carry != 1) return false;
     return std::isfinite(p->eps_inc) && std::isfinite(p->eps_dec);
 }
 
@@ -257,6 +258,7 @@ void carve(m1_plan& P, Carver& c, const Dims& d)
                 lv.e2 = c.soa32(lv.n, dim);
                 lv.gg = c.soa32(lv.n, dim);
                 lv.rho = c.soa32(lv.n, dim);
+                lv.fr = c.soa32(lv.n, dim);
             }
         }
     }
@@ -648,7 +650,7 @@ Soa32 mx_pseudo_smooth(m1_plan& P, int l, const Gate& G, Soa32 start, bool first
     Soa32 in = start;
     for (int m = 0; m < P.params.pseudo_steps; ++m) {
         const Soa32 out = same32(in, c.e) ? c.e2 : c.e;
-        m1::launch_mx_pseudo(P.st, P.dim, P.ph, c.L32, cs(c.w), c.gg, cs(in), out, G.dtau, G.dtau_dev,
+        m1::launch_mx_pseudo(P.st, P.dim, P.ph, c.L32, cs(c.w), c.gg, c.fr, cs(in), out, G.dtau, G.dtau_dev,
                              (float)P.reach, P.params.pseudo_local, first && m == 0, G.active);
         in = out;
     }
@@ -877,6 +879,7 @@ void m1_default_params(m1_params* p)
     p->dtau_rule = M1_DTAU_SIGNED;
     p->pseudo_local = 1;
     p->precision = M1_FP64;
+    p->dtau_carry = 1;
     p->dtau_im0 = 1e-3;
     p->eps_inc = 0.05;
     p->eps_dec = 0.0;
@@ -1007,7 +1010,7 @@ static m1_status plan_init(m1_plan* P, const m1_grid* g, const m1_params* p, con
     ta32.eta = p->eta;
     for (int l = 0; l < P->L && l < m1::kMaxLevels; ++l) {
         const LevelBuf& lv = P->lev[l];
-        ta32.lev[l] = m1::TailLevel32{lv.L32, lv.w, lv.d, lv.e, lv.e2, lv.gg, lv.rho};
+        ta32.lev[l] = m1::TailLevel32{lv.L32, lv.w, lv.d, lv.e, lv.e2, lv.gg, lv.rho, lv.fr};
     }
 
     // opacity validation and the coarse opacity hierarchy
@@ -1192,14 +1195,14 @@ m1_status m1_step(m1_plan* P, m1_state* v, int32_t nsteps, m1_info* info)
         // a residual at the rounding level of evaluating A counts as converged
         const double floor_r = 16.0 * DBL_EPSILON * P->lev[0].L.a * bnorm;
         rel = 0.0;
-        dtau = p.dtau_im0;
+        if (!p.dtau_carry) dtau = p.dtau_im0;  // else the last step's final dtau
         if (info) info->steps_done = step + 1;
         if (r0 <= floor_r) continue;
 
         m1::Ctrl init{};
         init.r0 = r0;
         init.rprev = r0;
-        init.dtau = p.dtau_im0;
+        init.dtau = dtau;
         init.rel = 1.0;
         init.floor_r = floor_r;
         init.rtol = p.rtol;
@@ -1212,7 +1215,7 @@ m1_status m1_step(m1_plan* P, m1_state* v, int32_t nsteps, m1_info* info)
         init.max_cycles = p.max_cycles;
         init.literal = p.dtau_rule == M1_DTAU_LITERAL;
         m1::launch_ctrl_init(P->st, P->dctrl, init);
-        const Gate G{p.dtau_im0, &P->dctrl->dtau, &P->dctrl->active};
+        const Gate G{dtau, &P->dctrl->dtau, &P->dctrl->active};
 
         // Enqueue whole cycles ahead of the host's check; kernels of cycles
         // after convergence exit at once.  Each cycle's first sweep measures the
@@ -1770,6 +1773,7 @@ m1_status rebuild(m1_engine& E)
         c.dtau_max = rp.dtau_max;
         c.max_cycles = rp.max_cycles;
         c.literal = rp.dtau_rule == M1_DTAU_LITERAL;
+        c.carry = rp.dtau_carry;
         b.proto = c;
         for (int l = 0; l < P.L; ++l) {
             m1::BSlot& s = hs[(size_t)i * m1::kMaxLevels + l];
@@ -1795,6 +1799,7 @@ m1_status rebuild(m1_engine& E)
                 t.e2 = lv.e2;
                 t.g = lv.gg;
                 t.rho = lv.rho;
+                t.fr = lv.fr;
                 if (l == 0) {
                     t.base = P.base32;
                     t.r32 = P.r32;

@@ -99,6 +99,7 @@ bool valid_params3(const m1_params* p)
         return false;
     if (!(p->eta > 0.0 && p->eta < 1.0) || !(p->omega > 0.0 && p->omega <= 1.0) || !(p->rtol > 0.0)) return false;
     if (!(p->dtau_im0 > 0.0) || !(p->dtau_min > 0.0) || !(p->dtau_max >= p->dtau_min)) return false;
+    if (p->dtau_carry != 0 && p->dtau_carry != 1) return false;
     return std::isfinite(p->eps_inc) && std::isfinite(p->eps_dec);
 }
 
@@ -540,13 +541,13 @@ m1_status m1_step3(m1_plan3* P, m1_state3* v, int32_t nsteps, m1_info* info)
         if (e != M1_OK) return e;
         const double floor_r = 16.0 * DBL_EPSILON * P->lev[0].L.a * bnorm;  // A's rounding level
         rel = 0.0;
-        dtau = p.dtau_im0;
+        if (!p.dtau_carry) dtau = p.dtau_im0;  // else the last step's final dtau
         if (info) info->steps_done = step + 1;
         if (r0 <= floor_r) continue;
         m1::Ctrl init{};
         init.r0 = r0;
         init.rprev = r0;
-        init.dtau = p.dtau_im0;
+        init.dtau = dtau;
         init.rel = 1.0;
         init.floor_r = floor_r;
         init.rtol = p.rtol;
@@ -559,7 +560,7 @@ m1_status m1_step3(m1_plan3* P, m1_state3* v, int32_t nsteps, m1_info* info)
         init.max_cycles = p.max_cycles;
         init.literal = p.dtau_rule == M1_DTAU_LITERAL;
         m1::launch_ctrl_init(P->st, P->dctrl, init);
-        const Gate3 G{p.dtau_im0, &P->dctrl->dtau, &P->dctrl->active};
+        const Gate3 G{dtau, &P->dctrl->dtau, &P->dctrl->active};
         // whole cycles enqueued ahead of the host's check, each followed by the residual norm and the control
         // update on the device; cycles after the stop exit at once
         m1::Soa3 cur = user, other = P->tmp;

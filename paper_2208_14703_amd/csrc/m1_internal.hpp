@@ -39,6 +39,7 @@ struct Ctrl {
     double r0, rprev, dtau, rel, floor_r, rtol, eps_inc, eps_dec, dtau_min, dtau_max;
     int active, cycles, conv, max_cycles, literal;
     int flip;  // batched mixed precision: the FP64 state of the step is in x1 (toggled by every executed cycle)
+    int carry;  // batched: a step start keeps the dtau the previous step of the request ended with
 };
 
 // One level of the single-workgroup bottom of the V-cycle.
@@ -87,6 +88,7 @@ void launch_check_sigma(hipStream_t st, int64_t n, const double* sa, const doubl
 struct TailLevel32 {
     Lvl32 L;
     Soa32 w, d, e, e2, g, rho;
+    Soa32 fr;  // source of the explicit sub-steps, A(w + d) + R(rho)
 };
 
 struct TailArgs32 {
@@ -112,7 +114,7 @@ struct BSlot {
 // One (problem, level) of a mixed-precision batch: the FP32 buffers of that level.
 struct BSlot32 {
     Lvl32 L;
-    Soa32 w, d, e, e2, g, rho;      // level >= 1
+    Soa32 w, d, e, e2, g, rho, fr;  // level >= 1 (fr: source of the explicit sub-steps)
     Soa32 base, r32, dA, dB, rho0;  // level 0
 };
 
@@ -211,8 +213,10 @@ void launch_mx_residual_restrict(hipStream_t st, const Phys& ph, const Lvl32& L,
                                  float sgn, int px, int py, Soa32 wc, Soa32 dc, Soa32 gc, const int* active);
 void launch_mx_apply(hipStream_t st, int dim, const Phys& ph, const Lvl32& L, CSoa32 w, CSoa32 d, CSoa32 X, float sgn,
                      Soa32 out, const int* active);
-void launch_mx_pseudo(hipStream_t st, int dim, const Phys& ph, const Lvl32& L, CSoa32 w, Soa32 g, CSoa32 e,
-                      Soa32 out, double dtau, const double* dtau_dev, float reach, int local, int first,
+// fr: the source of the explicit sub-steps, A(w + d) + R(rho), formed by the first pseudo-time step of a visit
+// (first != 0) and read by the others.
+void launch_mx_pseudo(hipStream_t st, int dim, const Phys& ph, const Lvl32& L, CSoa32 w, Soa32 g, Soa32 fr,
+                      CSoa32 e, Soa32 out, double dtau, const double* dtau_dev, float reach, int local, int first,
                       const int* active);
 void launch_mx_prolong(hipStream_t st, int dim, const Phys& ph, int nx, int ny, int px, int py, float eta, CSoa32 w,
                        CSoa32 e, CSoa32 ec, CSoa32 dc, Soa32 out, const int* active);

@@ -1190,7 +1190,8 @@ __global__ __launch_bounds__(kBlock) void kb_init_tiles(const BProb* __restrict_
 }
 
 // One block per starting problem: |b| for the rounding floor and a fresh
-// cycle control (state in x0).
+// cycle control (state in x0), its dtau carried over from the request's
+// previous step when the request asks for that.
 __global__ __launch_bounds__(1024) void kb_init_ctrl(const BProb* __restrict__ P, const BSlot* __restrict__ S,
                                                      const int* __restrict__ plist)
 {
@@ -1199,6 +1200,8 @@ __global__ __launch_bounds__(1024) void kb_init_ctrl(const BProb* __restrict__ P
     const double t = block_sum(pb.partials, pb.npart);
     if (threadIdx.x == 0) {
         Ctrl c = pb.proto;
+        // a request's first step finds the plan's stopped control (dtau 0); later ones the last step's dtau
+        if (c.carry && pb.ctrl->dtau > 0.0) c.dtau = pb.ctrl->dtau;
         c.floor_r = 16.0 * DBL_EPSILON * S[p * kMaxLevels].L.a * sqrt(t);
         c.active = 1;
         c.cycles = -1;

@@ -601,15 +601,74 @@ __global__ __launch_bounds__(kBlock32) void k_mx_apply(Phys ph, Lvl32 L, CSoa32 
     mx_apply_cell<DIM>(ph, L, w, d, X, sgn, out, k, i, j, live);
 }
 
+// The source of the explicit sub-steps of a coarse level's pseudo-time solve
+// (Algorithm 3): the level's FAS right-hand side in absolute form,
+// f = A(w + d) + R(rho) (d = R(correction above), g = R(rho) on entry), the
+// same f as the FP64 cycle's.  Formed in FP64 from the FP32 values by the first
+// pseudo-time step of a visit (its neighbour loads are those offdiag_inc has
+// just made) and stored in FP32 for the later ones.
+template <int DIM>
+__device__ __forceinline__ void mx_ray_src(const Phys& ph, const Lvl32& L, const CSoa32& w, const CSoa32& d,
+                                           const Soa32& g, uint32_t k, int i, int j, float f[4])
+{
+    const double c = ph.c, c2 = ph.c2;
+    double S0 = 0.0, S1 = 0.0, S2 = 0.0;
+    float E, Fx, Fy, e, gx, gy;
+    const uint32_t wx = (uint32_t)(L.nx - 1);
+    nb_inc<DIM>(ph, 0, i > 0, in_seg(L, 0, j), i > 0 ? k - 1 : k + wx, k, w, d, E, Fx, Fy, e, gx, gy);
+    add_x((double)L.kx, c, c2, +1.0, (double)E + e, (double)Fx + gx, (double)Fy + gy, S0, S1, S2);
+    nb_inc<DIM>(ph, 1, i < L.nx - 1, in_seg(L, 1, j), i < L.nx - 1 ? k + 1 : k - wx, k, w, d, E, Fx, Fy, e, gx, gy);
+    add_x((double)L.kx, c, c2, -1.0, (double)E + e, (double)Fx + gx, (double)Fy + gy, S0, S1, S2);
+    if (DIM == 2) {
+        const uint32_t nx = (uint32_t)L.nx, wrap = (uint32_t)(L.ny - 1) * nx;
+        nb_inc<DIM>(ph, 2, j > 0, in_seg(L, 2, i), j > 0 ? k - nx : k + wrap, k, w, d, E, Fx, Fy, e, gx, gy);
+        add_y((double)L.ky, c, c2, +1.0, (double)E + e, (double)Fx + gx, (double)Fy + gy, S0, S1, S2);
+        nb_inc<DIM>(ph, 3, j < L.ny - 1, in_seg(L, 3, i), j < L.ny - 1 ? k + nx : k - wrap, k, w, d, E, Fx, Fy, e,
+                    gx, gy);
+        add_y((double)L.ky, c, c2, -1.0, (double)E + e, (double)Fx + gx, (double)Fy + gy, S0, S1, S2);
+    }
+    const double uE = (double)ldf(w.E, k) + ldf(d.E, k), uFx = (double)ldf(w.Fx, k) + ldf(d.Fx, k);
+    const double uFy = (DIM == 2) ? (double)ldf(w.Fy, k) + ldf(d.Fy, k) : 0.0;
+    const double uT = (double)ldf(w.T, k) + ldf(d.T, k);
+    const double ka = (double)L.cdt * ldf(L.sa, k), ks = (double)L.cdt * ldf(L.ss, k);
+    const double T2 = uT * uT;
+    const double ex = ka * fma(-ph.a_r * T2, T2, uE);  // ka (E - a_r T^4)
+    const double a = L.a;
+    f[0] = (float)(ldf(g.E, k) + (fma(a, uE, ex) - S0));
+    f[1] = (float)(ldf(g.Fx, k) + fma(a + ka + ks, uFx, -S1));
+    f[2] = (DIM == 2) ? (float)(ldf(g.Fy, k) + fma(a + ka + ks, uFy, -S2)) : 0.0f;
+    f[3] = (float)(ldf(g.T, k) + fma(ph.c_v, uT, -ex));
+}
+
+// The explicit sub-steps' source of cell k: formed (FIRST; e = d then) or stored.
+template <int DIM, bool FIRST>
+__device__ __forceinline__ void mx_ray_src_at(const Phys& ph, const Lvl32& L, const CSoa32& w, const CSoa32& e,
+                                              const Soa32& g, const Soa32& fr, uint32_t k, int i, int j, float f[4])
+{
+    if (FIRST) {
+        mx_ray_src<DIM>(ph, L, w, e, g, k, i, j, f);
+    } else {
+        f[0] = ldf(fr.E, k);
+        f[1] = ldf(fr.Fx, k);
+        f[2] = (DIM == 2) ? ldf(fr.Fy, k) : 0.0f;
+        f[3] = ldf(fr.T, k);
+    }
+}
+
 // One pseudo-time step of M de/dtau + N_w(e) = g (Algorithm 3 in increment
 // form).  FIRST: e_in = d_l = R(correction above) and g holds R(rho) on entry;
-// g = N_w(d_l) + R(rho) is formed and stored.
-// The step at cell k from its off-diagonal sums S and its correction e.
+// g = N_w(d_l) + R(rho) is formed and stored, and so is the absolute source
+// f = g + A(w) (mx_ray_src).  The explicit sub-steps move u = w + e along f
+// (the FP64 cycle's ray, so that u + tau_i f, the right-hand side of the
+// implicit step, is admissible); the implicit step is the FP64 one,
+// u' + gamma A(u') = u + tau_i f, in increment form:
+// e' + gamma N_w(e') = e + gamma g + (tau_i - gamma) f.
+// The step at cell k from its off-diagonal sums S, its correction e and f.
 template <int DIM, bool FIRST>
 __device__ __forceinline__ void mx_pseudo_finish(const Phys& ph, const Lvl32& L, const CSoa32& w, const Soa32& g,
-                                                 const Soa32& out, float dt, float reach, int local, uint32_t k,
-                                                 float S0, float S1, float S2, float eE, float eFx, float eFy,
-                                                 float eT, bool live)
+                                                 const Soa32& fr, const float f[4], const Soa32& out, float dt,
+                                                 float reach, int local, uint32_t k, float S0, float S1, float S2,
+                                                 float eE, float eFx, float eFy, float eT, bool live)
 {
     const float c2 = (float)ph.c2, cv = (float)ph.c_v;
     const float wE = ldf(w.E, k), wFx = ldf(w.Fx, k), wFy = (DIM == 2) ? ldf(w.Fy, k) : 0.0f, wT = ldf(w.T, k);
@@ -627,15 +686,23 @@ __device__ __forceinline__ void mx_pseudo_finish(const Phys& ph, const Lvl32& L,
             stf(g.Fx, k, gFx);
             if (DIM == 2) stf(g.Fy, k, gFy);
             stf(g.T, k, gT);
+            stf(fr.E, k, f[0]);
+            stf(fr.Fx, k, f[1]);
+            if (DIM == 2) stf(fr.Fy, k, f[2]);
+            stf(fr.T, k, f[3]);
         }
     }
-    const float sT = gT * rcp32(cv);
-    const float ts = ray_len32(c2, wE + eE, wFx + eFx, wFy + eFy, wT + eT, gE, gFx, gFy, sT);
+    const float icv = rcp32(cv);
+    const float fE = f[0], fFx = f[1], fFy = f[2];
+    const float sT = gT * icv, fsT = f[3] * icv;
+    const float ts = ray_len32(c2, wE + eE, wFx + eFx, wFy + eFy, wT + eT, fE, fFx, fFy, fsT);
     if (live && ts == 0.0f && ph.stalls) note_stall(ph.stalls);
     const float tau = fminf(dt, ts * reach);
-    const float tE = fmaf(tau, gE, eE), tFx = fmaf(tau, gFx, eFx), tFy = fmaf(tau, gFy, eFy);
-    const float tT = cv * fmaf(tau, sT, eT);
     const float gm = local ? tau : dt;
+    const float off = tau - gm;  // 0 in the local reading
+    const float tE = fmaf(off, fE, fmaf(gm, gE, eE)), tFx = fmaf(off, fFx, fmaf(gm, gFx, eFx));
+    const float tFy = fmaf(off, fFy, fmaf(gm, gFy, eFy));
+    const float tT = cv * fmaf(off, fsT, fmaf(gm, sT, eT));
     float xE, xFx, xFy, xT;
     local_solve_inc(1.0, gm, L.a, ka, ks, ph.c_v, ph.a_r, fmaf(gm, S0, tE), fmaf(gm, S1, tFx), fmaf(gm, S2, tFy), tT,
                     wT, eT, xE, xFx, xFy, xT);
@@ -648,18 +715,20 @@ __device__ __forceinline__ void mx_pseudo_finish(const Phys& ph, const Lvl32& L,
 
 template <int DIM, bool FIRST>
 __device__ __forceinline__ void mx_pseudo_cell(const Phys& ph, const Lvl32& L, const CSoa32& w, const Soa32& g,
-                                               const CSoa32& e, const Soa32& out, float dt, float reach, int local,
-                                               uint32_t k, int i, int j, bool live = true)
+                                               const Soa32& fr, const CSoa32& e, const Soa32& out, float dt,
+                                               float reach, int local, uint32_t k, int i, int j, bool live = true)
 {
     float S0, S1, S2;
     offdiag_inc<DIM>(ph, L, w, e, i, j, k, S0, S1, S2);
+    float f[4];
+    mx_ray_src_at<DIM, FIRST>(ph, L, w, e, g, fr, k, i, j, f);
     const float eE = ldf(e.E, k), eFx = ldf(e.Fx, k), eFy = (DIM == 2) ? ldf(e.Fy, k) : 0.0f, eT = ldf(e.T, k);
-    mx_pseudo_finish<DIM, FIRST>(ph, L, w, g, out, dt, reach, local, k, S0, S1, S2, eE, eFx, eFy, eT, live);
+    mx_pseudo_finish<DIM, FIRST>(ph, L, w, g, fr, f, out, dt, reach, local, k, S0, S1, S2, eE, eFx, eFy, eT, live);
 }
 
 template <int DIM>
-__global__ __launch_bounds__(kBlock32) void k_mx_pseudo(Phys ph, Lvl32 L, CSoa32 w, Soa32 g, CSoa32 e, Soa32 out,
-                                                        double dtau, const double* __restrict__ dtau_dev,
+__global__ __launch_bounds__(kBlock32) void k_mx_pseudo(Phys ph, Lvl32 L, CSoa32 w, Soa32 g, Soa32 fr, CSoa32 e,
+                                                        Soa32 out, double dtau, const double* __restrict__ dtau_dev,
                                                         float reach, int local, int first,
                                                         const int* __restrict__ active)
 {
@@ -669,8 +738,8 @@ __global__ __launch_bounds__(kBlock32) void k_mx_pseudo(Phys ph, Lvl32 L, CSoa32
     uint32_t k;
     int i, j;
     if (!mx_cell(L.nx, L.ny, L.sh, k, i, j)) return;
-    if (first) mx_pseudo_cell<DIM, true>(ph, L, w, g, e, out, dt, reach, local, k, i, j, live);
-    else mx_pseudo_cell<DIM, false>(ph, L, w, g, e, out, dt, reach, local, k, i, j, live);
+    if (first) mx_pseudo_cell<DIM, true>(ph, L, w, g, fr, e, out, dt, reach, local, k, i, j, live);
+    else mx_pseudo_cell<DIM, false>(ph, L, w, g, fr, e, out, dt, reach, local, k, i, j, live);
 }
 
 // LDS-staged pseudo-time step (2-D, large levels): the staging of
@@ -683,9 +752,9 @@ __global__ __launch_bounds__(kBlock32) void k_mx_pseudo(Phys ph, Lvl32 L, CSoa32
 constexpr int64_t kMxPseudoLdsCells = 524288;
 
 template <int TY, bool FIRST>
-__global__ __launch_bounds__(kMxTX * TY) void k_mx_pseudo_lds(Phys ph, Lvl32 L, CSoa32 w, Soa32 g, CSoa32 e, Soa32 out,
-                                                             const double* __restrict__ dtau_dev, float reach,
-                                                             int local, const int* __restrict__ active)
+__global__ __launch_bounds__(kMxTX * TY) void k_mx_pseudo_lds(Phys ph, Lvl32 L, CSoa32 w, Soa32 g, Soa32 fr,
+                                                             CSoa32 e, Soa32 out, const double* __restrict__ dtau_dev,
+                                                             float reach, int local, const int* __restrict__ active)
 {
     constexpr int W = MxTile<TY>::W;
     __shared__ MxTile<TY> q;
@@ -709,7 +778,9 @@ __global__ __launch_bounds__(kMxTX * TY) void k_mx_pseudo_lds(Phys ph, Lvl32 L, 
     nb(n + 1, L.kx, -1.0f, true);
     nb(n - W, L.ky, +1.0f, false);
     nb(n + W, L.ky, -1.0f, false);
-    mx_pseudo_finish<2, FIRST>(ph, L, w, g, out, dt, reach, local, k, S0, S1, S2, q.e[n], q.gx[n], q.gy[n],
+    float f[4];
+    mx_ray_src_at<2, FIRST>(ph, L, w, e, g, fr, k, i, j, f);
+    mx_pseudo_finish<2, FIRST>(ph, L, w, g, fr, f, out, dt, reach, local, k, S0, S1, S2, q.e[n], q.gx[n], q.gy[n],
                                ldf(e.T, k), true);
 }
 
@@ -950,8 +1021,10 @@ __device__ __forceinline__ Soa32 mx_tail_pseudo(const TailArgs32& A, const TailL
         for (uint32_t k = threadIdx.x; k < n; k += blockDim.x) {
             int i, j;
             ij_of(T.L.nx, T.L.sh, k, i, j);
-            if (first && m == 0) mx_pseudo_cell<DIM, true>(A.ph, T.L, cs(T.w), T.g, cs(in), out, dt, A.reach, A.local, k, i, j);
-            else mx_pseudo_cell<DIM, false>(A.ph, T.L, cs(T.w), T.g, cs(in), out, dt, A.reach, A.local, k, i, j);
+            if (first && m == 0)
+                mx_pseudo_cell<DIM, true>(A.ph, T.L, cs(T.w), T.g, T.fr, cs(in), out, dt, A.reach, A.local, k, i, j);
+            else
+                mx_pseudo_cell<DIM, false>(A.ph, T.L, cs(T.w), T.g, T.fr, cs(in), out, dt, A.reach, A.local, k, i, j);
         }
         __syncthreads();
         in = out;
@@ -1377,10 +1450,10 @@ __global__ __launch_bounds__(kBlock32) void kbm_pseudo(const BProb* __restrict__
     ij_of(s.L.nx, s.L.sh, k, i, j);
     const float dt = (float)pb.ctrl->dtau;
     if (first)
-        mx_pseudo_cell<2, true>(pb.ph, s.L, cs(s.w), s.g, cs(pick32(s, in_sel)), pick32(s, out_sel), dt,
+        mx_pseudo_cell<2, true>(pb.ph, s.L, cs(s.w), s.g, s.fr, cs(pick32(s, in_sel)), pick32(s, out_sel), dt,
                                 (float)pb.reach, pb.local, k, i, j);
     else
-        mx_pseudo_cell<2, false>(pb.ph, s.L, cs(s.w), s.g, cs(pick32(s, in_sel)), pick32(s, out_sel), dt,
+        mx_pseudo_cell<2, false>(pb.ph, s.L, cs(s.w), s.g, s.fr, cs(pick32(s, in_sel)), pick32(s, out_sel), dt,
                                  (float)pb.reach, pb.local, k, i, j);
     }
 }
@@ -1490,8 +1563,8 @@ void launch_mx_apply(hipStream_t st, int dim, const Phys& ph, const Lvl32& L, CS
     MX_DISPATCH(dim, k_mx_apply, nblk((int64_t)L.nx * L.ny), ph, L, w, d, X, sgn, out, active);
 }
 
-void launch_mx_pseudo(hipStream_t st, int dim, const Phys& ph, const Lvl32& L, CSoa32 w, Soa32 g, CSoa32 e,
-                      Soa32 out, double dtau, const double* dtau_dev, float reach, int local, int first,
+void launch_mx_pseudo(hipStream_t st, int dim, const Phys& ph, const Lvl32& L, CSoa32 w, Soa32 g, Soa32 fr,
+                      CSoa32 e, Soa32 out, double dtau, const double* dtau_dev, float reach, int local, int first,
                       const int* active)
 {
     const int rows = mx_sweep_rows();
@@ -1501,10 +1574,10 @@ void launch_mx_pseudo(hipStream_t st, int dim, const Phys& ph, const Lvl32& L, C
 #define M1_MX_PSEUDO_LDS(R)                                                                                           \
     do {                                                                                                              \
         if (first)                                                                                                    \
-            hipLaunchKernelGGL((k_mx_pseudo_lds<R, true>), gl, bl, 0, st, ph, L, w, g, e, out, dtau_dev, reach, local, \
-                               active);                                                                               \
+            hipLaunchKernelGGL((k_mx_pseudo_lds<R, true>), gl, bl, 0, st, ph, L, w, g, fr, e, out, dtau_dev, reach,    \
+                               local, active);                                                                        \
         else                                                                                                          \
-            hipLaunchKernelGGL((k_mx_pseudo_lds<R, false>), gl, bl, 0, st, ph, L, w, g, e, out, dtau_dev, reach,       \
+            hipLaunchKernelGGL((k_mx_pseudo_lds<R, false>), gl, bl, 0, st, ph, L, w, g, fr, e, out, dtau_dev, reach,   \
                                local, active);                                                                        \
     } while (0)
         if (rows == 4) M1_MX_PSEUDO_LDS(4);
@@ -1513,7 +1586,7 @@ void launch_mx_pseudo(hipStream_t st, int dim, const Phys& ph, const Lvl32& L, C
 #undef M1_MX_PSEUDO_LDS
         return;
     }
-    MX_DISPATCH(dim, k_mx_pseudo, nblk((int64_t)L.nx * L.ny), ph, L, w, g, e, out, dtau, dtau_dev, reach, local,
+    MX_DISPATCH(dim, k_mx_pseudo, nblk((int64_t)L.nx * L.ny), ph, L, w, g, fr, e, out, dtau, dtau_dev, reach, local,
                 first, active);
 }
 
