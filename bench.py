@@ -121,7 +121,8 @@ def parse():
                     help="default: fp64 for hotwall, mixed for lognormal")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-cycles", type=int, default=60, help="oracle V-cycles in the CPU-baseline sample")
-    ap.add_argument("--no-extras", action="store_true", help="skip the batched and serving legs")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the other dtau reading, C1, C3, 3-D, batched and serving legs")
     ap.add_argument("--batch", type=int, default=256, help="problems in the batched leg")
     ap.add_argument("--requests", type=int, default=48, help="requests per rate in the serving leg")
     ap.add_argument("--rates", default="50", help="comma-separated arrival rates (1/s) for serving")
@@ -555,6 +556,21 @@ SERVE_DESC = ("Poisson stream, side log-uniform in 64..2048, contrast 10^U[0,6],
 
 
 # ---------------------------------------------------------------------------
+def reset_leg(torch, out, args, prob, dev_sig, v_init, run, precision, cells):
+    """The whole solve with the pseudo-time step restarted at 1e-3 in every time step (dtau_carry=0), at that
+    reading's own fastest depth."""
+    rlevels = RESET_LEVELS[args.workload] if args.levels < 0 else args.levels
+    rplan = binding.Plan(prob, dev_sig, dict(rtol=run["rtol"], max_cycles=20000, precision=precision,
+                                             **dict(SOLVER, levels=rlevels, dtau_carry=0)))
+    t_reset, i_reset, _ = timed_solves(torch, rplan, v_init, run["steps"], 2)
+    del rplan
+    out["dtau_reset"] = {"what": "the pseudo-time step restarted at 1e-3 in every time step (dtau_carry=0), "
+                                 f"{rlevels} levels",
+                         "value": round(cells * run["steps"] / t_reset / 1e6, 3),
+                         "ms_per_step": round(t_reset * 1e3, 3),
+                         "cycles_per_time_step": i_reset["cycles"] / run["steps"], "solver_status": i_reset["status"]}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -645,16 +661,8 @@ def main():
         "launch_shapes": {k: binding.tune_get(k) for k in binding.TUNE_ENV},
     }
     # the other reading of the pseudo-time step across time steps: restarted at 1e-3 in every time step
-    rlevels = RESET_LEVELS[args.workload] if args.levels < 0 else args.levels
-    rplan = binding.Plan(prob, dev_sig, dict(rtol=run["rtol"], max_cycles=20000, precision=precision,
-                                             **dict(SOLVER, levels=rlevels, dtau_carry=0)))
-    t_reset, i_reset, _ = timed_solves(torch, rplan, v_init, run["steps"], 2)
-    del rplan
-    out["dtau_reset"] = {"what": "the pseudo-time step restarted at 1e-3 in every time step (dtau_carry=0), "
-                                 f"{rlevels} levels",
-                         "value": round(cells * run["steps"] / t_reset / 1e6, 3),
-                         "ms_per_step": round(t_reset * 1e3, 3),
-                         "cycles_per_time_step": i_reset["cycles"] / run["steps"], "solver_status": i_reset["status"]}
+    if not args.no_extras:
+        reset_leg(torch, out, args, prob, dev_sig, v_init, run, precision, cells)
     # the workload's own finest sweep (cache-resident at 1024^2), then the kernels at an HBM-resident size
     t_own = time_launches(torch, plan.stream, sweep_launcher(plan, b, v_init, sweeps_per_launch()), args.reps)
     own = roofline_entry(sweep_kernel(), f"finest-level FP64 Jacobi sweeps, {sweeps_per_launch()} per launch",
