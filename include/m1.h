@@ -401,7 +401,8 @@ m1_status m1_batch_release(m1_engine* e, uint64_t ticket);
 /* HBM of the engine's request pool (the part of the arena that request
  * workspaces are carved from; the rest holds the device tables): bytes in use
  * and in total, and the numbers of resident and waiting requests (either
- * pointer may be NULL).  Waits for a running round to end.                   */
+ * pointer may be NULL).  Does not wait for a running round: the figures are
+ * those of the last admission or retirement.                                 */
 m1_status m1_engine_memory(m1_engine* e, size_t* pool_in_use, size_t* pool_bytes, int32_t* resident,
                            int32_t* pending);
 

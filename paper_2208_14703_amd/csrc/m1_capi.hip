@@ -1553,7 +1553,10 @@ struct m1_engine {
     // entry: its control stays inactive in its freed (not yet reused) workspace, so the
     // tables stay valid without a rebuild until the next admission or compaction.
     std::vector<m1_req*> running;
-    int live = 0;
+    // resident requests and the pool bytes they hold; atomic, so that m1_engine_memory reads them without
+    // waiting for a round (a serving loop runs rounds back to back and would hold it off)
+    std::atomic<int> live{0};
+    std::atomic<size_t> pool_used{0};
     int64_t live_tiles = 0, dead_tiles = 0;
     std::unordered_map<uint64_t, m1_req*> reqs;
     uint64_t next = 1;
@@ -1604,6 +1607,7 @@ bool pool_alloc(m1_engine& E, size_t bytes, size_t& off)
             const size_t rest = it->second - bytes;
             E.free_.erase(it);
             if (rest) E.free_[off + bytes] = rest;
+            E.pool_used += bytes;
             return true;
         }
     }
@@ -1613,6 +1617,7 @@ bool pool_alloc(m1_engine& E, size_t bytes, size_t& off)
 void pool_free(m1_engine& E, size_t off, size_t bytes)
 {
     bytes = align_up(bytes);
+    E.pool_used -= bytes;
     auto it = E.free_.emplace(off, bytes).first;
     auto nx = std::next(it);
     if (nx != E.free_.end() && it->first + it->second == nx->first) {
@@ -2302,12 +2307,9 @@ m1_status m1_engine_memory(m1_engine* E, size_t* pool_in_use, size_t* pool_bytes
                            int32_t* pending)
 {
     if (!E || !pool_in_use || !pool_bytes) return M1_ERR_ARG;
-    std::lock_guard<std::mutex> lk(E->rmu);  // the pool changes inside rounds
-    size_t free_bytes = 0;
-    for (const auto& f : E->free_) free_bytes += f.second;
     *pool_bytes = E->pool_bytes;
-    *pool_in_use = E->pool_bytes - free_bytes;
-    if (resident) *resident = E->live;
+    *pool_in_use = E->pool_used.load();
+    if (resident) *resident = E->live.load();
     if (pending) {
         std::lock_guard<std::mutex> q(E->qmu);
         *pending = (int32_t)E->pending.size();

@@ -143,10 +143,18 @@ struct LdsTile {
     double E[N], Fx[N], Fy[N], XX[N], XY[N], YY[N];
 };
 
+// Whether the 64 x TY tile at (i0, j0) and its one-cell halo lie inside the
+// grid (no ghost, wrap or ragged edge).
+__device__ __forceinline__ bool tile_interior(const Lvl& L, int ty, int i0, int j0)
+{
+    return i0 >= 1 && j0 >= 1 && i0 + kLdsTX + 1 <= L.nx && j0 + ty + 1 <= L.ny;
+}
+
 // Stage the tile at (i0, j0) of state u.  UP: each gathered state is first
 // corrected from the coarse level (uc, vc) and projected (prolong_value, as
-// k_prolong_project) and its temperature kept in qT.
-template <int TY, bool UP>
+// k_prolong_project) and its temperature kept in qT.  INTERIOR: the tile is
+// tile_interior, and the side logic drops out (same arithmetic, same result).
+template <int TY, bool UP, bool INTERIOR = false>
 __device__ __forceinline__ void stage_tile(LdsTile<TY>& q, double* qT, const Phys& ph, const Lvl& L, const CSoa& u,
                                            int i0, int j0, const CSoa& uc, const CSoa& vc, int px, int py, double eta)
 {
@@ -158,8 +166,8 @@ __device__ __forceinline__ void stage_tile(LdsTile<TY>& q, double* qT, const Phy
     // (or the periodic image); corners and points past a ragged edge are unused
     auto gather = [&](int li, int lj) {
         int gi = i0 + li, gj = j0 + lj, side = 0;
-        const bool ox = gi < 0 || gi >= L.nx, oy = gj < 0 || gj >= L.ny;
-        const bool need = gi <= L.nx && gj <= L.ny && !(ox && oy);
+        const bool ox = !INTERIOR && (gi < 0 || gi >= L.nx), oy = !INTERIOR && (gj < 0 || gj >= L.ny);
+        const bool need = INTERIOR || (gi <= L.nx && gj <= L.ny && !(ox && oy));
         if (ox) {
             side = gi < 0 ? 0 : 1;
             gi = perx ? (gi < 0 ? gi + L.nx : gi - L.nx) : (gi < 0 ? 0 : L.nx - 1);
@@ -240,7 +248,8 @@ __global__ __launch_bounds__(kLdsTX * TY) void k_relax_lds(Phys ph, Lvl L, CSoa 
     if (*active == 0) return;
     int i0, j0;
     tile_origin(L, TY, i0, j0);
-    stage_tile<TY, UP>(q, qT, ph, L, u, i0, j0, uc, vc, px, py, eta);
+    if (tile_interior(L, TY, i0, j0)) stage_tile<TY, UP, true>(q, qT, ph, L, u, i0, j0, uc, vc, px, py, eta);
+    else stage_tile<TY, UP>(q, qT, ph, L, u, i0, j0, uc, vc, px, py, eta);
     __syncthreads();
     const int li = threadIdx.x % kLdsTX, lj = threadIdx.x / kLdsTX, i = i0 + li, j = j0 + lj;
     if (i >= L.nx || j >= L.ny) return;
@@ -323,8 +332,18 @@ __device__ __forceinline__ void lds_put(double* const* f, const Phys& ph, int c,
     f[5][c] = p_yy(p, fy);
 }
 
-// The two sweeps of the tile at (i0, j0); every thread of the block calls it.
+// Whether the two-sweep tile at (i0, j0) and its 2-cell halo lie inside the
+// grid: then no ghost, wrap or ragged edge applies.
 template <int TY>
+__device__ __forceinline__ bool pair_interior(const Lvl& L, int i0, int j0)
+{
+    return i0 >= 2 && j0 >= 2 && i0 + kLdsTX + 2 <= L.nx && j0 + TY + 2 <= L.ny;
+}
+
+// The two sweeps of the tile at (i0, j0); every thread of the block calls it.
+// INTERIOR: the tile is pair_interior, and the side logic drops out (the
+// arithmetic, and so the result, is the same).
+template <int TY, bool INTERIOR = false>
 __device__ __forceinline__ void relax2_tile(Lds2<TY>& q, const Phys& ph, const Lvl& L, const CSoa& rhs, double omega,
                                             const CSoa& u, const Soa& out, int i0, int j0)
 {
@@ -332,7 +351,8 @@ __device__ __forceinline__ void relax2_tile(Lds2<TY>& q, const Phys& ph, const L
     constexpr int NT = kLdsTX * TY, NR = 2 * kLdsTX + 2 * TY;  // threads; ring points
     static_assert(NR <= NT, "one ring point per thread");
     const bool perx = ph.bc[0] == BC_PERIODIC, pery = ph.bc[2] == BC_PERIODIC;
-    const int xe = min(i0 + kLdsTX, L.nx) - 1, ye = min(j0 + TY, L.ny) - 1;  // the last final cell
+    const int xe = INTERIOR ? i0 + kLdsTX - 1 : min(i0 + kLdsTX, L.nx) - 1;  // the last final cell
+    const int ye = INTERIOR ? j0 + TY - 1 : min(j0 + TY, L.ny) - 1;
     // the plus of half-widths (a, b) around the final cells holds (gi, gj)
     auto plus = [&](int gi, int gj, int a, int b) {
         return (gi >= i0 && gi <= xe && gj >= j0 - a && gj <= ye + a) ||
@@ -348,10 +368,12 @@ __device__ __forceinline__ void relax2_tile(Lds2<TY>& q, const Phys& ph, const L
     // 1. stage the state (boundary rule on ghosts) and its closures
     for (int p = threadIdx.x; p < Q::N2; p += NT) {
         const int gi = i0 + p % Q::W2 - 2, gj = j0 + p / Q::W2 - 2;
-        int si, sj;
-        bool gx, gy, nx_, ny_;
-        rc_axis(gi, L.nx, perx, si, gx, nx_);
-        rc_axis(gj, L.ny, pery, sj, gy, ny_);
+        int si = gi, sj = gj;
+        bool gx = false, gy = false, nx_ = true, ny_ = true;
+        if (!INTERIOR) {
+            rc_axis(gi, L.nx, perx, si, gx, nx_);
+            rc_axis(gj, L.ny, pery, sj, gy, ny_);
+        }
         if (plus(gi, gj, 2, 1) && nx_ && ny_ && !(gx && gy)) {
             const uint32_t k = (uint32_t)sj * (uint32_t)L.nx + (uint32_t)si;
             const int side = gx ? (gi < 0 ? 0 : 1) : (gj < 0 ? 2 : 3);
@@ -383,10 +405,12 @@ __device__ __forceinline__ void relax2_tile(Lds2<TY>& q, const Phys& ph, const L
         if (m == 1 && t >= NR) continue;
         const int gi = i0 + li[m], gj = j0 + lj[m];
         if (!plus(gi, gj, 1, 0)) continue;
-        int si, sj;
-        bool gx, gy, nx_, ny_;
-        rc_axis(gi, L.nx, perx, si, gx, nx_);
-        rc_axis(gj, L.ny, pery, sj, gy, ny_);
+        int si = gi, sj = gj;
+        bool gx = false, gy = false, nx_ = true, ny_ = true;
+        if (!INTERIOR) {
+            rc_axis(gi, L.nx, perx, si, gx, nx_);
+            rc_axis(gj, L.ny, pery, sj, gy, ny_);
+        }
         if (gx || gy) {  // the plus holds no corner: only one side is off the domain
             kind[m] = 2;
             gsx[m] = si;
@@ -407,7 +431,7 @@ __device__ __forceinline__ void relax2_tile(Lds2<TY>& q, const Phys& ph, const L
     for (int m = 0; m < 2; ++m)
         if (kind[m] == 1) lds_put(f1, ph, (lj[m] + 1) * Q::W1 + li[m] + 1, vE[m], vFx[m], vFy[m]);
     // 3. ghosts of the iterate (only tiles on a non-periodic side have any)
-    const bool edge = (!perx && (i0 == 0 || xe == L.nx - 1)) || (!pery && (j0 == 0 || ye == L.ny - 1));
+    const bool edge = !INTERIOR && ((!perx && (i0 == 0 || xe == L.nx - 1)) || (!pery && (j0 == 0 || ye == L.ny - 1)));
     if (edge) {
         __syncthreads();
 #pragma unroll
@@ -425,7 +449,7 @@ __device__ __forceinline__ void relax2_tile(Lds2<TY>& q, const Phys& ph, const L
     __syncthreads();
     // 4. second sweep on the final cells
     const int i = i0 + li[0], j = j0 + lj[0];
-    if (i < L.nx && j < L.ny) {
+    if (INTERIOR || (i < L.nx && j < L.ny)) {
         const uint32_t k = (uint32_t)j * (uint32_t)L.nx + (uint32_t)i;
         const int c = (lj[0] + 1) * Q::W1 + li[0] + 1;
         double S0, S1, S2;
@@ -446,7 +470,8 @@ __global__ __launch_bounds__(kLdsTX * TY) __attribute__((amdgpu_waves_per_eu(6))
     if (*active == 0) return;
     int i0, j0;
     tile_origin(L, TY, i0, j0);
-    relax2_tile<TY>(q, ph, L, rhs, omega, u, out, i0, j0);
+    if (pair_interior<TY>(L, i0, j0)) relax2_tile<TY, true>(q, ph, L, rhs, omega, u, out, i0, j0);
+    else relax2_tile<TY>(q, ph, L, rhs, omega, u, out, i0, j0);
 }
 
 // ---------------------------------------------------------------------------
@@ -478,8 +503,19 @@ struct RcLds {
 };
 static_assert(RcLds::NR <= RcLds::NS, "residuals are kept in the closure arrays");
 
+// Whether every point the tile at (I0, J0) stages lies inside the grid: then no
+// ghost, wrap or clamp applies, every residual point and coarse cell of the
+// tile exists and the restriction weights are (1/4, 1/2, 1/4) on both axes.
+__device__ __forceinline__ bool rc_interior(const Lvl& L, int I0, int J0)
+{
+    return I0 >= 1 && J0 >= 1 && 2 * (I0 + kRcW) <= L.nx - 1 && 2 * (J0 + kRcH) <= L.ny - 1;
+}
+
 // The fused residual and restriction of the coarse tile at (I0, J0) (all
-// threads of the block take part; no thread returns early).
+// threads of the block take part; no thread returns early).  INTERIOR: the
+// tile is rc_interior, and the side logic drops out; the arithmetic, and so
+// the result, is the same.
+template <bool INTERIOR>
 __device__ __forceinline__ void residual_restrict_tile(RcLds& sm, const Phys& ph, const Lvl& L, const CSoa& u,
                                                        const CSoa& X, double sgn, int px, int py, const Soa& vc,
                                                        const Soa& rc, int I0, int J0, bool live)
@@ -488,37 +524,43 @@ __device__ __forceinline__ void residual_restrict_tile(RcLds& sm, const Phys& ph
     constexpr int RPT = (NR + kRcThreads - 1) / kRcThreads;  // residual points per thread
     const int nxc = L.nx / 2, nyc = L.ny / 2;
     const int fi0 = 2 * I0, fj0 = 2 * J0;
-    // Each residual point's own loads (opacities, right-hand side, temperature) are issued first, so that
-    // their latency overlaps the staging.  A point dropped at a non-periodic side reads the clamped cell.
-    double own[RPT][7];
-    bool has[RPT];
-#pragma unroll
-    for (int it = 0; it < RPT; ++it) {
+    // A residual point's own loads (opacities, temperature, right-hand side); false for points past the grid,
+    // which belong to no coarse cell.  A point dropped at a non-periodic side reads the clamped cell.
+    auto own_point = [&](int it, double o[7]) {
         const int q = threadIdx.x + it * kRcThreads;
         const int gi = fi0 + q % kRrW - 1, gj = fj0 + q / kRrW - 1;
-        has[it] = q < NR && gi < L.nx && gj < L.ny;  // points past the grid belong to no coarse cell
+        const bool h = q < NR && (INTERIOR || (gi < L.nx && gj < L.ny));
 #pragma unroll
-        for (int m = 0; m < 7; ++m) own[it][m] = 0.0;
-        if (has[it]) {
-            const int si = gi < 0 ? (px ? gi + L.nx : 0) : gi, sj = gj < 0 ? (py ? gj + L.ny : 0) : gj;
+        for (int m = 0; m < 7; ++m) o[m] = 0.0;
+        if (h) {
+            const int si = (INTERIOR || gi >= 0) ? gi : (px ? gi + L.nx : 0);
+            const int sj = (INTERIOR || gj >= 0) ? gj : (py ? gj + L.ny : 0);
             const uint32_t k = (uint32_t)sj * (uint32_t)L.nx + (uint32_t)si;
-            own[it][0] = ld(L.sa, k);
-            own[it][1] = ld(L.ss, k);
-            own[it][2] = ld(u.T, k);
+            o[0] = ld(L.sa, k);
+            o[1] = ld(L.ss, k);
+            o[2] = ld(u.T, k);
             if (X.E) {
-                own[it][3] = ld(X.E, k);
-                own[it][4] = ld(X.Fx, k);
-                own[it][5] = ld(X.Fy, k);
-                own[it][6] = ld(X.T, k);
+                o[3] = ld(X.E, k);
+                o[4] = ld(X.Fx, k);
+                o[5] = ld(X.Fy, k);
+                o[6] = ld(X.T, k);
             }
         }
-    }
+        return h;
+    };
+    // The first point's loads are issued before the staging, so that their latency overlaps it; the few
+    // threads with a second point load it when they reach it (registers held across the staging cost
+    // occupancy).
+    double own0[7];
+    const bool has0 = own_point(0, own0);
     for (int q = threadIdx.x; q < NS; q += kRcThreads) {
         const int gi = fi0 + q % kRsW - 2, gj = fj0 + q / kRsW - 2;
-        int si, sj;
-        bool hx, hy, nx_, ny_;
-        rc_axis(gi, L.nx, px != 0, si, hx, nx_);
-        rc_axis(gj, L.ny, py != 0, sj, hy, ny_);
+        int si = gi, sj = gj;
+        bool hx = false, hy = false, nx_ = true, ny_ = true;
+        if (!INTERIOR) {
+            rc_axis(gi, L.nx, px != 0, si, hx, nx_);
+            rc_axis(gj, L.ny, py != 0, sj, hy, ny_);
+        }
         double e = 0.0, fx = 0.0, fy = 0.0, xx = 0.0, xy = 0.0, yy = 0.0;
         if (nx_ && ny_ && !(hx && hy)) {
             const int side = hx ? (gi < 0 ? 0 : 1) : (hy ? (gj < 0 ? 2 : 3) : 0);
@@ -540,8 +582,8 @@ __device__ __forceinline__ void residual_restrict_tile(RcLds& sm, const Phys& ph
     __syncthreads();
     // staged index of the cell a residual point (fine offsets ri, rj) reads
     auto centre = [&](int ri, int rj) {
-        if (fi0 + ri < 0 && !px) ri += 1;
-        if (fj0 + rj < 0 && !py) rj += 1;
+        if (!INTERIOR && fi0 + ri < 0 && !px) ri += 1;
+        if (!INTERIOR && fj0 + rj < 0 && !py) rj += 1;
         return (rj + 2) * kRsW + ri + 2;
     };
     double res[RPT][4];
@@ -549,7 +591,15 @@ __device__ __forceinline__ void residual_restrict_tile(RcLds& sm, const Phys& ph
     for (int it = 0; it < RPT; ++it) {
         const int q = threadIdx.x + it * kRcThreads;
         double rE = 0.0, rFx = 0.0, rFy = 0.0, rT = 0.0;
-        if (has[it]) {
+        double o[7];
+        bool h = has0;
+        if (it == 0) {
+#pragma unroll
+            for (int m = 0; m < 7; ++m) o[m] = own0[m];
+        } else {
+            h = own_point(it, o);
+        }
+        if (h) {
             const int c = centre(q % kRrW - 1, q / kRrW - 1);
             double S0 = 0.0, S1 = 0.0, S2 = 0.0;  // the order of offdiag: x-, x+, y-, y+
             acc_x(L.kx, ph.c, +1.0, sm.sE[c - 1], sm.sFx[c - 1], sm.sFy[c - 1], sm.sXX[c - 1], sm.sXY[c - 1], S0, S1,
@@ -560,8 +610,8 @@ __device__ __forceinline__ void residual_restrict_tile(RcLds& sm, const Phys& ph
                   sm.sYY[c - kRsW], S0, S1, S2);
             acc_y(L.ky, ph.c, -1.0, sm.sE[c + kRsW], sm.sFx[c + kRsW], sm.sFy[c + kRsW], sm.sXY[c + kRsW],
                   sm.sYY[c + kRsW], S0, S1, S2);
-            apply_values_from<2>(ph, L, sm.sE[c], sm.sFx[c], sm.sFy[c], own[it][2], S0, S1, S2, own[it][0],
-                                 own[it][1], X.E ? &own[it][3] : nullptr, sgn, rE, rFx, rFy, rT);
+            apply_values_from<2>(ph, L, sm.sE[c], sm.sFx[c], sm.sFy[c], o[2], S0, S1, S2, o[0], o[1],
+                                 X.E ? &o[3] : nullptr, sgn, rE, rFx, rFy, rT);
         }
         res[it][0] = rE;
         res[it][1] = rFx;
@@ -585,11 +635,20 @@ __device__ __forceinline__ void residual_restrict_tile(RcLds& sm, const Phys& ph
     static_assert(kRcThreads == 4 * NC, "four groups of threads, two restricted fields each");
     const int cc = threadIdx.x % NC, grp = threadIdx.x / NC;
     const int ci = cc % kRcW, cj = cc / kRcW, I = I0 + ci, J = J0 + cj;
-    if (I < nxc && J < nyc && live) {
+    if ((INTERIOR || (I < nxc && J < nyc)) && live) {
         int ix[3], iy[3];
         double wx[3], wy[3];
-        rweights(I, L.nx, px != 0, ix, wx);
-        rweights(J, L.ny, py != 0, iy, wy);
+        if (INTERIOR) {  // the weights rweights gives inside the grid
+#pragma unroll
+            for (int m = 0; m < 3; ++m) {
+                ix[m] = 2 * I - 1 + m;
+                iy[m] = 2 * J - 1 + m;
+                wx[m] = wy[m] = (m == 1) ? 0.5 : 0.25;
+            }
+        } else {
+            rweights(I, L.nx, px != 0, ix, wx);
+            rweights(J, L.ny, py != 0, iy, wy);
+        }
         // fine cell 2I-1+a, 2J-1+b: residual index (2cj+b) kRrW + 2ci+a, staged cell centre(2ci+a-1, 2cj+b-1),
         // global cell (ix[a], iy[b]); all three name the cells restrict_cell reads, in its order
         auto restrict9 = [&](auto&& value, double* dst) {
@@ -635,7 +694,9 @@ __global__ __launch_bounds__(kRcThreads) void k_residual_restrict(Phys ph, Lvl L
     const bool live = active[lane_zero()] != 0;
     const int ntx = (L.nx / 2 + kRcW - 1) / kRcW;
     const int b = (int)xcd_block();
-    residual_restrict_tile(sm, ph, L, u, X, sgn, px, py, vc, rc, (b % ntx) * kRcW, (b / ntx) * kRcH, live);
+    const int I0 = (b % ntx) * kRcW, J0 = (b / ntx) * kRcH;
+    if (rc_interior(L, I0, J0)) residual_restrict_tile<true>(sm, ph, L, u, X, sgn, px, py, vc, rc, I0, J0, live);
+    else residual_restrict_tile<false>(sm, ph, L, u, X, sgn, px, py, vc, rc, I0, J0, live);
 }
 
 
@@ -677,7 +738,8 @@ __global__ __launch_bounds__(kLdsTX * TY) void k_pseudo_lds(Phys ph, Lvl L, Soa 
     const bool live = active[z] != 0;
     int i0, j0;
     tile_origin(L, TY, i0, j0);
-    stage_tile<TY, false>(q, nullptr, ph, L, u, i0, j0, CSoa{}, CSoa{}, 0, 0, 0.0);
+    if (tile_interior(L, TY, i0, j0)) stage_tile<TY, false, true>(q, nullptr, ph, L, u, i0, j0, CSoa{}, CSoa{}, 0, 0, 0.0);
+    else stage_tile<TY, false>(q, nullptr, ph, L, u, i0, j0, CSoa{}, CSoa{}, 0, 0, 0.0);
     __syncthreads();
     const int li = threadIdx.x % kLdsTX, lj = threadIdx.x / kLdsTX, i = i0 + li, j = j0 + lj;
     if (i >= L.nx || j >= L.ny) return;
@@ -963,8 +1025,11 @@ __global__ __launch_bounds__(kRcThreads) void kb_residual_restrict(
         const Soa& u = (level == 1) ? (in_sel ? f.x1 : f.x0) : pick(f, in_sel);
         const Soa& X = (level == 1) ? f.b : f.f;
         const uint32_t ntx = (uint32_t)((f.L.nx / 2 + kRcW - 1) / kRcW);
-        residual_restrict_tile(sm, pb.ph, f.L, cs(u), cs(X), -1.0, pb.px, pb.py, c.v, c.f,
-                               (int)(tile % ntx) * kRcW, (int)(tile / ntx) * kRcH, true);
+        const int I0 = (int)(tile % ntx) * kRcW, J0 = (int)(tile / ntx) * kRcH;
+        if (rc_interior(f.L, I0, J0))
+            residual_restrict_tile<true>(sm, pb.ph, f.L, cs(u), cs(X), -1.0, pb.px, pb.py, c.v, c.f, I0, J0, true);
+        else
+            residual_restrict_tile<false>(sm, pb.ph, f.L, cs(u), cs(X), -1.0, pb.px, pb.py, c.v, c.f, I0, J0, true);
         __syncthreads();  // the next tile of this block reuses the LDS
     }
 }
@@ -993,9 +1058,16 @@ __global__ __launch_bounds__(kLdsTX * TY) void kb_relax_lds(const BProb* __restr
         const Soa& out = in_x1 ? s.x0 : s.x1;
         const uint32_t ntx = (uint32_t)((s.L.nx + kLdsTX - 1) / kLdsTX);
         const int i0 = (int)(tile % ntx) * kLdsTX, j0 = (int)(tile / ntx) * TY;
+        const bool inner = tile_interior(s.L, TY, i0, j0);
         if (UP) {
             const BSlot& cl = S[p * kMaxLevels + 1];
-            stage_tile<TY, true>(q, qT, pb.ph, s.L, cs(in), i0, j0, cs(cl.u), cs(cl.v), pb.px, pb.py, pb.eta);
+            if (inner)
+                stage_tile<TY, true, true>(q, qT, pb.ph, s.L, cs(in), i0, j0, cs(cl.u), cs(cl.v), pb.px, pb.py,
+                                           pb.eta);
+            else
+                stage_tile<TY, true>(q, qT, pb.ph, s.L, cs(in), i0, j0, cs(cl.u), cs(cl.v), pb.px, pb.py, pb.eta);
+        } else if (inner) {
+            stage_tile<TY, false, true>(q, nullptr, pb.ph, s.L, cs(in), i0, j0, CSoa{}, CSoa{}, 0, 0, 0.0);
         } else {
             stage_tile<TY, false>(q, nullptr, pb.ph, s.L, cs(in), i0, j0, CSoa{}, CSoa{}, 0, 0, 0.0);
         }
@@ -1033,8 +1105,9 @@ __global__ __launch_bounds__(kLdsTX * TY) void kb_relax2_lds(
         const Soa& in = in_x1 ? s.x1 : s.x0;
         const Soa& out = in_x1 ? s.x0 : s.x1;
         const uint32_t ntx = (uint32_t)((s.L.nx + kLdsTX - 1) / kLdsTX);
-        relax2_tile<TY>(q, pb.ph, s.L, cs(s.b), pb.omega, cs(in), out, (int)(tile % ntx) * kLdsTX,
-                        (int)(tile / ntx) * TY);
+        const int i0 = (int)(tile % ntx) * kLdsTX, j0 = (int)(tile / ntx) * TY;
+        if (pair_interior<TY>(s.L, i0, j0)) relax2_tile<TY, true>(q, pb.ph, s.L, cs(s.b), pb.omega, cs(in), out, i0, j0);
+        else relax2_tile<TY>(q, pb.ph, s.L, cs(s.b), pb.omega, cs(in), out, i0, j0);
         __syncthreads();  // the next tile of this block reuses the LDS
     }
 }

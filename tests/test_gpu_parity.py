@@ -215,11 +215,14 @@ def test_local_solve_extremes(omega):
     assert eE.max() <= 1e-12 and eF.max() <= 1e-12 and eT.max() <= 1e-12, (eE.max(), eF.max(), eT.max())
 
 
-@pytest.mark.parametrize("nx,ny,bcs", [(100, 37, "mixed"), (64, 64, "periodic"), (130, 70, "wall"), (3, 5, "xper")])
+@pytest.mark.parametrize("nx,ny,bcs", [(100, 37, "mixed"), (64, 64, "periodic"), (130, 70, "wall"), (3, 5, "xper"),
+                                        (260, 52, "periodic"), (200, 90, "mixed")])
 def test_sweeps_match_chained_sweeps(nx, ny, bcs):
     """m1_sweeps(n) -- fused pairs, and one single sweep for odd n -- gives n
     chained m1_sweep calls to the bit, with the pair launch on and off, and
-    leaves its input alone; two sweeps agree with the oracle's two sweeps."""
+    leaves its input alone; two sweeps agree with the oracle's two sweeps.
+    The wider grids hold tiles whose halo touches no side (their kernels skip
+    the side logic) beside tiles on every side."""
     announce("sweeps", nx, ny, bcs)
     kinds = BC_SETS.get(bcs, ("periodic", "periodic", "dirichlet", "reflective"))
     prob, v, sig = inputs.random_problem(8, 2, nx, ny, bc_kinds=kinds, cfl=40.0, fmax=1.0)
@@ -244,13 +247,14 @@ def test_sweeps_match_chained_sweeps(nx, ny, bcs):
 
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
-@pytest.mark.parametrize("nx,ny", [(96, 80), (100, 36), (66, 10), (130, 70), (64, 64)])
+@pytest.mark.parametrize("nx,ny", [(96, 80), (100, 36), (66, 10), (130, 70), (64, 64), (258, 130)])
 @pytest.mark.parametrize("bcs", ["periodic", "mixed", "wall"])
 def test_fused_residual_restriction_matches_two_kernels(nx, ny, bcs, precision):
     """The finest residual restricted as it is formed (one launch) gives the
     stored-then-restricted path's cycle to the bit: odd coarse sizes, ragged
-    coarse tiles, periodic wrap and dropped points at every kind of side; one
-    V-cycle and a whole time step."""
+    coarse tiles, periodic wrap and dropped points at every kind of side, and
+    tiles that touch no side (258 x 130: three columns of them); one V-cycle and
+    a whole time step."""
     announce("fused residual/restriction", nx, ny, bcs, precision)
     kinds = BC_SETS[bcs]
     prob, v, sig = inputs.random_problem(6, 2, nx, ny, bc_kinds=kinds, cfl=60.0, fmax=0.9)
