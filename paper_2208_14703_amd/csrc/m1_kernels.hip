@@ -1025,11 +1025,9 @@ __global__ __launch_bounds__(kRcThreads) void kb_residual_restrict(
         const Soa& u = (level == 1) ? (in_sel ? f.x1 : f.x0) : pick(f, in_sel);
         const Soa& X = (level == 1) ? f.b : f.f;
         const uint32_t ntx = (uint32_t)((f.L.nx / 2 + kRcW - 1) / kRcW);
-        const int I0 = (int)(tile % ntx) * kRcW, J0 = (int)(tile / ntx) * kRcH;
-        if (rc_interior(f.L, I0, J0))
-            residual_restrict_tile<true>(sm, pb.ph, f.L, cs(u), cs(X), -1.0, pb.px, pb.py, c.v, c.f, I0, J0, true);
-        else
-            residual_restrict_tile<false>(sm, pb.ph, f.L, cs(u), cs(X), -1.0, pb.px, pb.py, c.v, c.f, I0, J0, true);
+        // one variant only in the work-list loop: two inlined cost registers
+        residual_restrict_tile<false>(sm, pb.ph, f.L, cs(u), cs(X), -1.0, pb.px, pb.py, c.v, c.f,
+                                      (int)(tile % ntx) * kRcW, (int)(tile / ntx) * kRcH, true);
         __syncthreads();  // the next tile of this block reuses the LDS
     }
 }
@@ -1058,16 +1056,9 @@ __global__ __launch_bounds__(kLdsTX * TY) void kb_relax_lds(const BProb* __restr
         const Soa& out = in_x1 ? s.x0 : s.x1;
         const uint32_t ntx = (uint32_t)((s.L.nx + kLdsTX - 1) / kLdsTX);
         const int i0 = (int)(tile % ntx) * kLdsTX, j0 = (int)(tile / ntx) * TY;
-        const bool inner = tile_interior(s.L, TY, i0, j0);
         if (UP) {
             const BSlot& cl = S[p * kMaxLevels + 1];
-            if (inner)
-                stage_tile<TY, true, true>(q, qT, pb.ph, s.L, cs(in), i0, j0, cs(cl.u), cs(cl.v), pb.px, pb.py,
-                                           pb.eta);
-            else
-                stage_tile<TY, true>(q, qT, pb.ph, s.L, cs(in), i0, j0, cs(cl.u), cs(cl.v), pb.px, pb.py, pb.eta);
-        } else if (inner) {
-            stage_tile<TY, false, true>(q, nullptr, pb.ph, s.L, cs(in), i0, j0, CSoa{}, CSoa{}, 0, 0, 0.0);
+            stage_tile<TY, true>(q, qT, pb.ph, s.L, cs(in), i0, j0, cs(cl.u), cs(cl.v), pb.px, pb.py, pb.eta);
         } else {
             stage_tile<TY, false>(q, nullptr, pb.ph, s.L, cs(in), i0, j0, CSoa{}, CSoa{}, 0, 0, 0.0);
         }
@@ -1105,9 +1096,8 @@ __global__ __launch_bounds__(kLdsTX * TY) void kb_relax2_lds(
         const Soa& in = in_x1 ? s.x1 : s.x0;
         const Soa& out = in_x1 ? s.x0 : s.x1;
         const uint32_t ntx = (uint32_t)((s.L.nx + kLdsTX - 1) / kLdsTX);
-        const int i0 = (int)(tile % ntx) * kLdsTX, j0 = (int)(tile / ntx) * TY;
-        if (pair_interior<TY>(s.L, i0, j0)) relax2_tile<TY, true>(q, pb.ph, s.L, cs(s.b), pb.omega, cs(in), out, i0, j0);
-        else relax2_tile<TY>(q, pb.ph, s.L, cs(s.b), pb.omega, cs(in), out, i0, j0);
+        relax2_tile<TY>(q, pb.ph, s.L, cs(s.b), pb.omega, cs(in), out, (int)(tile % ntx) * kLdsTX,
+                        (int)(tile / ntx) * TY);
         __syncthreads();  // the next tile of this block reuses the LDS
     }
 }

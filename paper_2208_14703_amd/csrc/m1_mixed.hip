@@ -250,11 +250,19 @@ struct MxTile {
     float e[N], gx[N], gy[N], xx[N], xy[N], yy[N];
 };
 
+// Whether the 64 x TY tile at (i0, j0) and a halo of `halo` cells lie inside
+// the grid (no ghost, wrap or ragged edge).
+__device__ __forceinline__ bool mx_interior(const Lvl32& L, int ty, int halo, int i0, int j0)
+{
+    return i0 >= halo && j0 >= halo && i0 + kMxTX + halo <= L.nx && j0 + ty + halo <= L.ny;
+}
+
 // Stage the 64 x TY tile at (i0, j0): correction (after the boundary rule) and
 // c^2 P increment of every tile and halo point.  d_at(k, E, Fx, Fy, T) gives
 // the correction of cell k; returns the T correction of this thread's own cell
-// (0 outside the grid).
-template <int TY, class DAt>
+// (0 outside the grid).  INTERIOR: mx_interior with a one-cell halo, and the
+// side logic drops out (same arithmetic, same result).
+template <int TY, bool INTERIOR = false, class DAt>
 __device__ __forceinline__ float mx_stage_tile_at(MxTile<TY>& q, const Phys& ph, const Lvl32& L, const CSoa32& w,
                                                   DAt&& d_at, int i0, int j0)
 {
@@ -264,8 +272,8 @@ __device__ __forceinline__ float mx_stage_tile_at(MxTile<TY>& q, const Phys& ph,
     const bool perx = ph.bc[0] == BC_PERIODIC, pery = ph.bc[2] == BC_PERIODIC;
     auto gather = [&](int li, int lj) {
         int gi = i0 + li, gj = j0 + lj, side = 0;
-        const bool ox = gi < 0 || gi >= L.nx, oy = gj < 0 || gj >= L.ny;
-        const bool need = gi <= L.nx && gj <= L.ny && !(ox && oy);
+        const bool ox = !INTERIOR && (gi < 0 || gi >= L.nx), oy = !INTERIOR && (gj < 0 || gj >= L.ny);
+        const bool need = INTERIOR || (gi <= L.nx && gj <= L.ny && !(ox && oy));
         if (ox) {
             side = gi < 0 ? 0 : 1;
             gi = perx ? (gi < 0 ? gi + L.nx : gi - L.nx) : (gi < 0 ? 0 : L.nx - 1);
@@ -304,11 +312,11 @@ __device__ __forceinline__ float mx_stage_tile_at(MxTile<TY>& q, const Phys& ph,
     return own;
 }
 
-template <int TY>
+template <int TY, bool INTERIOR = false>
 __device__ __forceinline__ void mx_stage_tile(MxTile<TY>& q, const Phys& ph, const Lvl32& L, const CSoa32& w,
                                               const CSoa32& d, int i0, int j0)
 {
-    (void)mx_stage_tile_at<TY>(
+    (void)mx_stage_tile_at<TY, INTERIOR>(
         q, ph, L, w,
         [&](uint32_t k, float& E, float& Fx, float& Fy, float& T) {
             E = ldf(d.E, k);
@@ -357,7 +365,8 @@ __global__ __launch_bounds__(kMxTX * TY) void k_mx_sweep_lds(Phys ph, Lvl32 L, C
     const int ntx = (L.nx + kMxTX - 1) / kMxTX;
     const int b = (int)xcd_block();
     const int i0 = (b % ntx) * kMxTX, j0 = (b / ntx) * TY;
-    mx_stage_tile<TY>(q, ph, L, w, d, i0, j0);
+    if (mx_interior(L, TY, 1, i0, j0)) mx_stage_tile<TY, true>(q, ph, L, w, d, i0, j0);
+    else mx_stage_tile<TY>(q, ph, L, w, d, i0, j0);
     __syncthreads();
     mx_tile_sweep<TY>(q, ph, L, w, d, rhs, beta, gamma, omega, out, i0, j0);
 }
@@ -403,8 +412,10 @@ __device__ __forceinline__ void mx_lds_put(float* const* f, int n, float e, floa
     f[5][n] = p.yy;
 }
 
-// The two correction sweeps of the tile at (i0, j0); every thread of the block calls it.
-template <int TY>
+// The two correction sweeps of the tile at (i0, j0); every thread of the block
+// calls it.  INTERIOR: mx_interior with a two-cell halo (no side logic; same
+// result).
+template <int TY, bool INTERIOR = false>
 __device__ __forceinline__ void mx_sweep2_tile(MxLds2<TY>& q, const Phys& ph, const Lvl32& L, const CSoa32& w,
                                                const CSoa32& d, const CSoa32& rhs, float omega, const Soa32& out,
                                                int i0, int j0)
@@ -414,7 +425,8 @@ __device__ __forceinline__ void mx_sweep2_tile(MxLds2<TY>& q, const Phys& ph, co
     static_assert(NR <= NT, "one ring point per thread");
     const float c = (float)ph.c, c2 = (float)ph.c2;
     const bool perx = ph.bc[0] == BC_PERIODIC, pery = ph.bc[2] == BC_PERIODIC;
-    const int xe = min(i0 + kMxTX, L.nx) - 1, ye = min(j0 + TY, L.ny) - 1;  // the last final cell
+    const int xe = INTERIOR ? i0 + kMxTX - 1 : min(i0 + kMxTX, L.nx) - 1;  // the last final cell
+    const int ye = INTERIOR ? j0 + TY - 1 : min(j0 + TY, L.ny) - 1;
     // the plus of half-widths (a, b) around the final cells holds (gi, gj) (as in k_relax2_lds)
     auto plus = [&](int gi, int gj, int a, int bb) {
         return (gi >= i0 && gi <= xe && gj >= j0 - a && gj <= ye + a) ||
@@ -428,10 +440,12 @@ __device__ __forceinline__ void mx_sweep2_tile(MxLds2<TY>& q, const Phys& ph, co
     // 1. stage base and correction (boundary rule on ghosts) and the increments
     for (int p = threadIdx.x; p < Q::N2; p += NT) {
         const int gi = i0 + p % Q::W2 - 2, gj = j0 + p / Q::W2 - 2;
-        int si, sj;
-        bool gx_, gy_, nx_, ny_;
-        rc_axis(gi, L.nx, perx, si, gx_, nx_);
-        rc_axis(gj, L.ny, pery, sj, gy_, ny_);
+        int si = gi, sj = gj;
+        bool gx_ = false, gy_ = false, nx_ = true, ny_ = true;
+        if (!INTERIOR) {
+            rc_axis(gi, L.nx, perx, si, gx_, nx_);
+            rc_axis(gj, L.ny, pery, sj, gy_, ny_);
+        }
         float e = 0.0f, gx = 0.0f, gy = 0.0f, E = 0.0f, Fx = 0.0f, Fy = 0.0f;
         DP pp{0.0f, 0.0f, 0.0f};
         if (plus(gi, gj, 2, 1) && nx_ && ny_ && !(gx_ && gy_)) {
@@ -465,9 +479,13 @@ __device__ __forceinline__ void mx_sweep2_tile(MxLds2<TY>& q, const Phys& ph, co
         vE[m] = vFx[m] = vFy[m] = vT[m] = bE[m] = bFx[m] = bFy[m] = 0.0f;
         const int gi = i0 + li[m], gj = j0 + lj[m];
         if ((m == 1 && t >= NR) || !plus(gi, gj, 1, 0)) continue;
-        bool gx_, gy_, nx_, ny_;
-        rc_axis(gi, L.nx, perx, gsx[m], gx_, nx_);
-        rc_axis(gj, L.ny, pery, gsy[m], gy_, ny_);
+        bool gx_ = false, gy_ = false, nx_ = true, ny_ = true;
+        gsx[m] = gi;
+        gsy[m] = gj;
+        if (!INTERIOR) {
+            rc_axis(gi, L.nx, perx, gsx[m], gx_, nx_);
+            rc_axis(gj, L.ny, pery, gsy[m], gy_, ny_);
+        }
         kind[m] = (gx_ || gy_) ? 2 : 1;  // the plus holds no corner: at most one side is off the domain
         if (kind[m] != 1) continue;
         const uint32_t k = (uint32_t)gsy[m] * (uint32_t)L.nx + (uint32_t)gsx[m];
@@ -487,7 +505,8 @@ __device__ __forceinline__ void mx_sweep2_tile(MxLds2<TY>& q, const Phys& ph, co
             mx_lds_put(f1, (lj[m] + 1) * Q::W1 + li[m] + 1, vE[m], vFx[m], vFy[m],
                        closure_inc(c, c2, bE[m], bFx[m], bFy[m], vE[m], vFx[m], vFy[m]));
     // 3. ghosts of the iterate (only tiles on a non-periodic side have any)
-    const bool edge = (!perx && (i0 == 0 || xe == L.nx - 1)) || (!pery && (j0 == 0 || ye == L.ny - 1));
+    const bool edge =
+        !INTERIOR && ((!perx && (i0 == 0 || xe == L.nx - 1)) || (!pery && (j0 == 0 || ye == L.ny - 1)));
     if (edge) {
         __syncthreads();
 #pragma unroll
@@ -506,7 +525,7 @@ __device__ __forceinline__ void mx_sweep2_tile(MxLds2<TY>& q, const Phys& ph, co
     __syncthreads();
     // 4. second sweep on the final cells
     const int i = i0 + li[0], j = j0 + lj[0];
-    if (i < L.nx && j < L.ny) {
+    if (INTERIOR || (i < L.nx && j < L.ny)) {
         const uint32_t k = (uint32_t)j * (uint32_t)L.nx + (uint32_t)i;
         float S0, S1, S2;
         mx_lds_sums<Q::W1>(f1, L, c, (lj[0] + 1) * Q::W1 + li[0] + 1, S0, S1, S2);
@@ -525,7 +544,9 @@ __global__ __launch_bounds__(kMxTX * TY) __attribute__((amdgpu_waves_per_eu(6)))
     if (*active == 0) return;
     const int ntx = (L.nx + kMxTX - 1) / kMxTX;
     const int b = (int)xcd_block();
-    mx_sweep2_tile<TY>(q, ph, L, w, d, rhs, omega, out, (b % ntx) * kMxTX, (b / ntx) * TY);
+    const int i0 = (b % ntx) * kMxTX, j0 = (b / ntx) * TY;
+    if (mx_interior(L, TY, 2, i0, j0)) mx_sweep2_tile<TY, true>(q, ph, L, w, d, rhs, omega, out, i0, j0);
+    else mx_sweep2_tile<TY>(q, ph, L, w, d, rhs, omega, out, i0, j0);
 }
 
 template <int DIM>
@@ -763,7 +784,8 @@ __global__ __launch_bounds__(kMxTX * TY) void k_mx_pseudo_lds(Phys ph, Lvl32 L, 
     const int ntx = (L.nx + kMxTX - 1) / kMxTX;
     const int b = (int)xcd_block();
     const int i0 = (b % ntx) * kMxTX, j0 = (b / ntx) * TY;
-    mx_stage_tile<TY>(q, ph, L, w, e, i0, j0);
+    if (mx_interior(L, TY, 1, i0, j0)) mx_stage_tile<TY, true>(q, ph, L, w, e, i0, j0);
+    else mx_stage_tile<TY>(q, ph, L, w, e, i0, j0);
     __syncthreads();
     const int li = threadIdx.x % kMxTX, lj = threadIdx.x / kMxTX, i = i0 + li, j = j0 + lj;
     if (i >= L.nx || j >= L.ny) return;
@@ -925,12 +947,11 @@ __global__ __launch_bounds__(kMxTX * TY) void k_mx_prolong_sweep_lds(Phys ph, Lv
     const int ntx = (L.nx + kMxTX - 1) / kMxTX;
     const int b = (int)xcd_block();
     const int i0 = (b % ntx) * kMxTX, j0 = (b / ntx) * TY;
-    const float dT = mx_stage_tile_at<TY>(
-        q, ph, L, w,
-        [&](uint32_t k, float& E, float& Fx, float& Fy, float& T) {
-            mx_prolong_fine_values<2>(ph, L.nx, L.ny, sh, px, py, eta, v, e, ec, dc, k, E, Fx, Fy, T);
-        },
-        i0, j0);
+    auto d_at = [&](uint32_t k, float& E, float& Fx, float& Fy, float& T) {
+        mx_prolong_fine_values<2>(ph, L.nx, L.ny, sh, px, py, eta, v, e, ec, dc, k, E, Fx, Fy, T);
+    };
+    const float dT = mx_interior(L, TY, 1, i0, j0) ? mx_stage_tile_at<TY, true>(q, ph, L, w, d_at, i0, j0)
+                                                    : mx_stage_tile_at<TY>(q, ph, L, w, d_at, i0, j0);
     __syncthreads();
     mx_tile_sweep<TY, true>(q, ph, L, w, CSoa32{}, rhs, 0.0f, 1.0f, omega, out, i0, j0, dT);
 }
@@ -1190,6 +1211,15 @@ static_assert(MrLds::NR <= MrLds::NS, "residuals are kept in the closure arrays"
 
 // The fused residual and restriction of the coarse tile at (I0, J0) (all
 // threads of the block take part; no thread returns early).
+// Whether every point the coarse tile at (I0, J0) stages lies inside the grid
+// (as rc_interior of the FP64 kernel): no ghost, wrap or clamp, and the
+// restriction weights are (1/4, 1/2, 1/4).
+__device__ __forceinline__ bool mr_interior(const Lvl32& L, int I0, int J0)
+{
+    return I0 >= 1 && J0 >= 1 && 2 * (I0 + kMrCW) <= L.nx - 1 && 2 * (J0 + kMrCH) <= L.ny - 1;
+}
+
+template <bool INTERIOR>
 __device__ __forceinline__ void mx_residual_restrict_tile(MrLds& sm, const Phys& ph, const Lvl32& L, const CSoa32& w,
                                                           const CSoa32& d, const CSoa32& X, float sgn, int px, int py,
                                                           const Soa32& wc, const Soa32& dc, const Soa32& gc, int I0,
@@ -1207,11 +1237,12 @@ __device__ __forceinline__ void mx_residual_restrict_tile(MrLds& sm, const Phys&
     for (int it = 0; it < RPT; ++it) {
         const int q = threadIdx.x + it * kMrThreads;
         const int gi = fi0 + q % kMrRW - 1, gj = fj0 + q / kMrRW - 1;
-        has[it] = q < NR && gi < L.nx && gj < L.ny;
+        has[it] = q < NR && (INTERIOR || (gi < L.nx && gj < L.ny));
 #pragma unroll
         for (int m = 0; m < 6; ++m) own[it][m] = 0.0f;
         if (has[it]) {
-            const int si = gi < 0 ? (px ? gi + L.nx : 0) : gi, sj = gj < 0 ? (py ? gj + L.ny : 0) : gj;
+            const int si = (INTERIOR || gi >= 0) ? gi : (px ? gi + L.nx : 0);
+            const int sj = (INTERIOR || gj >= 0) ? gj : (py ? gj + L.ny : 0);
             const uint32_t k = (uint32_t)sj * (uint32_t)L.nx + (uint32_t)si;
             own[it][0] = ldf(L.sa, k);
             own[it][1] = ldf(L.ss, k);
@@ -1223,10 +1254,12 @@ __device__ __forceinline__ void mx_residual_restrict_tile(MrLds& sm, const Phys&
     }
     for (int q = threadIdx.x; q < NS; q += kMrThreads) {
         const int gi = fi0 + q % kMrSW - 2, gj = fj0 + q / kMrSW - 2;
-        int si, sj;
-        bool hx, hy, nx_, ny_;
-        rc_axis(gi, L.nx, px != 0, si, hx, nx_);
-        rc_axis(gj, L.ny, py != 0, sj, hy, ny_);
+        int si = gi, sj = gj;
+        bool hx = false, hy = false, nx_ = true, ny_ = true;
+        if (!INTERIOR) {
+            rc_axis(gi, L.nx, px != 0, si, hx, nx_);
+            rc_axis(gj, L.ny, py != 0, sj, hy, ny_);
+        }
         float E = 0.0f, Fx = 0.0f, Fy = 0.0f, T = 0.0f, e = 0.0f, gx = 0.0f, gy = 0.0f, t = 0.0f;
         DP p{0.0f, 0.0f, 0.0f};
         if (nx_ && ny_ && !(hx && hy)) {
@@ -1252,8 +1285,8 @@ __device__ __forceinline__ void mx_residual_restrict_tile(MrLds& sm, const Phys&
     }
     __syncthreads();
     auto centre = [&](int ri, int rj) {
-        if (fi0 + ri < 0 && !px) ri += 1;
-        if (fj0 + rj < 0 && !py) rj += 1;
+        if (!INTERIOR && fi0 + ri < 0 && !px) ri += 1;
+        if (!INTERIOR && fj0 + rj < 0 && !py) rj += 1;
         return (rj + 2) * kMrSW + ri + 2;
     };
     float res[RPT][4];
@@ -1302,11 +1335,16 @@ __device__ __forceinline__ void mx_residual_restrict_tile(MrLds& sm, const Phys&
     static_assert(kMrThreads == 4 * NC, "four groups of threads, three restricted fields each");
     const int cc = threadIdx.x % NC, grp = threadIdx.x / NC;
     const int ci = cc % kMrCW, cj = cc / kMrCW, I = I0 + ci, J = J0 + cj;
-    if (I < nxc && J < nyc && live) {
-        int ix[3], iy[3];
+    if ((INTERIOR || (I < nxc && J < nyc)) && live) {
         float wx[3], wy[3];
-        rweights32(I, L.nx, px != 0, ix, wx);
-        rweights32(J, L.ny, py != 0, iy, wy);
+        if (INTERIOR) {  // the weights rweights32 gives inside the grid
+#pragma unroll
+            for (int m = 0; m < 3; ++m) wx[m] = wy[m] = (m == 1) ? 0.5f : 0.25f;
+        } else {
+            int ix[3], iy[3];
+            rweights32(I, L.nx, px != 0, ix, wx);
+            rweights32(J, L.ny, py != 0, iy, wy);
+        }
         auto restrict12 = [&](const float* src, bool staged, float* dst) {
             float s = 0.0f;
 #pragma unroll
@@ -1349,8 +1387,11 @@ __global__ __launch_bounds__(kMrThreads) void k_mx_residual_restrict(Phys ph, Lv
     const bool live = active[mx_lane_zero()] != 0;
     const int ntx = (L.nx / 2 + kMrCW - 1) / kMrCW;
     const int b = (int)xcd_block();
-    mx_residual_restrict_tile(sm, ph, L, w, d, X, sgn, px, py, wc, dc, gc, (b % ntx) * kMrCW, (b / ntx) * kMrCH,
-                              live);
+    const int I0 = (b % ntx) * kMrCW, J0 = (b / ntx) * kMrCH;
+    if (mr_interior(L, I0, J0))
+        mx_residual_restrict_tile<true>(sm, ph, L, w, d, X, sgn, px, py, wc, dc, gc, I0, J0, live);
+    else
+        mx_residual_restrict_tile<false>(sm, ph, L, w, d, X, sgn, px, py, wc, dc, gc, I0, J0, live);
 }
 
 // Batched: work-list entries are the 32 x 4 coarse tiles of level `level` of
@@ -1374,8 +1415,9 @@ __global__ __launch_bounds__(kMrThreads) void kbm_residual_restrict(const BProb*
         const Soa32& d = (level == 1) ? pickA(f, d0_sel) : f.e;
         const Soa32& X = (level == 1) ? f.r32 : f.g;
         const uint32_t ntx = (uint32_t)((f.L.nx / 2 + kMrCW - 1) / kMrCW);
-        mx_residual_restrict_tile(sm, pb.ph, f.L, cs(w), cs(d), cs(X), -1.0f, pb.px, pb.py, c.w, c.d, c.g,
-                                  (int)(tile % ntx) * kMrCW, (int)(tile / ntx) * kMrCH, true);
+        // one variant only: two inlined into the work-list loop cost registers (130 against 79 VGPRs)
+        mx_residual_restrict_tile<false>(sm, pb.ph, f.L, cs(w), cs(d), cs(X), -1.0f, pb.px, pb.py, c.w, c.d, c.g,
+                                         (int)(tile % ntx) * kMrCW, (int)(tile / ntx) * kMrCH, true);
         __syncthreads();  // the next tile of this block reuses the LDS
     }
 }
