@@ -485,7 +485,7 @@ void vcycle_impl(m1_plan& P, Soa& cur, Soa& other, const Gate& G, bool control =
             break;
         }
         if (tiled[l]) {
-            m1::launch_smooth_tb(P.st, P.ph, c.L, p.pseudo_steps, false, cs(c.rb), c.f, cs(c.v), c.u, G.dtau_dev,
+            m1::launch_smooth_tb(P.st, P.ph, c.L, p.pseudo_steps, m1::kLegDown, cs(c.rb), c.f, cs(c.v), c.u, G.dtau_dev,
                                  P.reach, p.pseudo_local, CSoa{}, CSoa{}, P.px, P.py, p.eta, G.active);
             ul[l] = c.u;
         } else {
@@ -502,7 +502,7 @@ void vcycle_impl(m1_plan& P, Soa& cur, Soa& other, const Gate& G, bool control =
         LevelBuf& f = P.lev[l];
         if (tiled[l]) {  // prolongation, projection and the post-smoothing in one launch
             const Soa out = same(ul[l], f.u) ? f.u2 : f.u;
-            m1::launch_smooth_tb(P.st, P.ph, f.L, p.pseudo_steps, true, cs(f.f), f.f, cs(ul[l]), out, G.dtau_dev,
+            m1::launch_smooth_tb(P.st, P.ph, f.L, p.pseudo_steps, m1::kLegUp, cs(f.f), f.f, cs(ul[l]), out, G.dtau_dev,
                                  P.reach, p.pseudo_local, cs(ul[l + 1]), cs(c.v), P.px, P.py, p.eta, G.active);
             ul[l] = out;
             continue;
@@ -551,36 +551,48 @@ void plan_prolong_project(m1_plan& P, int l, const CSoa& u, const CSoa& uc, cons
 }
 
 // ---- W- and F-cycles (Sect. 6.3) --------------------------------------------
-// The cycle written as a recursion over the coarse problems, every level by
-// grid kernels (no tail, no tiled legs): a visit of level l smooths its FAS
-// problem in pseudo time (Algorithm 3), restricts the iterate and its residual
-// to level l + 1, visits that level once (V), twice (W) or by an F-cycle then a
-// V-cycle (F), corrects with admissibility (eq. prolongatedSol) and smooths
-// again; the coarsest level is smoothed once per visit.
+// The cycle written as a recursion over the coarse problems (no tail): a visit
+// of level l smooths its FAS problem in pseudo time (Algorithm 3), restricts
+// the iterate and its residual to level l + 1, visits that level once (V),
+// twice (W) or by an F-cycle then a V-cycle (F), corrects with admissibility
+// (eq. prolongatedSol) and smooths again; the coarsest level is smoothed once
+// per visit.  Levels small enough for the tiled legs (as in the V-cycle) run
+// each smoothing as one launch: the first of a descent forming the FAS
+// right-hand side, a later visit's pre-smoothing plain, and the correction
+// with the post-smoothing; the finest level's correction is fused with its
+// first post-sweep.  Every launch gives the one-step kernels' bits.
 
-// v_{l+1} = R(u) and R(rhs - A_l(u)) into level l + 1 (its f, which the first
-// pseudo-time step of the next visit turns into A(v_{l+1}) + R(rbar)).
+// Whether level l's smoothing legs run as tiled launches.
+bool rc_tiled(const m1_plan& P, int l)
+{
+    return l >= 1 && l < P.L && P.tiled && P.lev[l].n <= P.tiled_max &&
+           m1::smooth_tb_fits(P.dim, P.lev[l].L, P.params.pseudo_steps);
+}
+
+// v_{l+1} = R(u) and R(rhs - A_l(u)) into level l + 1 (its f, or its rb when
+// that level is tiled; the first pseudo-time step of the next visit turns it
+// into A(v_{l+1}) + R(rbar)).
 void descend(m1_plan& P, int l, const Soa& u, const Gate& G)
 {
     const LevelBuf& f = P.lev[l];
     LevelBuf& c = P.lev[l + 1];
     const CSoa rhs = l == 0 ? cs(P.b) : cs(f.f);
+    const Soa to = rc_tiled(P, l + 1) ? c.rb : c.f;
     if (P.dim == 2 && m1::residual_restrict() && !mean_transfer(P)) {
-        m1::launch_residual_restrict(P.st, P.ph, f.L, cs(u), rhs, -1.0, P.px, P.py, c.v, c.f, G.active);
+        m1::launch_residual_restrict(P.st, P.ph, f.L, cs(u), rhs, -1.0, P.px, P.py, c.v, to, G.active);
         return;
     }
     const Soa r = l == 0 ? P.rfine : f.rb;
     m1::launch_apply(P.st, P.dim, P.ph, f.L, cs(u), rhs, -1.0, r, nullptr, G.active);
-    plan_restrict(P, l, fields2(u, r, c.v, c.f, P.dim), G.active);
+    plan_restrict(P, l, fields2(u, r, c.v, to, P.dim), G.active);
 }
 
 Soa coarse_visit(m1_plan& P, int l, int kind, const Gate& G, Soa u, bool first);
 
-// Visit level l + 1 as `kind` prescribes, then u <- projected(u + P(u_{l+1} - v_{l+1})) in place.
-void visit_and_correct(m1_plan& P, int l, int kind, const Gate& G, const Soa& u)
+// Visit level l + 1 as `kind` prescribes; its final iterate.
+Soa visit_below(m1_plan& P, int l, int kind, const Gate& G)
 {
     const LevelBuf& c = P.lev[l + 1];
-    const LevelBuf& f = P.lev[l];
     Soa uc;
     if (kind == M1_CYCLE_F) {
         uc = coarse_visit(P, l + 1, M1_CYCLE_F, G, c.v, true);
@@ -589,27 +601,61 @@ void visit_and_correct(m1_plan& P, int l, int kind, const Gate& G, const Soa& u)
         uc = coarse_visit(P, l + 1, kind, G, c.v, true);
         if (kind == M1_CYCLE_W) uc = coarse_visit(P, l + 1, kind, G, uc, false);
     }
-    plan_prolong_project(P, l, cs(u), cs(uc), cs(c.v), u, G.active);
+    return uc;
+}
+
+// The m pseudo-time steps of level l >= 1 from u as one tiled launch (first:
+// forming f from R(rbar) in rb); the result in the level buffer u is not in.
+Soa tiled_leg(m1_plan& P, int l, const Gate& G, const Soa& u, bool first)
+{
+    LevelBuf& c = P.lev[l];
+    const Soa out = same(u, c.u) ? c.u2 : c.u;
+    m1::launch_smooth_tb(P.st, P.ph, c.L, P.params.pseudo_steps, first ? m1::kLegDown : m1::kLegPlain,
+                         first ? cs(c.rb) : cs(c.f), c.f, cs(u), out, G.dtau_dev, P.reach, P.params.pseudo_local,
+                         CSoa{}, CSoa{}, P.px, P.py, P.params.eta, G.active);
+    return out;
 }
 
 // One visit of coarse level l from the iterate u (v_l on the first visit of a
 // descent, whose first pseudo-time step forms f = A(v_l) + R(rbar)).
 Soa coarse_visit(m1_plan& P, int l, int kind, const Gate& G, Soa u, bool first)
 {
-    u = pseudo_smooth(P, l, G, u, first);
+    const bool tl = rc_tiled(P, l);
+    u = tl ? tiled_leg(P, l, G, u, first) : pseudo_smooth(P, l, G, u, first);
     if (l == P.L - 1) return u;
     descend(P, l, u, G);
-    visit_and_correct(P, l, kind, G, u);
+    const Soa uc = visit_below(P, l, kind, G);
+    const LevelBuf& c = P.lev[l + 1];
+    LevelBuf& f = P.lev[l];
+    if (tl) {  // correction, projection and the post-smoothing in one launch
+        const Soa out = same(u, f.u) ? f.u2 : f.u;
+        m1::launch_smooth_tb(P.st, P.ph, f.L, P.params.pseudo_steps, m1::kLegUp, cs(f.f), f.f, cs(u), out,
+                             G.dtau_dev, P.reach, P.params.pseudo_local, cs(uc), cs(c.v), P.px, P.py, P.params.eta,
+                             G.active);
+        return out;
+    }
+    plan_prolong_project(P, l, cs(u), cs(uc), cs(c.v), u, G.active);
     return pseudo_smooth(P, l, G, u, false);
 }
 
 void rcycle_impl(m1_plan& P, Soa& cur, Soa& other, const Gate& G, bool control)
 {
-    fine_sweeps(P, cur, other, P.params.nu0, G, control);
+    const m1_params& p = P.params;
+    fine_sweeps(P, cur, other, p.nu0, G, control);
     if (P.L == 1) return;
     descend(P, 0, cur, G);
-    visit_and_correct(P, 0, P.params.cycle, G, cur);
-    fine_sweeps(P, cur, other, P.params.nu0, G);
+    const Soa uc = visit_below(P, 0, p.cycle, G);
+    const LevelBuf& c = P.lev[1];
+    if (P.dim == 2 && p.nu0 > 0 && p.smoother == M1_SMOOTH_JACOBI && !mean_transfer(P) &&
+        m1::launch_relax_lds(P.st, P.ph, P.lev[0].L, cs(P.b), p.omega, cs(cur), other, G.active, cs(uc), cs(c.v),
+                             P.px, P.py, p.eta)) {
+        // correction, projection and the first post-sweep in one launch
+        std::swap(cur, other);
+        fine_sweeps(P, cur, other, p.nu0 - 1, G);
+        return;
+    }
+    plan_prolong_project(P, 0, cs(cur), cs(uc), cs(c.v), cur, G.active);
+    fine_sweeps(P, cur, other, p.nu0, G);
 }
 
 // One cycle of the plan's shape (the V-cycle with full weighting has its own fused form).
@@ -991,7 +1037,7 @@ static m1_status plan_init(m1_plan* P, const m1_grid* g, const m1_params* p, con
     P->graphs = use_graphs();
     // the recursion (other shapes, other transfers) runs every level by grid kernels
     const bool fused_form = p->cycle == M1_CYCLE_V && p->transfer == M1_TRANSFER_FULL;
-    if (!fused_form) P->tiled = false;
+    if (p->transfer != M1_TRANSFER_FULL) P->tiled = false;  // the up leg prolongs linearly
     const bool tail_ok = P->L <= m1::kMaxLevels && p->nu_l == 1 && fused_form;
     if (!tail_ok) P->lt = P->L;  // the tail fuses exactly one Jacobi sweep per pseudo-time step
     for (int l = 0; l < P->L && l < m1::kMaxLevels; ++l) {

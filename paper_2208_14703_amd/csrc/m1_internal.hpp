@@ -74,9 +74,12 @@ void launch_prolong_project(hipStream_t st, int dim, const Phys& ph, int nx, int
                             CSoa u, CSoa uc, CSoa vc, Soa out, const int* active);
 void launch_tail(hipStream_t st, int dim, const TailArgs* args_dev, double dtau, const double* dtau_dev,
                  const int* active);
-// LDS-tiled smoothing leg of one coarse level (all m pseudo-time steps in one launch).
+// LDS-tiled smoothing leg of one coarse level (all m pseudo-time steps in one launch).  Legs: the first
+// smoothing of a descent (forms the FAS right-hand side from R(rbar)), the correction from the level below
+// with the post-smoothing, and plain smoothing (a later visit in a W- or F-cycle).
+constexpr int kLegDown = 0, kLegUp = 1, kLegPlain = 2;
 bool smooth_tb_fits(int dim, const Lvl& L, int m);
-void launch_smooth_tb(hipStream_t st, const Phys& ph, const Lvl& L, int m, bool up, CSoa fr, Soa f, CSoa u, Soa out,
+void launch_smooth_tb(hipStream_t st, const Phys& ph, const Lvl& L, int m, int leg, CSoa fr, Soa f, CSoa u, Soa out,
                       const double* dtau_dev, double reach, int local, CSoa uc, CSoa vc, int px, int py, double eta,
                       const int* active);
 void launch_make_rhs(hipStream_t st, int dim, int64_t n, double cv, CSoa v, Soa b);

@@ -864,21 +864,24 @@ __global__ void k_ctrl_init(Ctrl* ctrl, Ctrl init) { *ctrl = init; }
 // smoothing leg in one launch.  A block owns a 16x16 tile and loads it with a
 // halo of M = m cells; step s recomputes the region M - s cells around the
 // tile, so no step needs another block's result (temporal blocking; the halo
-// work is redundant).  Down leg: the first step forms the FAS right-hand side
-// from R(rbar), read from `fr` and written to `f` (other tiles still read fr).
-// Up leg: the load applies the prolongation and projection from level l + 1
-// (uc, vc) to the level's pre-smoothed iterate `u`.  The per-cell arithmetic is
-// that of the one-step kernels, so the results are the same to the bit.
-// Requires nx, ny multiples of 16, at least 32; u and out distinct.
+// work is redundant).  LEG kLegDown: the first step forms the FAS right-hand
+// side from R(rbar), read from `fr` and written to `f` (other tiles still read
+// fr).  kLegUp: the load applies the prolongation and projection from level
+// l + 1 (uc, vc) to the level's pre-smoothed iterate `u`.  kLegPlain: m steps
+// from `u` with the right-hand side `fr` (a later visit of the level in a W- or
+// F-cycle).  The per-cell arithmetic is that of the one-step kernels, so the
+// results are the same to the bit.  Requires nx, ny multiples of 16, at least
+// 32; u and out distinct.
 constexpr int kTbTile = 16;
 constexpr int kTbThreads = 512;
 
-template <int M, bool UP>
+template <int M, int LEG>
 __global__ __launch_bounds__(kTbThreads) void k_smooth_tb(Phys ph, Lvl L, CSoa fr, Soa f, CSoa u, Soa out,
                                                            const double* __restrict__ dtau_dev, double reach,
                                                            int local, CSoa uc, CSoa vc, int px, int py, double eta,
                                                            const int* __restrict__ active)
 {
+    constexpr bool UP = LEG == kLegUp;
     constexpr int W = kTbTile + 2 * M, NC = W * W;
     __shared__ double sE[2][NC], sFx[2][NC], sFy[2][NC], sT[2][NC];
     __shared__ double qE[NC], qFx[NC], qFy[NC], qT[NC], qa[NC], qs[NC];
@@ -932,7 +935,7 @@ __global__ __launch_bounds__(kTbThreads) void k_smooth_tb(Phys ph, Lvl L, CSoa f
 #pragma unroll 1
     for (int s = 1; s <= M; ++s) {
         const int nw = W - 2 * s, n = nw * nw;
-        const bool first = !UP && s == 1;
+        const bool first = LEG == kLegDown && s == 1;
         for (int q = threadIdx.x; q < n; q += kTbThreads) {
             const int li = s + q % nw, lj = s + q / nw;
             int gi, gj;
@@ -1636,19 +1639,22 @@ bool smooth_tb_fits(int dim, const Lvl& L, int m)
            L.ny >= 2 * kTbTile;
 }
 
-void launch_smooth_tb(hipStream_t st, const Phys& ph, const Lvl& L, int m, bool up, CSoa fr, Soa f, CSoa u, Soa out,
+void launch_smooth_tb(hipStream_t st, const Phys& ph, const Lvl& L, int m, int leg, CSoa fr, Soa f, CSoa u, Soa out,
                       const double* dtau_dev, double reach, int local, CSoa uc, CSoa vc, int px, int py, double eta,
                       const int* active)
 {
     const dim3 g((unsigned)((L.nx / kTbTile) * (L.ny / kTbTile))), b(kTbThreads);
 #define M1_TB(MM)                                                                                                    \
     do {                                                                                                             \
-        if (up)                                                                                                      \
-            hipLaunchKernelGGL((k_smooth_tb<MM, true>), g, b, 0, st, ph, L, fr, f, u, out, dtau_dev, reach, local, \
+        if (leg == kLegUp)                                                                                           \
+            hipLaunchKernelGGL((k_smooth_tb<MM, kLegUp>), g, b, 0, st, ph, L, fr, f, u, out, dtau_dev, reach, local, \
                                uc, vc, px, py, eta, active);                                                         \
+        else if (leg == kLegPlain)                                                                                   \
+            hipLaunchKernelGGL((k_smooth_tb<MM, kLegPlain>), g, b, 0, st, ph, L, fr, f, u, out, dtau_dev, reach,     \
+                               local, uc, vc, px, py, eta, active);                                                  \
         else                                                                                                         \
-            hipLaunchKernelGGL((k_smooth_tb<MM, false>), g, b, 0, st, ph, L, fr, f, u, out, dtau_dev, reach, local, \
-                               uc, vc, px, py, eta, active);                                                         \
+            hipLaunchKernelGGL((k_smooth_tb<MM, kLegDown>), g, b, 0, st, ph, L, fr, f, u, out, dtau_dev, reach,      \
+                               local, uc, vc, px, py, eta, active);                                                  \
     } while (0)
     if (m == 1) M1_TB(1);
     else if (m == 2) M1_TB(2);

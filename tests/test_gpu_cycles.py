@@ -97,6 +97,39 @@ def test_converged_step_parity(kind, case):
     assert abs(cycles - info_o["cycles"]) <= 1
 
 
+@pytest.mark.parametrize("kind", ["W", "F"])
+@pytest.mark.parametrize("case", ["logn128", "mixed96x80"])
+def test_cycle_launch_shapes_give_the_same_bits(kind, case):
+    """The recursive cycles smooth small levels by tiled legs (the first visit's forming the FAS right-hand side,
+    a later visit's plain, the correction with the post-smoothing) and fuse the finest correction with the first
+    post-sweep; with those off (one-step kernels, separate correction) the cycles and a converged step give the
+    same bits and cycle count."""
+    announce("cycle launch shapes", kind, case)
+    prob, v, sig = case_problem(case)
+    o = oracle.Oracle(prob, sig)
+    b = o.rhs(v)
+    keys = ("tiled_max_cells", "sweep_rows")
+    old = {k: binding.tune_get(k) for k in keys}
+    res = {}
+    try:
+        for off in (0, 1):
+            for k in keys:
+                binding.tune_set(k, 0 if off else old[k])
+            P = binding.Plan(prob, to_dev(sig), dict(omega=OMEGA, cycle=kind, rtol=1e-12, max_cycles=20000))
+            vd, vn = to_dev(v), to_dev(v)
+            for dtau in (1e-3, 0.3, 5.0):
+                P.vcycle(vd, vn, dtau)
+            w = to_dev(v)
+            info = P.step(w, 2)
+            res[off] = (to_host(vd), to_host(w), info["cycles"])
+    finally:
+        for k in keys:
+            binding.tune_set(k, old[k])
+    np.testing.assert_array_equal(res[0][0], res[1][0])
+    np.testing.assert_array_equal(res[0][1], res[1][1])
+    assert res[0][2] == res[1][2]
+
+
 @pytest.mark.parametrize("kind,transfer", [("W", "full"), ("F", "full"), ("V", "mean")])
 def test_mixed_precision_and_engines_reject_w_f_and_the_pair(kind, transfer):
     announce("cycle rejections", kind, transfer)
