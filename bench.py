@@ -80,6 +80,7 @@ SOLVER = dict(omega=0.8, levels=0)
 # (coarsest 64^2).
 WORKLOAD_LEVELS = {"hotwall": 5, "lognormal": 7}
 RESET_LEVELS = {"hotwall": 6, "lognormal": 7}  # the fastest depths with the step restarted at every time step
+FCYCLE_LEVELS = {"hotwall": 4, "lognormal": 6}  # the fastest depths of F-cycles (a sweep over 4..8 levels)
 
 
 def sweeps_per_launch():
@@ -556,6 +557,20 @@ SERVE_DESC = ("Poisson stream, side log-uniform in 64..2048, contrast 10^U[0,6],
 
 
 # ---------------------------------------------------------------------------
+def fcycle_leg(torch, out, args, prob, dev_sig, v_init, run, precision, cells):
+    """The same solve with F-cycles (Sect. 6.3's alternative shape) at their fastest depth, FP64."""
+    if precision != "fp64":
+        return
+    levels = FCYCLE_LEVELS[args.workload]
+    plan = binding.Plan(prob, dev_sig, dict(rtol=run["rtol"], max_cycles=20000, precision=precision,
+                                            **dict(SOLVER, levels=levels, cycle="F")))
+    t, info, _ = timed_solves(torch, plan, v_init, run["steps"], 2)
+    del plan
+    out["f_cycles"] = {"what": f"F-cycles, {levels} levels, the rest as the headline solve",
+                       "value": round(cells * run["steps"] / t / 1e6, 3), "ms_per_step": round(t * 1e3, 3),
+                       "cycles_per_time_step": info["cycles"] / run["steps"], "solver_status": info["status"]}
+
+
 def reset_leg(torch, out, args, prob, dev_sig, v_init, run, precision, cells):
     """The whole solve with the pseudo-time step restarted at 1e-3 in every time step (dtau_carry=0), at that
     reading's own fastest depth."""
@@ -663,6 +678,7 @@ def main():
     # the other reading of the pseudo-time step across time steps: restarted at 1e-3 in every time step
     if not args.no_extras:
         reset_leg(torch, out, args, prob, dev_sig, v_init, run, precision, cells)
+        fcycle_leg(torch, out, args, prob, dev_sig, v_init, run, precision, cells)
     # the workload's own finest sweep (cache-resident at 1024^2), then the kernels at an HBM-resident size
     t_own = time_launches(torch, plan.stream, sweep_launcher(plan, b, v_init, sweeps_per_launch()), args.reps)
     own = roofline_entry(sweep_kernel(), f"finest-level FP64 Jacobi sweeps, {sweeps_per_launch()} per launch",
