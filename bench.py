@@ -348,6 +348,13 @@ def c3_leg(torch):
                      "cycles": info["cycles"], "levels": info["levels"], "status": info["status"],
                      "rel_residual": info["rel_residual"]}
         del plan
+    # W-cycles (Sect. 6.3's alternative shape) in mixed precision, at their fastest depth
+    plan = binding.Plan(prob, sd, dict(rtol=run["rtol"], max_cycles=20000, precision="mixed",
+                                       **dict(SOLVER, levels=5, cycle="W")))
+    t, info, _ = timed_solves(torch, plan, vd, run["steps"], 3)
+    del plan
+    out["mixed_w_cycles"] = {"levels": 5, "Mcell_updates_per_s": round(cells * run["steps"] / t / 1e6, 2),
+                             "time_to_rtol_ms": round(t * 1e3, 2), "cycles": info["cycles"], "status": info["status"]}
     out["mixed_speedup_vs_fp64"] = round(out["fp64"]["time_to_rtol_ms"] / out["mixed"]["time_to_rtol_ms"], 3)
     out["max_rel_diff_mixed_vs_fp64"] = state_rel(res["mixed"], res["fp64"], prob["c"])
     del res

@@ -119,7 +119,7 @@ typedef struct {
  *                 the alternatives of Sect. 6.3.  Every visit of a coarse
  *                 level runs the pseudo-time smoothing of Algorithm 3 before
  *                 and after its correction (the coarsest: once per visit).
- *                 W and F: FP64 plans only, not in engines;
+ *                 W and F: not in engines;
  *   transfer      grid-transfer operators: M1_TRANSFER_FULL (Sect. 4.2: linear
  *                 prolongation, full-weighting restriction R = 2^-d P^T) or
  *                 M1_TRANSFER_MEAN (coarse cell I is fine cells 2I, 2I+1 per

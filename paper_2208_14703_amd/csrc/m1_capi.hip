@@ -122,7 +122,6 @@ bool valid_params(const m1_params* p)
     if (p->smoother != M1_SMOOTH_JACOBI && p->smoother != M1_SMOOTH_RBGS) return false;
     if (p->smoother == M1_SMOOTH_RBGS && p->precision != M1_FP64) return false;
     if (p->cycle != M1_CYCLE_V && p->cycle != M1_CYCLE_W && p->cycle != M1_CYCLE_F) return false;
-    if (p->cycle != M1_CYCLE_V && p->precision != M1_FP64) return false;  // the recursion is FP64 only
     if (p->transfer != M1_TRANSFER_FULL && p->transfer != M1_TRANSFER_MEAN) return false;
     if (p->transfer != M1_TRANSFER_FULL && p->precision != M1_FP64) return false;
     if (!(p->eta > 0.0 && p->eta < 1.0) || !(p->omega > 0.0 && p->omega <= 1.0) || !(p->rtol > 0.0)) return false;
@@ -703,13 +702,69 @@ Soa32 mx_pseudo_smooth(m1_plan& P, int l, const Gate& G, Soa32 start, bool first
     return in;
 }
 
-// One mixed-precision V-cycle.  cur64 holds the FP64 state; the pending FP32
+// Mixed-precision W- and F-cycles: the recursion of the FP64 form on the FP32
+// correction levels.  Level l >= 1 carries the base w, the restricted
+// correction d, the iterate e/e2 and the FAS right-hand side g (and the
+// explicit sub-steps' source fr); a visit smooths from d (the first of a
+// descent, which forms g and fr) or from the previous visit's result.
+
+// rho of level l (r - N(d) on the finest level, g - N_w(e) below) restricted
+// with w and the correction into level l + 1 (w, d, g).
+void mx_descend(m1_plan& P, int l, const Soa32& e, const Gate& G)
+{
+    const LevelBuf& fl = P.lev[l];
+    LevelBuf& c = P.lev[l + 1];
+    const Soa32& w = l == 0 ? P.base32 : fl.w;
+    const Soa32& rhs = l == 0 ? P.r32 : fl.gg;
+    if (P.dim == 2 && m1::residual_restrict()) {
+        m1::launch_mx_residual_restrict(P.st, P.ph, fl.L32, cs(w), cs(e), cs(rhs), -1.0f, P.px, P.py, c.w, c.d, c.gg,
+                                        G.active);
+        return;
+    }
+    const Soa32& rho = l == 0 ? P.rho0 : fl.rho;
+    m1::launch_mx_apply(P.st, P.dim, P.ph, fl.L32, cs(w), cs(e), cs(rhs), -1.0f, rho, G.active);
+    m1::launch_mx_restrict(P.st, P.dim, fl.nx, fl.ny, P.px, P.py, fields32({{&w, &c.w}, {&e, &c.d}, {&rho, &c.gg}},
+                                                                           P.dim),
+                           G.active);
+}
+
+Soa32 mx_coarse_visit(m1_plan& P, int l, int kind, const Gate& G, Soa32 e, bool first);
+
+// Visit level l + 1 as `kind` prescribes; its final iterate.
+Soa32 mx_visit_below(m1_plan& P, int l, int kind, const Gate& G)
+{
+    const LevelBuf& c = P.lev[l + 1];
+    Soa32 ec;
+    if (kind == M1_CYCLE_F) {
+        ec = mx_coarse_visit(P, l + 1, M1_CYCLE_F, G, c.d, true);
+        ec = mx_coarse_visit(P, l + 1, M1_CYCLE_V, G, ec, false);
+    } else {
+        ec = mx_coarse_visit(P, l + 1, kind, G, c.d, true);
+        if (kind == M1_CYCLE_W) ec = mx_coarse_visit(P, l + 1, kind, G, ec, false);
+    }
+    return ec;
+}
+
+Soa32 mx_coarse_visit(m1_plan& P, int l, int kind, const Gate& G, Soa32 e, bool first)
+{
+    e = mx_pseudo_smooth(P, l, G, e, first);
+    if (l == P.L - 1) return e;
+    mx_descend(P, l, e, G);
+    const Soa32 ec = mx_visit_below(P, l, kind, G);
+    const LevelBuf& c = P.lev[l + 1];
+    const LevelBuf& fl = P.lev[l];
+    m1::launch_mx_prolong(P.st, P.dim, P.ph, fl.nx, fl.ny, P.px, P.py, (float)P.params.eta, cs(fl.w), cs(e), cs(ec),
+                          cs(c.d), e, G.active);
+    return mx_pseudo_smooth(P, l, G, e, false);
+}
+
+// One mixed-precision cycle (V, W or F).  cur64 holds the FP64 state; the pending FP32
 // correction of the previous cycle (`first`: none) is applied by the FP64
 // residual kernel, which writes the updated state into the partner buffer.
 // On return `pend` is this cycle's correction (applied by the next cycle or
 // by the caller).  With `control` the FP64 residual norm feeds the cycle control.
 // False (nothing enqueued) if the buffers would alias.
-bool mx_vcycle(m1_plan& P, Soa& cur64, Soa& other64, const Gate& G, bool control, bool first, Soa32& pend)
+bool mx_cycle(m1_plan& P, Soa& cur64, Soa& other64, const Gate& G, bool control, bool first, Soa32& pend)
 {
     const m1_params& p = P.params;
     const LevelBuf& f0 = P.lev[0];
@@ -747,40 +802,46 @@ bool mx_vcycle(m1_plan& P, Soa& cur64, Soa& other64, const Gate& G, bool control
         pend = d;
         return true;
     }
-    const bool fused = P.dim == 2 && m1::residual_restrict();  // rho0 restricted as it is formed
-    if (!fused)
-        m1::launch_mx_apply(P.st, P.dim, P.ph, f0.L32, cs(P.base32), cs(d), cs(P.r32), -1.0f, P.rho0, G.active);
     Soa32 el[kMaxPlanLevels];
     el[0] = d;
-    const Soa32* wprev = &P.base32;
-    const Soa32* rprev = &P.rho0;
-    for (int l = 1; l < P.L; ++l) {
-        LevelBuf& c = P.lev[l];
-        const LevelBuf& fl = P.lev[l - 1];
-        if (fused)  // rho of level l - 1 (r - N(d) on the finest, g - N_w(e) below) and the restrictions
-            m1::launch_mx_residual_restrict(P.st, P.ph, fl.L32, cs(*wprev), cs(el[l - 1]),
-                                            l == 1 ? cs(P.r32) : cs(fl.gg), -1.0f, P.px, P.py, c.w, c.d, c.gg,
-                                            G.active);
-        else
-            m1::launch_mx_restrict(P.st, P.dim, fl.nx, fl.ny, P.px, P.py,
-                                   fields32({{wprev, &c.w}, {&el[l - 1], &c.d}, {rprev, &c.gg}}, P.dim), G.active);
-        if (l == P.lt) {  // the rest of the cycle below (and including) level lt in one workgroup
-            m1::launch_mx_tail(P.st, P.dim, P.dtail32, G.dtau, G.dtau_dev, G.active);
-            el[l] = c.e;
-            break;
+    if (p.cycle == M1_CYCLE_V) {
+        const bool fused = P.dim == 2 && m1::residual_restrict();  // rho0 restricted as it is formed
+        if (!fused)
+            m1::launch_mx_apply(P.st, P.dim, P.ph, f0.L32, cs(P.base32), cs(d), cs(P.r32), -1.0f, P.rho0, G.active);
+        const Soa32* wprev = &P.base32;
+        const Soa32* rprev = &P.rho0;
+        for (int l = 1; l < P.L; ++l) {
+            LevelBuf& c = P.lev[l];
+            const LevelBuf& fl = P.lev[l - 1];
+            if (fused)  // rho of level l - 1 (r - N(d) on the finest, g - N_w(e) below) and the restrictions
+                m1::launch_mx_residual_restrict(P.st, P.ph, fl.L32, cs(*wprev), cs(el[l - 1]),
+                                                l == 1 ? cs(P.r32) : cs(fl.gg), -1.0f, P.px, P.py, c.w, c.d, c.gg,
+                                                G.active);
+            else
+                m1::launch_mx_restrict(P.st, P.dim, fl.nx, fl.ny, P.px, P.py,
+                                       fields32({{wprev, &c.w}, {&el[l - 1], &c.d}, {rprev, &c.gg}}, P.dim),
+                                       G.active);
+            if (l == P.lt) {  // the rest of the cycle below (and including) level lt in one workgroup
+                m1::launch_mx_tail(P.st, P.dim, P.dtail32, G.dtau, G.dtau_dev, G.active);
+                el[l] = c.e;
+                break;
+            }
+            el[l] = mx_pseudo_smooth(P, l, G, c.d, true);  // forms g = N_w(d) + R(rho)
+            if (l < P.L - 1 && !fused)
+                m1::launch_mx_apply(P.st, P.dim, P.ph, c.L32, cs(c.w), cs(el[l]), cs(c.gg), -1.0f, c.rho, G.active);
+            wprev = &c.w;
+            rprev = &c.rho;
         }
-        el[l] = mx_pseudo_smooth(P, l, G, c.d, true);  // forms g = N_w(d) + R(rho)
-        if (l < P.L - 1 && !fused)
-            m1::launch_mx_apply(P.st, P.dim, P.ph, c.L32, cs(c.w), cs(el[l]), cs(c.gg), -1.0f, c.rho, G.active);
-        wprev = &c.w;
-        rprev = &c.rho;
-    }
-    for (int l = std::min(P.lt, P.L - 1) - 1; l >= 1; --l) {
-        const LevelBuf& c = P.lev[l + 1];
-        const LevelBuf& fl = P.lev[l];
-        m1::launch_mx_prolong(P.st, P.dim, P.ph, fl.nx, fl.ny, P.px, P.py, (float)p.eta, cs(fl.w), cs(el[l]),
-                              cs(el[l + 1]), cs(c.d), el[l], G.active);
-        el[l] = mx_pseudo_smooth(P, l, G, el[l], false);
+        for (int l = std::min(P.lt, P.L - 1) - 1; l >= 1; --l) {
+            const LevelBuf& c = P.lev[l + 1];
+            const LevelBuf& fl = P.lev[l];
+            m1::launch_mx_prolong(P.st, P.dim, P.ph, fl.nx, fl.ny, P.px, P.py, (float)p.eta, cs(fl.w), cs(el[l]),
+                                  cs(el[l + 1]), cs(c.d), el[l], G.active);
+            el[l] = mx_pseudo_smooth(P, l, G, el[l], false);
+        }
+    } else {  // W- or F-cycle: the coarse problems as a recursion
+        mx_descend(P, 0, d, G);
+        el[1] = mx_visit_below(P, 0, p.cycle, G);
     }
     const Soa32 post = same32(el[0], P.dA) ? P.dB : P.dA;
     if (P.dim == 2 && p.nu0 >= 1 &&
@@ -844,7 +905,7 @@ m1_status graph_cycle(m1_plan& P, Soa& cur, Soa& other, Soa32& pend, const Gate&
         m1_plan::CycleGraph c{cur.E, other.E, pk, f, cur, other, pend, nullptr};
         bool ok = true;
         const m1_status s = record(&P.st, P.cap, [&] {
-            if (P.mixed) ok = mx_vcycle(P, c.cur, c.other, G, true, first, c.pend);
+            if (P.mixed) ok = mx_cycle(P, c.cur, c.other, G, true, first, c.pend);
             else cycle_impl(P, c.cur, c.other, G, true);
         }, &c.exec);
         if (s == M1_OK && !ok) (void)hipGraphExecDestroy(c.exec);
@@ -1177,7 +1238,7 @@ m1_status m1_vcycle(m1_plan* P, m1_state* v, const m1_state* vn, double dtau, m1
     }
     if (P->mixed) {
         Soa32 pend{};
-        if (!mx_vcycle(*P, cur, other, fixed_gate(*P, dtau), false, true, pend)) return M1_ERR_DEVICE;
+        if (!mx_cycle(*P, cur, other, fixed_gate(*P, dtau), false, true, pend)) return M1_ERR_DEVICE;
         // apply the correction: the state is now in tmp; write the update back to v
         m1::launch_mx_resid(P->st, P->dim, P->ph, P->lev[0].L, P->params.eta, cs(cur), cs(pend), cs(P->b), user,
                             P->base32, P->r32, nullptr, &P->dfix->active);
@@ -1282,7 +1343,7 @@ m1_status m1_step(m1_plan* P, m1_state* v, int32_t nsteps, m1_info* info)
                     const m1_status s = graph_cycle(*P, cur, other, pend, G, enqueued + c == 0);
                     if (s != M1_OK) return s;
                 } else if (P->mixed) {
-                    if (!mx_vcycle(*P, cur, other, G, true, enqueued + c == 0, pend)) return M1_ERR_DEVICE;
+                    if (!mx_cycle(*P, cur, other, G, true, enqueued + c == 0, pend)) return M1_ERR_DEVICE;
                 } else {
                     cycle_impl(*P, cur, other, G, true);
                 }

@@ -11,7 +11,10 @@
   restriction, the residual with its restriction and the correction with
   projection on the finest and a coarse level (1e-14 / 1e-13), cycles of every
   shape (1e-11) and converged steps (1e-10) against the oracle.
-* W, F and the pair are FP64 only: mixed-precision plans and engines reject them.
+* Mixed precision runs W and F cycles too: converged steps within the mixed
+  bound (5e-10 at rtol 1e-12) of the oracle, cycle counts within a few of the
+  FP64 path's, and three cycles within 1e-5 of the FP64 cycles' results.
+* Engines reject W, F and the pair; mixed-precision plans reject the pair.
 """
 import ctypes
 
@@ -134,14 +137,53 @@ def test_cycle_launch_shapes_give_the_same_bits(kind, case):
 def test_mixed_precision_and_engines_reject_w_f_and_the_pair(kind, transfer):
     announce("cycle rejections", kind, transfer)
     prob, v, sig, _ = inputs.hot_wall_2d(n=64)
-    with pytest.raises(binding.M1Error) as e:
-        binding.Plan(prob, to_dev(sig), dict(omega=OMEGA, cycle=kind, transfer=transfer, precision="mixed"))
-    assert "M1_ERR_ARG" in str(e.value)
+    if transfer == "mean":  # mixed-precision W and F cycles are built; the transfer pair is FP64 only
+        with pytest.raises(binding.M1Error) as e:
+            binding.Plan(prob, to_dev(sig), dict(omega=OMEGA, cycle=kind, transfer=transfer, precision="mixed"))
+        assert "M1_ERR_ARG" in str(e.value)
     p = binding.make_params(binding.default_params(omega=OMEGA, cycle=kind, transfer=transfer))
     arena = ctypes.c_void_p(256)  # never dereferenced: the parameters are checked first
     out = ctypes.c_void_p()
     st = binding.lib().m1_engine_create(ctypes.byref(p), arena, 1 << 20, 4, None, ctypes.byref(out))
     assert st == 1 and not out.value  # M1_ERR_ARG
+
+
+@pytest.mark.parametrize("kind", ["W", "F"])
+@pytest.mark.parametrize("case", ["hot128", "mixed96x80"])
+def test_mixed_precision_cycles(kind, case):
+    """Mixed-precision W and F cycles: the FP32 correction levels take the FP64 recursion.  Three cycles stay
+    within 1e-5 (relative, E/F/T scales; FP32 rounding of corrections of the state's size, 1.1e-6 observed) of the
+    FP64 cycles from the same state, converged steps within the mixed bound of the oracle."""
+    announce("mixed cycle", kind, case)
+    if case == "hot128":
+        prob, v, sig, _ = inputs.hot_wall_2d(n=128)
+    else:
+        prob, v, sig = case_problem(case)
+    sd = to_dev(sig)
+    got = {}
+    for prec in ("fp64", "mixed"):
+        P = binding.Plan(prob, sd, dict(omega=OMEGA, cycle=kind, precision=prec))
+        vd, vn = to_dev(v), to_dev(v)
+        for dtau in (1e-3, 0.3, 5.0):
+            P.vcycle(vd, vn, dtau)
+        got[prec] = to_host(vd)
+    err_c = rel_err(got["mixed"], got["fp64"], prob["c"])
+    o = oracle.Oracle(prob, sig)
+    ref, io = o.step(v, 2, oracle.make_params(omega=OMEGA, rtol=1e-13, max_cycles=40000, cycle=kind))
+    counts = {}
+    for prec, rtol in (("mixed", 1e-12), ("fp64", 1e-12)):
+        P = binding.Plan(prob, sd, dict(omega=OMEGA, cycle=kind, precision=prec, rtol=rtol, max_cycles=40000))
+        vd = to_dev(v)
+        info = P.step(vd, 2)
+        assert info["status"] == 0, info
+        counts[prec] = info["cycles"]
+        if prec == "mixed":
+            err_s = rel_err(to_host(vd), ref, prob["c"])
+    print(f"mixed {kind} {case}: three cycles vs FP64 {err_c:.2e}; two steps vs oracle {err_s:.2e}; cycles "
+          f"mixed/fp64/oracle {counts['mixed']} {counts['fp64']} {io['cycles']}", flush=True)
+    assert err_c <= 1e-5
+    assert err_s <= 5e-10
+    assert abs(counts["mixed"] - counts["fp64"]) <= 4
 
 
 # ------------------------------------------------------------------ the cell-agglomeration transfer pair
