@@ -47,8 +47,9 @@ The same JSON line also carries:
 Other modes:
 - --workload lognormal: the 4096^2 single solve (mixed or fp64).
 - --workload serve: the serving sweep over arrival rates.
+- --workload hotwall3d: the 256^3 3-D hot wall (10 steps) and its sweep kernel.
 - --profile kernels: only the 4096^2 kernel launches of the roofline entries and a copy kernel
-  of known size, for PMC counter runs.
+  of known size, for PMC counter runs (kernels3d: the 256^3 3-D sweep and the copy).
 """
 from __future__ import annotations
 
@@ -114,7 +115,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="hotwall", choices=["hotwall", "lognormal", "batch", "serve"])
+    ap.add_argument("--workload", default="hotwall", choices=["hotwall", "lognormal", "batch", "serve", "hotwall3d"])
     ap.add_argument("--n", type=int, default=0, help="grid side (default: the workload's own)")
     ap.add_argument("--levels", type=int, default=-1,
                     help="L_max of the hot-wall/lognormal solve (default: the workload's measured fastest; 0: to side 4)")
@@ -129,8 +130,9 @@ def parse():
     ap.add_argument("--rates", default="50", help="comma-separated arrival rates (1/s) for serving")
     ap.add_argument("--arena-gb", type=float, default=64.0, help="engine HBM budget for serving")
     ap.add_argument("--serve-precision", default="mixed", choices=["fp64", "mixed"])
-    ap.add_argument("--profile", default="none", choices=["none", "kernels"],
-                    help="kernels: only the 4096^2 kernel launches and a copy of known size (for counter runs)")
+    ap.add_argument("--profile", default="none", choices=["none", "kernels", "kernels3d"],
+                    help="kernels: only the 4096^2 kernel launches and a copy of known size (for counter runs); "
+                         "kernels3d: the same for the 256^3 3-D sweep")
     ap.add_argument("--reps", type=int, default=40, help="sweep launches timed for the roofline")
     ap.add_argument("--stream", default="own", choices=["own", "default"],
                     help="own: run on a created stream (default priority); default: the null stream")
@@ -380,11 +382,6 @@ def three_d_leg(torch, reps):
     info = plan.step(v, run["steps"])
     torch.cuda.synchronize()
     t = time.perf_counter() - t0
-    L = binding.lib()
-    b = vd.clone()
-    b[4] *= prob["c_v"]
-    bufs, k = [vd.clone(), vd.clone()], [0]
-
     rplan = binding.Plan3(prob, sd, dict(rtol=run["rtol"], max_cycles=20000, **dict(SOLVER, dtau_carry=0)))
     v.copy_(vd)
     torch.cuda.synchronize()
@@ -393,6 +390,24 @@ def three_d_leg(torch, reps):
     torch.cuda.synchronize()
     t_reset = time.perf_counter() - t0
     del rplan
+    out = {"workload": "hot wall 3-D 256^3, 10 implicit steps, dt=100h/c, 8^3 opacity blocks, FP64, rtol 1e-8",
+           "Mcell_updates_per_s": round(cells * run["steps"] / t / 1e6, 2), "time_to_rtol_ms": round(t * 1e3, 1),
+           "cycles": info["cycles"], "levels": info["levels"], "status": info["status"],
+           "dtau_reset": {"time_to_rtol_ms": round(t_reset * 1e3, 1), "cycles": i_reset["cycles"],
+                          "status": i_reset["status"]},
+           "roofline": sweep3_entry(torch, plan, prob, vd, reps)}
+    del plan, v
+    torch.cuda.empty_cache()
+    return out
+
+
+def sweep3_entry(torch, plan, prob, vd, reps):
+    """The 3-D finest-level sweep (m1_sweep3) timed with HIP events on the plan's stream."""
+    L = binding.lib()
+    cells = prob["nx"] * prob["ny"] * prob["nz"]
+    b = vd.clone()
+    b[4] *= prob["c_v"]
+    bufs, k = [vd.clone(), vd.clone()], [0]
 
     def launch():
         binding._check(L.m1_sweep3(plan.handle, binding.ctypes.byref(plan._st(b)),
@@ -401,16 +416,19 @@ def three_d_leg(torch, reps):
         k[0] ^= 1
     tk = time_launches(torch, plan.stream, launch, reps)
     kname = "k3_staged<1>" if binding.tune_get("stage3") >= 1 else "k3_relax"
-    out = {"workload": "hot wall 3-D 256^3, 10 implicit steps, dt=100h/c, 8^3 opacity blocks, FP64, rtol 1e-8",
-           "Mcell_updates_per_s": round(cells * run["steps"] / t / 1e6, 2), "time_to_rtol_ms": round(t * 1e3, 1),
-           "cycles": info["cycles"], "levels": info["levels"], "status": info["status"],
-           "dtau_reset": {"time_to_rtol_ms": round(t_reset * 1e3, 1), "cycles": i_reset["cycles"],
-                          "status": i_reset["status"]},
-           "roofline": roofline_entry(kname, "finest-level FP64 Jacobi sweep, 3-D", SWEEP3_BYTES_PER_CELL * cells, tk,
-                                      None, "256x256x256", "HBM (2.3 GB working set)")}
-    del plan, v, b, bufs
+    tag = "k3_staged1" if binding.tune_get("stage3") >= 1 else "k3_relax"
+    return roofline_entry(kname, "finest-level FP64 Jacobi sweep, 3-D", SWEEP3_BYTES_PER_CELL * cells, tk,
+                          read_traffic(tag, "hotwall3d256", kname, cells), "256x256x256", "HBM (2.3 GB working set)")
+
+
+def kernel3_leg(torch, reps):
+    """Only the 3-D sweep kernel on the 256^3 hot wall's plan (for counter runs)."""
+    prob, v0, sig, run = inputs.hot_wall_3d(n=256)
+    plan = binding.Plan3(prob, binding.to_device(sig), dict(rtol=run["rtol"], max_cycles=20000, **SOLVER))
+    entry = sweep3_entry(torch, plan, prob, binding.to_device(v0), reps)
+    del plan
     torch.cuda.empty_cache()
-    return out
+    return entry
 
 
 # ---------------------------------------------------------------------------
@@ -617,6 +635,15 @@ def main():
                           "rates": legs}), flush=True)
         return
 
+    if args.workload == "hotwall3d":
+        leg = three_d_leg(torch, args.reps)
+        print(json.dumps({"metric": METRIC, "value": leg["Mcell_updates_per_s"], "unit": "Mcell-updates/s",
+                          "n_gpus": 1, "steps": 1, "warmup": 1, "ms_per_step": leg["time_to_rtol_ms"],
+                          "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+                          "data": "synthetic", "config": {"workload": leg["workload"]}, "roofline": leg["roofline"],
+                          "three_d": leg}), flush=True)
+        return
+
     if args.workload == "batch":
         leg = batch_leg(torch, args.batch)
         best = leg["mixed"]
@@ -645,6 +672,14 @@ def main():
     v = torch.empty_like(v_init)
     b = v_init.clone()
     b[3] *= prob["c_v"]
+
+    if args.profile == "kernels3d":
+        del plan
+        torch.cuda.empty_cache()
+        entry = kernel3_leg(torch, args.reps)
+        print(json.dumps({"profile": "kernels3d", "cells": 256 ** 3, "kernels": [entry], "copy": copy_timing(torch)}),
+              flush=True)
+        return
 
     if args.profile == "kernels":
         del plan
