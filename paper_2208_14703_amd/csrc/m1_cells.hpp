@@ -379,6 +379,46 @@ __device__ __forceinline__ void prolong_value(const Phys& ph, int nx, int ny, in
     }
 }
 
+// prolong_value of a fine cell (i, j) of a level of nx x ny cells whose coarse
+// corrections uc - vc are staged: c?[(Jc - Jc0) cw + Ic - Ic0] for the coarse
+// cells it reads, none of them across a side (no wrap, no clamp).  The same
+// weights, differences and order as prolong_value, so the same result.
+__device__ __forceinline__ void prolong_value_staged(const Phys& ph, int nx, int ny, double eta, int i, int j,
+                                                     double uE, double uFx, double uFy, double uT, const double* cE,
+                                                     const double* cFx, const double* cFy, const double* cT, int Ic0,
+                                                     int Jc0, int cw, double& wE, double& wFx, double& wFy,
+                                                     double& wT)
+{
+    int ix[2], iy[2];
+    double wx[2], wy[2];
+    pweights(i, nx / 2, false, ix, wx);
+    pweights(j, ny / 2, false, iy, wy);
+    double e0 = 0.0, e1 = 0.0, e2 = 0.0, e3 = 0.0;
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+#pragma unroll
+        for (int a = 0; a < 2; ++a) {
+            const int c = (iy[b] - Jc0) * cw + ix[a] - Ic0;
+            const double w = wx[a] * wy[b];
+            e0 = fma(w, cE[c], e0);
+            e1 = fma(w, cFx[c], e1);
+            e2 = fma(w, cFy[c], e2);
+            e3 = fma(w, cT[c], e3);
+        }
+    }
+    wE = uE + e0;
+    wFx = uFx + e1;
+    wFy = uFy + e2;
+    wT = uT + e3;
+    if (!admissible(ph.c2, wE, wFx, wFy, wT)) {
+        const double th = eta * fmin(ray_len(ph.c2, uE, uFx, uFy, uT, e0, e1, e2, e3), 1.0);
+        wE = fma(th, e0, uE);
+        wFx = fma(th, e1, uFx);
+        wFy = fma(th, e2, uFy);
+        wT = fma(th, e3, uT);
+    }
+}
+
 template <int DIM>
 __device__ __forceinline__ void prolong_cell(const Phys& ph, int nx, int ny, int sh, int px, int py, double eta,
                                              const CSoa& u, const CSoa& uc, const CSoa& vc, const Soa& out, uint32_t k,

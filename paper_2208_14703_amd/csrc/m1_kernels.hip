@@ -150,13 +150,42 @@ __device__ __forceinline__ bool tile_interior(const Lvl& L, int ty, int i0, int 
     return i0 >= 1 && j0 >= 1 && i0 + kLdsTX + 1 <= L.nx && j0 + ty + 1 <= L.ny;
 }
 
+// The coarse corrections uc - vc an up-leg tile reads, staged once per block
+// when the tile's coarse footprint lies inside the coarse grid (no wrap or
+// clamp): CW x CH coarse cells from (i0 / 2 - 1, j0 / 2 - 1).
+template <int TY>
+struct CoarseStage {
+    static constexpr int CW = kLdsTX / 2 + 3, CH = TY / 2 + 3, N = CW * CH;
+    double E[N], Fx[N], Fy[N], T[N];
+};
+__device__ __forceinline__ bool coarse_stage_fits(const Lvl& L, int ty, int i0, int j0)
+{
+    return i0 >= 2 && j0 >= 2 && i0 + kLdsTX + 4 <= L.nx && j0 + ty + 4 <= L.ny;
+}
+template <int TY>
+__device__ __forceinline__ void stage_coarse(CoarseStage<TY>& s, const Lvl& L, const CSoa& uc, const CSoa& vc, int i0,
+                                             int j0)
+{
+    using S = CoarseStage<TY>;
+    const int Ic0 = i0 / 2 - 1, Jc0 = j0 / 2 - 1, nxc = L.nx / 2;
+    for (int c = threadIdx.x; c < S::N; c += kLdsTX * TY) {
+        const uint32_t kc = (uint32_t)(Jc0 + c / S::CW) * (uint32_t)nxc + (uint32_t)(Ic0 + c % S::CW);
+        s.E[c] = ld(uc.E, kc) - ld(vc.E, kc);
+        s.Fx[c] = ld(uc.Fx, kc) - ld(vc.Fx, kc);
+        s.Fy[c] = ld(uc.Fy, kc) - ld(vc.Fy, kc);
+        s.T[c] = ld(uc.T, kc) - ld(vc.T, kc);
+    }
+}
+
 // Stage the tile at (i0, j0) of state u.  UP: each gathered state is first
 // corrected from the coarse level (uc, vc) and projected (prolong_value, as
-// k_prolong_project) and its temperature kept in qT.  INTERIOR: the tile is
+// k_prolong_project) and its temperature kept in qT; with cst, from the staged
+// coarse corrections (prolong_value_staged).  INTERIOR: the tile is
 // tile_interior, and the side logic drops out (same arithmetic, same result).
 template <int TY, bool UP, bool INTERIOR = false>
 __device__ __forceinline__ void stage_tile(LdsTile<TY>& q, double* qT, const Phys& ph, const Lvl& L, const CSoa& u,
-                                           int i0, int j0, const CSoa& uc, const CSoa& vc, int px, int py, double eta)
+                                           int i0, int j0, const CSoa& uc, const CSoa& vc, int px, int py, double eta,
+                                           const CoarseStage<TY>* cst = nullptr)
 {
     static_assert(kLdsTX * TY >= 2 * kLdsTX + 2 * TY, "the halo needs 2 rows and 2 columns of threads");
     constexpr int W = LdsTile<TY>::W;
@@ -180,7 +209,14 @@ __device__ __forceinline__ void stage_tile(LdsTile<TY>& q, double* qT, const Phy
         if (need) {
             const uint32_t k = (uint32_t)gj * (uint32_t)L.nx + (uint32_t)gi;
             double le = ld(u.E, k), lfx = ld(u.Fx, k), lfy = ld(u.Fy, k);
-            if (UP) {
+            if (UP && cst) {
+                double wE, wFx, wFy;
+                prolong_value_staged(ph, L.nx, L.ny, eta, gi, gj, le, lfx, lfy, ld(u.T, k), cst->E, cst->Fx, cst->Fy,
+                                     cst->T, i0 / 2 - 1, j0 / 2 - 1, CoarseStage<TY>::CW, wE, wFx, wFy, tt);
+                le = wE;
+                lfx = wFx;
+                lfy = wFy;
+            } else if (UP) {
                 double wE, wFx, wFy;
                 prolong_value<2>(ph, L.nx, L.ny, px, py, eta, gi, gj, le, lfx, lfy, ld(u.T, k), uc, vc, wE, wFx, wFy,
                                  tt);
@@ -245,11 +281,21 @@ __global__ __launch_bounds__(kLdsTX * TY) void k_relax_lds(Phys ph, Lvl L, CSoa 
     constexpr int W = LdsTile<TY>::W;
     __shared__ LdsTile<TY> q;
     __shared__ double qT[UP ? LdsTile<TY>::N : 1];
+    __shared__ CoarseStage<UP ? TY : 2> cs_;
     if (*active == 0) return;
     int i0, j0;
     tile_origin(L, TY, i0, j0);
-    if (tile_interior(L, TY, i0, j0)) stage_tile<TY, UP, true>(q, qT, ph, L, u, i0, j0, uc, vc, px, py, eta);
-    else stage_tile<TY, UP>(q, qT, ph, L, u, i0, j0, uc, vc, px, py, eta);
+    if (UP && coarse_stage_fits(L, TY, i0, j0)) {  // inside the grid, coarse corrections staged
+        if constexpr (UP) {
+            stage_coarse<TY>(cs_, L, uc, vc, i0, j0);
+            __syncthreads();
+            stage_tile<TY, UP, true>(q, qT, ph, L, u, i0, j0, uc, vc, px, py, eta, &cs_);
+        }
+    } else if (tile_interior(L, TY, i0, j0)) {
+        stage_tile<TY, UP, true>(q, qT, ph, L, u, i0, j0, uc, vc, px, py, eta);
+    } else {
+        stage_tile<TY, UP>(q, qT, ph, L, u, i0, j0, uc, vc, px, py, eta);
+    }
     __syncthreads();
     const int li = threadIdx.x % kLdsTX, lj = threadIdx.x / kLdsTX, i = i0 + li, j = j0 + lj;
     if (i >= L.nx || j >= L.ny) return;

@@ -322,7 +322,8 @@ def test_launch_shape_settings_do_not_change_results(precision):
     keys = ("sweep_rows", "pair_rows", "mx_sweep_rows", "residual_restrict", "tail_cells", "tiled_max_cells",
             "batch_grid")
     saved = {key: binding.tune_get(key) for key in keys}
-    prob, v, sig = inputs.random_problem(41, 2, 96, 80, cfl=100.0, block=8)
+    # wide enough for tiles inside the grid (their fused correction sweep stages the coarse corrections once)
+    prob, v, sig = inputs.random_problem(41, 2, 260, 136, cfl=100.0, block=8)
     cases = problems(4)
     need = sum(binding.Engine.request_bytes(p, params) for p, _, _, _ in cases)
     settings = [dict(saved),
