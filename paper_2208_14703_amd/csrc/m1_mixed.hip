@@ -884,16 +884,13 @@ __global__ __launch_bounds__(kBlock32) void k_mx_prolong(Phys ph, int nx, int ny
     mx_prolong_cell<DIM>(ph, nx, ny, sh, px, py, eta, w, e, ec, dc, out, k, live);
 }
 
-// The corrected correction of fine cell k: e + theta P(e_c - d_c), theta from
-// the admissibility test of v + e + P(e_c - d_c) in FP64.
+// The rest of the fine correction of cell k from its coarse correction (c0..c3): the admissibility test of
+// v + e + c in FP64 (eq. prolongatedSol).
 template <int DIM>
-__device__ __forceinline__ void mx_prolong_fine_values(const Phys& ph, int nx, int ny, int sh, int px, int py,
-                                                       double eta, const CSoa& v, const CSoa32& e, const CSoa32& ec,
-                                                       const CSoa32& dc, uint32_t k, float& oE, float& oFx,
-                                                       float& oFy, float& oT)
+__device__ __forceinline__ void mx_prolong_fine_finish(const Phys& ph, double eta, const CSoa& v, const CSoa32& e,
+                                                       uint32_t k, float c0, float c1, float c2, float c3, float& oE,
+                                                       float& oFx, float& oFy, float& oT)
 {
-    float c0, c1, c2, c3;
-    coarse_corr<DIM>(nx, ny, sh, px, py, ec, dc, k, c0, c1, c2, c3);
     const float eE = ldf(e.E, k), eFx = ldf(e.Fx, k), eFy = (DIM == 2) ? ldf(e.Fy, k) : 0.0f, eT = ldf(e.T, k);
     const double sE = ld(v.E, k) + (double)eE, sFx = ld(v.Fx, k) + (double)eFx;
     const double sFy = ((DIM == 2) ? ld(v.Fy, k) : 0.0) + (double)eFy, sT = ld(v.T, k) + (double)eT;
@@ -905,6 +902,49 @@ __device__ __forceinline__ void mx_prolong_fine_values(const Phys& ph, int nx, i
     oFy = (DIM == 2) ? (float)fma(th, (double)c2, (double)eFy) : 0.0f;
     oT = (float)fma(th, (double)c3, (double)eT);
 }
+
+// The corrected correction of fine cell k: e + theta P(e_c - d_c), theta from
+// the admissibility test of v + e + P(e_c - d_c) in FP64.
+template <int DIM>
+__device__ __forceinline__ void mx_prolong_fine_values(const Phys& ph, int nx, int ny, int sh, int px, int py,
+                                                       double eta, const CSoa& v, const CSoa32& e, const CSoa32& ec,
+                                                       const CSoa32& dc, uint32_t k, float& oE, float& oFx,
+                                                       float& oFy, float& oT)
+{
+    float c0, c1, c2, c3;
+    coarse_corr<DIM>(nx, ny, sh, px, py, ec, dc, k, c0, c1, c2, c3);
+    mx_prolong_fine_finish<DIM>(ph, eta, v, e, k, c0, c1, c2, c3, oE, oFx, oFy, oT);
+}
+
+// The corrected correction of fine cell (i, j) of a 2-D level whose coarse
+// differences ec - dc are staged: c?[(Jc - Jc0) cw + Ic - Ic0] for the coarse
+// cells it reads, none across a side.  The weights, differences and order of
+// coarse_corr, so the result of mx_prolong_fine_values.
+__device__ __forceinline__ void mx_prolong_fine_values_staged(const Phys& ph, int nx, int ny, double eta, const CSoa& v,
+                                                              const CSoa32& e, uint32_t k, int i, int j,
+                                                              const float* cE, const float* cFx, const float* cFy,
+                                                              const float* cT, int Ic0, int Jc0, int cw, float& oE,
+                                                              float& oFx, float& oFy, float& oT)
+{
+    int ix[2], iy[2];
+    float wx[2], wy[2];
+    pw32(i, nx / 2, false, ix, wx);
+    pw32(j, ny / 2, false, iy, wy);
+    float c0 = 0.0f, c1 = 0.0f, c2 = 0.0f, c3 = 0.0f;
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+        for (int a = 0; a < 2; ++a) {
+            const int c = (iy[b] - Jc0) * cw + ix[a] - Ic0;
+            const float wgt = wx[a] * wy[b];
+            c0 = fmaf(wgt, cE[c], c0);
+            c1 = fmaf(wgt, cFx[c], c1);
+            c2 = fmaf(wgt, cFy[c], c2);
+            c3 = fmaf(wgt, cT[c], c3);
+        }
+    mx_prolong_fine_finish<2>(ph, eta, v, e, k, c0, c1, c2, c3, oE, oFx, oFy, oT);
+}
+
 
 template <int DIM>
 __device__ __forceinline__ void mx_prolong_fine_cell(const Phys& ph, int nx, int ny, int sh, int px, int py,
@@ -942,16 +982,41 @@ __global__ __launch_bounds__(kMxTX * TY) void k_mx_prolong_sweep_lds(Phys ph, Lv
                                                                     double eta, CSoa32 rhs, float omega, Soa32 out,
                                                                     const int* __restrict__ active)
 {
+    // the coarse differences ec - dc of the tile's footprint, staged once where it lies inside the coarse grid
+    constexpr int CW = kMxTX / 2 + 3, CH = TY / 2 + 3, CN = CW * CH;
     __shared__ MxTile<TY> q;
+    __shared__ float cE[CN], cFx[CN], cFy[CN], cT[CN];
     if (*active == 0) return;
     const int ntx = (L.nx + kMxTX - 1) / kMxTX;
     const int b = (int)xcd_block();
     const int i0 = (b % ntx) * kMxTX, j0 = (b / ntx) * TY;
-    auto d_at = [&](uint32_t k, float& E, float& Fx, float& Fy, float& T) {
-        mx_prolong_fine_values<2>(ph, L.nx, L.ny, sh, px, py, eta, v, e, ec, dc, k, E, Fx, Fy, T);
-    };
-    const float dT = mx_interior(L, TY, 1, i0, j0) ? mx_stage_tile_at<TY, true>(q, ph, L, w, d_at, i0, j0)
-                                                    : mx_stage_tile_at<TY>(q, ph, L, w, d_at, i0, j0);
+    float dT;
+    if (i0 >= 2 && j0 >= 2 && i0 + kMxTX + 4 <= L.nx && j0 + TY + 4 <= L.ny) {
+        const int Ic0 = i0 / 2 - 1, Jc0 = j0 / 2 - 1, nxc = L.nx / 2;
+        for (int c = threadIdx.x; c < CN; c += kMxTX * TY) {
+            const uint32_t kc = (uint32_t)(Jc0 + c / CW) * (uint32_t)nxc + (uint32_t)(Ic0 + c % CW);
+            cE[c] = ldf(ec.E, kc) - ldf(dc.E, kc);
+            cFx[c] = ldf(ec.Fx, kc) - ldf(dc.Fx, kc);
+            cFy[c] = ldf(ec.Fy, kc) - ldf(dc.Fy, kc);
+            cT[c] = ldf(ec.T, kc) - ldf(dc.T, kc);
+        }
+        __syncthreads();
+        dT = mx_stage_tile_at<TY, true>(
+            q, ph, L, w,
+            [&](uint32_t k, float& E, float& Fx, float& Fy, float& T) {
+                int i, j;
+                ij_of(L.nx, sh, k, i, j);
+                mx_prolong_fine_values_staged(ph, L.nx, L.ny, eta, v, e, k, i, j, cE, cFx, cFy, cT, Ic0, Jc0, CW, E,
+                                              Fx, Fy, T);
+            },
+            i0, j0);
+    } else {
+        auto d_at = [&](uint32_t k, float& E, float& Fx, float& Fy, float& T) {
+            mx_prolong_fine_values<2>(ph, L.nx, L.ny, sh, px, py, eta, v, e, ec, dc, k, E, Fx, Fy, T);
+        };
+        dT = mx_interior(L, TY, 1, i0, j0) ? mx_stage_tile_at<TY, true>(q, ph, L, w, d_at, i0, j0)
+                                            : mx_stage_tile_at<TY>(q, ph, L, w, d_at, i0, j0);
+    }
     __syncthreads();
     mx_tile_sweep<TY, true>(q, ph, L, w, CSoa32{}, rhs, 0.0f, 1.0f, omega, out, i0, j0, dT);
 }
