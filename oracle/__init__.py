@@ -391,6 +391,7 @@ def lib3():
         L.or3_num_levels.restype = ctypes.c_int32
         L.or3_num_levels.argtypes = [gp, pp]
         L.or3_vcycle.argtypes = [gp, dp, pp, ctypes.c_double, dp, dp, dp]
+        L.or3_cycle.argtypes = [gp, dp, pp, ctypes.c_int32, ctypes.c_double, dp, dp, dp]
         L.or3_step.restype = ctypes.c_int32
         L.or3_step.argtypes = [gp, dp, pp, dp, ctypes.c_int32, ctypes.POINTER(Info)]
         _lib3 = L
@@ -497,6 +498,14 @@ class Oracle3:
         out = self._new()
         self.L.or3_vcycle(ctypes.byref(self.g), _p(self.sigma), ctypes.byref(p), dtau, _p(self._c(b)),
                           _p(self._c(v)), _p(out))
+        return out
+
+    def cycle(self, b, v, dtau, kind, params=None):
+        """One cycle of the recursive form (kind "V", "W" or "F")."""
+        p = params or make_params()
+        out = self._new()
+        self.L.or3_cycle(ctypes.byref(self.g), _p(self.sigma), ctypes.byref(p), CYCLE[kind], dtau, _p(self._c(b)),
+                         _p(self._c(v)), _p(out))
         return out
 
     def step(self, v, nsteps=1, params=None):

@@ -9,7 +9,8 @@
  * directional flux (F_axis, c^2 P[:, axis]), the sources of eq. (m1) taken
  * implicitly, the nonlinear Jacobi sweep (Algorithm 1), the pseudo-time steps
  * of Algorithm 3, the admissible correction of eq. (prolongatedSol), trilinear
- * prolongation and its scaled transpose, and the V-cycle / time-step driver of
+ * prolongation and its scaled transpose, and the V-cycle (with the W and F
+ * shapes of Sect. 6.3) / time-step driver of
  * Appendix A with the same readings as the 2-D oracle.  The single-cell
  * gas-radiation solve is the 2-D oracle's (the flux components decouple from
  * it and share one divisor).
@@ -458,8 +459,127 @@ static void smooth3(const or3_grid* g, const double* sigma, const or_params* p, 
     free(nxt);
 }
 
-/* One V-cycle (Appendix A) with the FAS coarse problems of Sect. 4.2, as the 2-D oracle's loop form. */
+/* W- and F-cycles (Sect. 6.3; the shapes of or_cycle): the recursion over the
+ * coarse problems.  A visit of level l smooths its FAS problem (Algorithm 3),
+ * restricts the iterate and its residual to level l+1, visits that level once
+ * (V), twice (W) or by an F-visit then a V-visit (F), corrects with the
+ * projection of eq. (prolongatedSol) and smooths again; the coarsest level is
+ * smoothed once per visit.  Same steps as or3_vcycle below for kind V. */
+typedef struct {
+    int L;
+    or3_grid* G;
+    double **S, **U, **V, **F;
+} cyc3;
+
+static void visit3(const cyc3* c, const or_params* p, double dtau, int l, int kind);
+
+static void descend3(const cyc3* c, int l, const double* rhs)
+{
+    const size_t nc = ncell3(&c->G[l + 1]);
+    double* rb = dalloc3(NF3 * ncell3(&c->G[l]));
+    double* rr = dalloc3(NF3 * nc);
+    or3_residual(&c->G[l], c->S[l], rhs, c->U[l], rb);
+    or3_restrict(&c->G[l], c->U[l], NF3, c->V[l + 1]);
+    or3_restrict(&c->G[l], rb, NF3, rr);
+    or3_apply_A(&c->G[l + 1], c->S[l + 1], c->V[l + 1], c->F[l + 1]);
+    for (size_t k = 0; k < NF3 * nc; ++k) c->F[l + 1][k] += rr[k];
+    memcpy(c->U[l + 1], c->V[l + 1], NF3 * nc * sizeof(double));
+    free(rb);
+    free(rr);
+}
+
+static void below_and_correct3(const cyc3* c, const or_params* p, double dtau, int l, int kind)
+{
+    if (kind == OR_CYCLE_F) {
+        visit3(c, p, dtau, l + 1, OR_CYCLE_F);
+        visit3(c, p, dtau, l + 1, OR_CYCLE_V);
+    } else {
+        for (int t = 0; t < ((kind == OR_CYCLE_W) ? 2 : 1); ++t) visit3(c, p, dtau, l + 1, kind);
+    }
+    const size_t n = ncell3(&c->G[l]), nc = ncell3(&c->G[l + 1]);
+    double* e = dalloc3(NF3 * nc);
+    double* w = dalloc3(NF3 * n);
+    for (size_t k = 0; k < NF3 * nc; ++k) e[k] = c->U[l + 1][k] - c->V[l + 1][k];
+    or3_prolong(&c->G[l], e, NF3, w);
+    for (size_t k = 0; k < NF3 * n; ++k) w[k] += c->U[l][k];
+    or3_project(&c->G[l], p, c->U[l], w, c->U[l]);
+    free(e);
+    free(w);
+}
+
+static void visit3(const cyc3* c, const or_params* p, double dtau, int l, int kind)
+{
+    const size_t n = ncell3(&c->G[l]);
+    double* t = dalloc3(NF3 * n);
+    smooth3(&c->G[l], c->S[l], p, dtau, c->F[l], c->U[l], t);
+    memcpy(c->U[l], t, NF3 * n * sizeof(double));
+    if (l < c->L - 1) {
+        descend3(c, l, c->F[l]);
+        below_and_correct3(c, p, dtau, l, kind);
+        smooth3(&c->G[l], c->S[l], p, dtau, c->F[l], c->U[l], t);
+        memcpy(c->U[l], t, NF3 * n * sizeof(double));
+    }
+    free(t);
+}
+
+void or3_cycle(const or3_grid* g, const double* sigma, const or_params* p, int32_t kind, double dtau, const double* b,
+               const double* v, double* out)
+{
+    cyc3 c;
+    c.L = or3_num_levels(g, p);
+    c.G = (or3_grid*)malloc(sizeof(or3_grid) * c.L);
+    c.S = (double**)calloc(c.L, sizeof(double*));
+    c.U = (double**)calloc(c.L, sizeof(double*));
+    c.V = (double**)calloc(c.L, sizeof(double*));
+    c.F = (double**)calloc(c.L, sizeof(double*));
+    c.G[0] = *g;
+    c.S[0] = (double*)sigma;
+    for (int l = 1; l < c.L; ++l) {
+        c.G[l] = or3_coarse_grid(&c.G[l - 1]);
+        c.S[l] = dalloc3(2 * ncell3(&c.G[l]));
+        or3_restrict(&c.G[l - 1], c.S[l - 1], 2, c.S[l]);
+    }
+    for (int l = 0; l < c.L; ++l) {
+        c.U[l] = dalloc3(NF3 * ncell3(&c.G[l]));
+        c.V[l] = dalloc3(NF3 * ncell3(&c.G[l]));
+        c.F[l] = dalloc3(NF3 * ncell3(&c.G[l]));
+    }
+    sweeps3(&c.G[0], c.S[0], p->omega, b, v, p->nu0, c.U[0]);
+    if (c.L > 1) {
+        double* t = dalloc3(NF3 * ncell3(g));
+        descend3(&c, 0, b);
+        below_and_correct3(&c, p, dtau, 0, kind);
+        sweeps3(&c.G[0], c.S[0], p->omega, b, c.U[0], p->nu0, t);
+        memcpy(c.U[0], t, NF3 * ncell3(g) * sizeof(double));
+        free(t);
+    }
+    memcpy(out, c.U[0], NF3 * ncell3(g) * sizeof(double));
+    for (int l = 0; l < c.L; ++l) {
+        free(c.U[l]);
+        free(c.V[l]);
+        free(c.F[l]);
+        if (l > 0) free(c.S[l]);
+    }
+    free(c.G);
+    free(c.S);
+    free(c.U);
+    free(c.V);
+    free(c.F);
+}
+
+/* One cycle of the parameters' shape: the V-cycle's loop form below, W and F by or3_cycle. */
+static void vcycle3_loop(const or3_grid* g, const double* sigma, const or_params* p, double dtau, const double* b,
+                         const double* v, double* out);
+
 void or3_vcycle(const or3_grid* g, const double* sigma, const or_params* p, double dtau, const double* b,
+                const double* v, double* out)
+{
+    if (p->cycle == OR_CYCLE_V) vcycle3_loop(g, sigma, p, dtau, b, v, out);
+    else or3_cycle(g, sigma, p, p->cycle, dtau, b, v, out);
+}
+
+/* One V-cycle (Appendix A) with the FAS coarse problems of Sect. 4.2, as the 2-D oracle's loop form. */
+static void vcycle3_loop(const or3_grid* g, const double* sigma, const or_params* p, double dtau, const double* b,
                 const double* v, double* out)
 {
     const int L = or3_num_levels(g, p);

@@ -42,6 +42,8 @@ void    or3_prolong(const or3_grid* fine, const double* x_coarse, int32_t nfield
 int32_t or3_num_levels(const or3_grid* g, const or_params* p);
 void    or3_vcycle(const or3_grid* g, const double* sigma, const or_params* p, double dtau, const double* b,
                    const double* v, double* out);
+void    or3_cycle(const or3_grid* g, const double* sigma, const or_params* p, int32_t kind, double dtau,
+                  const double* b, const double* v, double* out);
 int32_t or3_step(const or3_grid* g, const double* sigma, const or_params* p, double* v, int32_t nsteps,
                  or_info* info);
 
