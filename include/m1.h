@@ -429,9 +429,10 @@ m1_status m1_serve_stop(m1_engine* e);
  * closure (Sect. 2.1), the implicit sources, the nonlinear Jacobi sweep
  * (Algorithm 1), pseudo-time steps (Algorithm 3), the admissible correction
  * (eq. prolongatedSol), trilinear prolongation with full weighting R, and the
- * V-cycle / time-step driver of Appendix A.  FP64 plans with the V-cycle, full
- * weighting, Jacobi smoothing and nu_l = 1 (other m1_params choices give
- * M1_ERR_ARG); sides PERIODIC, REFLECTIVE, NEUMANN or DIRICHLET. */
+ * V-cycle / time-step driver of Appendix A, with the W- and F-cycles of
+ * Sect. 6.3 as the 2-D plans run them.  FP64 plans with full weighting, Jacobi
+ * smoothing and nu_l = 1 (other m1_params choices give M1_ERR_ARG); sides
+ * PERIODIC, REFLECTIVE, NEUMANN or DIRICHLET. */
 
 /* Side condition of a 3-D grid (kinds as m1_bc; (E, Fx, Fy, Fz) for DIRICHLET). */
 typedef struct {
@@ -490,7 +491,8 @@ m1_status m1_prolong_project3(m1_plan3* plan, int32_t level, const m1_state3* u,
 /* r = b - A(v), b = (E^n, F^n, C_v T^n) of vn; the L2 norm of (r_E, r_F/c, r_T)
  * to *norm_out (host; blocks), the fields to r_out when not NULL.            */
 m1_status m1_residual3(m1_plan3* plan, const m1_state3* v, const m1_state3* vn, double* norm_out, m1_state3* r_out);
-/* One V-cycle (Appendix A) of A(v) = b(vn) with pseudo-time step dtau, in place on v (v must not alias vn). */
+/* One cycle of the plan's shape (params.cycle: Appendix A's V-cycle, or the W- or F-cycle of Sect. 6.3) of
+ * A(v) = b(vn) with pseudo-time step dtau, in place on v (v must not alias vn). */
 m1_status m1_vcycle3(m1_plan3* plan, m1_state3* v, const m1_state3* vn, double dtau);
 /* nsteps implicit Euler steps in place on v (Appendix A, Algorithm 4), as m1_step: cycles until the relative
  * residual rtol or A's rounding level, dtau carried from step to step (dtau_carry) and adapted after every cycle; M1_ERR_NOT_ADMISSIBLE

@@ -3,8 +3,9 @@
 //
 // The hierarchy halves every side per level (Sect. 4.2 with d = 3: R = 2^-3 P^T,
 // trilinear P), coarse opacities by full weighting, the FAS coarse problems
-// smoothed by pseudo-time steps (Algorithm 3), the V-cycle and the time-step
-// driver of Appendix A with the cycle control on the device (the same control
+// smoothed by pseudo-time steps (Algorithm 3), the V-cycle (and the W and F
+// shapes of Sect. 6.3 as a recursion) and the time-step driver of Appendix A
+// with the cycle control on the device (the same control
 // kernel as the 2-D plans).  Every level runs one-cell grid kernels
 // (m1_kernels3.hip); FP64 only.
 #include <algorithm>
@@ -94,7 +95,8 @@ bool valid_params3(const m1_params* p)
     if (p->levels < 0 || p->nu0 < 1 || p->nu_l != 1 || p->pseudo_steps < 1 || p->sub_steps < 1 || p->max_cycles < 1)
         return false;
     if (p->dtau_rule != M1_DTAU_SIGNED && p->dtau_rule != M1_DTAU_LITERAL) return false;
-    if (p->precision != M1_FP64 || p->smoother != M1_SMOOTH_JACOBI || p->cycle != M1_CYCLE_V ||
+    if (p->precision != M1_FP64 || p->smoother != M1_SMOOTH_JACOBI ||
+        (p->cycle != M1_CYCLE_V && p->cycle != M1_CYCLE_W && p->cycle != M1_CYCLE_F) ||
         p->transfer != M1_TRANSFER_FULL)
         return false;
     if (!(p->eta > 0.0 && p->eta < 1.0) || !(p->omega > 0.0 && p->omega <= 1.0) || !(p->rtol > 0.0)) return false;
@@ -293,6 +295,72 @@ void vcycle3(m1_plan3& P, m1::Soa3& cur, m1::Soa3& other, const Gate3& G)
             ul[l] = smooth3(P, l, G, ul[l]);
         }
     }
+}
+
+// W- and F-cycles (Sect. 6.3) as a recursion over the coarse FAS problems.  A visit of coarse level l takes
+// m pseudo-time steps from u_l; above the coarsest level it then forms rbar_l = f_l - A_l(u_l), restricts
+// (u_l, rbar_l) to v_{l+1} and f_{l+1} = A(v_{l+1}) + R(rbar_l), visits level l+1 once (V), twice (W) or by an
+// F-visit then a V-visit (F), corrects u_l by the projected prolongation of u_{l+1} - v_{l+1} and smooths
+// again.  The finest level takes nu0 sweeps each side.  One visit per level gives vcycle3's launches.
+struct Rec3 {
+    m1_plan3& P;
+    const Gate3& G;
+    m1::Soa3 ul[kMaxLevels3];
+};
+
+void descend3(Rec3& R, int l)
+{
+    m1_plan3& P = R.P;
+    Level3& f = P.lev[l];
+    Level3& c = P.lev[l + 1];
+    const m1::Soa3 rbar = l == 0 ? P.rfine : f.rb;
+    if (l == 0) apply3(P, 0, m1::cs3(R.ul[0]), m1::cs3(P.b), -1.0, rbar, R.G.active);
+    else apply3(P, l, m1::cs3(R.ul[l]), m1::cs3(f.f), -1.0, rbar, R.G.active);
+    m1::launch3_restrict(P.st, f.nx, f.ny, f.nz, P.px, P.py, P.pz, fields3(R.ul[l], rbar, c.v, c.rb), R.G.active);
+    apply3(P, l + 1, m1::cs3(c.v), m1::cs3(c.rb), 1.0, c.f, R.G.active);
+    R.ul[l + 1] = c.v;  // the first pseudo-time step reads v_{l+1} and writes an iterate buffer
+}
+
+void visit3(Rec3& R, int l, int kind);
+
+void below3(Rec3& R, int l, int kind)
+{
+    if (kind == M1_CYCLE_F) {
+        visit3(R, l + 1, M1_CYCLE_F);
+        visit3(R, l + 1, M1_CYCLE_V);
+    } else {
+        for (int t = 0; t < (kind == M1_CYCLE_W ? 2 : 1); ++t) visit3(R, l + 1, kind);
+    }
+    m1_plan3& P = R.P;
+    const Level3& f = P.lev[l];
+    const Level3& c = P.lev[l + 1];
+    m1::launch3_prolong_project(P.st, P.ph, f.nx, f.ny, f.nz, P.px, P.py, P.pz, P.params.eta, m1::cs3(R.ul[l]),
+                                m1::cs3(R.ul[l + 1]), m1::cs3(c.v), R.ul[l], R.G.active);
+}
+
+void visit3(Rec3& R, int l, int kind)
+{
+    R.ul[l] = smooth3(R.P, l, R.G, R.ul[l]);
+    if (l == R.P.L - 1) return;
+    descend3(R, l);
+    below3(R, l, kind);
+    R.ul[l] = smooth3(R.P, l, R.G, R.ul[l]);
+}
+
+// One cycle of the plan's shape on the finest iterate cur (partner buffer other).
+void cycle3(m1_plan3& P, m1::Soa3& cur, m1::Soa3& other, const Gate3& G)
+{
+    if (P.params.cycle == M1_CYCLE_V) {
+        vcycle3(P, cur, other, G);
+        return;
+    }
+    sweeps3(P, cur, other, P.params.nu0, G);
+    if (P.L == 1) return;
+    Rec3 R{P, G, {}};
+    R.ul[0] = cur;
+    descend3(R, 0);
+    below3(R, 0, P.params.cycle);
+    sweeps3(P, cur, other, P.params.nu0, G);
 }
 
 // |x + sgn A_0(v)| (x = b, sgn = -1: the residual; sgn = 0: |b|) to the host, r_out written when set.
@@ -496,7 +564,7 @@ m1_status m1_vcycle3(m1_plan3* P, m1_state3* v, const m1_state3* vn, double dtau
     if (!P || !valid_state3(v) || !valid_state3(vn) || !(dtau > 0.0) || v->E == vn->E) return M1_ERR_ARG;
     m1::launch3_make_rhs(P->st, P->lev[0].n, P->grid.c_v, m1::cs3(soa3(vn)), P->b);
     m1::Soa3 user = soa3(v), cur = user, other = P->tmp;
-    vcycle3(*P, cur, other, fixed_gate3(*P, dtau));
+    cycle3(*P, cur, other, fixed_gate3(*P, dtau));
     if (!same3(cur, user)) m1::launch3_copy(P->st, P->lev[0].n, m1::cs3(cur), user);
     return status_of(hipGetLastError());
 }
@@ -569,7 +637,7 @@ m1_status m1_step3(m1_plan3* P, m1_state3* v, int32_t nsteps, m1_info* info)
         for (;;) {
             const int todo = std::min(chunk, p.max_cycles - enqueued);
             for (int c = 0; c < todo; ++c) {
-                vcycle3(*P, cur, other, G);
+                cycle3(*P, cur, other, G);
                 if (enqueued + c == 0) flips = !same3(cur, user);
                 m1::launch3_apply(P->st, P->ph, P->lev[0].L, m1::cs3(cur), m1::cs3(P->b), -1.0, m1::Soa3{},
                                   P->partials, G.active);

@@ -144,10 +144,13 @@ def test_workspace3_size_and_host_validation():
     assert L.m1_workspace3_bytes(ctypes.byref(g), ctypes.byref(pl)) == nbytes
     pl = binding.make_params(binding.default_params(levels=6))
     assert L.m1_workspace3_bytes(ctypes.byref(g), ctypes.byref(pl)) == 0
-    for extra in (dict(precision="mixed"), dict(cycle="W"), dict(transfer="mean"), dict(nu_l=2),
+    for extra in (dict(precision="mixed"), dict(cycle=3), dict(transfer="mean"), dict(nu_l=2),
                   dict(smoother="rbgs"), dict(omega=1.5)):
         q = binding.make_params(binding.default_params(**extra))
         assert L.m1_workspace3_bytes(ctypes.byref(g), ctypes.byref(q)) == 0, extra
+    for kind in ("W", "F"):  # the cycle shapes use the V-cycle's buffers
+        q = binding.make_params(binding.default_params(cycle=kind))
+        assert L.m1_workspace3_bytes(ctypes.byref(g), ctypes.byref(q)) == nbytes
     bad = binding.make_grid3(prob)
     bad.bc[4].kind = 0  # periodic on one z side only
     assert L.m1_workspace3_bytes(ctypes.byref(bad), ctypes.byref(p)) == 0

@@ -146,7 +146,7 @@ def test_edge_cases():
     bad[0, 1, 1, 1] = -1.0
     with pytest.raises(binding.M1Error):
         binding.Plan3(prob, to_dev(bad), dict(omega=OMEGA))
-    for extra in (dict(precision="mixed"), dict(cycle="W"), dict(transfer="mean"), dict(nu_l=2),
+    for extra in (dict(precision="mixed"), dict(cycle=3), dict(transfer="mean"), dict(nu_l=2),
                   dict(smoother="rbgs")):
         with pytest.raises(binding.M1Error):
             binding.Plan3(prob, to_dev(sig), dict(omega=OMEGA, **extra))
