@@ -421,7 +421,7 @@ def sweep3_entry(torch, plan, prob, vd, reps):
                                    binding.ctypes.byref(plan._st(bufs[1 - k[0]]))), "m1_sweep3")
         k[0] ^= 1
     tk = time_launches(torch, plan.stream, launch, reps)
-    kname = "k3_staged<1>" if binding.tune_get("stage3") >= 1 else "k3_relax"
+    kname = "k3_staged<1>" if binding.tune_get("stage3") >= 1 else "k3_relax<false>"
     tag = "k3_staged1" if binding.tune_get("stage3") >= 1 else "k3_relax"
     return roofline_entry(kname, "finest-level FP64 Jacobi sweep, 3-D", SWEEP3_BYTES_PER_CELL * cells, tk,
                           read_traffic(tag, "hotwall3d256", kname, cells), "256x256x256", "HBM (2.3 GB working set)")

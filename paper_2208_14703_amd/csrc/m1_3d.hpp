@@ -40,9 +40,11 @@ inline CSoa3 cs3(const Soa3& s) { return CSoa3{s.E, s.Fx, s.Fy, s.Fz, s.T}; }
 // of r_E^2 + |r_F/c|^2 + r_T^2 of out goes to partials[block] (256-thread blocks).
 void launch3_apply(hipStream_t st, const Phys3& ph, const Lvl3& L, CSoa3 v, CSoa3 x, double sgn, Soa3 out,
                    double* partials, const int* active);
-// One relaxed Jacobi sweep of A(u) = b (Algorithm 1): out = u + omega (J(u) - u).
-void launch3_relax(hipStream_t st, const Phys3& ph, const Lvl3& L, CSoa3 b, double omega, CSoa3 in, Soa3 out,
-                   const int* active);
+// One relaxed Jacobi sweep of A(u) = b (Algorithm 1): out = u + omega (J(u) - u).  With partials, the
+// block sums of r_E^2 + |r_F/c|^2 + r_T^2 of the input's residual b - A(u) (per cell the value k3_apply
+// gives) go to partials[block]; returns the number of blocks (of partials written).
+unsigned launch3_relax(hipStream_t st, const Phys3& ph, const Lvl3& L, CSoa3 b, double omega, CSoa3 in, Soa3 out,
+                       const int* active, double* partials = nullptr);
 // One pseudo-time step (Algorithm 3) of M du/dtau + A_l(u) = f with one Jacobi
 // sweep; reach = 1 - (1 - eta)^K; dtau from dtau_dev when not null.
 void launch3_pseudo(hipStream_t st, const Phys3& ph, const Lvl3& L, CSoa3 f, CSoa3 in, Soa3 out, double dtau,
@@ -60,8 +62,8 @@ void set_stage3(int mode);
 int stage3();
 void launch3_apply_staged(hipStream_t st, const Phys3& ph, const Lvl3& L, CSoa3 v, CSoa3 x, double sgn, Soa3 out,
                           const int* active);
-void launch3_relax_staged(hipStream_t st, const Phys3& ph, const Lvl3& L, CSoa3 b, double omega, CSoa3 in,
-                          Soa3 out, const int* active);
+unsigned launch3_relax_staged(hipStream_t st, const Phys3& ph, const Lvl3& L, CSoa3 b, double omega, CSoa3 in,
+                              Soa3 out, const int* active, double* partials = nullptr);
 void launch3_pseudo_staged(hipStream_t st, const Phys3& ph, const Lvl3& L, CSoa3 f, CSoa3 in, Soa3 out,
                            double dtau, const double* dtau_dev, double reach, int local, const int* active);
 // Full weighting R = 2^-3 P^T of the fields in F from a fine nxf x nyf x nzf level.

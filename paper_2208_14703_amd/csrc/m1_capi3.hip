@@ -191,12 +191,15 @@ Gate3 fixed_gate3(m1_plan3& P, double dtau)
     return Gate3{dtau, &P.dfix->dtau, &P.dfix->active};
 }
 
-// The three stencil operations, staged where the level is wide enough (bitwise the one-cell forms).
-void relax3(m1_plan3& P, const m1::CSoa3& b, const m1::CSoa3& in, const m1::Soa3& out, const int* active)
+// The three stencil operations, staged where the level is wide enough (bitwise the one-cell forms).  The
+// sweep reduces its input's residual norm into `partials` when given and returns the number of partials.
+unsigned relax3(m1_plan3& P, const m1::CSoa3& b, const m1::CSoa3& in, const m1::Soa3& out, const int* active,
+                double* partials = nullptr)
 {
     const m1::Lvl3& L = P.lev[0].L;
-    if (m1::stage3_fits(L, true)) m1::launch3_relax_staged(P.st, P.ph, L, b, P.params.omega, in, out, active);
-    else m1::launch3_relax(P.st, P.ph, L, b, P.params.omega, in, out, active);
+    if (m1::stage3_fits(L, true))
+        return m1::launch3_relax_staged(P.st, P.ph, L, b, P.params.omega, in, out, active, partials);
+    return m1::launch3_relax(P.st, P.ph, L, b, P.params.omega, in, out, active, partials);
 }
 
 void apply3(m1_plan3& P, int l, const m1::CSoa3& v, const m1::CSoa3& x, double sgn, const m1::Soa3& out,
@@ -217,10 +220,14 @@ void pseudo3(m1_plan3& P, int l, const m1::CSoa3& f, const m1::CSoa3& in, const 
         m1::launch3_pseudo(P.st, P.ph, L, f, in, out, dtau, dtau_dev, P.reach, P.params.pseudo_local, active);
 }
 
-void sweeps3(m1_plan3& P, m1::Soa3& cur, m1::Soa3& other, int nu, const Gate3& G)
+// nu finest-level sweeps.  With `control` the first sweep also reduces the residual norm of its input (the
+// previous cycle's result) and the cycle control updates dtau / the stop flag before the rest of the cycle.
+void sweeps3(m1_plan3& P, m1::Soa3& cur, m1::Soa3& other, int nu, const Gate3& G, bool control = false)
 {
     for (int s = 0; s < nu; ++s) {
-        relax3(P, m1::cs3(P.b), m1::cs3(cur), other, G.active);
+        const bool norm = control && s == 0;
+        const unsigned np = relax3(P, m1::cs3(P.b), m1::cs3(cur), other, G.active, norm ? P.partials : nullptr);
+        if (norm) m1::launch_norm_control(P.st, P.partials, (int)np, P.dctrl);
         std::swap(cur, other);
     }
 }
@@ -262,11 +269,12 @@ m1::Fields fields3(const m1::Soa3& a, const m1::Soa3& b, const m1::Soa3& ca, con
 
 // One V-cycle (Appendix A) on the finest iterate cur (partner buffer other): nu0 sweeps; per coarse level
 // v_l = R(u_{l-1}), f_l = A_l(v_l) + R(rbar_{l-1}), m pseudo-time steps from v_l and rbar_l = f_l - A_l(u_l);
-// upward u_l <- projected(u_l + P(u_{l+1} - v_{l+1})) and the same smoothing again.
-void vcycle3(m1_plan3& P, m1::Soa3& cur, m1::Soa3& other, const Gate3& G)
+// upward u_l <- projected(u_l + P(u_{l+1} - v_{l+1})) and the same smoothing again.  `control`: the first
+// sweep feeds the previous result's residual norm to the cycle control (sweeps3).
+void vcycle3(m1_plan3& P, m1::Soa3& cur, m1::Soa3& other, const Gate3& G, bool control)
 {
     const m1_params& p = P.params;
-    sweeps3(P, cur, other, p.nu0, G);
+    sweeps3(P, cur, other, p.nu0, G, control);
     if (P.L == 1) return;
     m1::Soa3 ul[kMaxLevels3];
     ul[0] = cur;
@@ -347,14 +355,14 @@ void visit3(Rec3& R, int l, int kind)
     R.ul[l] = smooth3(R.P, l, R.G, R.ul[l]);
 }
 
-// One cycle of the plan's shape on the finest iterate cur (partner buffer other).
-void cycle3(m1_plan3& P, m1::Soa3& cur, m1::Soa3& other, const Gate3& G)
+// One cycle of the plan's shape on the finest iterate cur (partner buffer other); `control` as in sweeps3.
+void cycle3(m1_plan3& P, m1::Soa3& cur, m1::Soa3& other, const Gate3& G, bool control = false)
 {
     if (P.params.cycle == M1_CYCLE_V) {
-        vcycle3(P, cur, other, G);
+        vcycle3(P, cur, other, G, control);
         return;
     }
-    sweeps3(P, cur, other, P.params.nu0, G);
+    sweeps3(P, cur, other, P.params.nu0, G, control);
     if (P.L == 1) return;
     Rec3 R{P, G, {}};
     R.ul[0] = cur;
@@ -624,36 +632,36 @@ m1_status m1_step3(m1_plan3* P, m1_state3* v, int32_t nsteps, m1_info* info)
         init.dtau_min = p.dtau_min;
         init.dtau_max = p.dtau_max;
         init.active = 1;
-        init.cycles = 0;  // r0 is known: every control call follows a cycle
+        init.cycles = -1;  // the first control call measures r0 (no cycle done yet)
         init.max_cycles = p.max_cycles;
         init.literal = p.dtau_rule == M1_DTAU_LITERAL;
         m1::launch_ctrl_init(P->st, P->dctrl, init);
         const Gate3 G{dtau, &P->dctrl->dtau, &P->dctrl->active};
-        // whole cycles enqueued ahead of the host's check, each followed by the residual norm and the control
-        // update on the device; cycles after the stop exit at once
+        // whole cycles enqueued ahead of the host's check; each cycle's first sweep measures the residual of the
+        // previous result and the control updates dtau / the stop flag on the device, so one more (partial)
+        // cycle than needed is enqueued; kernels of cycles after the stop store nothing
         m1::Soa3 cur = user, other = P->tmp;
         bool flips = false;
         int enqueued = 0, chunk = 2;
         for (;;) {
-            const int todo = std::min(chunk, p.max_cycles - enqueued);
+            const int todo = std::min(chunk, p.max_cycles + 1 - enqueued);
             for (int c = 0; c < todo; ++c) {
-                cycle3(*P, cur, other, G);
+                cycle3(*P, cur, other, G, true);
                 if (enqueued + c == 0) flips = !same3(cur, user);
-                m1::launch3_apply(P->st, P->ph, P->lev[0].L, m1::cs3(cur), m1::cs3(P->b), -1.0, m1::Soa3{},
-                                  P->partials, G.active);
-                m1::launch_norm_control(P->st, P->partials, P->npart, P->dctrl);
             }
             enqueued += todo;
             if (hipMemcpyAsync(hctrl, P->dctrl, sizeof(m1::Ctrl), hipMemcpyDeviceToHost, P->st) != hipSuccess ||
                 hipStreamSynchronize(P->st) != hipSuccess || hipGetLastError() != hipSuccess)
                 return M1_ERR_DEVICE;
-            if (!hctrl->active || enqueued >= p.max_cycles) break;
+            if (!hctrl->active || enqueued >= p.max_cycles + 1) break;
             chunk = std::min(16, 2 * chunk);
         }
         const m1::Ctrl h = *hctrl;
         total += h.cycles;
         rel = h.rel;
         dtau = h.dtau;
+        // the result is the iterate after h.cycles full cycles (the last cycle enqueued only measured it), in
+        // `user` unless a cycle moves it to the other buffer and h.cycles is odd
         const m1::Soa3 res = (flips && h.cycles % 2 == 1) ? P->tmp : user;
         if (!same3(res, user)) m1::launch3_copy(P->st, n0, m1::cs3(res), user);
         if (!h.conv) status = M1_ERR_NO_CONVERGENCE;

@@ -259,18 +259,24 @@ __global__ __launch_bounds__(kB3) void k3_apply(Phys3 ph, Lvl3 L, CSoa3 v, CSoa3
     if (partials) block_partial(q, partials + blockIdx.x);
 }
 
+// NORM: also the norm partials of the input's residual b - A(u) (per cell fin_apply's value, as k3_apply).
+template <bool NORM>
 __global__ __launch_bounds__(kB3) void k3_relax(Phys3 ph, Lvl3 L, CSoa3 b, double omega, CSoa3 u, Soa3 out,
-                                                const int* __restrict__ active)
+                                                double* __restrict__ partials, const int* __restrict__ active)
 {
     const bool live = active[vzero3()] != 0;
     uint32_t k;
     int i, j, l;
-    if (!cell3(L, k, i, j, l)) return;
-    double S[4], uc[5], o[5];
-    offdiag3(ph, L, u, i, j, l, k, S);
-    load5(u, k, uc);
-    fin_relax(ph, L, uc, S, b, omega, k, o);
-    if (live) st5(out, k, o);
+    double q = 0.0;
+    if (cell3(L, k, i, j, l)) {
+        double S[4], uc[5], o[5];
+        offdiag3(ph, L, u, i, j, l, k, S);
+        load5(u, k, uc);
+        if (NORM) q = fin_apply(ph, L, uc, S, b, -1.0, k, o);
+        fin_relax(ph, L, uc, S, b, omega, k, o);
+        if (live) st5(out, k, o);
+    }
+    if (NORM) block_partial(q, partials + blockIdx.x);
 }
 
 __global__ __launch_bounds__(kB3) void k3_pseudo(Phys3 ph, Lvl3 L, CSoa3 f, CSoa3 u, Soa3 out, double dtau_h,
@@ -354,6 +360,7 @@ __device__ __forceinline__ Rec3 column_rec(const Phys3& ph, const Lvl3& L, const
 
 struct StageArgs3 {
     CSoa3 rhs;      // apply: x (nullable); relax: b; pseudo: f
+    double* partials;  // relax with the norm: per block
     double omega;   // relax
     double sgn;     // apply
     Soa3 out;
@@ -363,7 +370,9 @@ struct StageArgs3 {
     int local;
 };
 
-template <int MODE>  // 0: out = x + sgn A(u); 1: relaxed Jacobi sweep; 2: pseudo-time step
+// MODE 0: out = x + sgn A(u); 1: relaxed Jacobi sweep; 2: pseudo-time step; 3: the sweep with the norm
+// partials of its input's residual b - A(u) (per cell fin_apply's value, as k3_apply)
+template <int MODE>
 __global__ __launch_bounds__(kB3) void k3_staged(Phys3 ph, Lvl3 L, CSoa3 u, StageArgs3 A,
                                                  const int* __restrict__ active)
 {
@@ -413,6 +422,7 @@ __global__ __launch_bounds__(kB3) void k3_staged(Phys3 ph, Lvl3 L, CSoa3 u, Stag
         cur = column_rec(ph, L, u, i, j, z0);
     }
     const int slot = (ty + 1) * kSW + tx + 1;
+    double q = 0.0;
     for (int z = z0; z < z1; ++z) {
         if (own) next = column_rec(ph, L, u, i, j, z + 1);
         __syncthreads();  // the previous plane's reads are done
@@ -430,8 +440,9 @@ __global__ __launch_bounds__(kB3) void k3_staged(Phys3 ph, Lvl3 L, CSoa3 u, Stag
             const uint32_t k = ((uint32_t)z * (uint32_t)L.ny + (uint32_t)j) * (uint32_t)L.nx + (uint32_t)i;
             double uc[5] = {cur.E, cur.F[0], cur.F[1], cur.F[2], ld(u.T, k)}, o[5];
             bool stall = false;
+            if (MODE == 3) q += fin_apply(ph, L, uc, S, A.rhs, -1.0, k, o);
             if (MODE == 0) (void)fin_apply(ph, L, uc, S, A.rhs, A.sgn, k, o);
-            else if (MODE == 1) fin_relax(ph, L, uc, S, A.rhs, A.omega, k, o);
+            else if (MODE == 1 || MODE == 3) fin_relax(ph, L, uc, S, A.rhs, A.omega, k, o);
             else fin_pseudo(ph, L, uc, S, A.rhs, dtau, A.reach, A.local, k, o, stall);
             if (live && stall && ph.stalls) note_stall(ph.stalls);
             if (live && A.out.E) st5(A.out, k, o);
@@ -439,6 +450,7 @@ __global__ __launch_bounds__(kB3) void k3_staged(Phys3 ph, Lvl3 L, CSoa3 u, Stag
         prev = cur;
         cur = next;
     }
+    if (MODE == 3) block_partial(q, A.partials + blockIdx.x);  // every thread of the block gets here
 }
 
 namespace {
@@ -616,11 +628,16 @@ void launch3_apply(hipStream_t st, const Phys3& ph, const Lvl3& L, CSoa3 v, CSoa
     hipLaunchKernelGGL(k3_apply, dim3(blocks3(n)), dim3(kB3), 0, st, ph, L, v, x, sgn, out, partials, active);
 }
 
-void launch3_relax(hipStream_t st, const Phys3& ph, const Lvl3& L, CSoa3 b, double omega, CSoa3 in, Soa3 out,
-                   const int* active)
+unsigned launch3_relax(hipStream_t st, const Phys3& ph, const Lvl3& L, CSoa3 b, double omega, CSoa3 in, Soa3 out,
+                       const int* active, double* partials)
 {
     const int64_t n = (int64_t)L.nx * L.ny * L.nz;
-    hipLaunchKernelGGL(k3_relax, dim3(blocks3(n)), dim3(kB3), 0, st, ph, L, b, omega, in, out, active);
+    const unsigned g = blocks3(n);
+    if (partials)
+        hipLaunchKernelGGL(k3_relax<true>, dim3(g), dim3(kB3), 0, st, ph, L, b, omega, in, out, partials, active);
+    else
+        hipLaunchKernelGGL(k3_relax<false>, dim3(g), dim3(kB3), 0, st, ph, L, b, omega, in, out, nullptr, active);
+    return g;
 }
 
 void launch3_pseudo(hipStream_t st, const Phys3& ph, const Lvl3& L, CSoa3 f, CSoa3 in, Soa3 out, double dtau,
@@ -659,14 +676,18 @@ void launch3_apply_staged(hipStream_t st, const Phys3& ph, const Lvl3& L, CSoa3 
     hipLaunchKernelGGL(k3_staged<0>, dim3(staged_blocks(L)), dim3(kB3), 0, st, ph, L, v, A, active);
 }
 
-void launch3_relax_staged(hipStream_t st, const Phys3& ph, const Lvl3& L, CSoa3 b, double omega, CSoa3 in,
-                          Soa3 out, const int* active)
+unsigned launch3_relax_staged(hipStream_t st, const Phys3& ph, const Lvl3& L, CSoa3 b, double omega, CSoa3 in,
+                              Soa3 out, const int* active, double* partials)
 {
     StageArgs3 A{};
     A.rhs = b;
     A.omega = omega;
     A.out = out;
-    hipLaunchKernelGGL(k3_staged<1>, dim3(staged_blocks(L)), dim3(kB3), 0, st, ph, L, in, A, active);
+    A.partials = partials;
+    const unsigned g = staged_blocks(L);
+    if (partials) hipLaunchKernelGGL(k3_staged<3>, dim3(g), dim3(kB3), 0, st, ph, L, in, A, active);
+    else hipLaunchKernelGGL(k3_staged<1>, dim3(g), dim3(kB3), 0, st, ph, L, in, A, active);
+    return g;
 }
 
 void launch3_pseudo_staged(hipStream_t st, const Phys3& ph, const Lvl3& L, CSoa3 f, CSoa3 in, Soa3 out,

@@ -11,7 +11,10 @@ recursion over the coarse FAS problems:
   pseudo-time steps (the oracle's pin, here on the device's own launches);
 * converged time steps (both sides at 1e-13: 1e-10, cycle counts within one per
   step) of the 32^3 hot wall, both shapes;
-* a plan of one level runs the shapes as its sweeps.
+* a plan of one level runs the shapes as its sweeps;
+* at the cycle cap the state is the oracle's after that many cycles (the last
+  cycle enqueued only measures the residual of the one before), with the
+  iterate in either buffer.
 """
 import numpy as np
 import pytest
@@ -120,3 +123,23 @@ def test_one_level_plan():
         info = P.step(vd, 2)
         assert info["status"] == io["status"] == 0
         assert rel3(to_host(vd), ref, prob["c"]) <= 1e-12
+
+
+@pytest.mark.parametrize("levels,nu0", [(0, 3), (1, 3), (1, 2)])
+def test_cycle_cap_returns_the_last_full_cycle(levels, nu0):
+    """Each cycle's first sweep measures the previous result's residual, so the last cycle enqueued only
+    measures: at the cycle cap the state is the one after max_cycles full cycles, wherever the sweeps left
+    it (one level with an odd nu0 moves it to the partner buffer every cycle)."""
+    announce("3-D cycle cap", levels, nu0)
+    prob, v, sig = problem("mixed32x24x16", seed=9)
+    o = oracle.Oracle3(prob, sig)
+    for kind in "VW":
+        for cap in (1, 4, 5):
+            params = dict(omega=OMEGA, rtol=1e-30, max_cycles=cap, cycle=kind, levels=levels, nu0=nu0)
+            ref, io = o.step(v, 1, oracle.make_params(**params))
+            P = binding.Plan3(prob, to_dev(sig), params)
+            vd = to_dev(v)
+            info = P.step(vd, 1)
+            assert info["status"] == io["status"] == 3 and info["cycles"] == io["cycles"] == cap, (info, io)
+            err = rel3(to_host(vd), ref, prob["c"])
+            assert err <= 1e-11, (kind, cap, err)
