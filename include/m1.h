@@ -334,7 +334,17 @@ m1_status m1_stalls(m1_plan* plan, int64_t* count, int32_t reset);
  *                      the same for a round); 0: launches are enqueued one by
  *                      one (default 0; read when a plan or engine is created);
  *   "batch_grid"       most blocks of one batched launch (default 16384; read
- *                      at each launch, and when a V-cycle is recorded).
+ *                      at each launch, and when a V-cycle is recorded);
+ *   "stage3"           3-D plans: 0 one-cell stencil kernels only; 1 the
+ *                      finest-level sweeps of levels of at least 2^23 cells
+ *                      staged in LDS per z-plane; 2 every stencil operation
+ *                      staged where the level is at least 32 cells wide
+ *                      (default 1; the same bits in every case; read at each
+ *                      launch);
+ *   "prolong3_lds"     3-D plans: 1 the correction of eq. prolongatedSol
+ *                      with the coarse differences of a tile staged in LDS, 0
+ *                      one fine cell per thread reading its coarse cells
+ *                      (default 1; the same bits; read at each launch).
  * m1_tune_set: M1_ERR_ARG for an unknown key or a value out of range.
  * m1_tune_get: the current value, -1 for an unknown key.  The autotuner
  * (paper_2208_14703_amd/autotune.py) times candidates and stores its choice. */

@@ -69,7 +69,11 @@ void launch3_pseudo_staged(hipStream_t st, const Phys3& ph, const Lvl3& L, CSoa3
 // Full weighting R = 2^-3 P^T of the fields in F from a fine nxf x nyf x nzf level.
 void launch3_restrict(hipStream_t st, int nxf, int nyf, int nzf, int px, int py, int pz, const Fields& F,
                       const int* active);
-// out = u + P(uc - vc) (trilinear) with the admissibility correction (eq. prolongatedSol).
+// out = u + P(uc - vc) (trilinear) with the admissibility correction (eq. prolongatedSol).  Launch shape
+// "prolong3_lds": 1 (default) the coarse differences of a 32 x 4 x 2 coarse tile staged in LDS once, 0 one
+// fine cell per thread reading its coarse cells; the same bits either way.
+void set_prolong3_lds(int on);
+int prolong3_lds();
 void launch3_prolong_project(hipStream_t st, const Phys3& ph, int nx, int ny, int nz, int px, int py, int pz,
                              double eta, CSoa3 u, CSoa3 uc, CSoa3 vc, Soa3 out, const int* active);
 // b = (E, F, C_v T) of v.

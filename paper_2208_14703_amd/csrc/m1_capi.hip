@@ -1571,6 +1571,7 @@ m1_status m1_tune_set(const char* key, int64_t value)
     else if (k == "residual_restrict" && value <= 1) m1::set_residual_restrict((int)value);
     else if (k == "batch_grid" && value >= 1 && value <= (int64_t(1) << 24)) m1::set_batch_grid_cap((int)value);
     else if (k == "stage3" && value <= 2) m1::set_stage3((int)value);
+    else if (k == "prolong3_lds" && value <= 1) m1::set_prolong3_lds((int)value);
     else return M1_ERR_ARG;
     return M1_OK;
 }
@@ -1588,6 +1589,7 @@ int64_t m1_tune_get(const char* key)
     if (k == "residual_restrict") return m1::residual_restrict();
     if (k == "batch_grid") return m1::batch_grid_cap();
     if (k == "stage3") return m1::stage3();
+    if (k == "prolong3_lds") return m1::prolong3_lds();
     return -1;
 }
 

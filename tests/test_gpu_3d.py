@@ -9,6 +9,9 @@
   1e-13: 1e-10, cycle counts within one).
 * Edge cases: one cell, zero steps, a non-admissible input cell (its index is
   reported), a negative opacity, parameter choices the 3-D plans do not take.
+* The staged launch shapes give the one-cell kernels' bits: the apply, sweep and
+  pseudo-time step staged per z-plane, and the correction with its coarse
+  differences staged per tile (also whole steps, with equal cycle counts).
 """
 import numpy as np
 import pytest
@@ -186,3 +189,42 @@ def test_staged_operations_equal_the_one_cell_forms(shape):
         np.testing.assert_array_equal(a, c)
     assert res[2][4] == res[0][4]
     assert rel3(res[2][1], o.sweep(b, u, OMEGA), prob["c"]) <= 1e-13
+
+
+PROLONG_SHAPES = [(100, 12, 10, ALLKINDS), (72, 18, 14, ("periodic",) * 6), (8, 8, 8, MIXED),
+                  (66, 10, 8, ("periodic", "periodic", "neumann", "dirichlet", "periodic", "periodic"))]
+
+
+@pytest.mark.parametrize("shape", range(len(PROLONG_SHAPES)))
+def test_staged_prolongation_equals_the_one_cell_form(shape):
+    """The correction with the coarse differences of a tile staged in LDS gives the one-thread-per-fine-cell
+    kernel's bits on coarse tiles cut by the grid's end in every axis, periodic and other sides; whole steps
+    give the same bits and cycle counts."""
+    nx, ny, nz, bcs = PROLONG_SHAPES[shape]
+    announce("3-D staged prolongation", nx, ny, nz)
+    prob, v, sig = inputs.random_problem3(60 + shape, nx, ny, nz, bc_kinds=bcs, cfl=30.0, log10_sa=(-3, 2),
+                                          wall_E=5.0)
+    rng = np.random.default_rng(70 + shape)
+    u = inputs.random_state3(rng, nz, ny, nx, c=prob["c"], fmax=0.9)
+    u[4] = rng.uniform(0.5, 1.5, size=u[4].shape)
+    o = oracle.Oracle3(prob, sig)
+    u1 = o.restrict(u)
+    uc = u1 * (1.0 + 0.6 * rng.normal(size=u1.shape))  # large coarse changes: the projection acts somewhere
+    old = binding.tune_get("prolong3_lds")
+    res = {}
+    try:
+        for lds in (1, 0):
+            binding.tune_set("prolong3_lds", lds)
+            P = binding.Plan3(prob, to_dev(sig), dict(omega=OMEGA, rtol=1e-12, max_cycles=5000))
+            assert P.levels >= 2
+            vd = to_dev(v)
+            info = P.step(vd, 1)
+            res[lds] = (to_host(P.prolong_project(0, to_dev(u), to_dev(uc), to_dev(u1))), to_host(vd), info["cycles"])
+    finally:
+        binding.tune_set("prolong3_lds", old)
+    np.testing.assert_array_equal(res[1][0], res[0][0])
+    np.testing.assert_array_equal(res[1][1], res[0][1])
+    assert res[1][2] == res[0][2]
+    ref = o.project(u, u + o.prolong(uc - u1), oracle.make_params())
+    assert rel3(res[1][0], ref, prob["c"]) <= 1e-13
+    assert not np.array_equal(ref, u + o.prolong(uc - u1))
