@@ -29,7 +29,8 @@ import re
 import sys
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-KERNEL_SOURCES = ["m1_kernels.hip", "m1_cells.hpp", "m1_device.hpp", "m1_internal.hpp", "m1_kernels3.hip", "m1_3d.hpp"]
+KERNEL_SOURCES = ["m1_kernels.hip", "m1_cells.hpp", "m1_device.hpp", "m1_internal.hpp", "m1_mixed.hip", "m1_transfer.hip",
+                  "m1_mixed.hpp", "m1_transfer.hpp", "m1_kernels3.hip", "m1_3d.hpp"]
 
 
 def code_only(text: str) -> str:
