@@ -58,6 +58,9 @@ void launch3_pseudo(hipStream_t st, const Phys3& ph, const Lvl3& L, CSoa3 f, CSo
 constexpr int kStage3MinNx = 32;
 constexpr int64_t kStage3MinCells = int64_t(1) << 23;
 bool stage3_fits(const Lvl3& L, bool sweep);
+// Blocks of one staged launch on an nx x ny x nz level (each writes one norm partial when it reduces one): on
+// thin levels more than the one-cell kernels' ceil(n / 256).
+int64_t staged3_blocks(int nx, int ny, int nz);
 void set_stage3(int mode);
 int stage3();
 void launch3_apply_staged(hipStream_t st, const Phys3& ph, const Lvl3& L, CSoa3 v, CSoa3 x, double sgn, Soa3 out,

@@ -150,7 +150,8 @@ size_t carve3(m1_plan3* P, char* base, int L, const int nx[], const int ny[], co
             lv.L.ss = ss;
         }
     }
-    const int npart = (int)((n0 + 255) / 256);
+    // one norm partial per block of the one-cell kernels (256 cells) or of a staged sweep, whichever is more
+    const int npart = (int)std::max<int64_t>((n0 + 255) / 256, m1::staged3_blocks(nx[0], ny[0], nz[0]));
     double* partials = c.take(npart);
     double* dscal = c.take(8);
     double* dbad = c.take(1);

@@ -733,11 +733,13 @@ namespace {
 std::atomic<int> g_stage3{1};
 std::atomic<int> g_prolong_lds{1};
 
-unsigned staged_blocks(const Lvl3& L)
-{
-    return (unsigned)(((L.nx + kSX - 1) / kSX) * ((L.ny + kSY - 1) / kSY) * ((L.nz + kSZ - 1) / kSZ));
-}
+unsigned staged_blocks(const Lvl3& L) { return (unsigned)staged3_blocks(L.nx, L.ny, L.nz); }
 }  // namespace
+
+int64_t staged3_blocks(int nx, int ny, int nz)
+{
+    return (int64_t)((nx + kSX - 1) / kSX) * ((ny + kSY - 1) / kSY) * ((nz + kSZ - 1) / kSZ);
+}
 
 void set_stage3(int mode) { g_stage3 = mode < 0 ? 0 : (mode > 2 ? 2 : mode); }
 int stage3() { return g_stage3.load(); }

@@ -228,3 +228,32 @@ def test_staged_prolongation_equals_the_one_cell_form(shape):
     ref = o.project(u, u + o.prolong(uc - u1), oracle.make_params())
     assert rel3(res[1][0], ref, prob["c"]) <= 1e-13
     assert not np.array_equal(ref, u + o.prolong(uc - u1))
+
+
+@pytest.mark.parametrize("shape", [(1024, 1, 1), (2048, 2, 1), (512, 1, 17)])
+def test_staged_sweeps_on_thin_grids(shape):
+    """Staged sweeps on levels one or two cells thick launch more blocks than the one-cell kernels' 256-cell
+    blocks; the first sweep of each cycle writes one norm partial per block, so the plan holds as many.  Whole
+    steps against the oracle with every stencil operation staged."""
+    nx, ny, nz = shape
+    announce("3-D staged thin grid", nx, ny, nz)
+    prob, v, sig = inputs.random_problem3(80 + nx + ny + nz, nx, ny, nz, bc_kinds=MIXED, cfl=20.0, log10_sa=(-3, 2),
+                                          wall_E=5.0)
+    params = dict(omega=OMEGA, rtol=1e-12, max_cycles=20000)
+    ref, io = oracle.Oracle3(prob, sig).step(v, 2, oracle.make_params(**params))
+    assert io["status"] == 0
+    old = binding.tune_get("stage3")
+    try:
+        got = {}
+        for staged in (2, 0):
+            binding.tune_set("stage3", staged)
+            P = binding.Plan3(prob, to_dev(sig), params)
+            vd = to_dev(v)
+            info = P.step(vd, 2)
+            assert info["status"] == 0, info
+            assert abs(info["cycles"] - io["cycles"]) <= 2, (staged, info["cycles"], io["cycles"])
+            got[staged] = to_host(vd)
+            assert rel3(got[staged], ref, prob["c"]) <= 1e-10, staged
+    finally:
+        binding.tune_set("stage3", old)
+    assert rel3(got[2], got[0], prob["c"]) <= 1e-12
