@@ -643,7 +643,8 @@ m1_status m1_step3(m1_plan3* P, m1_state3* v, int32_t nsteps, m1_info* info)
         // cycle than needed is enqueued; kernels of cycles after the stop store nothing
         m1::Soa3 cur = user, other = P->tmp;
         bool flips = false;
-        int enqueued = 0, chunk = 2;
+        int enqueued = 0, chunk = 2, prev_cycles = 0;
+        double prev_rel = 1.0;
         for (;;) {
             const int todo = std::min(chunk, p.max_cycles + 1 - enqueued);
             for (int c = 0; c < todo; ++c) {
@@ -655,7 +656,16 @@ m1_status m1_step3(m1_plan3* P, m1_state3* v, int32_t nsteps, m1_info* info)
                 hipStreamSynchronize(P->st) != hipSuccess || hipGetLastError() != hipSuccess)
                 return M1_ERR_DEVICE;
             if (!hctrl->active || enqueued >= p.max_cycles + 1) break;
-            chunk = std::min(16, 2 * chunk);
+            // cycles still needed at the recent convergence rate (at least 1, at most 16 per chunk)
+            const int dc = hctrl->cycles - prev_cycles;
+            double need = 4.0;
+            if (dc > 0 && hctrl->rel > 0.0 && hctrl->rel < prev_rel) {
+                const double rate = std::pow(hctrl->rel / prev_rel, 1.0 / dc);
+                need = std::log(p.rtol / hctrl->rel) / std::log(rate);
+            }
+            chunk = (int)std::min(16.0, std::max(1.0, std::ceil(need)));
+            prev_rel = hctrl->rel;
+            prev_cycles = hctrl->cycles;
         }
         const m1::Ctrl h = *hctrl;
         total += h.cycles;

@@ -246,6 +246,7 @@ __global__ __launch_bounds__(kB3) void k3_apply(Phys3 ph, Lvl3 L, CSoa3 v, CSoa3
                                                 double* __restrict__ partials, const int* __restrict__ active)
 {
     const bool live = active[vzero3()] != 0;
+    if (!live) return;  // a cycle enqueued after the stop: nothing to compute (the flag is uniform)
     uint32_t k;
     int i, j, l;
     double q = 0.0;
@@ -265,6 +266,7 @@ __global__ __launch_bounds__(kB3) void k3_relax(Phys3 ph, Lvl3 L, CSoa3 b, doubl
                                                 double* __restrict__ partials, const int* __restrict__ active)
 {
     const bool live = active[vzero3()] != 0;
+    if (!live) return;  // a cycle enqueued after the stop: nothing to compute (the flag is uniform)
     uint32_t k;
     int i, j, l;
     double q = 0.0;
@@ -284,6 +286,7 @@ __global__ __launch_bounds__(kB3) void k3_pseudo(Phys3 ph, Lvl3 L, CSoa3 f, CSoa
                                                  const int* __restrict__ active)
 {
     const bool live = active[vzero3()] != 0;
+    if (!live) return;  // a cycle enqueued after the stop: nothing to compute (the flag is uniform)
     const double dtau = dtau_dev ? dtau_dev[vzero3()] : dtau_h;
     uint32_t k;
     int i, j, l;
@@ -378,6 +381,7 @@ __global__ __launch_bounds__(kB3) void k3_staged(Phys3 ph, Lvl3 L, CSoa3 u, Stag
 {
     __shared__ double sE[kSN], sF0[kSN], sF1[kSN], sF2[kSN], sI[kSN], sR[kSN];
     const bool live = active[vzero3()] != 0;
+    if (!live) return;  // a cycle enqueued after the stop: nothing to compute (the flag is uniform)
     const double dtau = (MODE == 2 && A.dtau_dev) ? A.dtau_dev[vzero3()] : A.dtau;
     const int ntx = (L.nx + kSX - 1) / kSX, nty = (L.ny + kSY - 1) / kSY;
     const int b = (int)xcd_block();
@@ -508,6 +512,7 @@ __global__ __launch_bounds__(kB3) void k3_restrict(int nxf, int nyf, int nzf, in
                                                    const int* __restrict__ active)
 {
     const bool live = active[vzero3()] != 0;
+    if (!live) return;  // a cycle enqueued after the stop: nothing to compute (the flag is uniform)
     const int nxc = nxf / 2, nyc = nyf / 2, nzc = nzf / 2;
     const uint32_t nxy = (uint32_t)nxc * (uint32_t)nyc;
     const uint32_t k = (uint32_t)xcd_block() * kB3 + threadIdx.x;
@@ -567,6 +572,7 @@ __global__ __launch_bounds__(kB3) void k3_prolong_project(Phys3 ph, int nx, int 
                                                           const int* __restrict__ active)
 {
     const bool live = active[vzero3()] != 0;
+    if (!live) return;  // a cycle enqueued after the stop: nothing to compute (the flag is uniform)
     const uint32_t nxy = (uint32_t)nx * (uint32_t)ny;
     const uint32_t k = (uint32_t)xcd_block() * kB3 + threadIdx.x;
     if (k >= nxy * (uint32_t)nz) return;
@@ -610,6 +616,7 @@ __global__ __launch_bounds__(kB3) void k3_prolong_project_lds(Phys3 ph, int nx, 
 {
     __shared__ double dq[5][kPN];
     const bool live = active[vzero3()] != 0;
+    if (!live) return;  // a cycle enqueued after the stop: nothing to compute (the flag is uniform)
     const int nxc = nx / 2, nyc = ny / 2, nzc = nz / 2;
     const int tbx = (nxc + kPX - 1) / kPX, tby = (nyc + kPY - 1) / kPY;
     const int blk = (int)xcd_block();
