@@ -6,8 +6,9 @@
 // smoothed by pseudo-time steps (Algorithm 3), the V-cycle (and the W and F
 // shapes of Sect. 6.3 as a recursion) and the time-step driver of Appendix A
 // with the cycle control on the device (the same control
-// kernel as the 2-D plans).  Every level runs one-cell grid kernels
-// (m1_kernels3.hip); FP64 only.
+// kernel as the 2-D plans).  Every level runs the grid kernels of
+// m1_kernels3.hip (one cell per thread, or staged in LDS where that pays);
+// FP64 only.
 #include <algorithm>
 #include <cfloat>
 #include <climits>
