@@ -11,7 +11,9 @@
   reported), a negative opacity, parameter choices the 3-D plans do not take.
 * The staged launch shapes give the one-cell kernels' bits: the apply, sweep and
   pseudo-time step staged per z-plane, and the correction with its coarse
-  differences staged per tile (also whole steps, with equal cycle counts).
+  differences staged per tile (also whole steps, with equal cycle counts);
+  every operation staged on grids one or two cells thick, whose staged
+  sweeps launch more blocks (and norm partials) than 256-cell blocks would.
 """
 import numpy as np
 import pytest
