@@ -336,7 +336,7 @@ m1_status m1_stalls(m1_plan* plan, int64_t* count, int32_t reset);
  *   "batch_grid"       most blocks of one batched launch (default 16384; read
  *                      at each launch, and when a V-cycle is recorded);
  *   "stage3"           3-D plans: 0 one-cell stencil kernels only; 1 the
- *                      finest-level sweeps of levels of at least 2^23 cells
+ *                      sweeps and A(u) of levels of at least 2^23 cells
  *                      staged in LDS per z-plane; 2 every stencil operation
  *                      staged where the level is at least 32 cells wide
  *                      (default 1; the same bits in every case; read at each

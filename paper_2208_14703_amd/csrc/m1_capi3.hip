@@ -193,8 +193,9 @@ Gate3 fixed_gate3(m1_plan3& P, double dtau)
     return Gate3{dtau, &P.dfix->dtau, &P.dfix->active};
 }
 
-// The three stencil operations, staged where the level is wide enough (bitwise the one-cell forms).  The
-// sweep reduces its input's residual norm into `partials` when given and returns the number of partials.
+// The three stencil operations, staged where the level is wide enough (bitwise the one-cell forms; by
+// default the sweeps and A on the large levels, the pseudo-time steps never).  The sweep reduces its input's
+// residual norm into `partials` when given and returns the number of partials.
 unsigned relax3(m1_plan3& P, const m1::CSoa3& b, const m1::CSoa3& in, const m1::Soa3& out, const int* active,
                 double* partials = nullptr)
 {
@@ -208,7 +209,7 @@ void apply3(m1_plan3& P, int l, const m1::CSoa3& v, const m1::CSoa3& x, double s
             const int* active)
 {
     const m1::Lvl3& L = P.lev[l].L;
-    if (m1::stage3_fits(L, false)) m1::launch3_apply_staged(P.st, P.ph, L, v, x, sgn, out, active);
+    if (m1::stage3_fits(L, true)) m1::launch3_apply_staged(P.st, P.ph, L, v, x, sgn, out, active);
     else m1::launch3_apply(P.st, P.ph, L, v, x, sgn, out, nullptr, active);
 }
 
