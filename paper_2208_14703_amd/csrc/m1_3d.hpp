@@ -52,7 +52,7 @@ void launch3_pseudo(hipStream_t st, const Phys3& ph, const Lvl3& L, CSoa3 f, CSo
 // The same three operations staged (2.5-D blocking: closures of a 64 x 4 tile and its ring once per z-plane
 // in LDS), bitwise equal to the one-cell forms above; the apply form without the norm partials.  Launch
 // shape "stage3": 0 one-cell kernels only; 1 (default) staged sweeps and A (stage3_fits with sweep = true) on
-// levels of at least kStage3MinCells cells (on smaller ones too few blocks, each marching through 16 planes in
+// levels of at least kStage3MinCells cells (on smaller ones too few blocks, each marching through 8 planes in
 // sequence); 2 every staged form on every level.  Levels narrower than kStage3MinNx keep the one-cell kernels (most of a 64-wide
 // tile would idle).
 constexpr int kStage3MinNx = 32;

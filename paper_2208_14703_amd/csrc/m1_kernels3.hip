@@ -310,7 +310,9 @@ __global__ __launch_bounds__(kB3) void k3_pseudo(Phys3 ph, Lvl3 L, CSoa3 f, CSoa
 // evaluations per cell instead of 6.
 namespace {
 
-constexpr int kSX = 64, kSY = 4, kSZ = 16, kSW = kSX + 2, kSH = kSY + 2, kSN = kSW * kSH, kRing = kSN - kSX * kSY;
+// 8 planes per block: about 2 % less time per sweep than 16 and 1.5 % less than 4 at 256^3 (more blocks to balance
+// against the two extra column closures a block evaluates to start its march)
+constexpr int kSX = 64, kSY = 4, kSZ = 8, kSW = kSX + 2, kSH = kSY + 2, kSN = kSW * kSH, kRing = kSN - kSX * kSY;
 
 // Closure record of the neighbour position (gx, gy) of plane z: a cell, the ghost beyond an x or y side (by the
 // side's rule, as nb3), or (never read) a placeholder.
